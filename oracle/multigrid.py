@@ -1,0 +1,166 @@
+"""Block smoothers, the V-cycle and the preconditioned outer solve.
+
+Everything here acts on time-major vectors y = Q x, b~ = P b (eq. (augsysp2))
+of one level, with A~ = P A Q^T split as L + D + L^T (Sec. 5.3.2):
+
+  block Jacobi (eq. (jacobi)):  y <- y + D^{-1} (b~ - A~ y)
+  symmetric block Gauss-Seidel (Sec. 5.3.4), used as the right
+  preconditioner of the coarse GMRES:
+        M = (D + L) D^{-1} (D + L^T),   M^{-1} r = (D+L^T)^{-1} D (D+L)^{-1} r
+  V-cycle (Alg. 1, recursed level by level, zero initial guess on each
+  level): pre-smooth, restrict b - A y, recurse, interpolate and add,
+  post-smooth; on the last level GMRES + SGS to a relative tolerance.
+  Outer solve: flexible GMRES preconditioned by one V-cycle (Sec. 5.3.4, 6).
+
+Factorisations are SuperLU (scipy.sparse.linalg.splu) of the assembled
+sparse block parts; nothing uses the derived Schur-complement formulas.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .system import assemble_A, time_major_perm, block_bounds, split_blocks
+from .transfer import restriction, interpolation
+from .krylov import gmres_right, fgmres
+
+
+class OracleLevel:
+    """One level: the time-major operator and factorisations of its parts."""
+
+    def __init__(self, N, V, Z, factor_sgs: bool = False):
+        N = np.asarray(N, dtype=np.float64)
+        self.n, self.p, _ = N.shape
+        self.q = Z.shape[2]
+        V = np.broadcast_to(V, (self.n, self.p, self.p))
+        Z = np.broadcast_to(Z, (self.n, self.p, self.q))
+        self.A = assemble_A(N, V, Z)                       # type-major
+        self.perm = time_major_perm(self.p, self.q, self.n)
+        self.At = self.A[self.perm][:, self.perm].tocsc()  # P A Q^T
+        self.bounds = block_bounds(self.p, self.q, self.n)
+        self.D, self.L, self.U = split_blocks(self.At.tocsr(), self.bounds)
+        self.D_lu = spla.splu(self.D.tocsc())
+        self.sgs_lo = self.sgs_up = None
+        if factor_sgs:
+            self.factor_sgs()
+
+    def factor_sgs(self):
+        self.sgs_lo = spla.splu((self.D + self.L).tocsc())
+        self.sgs_up = spla.splu((self.D + self.U).tocsc())
+
+    # -- smoothers ----------------------------------------------------------
+    def jacobi(self, b: np.ndarray, y: np.ndarray) -> np.ndarray:
+        """One undamped block Jacobi sweep, first form of eq. (jacobi)."""
+        return y + self.D_lu.solve(b - self.At @ y)
+
+    def sgs(self, r: np.ndarray) -> np.ndarray:
+        """M^{-1} r for the symmetric block Gauss-Seidel splitting."""
+        a = self.sgs_lo.solve(r)                 # (D + L) a = r
+        return self.sgs_up.solve(self.D @ a)     # (D + L^T) y = D a
+
+    def fgs(self, r: np.ndarray) -> np.ndarray:
+        return self.sgs_lo.solve(r)
+
+    def bgs(self, r: np.ndarray) -> np.ndarray:
+        return self.sgs_up.solve(r)
+
+
+@dataclass
+class MGOptions:
+    nu_pre: int = 2
+    nu_post: int = 2
+    coarse_tol: float = 1e-3
+    coarse_maxit: int = 50
+    coarse_fixed_its: int = 0
+    transfer_variant: int = 0
+
+
+class Hierarchy:
+    """The multigrid hierarchy of one problem (blocks given per level)."""
+
+    def __init__(self, levels, opts: Optional[MGOptions] = None):
+        """levels: list of objects with N (n,p,p), V, Z arrays (V/Z may be
+        (1,p,p)/(1,p,q) when shared by every step)."""
+        self.opts = opts or MGOptions()
+        self.levels: List[OracleLevel] = []
+        for i, lv in enumerate(levels):
+            last = i == len(levels) - 1
+            self.levels.append(OracleLevel(lv.N, lv.V, lv.Z, factor_sgs=last))
+        self.R, self.P = [], []
+        for i in range(len(self.levels) - 1):
+            f, c = self.levels[i], self.levels[i + 1]
+            if c.n * 2 != f.n:
+                raise ValueError("levels must halve the step count")
+            Rt = restriction(f.p, f.q, f.n, self.opts.transfer_variant)
+            Pt = interpolation(f.p, f.q, f.n, self.opts.transfer_variant)
+            # time-major transfers: R~ = P_c R Q_f^T, P~ = P_f P Q_c^T
+            self.R.append(Rt[c.perm][:, f.perm].tocsr())
+            self.P.append(Pt[f.perm][:, c.perm].tocsr())
+        self.coarse_its: List[int] = []
+
+    # -- multigrid ------------------------------------------------------------
+    def coarse_solve(self, b: np.ndarray) -> np.ndarray:
+        lv = self.levels[-1]
+        o = self.opts
+        x, its = gmres_right(lv.At, b, lv.sgs, o.coarse_tol, o.coarse_maxit,
+                             o.coarse_fixed_its)
+        self.coarse_its.append(its)
+        return x
+
+    def mg(self, lev: int, b: np.ndarray) -> np.ndarray:
+        """MG_lev(b): one V-cycle from a zero initial guess (Alg. 1)."""
+        if lev == len(self.levels) - 1:
+            return self.coarse_solve(b)
+        lv = self.levels[lev]
+        o = self.opts
+        y = np.zeros_like(b)
+        for _ in range(o.nu_pre):                 # pre-smooth
+            y = lv.jacobi(b, y)
+        r = b - lv.At @ y                         # residual
+        e = self.mg(lev + 1, self.R[lev] @ r)     # restrict + coarse solve
+        y = y + self.P[lev] @ e                   # interpolate and add
+        for _ in range(o.nu_post):                # post-smooth
+            y = lv.jacobi(b, y)
+        return y
+
+    # -- type-major front end -------------------------------------------------
+    def to_time(self, x: np.ndarray, lev: int = 0) -> np.ndarray:
+        return x[self.levels[lev].perm]
+
+    def to_type(self, y: np.ndarray, lev: int = 0) -> np.ndarray:
+        x = np.empty_like(y)
+        x[self.levels[lev].perm] = y
+        return x
+
+    def vcycle(self, r_type: np.ndarray) -> np.ndarray:
+        """One V-cycle applied to a type-major vector (zero initial guess)."""
+        return self.to_type(self.mg(0, self.to_time(r_type)))
+
+    def apply(self, x_type: np.ndarray) -> np.ndarray:
+        return self.levels[0].A @ x_type
+
+    def solve(self, b_type: np.ndarray, tol: float = 1e-10, restart: int = 30,
+              maxit: int = 300, x0: np.ndarray = None):
+        """FGMRES on A~ y = b~ preconditioned by one V-cycle per step."""
+        self.coarse_its = []
+        bt = self.to_time(b_type)
+        y0 = None if x0 is None else self.to_time(x0)
+        y, info = fgmres(self.levels[0].At, bt, lambda v: self.mg(0, v), tol,
+                         restart=restart, maxit=maxit, x0=y0)
+        info["coarse_its"] = list(self.coarse_its)
+        return self.to_type(y), info
+
+
+def direct_solve(level, b_type: np.ndarray) -> np.ndarray:
+    """The plain definition y* = A^{-1} b (sparse LU of the whole matrix)."""
+    N = np.asarray(level.N)
+    n, p, _ = N.shape
+    q = level.Z.shape[2]
+    V = np.broadcast_to(level.V, (n, p, p))
+    Z = np.broadcast_to(level.Z, (n, p, q))
+    A = assemble_A(N, V, Z).tocsc()
+    return spla.splu(A).solve(b_type)
