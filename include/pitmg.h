@@ -1,0 +1,174 @@
+/*
+ * pitmg.h -- parallel-in-time multigrid preconditioned FGMRES for the lifted,
+ * time-major augmented system of an optimal-control problem, on gfx950.
+ *
+ * Method: arXiv 2405.04808 (Vuchkov, Cyr, Javeed, Ridzal).
+ *   - augmented system A = [[I, B^T], [B, 0]] with B = dF~ (eq. (augsys),
+ *     Sec. 5.1), lifted with virtual interface variables v and multipliers
+ *     mu (Fig. 4), permuted to time-major block-tridiagonal form A~ = P A Q^T
+ *     (Fig. 5, eq. (augsysp));
+ *   - preconditioner: one multigrid V-cycle (Alg. 1, recursed) with undamped
+ *     block Jacobi smoothing (eq. (jacobi)), injection / linear interpolation
+ *     in time and averaging / piecewise-constant transfer of the control
+ *     (Sec. 5.3.1), and GMRES right-preconditioned by symmetric block
+ *     Gauss-Seidel on the coarsest grid, to a relative tolerance (Sec. 5.3.4);
+ *   - outer solver: flexible GMRES (Saad 1993), needed because the coarse
+ *     GMRES makes the preconditioner nonlinear (Sec. 5.3.4, Sec. 6).
+ *
+ * Vectors.  Every vector crossing this interface is a DEVICE pointer to FP64
+ * data in type-major order (Fig. 4):
+ *     x = [ u_1..u_n | v_1..v_n | z_1..z_n | lambda_1..lambda_n | mu_1..mu_n ]
+ * with u_k, v_k, lambda_k, mu_k of length p and z_k of length q, so the
+ * length is (4p+q) n.  The library permutes to the time-major blocks of
+ * Fig. 5 internally; callers never see the permutation.
+ *
+ * Blocks.  For level l (n_l = n / 2^l steps, l = 0 finest) the caller gives
+ * the Jacobian blocks of the lifted constraint (Sec. 4.1 eq. (blocks) with
+ * the substitutions of Sec. 5.1), row-major FP64:
+ *     N[l]: n_l blocks p x p  (N_k)
+ *     V[l]: n_l blocks p x p  (V_k; the block of step 1 is never read,
+ *                              since v_0 := 0)
+ *     Z[l]: n_l blocks p x q  (Z~_k)
+ * Block k of level l starts at X[l] + k * X_stride.  A stride of 0 means one
+ * block shared by every step (the natural form of V and Z~ for theta = 1).
+ * Coarse levels are rediscretisations at step 2^l dt (geometric multigrid,
+ * Sec. 5.3): the caller supplies them.
+ *
+ * Streams and ownership.  All device work of a handle is ordered on the HIP
+ * stream given at setup (0 = the null stream).  Setup copies host blocks
+ * into library memory (blocks_on_device = 0) or borrows device blocks
+ * (blocks_on_device = 1: the caller keeps them alive and unchanged until
+ * pitmg_refactor or pitmg_destroy).  The handle owns the factors and all
+ * work buffers.  Vector arguments are caller-owned.  Entry points that
+ * return results to the host synchronise the stream before returning.
+ *
+ * Errors.  Every call returns a pitmg_status.  A negative value is an error
+ * and leaves output vectors unspecified; PITMG_NOT_CONVERGED (1) from the
+ * solver leaves the last iterate in x.  pitmg_last_error() gives a message.
+ * Argument checks run on the host before any device work.
+ */
+#ifndef PITMG_H
+#define PITMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pitmg_handle pitmg_handle;
+
+typedef enum {
+  PITMG_OK = 0,
+  PITMG_NOT_CONVERGED = 1,     /* maxit reached; x holds the last iterate      */
+  PITMG_ERR_INVALID = -1,      /* bad argument (sizes, null pointer, level)    */
+  PITMG_ERR_SINGULAR = -2,     /* a block S_k = N_k N_k^T + Z~_k Z~_k^T is not
+                                  positive definite: the time-step block of
+                                  D is singular (Thm. 1's hypothesis fails);
+                                  see pitmg_failed_block                       */
+  PITMG_ERR_NONFINITE = -3,    /* right-hand side or residual not finite       */
+  PITMG_ERR_HIP = -4,          /* HIP runtime error                            */
+  PITMG_ERR_OOM = -5,          /* device allocation failed                     */
+  PITMG_ERR_UNSUPPORTED = -6   /* sizes beyond what this build handles         */
+} pitmg_status;
+
+typedef struct {
+  int p;                       /* states per step                              */
+  int q;                       /* controls per step                            */
+  int n;                       /* steps on the finest grid                     */
+  int n_levels;                /* grids l = 0..n_levels-1; n % 2^(n_levels-1)
+                                  must be 0 (coarsening by 2, Sec. 5.3.1)      */
+  const double* const* N;      /* n_levels pointers                            */
+  const double* const* V;
+  const double* const* Z;
+  long long N_stride;          /* p*p (or 0: shared)                           */
+  long long V_stride;          /* p*p or 0                                     */
+  long long Z_stride;          /* p*q or 0                                     */
+  int blocks_on_device;        /* 0: host pointers (copied); 1: device (borrowed) */
+} pitmg_problem;
+
+typedef struct {
+  int nu_pre;                  /* block Jacobi sweeps before the coarse solve  */
+  int nu_post;                 /* and after it                                 */
+  double coarse_tol;           /* relative tolerance of the coarse GMRES       */
+  int coarse_maxit;            /* coarse GMRES step limit (no restart)         */
+  int coarse_fixed_its;        /* >0: exactly this many coarse steps, no
+                                  tolerance test (deterministic cycle)         */
+  int restart;                 /* FGMRES restart length                        */
+  int maxit;                   /* FGMRES total step limit                      */
+  int transfer_variant;        /* 0: transfers as printed (coarse step k <->
+                                  fine step 2k-1, last even fine step copies the
+                                  last coarse value); 1: time-aligned
+                                  (coarse k <-> fine 2k)                        */
+} pitmg_options;
+
+typedef struct {
+  int iters;                   /* FGMRES steps taken                           */
+  int converged;               /* 1 if the residual estimate met tol           */
+  double relres_est;           /* last residual estimate / ||b||               */
+  double relres_true;          /* ||b - A~ x|| / ||b|| recomputed at the end   */
+  int coarse_calls;            /* coarse solves in this call                   */
+  int coarse_its_total;        /* their GMRES steps, summed                    */
+  double ms_solve;             /* wall time of the call, ms                    */
+} pitmg_stats;
+
+/* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
+ * transfer_variant 0. */
+void pitmg_default_options(pitmg_options* opt);
+
+/* Create a handle: validate, allocate, take the blocks (copy or borrow) and
+ * factor every block of every level (S_k = N_k N_k^T + Z~_k Z~_k^T, its
+ * Cholesky factor G_k and G_k^{-1}).  stream: a hipStream_t or NULL. */
+int pitmg_setup(pitmg_handle** h, const pitmg_problem* pb,
+                const pitmg_options* opt, void* stream);
+
+/* New blocks of the same sizes and strides (a new linearisation point):
+ * re-borrow or re-copy and re-factor without allocating. */
+int pitmg_refactor(pitmg_handle* h, const pitmg_problem* pb);
+
+/* Replace the options (sizes of the Krylov space may only shrink below the
+ * values given at setup). */
+int pitmg_set_options(pitmg_handle* h, const pitmg_options* opt);
+
+/* y = A~ x on level `level` (type-major device vectors of that level). */
+int pitmg_apply(pitmg_handle* h, int level, const double* x, double* y);
+
+/* One block Jacobi sweep on level `level` (eq. (jacobi), second form):
+ * y_out = D^{-1} (b - (L + L^T) y_in); y_in == NULL means y_in = 0. */
+int pitmg_jacobi_sweep(pitmg_handle* h, int level, const double* b,
+                       const double* y_in, double* y_out);
+
+/* The coarsest-level solve on its own: GMRES + SGS from x0 = 0 on level
+ * n_levels-1; *its receives the step count (host int, may be NULL). */
+int pitmg_coarse_solve(pitmg_handle* h, const double* b, double* x, int* its);
+
+/* e = MG(r): one V-cycle from a zero initial guess on the finest level. */
+int pitmg_vcycle(pitmg_handle* h, const double* r, double* e);
+
+/* Solve A~ y = b~ (type-major x) by FGMRES preconditioned with one V-cycle
+ * per step, to ||b - A~ x|| estimate <= tol ||b||.  x: in = initial guess if
+ * use_x0 != 0 (else ignored), out = solution.  st may be NULL. */
+int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x,
+                       double tol, int use_x0, pitmg_stats* st);
+
+/* Kernel timing: while enabled, the library brackets every launch with HIP
+ * events on its stream and accumulates per-kernel-class time.  Classes:
+ * 0 factor, 1 jacobi, 2 apply, 3 transfer, 4 coarse, 5 krylov. */
+int pitmg_profile_enable(pitmg_handle* h, int on);
+int pitmg_profile_read(pitmg_handle* h, int cls, int* launches, double* ms,
+                       double* bytes);
+int pitmg_profile_reset(pitmg_handle* h);
+
+/* After PITMG_ERR_SINGULAR: the (level, step k, 1-based) of the first
+ * failing block. */
+int pitmg_failed_block(const pitmg_handle* h, int* level, int* k);
+
+/* Bytes of device memory held by the handle. */
+long long pitmg_device_bytes(const pitmg_handle* h);
+
+const char* pitmg_status_string(int code);
+const char* pitmg_last_error(const pitmg_handle* h);
+void pitmg_destroy(pitmg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PITMG_H */

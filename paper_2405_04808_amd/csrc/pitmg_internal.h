@@ -1,0 +1,81 @@
+// Internal declarations shared by the kernel and host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pitmg {
+
+constexpr int kWave = 64;
+
+// One level of the hierarchy as the kernels see it.
+struct LevelView {
+  int n;                       // steps on this level
+  int p, q;
+  const double* N;  long long sN;   // N_k = N + k*sN (k 0-based)
+  const double* V;  long long sV;
+  const double* Z;  long long sZ;
+  const double* Gi;            // [n][p][p] row-major, lower triangle of G_k^{-1}
+};
+
+// Offsets of the five variable types in a type-major vector of n steps.
+struct TypeMajor {
+  long long u, v, z, l, m, len;
+  __host__ __device__ TypeMajor(int p, int q, int n) {
+    u = 0; v = (long long)p * n; z = 2LL * p * n; l = z + (long long)q * n;
+    m = l + (long long)p * n; len = m + (long long)p * n;
+  }
+};
+
+// ---- launchers (pitmg_kernels.hip) ---------------------------------------
+// Factor every block of one level: S_k = N_k N_k^T + Z_k Z_k^T, Cholesky
+// S_k = G_k G_k^T, and G_k^{-1} stored in Gi.  fail: device int, atomicMin'd
+// with (level << 20 | k) on a non-positive pivot.
+hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail,
+                         hipStream_t s);
+size_t factor_lds_bytes(int p);
+
+// One block Jacobi sweep: ynew = D^{-1}(b - (L+L^T) yc) where the coupling
+// values yc are taken from yold (NULL = 0) plus, if ecoarse != NULL, the
+// interpolation of the coarse vector ecoarse (variant as in the options).
+hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
+                         const double* ecoarse, int variant, double* ynew,
+                         hipStream_t s);
+
+// out = beta*b + alpha*(A~ x) on one level (b may be NULL when beta == 0).
+hipError_t launch_apply(const LevelView& L, const double* x, const double* b,
+                        double alpha, double beta, double* out, hipStream_t s);
+
+// Coarse right-hand side from the last pre-smoothing sweep:
+// bc = R (L+L^T)(yprev - y)  (yprev NULL = 0).
+hipError_t launch_restrict_delta(int p, int q, int nf, const double* yprev,
+                                 const double* y, int variant, double* bc,
+                                 hipStream_t s);
+// bc = R r (general restriction of a full fine vector).
+hipError_t launch_restrict(int p, int q, int nf, const double* r, int variant,
+                           double* bc, hipStream_t s);
+// y += P e  (interpolate and add).
+hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant,
+                             double* y, hipStream_t s);
+
+// Coarse GMRES + SGS in one work-group.  work: device scratch of
+// coarse_work_doubles(...) doubles; its_out: device int.
+size_t coarse_work_doubles(int p, int q, int n, int maxit);
+hipError_t launch_coarse(const LevelView& L, const double* b, double* x,
+                         double tol, int maxit, int fixed_its, double* work,
+                         int* its_out, hipStream_t s);
+
+// Krylov helpers.  Basis vectors are rows of a [k][len] array.
+int krylov_partial_blocks(long long len);
+hipError_t launch_multidot(const double* basis, int nvec, const double* w,
+                           long long len, double* partial, hipStream_t s);
+hipError_t launch_reduce_partials(const double* partial, int nblk, int nval,
+                                  double* out, hipStream_t s);
+hipError_t launch_multi_axpy(double* w, const double* basis, int nvec,
+                             const double* coef, double sign, long long len,
+                             hipStream_t s);
+hipError_t launch_scale(double* dst, const double* src, double alpha,
+                        long long len, hipStream_t s);
+hipError_t launch_axpby(double* y, const double* x, double a, double b,
+                        long long len, hipStream_t s);   // y = a*x + b*y
+
+}  // namespace pitmg

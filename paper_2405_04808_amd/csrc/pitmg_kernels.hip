@@ -1,0 +1,895 @@
+// HIP kernels for gfx950: block factorisation, block Jacobi sweep, operator
+// apply, transfers in time, the coarse GMRES+SGS solve and Krylov helpers.
+//
+// Block algebra (time-major block k of Fig. 5, unknowns
+// (v_{k-1}, u_k, z_k, lambda_k, mu_{k-1})).  The diagonal block D_k is
+//     [ I    .    .    V_k^T  -I ]   v_{k-1}
+//     [ .    I    .    N_k^T   . ]   u_k
+//     [ .    .    I    Z_k^T   . ]   z_k
+//     [ V_k  N_k  Z_k  .       . ]   lambda_k
+//     [ -I   .    .    .       . ]   mu_{k-1}
+// Eliminating v, u, z gives the Schur complement in lambda,
+//     S_k = N_k N_k^T + Z_k Z_k^T       (the V_k V_k^T terms cancel),
+// which is positive definite when N_k is invertible (Thm. 1).  With
+// S_k = G_k G_k^T and the right-hand side (r_v, r_u, r_z, r_l, r_m):
+//     t = N r_u + Z r_z - V r_m - r_l,  lambda = G^{-T} G^{-1} t,
+//     u = r_u - N^T lambda,  z = r_z - Z^T lambda,
+//     mu = V^T lambda - r_m - r_v,  v = -r_m.
+// Block 1 has no v, mu (and V_1 is unused); block n+1 is (v_n, mu_n) with
+// v_n = -r_m, mu_n = -r_m - r_v.  Between blocks the only couplings are the
+// +I entries u_k <-> mu_k (Sec. 5.3.2), so a Jacobi sweep needs just u_{k-1}
+// and mu_k of the previous iterate.
+#include "pitmg_internal.h"
+#include <climits>
+
+namespace pitmg {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over the work-group; every thread returns the same value.  red must
+// hold NT/64 doubles.  Fixed summation order (deterministic).
+template <int NT>
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / kWave; ++i) r += red[i];
+  return r;
+}
+
+// out[j] = sum_{i in rows} A[i*lda + j] * x[i] for j < ncols; rows are
+// 0..nrows-1, or j..nrows-1 when `lower`.  Consecutive threads take
+// consecutive columns (coalesced rows); row slices are summed through part
+// (NT doubles).  Ends with a barrier.
+template <int NT>
+__device__ void col_dot(int nrows, int ncols, const double* __restrict__ A,
+                        long long lda, const double* x, bool lower,
+                        double* part, double* out) {
+  const int tid = threadIdx.x;
+  for (int j0 = 0; j0 < ncols; j0 += NT) {
+    const int nc = min(NT, ncols - j0);
+    const int G = NT / nc;
+    const int jl = tid % nc, g = tid / nc;
+    const int j = j0 + jl;
+    double acc = 0.0;
+    if (g < G) {
+      int i = g;
+      if (lower && j > g) i = g + ((j - g + G - 1) / G) * G;
+      for (; i < nrows; i += G) acc += A[(long long)i * lda + j] * x[i];
+      part[g * nc + jl] = acc;
+    }
+    __syncthreads();
+    if (tid < nc) {
+      double s = 0.0;
+      for (int gg = 0; gg < G; ++gg) s += part[gg * nc + tid];
+      out[j0 + tid] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Solve D_k (v,u,z,lambda,mu) = (rv,ru,rz,rl,rm) for one time-step block with
+// the whole work-group.  All vector arguments live in LDS; the matrices in
+// global memory.  has_vm = false for block 1 (no v, mu; V unused).
+template <int NT>
+__device__ void block_solve(int p, int q, const double* __restrict__ Nk,
+                            const double* __restrict__ Vk,
+                            const double* __restrict__ Zk,
+                            const double* __restrict__ Gk, bool has_vm,
+                            const double* rv, const double* ru, const double* rz,
+                            const double* rl, const double* rm, double* ov,
+                            double* ou, double* oz, double* ol, double* om,
+                            double* t, double* s, double* part) {
+  constexpr int NW = NT / kWave;
+  const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+  // t = N r_u + Z r_z - V r_m - r_l   (row dots, one wave per row)
+  for (int i = w; i < p; i += NW) {
+    double acc = 0.0;
+    const double* Ni = Nk + (long long)i * p;
+    for (int j = lane; j < p; j += kWave) acc += Ni[j] * ru[j];
+    if (has_vm) {
+      const double* Vi = Vk + (long long)i * p;
+      for (int j = lane; j < p; j += kWave) acc -= Vi[j] * rm[j];
+    }
+    const double* Zi = Zk + (long long)i * q;
+    for (int j = lane; j < q; j += kWave) acc += Zi[j] * rz[j];
+    acc = wave_sum(acc);
+    if (lane == 0) t[i] = acc - rl[i];
+  }
+  __syncthreads();
+  // s = G^{-1} t  (lower triangular)
+  for (int i = w; i < p; i += NW) {
+    double acc = 0.0;
+    const double* Gr = Gk + (long long)i * p;
+    for (int j = lane; j <= i; j += kWave) acc += Gr[j] * t[j];
+    acc = wave_sum(acc);
+    if (lane == 0) s[i] = acc;
+  }
+  __syncthreads();
+  // lambda = G^{-T} s
+  col_dot<NT>(p, p, Gk, p, s, true, part, ol);
+  // u = r_u - N^T lambda ; z = r_z - Z^T lambda ; mu = V^T lambda - r_m - r_v
+  col_dot<NT>(p, p, Nk, p, ol, false, part, ou);
+  col_dot<NT>(p, q, Zk, q, ol, false, part, oz);
+  if (has_vm) col_dot<NT>(p, p, Vk, p, ol, false, part, om);
+  for (int i = tid; i < p; i += NT) {
+    ou[i] = ru[i] - ou[i];
+    if (has_vm) {
+      om[i] = om[i] - rm[i] - rv[i];
+      ov[i] = -rm[i];
+    }
+  }
+  for (int i = tid; i < q; i += NT) oz[i] = rz[i] - oz[i];
+  __syncthreads();
+}
+
+// Value of the interpolated coarse vector (one node-type segment, nc coarse
+// steps, width p) at fine step k (1-based), component i (Sec. 5.3.1).
+__device__ __forceinline__ double interp_node(const double* __restrict__ seg, int nc,
+                                              int p, int k, int i, int variant) {
+  if (variant == 0) {
+    if (k & 1) return seg[(long long)((k + 1) / 2 - 1) * p + i];
+    const int m = k / 2, m2 = m < nc ? m + 1 : nc;
+    return 0.5 * (seg[(long long)(m - 1) * p + i] + seg[(long long)(m2 - 1) * p + i]);
+  }
+  if (!(k & 1)) return seg[(long long)(k / 2 - 1) * p + i];
+  const int m = (k + 1) / 2;
+  const double a = seg[(long long)(m - 1) * p + i];
+  const double b = m >= 2 ? seg[(long long)(m - 2) * p + i] : 0.0;
+  return 0.5 * (a + b);
+}
+
+// ---------------------------------------------------------------------------
+// K1/K2: factorisation of S_k = N N^T + Z Z^T, Cholesky, triangular inverse
+// ---------------------------------------------------------------------------
+
+constexpr int kFactorThreads = 256;
+
+template <bool USE_LDS>
+__global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, double* Gi,
+                                                           int level, int* fail) {
+  extern __shared__ double smem[];
+  const int p = L.p, q = L.q;
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double* __restrict__ Nk = L.N + (long long)k * L.sN;
+  const double* __restrict__ Zk = L.Z + (long long)k * L.sZ;
+  double* Gk = Gi + (long long)k * p * p;
+  const int ld = USE_LDS ? p + 1 : p;
+  double* S = USE_LDS ? smem : Gk;
+  double* tmp = USE_LDS ? smem + (size_t)p * ld : smem;
+
+  // S = N N^T + Z Z^T (lower triangle)
+  for (int idx = tid; idx < p * p; idx += kFactorThreads) {
+    const int i = idx / p, j = idx % p;
+    if (j > i) continue;
+    double acc = 0.0;
+    const double* Ni = Nk + (long long)i * p;
+    const double* Nj = Nk + (long long)j * p;
+    for (int m = 0; m < p; ++m) acc += Ni[m] * Nj[m];
+    const double* Zi = Zk + (long long)i * q;
+    const double* Zj = Zk + (long long)j * q;
+    for (int m = 0; m < q; ++m) acc += Zi[m] * Zj[m];
+    S[(long long)i * ld + j] = acc;
+  }
+  // Cholesky, right-looking, column by column
+  for (int j = 0; j < p; ++j) {
+    __syncthreads();
+    double d = S[(long long)j * ld + j];
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0) atomicMin(fail, (level << 20) | k);
+      return;                                  // uniform: every thread read d
+    }
+    d = sqrt(d);
+    __syncthreads();
+    if (tid == 0) S[(long long)j * ld + j] = d;
+    const double inv = 1.0 / d;
+    for (int i = j + 1 + tid; i < p; i += kFactorThreads) S[(long long)i * ld + j] *= inv;
+    __syncthreads();
+    const int m = p - j - 1;
+    for (int idx = tid; idx < m * m; idx += kFactorThreads) {
+      const int ii = idx / m, cc = idx % m;
+      if (cc > ii) continue;
+      const int i = j + 1 + ii, c = j + 1 + cc;
+      S[(long long)i * ld + c] -= S[(long long)i * ld + j] * S[(long long)c * ld + j];
+    }
+  }
+  // In-place inverse of the lower-triangular G, columns right to left:
+  // X[j][j] = 1/G[j][j], X[i][j] = -X[j][j] sum_{m=j+1..i} X[i][m] G[m][j].
+  for (int j = p - 1; j >= 0; --j) {
+    __syncthreads();
+    const double djj = 1.0 / S[(long long)j * ld + j];
+    for (int i = j + 1 + tid; i < p; i += kFactorThreads) {
+      double acc = 0.0;
+      for (int m = j + 1; m <= i; ++m) acc += S[(long long)i * ld + m] * S[(long long)m * ld + j];
+      tmp[i] = -djj * acc;
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < p; i += kFactorThreads) S[(long long)i * ld + j] = tmp[i];
+    if (tid == 0) S[(long long)j * ld + j] = djj;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < p * p; idx += kFactorThreads) {
+    const int i = idx / p, j = idx % p;
+    const double v = j <= i ? S[(long long)i * ld + j] : 0.0;
+    Gk[idx] = v;
+  }
+}
+
+size_t factor_lds_bytes(int p) {
+  if (p <= 128) return ((size_t)p * (p + 1) + p) * sizeof(double);
+  return (size_t)p * sizeof(double);
+}
+
+hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail,
+                         hipStream_t s) {
+  const size_t lds = factor_lds_bytes(L.p);
+  if (L.p <= 128) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_factor<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_factor<true>, dim3(L.n), dim3(kFactorThreads), lds, s, L, Gi,
+                       level, fail);
+  } else {
+    hipLaunchKernelGGL(k_factor<false>, dim3(L.n), dim3(kFactorThreads), lds, s, L, Gi,
+                       level, fail);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K3: block Jacobi sweep, one work-group per time-major block
+// ---------------------------------------------------------------------------
+
+constexpr int kSweepThreads = 256;
+
+// LDS doubles used by one block solve: 5 inputs, 5 outputs, t, s, part.
+__host__ __device__ inline size_t solve_lds_doubles(int p, int q, int nt) {
+  return (size_t)8 * p + 2 * q + 2 * p + nt + (size_t)2 * p;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_jacobi(LevelView L, const double* __restrict__ b,
+                                               const double* __restrict__ yold,
+                                               const double* __restrict__ ec, int variant,
+                                               double* __restrict__ ynew) {
+  extern __shared__ double sm[];
+  const int p = L.p, q = L.q, n = L.n;
+  const TypeMajor T(p, q, n);
+  const int nc = n / 2;
+  const TypeMajor Tc(p, q, nc > 0 ? nc : 1);
+  const int kb = blockIdx.x, tid = threadIdx.x;
+
+  // coupling values of the previous iterate: yold + P ec (u and mu only)
+  auto cu = [&](int k1, int i) -> double {
+    double v = yold ? yold[T.u + (long long)(k1 - 1) * p + i] : 0.0;
+    if (ec) v += interp_node(ec + Tc.u, nc, p, k1, i, variant);
+    return v;
+  };
+  auto cm = [&](int k1, int i) -> double {
+    double v = yold ? yold[T.m + (long long)(k1 - 1) * p + i] : 0.0;
+    if (ec) v += interp_node(ec + Tc.m, nc, p, k1, i, variant);
+    return v;
+  };
+
+  if (kb == n) {                               // block n+1 = (v_n, mu_n)
+    for (int i = tid; i < p; i += NT) {
+      const double rvv = b[T.v + (long long)(n - 1) * p + i];
+      const double rmm = b[T.m + (long long)(n - 1) * p + i] - cu(n, i);
+      ynew[T.v + (long long)(n - 1) * p + i] = -rmm;
+      ynew[T.m + (long long)(n - 1) * p + i] = -rmm - rvv;
+    }
+    return;
+  }
+  const int k = kb + 1;
+  const bool hv = k >= 2;
+  double* rv = sm;
+  double* ru = rv + p;
+  double* rz = ru + p;
+  double* rl = rz + q;
+  double* rm = rl + p;
+  double* ov = rm + p;
+  double* ou = ov + p;
+  double* oz = ou + p;
+  double* ol = oz + q;
+  double* om = ol + p;
+  double* t = om + p;
+  double* s = t + p;
+  double* part = s + p;
+  for (int i = tid; i < p; i += NT) {
+    ru[i] = b[T.u + (long long)(k - 1) * p + i] - cm(k, i);
+    rl[i] = b[T.l + (long long)(k - 1) * p + i];
+    if (hv) {
+      rv[i] = b[T.v + (long long)(k - 2) * p + i];
+      rm[i] = b[T.m + (long long)(k - 2) * p + i] - cu(k - 1, i);
+    } else {
+      rv[i] = 0.0;
+      rm[i] = 0.0;
+    }
+  }
+  for (int i = tid; i < q; i += NT) rz[i] = b[T.z + (long long)(k - 1) * q + i];
+  __syncthreads();
+  const long long kk = k - 1;
+  block_solve<NT>(p, q, L.N + kk * L.sN, L.V + kk * L.sV, L.Z + kk * L.sZ,
+                  L.Gi + kk * p * p, hv, rv, ru, rz, rl, rm, ov, ou, oz, ol, om, t, s,
+                  part);
+  for (int i = tid; i < p; i += NT) {
+    ynew[T.u + kk * p + i] = ou[i];
+    ynew[T.l + kk * p + i] = ol[i];
+    if (hv) {
+      ynew[T.v + (kk - 1) * p + i] = ov[i];
+      ynew[T.m + (kk - 1) * p + i] = om[i];
+    }
+  }
+  for (int i = tid; i < q; i += NT) ynew[T.z + kk * q + i] = oz[i];
+}
+
+hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
+                         const double* ecoarse, int variant, double* ynew, hipStream_t s) {
+  const size_t lds = solve_lds_doubles(L.p, L.q, kSweepThreads) * sizeof(double);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<kSweepThreads>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_jacobi<kSweepThreads>, dim3(L.n + 1), dim3(kSweepThreads), lds, s,
+                     L, b, yold, ecoarse, variant, ynew);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K4: out = beta*b + alpha*(A~ x), one work-group per time step
+// ---------------------------------------------------------------------------
+
+// Rows of time-major block k (1-based): v_{k-1}, u_k, z_k, lambda_k,
+// mu_{k-1}; block n also writes block n+1's rows v_n, mu_n.
+template <int NT>
+__device__ void apply_step(const LevelView& L, int k, const double* __restrict__ x,
+                           const double* __restrict__ b, double alpha, double beta,
+                           double* __restrict__ out, double* sm) {
+  const int p = L.p, q = L.q, n = L.n;
+  const TypeMajor T(p, q, n);
+  const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+  constexpr int NW = NT / kWave;
+  const bool hv = k >= 2;
+  const long long kk = k - 1;
+  const double* Nk = L.N + kk * L.sN;
+  const double* Vk = L.V + kk * L.sV;
+  const double* Zk = L.Z + kk * L.sZ;
+  double* xu = sm;
+  double* xv = xu + p;
+  double* xz = xv + p;
+  double* xl = xz + q;
+  double* t = xl + p;
+  double* part = t + p;
+  for (int i = tid; i < p; i += NT) {
+    xu[i] = x[T.u + kk * p + i];
+    xl[i] = x[T.l + kk * p + i];
+    xv[i] = hv ? x[T.v + (kk - 1) * p + i] : 0.0;
+  }
+  for (int i = tid; i < q; i += NT) xz[i] = x[T.z + kk * q + i];
+  __syncthreads();
+  auto put = [&](long long idx, double val) {
+    out[idx] = (beta != 0.0 ? beta * b[idx] : 0.0) + alpha * val;
+  };
+  // row lambda_k = N u_k + V v_{k-1} + Z z_k
+  for (int i = w; i < p; i += NW) {
+    double acc = 0.0;
+    const double* Ni = Nk + (long long)i * p;
+    for (int j = lane; j < p; j += kWave) acc += Ni[j] * xu[j];
+    if (hv) {
+      const double* Vi = Vk + (long long)i * p;
+      for (int j = lane; j < p; j += kWave) acc += Vi[j] * xv[j];
+    }
+    const double* Zi = Zk + (long long)i * q;
+    for (int j = lane; j < q; j += kWave) acc += Zi[j] * xz[j];
+    acc = wave_sum(acc);
+    if (lane == 0) put(T.l + kk * p + i, acc);
+  }
+  // rows u_k, z_k, v_{k-1}
+  col_dot<NT>(p, p, Nk, p, xl, false, part, t);
+  for (int i = tid; i < p; i += NT)
+    put(T.u + kk * p + i, xu[i] + t[i] + x[T.m + kk * p + i]);
+  __syncthreads();
+  col_dot<NT>(p, q, Zk, q, xl, false, part, t);
+  for (int i = tid; i < q; i += NT) put(T.z + kk * q + i, xz[i] + t[i]);
+  __syncthreads();
+  if (hv) {
+    col_dot<NT>(p, p, Vk, p, xl, false, part, t);
+    for (int i = tid; i < p; i += NT) {
+      put(T.v + (kk - 1) * p + i, xv[i] + t[i] - x[T.m + (kk - 1) * p + i]);
+      put(T.m + (kk - 1) * p + i, x[T.u + (kk - 1) * p + i] - xv[i]);
+    }
+    __syncthreads();
+  }
+  if (k == n) {
+    for (int i = tid; i < p; i += NT) {
+      const double vn = x[T.v + kk * p + i], mn = x[T.m + kk * p + i];
+      put(T.v + kk * p + i, vn - mn);
+      put(T.m + kk * p + i, xu[i] - vn);
+    }
+  }
+  __syncthreads();
+}
+
+constexpr int kApplyThreads = 256;
+
+__host__ __device__ inline size_t apply_lds_doubles(int p, int q, int nt) { return (size_t)4 * p + q + nt + p; }
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_apply(LevelView L, const double* __restrict__ x,
+                                              const double* __restrict__ b, double alpha,
+                                              double beta, double* __restrict__ out) {
+  extern __shared__ double sm[];
+  apply_step<NT>(L, blockIdx.x + 1, x, b, alpha, beta, out, sm);
+}
+
+hipError_t launch_apply(const LevelView& L, const double* x, const double* b, double alpha,
+                        double beta, double* out, hipStream_t s) {
+  const size_t lds = apply_lds_doubles(L.p, L.q, kApplyThreads) * sizeof(double);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_apply<kApplyThreads>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_apply<kApplyThreads>, dim3(L.n), dim3(kApplyThreads), lds, s, L, x,
+                     b, alpha, beta, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K5: transfers in time
+// ---------------------------------------------------------------------------
+
+// Locate coarse element idx: type (0 u,1 v,2 z,3 l,4 m), step m (1-based),
+// component i.
+__device__ __forceinline__ void locate(long long idx, const TypeMajor& T, int p, int q,
+                                       int& type, int& m, int& i) {
+  long long off;
+  if (idx < T.v) { type = 0; off = idx - T.u; }
+  else if (idx < T.z) { type = 1; off = idx - T.v; }
+  else if (idx < T.l) { type = 2; off = idx - T.z; m = (int)(off / q) + 1; i = (int)(off % q); return; }
+  else if (idx < T.m) { type = 3; off = idx - T.l; }
+  else { type = 4; off = idx - T.m; }
+  m = (int)(off / p) + 1;
+  i = (int)(off % p);
+}
+
+__global__ void k_restrict_delta(int p, int q, int nf, const double* __restrict__ yprev,
+                                 const double* __restrict__ y, int variant,
+                                 double* __restrict__ bc) {
+  const int nc = nf / 2;
+  const TypeMajor Tf(p, q, nf), Tc(p, q, nc);
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Tc.len;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int type, m, i;
+    locate(idx, Tc, p, q, type, m, i);
+    double v = 0.0;
+    const int kf = variant == 0 ? 2 * m - 1 : 2 * m;
+    if (type == 0) {            // r_u,k = mu_k^prev - mu_k
+      const long long f = Tf.m + (long long)(kf - 1) * p + i;
+      v = (yprev ? yprev[f] : 0.0) - y[f];
+    } else if (type == 4) {     // r_mu,k = u_k^prev - u_k
+      const long long f = Tf.u + (long long)(kf - 1) * p + i;
+      v = (yprev ? yprev[f] : 0.0) - y[f];
+    }
+    bc[idx] = v;
+  }
+}
+
+__global__ void k_restrict(int p, int q, int nf, const double* __restrict__ r, int variant,
+                           double* __restrict__ bc) {
+  const int nc = nf / 2;
+  const TypeMajor Tf(p, q, nf), Tc(p, q, nc);
+  const long long segf[5] = {Tf.u, Tf.v, Tf.z, Tf.l, Tf.m};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Tc.len;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int type, m, i;
+    locate(idx, Tc, p, q, type, m, i);
+    double v;
+    if (type == 2) {
+      v = 0.5 * (r[Tf.z + (long long)(2 * m - 2) * q + i] + r[Tf.z + (long long)(2 * m - 1) * q + i]);
+    } else {
+      const int kf = variant == 0 ? 2 * m - 1 : 2 * m;
+      v = r[segf[type] + (long long)(kf - 1) * p + i];
+    }
+    bc[idx] = v;
+  }
+}
+
+__global__ void k_interp_add(int p, int q, int nf, const double* __restrict__ e, int variant,
+                             double* __restrict__ y) {
+  const int nc = nf / 2;
+  const TypeMajor Tf(p, q, nf), Tc(p, q, nc);
+  const long long segc[5] = {Tc.u, Tc.v, Tc.z, Tc.l, Tc.m};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Tf.len;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int type, k, i;
+    locate(idx, Tf, p, q, type, k, i);
+    double v;
+    if (type == 2) v = e[Tc.z + (long long)((k + 1) / 2 - 1) * q + i];
+    else v = interp_node(e + segc[type], nc, p, k, i, variant);
+    y[idx] += v;
+  }
+}
+
+static inline int grid_for(long long len, int nt) {
+  long long g = (len + nt - 1) / nt;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_restrict_delta(int p, int q, int nf, const double* yprev, const double* y,
+                                 int variant, double* bc, hipStream_t s) {
+  const TypeMajor Tc(p, q, nf / 2);
+  hipLaunchKernelGGL(k_restrict_delta, dim3(grid_for(Tc.len, 256)), dim3(256), 0, s, p, q, nf,
+                     yprev, y, variant, bc);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(int p, int q, int nf, const double* r, int variant, double* bc,
+                           hipStream_t s) {
+  const TypeMajor Tc(p, q, nf / 2);
+  hipLaunchKernelGGL(k_restrict, dim3(grid_for(Tc.len, 256)), dim3(256), 0, s, p, q, nf, r,
+                     variant, bc);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant, double* y,
+                             hipStream_t s) {
+  const TypeMajor Tf(p, q, nf);
+  hipLaunchKernelGGL(k_interp_add, dim3(grid_for(Tf.len, 256)), dim3(256), 0, s, p, q, nf, e,
+                     variant, y);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K6: coarse GMRES right-preconditioned by symmetric block Gauss-Seidel, in
+// one work-group (the coarse grid is small; the solve is serial in time).
+// ---------------------------------------------------------------------------
+
+constexpr int kCoarseThreads = 1024;
+
+size_t coarse_work_doubles(int p, int q, int n, int maxit) {
+  const TypeMajor T(p, q, n);
+  return (size_t)T.len * (2 * (size_t)maxit + 3);
+}
+
+template <int NT>
+__device__ double wg_dot(const double* a, const double* b, long long len, double* red) {
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < len; i += NT) acc += a[i] * b[i];
+  return block_sum<NT>(acc, red);
+}
+
+// dst = M^{-1} src for M = (D+L) D^{-1} (D+L^T): forward block sweep into a,
+// then the backward sweep dst_k = a_k - D_k^{-1} (L^T dst)_k.
+template <int NT>
+__device__ void sgs_apply(const LevelView& L, const double* src, double* a, double* dst,
+                          double* sm) {
+  const int p = L.p, q = L.q, n = L.n;
+  const TypeMajor T(p, q, n);
+  const int tid = threadIdx.x;
+  double* rv = sm;
+  double* ru = rv + p;
+  double* rz = ru + p;
+  double* rl = rz + q;
+  double* rm = rl + p;
+  double* ov = rm + p;
+  double* ou = ov + p;
+  double* oz = ou + p;
+  double* ol = oz + q;
+  double* om = ol + p;
+  double* t = om + p;
+  double* s = t + p;
+  double* part = s + p;
+  // forward: (D + L) a = src, blocks 1..n+1
+  for (int kb = 0; kb <= n; ++kb) {
+    if (kb == n) {
+      for (int i = tid; i < p; i += NT) {
+        const long long o = (long long)(n - 1) * p + i;
+        const double rmm = src[T.m + o] - a[T.u + o];
+        a[T.v + o] = -rmm;
+        a[T.m + o] = -rmm - src[T.v + o];
+      }
+      __syncthreads();
+      break;
+    }
+    const int k = kb + 1;
+    const bool hv = k >= 2;
+    const long long kk = k - 1;
+    for (int i = tid; i < p; i += NT) {
+      ru[i] = src[T.u + kk * p + i];
+      rl[i] = src[T.l + kk * p + i];
+      rv[i] = hv ? src[T.v + (kk - 1) * p + i] : 0.0;
+      rm[i] = hv ? src[T.m + (kk - 1) * p + i] - a[T.u + (kk - 1) * p + i] : 0.0;
+    }
+    for (int i = tid; i < q; i += NT) rz[i] = src[T.z + kk * q + i];
+    __syncthreads();
+    block_solve<NT>(p, q, L.N + kk * L.sN, L.V + kk * L.sV, L.Z + kk * L.sZ,
+                    L.Gi + kk * p * p, hv, rv, ru, rz, rl, rm, ov, ou, oz, ol, om, t, s, part);
+    for (int i = tid; i < p; i += NT) {
+      a[T.u + kk * p + i] = ou[i];
+      a[T.l + kk * p + i] = ol[i];
+      if (hv) {
+        a[T.v + (kk - 1) * p + i] = ov[i];
+        a[T.m + (kk - 1) * p + i] = om[i];
+      }
+    }
+    for (int i = tid; i < q; i += NT) a[T.z + kk * q + i] = oz[i];
+    __syncthreads();
+  }
+  // backward: block n+1 has no upper coupling
+  for (int i = tid; i < p; i += NT) {
+    const long long o = (long long)(n - 1) * p + i;
+    dst[T.v + o] = a[T.v + o];
+    dst[T.m + o] = a[T.m + o];
+  }
+  __syncthreads();
+  for (int k = n; k >= 1; --k) {
+    const bool hv = k >= 2;
+    const long long kk = k - 1;
+    for (int i = tid; i < p; i += NT) {
+      rv[i] = 0.0;
+      rm[i] = 0.0;
+      rl[i] = 0.0;
+      ru[i] = dst[T.m + kk * p + i];          // (L^T dst) in row u_k = mu_k
+    }
+    for (int i = tid; i < q; i += NT) rz[i] = 0.0;
+    __syncthreads();
+    block_solve<NT>(p, q, L.N + kk * L.sN, L.V + kk * L.sV, L.Z + kk * L.sZ,
+                    L.Gi + kk * p * p, hv, rv, ru, rz, rl, rm, ov, ou, oz, ol, om, t, s, part);
+    for (int i = tid; i < p; i += NT) {
+      dst[T.u + kk * p + i] = a[T.u + kk * p + i] - ou[i];
+      dst[T.l + kk * p + i] = a[T.l + kk * p + i] - ol[i];
+      if (hv) {
+        dst[T.v + (kk - 1) * p + i] = a[T.v + (kk - 1) * p + i] - ov[i];
+        dst[T.m + (kk - 1) * p + i] = a[T.m + (kk - 1) * p + i] - om[i];
+      }
+    }
+    for (int i = tid; i < q; i += NT) dst[T.z + kk * q + i] = a[T.z + kk * q + i] - oz[i];
+    __syncthreads();
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_coarse(LevelView L, const double* __restrict__ b,
+                                               double* __restrict__ x, double tol, int maxit,
+                                               int fixed_its, double* __restrict__ work,
+                                               int* its_out) {
+  extern __shared__ double sm[];
+  const int p = L.p, q = L.q, n = L.n;
+  const TypeMajor T(p, q, n);
+  const long long len = T.len;
+  const int tid = threadIdx.x;
+  const int nsteps = fixed_its > 0 ? fixed_its : maxit;
+  double* Vb = work;                                   // [nsteps+1][len]
+  double* Zb = Vb + (size_t)(nsteps + 1) * len;        // [nsteps][len]
+  double* wv = Zb + (size_t)nsteps * len;
+  double* av = wv + len;
+  // LDS: solver scratch, then H (nsteps+1 x nsteps), cs, sn, g, y, red
+  const size_t solve_sz = solve_lds_doubles(p, q, NT);
+  const size_t app_sz = apply_lds_doubles(p, q, NT);
+  double* ssolve = sm;
+  double* H = sm + (solve_sz > app_sz ? solve_sz : app_sz);
+  double* cs = H + (size_t)(nsteps + 1) * nsteps;
+  double* sn = cs + nsteps;
+  double* g = sn + nsteps;
+  double* yv = g + nsteps + 1;
+  double* red = yv + nsteps;
+  __shared__ int stop_flag;
+
+  const double beta = sqrt(wg_dot<NT>(b, b, len, red));
+  if (beta == 0.0) {
+    for (long long i = tid; i < len; i += NT) x[i] = 0.0;
+    if (tid == 0) *its_out = 0;
+    return;
+  }
+  for (long long i = tid; i < len; i += NT) Vb[i] = b[i] / beta;
+  if (tid == 0) {
+    g[0] = beta;
+    for (int i = 1; i <= nsteps; ++i) g[i] = 0.0;
+  }
+  __syncthreads();
+  int its = 0;
+  for (int j = 0; j < nsteps; ++j) {
+    double* vj = Vb + (size_t)j * len;
+    double* zj = Zb + (size_t)j * len;
+    sgs_apply<NT>(L, vj, av, zj, ssolve);
+    for (int k = 1; k <= n; ++k) apply_step<NT>(L, k, zj, nullptr, 1.0, 0.0, wv, ssolve);
+    __syncthreads();
+    const double w0 = sqrt(wg_dot<NT>(wv, wv, len, red));
+    for (int i = 0; i <= j; ++i) {                     // modified Gram-Schmidt
+      const double* vi = Vb + (size_t)i * len;
+      const double h = wg_dot<NT>(wv, vi, len, red);
+      for (long long e = tid; e < len; e += NT) wv[e] -= h * vi[e];
+      if (tid == 0) H[(size_t)i * nsteps + j] = h;
+      __syncthreads();
+    }
+    const double hn = sqrt(wg_dot<NT>(wv, wv, len, red));
+    if (tid == 0) {
+      H[(size_t)(j + 1) * nsteps + j] = hn;
+      for (int i = 0; i < j; ++i) {                    // previous rotations
+        const double a0 = H[(size_t)i * nsteps + j], a1 = H[(size_t)(i + 1) * nsteps + j];
+        H[(size_t)i * nsteps + j] = cs[i] * a0 + sn[i] * a1;
+        H[(size_t)(i + 1) * nsteps + j] = -sn[i] * a0 + cs[i] * a1;
+      }
+      const double a0 = H[(size_t)j * nsteps + j], a1 = hn;
+      const double r = hypot(a0, a1);
+      cs[j] = r > 0.0 ? a0 / r : 1.0;
+      sn[j] = r > 0.0 ? a1 / r : 0.0;
+      H[(size_t)j * nsteps + j] = r;
+      H[(size_t)(j + 1) * nsteps + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      const double res = fabs(g[j + 1]);
+      int st = 0;
+      if (fixed_its > 0) st = (j + 1 == fixed_its);
+      else st = (res <= tol * beta);
+      if (!st && hn <= 1e-14 * w0) st = 1;
+      stop_flag = st;
+    }
+    __syncthreads();
+    its = j + 1;
+    if (stop_flag) break;
+    double* vn = Vb + (size_t)(j + 1) * len;
+    for (long long e = tid; e < len; e += NT) vn[e] = wv[e] / hn;
+    __syncthreads();
+  }
+  // back substitution H y = g, then x = Z y
+  if (tid == 0) {
+    for (int i = its - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int c = i + 1; c < its; ++c) acc -= H[(size_t)i * nsteps + c] * yv[c];
+      yv[i] = acc / H[(size_t)i * nsteps + i];
+    }
+    *its_out = its;
+  }
+  __syncthreads();
+  for (long long e = tid; e < len; e += NT) {
+    double acc = 0.0;
+    for (int i = 0; i < its; ++i) acc += yv[i] * Zb[(size_t)i * len + e];
+    x[e] = acc;
+  }
+}
+
+hipError_t launch_coarse(const LevelView& L, const double* b, double* x, double tol, int maxit,
+                         int fixed_its, double* work, int* its_out, hipStream_t s) {
+  const int nsteps = fixed_its > 0 ? fixed_its : maxit;
+  const size_t solve_sz = solve_lds_doubles(L.p, L.q, kCoarseThreads);
+  const size_t app_sz = apply_lds_doubles(L.p, L.q, kCoarseThreads);
+  const size_t lds = ((solve_sz > app_sz ? solve_sz : app_sz) + (size_t)(nsteps + 1) * nsteps +
+                      4 * (size_t)nsteps + 1 + kCoarseThreads / kWave) *
+                     sizeof(double);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void*)k_coarse<kCoarseThreads>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_coarse<kCoarseThreads>, dim3(1), dim3(kCoarseThreads), lds, s, L, b, x,
+                     tol, maxit, fixed_its, work, its_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K7: Krylov helpers (deterministic two-stage reductions, no atomics)
+// ---------------------------------------------------------------------------
+
+constexpr int kVecThreads = 256;
+constexpr int kDotChunk = 8;
+
+int krylov_partial_blocks(long long len) {
+  long long g = (len + kVecThreads * 4 - 1) / (kVecThreads * 4);
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+// partial[blk * nvec + i] = sum over this block's elements of basis_i . w
+__global__ __launch_bounds__(kVecThreads) void k_multidot(const double* __restrict__ basis,
+                                                          int nvec, const double* __restrict__ w,
+                                                          long long len,
+                                                          double* __restrict__ partial) {
+  __shared__ double red[kVecThreads / kWave];
+  for (int i0 = 0; i0 < nvec; i0 += kDotChunk) {
+    const int nv = min(kDotChunk, nvec - i0);
+    double acc[kDotChunk];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c) acc[c] = 0.0;
+    for (long long e = blockIdx.x * (long long)kVecThreads + threadIdx.x; e < len;
+         e += (long long)gridDim.x * kVecThreads) {
+      const double we = w[e];
+#pragma unroll
+      for (int c = 0; c < kDotChunk; ++c)
+        if (c < nv) acc[c] += basis[(size_t)(i0 + c) * len + e] * we;
+    }
+    for (int c = 0; c < nv; ++c) {
+      const double s = block_sum<kVecThreads>(acc[c], red);
+      if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nvec + i0 + c] = s;
+    }
+  }
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int nval,
+                                  double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nval) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * nval + i];
+  out[i] = s;
+}
+
+// w += sign * sum_i coef[i] basis_i
+__global__ __launch_bounds__(kVecThreads) void k_multi_axpy(double* __restrict__ w,
+                                                            const double* __restrict__ basis,
+                                                            int nvec,
+                                                            const double* __restrict__ coef,
+                                                            double sign, long long len) {
+  for (long long e = blockIdx.x * (long long)kVecThreads + threadIdx.x; e < len;
+       e += (long long)gridDim.x * kVecThreads) {
+    double acc = 0.0;
+    for (int i = 0; i < nvec; ++i) acc += coef[i] * basis[(size_t)i * len + e];
+    w[e] += sign * acc;
+  }
+}
+
+__global__ void k_scale(double* __restrict__ dst, const double* __restrict__ src, double alpha,
+                        long long len) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < len;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = alpha * src[e];
+}
+
+__global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a,
+                        double b, long long len) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < len;
+       e += (long long)gridDim.x * blockDim.x)
+    y[e] = a * x[e] + b * y[e];
+}
+
+hipError_t launch_multidot(const double* basis, int nvec, const double* w, long long len,
+                           double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot, dim3(krylov_partial_blocks(len)), dim3(kVecThreads), 0, s,
+                     basis, nvec, w, len, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partial, int nblk, int nval, double* out,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3((nval + 255) / 256), dim3(256), 0, s, partial,
+                     nblk, nval, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(double* w, const double* basis, int nvec, const double* coef,
+                             double sign, long long len, hipStream_t s) {
+  hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(len, kVecThreads)), dim3(kVecThreads), 0, s,
+                     w, basis, nvec, coef, sign, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(double* dst, const double* src, double alpha, long long len,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(len, 256)), dim3(256), 0, s, dst, src, alpha, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double* y, const double* x, double a, double b, long long len,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(len, 256)), dim3(256), 0, s, y, x, a, b, len);
+  return hipGetLastError();
+}
+
+}  // namespace pitmg

@@ -1,0 +1,284 @@
+"""ctypes binding of libpitmg.so (declarations: include/pitmg.h).
+
+The functions keep the C names (pitmg_setup, pitmg_apply, pitmg_jacobi_sweep,
+pitmg_coarse_solve, pitmg_vcycle, pitmg_fgmres_solve, ...) and only marshal
+arguments.  Device memory and the stream come from PyTorch; every step of the
+solve runs in the HIP library.  There is no fallback: if the library is not
+built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpitmg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pitmg.h")
+
+PITMG_OK = 0
+PITMG_NOT_CONVERGED = 1
+PITMG_ERR_INVALID = -1
+PITMG_ERR_SINGULAR = -2
+PITMG_ERR_NONFINITE = -3
+PITMG_ERR_HIP = -4
+PITMG_ERR_OOM = -5
+PITMG_ERR_UNSUPPORTED = -6
+
+PROFILE_CLASSES = ("factor", "jacobi", "apply", "transfer", "coarse", "krylov")
+
+
+class pitmg_problem(C.Structure):
+    _fields_ = [("p", C.c_int), ("q", C.c_int), ("n", C.c_int), ("n_levels", C.c_int),
+                ("N", C.POINTER(C.c_void_p)), ("V", C.POINTER(C.c_void_p)),
+                ("Z", C.POINTER(C.c_void_p)), ("N_stride", C.c_longlong),
+                ("V_stride", C.c_longlong), ("Z_stride", C.c_longlong),
+                ("blocks_on_device", C.c_int)]
+
+
+class pitmg_options(C.Structure):
+    _fields_ = [("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_tol", C.c_double),
+                ("coarse_maxit", C.c_int), ("coarse_fixed_its", C.c_int),
+                ("restart", C.c_int), ("maxit", C.c_int), ("transfer_variant", C.c_int)]
+
+
+class pitmg_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres_est", C.c_double),
+                ("relres_true", C.c_double), ("coarse_calls", C.c_int),
+                ("coarse_its_total", C.c_int), ("ms_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PitmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pitmg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpitmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2405_04808_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    sig = {
+        "pitmg_default_options": (None, [C.POINTER(pitmg_options)]),
+        "pitmg_setup": (i, [C.POINTER(vp), C.POINTER(pitmg_problem), C.POINTER(pitmg_options), vp]),
+        "pitmg_refactor": (i, [vp, C.POINTER(pitmg_problem)]),
+        "pitmg_set_options": (i, [vp, C.POINTER(pitmg_options)]),
+        "pitmg_apply": (i, [vp, i, vp, vp]),
+        "pitmg_jacobi_sweep": (i, [vp, i, vp, vp, vp]),
+        "pitmg_coarse_solve": (i, [vp, vp, vp, C.POINTER(i)]),
+        "pitmg_vcycle": (i, [vp, vp, vp]),
+        "pitmg_fgmres_solve": (i, [vp, vp, vp, d, i, C.POINTER(pitmg_stats)]),
+        "pitmg_profile_enable": (i, [vp, i]),
+        "pitmg_profile_read": (i, [vp, i, C.POINTER(i), C.POINTER(d), C.POINTER(d)]),
+        "pitmg_profile_reset": (i, [vp]),
+        "pitmg_failed_block": (i, [vp, C.POINTER(i), C.POINTER(i)]),
+        "pitmg_device_bytes": (C.c_longlong, [vp]),
+        "pitmg_status_string": (C.c_char_p, [i]),
+        "pitmg_last_error": (C.c_char_p, [vp]),
+        "pitmg_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_functions(path: str = HEADER) -> List[str]:
+    """Names of the functions declared in include/pitmg.h."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pitmg_[a-z_]+)\s*\(", txt)))
+
+
+def default_options(**over) -> pitmg_options:
+    o = pitmg_options()
+    load_library().pitmg_default_options(C.byref(o))
+    for k, v in over.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Solver:
+    """One handle of the HIP solver over device copies of the blocks.
+
+    levels: sequence with .N (n_l,p,p), .V, .Z numpy arrays per level (V/Z of
+    leading size 1 when shared by every step); they are uploaded once into
+    torch device tensors which the library borrows.
+    """
+
+    def __init__(self, levels: Sequence, options: Optional[pitmg_options] = None,
+                 device: str = "cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the solver runs on a GPU device")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.options = options if options is not None else default_options()
+        self.h = C.c_void_p()
+        self._upload(levels)
+        pb = self._problem()
+        with torch.cuda.device(self.device):
+            rc = self.lib.pitmg_setup(C.byref(self.h), C.byref(pb), C.byref(self.options),
+                                      C.c_void_p(self.stream.cuda_stream))
+        if rc < 0:
+            msg = self.last_error()
+            self.close()
+            raise PitmgError(rc, msg)
+
+    # -- blocks -----------------------------------------------------------------
+    def _upload(self, levels):
+        torch = self.torch
+        lv0 = levels[0]
+        self.p = lv0.N.shape[1]
+        self.q = lv0.Z.shape[2]
+        self.n = lv0.N.shape[0]
+        self.n_levels = len(levels)
+        self.shared_V = lv0.V.shape[0] == 1 and self.n > 1
+        self.shared_Z = lv0.Z.shape[0] == 1 and self.n > 1
+        self.dN, self.dV, self.dZ = [], [], []
+        for lv in levels:
+            self.dN.append(torch.as_tensor(lv.N, dtype=torch.float64).contiguous().to(self.device))
+            self.dV.append(torch.as_tensor(lv.V, dtype=torch.float64).contiguous().to(self.device))
+            self.dZ.append(torch.as_tensor(lv.Z, dtype=torch.float64).contiguous().to(self.device))
+        self.lens = [(4 * self.p + self.q) * (self.n >> l) for l in range(self.n_levels)]
+
+    def _problem(self) -> pitmg_problem:
+        arr = C.c_void_p * self.n_levels
+        self._pN = arr(*[t.data_ptr() for t in self.dN])
+        self._pV = arr(*[t.data_ptr() for t in self.dV])
+        self._pZ = arr(*[t.data_ptr() for t in self.dZ])
+        pb = pitmg_problem()
+        pb.p, pb.q, pb.n, pb.n_levels = self.p, self.q, self.n, self.n_levels
+        pb.N = C.cast(self._pN, C.POINTER(C.c_void_p))
+        pb.V = C.cast(self._pV, C.POINTER(C.c_void_p))
+        pb.Z = C.cast(self._pZ, C.POINTER(C.c_void_p))
+        pb.N_stride = self.p * self.p
+        pb.V_stride = 0 if self.shared_V else self.p * self.p
+        pb.Z_stride = 0 if self.shared_Z else self.p * self.q
+        pb.blocks_on_device = 1
+        return pb
+
+    def refactor(self, levels):
+        """New blocks (same sizes): copy into the borrowed tensors, re-factor."""
+        for l, lv in enumerate(levels):
+            self.dN[l].copy_(self.torch.as_tensor(lv.N, dtype=self.torch.float64))
+            self.dV[l].copy_(self.torch.as_tensor(lv.V, dtype=self.torch.float64))
+            self.dZ[l].copy_(self.torch.as_tensor(lv.Z, dtype=self.torch.float64))
+        self._check(self.lib.pitmg_refactor(self.h, C.byref(self._problem())))
+
+    def refactor_device(self):
+        """Re-factor from the (already updated) device block tensors."""
+        self._check(self.lib.pitmg_refactor(self.h, C.byref(self._problem())))
+
+    # -- calls ------------------------------------------------------------------
+    def _check(self, rc):
+        if rc < 0:
+            raise PitmgError(rc, self.last_error())
+        return rc
+
+    def last_error(self) -> str:
+        s = self.lib.pitmg_last_error(self.h)
+        return s.decode() if s else ""
+
+    def empty(self, level: int = 0):
+        return self.torch.empty(self.lens[level], dtype=self.torch.float64, device=self.device)
+
+    def set_options(self, **over):
+        o = pitmg_options()
+        C.memmove(C.byref(o), C.byref(self.options), C.sizeof(o))
+        for k, v in over.items():
+            setattr(o, k, v)
+        self._check(self.lib.pitmg_set_options(self.h, C.byref(o)))
+        self.options = o
+
+    def apply(self, x, level: int = 0, out=None):
+        out = self.empty(level) if out is None else out
+        self._check(self.lib.pitmg_apply(self.h, level, _ptr(x), _ptr(out)))
+        return out
+
+    def jacobi_sweep(self, b, y_in=None, level: int = 0, out=None):
+        out = self.empty(level) if out is None else out
+        self._check(self.lib.pitmg_jacobi_sweep(self.h, level, _ptr(b), _ptr(y_in), _ptr(out)))
+        return out
+
+    def coarse_solve(self, b, out=None):
+        out = self.empty(self.n_levels - 1) if out is None else out
+        its = C.c_int(0)
+        self._check(self.lib.pitmg_coarse_solve(self.h, _ptr(b), _ptr(out), C.byref(its)))
+        return out, its.value
+
+    def vcycle(self, r, out=None):
+        out = self.empty(0) if out is None else out
+        self._check(self.lib.pitmg_vcycle(self.h, _ptr(r), _ptr(out)))
+        return out
+
+    def solve(self, b, tol: float = 1e-10, x0=None, out=None):
+        """Returns (x, stats dict, status code >= 0)."""
+        x = out if out is not None else self.empty(0)
+        use_x0 = 0
+        if x0 is not None:
+            x.copy_(x0)
+            use_x0 = 1
+        st = pitmg_stats()
+        rc = self._check(self.lib.pitmg_fgmres_solve(self.h, _ptr(b), _ptr(x), float(tol),
+                                                     use_x0, C.byref(st)))
+        return x, st.as_dict(), rc
+
+    # -- profiling --------------------------------------------------------------
+    def profile(self, on: bool = True):
+        self._check(self.lib.pitmg_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        self._check(self.lib.pitmg_profile_reset(self.h))
+
+    def profile_read(self):
+        out = {}
+        for c, name in enumerate(PROFILE_CLASSES):
+            n = C.c_int(0)
+            ms = C.c_double(0)
+            by = C.c_double(0)
+            self._check(self.lib.pitmg_profile_read(self.h, c, C.byref(n), C.byref(ms), C.byref(by)))
+            out[name] = (n.value, ms.value)
+        return out
+
+    def failed_block(self):
+        lv, k = C.c_int(0), C.c_int(0)
+        self.lib.pitmg_failed_block(self.h, C.byref(lv), C.byref(k))
+        return lv.value, k.value
+
+    def device_bytes(self) -> int:
+        return self.lib.pitmg_device_bytes(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.pitmg_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
