@@ -63,10 +63,13 @@ def fgmres(A, b: np.ndarray, prec, tol: float, restart: int = 30,
            maxit: int = 300, x0: np.ndarray = None):
     """Flexible GMRES with restart.
 
-    prec(v) -> z may be nonlinear.  Convergence: the residual estimate of the
-    current cycle <= tol * ||b||.  Returns (x, info) with info holding the
-    step count, the history of relative residual estimates and the true
-    relative residual ||b - A x|| / ||b|| recomputed at the end.
+    prec(v) -> z may be nonlinear.  A cycle ends when its residual estimate
+    reaches tol * ||b|| (or at breakdown / restart length / maxit); the solve
+    is converged only when the true residual ||b - A x|| <= tol * ||b||, so
+    a cycle whose estimate met the tolerance but whose true residual did not
+    is followed by another cycle from the new residual.  Returns (x, info)
+    with the step count, the history of relative residual estimates and the
+    true relative residual at the end.
     """
     x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
     bnorm = np.linalg.norm(b)
@@ -102,11 +105,9 @@ def fgmres(A, b: np.ndarray, prec, tol: float, restart: int = 30,
             total += 1
             y, res = _lsq(H[:k + 1, :k], beta)
             hist.append(res / bnorm)
-            if res <= tol * bnorm:
-                converged = True
-                stop = True
-                break
-            if H[j + 1, j] <= 1e-14 * wnorm0 or total >= maxit:
+            if res <= tol * bnorm or H[j + 1, j] <= 1e-14 * wnorm0:
+                break                      # end of cycle; true residual decides
+            if total >= maxit:
                 stop = True
                 break
             V.append(w / H[j + 1, j])
@@ -114,5 +115,6 @@ def fgmres(A, b: np.ndarray, prec, tol: float, restart: int = 30,
         if stop:
             break
     relres = np.linalg.norm(b - A @ x) / bnorm
+    converged = relres <= tol
     return x, dict(iters=total, history=hist, relres_true=relres,
                    converged=converged)

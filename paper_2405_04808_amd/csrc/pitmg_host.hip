@@ -291,19 +291,22 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   return PITMG_OK;
 }
 
-// dots of w against nvec basis vectors -> device coef[off..off+nvec)
-int multidot(pitmg_handle* h, const double* basis, int nvec, const double* w, long long len,
-             int off) {
+// dots of w against nvec basis vectors (and w . w when with_self) -> device
+// coef[off .. off + nvec + with_self)
+int multidot(pitmg_handle* h, const double* basis, int nvec, int with_self, const double* w,
+             long long len, int off) {
   const int nb = krylov_partial_blocks(len);
-  int rc = timed(h, 5, [&] { return launch_multidot(basis, nvec, w, len, h->partial, h->stream); });
+  int rc = timed(h, 5, [&] {
+    return launch_multidot(basis, nvec, with_self, w, len, h->partial, h->stream);
+  });
   if (rc) return rc;
   return timed(h, 5, [&] {
-    return launch_reduce_partials(h->partial, nb, nvec, h->coef + off, h->stream);
+    return launch_reduce_partials(h->partial, nb, nvec + with_self, h->coef + off, h->stream);
   });
 }
 
 int device_norm(pitmg_handle* h, const double* x, long long len, double* out) {
-  int rc = multidot(h, x, 1, x, len, 0);
+  int rc = multidot(h, x, 1, 0, x, len, 0);
   if (rc) return rc;
   HIPCHK(h, hipMemcpyAsync(h->hbuf, h->coef, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -388,7 +391,7 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   if ((rc = dalloc(h, (void**)&h->r, len * 8))) return fail(rc);
   const int nb = krylov_partial_blocks(len);
   if ((rc = dalloc(h, (void**)&h->partial, (size_t)nb * (m + 2) * 8))) return fail(rc);
-  const int ncoef = 2 * (m + 1) + 8;
+  const int ncoef = 2 * (m + 2) + 8;
   if ((rc = dalloc(h, (void**)&h->coef, (size_t)ncoef * 8))) return fail(rc);
   if (hipHostMalloc((void**)&h->hbuf, (size_t)ncoef * 8, hipHostMallocDefault) != hipSuccess)
     return fail(set_err(h, PITMG_ERR_OOM, "hipHostMalloc failed"));
@@ -521,29 +524,35 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
       if ((rc = vcycle_level(h, 0, vj, zj))) return rc;
       if ((rc = timed(h, 2, [&] { return launch_apply(v0, zj, nullptr, 1.0, 0.0, h->w, h->stream); })))
         return rc;
-      // classical Gram-Schmidt, twice
+      // classical Gram-Schmidt, twice: h1 = V^T w (with ||w||^2), w -= V h1,
+      // h2 = V^T w, w -= V h2 (with the new ||w||^2)
       const int nv = j + 1;
-      if ((rc = multidot(h, h->w, 1, h->w, len, 2 * (m + 1)))) return rc;
-      if ((rc = multidot(h, h->Vk, nv, h->w, len, 0))) return rc;
+      const int nb = krylov_partial_blocks(len);
+      const int o2 = m + 2, on = 2 * (m + 2);
+      if ((rc = multidot(h, h->Vk, nv, 1, h->w, len, 0))) return rc;
       if ((rc = timed(h, 5, [&] {
-             return launch_multi_axpy(h->w, h->Vk, nv, h->coef, -1.0, len, h->stream);
+             return launch_multi_axpy(h->w, h->Vk, nv, h->coef, -1.0, len, nullptr, h->stream);
            })))
         return rc;
-      if ((rc = multidot(h, h->Vk, nv, h->w, len, m + 1))) return rc;
+      if ((rc = multidot(h, h->Vk, nv, 0, h->w, len, o2))) return rc;
       if ((rc = timed(h, 5, [&] {
-             return launch_multi_axpy(h->w, h->Vk, nv, h->coef + m + 1, -1.0, len, h->stream);
+             return launch_multi_axpy(h->w, h->Vk, nv, h->coef + o2, -1.0, len, h->partial,
+                                      h->stream);
            })))
         return rc;
-      if ((rc = multidot(h, h->w, 1, h->w, len, 2 * (m + 1) + 1))) return rc;
-      HIPCHK(h, hipMemcpyAsync(h->hbuf, h->coef, (2 * (m + 1) + 2) * sizeof(double),
+      if ((rc = timed(h, 5, [&] {
+             return launch_reduce_partials(h->partial, nb, 1, h->coef + on, h->stream);
+           })))
+        return rc;
+      HIPCHK(h, hipMemcpyAsync(h->hbuf, h->coef, (on + 1) * sizeof(double),
                                hipMemcpyDeviceToHost, h->stream));
       HIPCHK(h, hipStreamSynchronize(h->stream));
       if (h->prof) drain(h);
-      const double w0 = std::sqrt(h->hbuf[2 * (m + 1)]);
-      const double hn = std::sqrt(h->hbuf[2 * (m + 1) + 1]);
+      const double w0 = std::sqrt(h->hbuf[nv]);
+      const double hn = std::sqrt(h->hbuf[on]);
       if (!std::isfinite(hn) || !std::isfinite(w0))
         return set_err(h, PITMG_ERR_NONFINITE, "Krylov vector not finite");
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->hbuf[i] + h->hbuf[m + 1 + i];
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->hbuf[i] + h->hbuf[o2 + i];
       H[(size_t)(j + 1) * m + j] = hn;
       for (int i = 0; i < j; ++i) {
         const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
@@ -561,12 +570,10 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
       k = j + 1;
       total++;
       est = std::fabs(g[j + 1]) / bnorm;
-      if (std::fabs(g[j + 1]) <= tol * bnorm) {
-        converged = true;
-        stop = true;
-        break;
-      }
-      if (hn <= 1e-14 * w0 || total >= maxit) {
+      // the estimate (or a breakdown) ends the cycle; the true residual,
+      // computed at the top of the next pass, decides convergence
+      if (std::fabs(g[j + 1]) <= tol * bnorm || hn <= 1e-14 * w0) break;
+      if (total >= maxit) {
         stop = true;
         break;
       }
@@ -583,16 +590,18 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
     for (int i = 0; i < k; ++i) h->hbuf[i] = y[i];
     HIPCHK(h, hipMemcpyAsync(h->coef, h->hbuf, k * sizeof(double), hipMemcpyHostToDevice,
                              h->stream));
-    if ((rc = timed(h, 5, [&] { return launch_multi_axpy(x, h->Zk, k, h->coef, 1.0, len, h->stream); })))
+    if ((rc = timed(h, 5, [&] { return launch_multi_axpy(x, h->Zk, k, h->coef, 1.0, len, nullptr, h->stream); })))
       return rc;
     started_from_zero = false;
     if (stop) break;
   }
-  // true residual
-  if ((rc = timed(h, 2, [&] { return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream); })))
-    return rc;
-  double rn = 0.0;
-  if ((rc = device_norm(h, h->r, len, &rn))) return rc;
+  // true residual (already known when the loop ended on it)
+  double rn = est * bnorm;
+  if (!converged) {
+    if ((rc = timed(h, 2, [&] { return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream); })))
+      return rc;
+    if ((rc = device_norm(h, h->r, len, &rn))) return rc;
+  }
   if (h->prof) drain(h);
   // coarse statistics
   const int ncalls = h->coarse_calls - calls0;

@@ -41,6 +41,12 @@ hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold
                          const double* ecoarse, int variant, double* ynew,
                          hipStream_t s);
 
+// Register-tiled sweep for p == q in {64, 128} (16-byte aligned blocks).
+bool jacobi_tiled_supported(int p, int q);
+hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
+                               const double* ecoarse, int variant, double* ynew,
+                               hipStream_t s);
+
 // out = beta*b + alpha*(A~ x) on one level (b may be NULL when beta == 0).
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b,
                         double alpha, double beta, double* out, hipStream_t s);
@@ -64,15 +70,17 @@ hipError_t launch_coarse(const LevelView& L, const double* b, double* x,
                          double tol, int maxit, int fixed_its, double* work,
                          int* its_out, hipStream_t s);
 
-// Krylov helpers.  Basis vectors are rows of a [k][len] array.
+// Krylov helpers.  Basis vectors are rows of a [k][len] array; partial
+// results are value-major [value][krylov_partial_blocks(len)].
 int krylov_partial_blocks(long long len);
-hipError_t launch_multidot(const double* basis, int nvec, const double* w,
+hipError_t launch_multidot(const double* basis, int nvec, int with_self, const double* w,
                            long long len, double* partial, hipStream_t s);
 hipError_t launch_reduce_partials(const double* partial, int nblk, int nval,
                                   double* out, hipStream_t s);
+// w += sign * basis^T coef; optional per-slice sums of the new w squared.
 hipError_t launch_multi_axpy(double* w, const double* basis, int nvec,
                              const double* coef, double sign, long long len,
-                             hipStream_t s);
+                             double* norm_partial, hipStream_t s);
 hipError_t launch_scale(double* dst, const double* src, double alpha,
                         long long len, hipStream_t s);
 hipError_t launch_axpby(double* y, const double* x, double a, double b,

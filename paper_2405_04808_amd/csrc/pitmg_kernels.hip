@@ -20,6 +20,7 @@
 // +I entries u_k <-> mu_k (Sec. 5.3.2), so a Jacobi sweep needs just u_{k-1}
 // and mu_k of the previous iterate.
 #include "pitmg_internal.h"
+#include "pitmg_device.h"
 #include <climits>
 
 namespace pitmg {
@@ -27,12 +28,6 @@ namespace pitmg {
 // ---------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
 
 // Sum over the work-group; every thread returns the same value.  red must
 // hold NT/64 doubles.  Fixed summation order (deterministic).
@@ -133,22 +128,6 @@ __device__ void block_solve(int p, int q, const double* __restrict__ Nk,
   }
   for (int i = tid; i < q; i += NT) oz[i] = rz[i] - oz[i];
   __syncthreads();
-}
-
-// Value of the interpolated coarse vector (one node-type segment, nc coarse
-// steps, width p) at fine step k (1-based), component i (Sec. 5.3.1).
-__device__ __forceinline__ double interp_node(const double* __restrict__ seg, int nc,
-                                              int p, int k, int i, int variant) {
-  if (variant == 0) {
-    if (k & 1) return seg[(long long)((k + 1) / 2 - 1) * p + i];
-    const int m = k / 2, m2 = m < nc ? m + 1 : nc;
-    return 0.5 * (seg[(long long)(m - 1) * p + i] + seg[(long long)(m2 - 1) * p + i]);
-  }
-  if (!(k & 1)) return seg[(long long)(k / 2 - 1) * p + i];
-  const int m = (k + 1) / 2;
-  const double a = seg[(long long)(m - 1) * p + i];
-  const double b = m >= 2 ? seg[(long long)(m - 2) * p + i] : 0.0;
-  return 0.5 * (a + b);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,8 +315,13 @@ __global__ __launch_bounds__(NT) void k_jacobi(LevelView L, const double* __rest
   for (int i = tid; i < q; i += NT) ynew[T.z + kk * q + i] = oz[i];
 }
 
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
                          const double* ecoarse, int variant, double* ynew, hipStream_t s) {
+  if (jacobi_tiled_supported(L.p, L.q) && aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) &&
+      aligned16(L.Gi))
+    return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, s);
   const size_t lds = solve_lds_doubles(L.p, L.q, kSweepThreads) * sizeof(double);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<kSweepThreads>,
@@ -784,64 +768,123 @@ hipError_t launch_coarse(const LevelView& L, const double* b, double* x, double 
 }
 
 // ---------------------------------------------------------------------------
-// K7: Krylov helpers (deterministic two-stage reductions, no atomics)
+// K7: Krylov helpers.  Vectors are split into krylov_partial_blocks(len)
+// contiguous slices, one work-group each; partial results are stored
+// value-major ([value][slice]) and reduced by one wave per value, in a fixed
+// order (no atomics, bitwise reproducible).
 // ---------------------------------------------------------------------------
 
 constexpr int kVecThreads = 256;
 constexpr int kDotChunk = 8;
+constexpr long long kSliceTarget = 1024;
 
 int krylov_partial_blocks(long long len) {
-  long long g = (len + kVecThreads * 4 - 1) / (kVecThreads * 4);
+  long long g = (len + kSliceTarget - 1) / kSliceTarget;
   if (g > 1024) g = 1024;
   if (g < 1) g = 1;
   return (int)g;
 }
 
-// partial[blk * nvec + i] = sum over this block's elements of basis_i . w
+__device__ __forceinline__ void slice_of(long long len, long long& e0, long long& e1) {
+  const long long per = (len + gridDim.x - 1) / gridDim.x;
+  e0 = (long long)blockIdx.x * per;
+  e1 = e0 + per < len ? e0 + per : len;
+}
+
+// partial[i * nblk + blk] = basis_i . w over this slice, i < nvec; with_self
+// adds value nvec = w . w.
 __global__ __launch_bounds__(kVecThreads) void k_multidot(const double* __restrict__ basis,
-                                                          int nvec, const double* __restrict__ w,
+                                                          int nvec, int with_self,
+                                                          const double* __restrict__ w,
                                                           long long len,
                                                           double* __restrict__ partial) {
-  __shared__ double red[kVecThreads / kWave];
-  for (int i0 = 0; i0 < nvec; i0 += kDotChunk) {
-    const int nv = min(kDotChunk, nvec - i0);
+  __shared__ double red[kVecThreads / kWave][kDotChunk];
+  long long e0, e1;
+  slice_of(len, e0, e1);
+  const int nval = nvec + with_self;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  for (int i0 = 0; i0 < nval; i0 += kDotChunk) {
+    const int nv = min(kDotChunk, nval - i0);
     double acc[kDotChunk];
 #pragma unroll
     for (int c = 0; c < kDotChunk; ++c) acc[c] = 0.0;
-    for (long long e = blockIdx.x * (long long)kVecThreads + threadIdx.x; e < len;
-         e += (long long)gridDim.x * kVecThreads) {
+    for (long long e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
       const double we = w[e];
 #pragma unroll
-      for (int c = 0; c < kDotChunk; ++c)
-        if (c < nv) acc[c] += basis[(size_t)(i0 + c) * len + e] * we;
+      for (int c = 0; c < kDotChunk; ++c) {
+        if (c < nv) {
+          const int i = i0 + c;
+          const double bv = i < nvec ? basis[(size_t)i * len + e] : we;
+          acc[c] += bv * we;
+        }
+      }
     }
-    for (int c = 0; c < nv; ++c) {
-      const double s = block_sum<kVecThreads>(acc[c], red);
-      if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nvec + i0 + c] = s;
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c) acc[c] = wave_sum(acc[c]);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < kDotChunk; ++c) red[wv][c] = acc[c];
     }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kVecThreads / kWave; ++q) t += red[q][threadIdx.x];
+      partial[(size_t)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int nval,
-                                  double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// out[i] = sum over slices of partial[i * nblk + slice]; one wave per value.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial,
+                                                         int nblk, int nval,
+                                                         double* __restrict__ out) {
+  const int i = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
   if (i >= nval) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * nval + i];
-  out[i] = s;
+  for (int b = lane; b < nblk; b += kWave) s += partial[(size_t)i * nblk + b];
+  s = wave_sum(s);
+  if (lane == 0) out[i] = s;
 }
 
-// w += sign * sum_i coef[i] basis_i
+// w += sign * sum_i coef[i] basis_i; if norm_partial != NULL also
+// norm_partial[slice] = sum over the slice of (new w)^2.
 __global__ __launch_bounds__(kVecThreads) void k_multi_axpy(double* __restrict__ w,
                                                             const double* __restrict__ basis,
                                                             int nvec,
                                                             const double* __restrict__ coef,
-                                                            double sign, long long len) {
-  for (long long e = blockIdx.x * (long long)kVecThreads + threadIdx.x; e < len;
-       e += (long long)gridDim.x * kVecThreads) {
+                                                            double sign, long long len,
+                                                            double* __restrict__ norm_partial) {
+  __shared__ double red[kVecThreads / kWave];
+  long long e0, e1;
+  slice_of(len, e0, e1);
+  double nrm = 0.0;
+  for (long long e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
     double acc = 0.0;
-    for (int i = 0; i < nvec; ++i) acc += coef[i] * basis[(size_t)i * len + e];
-    w[e] += sign * acc;
+    int i = 0;
+    for (; i + 4 <= nvec; i += 4) {
+      acc += coef[i] * basis[(size_t)i * len + e];
+      acc += coef[i + 1] * basis[(size_t)(i + 1) * len + e];
+      acc += coef[i + 2] * basis[(size_t)(i + 2) * len + e];
+      acc += coef[i + 3] * basis[(size_t)(i + 3) * len + e];
+    }
+    for (; i < nvec; ++i) acc += coef[i] * basis[(size_t)i * len + e];
+    const double nw = w[e] + sign * acc;
+    w[e] = nw;
+    nrm += nw * nw;
+  }
+  if (norm_partial) {
+    nrm = wave_sum(nrm);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kVecThreads / kWave; ++q) t += red[q];
+      norm_partial[blockIdx.x] = t;
+    }
   }
 }
 
@@ -859,24 +902,25 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, do
     y[e] = a * x[e] + b * y[e];
 }
 
-hipError_t launch_multidot(const double* basis, int nvec, const double* w, long long len,
-                           double* partial, hipStream_t s) {
+hipError_t launch_multidot(const double* basis, int nvec, int with_self, const double* w,
+                           long long len, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(k_multidot, dim3(krylov_partial_blocks(len)), dim3(kVecThreads), 0, s,
-                     basis, nvec, w, len, partial);
+                     basis, nvec, with_self, w, len, partial);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const double* partial, int nblk, int nval, double* out,
                                   hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3((nval + 255) / 256), dim3(256), 0, s, partial,
+  const int per = 256 / kWave;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((nval + per - 1) / per), dim3(256), 0, s, partial,
                      nblk, nval, out);
   return hipGetLastError();
 }
 
 hipError_t launch_multi_axpy(double* w, const double* basis, int nvec, const double* coef,
-                             double sign, long long len, hipStream_t s) {
-  hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(len, kVecThreads)), dim3(kVecThreads), 0, s,
-                     w, basis, nvec, coef, sign, len);
+                             double sign, long long len, double* norm_partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_multi_axpy, dim3(krylov_partial_blocks(len)), dim3(kVecThreads), 0, s,
+                     w, basis, nvec, coef, sign, len, norm_partial);
   return hipGetLastError();
 }
 
