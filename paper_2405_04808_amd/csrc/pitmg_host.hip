@@ -291,27 +291,53 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   return PITMG_OK;
 }
 
-// dots of w against nvec basis vectors (and w . w when with_self) -> device
-// coef[off .. off + nvec + with_self)
-int multidot(pitmg_handle* h, const double* basis, int nvec, int with_self, const double* w,
-             long long len, int off) {
-  const int nb = krylov_partial_blocks(len);
-  int rc = timed(h, 5, [&] {
-    return launch_multidot(basis, nvec, with_self, w, len, h->partial, h->stream);
-  });
+// dots of the first nb basis vectors with x1 (and x2) plus the self dots,
+// reduced into device coef[0 ..) in the value order of launch_dots
+int dots(pitmg_handle* h, const double* basis, int nb, const double* x1, const double* x2,
+         long long len) {
+  const int ns = krylov_slices(len);
+  const int nval = x2 ? 2 * nb + 3 : nb + 1;
+  int rc = timed(h, 5, [&] { return launch_dots(basis, nb, x1, x2, len, h->partial, h->stream); });
   if (rc) return rc;
   return timed(h, 5, [&] {
-    return launch_reduce_partials(h->partial, nb, nvec + with_self, h->coef + off, h->stream);
+    return launch_reduce_partials(h->partial, ns, nval, h->coef, h->stream);
   });
 }
 
-int device_norm(pitmg_handle* h, const double* x, long long len, double* out) {
-  int rc = multidot(h, x, 1, 0, x, len, 0);
-  if (rc) return rc;
-  HIPCHK(h, hipMemcpyAsync(h->hbuf, h->coef, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+int fetch_coef(pitmg_handle* h, int count) {
+  HIPCHK(h, hipMemcpyAsync(h->hbuf, h->coef, count * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->prof) drain(h);
+  return PITMG_OK;
+}
+
+int device_norm(pitmg_handle* h, const double* x, long long len, double* out) {
+  int rc = dots(h, nullptr, 0, x, nullptr, len);
+  if (rc) return rc;
+  if ((rc = fetch_coef(h, 1))) return rc;
   *out = std::sqrt(h->hbuf[0]);
   return PITMG_OK;
+}
+
+// Apply the stored rotations 0..j-1 to column j of H (leading dim m), make
+// rotation j and update g.  Returns |g[j+1]|.
+double givens_column(std::vector<double>& H, int m, int j, std::vector<double>& cs,
+                     std::vector<double>& sn, std::vector<double>& g) {
+  for (int i = 0; i < j; ++i) {
+    const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
+    H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
+    H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
+  }
+  const double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
+  const double rr = std::hypot(a0, a1);
+  cs[j] = rr > 0.0 ? a0 / rr : 1.0;
+  sn[j] = rr > 0.0 ? a1 / rr : 0.0;
+  H[(size_t)j * m + j] = rr;
+  H[(size_t)(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  return std::fabs(g[j + 1]);
 }
 
 }  // namespace
@@ -389,9 +415,10 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   if ((rc = dalloc(h, (void**)&h->Zk, (size_t)m * len * 8))) return fail(rc);
   if ((rc = dalloc(h, (void**)&h->w, len * 8))) return fail(rc);
   if ((rc = dalloc(h, (void**)&h->r, len * 8))) return fail(rc);
-  const int nb = krylov_partial_blocks(len);
-  if ((rc = dalloc(h, (void**)&h->partial, (size_t)nb * (m + 2) * 8))) return fail(rc);
-  const int ncoef = 2 * (m + 2) + 8;
+  const int nb = krylov_slices(len) > krylov_partial_blocks(len) ? krylov_slices(len)
+                                                                   : krylov_partial_blocks(len);
+  if ((rc = dalloc(h, (void**)&h->partial, (size_t)nb * (2 * m + 4) * 8))) return fail(rc);
+  const int ncoef = 2 * (m + 2) + 8;   // >= 2m+3 dot values
   if ((rc = dalloc(h, (void**)&h->coef, (size_t)ncoef * 8))) return fail(rc);
   if (hipHostMalloc((void**)&h->hbuf, (size_t)ncoef * 8, hipHostMallocDefault) != hipSuccess)
     return fail(set_err(h, PITMG_ERR_OOM, "hipHostMalloc failed"));
@@ -470,12 +497,20 @@ int pitmg_vcycle(pitmg_handle* h, const double* r, double* e) {
 
 int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol, int use_x0,
                        pitmg_stats* st) {
+  // Flexible GMRES (Saad 1993).  The Arnoldi basis is built by classical
+  // Gram-Schmidt with delayed re-orthogonalisation: step j takes the dots of
+  // the finished basis q_0..q_{j-1} with both the lagged vector v_j (used as
+  // the preconditioner input) and w = A M(v_j) in one pass, then in one
+  // update pass re-orthogonalises v_j into q_j and orthogonalises w against
+  // q_0..q_j.  The correction of v_j is folded into Hessenberg column j-1,
+  // so A Z = Q H holds with the preconditioned vectors actually used.
   if (!h || !rhs || !x) return PITMG_ERR_INVALID;
   if (!(tol >= 0.0)) return set_err(h, PITMG_ERR_INVALID, "tol must be >= 0");
   const auto t0 = std::chrono::steady_clock::now();
   const long long len = h->lv[0].len;
   const int m = h->opt.restart, maxit = h->opt.maxit;
   const int calls0 = h->coarse_calls;
+  const int ns = krylov_slices(len);
   LevelView v0 = view(h, 0);
   int rc;
   double bnorm = 0.0;
@@ -490,15 +525,18 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
     return PITMG_OK;
   }
   if (!use_x0) HIPCHK(h, hipMemsetAsync(x, 0, len * 8, h->stream));
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hv(m + 1),
+      sv(m + 1);
   int total = 0;
-  bool converged = false, started_from_zero = !use_x0;
+  bool converged = false, first = !use_x0;
   double est = 1.0;
+  auto Vp = [&](int i) { return h->Vk + (size_t)i * len; };
+  auto Zp = [&](int i) { return h->Zk + (size_t)i * len; };
   for (;;) {
     double beta;
-    if (started_from_zero && total == 0) {
+    if (first) {
       beta = bnorm;
-      if ((rc = timed(h, 5, [&] { return launch_scale(h->Vk, rhs, 1.0 / beta, len, h->stream); })))
+      if ((rc = timed(h, 5, [&] { return launch_scale(Vp(0), rhs, 1.0 / beta, len, h->stream); })))
         return rc;
     } else {
       if ((rc = timed(h, 2, [&] { return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream); })))
@@ -511,75 +549,104 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
         break;
       }
       if (total >= maxit) break;
-      if ((rc = timed(h, 5, [&] { return launch_scale(h->Vk, h->r, 1.0 / beta, len, h->stream); })))
+      if ((rc = timed(h, 5, [&] { return launch_scale(Vp(0), h->r, 1.0 / beta, len, h->stream); })))
         return rc;
     }
+    first = false;
+    std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
     bool stop = false;
+    double rho_prev = 0.0;
     for (int j = 0; j < m; ++j) {
-      double* vj = h->Vk + (size_t)j * len;
-      double* zj = h->Zk + (size_t)j * len;
-      if ((rc = vcycle_level(h, 0, vj, zj))) return rc;
-      if ((rc = timed(h, 2, [&] { return launch_apply(v0, zj, nullptr, 1.0, 0.0, h->w, h->stream); })))
+      if ((rc = vcycle_level(h, 0, Vp(j), Zp(j)))) return rc;
+      if ((rc = timed(h, 2, [&] { return launch_apply(v0, Zp(j), nullptr, 1.0, 0.0, h->w, h->stream); })))
         return rc;
-      // classical Gram-Schmidt, twice: h1 = V^T w (with ||w||^2), w -= V h1,
-      // h2 = V^T w, w -= V h2 (with the new ||w||^2)
-      const int nv = j + 1;
-      const int nb = krylov_partial_blocks(len);
-      const int o2 = m + 2, on = 2 * (m + 2);
-      if ((rc = multidot(h, h->Vk, nv, 1, h->w, len, 0))) return rc;
-      if ((rc = timed(h, 5, [&] {
-             return launch_multi_axpy(h->w, h->Vk, nv, h->coef, -1.0, len, nullptr, h->stream);
-           })))
-        return rc;
-      if ((rc = multidot(h, h->Vk, nv, 0, h->w, len, o2))) return rc;
-      if ((rc = timed(h, 5, [&] {
-             return launch_multi_axpy(h->w, h->Vk, nv, h->coef + o2, -1.0, len, h->partial,
-                                      h->stream);
-           })))
-        return rc;
-      if ((rc = timed(h, 5, [&] {
-             return launch_reduce_partials(h->partial, nb, 1, h->coef + on, h->stream);
-           })))
-        return rc;
-      HIPCHK(h, hipMemcpyAsync(h->hbuf, h->coef, (on + 1) * sizeof(double),
-                               hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(h, hipStreamSynchronize(h->stream));
-      if (h->prof) drain(h);
-      const double w0 = std::sqrt(h->hbuf[nv]);
-      const double hn = std::sqrt(h->hbuf[on]);
-      if (!std::isfinite(hn) || !std::isfinite(w0))
-        return set_err(h, PITMG_ERR_NONFINITE, "Krylov vector not finite");
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h->hbuf[i] + h->hbuf[o2 + i];
-      H[(size_t)(j + 1) * m + j] = hn;
+      // one pass: s = Q^T v_j, hh = Q^T w, v_j.v_j, v_j.w, w.w
+      if ((rc = dots(h, h->Vk, j, Vp(j), h->w, len))) return rc;
+      if ((rc = fetch_coef(h, 2 * j + 3))) return rc;
+      const double* cb = h->hbuf;
+      const double vv = cb[2 * j], vw = cb[2 * j + 1], ww = cb[2 * j + 2];
+      double alpha = 1.0, ss = 0.0, sh = 0.0;
       for (int i = 0; i < j; ++i) {
-        const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
+        sv[i] = cb[i];
+        hv[i] = cb[j + i];
+        ss += sv[i] * sv[i];
+        sh += sv[i] * hv[i];
       }
-      const double a0 = H[(size_t)j * m + j];
-      const double rr = std::hypot(a0, hn);
-      cs[j] = rr > 0.0 ? a0 / rr : 1.0;
-      sn[j] = rr > 0.0 ? hn / rr : 0.0;
-      H[(size_t)j * m + j] = rr;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      k = j + 1;
+      if (j > 0) {
+        const double a2 = vv - ss;
+        if (!(a2 > 0.0) || !std::isfinite(a2))
+          return set_err(h, PITMG_ERR_NONFINITE, "lost orthogonality in the Arnoldi basis");
+        alpha = std::sqrt(a2);
+      }
+      const double cq = (vw - sh) / alpha;
+      // one pass: q_j = (v_j - Q s)/alpha, w -= Q hh + cq q_j, |w|^2
+      if ((rc = timed(h, 5, [&] {
+             return launch_update(h->Vk, j, Vp(j), h->w, h->coef, h->coef + j, alpha, cq,
+                                  j > 0 ? 1 : 0, len, h->partial, h->stream);
+           })))
+        return rc;
+      if ((rc = timed(h, 5, [&] {
+             return launch_reduce_partials(h->partial, ns, 1, h->coef, h->stream);
+           })))
+        return rc;
+      if ((rc = fetch_coef(h, 1))) return rc;
+      const double rho = std::sqrt(h->hbuf[0]);
+      if (!std::isfinite(rho) || !std::isfinite(ww))
+        return set_err(h, PITMG_ERR_NONFINITE, "Krylov vector not finite");
+      // finish column j-1: v_j = Q s + alpha q_j, scaled by rho_{j-1}
+      if (j > 0) {
+        for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += rho_prev * sv[i];
+        H[(size_t)j * m + (j - 1)] = rho_prev * alpha;
+        est = givens_column(H, m, j - 1, cs, sn, g) / bnorm;
+      }
+      // column j as far as known: w = Q hh + cq q_j + rho v_{j+1}
+      for (int i = 0; i < j; ++i) H[(size_t)i * m + j] = hv[i];
+      H[(size_t)j * m + j] = cq;
+      H[(size_t)(j + 1) * m + j] = rho;
       total++;
-      est = std::fabs(g[j + 1]) / bnorm;
-      // the estimate (or a breakdown) ends the cycle; the true residual,
-      // computed at the top of the next pass, decides convergence
-      if (std::fabs(g[j + 1]) <= tol * bnorm || hn <= 1e-14 * w0) break;
-      if (total >= maxit) {
-        stop = true;
+      k = j + 1;
+      // estimate with the column as it stands (v_{j+1} not yet re-orthogonalised)
+      double prov;
+      {
+        double a0 = H[(size_t)j * m + j], a1 = rho;
+        std::vector<double> col(j + 2);
+        for (int i = 0; i <= j; ++i) col[i] = H[(size_t)i * m + j];
+        for (int i = 0; i < j; ++i) {
+          const double c0 = col[i], c1 = col[i + 1];
+          col[i] = cs[i] * c0 + sn[i] * c1;
+          col[i + 1] = -sn[i] * c0 + cs[i] * c1;
+        }
+        a0 = col[j];
+        const double rr = std::hypot(a0, a1);
+        prov = rr > 0.0 ? std::fabs(a1 / rr * g[j]) : 0.0;
+      }
+      const bool breakdown = rho <= 1e-14 * std::sqrt(ww);
+      const bool end = prov <= tol * bnorm || breakdown || total >= maxit || j == m - 1;
+      if (!breakdown) {
+        if ((rc = timed(h, 5, [&] { return launch_scale(Vp(j + 1), h->w, 1.0 / rho, len, h->stream); })))
+          return rc;
+      }
+      if (end) {
+        // finish column j: re-orthogonalisation coefficients of v_{j+1}
+        if (!breakdown) {
+          if ((rc = dots(h, h->Vk, j + 1, Vp(j + 1), nullptr, len))) return rc;
+          if ((rc = fetch_coef(h, j + 2))) return rc;
+          double s2 = 0.0;
+          for (int i = 0; i <= j; ++i) {
+            H[(size_t)i * m + j] += rho * h->hbuf[i];
+            s2 += h->hbuf[i] * h->hbuf[i];
+          }
+          const double a2 = h->hbuf[j + 1] - s2;
+          H[(size_t)(j + 1) * m + j] = rho * std::sqrt(a2 > 0.0 ? a2 : 0.0);
+        }
+        est = givens_column(H, m, j, cs, sn, g) / bnorm;
+        if (total >= maxit) stop = true;
         break;
       }
-      double* vn = h->Vk + (size_t)(j + 1) * len;
-      if ((rc = timed(h, 5, [&] { return launch_scale(vn, h->w, 1.0 / hn, len, h->stream); })))
-        return rc;
+      rho_prev = rho;
     }
     // y = H^{-1} g, x += Z y
     for (int i = k - 1; i >= 0; --i) {
@@ -590,9 +657,10 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
     for (int i = 0; i < k; ++i) h->hbuf[i] = y[i];
     HIPCHK(h, hipMemcpyAsync(h->coef, h->hbuf, k * sizeof(double), hipMemcpyHostToDevice,
                              h->stream));
-    if ((rc = timed(h, 5, [&] { return launch_multi_axpy(x, h->Zk, k, h->coef, 1.0, len, nullptr, h->stream); })))
+    if ((rc = timed(h, 5, [&] {
+           return launch_multi_axpy(x, h->Zk, k, h->coef, 1.0, len, nullptr, h->stream);
+         })))
       return rc;
-    started_from_zero = false;
     if (stop) break;
   }
   // true residual (already known when the loop ended on it)
@@ -603,7 +671,6 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
     if ((rc = device_norm(h, h->r, len, &rn))) return rc;
   }
   if (h->prof) drain(h);
-  // coarse statistics
   const int ncalls = h->coarse_calls - calls0;
   long long cits = 0;
   if (ncalls > 0) {

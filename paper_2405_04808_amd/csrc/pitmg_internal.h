@@ -70,11 +70,19 @@ hipError_t launch_coarse(const LevelView& L, const double* b, double* x,
                          double tol, int maxit, int fixed_its, double* work,
                          int* its_out, hipStream_t s);
 
-// Krylov helpers.  Basis vectors are rows of a [k][len] array; partial
-// results are value-major [value][krylov_partial_blocks(len)].
+// Krylov helpers.  Basis vectors are rows of a [k][len] array.  Dot and
+// update kernels work on krylov_slices(len) slices of 1024 elements and store
+// value-major partials [value][slice]; launch_reduce_partials sums them.
+int krylov_slices(long long len);
 int krylov_partial_blocks(long long len);
-hipError_t launch_multidot(const double* basis, int nvec, int with_self, const double* w,
-                           long long len, double* partial, hipStream_t s);
+// values: basis_i.x1 (nb), basis_i.x2 (nb, if x2), x1.x1, [x1.x2, x2.x2]
+hipError_t launch_dots(const double* basis, int nb, const double* x1, const double* x2,
+                       long long len, double* partial, hipStream_t s);
+// x1 <- (x1 - basis^T s)/alpha if reorth;  x2 <- x2 - basis^T h - cq*x1;
+// norm_partial[slice] = |x2|^2 over the slice
+hipError_t launch_update(const double* basis, int nb, double* x1, double* x2,
+                         const double* scoef, const double* hcoef, double alpha, double cq,
+                         int reorth, long long len, double* norm_partial, hipStream_t s);
 hipError_t launch_reduce_partials(const double* partial, int nblk, int nval,
                                   double* out, hipStream_t s);
 // w += sign * basis^T coef; optional per-slice sums of the new w squared.

@@ -785,54 +785,139 @@ int krylov_partial_blocks(long long len) {
   return (int)g;
 }
 
+// slices of exactly kSliceLen elements for the dot / update kernels
+int krylov_slices(long long len) { return (int)((len + 1023) / 1024); }
+
 __device__ __forceinline__ void slice_of(long long len, long long& e0, long long& e1) {
   const long long per = (len + gridDim.x - 1) / gridDim.x;
   e0 = (long long)blockIdx.x * per;
   e1 = e0 + per < len ? e0 + per : len;
 }
 
-// partial[i * nblk + blk] = basis_i . w over this slice, i < nvec; with_self
-// adds value nvec = w . w.
-__global__ __launch_bounds__(kVecThreads) void k_multidot(const double* __restrict__ basis,
-                                                          int nvec, int with_self,
-                                                          const double* __restrict__ w,
-                                                          long long len,
-                                                          double* __restrict__ partial) {
-  __shared__ double red[kVecThreads / kWave][kDotChunk];
-  long long e0, e1;
-  slice_of(len, e0, e1);
-  const int nval = nvec + with_self;
+// Dots of a basis against one or two vectors over this work-group's slice,
+// value-major partials:
+//   value i          = basis_i . x1                 (i < nb)
+//   value nb + i     = basis_i . x2                 (i < nb, when x2)
+//   then x1.x1, and when x2 also x1.x2 and x2.x2.
+// Each wave takes every 4th basis vector and keeps the slices of x1, x2 in
+// registers (kSliceLen / 64 elements per lane): one coalesced pass over the
+// basis, no barriers.
+constexpr int kSliceLen = 1024;
+constexpr int kPerLane = kSliceLen / kWave;
+
+__global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__ basis, int nb,
+                                                      const double* __restrict__ x1,
+                                                      const double* __restrict__ x2,
+                                                      long long len,
+                                                      double* __restrict__ partial) {
+  const long long e0 = (long long)blockIdx.x * kSliceLen;
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-  for (int i0 = 0; i0 < nval; i0 += kDotChunk) {
-    const int nv = min(kDotChunk, nval - i0);
-    double acc[kDotChunk];
+  const int nblk = gridDim.x;
+  const bool two = x2 != nullptr;
+  double a[kPerLane], c[kPerLane];
 #pragma unroll
-    for (int c = 0; c < kDotChunk; ++c) acc[c] = 0.0;
-    for (long long e = e0 + threadIdx.x; e < e1; e += kVecThreads) {
-      const double we = w[e];
+  for (int t = 0; t < kPerLane; ++t) {
+    const long long e = e0 + lane + (long long)kWave * t;
+    a[t] = e < len ? x1[e] : 0.0;
+    c[t] = (two && e < len) ? x2[e] : 0.0;
+  }
+  for (int i = wv; i < nb; i += kVecThreads / kWave) {
+    const double* __restrict__ bi = basis + (size_t)i * len;
+    double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-      for (int c = 0; c < kDotChunk; ++c) {
-        if (c < nv) {
-          const int i = i0 + c;
-          const double bv = i < nvec ? basis[(size_t)i * len + e] : we;
-          acc[c] += bv * we;
-        }
+    for (int t = 0; t < kPerLane; ++t) {
+      const long long e = e0 + lane + (long long)kWave * t;
+      const double bv = e < len ? bi[e] : 0.0;
+      s1 += bv * a[t];
+      s2 += bv * c[t];
+    }
+    s1 = wave_sum(s1);
+    if (two) s2 = wave_sum(s2);
+    if (lane == 0) {
+      partial[(size_t)i * nblk + blockIdx.x] = s1;
+      if (two) partial[(size_t)(nb + i) * nblk + blockIdx.x] = s2;
+    }
+  }
+  if (wv == 0) {
+    double s11 = 0.0, s12 = 0.0, s22 = 0.0;
+#pragma unroll
+    for (int t = 0; t < kPerLane; ++t) {
+      s11 += a[t] * a[t];
+      s12 += a[t] * c[t];
+      s22 += c[t] * c[t];
+    }
+    s11 = wave_sum(s11);
+    if (two) {
+      s12 = wave_sum(s12);
+      s22 = wave_sum(s22);
+    }
+    if (lane == 0) {
+      const int base = two ? 2 * nb : nb;
+      partial[(size_t)base * nblk + blockIdx.x] = s11;
+      if (two) {
+        partial[(size_t)(base + 1) * nblk + blockIdx.x] = s12;
+        partial[(size_t)(base + 2) * nblk + blockIdx.x] = s22;
       }
     }
+  }
+}
+
+// Delayed re-orthogonalisation update over this work-group's slice:
+//   q  = (x1 - basis^T s) / alpha     (written back to x1 when reorth)
+//   x2 = x2 - basis^T h - c q
+// and norm_partial[slice] = sum of the new x2 squared.
+__global__ __launch_bounds__(kVecThreads) void k_update(const double* __restrict__ basis, int nb,
+                                                        double* __restrict__ x1,
+                                                        double* __restrict__ x2,
+                                                        const double* __restrict__ scoef,
+                                                        const double* __restrict__ hcoef,
+                                                        double alpha, double cq, int reorth,
+                                                        long long len,
+                                                        double* __restrict__ norm_partial) {
+  __shared__ double red[kVecThreads / kWave];
+  constexpr int kPer = kSliceLen / kVecThreads;
+  const long long e0 = (long long)blockIdx.x * kSliceLen;
+  double a1[kPer], a2[kPer];
 #pragma unroll
-    for (int c = 0; c < kDotChunk; ++c) acc[c] = wave_sum(acc[c]);
-    if (lane == 0) {
+  for (int t = 0; t < kPer; ++t) {
+    a1[t] = 0.0;
+    a2[t] = 0.0;
+  }
+  for (int i = 0; i < nb; ++i) {
+    const double* __restrict__ bi = basis + (size_t)i * len;
+    const double si = scoef[i], hi = hcoef[i];
 #pragma unroll
-      for (int c = 0; c < kDotChunk; ++c) red[wv][c] = acc[c];
+    for (int t = 0; t < kPer; ++t) {
+      const long long e = e0 + threadIdx.x + (long long)kVecThreads * t;
+      const double bv = e < len ? bi[e] : 0.0;
+      a1[t] += si * bv;
+      a2[t] += hi * bv;
     }
-    __syncthreads();
-    if (threadIdx.x < nv) {
-      double t = 0.0;
+  }
+  double nrm = 0.0;
+  const double inv = 1.0 / alpha;
 #pragma unroll
-      for (int q = 0; q < kVecThreads / kWave; ++q) t += red[q][threadIdx.x];
-      partial[(size_t)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+  for (int t = 0; t < kPer; ++t) {
+    const long long e = e0 + threadIdx.x + (long long)kVecThreads * t;
+    if (e < len) {
+      double q = x1[e];
+      if (reorth) {
+        q = (q - a1[t]) * inv;
+        x1[e] = q;
+      }
+      const double u = x2[e] - a2[t] - cq * q;
+      x2[e] = u;
+      nrm += u * u;
     }
-    __syncthreads();
+  }
+  nrm = wave_sum(nrm);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kVecThreads / kWave; ++q) t += red[q];
+    norm_partial[blockIdx.x] = t;
   }
 }
 
@@ -902,10 +987,18 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, do
     y[e] = a * x[e] + b * y[e];
 }
 
-hipError_t launch_multidot(const double* basis, int nvec, int with_self, const double* w,
-                           long long len, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_multidot, dim3(krylov_partial_blocks(len)), dim3(kVecThreads), 0, s,
-                     basis, nvec, with_self, w, len, partial);
+hipError_t launch_dots(const double* basis, int nb, const double* x1, const double* x2,
+                       long long len, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3(krylov_slices(len)), dim3(kVecThreads), 0, s, basis, nb, x1,
+                     x2, len, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const double* basis, int nb, double* x1, double* x2,
+                         const double* scoef, const double* hcoef, double alpha, double cq,
+                         int reorth, long long len, double* norm_partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(krylov_slices(len)), dim3(kVecThreads), 0, s, basis, nb, x1,
+                     x2, scoef, hcoef, alpha, cq, reorth, len, norm_partial);
   return hipGetLastError();
 }
 
