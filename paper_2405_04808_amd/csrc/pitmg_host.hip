@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -56,7 +57,15 @@ struct pitmg_handle {
   double* partial = nullptr;         // [blocks][restart+2]
   double* coef = nullptr;            // device scalars, 2*(restart+1)+4
   double* hbuf = nullptr;            // pinned host mirror of coef
-  double* coarse_work = nullptr;
+  double* coarse_work = nullptr;     // coarse Krylov bases
+  double* cst = nullptr;             // coarse GMRES state
+  int* ist = nullptr;                // {steps done, stop}
+  bool coarse_fast = false;          // block-parallel SGS available
+  int coarse_k = 1;                  // coarse steps enqueued per solve
+  int* its_pinned = nullptr;         // host copy of the last coarse step count
+  double *cC = nullptr, *cA = nullptr, *cD = nullptr, *cY = nullptr, *cY2 = nullptr,
+         *czero = nullptr;           // coarse work vectors
+  double *Phi = nullptr, *Pf = nullptr, *Qb = nullptr, *pscr = nullptr;
   int* coarse_its = nullptr;         // device log of coarse step counts
   int coarse_log_cap = 0;
   int coarse_calls = 0;
@@ -232,7 +241,74 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
     return set_err(h, PITMG_ERR_SINGULAR,
                    "S_k not positive definite at level " + std::to_string(code >> 20) +
                        ", step " + std::to_string((code & 0xFFFFF) + 1));
+  if (h->coarse_fast) {
+    LevelView vc = view(h, h->L - 1);
+    int rc = timed(h, 0, [&] {
+      return launch_propagators(vc, h->pscr, h->Phi, h->Pf, h->Qb, h->stream);
+    });
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
   return PITMG_OK;
+}
+
+// Coarsest level: GMRES + SGS.  Enqueue coarse_k steps with the
+// block-parallel SGS (no host wait), then a finish kernel that continues
+// block by block if the test was not met and forms x = Z y.
+int coarse_solve(pitmg_handle* h, const double* b, double* out) {
+  const pitmg_options& o = h->opt;
+  const int l = h->L - 1;
+  LevelView v = view(h, l);
+  const TypeMajor T(h->p, h->q, v.n);
+  const long long len = T.len;
+  const int cap = h->coarse_cap;
+  const int nsteps = o.coarse_fixed_its > 0 ? o.coarse_fixed_its : o.coarse_maxit;
+  int K = o.coarse_fixed_its > 0 ? o.coarse_fixed_its : std::min(h->coarse_k, nsteps);
+  if (!h->coarse_fast) K = 0;
+  int* its = h->coarse_its + (h->coarse_calls % h->coarse_log_cap);
+  h->coarse_calls++;
+  double* Vb = h->coarse_work;
+  double* Zb = Vb + (size_t)(cap + 1) * len;
+  double* W = Zb + (size_t)cap * len;
+  const int var = o.transfer_variant;
+  int rc = timed(h, 4, [&] {
+    return launch_coarse_init(b, len, Vb, h->cst, h->ist, cap, h->stream);
+  });
+  if (rc) return rc;
+  for (int j = 0; j < K; ++j) {
+    double* vj = Vb + (size_t)j * len;
+    double* zj = Zb + (size_t)j * len;
+    // forward sweep: c = D^{-1} v, a_u = P c_u, a = D^{-1}(v - L a)
+    if ((rc = timed(h, 4, [&] { return launch_jacobi(v, vj, nullptr, nullptr, var, h->cC, h->stream); })))
+      return rc;
+    if ((rc = timed(h, 4, [&] {
+           return launch_gemv_tri(h->Pf, v.n, h->p, 0, h->cC + T.u, h->cY + T.u, h->stream);
+         })))
+      return rc;
+    if ((rc = timed(h, 4, [&] { return launch_jacobi(v, vj, h->cY, nullptr, var, h->cA, h->stream); })))
+      return rc;
+    // backward sweep: y_mu = Q a_mu, z = a - D^{-1} L^T y
+    if ((rc = timed(h, 4, [&] {
+           return launch_gemv_tri(h->Qb, v.n, h->p, 1, h->cA + T.m, h->cY2 + T.m, h->stream);
+         })))
+      return rc;
+    if ((rc = timed(h, 4, [&] {
+           return launch_jacobi(v, h->czero, h->cY2, nullptr, var, h->cD, h->stream);
+         })))
+      return rc;
+    if ((rc = timed(h, 4, [&] { return launch_add(zj, h->cA, h->cD, len, h->stream); }))) return rc;
+    if ((rc = timed(h, 4, [&] { return launch_apply(v, zj, nullptr, 1.0, 0.0, W, h->stream); })))
+      return rc;
+    if ((rc = timed(h, 4, [&] {
+           return launch_coarse_arnoldi(j, W, Vb, len, h->cst, h->ist, cap, o.coarse_tol,
+                                        o.coarse_fixed_its, nsteps, h->stream);
+         })))
+      return rc;
+  }
+  return timed(h, 4, [&] {
+    return launch_coarse_finish(v, out, o.coarse_tol, o.coarse_fixed_its, nsteps,
+                                h->coarse_work, h->cst, h->ist, cap, its, h->stream);
+  });
 }
 
 // MG_l(b) -> out (Alg. 1 recursed; zero initial guess on every level).
@@ -240,14 +316,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   const pitmg_options& o = h->opt;
   const int var = o.transfer_variant;
   LevelView v = view(h, l);
-  if (l == h->L - 1) {
-    int* its = h->coarse_its + (h->coarse_calls % h->coarse_log_cap);
-    h->coarse_calls++;
-    return timed(h, 4, [&] {
-      return launch_coarse(v, b, out, o.coarse_tol, o.coarse_maxit, o.coarse_fixed_its,
-                           h->coarse_work, its, h->stream);
-    });
-  }
+  if (l == h->L - 1) return coarse_solve(h, b, out);
   LevelBuf& B = h->lv[l];
   LevelBuf& C = h->lv[l + 1];
   double* bufs[2] = {B.y0, B.y1};
@@ -426,6 +495,31 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   if ((rc = dalloc(h, (void**)&h->coarse_work,
                    coarse_work_doubles(h->p, h->q, lc.n, h->coarse_cap) * 8)))
     return fail(rc);
+  {
+    const long long lenc = lc.len;
+    const long long ncp = (long long)lc.n * h->p;
+    if ((rc = dalloc(h, (void**)&h->cst, coarse_state_doubles(h->coarse_cap) * 8))) return fail(rc);
+    if ((rc = dalloc(h, (void**)&h->ist, 2 * sizeof(int)))) return fail(rc);
+    h->coarse_fast = ncp <= 4096;
+    if (h->coarse_fast) {
+      double** vecs[6] = {&h->cC, &h->cA, &h->cD, &h->cY, &h->cY2, &h->czero};
+      for (auto pp2 : vecs) {
+        if ((rc = dalloc(h, (void**)pp2, lenc * 8))) return fail(rc);
+        if (hipMemset(*pp2, 0, lenc * 8) != hipSuccess)
+          return fail(set_err(h, PITMG_ERR_HIP, "hipMemset failed"));
+      }
+      if ((rc = dalloc(h, (void**)&h->Phi, (size_t)lc.n * pp * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&h->pscr, 2 * (size_t)lc.n * pp * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&h->Pf, (size_t)ncp * ncp * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&h->Qb, (size_t)ncp * ncp * 8))) return fail(rc);
+      if (hipMemset(h->Pf, 0, (size_t)ncp * ncp * 8) != hipSuccess ||
+          hipMemset(h->Qb, 0, (size_t)ncp * ncp * 8) != hipSuccess)
+        return fail(set_err(h, PITMG_ERR_HIP, "hipMemset failed"));
+    }
+    if (hipHostMalloc((void**)&h->its_pinned, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+      return fail(set_err(h, PITMG_ERR_OOM, "hipHostMalloc failed"));
+    h->its_pinned[0] = 1;
+  }
   h->coarse_log_cap = h->maxit_cap + 64;
   if ((rc = dalloc(h, (void**)&h->coarse_its, (size_t)h->coarse_log_cap * sizeof(int))))
     return fail(rc);
@@ -563,9 +657,13 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
       if ((rc = vcycle_level(h, 0, Vp(j), Zp(j)))) return rc;
       if ((rc = timed(h, 2, [&] { return launch_apply(v0, Zp(j), nullptr, 1.0, 0.0, h->w, h->stream); })))
         return rc;
+      HIPCHK(h, hipMemcpyAsync(h->its_pinned,
+                               h->coarse_its + ((h->coarse_calls - 1) % h->coarse_log_cap),
+                               sizeof(int), hipMemcpyDeviceToHost, h->stream));
       // one pass: s = Q^T v_j, hh = Q^T w, v_j.v_j, v_j.w, w.w
       if ((rc = dots(h, h->Vk, j, Vp(j), h->w, len))) return rc;
       if ((rc = fetch_coef(h, 2 * j + 3))) return rc;
+      h->coarse_k = std::max(1, h->its_pinned[0]);   // coarse steps to enqueue next time
       const double* cb = h->hbuf;
       const double vv = cb[2 * j], vw = cb[2 * j + 1], ww = cb[2 * j + 2];
       double alpha = 1.0, ss = 0.0, sh = 0.0;
@@ -771,6 +869,19 @@ void pitmg_destroy(pitmg_handle* h) {
   if (h->hbuf) hipHostFree(h->hbuf);
   hipFree(h->coarse_work);
   hipFree(h->coarse_its);
+  hipFree(h->cst);
+  hipFree(h->ist);
+  hipFree(h->cC);
+  hipFree(h->cA);
+  hipFree(h->cD);
+  hipFree(h->cY);
+  hipFree(h->cY2);
+  hipFree(h->czero);
+  hipFree(h->Phi);
+  hipFree(h->pscr);
+  hipFree(h->Pf);
+  hipFree(h->Qb);
+  if (h->its_pinned) hipHostFree(h->its_pinned);
   hipFree(h->fail);
   delete h;
 }

@@ -63,12 +63,27 @@ hipError_t launch_restrict(int p, int q, int nf, const double* r, int variant,
 hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant,
                              double* y, hipStream_t s);
 
-// Coarse GMRES + SGS in one work-group.  work: device scratch of
-// coarse_work_doubles(...) doubles; its_out: device int.
-size_t coarse_work_doubles(int p, int q, int n, int maxit);
-hipError_t launch_coarse(const LevelView& L, const double* b, double* x,
-                         double tol, int maxit, int fixed_its, double* work,
-                         int* its_out, hipStream_t s);
+// Coarse GMRES + SGS (pitmg_coarse.hip).  work: coarse_work_doubles(...)
+// doubles holding the coarse Krylov bases; cst: coarse_state_doubles(cap)
+// doubles of GMRES state; ist: 2 device ints {steps done, stop}.
+size_t coarse_work_doubles(int p, int q, int n, int cap);
+size_t coarse_state_doubles(int cap);
+hipError_t launch_coarse_init(const double* b, long long len, double* Vb, double* cst, int* ist,
+                              int cap, hipStream_t s);
+hipError_t launch_coarse_arnoldi(int j, double* w, double* Vb, long long len, double* cst,
+                                 int* ist, int cap, double tol, int fixed_its, int nsteps,
+                                 hipStream_t s);
+hipError_t launch_coarse_finish(const LevelView& L, double* x, double tol, int fixed_its,
+                                int nsteps, double* work, double* cst, int* ist, int cap,
+                                int* its_out, hipStream_t s);
+// Block propagators Phi_s = N_s^T S_s^{-1} V_s and the block-triangular
+// products P (forward SGS chain) and Q (backward chain), each (n p)^2.
+// scratch: 2 n p^2 doubles; P and Q must be zero-filled beforehand.
+hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, double* P,
+                              double* Q, hipStream_t s);
+hipError_t launch_gemv_tri(const double* M, int nc, int p, int upper, const double* x, double* y,
+                           hipStream_t s);
+hipError_t launch_add(double* z, const double* a, const double* d, long long len, hipStream_t s);
 
 // Krylov helpers.  Basis vectors are rows of a [k][len] array.  Dot and
 // update kernels work on krylov_slices(len) slices of 1024 elements and store

@@ -21,114 +21,10 @@
 // and mu_k of the previous iterate.
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
+#include "pitmg_blocks.h"
 #include <climits>
 
 namespace pitmg {
-
-// ---------------------------------------------------------------------------
-// small device helpers
-// ---------------------------------------------------------------------------
-
-// Sum over the work-group; every thread returns the same value.  red must
-// hold NT/64 doubles.  Fixed summation order (deterministic).
-template <int NT>
-__device__ double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  __syncthreads();
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double r = 0.0;
-#pragma unroll
-  for (int i = 0; i < NT / kWave; ++i) r += red[i];
-  return r;
-}
-
-// out[j] = sum_{i in rows} A[i*lda + j] * x[i] for j < ncols; rows are
-// 0..nrows-1, or j..nrows-1 when `lower`.  Consecutive threads take
-// consecutive columns (coalesced rows); row slices are summed through part
-// (NT doubles).  Ends with a barrier.
-template <int NT>
-__device__ void col_dot(int nrows, int ncols, const double* __restrict__ A,
-                        long long lda, const double* x, bool lower,
-                        double* part, double* out) {
-  const int tid = threadIdx.x;
-  for (int j0 = 0; j0 < ncols; j0 += NT) {
-    const int nc = min(NT, ncols - j0);
-    const int G = NT / nc;
-    const int jl = tid % nc, g = tid / nc;
-    const int j = j0 + jl;
-    double acc = 0.0;
-    if (g < G) {
-      int i = g;
-      if (lower && j > g) i = g + ((j - g + G - 1) / G) * G;
-      for (; i < nrows; i += G) acc += A[(long long)i * lda + j] * x[i];
-      part[g * nc + jl] = acc;
-    }
-    __syncthreads();
-    if (tid < nc) {
-      double s = 0.0;
-      for (int gg = 0; gg < G; ++gg) s += part[gg * nc + tid];
-      out[j0 + tid] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// Solve D_k (v,u,z,lambda,mu) = (rv,ru,rz,rl,rm) for one time-step block with
-// the whole work-group.  All vector arguments live in LDS; the matrices in
-// global memory.  has_vm = false for block 1 (no v, mu; V unused).
-template <int NT>
-__device__ void block_solve(int p, int q, const double* __restrict__ Nk,
-                            const double* __restrict__ Vk,
-                            const double* __restrict__ Zk,
-                            const double* __restrict__ Gk, bool has_vm,
-                            const double* rv, const double* ru, const double* rz,
-                            const double* rl, const double* rm, double* ov,
-                            double* ou, double* oz, double* ol, double* om,
-                            double* t, double* s, double* part) {
-  constexpr int NW = NT / kWave;
-  const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
-  // t = N r_u + Z r_z - V r_m - r_l   (row dots, one wave per row)
-  for (int i = w; i < p; i += NW) {
-    double acc = 0.0;
-    const double* Ni = Nk + (long long)i * p;
-    for (int j = lane; j < p; j += kWave) acc += Ni[j] * ru[j];
-    if (has_vm) {
-      const double* Vi = Vk + (long long)i * p;
-      for (int j = lane; j < p; j += kWave) acc -= Vi[j] * rm[j];
-    }
-    const double* Zi = Zk + (long long)i * q;
-    for (int j = lane; j < q; j += kWave) acc += Zi[j] * rz[j];
-    acc = wave_sum(acc);
-    if (lane == 0) t[i] = acc - rl[i];
-  }
-  __syncthreads();
-  // s = G^{-1} t  (lower triangular)
-  for (int i = w; i < p; i += NW) {
-    double acc = 0.0;
-    const double* Gr = Gk + (long long)i * p;
-    for (int j = lane; j <= i; j += kWave) acc += Gr[j] * t[j];
-    acc = wave_sum(acc);
-    if (lane == 0) s[i] = acc;
-  }
-  __syncthreads();
-  // lambda = G^{-T} s
-  col_dot<NT>(p, p, Gk, p, s, true, part, ol);
-  // u = r_u - N^T lambda ; z = r_z - Z^T lambda ; mu = V^T lambda - r_m - r_v
-  col_dot<NT>(p, p, Nk, p, ol, false, part, ou);
-  col_dot<NT>(p, q, Zk, q, ol, false, part, oz);
-  if (has_vm) col_dot<NT>(p, p, Vk, p, ol, false, part, om);
-  for (int i = tid; i < p; i += NT) {
-    ou[i] = ru[i] - ou[i];
-    if (has_vm) {
-      om[i] = om[i] - rm[i] - rv[i];
-      ov[i] = -rm[i];
-    }
-  }
-  for (int i = tid; i < q; i += NT) oz[i] = rz[i] - oz[i];
-  __syncthreads();
-}
 
 // ---------------------------------------------------------------------------
 // K1/K2: factorisation of S_k = N N^T + Z Z^T, Cholesky, triangular inverse
@@ -234,11 +130,6 @@ hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail,
 
 constexpr int kSweepThreads = 256;
 
-// LDS doubles used by one block solve: 5 inputs, 5 outputs, t, s, part.
-__host__ __device__ inline size_t solve_lds_doubles(int p, int q, int nt) {
-  return (size_t)8 * p + 2 * q + 2 * p + nt + (size_t)2 * p;
-}
-
 template <int NT>
 __global__ __launch_bounds__(NT) void k_jacobi(LevelView L, const double* __restrict__ b,
                                                const double* __restrict__ yold,
@@ -337,80 +228,8 @@ hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold
 // K4: out = beta*b + alpha*(A~ x), one work-group per time step
 // ---------------------------------------------------------------------------
 
-// Rows of time-major block k (1-based): v_{k-1}, u_k, z_k, lambda_k,
-// mu_{k-1}; block n also writes block n+1's rows v_n, mu_n.
-template <int NT>
-__device__ void apply_step(const LevelView& L, int k, const double* __restrict__ x,
-                           const double* __restrict__ b, double alpha, double beta,
-                           double* __restrict__ out, double* sm) {
-  const int p = L.p, q = L.q, n = L.n;
-  const TypeMajor T(p, q, n);
-  const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
-  constexpr int NW = NT / kWave;
-  const bool hv = k >= 2;
-  const long long kk = k - 1;
-  const double* Nk = L.N + kk * L.sN;
-  const double* Vk = L.V + kk * L.sV;
-  const double* Zk = L.Z + kk * L.sZ;
-  double* xu = sm;
-  double* xv = xu + p;
-  double* xz = xv + p;
-  double* xl = xz + q;
-  double* t = xl + p;
-  double* part = t + p;
-  for (int i = tid; i < p; i += NT) {
-    xu[i] = x[T.u + kk * p + i];
-    xl[i] = x[T.l + kk * p + i];
-    xv[i] = hv ? x[T.v + (kk - 1) * p + i] : 0.0;
-  }
-  for (int i = tid; i < q; i += NT) xz[i] = x[T.z + kk * q + i];
-  __syncthreads();
-  auto put = [&](long long idx, double val) {
-    out[idx] = (beta != 0.0 ? beta * b[idx] : 0.0) + alpha * val;
-  };
-  // row lambda_k = N u_k + V v_{k-1} + Z z_k
-  for (int i = w; i < p; i += NW) {
-    double acc = 0.0;
-    const double* Ni = Nk + (long long)i * p;
-    for (int j = lane; j < p; j += kWave) acc += Ni[j] * xu[j];
-    if (hv) {
-      const double* Vi = Vk + (long long)i * p;
-      for (int j = lane; j < p; j += kWave) acc += Vi[j] * xv[j];
-    }
-    const double* Zi = Zk + (long long)i * q;
-    for (int j = lane; j < q; j += kWave) acc += Zi[j] * xz[j];
-    acc = wave_sum(acc);
-    if (lane == 0) put(T.l + kk * p + i, acc);
-  }
-  // rows u_k, z_k, v_{k-1}
-  col_dot<NT>(p, p, Nk, p, xl, false, part, t);
-  for (int i = tid; i < p; i += NT)
-    put(T.u + kk * p + i, xu[i] + t[i] + x[T.m + kk * p + i]);
-  __syncthreads();
-  col_dot<NT>(p, q, Zk, q, xl, false, part, t);
-  for (int i = tid; i < q; i += NT) put(T.z + kk * q + i, xz[i] + t[i]);
-  __syncthreads();
-  if (hv) {
-    col_dot<NT>(p, p, Vk, p, xl, false, part, t);
-    for (int i = tid; i < p; i += NT) {
-      put(T.v + (kk - 1) * p + i, xv[i] + t[i] - x[T.m + (kk - 1) * p + i]);
-      put(T.m + (kk - 1) * p + i, x[T.u + (kk - 1) * p + i] - xv[i]);
-    }
-    __syncthreads();
-  }
-  if (k == n) {
-    for (int i = tid; i < p; i += NT) {
-      const double vn = x[T.v + kk * p + i], mn = x[T.m + kk * p + i];
-      put(T.v + kk * p + i, vn - mn);
-      put(T.m + kk * p + i, xu[i] - vn);
-    }
-  }
-  __syncthreads();
-}
-
 constexpr int kApplyThreads = 256;
 
-__host__ __device__ inline size_t apply_lds_doubles(int p, int q, int nt) { return (size_t)4 * p + q + nt + p; }
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_apply(LevelView L, const double* __restrict__ x,
@@ -537,233 +356,6 @@ hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant,
   const TypeMajor Tf(p, q, nf);
   hipLaunchKernelGGL(k_interp_add, dim3(grid_for(Tf.len, 256)), dim3(256), 0, s, p, q, nf, e,
                      variant, y);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// K6: coarse GMRES right-preconditioned by symmetric block Gauss-Seidel, in
-// one work-group (the coarse grid is small; the solve is serial in time).
-// ---------------------------------------------------------------------------
-
-constexpr int kCoarseThreads = 1024;
-
-size_t coarse_work_doubles(int p, int q, int n, int maxit) {
-  const TypeMajor T(p, q, n);
-  return (size_t)T.len * (2 * (size_t)maxit + 3);
-}
-
-template <int NT>
-__device__ double wg_dot(const double* a, const double* b, long long len, double* red) {
-  double acc = 0.0;
-  for (long long i = threadIdx.x; i < len; i += NT) acc += a[i] * b[i];
-  return block_sum<NT>(acc, red);
-}
-
-// dst = M^{-1} src for M = (D+L) D^{-1} (D+L^T): forward block sweep into a,
-// then the backward sweep dst_k = a_k - D_k^{-1} (L^T dst)_k.
-template <int NT>
-__device__ void sgs_apply(const LevelView& L, const double* src, double* a, double* dst,
-                          double* sm) {
-  const int p = L.p, q = L.q, n = L.n;
-  const TypeMajor T(p, q, n);
-  const int tid = threadIdx.x;
-  double* rv = sm;
-  double* ru = rv + p;
-  double* rz = ru + p;
-  double* rl = rz + q;
-  double* rm = rl + p;
-  double* ov = rm + p;
-  double* ou = ov + p;
-  double* oz = ou + p;
-  double* ol = oz + q;
-  double* om = ol + p;
-  double* t = om + p;
-  double* s = t + p;
-  double* part = s + p;
-  // forward: (D + L) a = src, blocks 1..n+1
-  for (int kb = 0; kb <= n; ++kb) {
-    if (kb == n) {
-      for (int i = tid; i < p; i += NT) {
-        const long long o = (long long)(n - 1) * p + i;
-        const double rmm = src[T.m + o] - a[T.u + o];
-        a[T.v + o] = -rmm;
-        a[T.m + o] = -rmm - src[T.v + o];
-      }
-      __syncthreads();
-      break;
-    }
-    const int k = kb + 1;
-    const bool hv = k >= 2;
-    const long long kk = k - 1;
-    for (int i = tid; i < p; i += NT) {
-      ru[i] = src[T.u + kk * p + i];
-      rl[i] = src[T.l + kk * p + i];
-      rv[i] = hv ? src[T.v + (kk - 1) * p + i] : 0.0;
-      rm[i] = hv ? src[T.m + (kk - 1) * p + i] - a[T.u + (kk - 1) * p + i] : 0.0;
-    }
-    for (int i = tid; i < q; i += NT) rz[i] = src[T.z + kk * q + i];
-    __syncthreads();
-    block_solve<NT>(p, q, L.N + kk * L.sN, L.V + kk * L.sV, L.Z + kk * L.sZ,
-                    L.Gi + kk * p * p, hv, rv, ru, rz, rl, rm, ov, ou, oz, ol, om, t, s, part);
-    for (int i = tid; i < p; i += NT) {
-      a[T.u + kk * p + i] = ou[i];
-      a[T.l + kk * p + i] = ol[i];
-      if (hv) {
-        a[T.v + (kk - 1) * p + i] = ov[i];
-        a[T.m + (kk - 1) * p + i] = om[i];
-      }
-    }
-    for (int i = tid; i < q; i += NT) a[T.z + kk * q + i] = oz[i];
-    __syncthreads();
-  }
-  // backward: block n+1 has no upper coupling
-  for (int i = tid; i < p; i += NT) {
-    const long long o = (long long)(n - 1) * p + i;
-    dst[T.v + o] = a[T.v + o];
-    dst[T.m + o] = a[T.m + o];
-  }
-  __syncthreads();
-  for (int k = n; k >= 1; --k) {
-    const bool hv = k >= 2;
-    const long long kk = k - 1;
-    for (int i = tid; i < p; i += NT) {
-      rv[i] = 0.0;
-      rm[i] = 0.0;
-      rl[i] = 0.0;
-      ru[i] = dst[T.m + kk * p + i];          // (L^T dst) in row u_k = mu_k
-    }
-    for (int i = tid; i < q; i += NT) rz[i] = 0.0;
-    __syncthreads();
-    block_solve<NT>(p, q, L.N + kk * L.sN, L.V + kk * L.sV, L.Z + kk * L.sZ,
-                    L.Gi + kk * p * p, hv, rv, ru, rz, rl, rm, ov, ou, oz, ol, om, t, s, part);
-    for (int i = tid; i < p; i += NT) {
-      dst[T.u + kk * p + i] = a[T.u + kk * p + i] - ou[i];
-      dst[T.l + kk * p + i] = a[T.l + kk * p + i] - ol[i];
-      if (hv) {
-        dst[T.v + (kk - 1) * p + i] = a[T.v + (kk - 1) * p + i] - ov[i];
-        dst[T.m + (kk - 1) * p + i] = a[T.m + (kk - 1) * p + i] - om[i];
-      }
-    }
-    for (int i = tid; i < q; i += NT) dst[T.z + kk * q + i] = a[T.z + kk * q + i] - oz[i];
-    __syncthreads();
-  }
-}
-
-template <int NT>
-__global__ __launch_bounds__(NT) void k_coarse(LevelView L, const double* __restrict__ b,
-                                               double* __restrict__ x, double tol, int maxit,
-                                               int fixed_its, double* __restrict__ work,
-                                               int* its_out) {
-  extern __shared__ double sm[];
-  const int p = L.p, q = L.q, n = L.n;
-  const TypeMajor T(p, q, n);
-  const long long len = T.len;
-  const int tid = threadIdx.x;
-  const int nsteps = fixed_its > 0 ? fixed_its : maxit;
-  double* Vb = work;                                   // [nsteps+1][len]
-  double* Zb = Vb + (size_t)(nsteps + 1) * len;        // [nsteps][len]
-  double* wv = Zb + (size_t)nsteps * len;
-  double* av = wv + len;
-  // LDS: solver scratch, then H (nsteps+1 x nsteps), cs, sn, g, y, red
-  const size_t solve_sz = solve_lds_doubles(p, q, NT);
-  const size_t app_sz = apply_lds_doubles(p, q, NT);
-  double* ssolve = sm;
-  double* H = sm + (solve_sz > app_sz ? solve_sz : app_sz);
-  double* cs = H + (size_t)(nsteps + 1) * nsteps;
-  double* sn = cs + nsteps;
-  double* g = sn + nsteps;
-  double* yv = g + nsteps + 1;
-  double* red = yv + nsteps;
-  __shared__ int stop_flag;
-
-  const double beta = sqrt(wg_dot<NT>(b, b, len, red));
-  if (beta == 0.0) {
-    for (long long i = tid; i < len; i += NT) x[i] = 0.0;
-    if (tid == 0) *its_out = 0;
-    return;
-  }
-  for (long long i = tid; i < len; i += NT) Vb[i] = b[i] / beta;
-  if (tid == 0) {
-    g[0] = beta;
-    for (int i = 1; i <= nsteps; ++i) g[i] = 0.0;
-  }
-  __syncthreads();
-  int its = 0;
-  for (int j = 0; j < nsteps; ++j) {
-    double* vj = Vb + (size_t)j * len;
-    double* zj = Zb + (size_t)j * len;
-    sgs_apply<NT>(L, vj, av, zj, ssolve);
-    for (int k = 1; k <= n; ++k) apply_step<NT>(L, k, zj, nullptr, 1.0, 0.0, wv, ssolve);
-    __syncthreads();
-    const double w0 = sqrt(wg_dot<NT>(wv, wv, len, red));
-    for (int i = 0; i <= j; ++i) {                     // modified Gram-Schmidt
-      const double* vi = Vb + (size_t)i * len;
-      const double h = wg_dot<NT>(wv, vi, len, red);
-      for (long long e = tid; e < len; e += NT) wv[e] -= h * vi[e];
-      if (tid == 0) H[(size_t)i * nsteps + j] = h;
-      __syncthreads();
-    }
-    const double hn = sqrt(wg_dot<NT>(wv, wv, len, red));
-    if (tid == 0) {
-      H[(size_t)(j + 1) * nsteps + j] = hn;
-      for (int i = 0; i < j; ++i) {                    // previous rotations
-        const double a0 = H[(size_t)i * nsteps + j], a1 = H[(size_t)(i + 1) * nsteps + j];
-        H[(size_t)i * nsteps + j] = cs[i] * a0 + sn[i] * a1;
-        H[(size_t)(i + 1) * nsteps + j] = -sn[i] * a0 + cs[i] * a1;
-      }
-      const double a0 = H[(size_t)j * nsteps + j], a1 = hn;
-      const double r = hypot(a0, a1);
-      cs[j] = r > 0.0 ? a0 / r : 1.0;
-      sn[j] = r > 0.0 ? a1 / r : 0.0;
-      H[(size_t)j * nsteps + j] = r;
-      H[(size_t)(j + 1) * nsteps + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      const double res = fabs(g[j + 1]);
-      int st = 0;
-      if (fixed_its > 0) st = (j + 1 == fixed_its);
-      else st = (res <= tol * beta);
-      if (!st && hn <= 1e-14 * w0) st = 1;
-      stop_flag = st;
-    }
-    __syncthreads();
-    its = j + 1;
-    if (stop_flag) break;
-    double* vn = Vb + (size_t)(j + 1) * len;
-    for (long long e = tid; e < len; e += NT) vn[e] = wv[e] / hn;
-    __syncthreads();
-  }
-  // back substitution H y = g, then x = Z y
-  if (tid == 0) {
-    for (int i = its - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int c = i + 1; c < its; ++c) acc -= H[(size_t)i * nsteps + c] * yv[c];
-      yv[i] = acc / H[(size_t)i * nsteps + i];
-    }
-    *its_out = its;
-  }
-  __syncthreads();
-  for (long long e = tid; e < len; e += NT) {
-    double acc = 0.0;
-    for (int i = 0; i < its; ++i) acc += yv[i] * Zb[(size_t)i * len + e];
-    x[e] = acc;
-  }
-}
-
-hipError_t launch_coarse(const LevelView& L, const double* b, double* x, double tol, int maxit,
-                         int fixed_its, double* work, int* its_out, hipStream_t s) {
-  const int nsteps = fixed_its > 0 ? fixed_its : maxit;
-  const size_t solve_sz = solve_lds_doubles(L.p, L.q, kCoarseThreads);
-  const size_t app_sz = apply_lds_doubles(L.p, L.q, kCoarseThreads);
-  const size_t lds = ((solve_sz > app_sz ? solve_sz : app_sz) + (size_t)(nsteps + 1) * nsteps +
-                      4 * (size_t)nsteps + 1 + kCoarseThreads / kWave) *
-                     sizeof(double);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void*)k_coarse<kCoarseThreads>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_coarse<kCoarseThreads>, dim3(1), dim3(kCoarseThreads), lds, s, L, b, x,
-                     tol, maxit, fixed_its, work, its_out);
   return hipGetLastError();
 }
 
