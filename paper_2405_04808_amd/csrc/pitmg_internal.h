@@ -47,6 +47,12 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
                                const double* ecoarse, int variant, double* ynew,
                                hipStream_t s);
 
+// Sweep for V and Z~ shared by every step (stride 0), p == q in {64, 128}.
+bool jacobi_shared_supported(const LevelView& L);
+hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
+                                const double* ecoarse, int variant, double* ynew,
+                                hipStream_t s);
+
 // out = beta*b + alpha*(A~ x) on one level (b may be NULL when beta == 0).
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b,
                         double alpha, double beta, double* out, hipStream_t s);

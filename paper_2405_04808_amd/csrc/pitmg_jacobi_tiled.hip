@@ -91,4 +91,248 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Sweep for V_k and Z~_k shared by every step (stride 0, the theta = 1 case).
+//
+// A work-group takes up to kMaxSteps consecutive steps.  The products with
+// the shared blocks are formed for all of its steps in one pass over each
+// shared block (Z~ r_z - V r_mu before, Z~^T lambda and V^T lambda after the
+// per-step solves), so each shared block crosses the CU's load path once per
+// work-group instead of twice per step.  Per step only N_k and G_k^{-1} are
+// read (register tiles, as in k_jacobi_tiled); the tiles of the next step are
+// requested as soon as the current step has finished with them (G^{-1}
+// after lambda, N after N^T lambda), so the HBM stream continues through the
+// reductions.
+// ---------------------------------------------------------------------------
+
+namespace {
+constexpr int kMaxSteps = 4;
+}
+
+template <int RT, int CT>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
+    LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
+    const double* __restrict__ ec, int variant, double* __restrict__ ynew, int per_wg) {
+  using TS = TiledSolve<RT, CT>;
+  constexpr int P = TS::P;
+  constexpr int G = kTiledThreads / P;                   // row groups of the post pass
+  __shared__ double sru[kMaxSteps][P], srz[kMaxSteps][P], srm[kMaxSteps][P],
+      srl[kMaxSteps][P], srv[kMaxSteps][P], sT[kMaxSteps][P], slam[kMaxSteps][P];
+  __shared__ double st[P], ss[P], red[kTiledWaves * P];
+  __shared__ double pz[G][kMaxSteps][P], pv[G][kMaxSteps][P];
+  const int tid = threadIdx.x, a = tid / 16, bq = tid % 16;
+  const int r0 = RT * a;
+  const int n = L.n;
+  const TypeMajor T(P, P, n);
+  const int nc = n / 2;
+  const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
+  const int k0 = blockIdx.x * per_wg + 1;                // first step (1-based)
+  const int nb = min(per_wg, n - k0 + 1);                // steps of this work-group
+  const double* __restrict__ Vs = L.V;                   // shared blocks
+  const double* __restrict__ Zs = L.Z;
+
+  auto cu = [&](int k1, int i) -> double {
+    double v = yold ? yold[T.u + (long long)(k1 - 1) * P + i] : 0.0;
+    if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
+    return v;
+  };
+  auto cm = [&](int k1, int i) -> double {
+    double v = yold ? yold[T.m + (long long)(k1 - 1) * P + i] : 0.0;
+    if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
+    return v;
+  };
+
+  // tiles of the first step in flight while the right-hand sides are gathered
+  typename TS::Regs R;
+  TS::load(L, k0 - 1, R);
+  for (int bi = 0; bi < nb; ++bi) {
+    const int k = k0 + bi;
+    const long long kk = k - 1;
+    for (int i = tid; i < P; i += kTiledThreads) {
+      sru[bi][i] = b[T.u + kk * P + i] - cm(k, i);
+      srl[bi][i] = b[T.l + kk * P + i];
+      srz[bi][i] = b[T.z + kk * P + i];
+      if (k >= 2) {
+        srv[bi][i] = b[T.v + (kk - 1) * P + i];
+        srm[bi][i] = b[T.m + (kk - 1) * P + i] - cu(k - 1, i);
+      } else {
+        srv[bi][i] = 0.0;
+        srm[bi][i] = 0.0;
+      }
+    }
+  }
+  if (k0 + nb - 1 == n) {                                // block n+1 = (v_n, mu_n)
+    for (int i = tid; i < P; i += kTiledThreads) {
+      const double rvv = b[T.v + (long long)(n - 1) * P + i];
+      const double rmm = b[T.m + (long long)(n - 1) * P + i] - cu(n, i);
+      ynew[T.v + (long long)(n - 1) * P + i] = -rmm;
+      ynew[T.m + (long long)(n - 1) * P + i] = -rmm - rvv;
+    }
+  }
+  __syncthreads();
+
+  // sT[s] = Z~ r_z[s] - V r_mu[s] for every step: one pass over Z~ and V
+  {
+    double acc[kMaxSteps][RT];
+#pragma unroll
+    for (int s = 0; s < kMaxSteps; ++s)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[s][r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      double zr[CT], vr[CT];
+      tile_load_row<CT>(Zs + (long long)(r0 + r) * P, zr);
+      tile_load_row<CT>(Vs + (long long)(r0 + r) * P, vr);
+#pragma unroll
+      for (int s = 0; s < kMaxSteps; ++s) {
+        if (s < nb) {
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+            acc[s][r] += zr[c] * srz[s][tile_col(c)] - vr[c] * srm[s][tile_col(c)];
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxSteps; ++s) {
+      if (s < nb) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const double v = tile_sum16(acc[s][r]);
+          if (bq == 0) sT[s][r0 + r] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int bi = 0; bi < nb; ++bi) {
+    const long long kk = k0 + bi - 1;
+    // t = N r_u + (Z~ r_z - V r_mu) - r_l
+    double acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) s += R.nt[r][c] * sru[bi][tile_col(c)];
+      acc[r] = tile_sum16(s);
+    }
+    if (bq == 0) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) st[r0 + r] = acc[r] + sT[bi][r0 + r] - srl[bi][r0 + r];
+    }
+    __syncthreads();
+    // s = G^{-1} t
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) s += R.gt[r][c] * st[tile_col(c)];
+      acc[r] = tile_sum16(s);
+    }
+    if (bq == 0) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) ss[r0 + r] = acc[r];
+    }
+    __syncthreads();
+    // lambda = G^{-T} s
+    double cacc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) s += R.gt[r][c] * ss[r0 + r];
+      cacc[c] = s;
+    }
+    TS::col_partial(cacc, red);
+    __syncthreads();
+    for (int j = tid; j < P; j += kTiledThreads) slam[bi][j] = TS::col_total(red, j);
+    __syncthreads();
+    if (bi + 1 < nb) TS::load_g(L, kk + 1, R);             // G^{-1} of the next step
+    // u = r_u - N^T lambda
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) s += R.nt[r][c] * slam[bi][r0 + r];
+      cacc[c] = s;
+    }
+    TS::col_partial(cacc, red);
+    __syncthreads();
+    if (bi + 1 < nb) TS::load_n(L, kk + 1, R);             // N of the next step
+    for (int i = tid; i < P; i += kTiledThreads) {
+      ynew[T.u + kk * P + i] = sru[bi][i] - TS::col_total(red, i);
+      ynew[T.l + kk * P + i] = slam[bi][i];
+    }
+    __syncthreads();
+  }
+
+  // Z~^T lambda and V^T lambda for every step: one pass over Z~ and V.
+  // Thread (j, g) = (tid % P, tid / P) sums rows i = g, g+G, ...
+  {
+    const int j = tid % P, g = tid / P;
+    double za[kMaxSteps], va[kMaxSteps];
+#pragma unroll
+    for (int s = 0; s < kMaxSteps; ++s) {
+      za[s] = 0.0;
+      va[s] = 0.0;
+    }
+    for (int i = g; i < P; i += G) {
+      const double zi = Zs[(long long)i * P + j], vi = Vs[(long long)i * P + j];
+#pragma unroll
+      for (int s = 0; s < kMaxSteps; ++s) {
+        if (s < nb) {
+          za[s] += zi * slam[s][i];
+          va[s] += vi * slam[s][i];
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxSteps; ++s) {
+      pz[g][s][j] = za[s];
+      pv[g][s][j] = va[s];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * P; idx += kTiledThreads) {
+    const int s = idx / P, i = idx % P;
+    const long long kk = k0 + s - 1;
+    double zt = 0.0, vt = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      zt += pz[g][s][i];
+      vt += pv[g][s][i];
+    }
+    ynew[T.z + kk * P + i] = srz[s][i] - zt;
+    if (kk >= 1) {
+      ynew[T.m + (kk - 1) * P + i] = vt - srm[s][i] - srv[s][i];
+      ynew[T.v + (kk - 1) * P + i] = -srm[s][i];
+    }
+  }
+}
+
+bool jacobi_shared_supported(const LevelView& L) {
+  return L.sV == 0 && L.sZ == 0 && L.p == L.q && (L.p == 128 || L.p == 64);
+}
+
+hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
+                                const double* ecoarse, int variant, double* ynew,
+                                hipStream_t s) {
+  // steps per work-group: enough to keep the grid near one work-group per CU
+  int per = (L.n + 255) / 256;
+  if (per > kMaxSteps) per = kMaxSteps;
+  if (per < 1) per = 1;
+  const int nwg = (L.n + per - 1) / per;
+  if (L.p == 128) {
+    hipLaunchKernelGGL((k_jacobi_shared<4, 8>), dim3(nwg), dim3(kTiledThreads), 0, s, L, b,
+                       yold, ecoarse, variant, ynew, per);
+  } else if (L.p == 64) {
+    hipLaunchKernelGGL((k_jacobi_shared<2, 4>), dim3(nwg), dim3(kTiledThreads), 0, s, L, b,
+                       yold, ecoarse, variant, ynew, per);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace pitmg

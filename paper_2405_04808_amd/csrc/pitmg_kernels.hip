@@ -210,8 +210,10 @@ static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
                          const double* ecoarse, int variant, double* ynew, hipStream_t s) {
-  if (jacobi_tiled_supported(L.p, L.q) && aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) &&
-      aligned16(L.Gi))
+  const bool al = aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi);
+  if (al && jacobi_shared_supported(L))
+    return launch_jacobi_shared(L, b, yold, ecoarse, variant, ynew, s);
+  if (al && jacobi_tiled_supported(L.p, L.q))
     return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, s);
   const size_t lds = solve_lds_doubles(L.p, L.q, kSweepThreads) * sizeof(double);
   if (lds > 64 * 1024) {

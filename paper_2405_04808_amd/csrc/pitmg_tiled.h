@@ -1,9 +1,11 @@
 // Register-tiled solve of one time-step block D_k x = r for p = q = 32*RT =
 // 16*CT with 512 threads (8 waves).
 //
-// Thread (a, b) = (tid / 16, tid % 16) owns rows [RT a, RT a + RT) and
-// columns [CT b, CT b + CT) of N_k and of the inverse Cholesky factor
-// G_k^{-1}; both tiles stay in registers, so every entry is read once and
+// Thread (a, b) = (tid / 16, tid % 16) owns rows [RT a, RT a + RT) and the
+// CT columns 2b + 32c + e (c < CT/2, e < 2) of N_k and of the inverse
+// Cholesky factor G_k^{-1}, so each 16-byte load instruction of a wave reads
+// four fully used 256-byte row segments.  Both tiles stay in registers, so
+// every entry is read once and
 // serves the row products (t = N r_u + ..., s = G^{-1} t) and the column
 // products (lambda = G^{-T} s, N^T lambda).  Row sums reduce over the 16
 // lanes that share a; column sums over the 4 row groups of a wave (lane xor
@@ -19,13 +21,38 @@ namespace pitmg {
 constexpr int kTiledThreads = 512;
 constexpr int kTiledWaves = kTiledThreads / kWave;
 
+// Column of the thread's c-th tile entry (c < CT): 2b + 32 (c / 2) + c % 2.
+__device__ __forceinline__ int tile_col(int c) { return 2 * (threadIdx.x % 16) + 32 * (c >> 1) + (c & 1); }
+
+// Load the thread's CT entries of one row (row points at the row start).
 template <int CT>
-__device__ __forceinline__ void tile_load_row(const double* __restrict__ src, double (&dst)[CT]) {
+__device__ __forceinline__ void tile_load_row(const double* __restrict__ row, double (&dst)[CT]) {
+  const double* src = row + 2 * (threadIdx.x % 16);
 #pragma unroll
   for (int c = 0; c < CT; c += 2) {
-    const double2 v = *reinterpret_cast<const double2*>(src + c);
+    const double2 v = *reinterpret_cast<const double2*>(src + 16 * c);
     dst[c] = v.x;
     dst[c + 1] = v.y;
+  }
+}
+
+// Same for a lower-triangular row i: pairs wholly above the diagonal are
+// zero in memory and are not loaded.
+template <int CT>
+__device__ __forceinline__ void tile_load_row_lower(const double* __restrict__ row, int i,
+                                                    double (&dst)[CT]) {
+  const int j0 = 2 * (threadIdx.x % 16);
+  const double* src = row + j0;
+#pragma unroll
+  for (int c = 0; c < CT; c += 2) {
+    if (j0 + 16 * c <= i) {
+      const double2 v = *reinterpret_cast<const double2*>(src + 16 * c);
+      dst[c] = v.x;
+      dst[c + 1] = v.y;
+    } else {
+      dst[c] = 0.0;
+      dst[c + 1] = 0.0;
+    }
   }
 }
 
@@ -52,27 +79,28 @@ struct TiledSolve {
 
   // Issue the loads of the N_k and G_k^{-1} tiles of step kk (0-based).
   __device__ __forceinline__ static void load(const LevelView& L, long long kk, Regs& R) {
-    const int tid = threadIdx.x, a = tid / 16, bq = tid % 16;
-    const int r0 = RT * a, c0 = CT * bq;
+    load_n(L, kk, R);
+    load_g(L, kk, R);
+  }
+
+  __device__ __forceinline__ static void load_n(const LevelView& L, long long kk, Regs& R) {
+    const int r0 = RT * (threadIdx.x / 16);
     const double* __restrict__ Nk = L.N + kk * L.sN;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) tile_load_row<CT>(Nk + (long long)(r0 + r) * P, R.nt[r]);
+  }
+
+  __device__ __forceinline__ static void load_g(const LevelView& L, long long kk, Regs& R) {
+    const int r0 = RT * (threadIdx.x / 16);
     const double* __restrict__ Gk = L.Gi + kk * (long long)P * P;
 #pragma unroll
-    for (int r = 0; r < RT; ++r) tile_load_row<CT>(Nk + (long long)(r0 + r) * P + c0, R.nt[r]);
-    const bool gnz = c0 <= r0 + RT - 1;        // tile meets the lower triangle
-#pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      if (gnz) {
-        tile_load_row<CT>(Gk + (long long)(r0 + r) * P + c0, R.gt[r]);
-      } else {
-#pragma unroll
-        for (int c = 0; c < CT; ++c) R.gt[r][c] = 0.0;
-      }
-    }
+    for (int r = 0; r < RT; ++r)
+      tile_load_row_lower<CT>(Gk + (long long)(r0 + r) * P, r0 + r, R.gt[r]);
   }
 
   // Column partials of one thread -> per-wave slot of red (lanes 0..15).
   __device__ __forceinline__ static void col_partial(double (&v)[CT], double* red) {
-    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, bq = tid % 16;
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       v[c] += __shfl_xor(v[c], 16, kWave);
@@ -80,7 +108,7 @@ struct TiledSolve {
     }
     if (lane < 16) {
 #pragma unroll
-      for (int c = 0; c < CT; ++c) red[w * P + CT * bq + c] = v[c];
+      for (int c = 0; c < CT; ++c) red[w * P + tile_col(c)] = v[c];
     }
   }
 
@@ -99,7 +127,7 @@ struct TiledSolve {
                                                const double* srz, const double* srm,
                                                const double* srl, double* ol, double* scr) {
     const int tid = threadIdx.x, a = tid / 16, bq = tid % 16;
-    const int r0 = RT * a, c0 = CT * bq;
+    const int r0 = RT * a;
     double* st = scr;
     double* ss = scr + P;
     double* red = scr + 2 * P;
@@ -111,16 +139,16 @@ struct TiledSolve {
     for (int r = 0; r < RT; ++r) {
       double s = 0.0;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += R.nt[r][c] * sru[c0 + c];
+      for (int c = 0; c < CT; ++c) s += R.nt[r][c] * sru[tile_col(c)];
       double zr[CT];
-      tile_load_row<CT>(Zk + (long long)(r0 + r) * P + c0, zr);
+      tile_load_row<CT>(Zk + (long long)(r0 + r) * P, zr);
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += zr[c] * srz[c0 + c];
+      for (int c = 0; c < CT; ++c) s += zr[c] * srz[tile_col(c)];
       if (hv) {
         double vr[CT];
-        tile_load_row<CT>(Vk + (long long)(r0 + r) * P + c0, vr);
+        tile_load_row<CT>(Vk + (long long)(r0 + r) * P, vr);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) s -= vr[c] * srm[c0 + c];
+        for (int c = 0; c < CT; ++c) s -= vr[c] * srm[tile_col(c)];
       }
       acc[r] = tile_sum16(s);
     }
@@ -134,7 +162,7 @@ struct TiledSolve {
     for (int r = 0; r < RT; ++r) {
       double s = 0.0;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += R.gt[r][c] * st[c0 + c];
+      for (int c = 0; c < CT; ++c) s += R.gt[r][c] * st[tile_col(c)];
       acc[r] = tile_sum16(s);
     }
     if (bq == 0) {
@@ -171,7 +199,7 @@ struct TiledSolve {
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
         double zr[CT];
-        tile_load_row<CT>(Zk + (long long)(r0 + r) * P + c0, zr);
+        tile_load_row<CT>(Zk + (long long)(r0 + r) * P, zr);
 #pragma unroll
         for (int c = 0; c < CT; ++c) zacc[c] += zr[c] * ol[r0 + r];
       }
@@ -184,7 +212,7 @@ struct TiledSolve {
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
         double vr[CT];
-        tile_load_row<CT>(Vk + (long long)(r0 + r) * P + c0, vr);
+        tile_load_row<CT>(Vk + (long long)(r0 + r) * P, vr);
 #pragma unroll
         for (int c = 0; c < CT; ++c) vacc[c] += vr[c] * ol[r0 + r];
       }

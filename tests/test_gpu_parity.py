@@ -26,6 +26,10 @@ CASES = {
     "burgers_p12": dict(kind="burgers", nx=12, nu=0.01, n=32, n_levels=3, seed=12),
     "burgers_ragged_p70": dict(kind="burgers", nx=70, nu=0.01, n=16, n_levels=2, seed=13),
     "burgers_p150": dict(kind="burgers", nx=150, nu=0.02, n=8, n_levels=2, seed=14),
+    # register-tiled sweeps: shared V/Z~ (theta = 1) and per-step V/Z~ (theta = 1/2)
+    "burgers_p64": dict(kind="burgers", nx=64, nu=0.01, n=32, n_levels=3, seed=16),
+    "burgers_p64_theta05": dict(kind="burgers", nx=64, nu=0.01, n=16, n_levels=2, seed=15,
+                                theta=0.5),
 }
 
 
@@ -138,7 +142,8 @@ def test_vcycle_fixed_coarse_steps(name, opt):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["vdp64", "burgers_p12", "burgers_ragged_p70"])
+@pytest.mark.parametrize("name", ["vdp64", "burgers_p12", "burgers_ragged_p70", "burgers_p64",
+                                  "burgers_p64_theta05"])
 def test_fgmres_matches_oracle(name):
     prob, rng, b, s = setup_case(name, restart=400, maxit=400)
     H = Hierarchy(prob.levels, mg_opts(s.options))
