@@ -98,6 +98,12 @@ typedef struct {
                                   fine step 2k-1, last even fine step copies the
                                   last coarse value); 1: time-aligned
                                   (coarse k <-> fine 2k)                        */
+  int smoother_fp32;           /* k > 0: the k finest levels (all levels above
+                                  the coarsest when k >= n_levels-1) factor and
+                                  smooth in FP32 from FP32 copies of N, V, Z~;
+                                  the finest-level residual, the coarse solve,
+                                  FGMRES and Arnoldi stay FP64.  0: all FP64.
+                                  Fixed at setup.                               */
 } pitmg_options;
 
 typedef struct {
@@ -111,7 +117,7 @@ typedef struct {
 } pitmg_stats;
 
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
- * transfer_variant 0. */
+ * transfer_variant 0, smoother_fp32 0. */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and

@@ -26,17 +26,17 @@ __device__ double block_sum(double v, double* red) {
 // 0..nrows-1, or j..nrows-1 when `lower`.  Consecutive threads take
 // consecutive columns (coalesced rows); row slices are summed through part
 // (NT doubles).  Ends with a barrier.
-template <int NT>
-__device__ void col_dot(int nrows, int ncols, const double* __restrict__ A,
-                        long long lda, const double* x, bool lower,
-                        double* part, double* out) {
+template <int NT, class T = double>
+__device__ void col_dot(int nrows, int ncols, const T* __restrict__ A,
+                        long long lda, const T* x, bool lower,
+                        T* part, T* out) {
   const int tid = threadIdx.x;
   for (int j0 = 0; j0 < ncols; j0 += NT) {
     const int nc = min(NT, ncols - j0);
     const int G = NT / nc;
     const int jl = tid % nc, g = tid / nc;
     const int j = j0 + jl;
-    double acc = 0.0;
+    T acc = 0;
     if (g < G) {
       int i = g;
       if (lower && j > g) i = g + ((j - g + G - 1) / G) * G;
@@ -45,7 +45,7 @@ __device__ void col_dot(int nrows, int ncols, const double* __restrict__ A,
     }
     __syncthreads();
     if (tid < nc) {
-      double s = 0.0;
+      T s = 0;
       for (int gg = 0; gg < G; ++gg) s += part[gg * nc + tid];
       out[j0 + tid] = s;
     }
@@ -56,27 +56,27 @@ __device__ void col_dot(int nrows, int ncols, const double* __restrict__ A,
 // Solve D_k (v,u,z,lambda,mu) = (rv,ru,rz,rl,rm) for one time-step block with
 // the whole work-group.  All vector arguments live in LDS; the matrices in
 // global memory.  has_vm = false for block 1 (no v, mu; V unused).
-template <int NT>
-__device__ void block_solve(int p, int q, const double* __restrict__ Nk,
-                            const double* __restrict__ Vk,
-                            const double* __restrict__ Zk,
-                            const double* __restrict__ Gk, bool has_vm,
-                            const double* rv, const double* ru, const double* rz,
-                            const double* rl, const double* rm, double* ov,
-                            double* ou, double* oz, double* ol, double* om,
-                            double* t, double* s, double* part) {
+template <int NT, class T = double>
+__device__ void block_solve(int p, int q, const T* __restrict__ Nk,
+                            const T* __restrict__ Vk,
+                            const T* __restrict__ Zk,
+                            const T* __restrict__ Gk, bool has_vm,
+                            const T* rv, const T* ru, const T* rz,
+                            const T* rl, const T* rm, T* ov,
+                            T* ou, T* oz, T* ol, T* om,
+                            T* t, T* s, T* part) {
   constexpr int NW = NT / kWave;
   const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
   // t = N r_u + Z r_z - V r_m - r_l   (row dots, one wave per row)
   for (int i = w; i < p; i += NW) {
-    double acc = 0.0;
-    const double* Ni = Nk + (long long)i * p;
+    T acc = 0;
+    const T* Ni = Nk + (long long)i * p;
     for (int j = lane; j < p; j += kWave) acc += Ni[j] * ru[j];
     if (has_vm) {
-      const double* Vi = Vk + (long long)i * p;
+      const T* Vi = Vk + (long long)i * p;
       for (int j = lane; j < p; j += kWave) acc -= Vi[j] * rm[j];
     }
-    const double* Zi = Zk + (long long)i * q;
+    const T* Zi = Zk + (long long)i * q;
     for (int j = lane; j < q; j += kWave) acc += Zi[j] * rz[j];
     acc = wave_sum(acc);
     if (lane == 0) t[i] = acc - rl[i];
@@ -84,19 +84,19 @@ __device__ void block_solve(int p, int q, const double* __restrict__ Nk,
   __syncthreads();
   // s = G^{-1} t  (lower triangular)
   for (int i = w; i < p; i += NW) {
-    double acc = 0.0;
-    const double* Gr = Gk + (long long)i * p;
+    T acc = 0;
+    const T* Gr = Gk + (long long)i * p;
     for (int j = lane; j <= i; j += kWave) acc += Gr[j] * t[j];
     acc = wave_sum(acc);
     if (lane == 0) s[i] = acc;
   }
   __syncthreads();
   // lambda = G^{-T} s
-  col_dot<NT>(p, p, Gk, p, s, true, part, ol);
+  col_dot<NT, T>(p, p, Gk, p, s, true, part, ol);
   // u = r_u - N^T lambda ; z = r_z - Z^T lambda ; mu = V^T lambda - r_m - r_v
-  col_dot<NT>(p, p, Nk, p, ol, false, part, ou);
-  col_dot<NT>(p, q, Zk, q, ol, false, part, oz);
-  if (has_vm) col_dot<NT>(p, p, Vk, p, ol, false, part, om);
+  col_dot<NT, T>(p, p, Nk, p, ol, false, part, ou);
+  col_dot<NT, T>(p, q, Zk, q, ol, false, part, oz);
+  if (has_vm) col_dot<NT, T>(p, p, Vk, p, ol, false, part, om);
   for (int i = tid; i < p; i += NT) {
     ou[i] = ru[i] - ou[i];
     if (has_vm) {

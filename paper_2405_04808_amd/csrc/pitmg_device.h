@@ -4,7 +4,8 @@
 
 namespace pitmg {
 
-__device__ __forceinline__ double wave_sum(double v) {
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;

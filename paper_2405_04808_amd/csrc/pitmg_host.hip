@@ -32,6 +32,12 @@ struct LevelBuf {
   double* y0 = nullptr;              // smoothing ping-pong buffers
   double* y1 = nullptr;
   double* out = nullptr;             // result of this level's cycle (l >= 1)
+  double* res = nullptr;             // explicit FP64 residual (finest level, FP32 smoother)
+  bool fp32 = false;                 // this level smooths in FP32
+  float* N32 = nullptr;
+  float* V32 = nullptr;
+  float* Z32 = nullptr;
+  float* Gi32 = nullptr;
 };
 
 struct ProfRec {
@@ -161,6 +167,13 @@ LevelView view(const pitmg_handle* h, int l) {
   v.Z = b.Z;
   v.sZ = b.sZ;
   v.Gi = b.Gi;
+  if (b.fp32) {
+    v.fp32 = 1;
+    v.N32 = b.N32;
+    v.V32 = b.V32;
+    v.Z32 = b.Z32;
+    v.Gi32 = b.Gi32;
+  }
   return v;
 }
 
@@ -173,6 +186,7 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "restart and maxit must be >= 1");
   if (o.transfer_variant != 0 && o.transfer_variant != 1)
     return set_err(h, PITMG_ERR_INVALID, "transfer_variant must be 0 or 1");
+  if (o.smoother_fp32 < 0) return set_err(h, PITMG_ERR_INVALID, "smoother_fp32 must be >= 0");
   return PITMG_OK;
 }
 
@@ -229,9 +243,22 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
   const int big = INT_MAX;
   HIPCHK(h, hipMemcpyAsync(h->fail, &big, sizeof(int), hipMemcpyHostToDevice, h->stream));
   for (int l = 0; l < h->L; ++l) {
-    LevelView v = view(h, l);
-    int rc = timed(h, 0, [&] { return launch_factor(v, h->lv[l].Gi, l, h->fail, h->stream); });
-    if (rc) return rc;
+    LevelBuf& b = h->lv[l];
+    if (b.fp32) {
+      const long long cN = (b.sN ? b.n : 1) * pp, cV = (b.sV ? b.n : 1) * pp,
+                      cZ = (b.sZ ? b.n : 1) * pq;
+      int rc = timed(h, 0, [&] { return launch_to_f32(b.N32, b.N, cN, h->stream); });
+      if (!rc) rc = timed(h, 0, [&] { return launch_to_f32(b.V32, b.V, cV, h->stream); });
+      if (!rc) rc = timed(h, 0, [&] { return launch_to_f32(b.Z32, b.Z, cZ, h->stream); });
+      if (rc) return rc;
+      LevelView v = view(h, l);
+      rc = timed(h, 0, [&] { return launch_factor32(v, b.Gi32, l, h->fail, h->stream); });
+      if (rc) return rc;
+    } else {
+      LevelView v = view(h, l);
+      int rc = timed(h, 0, [&] { return launch_factor(v, b.Gi, l, h->fail, h->stream); });
+      if (rc) return rc;
+    }
   }
   int code = INT_MAX;
   HIPCHK(h, hipMemcpyAsync(&code, h->fail, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -331,12 +358,22 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
     yprev = ycur;
     ycur = dst;
   }
-  if (ycur == nullptr)
+  if (ycur == nullptr) {
     rc = timed(h, 3, [&] { return launch_restrict(h->p, h->q, v.n, b, var, C.b, h->stream); });
-  else
+  } else if (B.res) {
+    // FP32 smoothing: the finest residual is formed explicitly in FP64
+    LevelView v64 = v;
+    v64.fp32 = 0;
+    rc = timed(h, 2, [&] { return launch_apply(v64, ycur, b, -1.0, 1.0, B.res, h->stream); });
+    if (!rc)
+      rc = timed(h, 3, [&] {
+        return launch_restrict(h->p, h->q, v.n, B.res, var, C.b, h->stream);
+      });
+  } else {
     rc = timed(h, 3, [&] {
       return launch_restrict_delta(h->p, h->q, v.n, yprev, ycur, var, C.b, h->stream);
     });
+  }
   if (rc) return rc;
   rc = vcycle_level(h, l + 1, C.b, C.out);
   if (rc) return rc;
@@ -423,6 +460,7 @@ void pitmg_default_options(pitmg_options* o) {
   o->restart = 30;
   o->maxit = 300;
   o->transfer_variant = 0;
+  o->smoother_fp32 = 0;
 }
 
 int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options* opt,
@@ -467,8 +505,19 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
       if ((rc = dalloc(h, (void**)&b.V_own, cV * 8))) return fail(rc);
       if ((rc = dalloc(h, (void**)&b.Z_own, cZ * 8))) return fail(rc);
     }
-    if ((rc = dalloc(h, (void**)&b.Gi, (size_t)b.n * pp * 8))) return fail(rc);
     const bool coarsest = l == h->L - 1;
+    b.fp32 = l < o.smoother_fp32 && !coarsest;
+    if (b.fp32) {
+      const long long cN = (pb->N_stride ? b.n : 1) * pp, cV = (pb->V_stride ? b.n : 1) * pp,
+                      cZ = (pb->Z_stride ? b.n : 1) * pq;
+      if ((rc = dalloc(h, (void**)&b.N32, cN * 4))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.V32, cV * 4))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.Z32, cZ * 4))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.Gi32, (size_t)b.n * pp * 4))) return fail(rc);
+      if (l == 0 && (rc = dalloc(h, (void**)&b.res, b.len * 8))) return fail(rc);
+    } else {
+      if ((rc = dalloc(h, (void**)&b.Gi, (size_t)b.n * pp * 8))) return fail(rc);
+    }
     if (l > 0) {
       if ((rc = dalloc(h, (void**)&b.b, b.len * 8))) return fail(rc);
       if ((rc = dalloc(h, (void**)&b.out, b.len * 8))) return fail(rc);
@@ -549,6 +598,8 @@ int pitmg_set_options(pitmg_handle* h, const pitmg_options* opt) {
   const int cneed = opt->coarse_fixed_its > 0 ? opt->coarse_fixed_its : opt->coarse_maxit;
   if (opt->restart > h->restart_cap || cneed > h->coarse_cap)
     return set_err(h, PITMG_ERR_INVALID, "restart / coarse steps exceed the setup capacity");
+  if (opt->smoother_fp32 != h->opt.smoother_fp32)
+    return set_err(h, PITMG_ERR_INVALID, "smoother_fp32 is fixed at setup");
   h->opt = *opt;
   return PITMG_OK;
 }
@@ -859,6 +910,11 @@ void pitmg_destroy(pitmg_handle* h) {
     hipFree(b.y0);
     hipFree(b.y1);
     hipFree(b.out);
+    hipFree(b.res);
+    hipFree(b.N32);
+    hipFree(b.V32);
+    hipFree(b.Z32);
+    hipFree(b.Gi32);
   }
   hipFree(h->Vk);
   hipFree(h->Zk);

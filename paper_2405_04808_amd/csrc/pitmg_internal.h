@@ -15,6 +15,31 @@ struct LevelView {
   const double* V;  long long sV;
   const double* Z;  long long sZ;
   const double* Gi;            // [n][p][p] row-major, lower triangle of G_k^{-1}
+  // FP32 smoother (levels above the coarsest when enabled): single-precision
+  // copies of the blocks and the factor, same layout and strides.
+  const float* N32 = nullptr;
+  const float* V32 = nullptr;
+  const float* Z32 = nullptr;
+  const float* Gi32 = nullptr;
+  int fp32 = 0;
+};
+
+// Block pointers of a level in the arithmetic of the smoother.
+template <class T>
+struct Mats;
+template <>
+struct Mats<double> {
+  __host__ __device__ static const double* N(const LevelView& L) { return L.N; }
+  __host__ __device__ static const double* V(const LevelView& L) { return L.V; }
+  __host__ __device__ static const double* Z(const LevelView& L) { return L.Z; }
+  __host__ __device__ static const double* Gi(const LevelView& L) { return L.Gi; }
+};
+template <>
+struct Mats<float> {
+  __host__ __device__ static const float* N(const LevelView& L) { return L.N32; }
+  __host__ __device__ static const float* V(const LevelView& L) { return L.V32; }
+  __host__ __device__ static const float* Z(const LevelView& L) { return L.Z32; }
+  __host__ __device__ static const float* Gi(const LevelView& L) { return L.Gi32; }
 };
 
 // Offsets of the five variable types in a type-major vector of n steps.
@@ -32,7 +57,11 @@ struct TypeMajor {
 // with (level << 20 | k) on a non-positive pivot.
 hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail,
                          hipStream_t s);
-size_t factor_lds_bytes(int p);
+// Same in FP32 from L.N32 / L.Z32 into Gi32.
+hipError_t launch_factor32(const LevelView& L, float* Gi32, int level, int* fail,
+                           hipStream_t s);
+// dst = (float) src
+hipError_t launch_to_f32(float* dst, const double* src, long long count, hipStream_t s);
 
 // One block Jacobi sweep: ynew = D^{-1}(b - (L+L^T) yc) where the coupling
 // values yc are taken from yold (NULL = 0) plus, if ecoarse != NULL, the
@@ -41,7 +70,8 @@ hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold
                          const double* ecoarse, int variant, double* ynew,
                          hipStream_t s);
 
-// Register-tiled sweep for p == q in {64, 128} (16-byte aligned blocks).
+// Register-tiled sweep for p == q in {64, 128} (16-byte aligned blocks); the
+// launchers follow L.fp32 for the arithmetic.
 bool jacobi_tiled_supported(int p, int q);
 hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
                                const double* ecoarse, int variant, double* ynew,

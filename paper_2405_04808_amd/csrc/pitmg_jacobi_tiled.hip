@@ -7,38 +7,38 @@
 
 namespace pitmg {
 
-template <int RT, int CT>
+template <int RT, int CT, class T>
 __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
     LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
     const double* __restrict__ ec, int variant, double* __restrict__ ynew) {
-  using TS = TiledSolve<RT, CT>;
+  using TS = TiledSolve<RT, CT, T>;
   constexpr int P = TS::P;
-  __shared__ double sru[P], srz[P], srm[P], srl[P], srv[P], slam[P];
-  __shared__ double scr[TS::kScratch];
+  __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P];
+  __shared__ T scr[TS::kScratch];
   const int tid = threadIdx.x;
   const int n = L.n;
-  const TypeMajor T(P, P, n);
+  const TypeMajor Tm(P, P, n);
   const int nc = n / 2;
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
   const int kb = blockIdx.x;
 
   auto cu = [&](int k1, int i) -> double {
-    double v = yold ? yold[T.u + (long long)(k1 - 1) * P + i] : 0.0;
+    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
     if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
     return v;
   };
   auto cm = [&](int k1, int i) -> double {
-    double v = yold ? yold[T.m + (long long)(k1 - 1) * P + i] : 0.0;
+    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
     if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
     return v;
   };
 
   if (kb == n) {                               // block n+1 = (v_n, mu_n)
     for (int i = tid; i < P; i += kTiledThreads) {
-      const double rvv = b[T.v + (long long)(n - 1) * P + i];
-      const double rmm = b[T.m + (long long)(n - 1) * P + i] - cu(n, i);
-      ynew[T.v + (long long)(n - 1) * P + i] = -rmm;
-      ynew[T.m + (long long)(n - 1) * P + i] = -rmm - rvv;
+      const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
+      const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
+      ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+      ynew[Tm.m + (long long)(n - 1) * P + i] = -rmm - rvv;
     }
     return;
   }
@@ -50,47 +50,54 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   // right-hand side with the coupling values of the previous iterate:
   // r_u = b_u,k - mu_k, r_mu = b_mu,k-1 - u_{k-1}
   for (int i = tid; i < P; i += kTiledThreads) {
-    sru[i] = b[T.u + kk * P + i] - cm(k, i);
-    srl[i] = b[T.l + kk * P + i];
-    srz[i] = b[T.z + kk * P + i];
+    sru[i] = (T)(b[Tm.u + kk * P + i] - cm(k, i));
+    srl[i] = (T)b[Tm.l + kk * P + i];
+    srz[i] = (T)b[Tm.z + kk * P + i];
     if (hv) {
-      srv[i] = b[T.v + (kk - 1) * P + i];
-      srm[i] = b[T.m + (kk - 1) * P + i] - cu(k - 1, i);
+      srv[i] = (T)b[Tm.v + (kk - 1) * P + i];
+      srm[i] = (T)(b[Tm.m + (kk - 1) * P + i] - cu(k - 1, i));
     } else {
-      srv[i] = 0.0;
-      srm[i] = 0.0;
+      srv[i] = 0;
+      srm[i] = 0;
     }
   }
   __syncthreads();
   TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
   for (int i = tid; i < P; i += kTiledThreads) {
-    ynew[T.u + kk * P + i] = TS::u_of(scr, sru, i);
-    ynew[T.z + kk * P + i] = TS::z_of(scr, srz, i);
-    ynew[T.l + kk * P + i] = slam[i];
+    ynew[Tm.u + kk * P + i] = (double)TS::u_of(scr, sru, i);
+    ynew[Tm.z + kk * P + i] = (double)TS::z_of(scr, srz, i);
+    ynew[Tm.l + kk * P + i] = (double)slam[i];
     if (hv) {
-      ynew[T.m + (kk - 1) * P + i] = TS::mu_of(scr, srm, srv, i);
-      ynew[T.v + (kk - 1) * P + i] = -srm[i];
+      ynew[Tm.m + (kk - 1) * P + i] = (double)TS::mu_of(scr, srm, srv, i);
+      ynew[Tm.v + (kk - 1) * P + i] = -(double)srm[i];
     }
   }
 }
 
 bool jacobi_tiled_supported(int p, int q) { return p == q && (p == 128 || p == 64); }
 
-hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
-                               const double* ecoarse, int variant, double* ynew,
-                               hipStream_t s) {
+template <class T>
+static hipError_t launch_tiled_t(const LevelView& L, const double* b, const double* yold,
+                                 const double* ecoarse, int variant, double* ynew,
+                                 hipStream_t s) {
   if (L.p == 128 && L.q == 128) {
-    hipLaunchKernelGGL((k_jacobi_tiled<4, 8>), dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b,
-                       yold, ecoarse, variant, ynew);
+    hipLaunchKernelGGL((k_jacobi_tiled<4, 8, T>), dim3(L.n + 1), dim3(kTiledThreads), 0, s, L,
+                       b, yold, ecoarse, variant, ynew);
   } else if (L.p == 64 && L.q == 64) {
-    hipLaunchKernelGGL((k_jacobi_tiled<2, 4>), dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b,
-                       yold, ecoarse, variant, ynew);
+    hipLaunchKernelGGL((k_jacobi_tiled<2, 4, T>), dim3(L.n + 1), dim3(kTiledThreads), 0, s, L,
+                       b, yold, ecoarse, variant, ynew);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
+                               const double* ecoarse, int variant, double* ynew,
+                               hipStream_t s) {
+  return L.fp32 ? launch_tiled_t<float>(L, b, yold, ecoarse, variant, ynew, s)
+                : launch_tiled_t<double>(L, b, yold, ecoarse, variant, ynew, s);
+}
 
 // ---------------------------------------------------------------------------
 // Sweep for V_k and Z~_k shared by every step (stride 0, the theta = 1 case).
@@ -110,35 +117,35 @@ namespace {
 constexpr int kMaxSteps = 4;
 }
 
-template <int RT, int CT>
+template <int RT, int CT, class T>
 __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
     const double* __restrict__ ec, int variant, double* __restrict__ ynew, int per_wg) {
-  using TS = TiledSolve<RT, CT>;
+  using TS = TiledSolve<RT, CT, T>;
   constexpr int P = TS::P;
   constexpr int G = kTiledThreads / P;                   // row groups of the post pass
-  __shared__ double sru[kMaxSteps][P], srz[kMaxSteps][P], srm[kMaxSteps][P],
+  __shared__ T sru[kMaxSteps][P], srz[kMaxSteps][P], srm[kMaxSteps][P],
       srl[kMaxSteps][P], srv[kMaxSteps][P], sT[kMaxSteps][P], slam[kMaxSteps][P];
-  __shared__ double st[P], ss[P], red[kTiledWaves * P];
-  __shared__ double pz[G][kMaxSteps][P], pv[G][kMaxSteps][P];
+  __shared__ T st[P], ss[P], red[kTiledWaves * P];
+  __shared__ T pz[G][kMaxSteps][P], pv[G][kMaxSteps][P];
   const int tid = threadIdx.x, a = tid / 16, bq = tid % 16;
   const int r0 = RT * a;
   const int n = L.n;
-  const TypeMajor T(P, P, n);
+  const TypeMajor Tm(P, P, n);
   const int nc = n / 2;
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
   const int k0 = blockIdx.x * per_wg + 1;                // first step (1-based)
   const int nb = min(per_wg, n - k0 + 1);                // steps of this work-group
-  const double* __restrict__ Vs = L.V;                   // shared blocks
-  const double* __restrict__ Zs = L.Z;
+  const T* __restrict__ Vs = Mats<T>::V(L);             // shared blocks
+  const T* __restrict__ Zs = Mats<T>::Z(L);
 
   auto cu = [&](int k1, int i) -> double {
-    double v = yold ? yold[T.u + (long long)(k1 - 1) * P + i] : 0.0;
+    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
     if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
     return v;
   };
   auto cm = [&](int k1, int i) -> double {
-    double v = yold ? yold[T.m + (long long)(k1 - 1) * P + i] : 0.0;
+    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
     if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
     return v;
   };
@@ -150,46 +157,46 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     const int k = k0 + bi;
     const long long kk = k - 1;
     for (int i = tid; i < P; i += kTiledThreads) {
-      sru[bi][i] = b[T.u + kk * P + i] - cm(k, i);
-      srl[bi][i] = b[T.l + kk * P + i];
-      srz[bi][i] = b[T.z + kk * P + i];
+      sru[bi][i] = (T)(b[Tm.u + kk * P + i] - cm(k, i));
+      srl[bi][i] = (T)b[Tm.l + kk * P + i];
+      srz[bi][i] = (T)b[Tm.z + kk * P + i];
       if (k >= 2) {
-        srv[bi][i] = b[T.v + (kk - 1) * P + i];
-        srm[bi][i] = b[T.m + (kk - 1) * P + i] - cu(k - 1, i);
+        srv[bi][i] = (T)b[Tm.v + (kk - 1) * P + i];
+        srm[bi][i] = (T)(b[Tm.m + (kk - 1) * P + i] - cu(k - 1, i));
       } else {
-        srv[bi][i] = 0.0;
-        srm[bi][i] = 0.0;
+        srv[bi][i] = 0;
+        srm[bi][i] = 0;
       }
     }
   }
   if (k0 + nb - 1 == n) {                                // block n+1 = (v_n, mu_n)
     for (int i = tid; i < P; i += kTiledThreads) {
-      const double rvv = b[T.v + (long long)(n - 1) * P + i];
-      const double rmm = b[T.m + (long long)(n - 1) * P + i] - cu(n, i);
-      ynew[T.v + (long long)(n - 1) * P + i] = -rmm;
-      ynew[T.m + (long long)(n - 1) * P + i] = -rmm - rvv;
+      const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
+      const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
+      ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+      ynew[Tm.m + (long long)(n - 1) * P + i] = -rmm - rvv;
     }
   }
   __syncthreads();
 
   // sT[s] = Z~ r_z[s] - V r_mu[s] for every step: one pass over Z~ and V
   {
-    double acc[kMaxSteps][RT];
+    T acc[kMaxSteps][RT];
 #pragma unroll
     for (int s = 0; s < kMaxSteps; ++s)
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[s][r] = 0.0;
+      for (int r = 0; r < RT; ++r) acc[s][r] = 0;
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-      double zr[CT], vr[CT];
-      tile_load_row<CT>(Zs + (long long)(r0 + r) * P, zr);
-      tile_load_row<CT>(Vs + (long long)(r0 + r) * P, vr);
+      T zr[CT], vr[CT];
+      tile_load_row<CT, T>(Zs + (long long)(r0 + r) * P, zr);
+      tile_load_row<CT, T>(Vs + (long long)(r0 + r) * P, vr);
 #pragma unroll
       for (int s = 0; s < kMaxSteps; ++s) {
         if (s < nb) {
 #pragma unroll
           for (int c = 0; c < CT; ++c)
-            acc[s][r] += zr[c] * srz[s][tile_col(c)] - vr[c] * srm[s][tile_col(c)];
+            acc[s][r] += zr[c] * srz[s][tile_col<T>(c)] - vr[c] * srm[s][tile_col<T>(c)];
         }
       }
     }
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
       if (s < nb) {
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
-          const double v = tile_sum16(acc[s][r]);
+          const T v = tile_sum16(acc[s][r]);
           if (bq == 0) sT[s][r0 + r] = v;
         }
       }
@@ -209,12 +216,12 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
   for (int bi = 0; bi < nb; ++bi) {
     const long long kk = k0 + bi - 1;
     // t = N r_u + (Z~ r_z - V r_mu) - r_l
-    double acc[RT];
+    T acc[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += R.nt[r][c] * sru[bi][tile_col(c)];
+      for (int c = 0; c < CT; ++c) s += R.nt[r][c] * sru[bi][tile_col<T>(c)];
       acc[r] = tile_sum16(s);
     }
     if (bq == 0) {
@@ -225,9 +232,9 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     // s = G^{-1} t
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += R.gt[r][c] * st[tile_col(c)];
+      for (int c = 0; c < CT; ++c) s += R.gt[r][c] * st[tile_col<T>(c)];
       acc[r] = tile_sum16(s);
     }
     if (bq == 0) {
@@ -236,10 +243,10 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     }
     __syncthreads();
     // lambda = G^{-T} s
-    double cacc[CT];
+    T cacc[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
       for (int r = 0; r < RT; ++r) s += R.gt[r][c] * ss[r0 + r];
       cacc[c] = s;
@@ -252,7 +259,7 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     // u = r_u - N^T lambda
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
       for (int r = 0; r < RT; ++r) s += R.nt[r][c] * slam[bi][r0 + r];
       cacc[c] = s;
@@ -261,8 +268,8 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     __syncthreads();
     if (bi + 1 < nb) TS::load_n(L, kk + 1, R);             // N of the next step
     for (int i = tid; i < P; i += kTiledThreads) {
-      ynew[T.u + kk * P + i] = sru[bi][i] - TS::col_total(red, i);
-      ynew[T.l + kk * P + i] = slam[bi][i];
+      ynew[Tm.u + kk * P + i] = (double)(sru[bi][i] - TS::col_total(red, i));
+      ynew[Tm.l + kk * P + i] = (double)slam[bi][i];
     }
     __syncthreads();
   }
@@ -271,14 +278,14 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
   // Thread (j, g) = (tid % P, tid / P) sums rows i = g, g+G, ...
   {
     const int j = tid % P, g = tid / P;
-    double za[kMaxSteps], va[kMaxSteps];
+    T za[kMaxSteps], va[kMaxSteps];
 #pragma unroll
     for (int s = 0; s < kMaxSteps; ++s) {
-      za[s] = 0.0;
-      va[s] = 0.0;
+      za[s] = 0;
+      va[s] = 0;
     }
     for (int i = g; i < P; i += G) {
-      const double zi = Zs[(long long)i * P + j], vi = Vs[(long long)i * P + j];
+      const T zi = Zs[(long long)i * P + j], vi = Vs[(long long)i * P + j];
 #pragma unroll
       for (int s = 0; s < kMaxSteps; ++s) {
         if (s < nb) {
@@ -297,22 +304,39 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
   for (int idx = tid; idx < nb * P; idx += kTiledThreads) {
     const int s = idx / P, i = idx % P;
     const long long kk = k0 + s - 1;
-    double zt = 0.0, vt = 0.0;
+    T zt = 0, vt = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       zt += pz[g][s][i];
       vt += pv[g][s][i];
     }
-    ynew[T.z + kk * P + i] = srz[s][i] - zt;
+    ynew[Tm.z + kk * P + i] = (double)(srz[s][i] - zt);
     if (kk >= 1) {
-      ynew[T.m + (kk - 1) * P + i] = vt - srm[s][i] - srv[s][i];
-      ynew[T.v + (kk - 1) * P + i] = -srm[s][i];
+      ynew[Tm.m + (kk - 1) * P + i] = (double)(vt - srm[s][i] - srv[s][i]);
+      ynew[Tm.v + (kk - 1) * P + i] = -(double)srm[s][i];
     }
   }
 }
 
 bool jacobi_shared_supported(const LevelView& L) {
   return L.sV == 0 && L.sZ == 0 && L.p == L.q && (L.p == 128 || L.p == 64);
+}
+
+template <class T>
+static hipError_t launch_shared_t(const LevelView& L, const double* b, const double* yold,
+                                  const double* ecoarse, int variant, double* ynew, int per,
+                                  hipStream_t s) {
+  const int nwg = (L.n + per - 1) / per;
+  if (L.p == 128) {
+    hipLaunchKernelGGL((k_jacobi_shared<4, 8, T>), dim3(nwg), dim3(kTiledThreads), 0, s, L, b,
+                       yold, ecoarse, variant, ynew, per);
+  } else if (L.p == 64) {
+    hipLaunchKernelGGL((k_jacobi_shared<2, 4, T>), dim3(nwg), dim3(kTiledThreads), 0, s, L, b,
+                       yold, ecoarse, variant, ynew, per);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
@@ -322,17 +346,8 @@ hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const doubl
   int per = (L.n + 255) / 256;
   if (per > kMaxSteps) per = kMaxSteps;
   if (per < 1) per = 1;
-  const int nwg = (L.n + per - 1) / per;
-  if (L.p == 128) {
-    hipLaunchKernelGGL((k_jacobi_shared<4, 8>), dim3(nwg), dim3(kTiledThreads), 0, s, L, b,
-                       yold, ecoarse, variant, ynew, per);
-  } else if (L.p == 64) {
-    hipLaunchKernelGGL((k_jacobi_shared<2, 4>), dim3(nwg), dim3(kTiledThreads), 0, s, L, b,
-                       yold, ecoarse, variant, ynew, per);
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return L.fp32 ? launch_shared_t<float>(L, b, yold, ecoarse, variant, ynew, per, s)
+                : launch_shared_t<double>(L, b, yold, ecoarse, variant, ynew, per, s);
 }
 
 }  // namespace pitmg

@@ -32,37 +32,38 @@ namespace pitmg {
 
 constexpr int kFactorThreads = 256;
 
-template <bool USE_LDS>
-__global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, double* Gi,
+template <class T, bool USE_LDS>
+__global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, T* Gi,
                                                            int level, int* fail) {
-  extern __shared__ double smem[];
+  extern __shared__ double smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
   const int p = L.p, q = L.q;
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
-  const double* __restrict__ Nk = L.N + (long long)k * L.sN;
-  const double* __restrict__ Zk = L.Z + (long long)k * L.sZ;
-  double* Gk = Gi + (long long)k * p * p;
+  const T* __restrict__ Nk = Mats<T>::N(L) + (long long)k * L.sN;
+  const T* __restrict__ Zk = Mats<T>::Z(L) + (long long)k * L.sZ;
+  T* Gk = Gi + (long long)k * p * p;
   const int ld = USE_LDS ? p + 1 : p;
-  double* S = USE_LDS ? smem : Gk;
-  double* tmp = USE_LDS ? smem + (size_t)p * ld : smem;
+  T* S = USE_LDS ? smem : Gk;
+  T* tmp = USE_LDS ? smem + (size_t)p * ld : smem;
 
   // S = N N^T + Z Z^T (lower triangle)
   for (int idx = tid; idx < p * p; idx += kFactorThreads) {
     const int i = idx / p, j = idx % p;
     if (j > i) continue;
-    double acc = 0.0;
-    const double* Ni = Nk + (long long)i * p;
-    const double* Nj = Nk + (long long)j * p;
+    T acc = 0;
+    const T* Ni = Nk + (long long)i * p;
+    const T* Nj = Nk + (long long)j * p;
     for (int m = 0; m < p; ++m) acc += Ni[m] * Nj[m];
-    const double* Zi = Zk + (long long)i * q;
-    const double* Zj = Zk + (long long)j * q;
+    const T* Zi = Zk + (long long)i * q;
+    const T* Zj = Zk + (long long)j * q;
     for (int m = 0; m < q; ++m) acc += Zi[m] * Zj[m];
     S[(long long)i * ld + j] = acc;
   }
   // Cholesky, right-looking, column by column
   for (int j = 0; j < p; ++j) {
     __syncthreads();
-    double d = S[(long long)j * ld + j];
+    T d = S[(long long)j * ld + j];
     if (!(d > 0.0) || !isfinite(d)) {
       if (tid == 0) atomicMin(fail, (level << 20) | k);
       return;                                  // uniform: every thread read d
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, double* 
     d = sqrt(d);
     __syncthreads();
     if (tid == 0) S[(long long)j * ld + j] = d;
-    const double inv = 1.0 / d;
+    const T inv = T(1) / d;
     for (int i = j + 1 + tid; i < p; i += kFactorThreads) S[(long long)i * ld + j] *= inv;
     __syncthreads();
     const int m = p - j - 1;
@@ -85,9 +86,9 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, double* 
   // X[j][j] = 1/G[j][j], X[i][j] = -X[j][j] sum_{m=j+1..i} X[i][m] G[m][j].
   for (int j = p - 1; j >= 0; --j) {
     __syncthreads();
-    const double djj = 1.0 / S[(long long)j * ld + j];
+    const T djj = T(1) / S[(long long)j * ld + j];
     for (int i = j + 1 + tid; i < p; i += kFactorThreads) {
-      double acc = 0.0;
+      T acc = 0;
       for (int m = j + 1; m <= i; ++m) acc += S[(long long)i * ld + m] * S[(long long)m * ld + j];
       tmp[i] = -djj * acc;
     }
@@ -98,29 +99,54 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, double* 
   __syncthreads();
   for (int idx = tid; idx < p * p; idx += kFactorThreads) {
     const int i = idx / p, j = idx % p;
-    const double v = j <= i ? S[(long long)i * ld + j] : 0.0;
+    const T v = j <= i ? S[(long long)i * ld + j] : T(0);
     Gk[idx] = v;
   }
 }
 
-size_t factor_lds_bytes(int p) {
-  if (p <= 128) return ((size_t)p * (p + 1) + p) * sizeof(double);
-  return (size_t)p * sizeof(double);
+template <class T>
+static size_t factor_lds(int p) {
+  if (p <= 128) return ((size_t)p * (p + 1) + p) * sizeof(T);
+  return (size_t)p * sizeof(T);
 }
 
-hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail,
-                         hipStream_t s) {
-  const size_t lds = factor_lds_bytes(L.p);
+template <class T>
+static hipError_t launch_factor_t(const LevelView& L, T* Gi, int level, int* fail, hipStream_t s) {
+  const size_t lds = factor_lds<T>(L.p);
   if (L.p <= 128) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_factor<true>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_factor<T, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_factor<true>, dim3(L.n), dim3(kFactorThreads), lds, s, L, Gi,
+    hipLaunchKernelGGL((k_factor<T, true>), dim3(L.n), dim3(kFactorThreads), lds, s, L, Gi,
                        level, fail);
   } else {
-    hipLaunchKernelGGL(k_factor<false>, dim3(L.n), dim3(kFactorThreads), lds, s, L, Gi,
+    hipLaunchKernelGGL((k_factor<T, false>), dim3(L.n), dim3(kFactorThreads), lds, s, L, Gi,
                        level, fail);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail, hipStream_t s) {
+  return launch_factor_t<double>(L, Gi, level, fail, s);
+}
+
+hipError_t launch_factor32(const LevelView& L, float* Gi32, int level, int* fail,
+                           hipStream_t s) {
+  return launch_factor_t<float>(L, Gi32, level, fail, s);
+}
+
+__global__ void k_to_f32(float* __restrict__ dst, const double* __restrict__ src,
+                         long long count) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+hipError_t launch_to_f32(float* dst, const double* src, long long count, hipStream_t s) {
+  long long g = (count + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)g), dim3(256), 0, s, dst, src, count);
   return hipGetLastError();
 }
 
@@ -130,100 +156,111 @@ hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail,
 
 constexpr int kSweepThreads = 256;
 
-template <int NT>
+template <int NT, class T>
 __global__ __launch_bounds__(NT) void k_jacobi(LevelView L, const double* __restrict__ b,
                                                const double* __restrict__ yold,
                                                const double* __restrict__ ec, int variant,
                                                double* __restrict__ ynew) {
-  extern __shared__ double sm[];
+  extern __shared__ double sm_raw[];
+  T* sm = reinterpret_cast<T*>(sm_raw);
   const int p = L.p, q = L.q, n = L.n;
-  const TypeMajor T(p, q, n);
+  const TypeMajor Tm(p, q, n);
   const int nc = n / 2;
   const TypeMajor Tc(p, q, nc > 0 ? nc : 1);
   const int kb = blockIdx.x, tid = threadIdx.x;
 
   // coupling values of the previous iterate: yold + P ec (u and mu only)
   auto cu = [&](int k1, int i) -> double {
-    double v = yold ? yold[T.u + (long long)(k1 - 1) * p + i] : 0.0;
+    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * p + i] : 0.0;
     if (ec) v += interp_node(ec + Tc.u, nc, p, k1, i, variant);
     return v;
   };
   auto cm = [&](int k1, int i) -> double {
-    double v = yold ? yold[T.m + (long long)(k1 - 1) * p + i] : 0.0;
+    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * p + i] : 0.0;
     if (ec) v += interp_node(ec + Tc.m, nc, p, k1, i, variant);
     return v;
   };
 
   if (kb == n) {                               // block n+1 = (v_n, mu_n)
     for (int i = tid; i < p; i += NT) {
-      const double rvv = b[T.v + (long long)(n - 1) * p + i];
-      const double rmm = b[T.m + (long long)(n - 1) * p + i] - cu(n, i);
-      ynew[T.v + (long long)(n - 1) * p + i] = -rmm;
-      ynew[T.m + (long long)(n - 1) * p + i] = -rmm - rvv;
+      const double rvv = b[Tm.v + (long long)(n - 1) * p + i];
+      const double rmm = b[Tm.m + (long long)(n - 1) * p + i] - cu(n, i);
+      ynew[Tm.v + (long long)(n - 1) * p + i] = -rmm;
+      ynew[Tm.m + (long long)(n - 1) * p + i] = -rmm - rvv;
     }
     return;
   }
   const int k = kb + 1;
   const bool hv = k >= 2;
-  double* rv = sm;
-  double* ru = rv + p;
-  double* rz = ru + p;
-  double* rl = rz + q;
-  double* rm = rl + p;
-  double* ov = rm + p;
-  double* ou = ov + p;
-  double* oz = ou + p;
-  double* ol = oz + q;
-  double* om = ol + p;
-  double* t = om + p;
-  double* s = t + p;
-  double* part = s + p;
+  T* rv = sm;
+  T* ru = rv + p;
+  T* rz = ru + p;
+  T* rl = rz + q;
+  T* rm = rl + p;
+  T* ov = rm + p;
+  T* ou = ov + p;
+  T* oz = ou + p;
+  T* ol = oz + q;
+  T* om = ol + p;
+  T* t = om + p;
+  T* s = t + p;
+  T* part = s + p;
   for (int i = tid; i < p; i += NT) {
-    ru[i] = b[T.u + (long long)(k - 1) * p + i] - cm(k, i);
-    rl[i] = b[T.l + (long long)(k - 1) * p + i];
+    ru[i] = (T)(b[Tm.u + (long long)(k - 1) * p + i] - cm(k, i));
+    rl[i] = (T)b[Tm.l + (long long)(k - 1) * p + i];
     if (hv) {
-      rv[i] = b[T.v + (long long)(k - 2) * p + i];
-      rm[i] = b[T.m + (long long)(k - 2) * p + i] - cu(k - 1, i);
+      rv[i] = (T)b[Tm.v + (long long)(k - 2) * p + i];
+      rm[i] = (T)(b[Tm.m + (long long)(k - 2) * p + i] - cu(k - 1, i));
     } else {
-      rv[i] = 0.0;
-      rm[i] = 0.0;
+      rv[i] = 0;
+      rm[i] = 0;
     }
   }
-  for (int i = tid; i < q; i += NT) rz[i] = b[T.z + (long long)(k - 1) * q + i];
+  for (int i = tid; i < q; i += NT) rz[i] = (T)b[Tm.z + (long long)(k - 1) * q + i];
   __syncthreads();
   const long long kk = k - 1;
-  block_solve<NT>(p, q, L.N + kk * L.sN, L.V + kk * L.sV, L.Z + kk * L.sZ,
-                  L.Gi + kk * p * p, hv, rv, ru, rz, rl, rm, ov, ou, oz, ol, om, t, s,
+  block_solve<NT, T>(p, q, Mats<T>::N(L) + kk * L.sN, Mats<T>::V(L) + kk * L.sV,
+                     Mats<T>::Z(L) + kk * L.sZ, Mats<T>::Gi(L) + kk * p * p, hv, rv, ru, rz, rl, rm, ov, ou, oz, ol, om, t, s,
                   part);
   for (int i = tid; i < p; i += NT) {
-    ynew[T.u + kk * p + i] = ou[i];
-    ynew[T.l + kk * p + i] = ol[i];
+    ynew[Tm.u + kk * p + i] = (double)ou[i];
+    ynew[Tm.l + kk * p + i] = (double)ol[i];
     if (hv) {
-      ynew[T.v + (kk - 1) * p + i] = ov[i];
-      ynew[T.m + (kk - 1) * p + i] = om[i];
+      ynew[Tm.v + (kk - 1) * p + i] = (double)ov[i];
+      ynew[Tm.m + (kk - 1) * p + i] = (double)om[i];
     }
   }
-  for (int i = tid; i < q; i += NT) ynew[T.z + kk * q + i] = oz[i];
+  for (int i = tid; i < q; i += NT) ynew[Tm.z + kk * q + i] = (double)oz[i];
 }
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+template <class T>
+static hipError_t launch_jacobi_generic(const LevelView& L, const double* b, const double* yold,
+                                        const double* ecoarse, int variant, double* ynew,
+                                        hipStream_t s) {
+  const size_t lds = solve_lds_doubles(L.p, L.q, kSweepThreads) * sizeof(T);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<kSweepThreads, T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_jacobi<kSweepThreads, T>), dim3(L.n + 1), dim3(kSweepThreads), lds, s,
+                     L, b, yold, ecoarse, variant, ynew);
+  return hipGetLastError();
+}
+
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
                          const double* ecoarse, int variant, double* ynew, hipStream_t s) {
-  const bool al = aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi);
+  const bool al = L.fp32 ? aligned16(L.N32) && aligned16(L.V32) && aligned16(L.Z32) &&
+                               aligned16(L.Gi32)
+                         : aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi);
   if (al && jacobi_shared_supported(L))
     return launch_jacobi_shared(L, b, yold, ecoarse, variant, ynew, s);
   if (al && jacobi_tiled_supported(L.p, L.q))
     return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, s);
-  const size_t lds = solve_lds_doubles(L.p, L.q, kSweepThreads) * sizeof(double);
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<kSweepThreads>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_jacobi<kSweepThreads>, dim3(L.n + 1), dim3(kSweepThreads), lds, s,
-                     L, b, yold, ecoarse, variant, ynew);
-  return hipGetLastError();
+  return L.fp32 ? launch_jacobi_generic<float>(L, b, yold, ecoarse, variant, ynew, s)
+                : launch_jacobi_generic<double>(L, b, yold, ecoarse, variant, ynew, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -21,42 +21,69 @@ namespace pitmg {
 constexpr int kTiledThreads = 512;
 constexpr int kTiledWaves = kTiledThreads / kWave;
 
-// Column of the thread's c-th tile entry (c < CT): 2b + 32 (c / 2) + c % 2.
-__device__ __forceinline__ int tile_col(int c) { return 2 * (threadIdx.x % 16) + 32 * (c >> 1) + (c & 1); }
-
-// Load the thread's CT entries of one row (row points at the row start).
-template <int CT>
-__device__ __forceinline__ void tile_load_row(const double* __restrict__ row, double (&dst)[CT]) {
-  const double* src = row + 2 * (threadIdx.x % 16);
-#pragma unroll
-  for (int c = 0; c < CT; c += 2) {
-    const double2 v = *reinterpret_cast<const double2*>(src + 16 * c);
-    dst[c] = v.x;
-    dst[c + 1] = v.y;
+// 16-byte vector of the tile element type.
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+  __device__ static void put(const type& v, double* d) {
+    d[0] = v.x;
+    d[1] = v.y;
   }
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+  __device__ static void put(const type& v, float* d) {
+    d[0] = v.x;
+    d[1] = v.y;
+    d[2] = v.z;
+    d[3] = v.w;
+  }
+};
+
+// Column of the thread's c-th tile entry (c < CT), with E = 16/sizeof(T)
+// elements per load: E b + 16 E (c / E) + c % E.
+template <class T>
+__device__ __forceinline__ int tile_col(int c) {
+  constexpr int E = Vec16<T>::n;
+  return E * (threadIdx.x % 16) + 16 * E * (c / E) + c % E;
 }
 
-// Same for a lower-triangular row i: pairs wholly above the diagonal are
-// zero in memory and are not loaded.
-template <int CT>
-__device__ __forceinline__ void tile_load_row_lower(const double* __restrict__ row, int i,
-                                                    double (&dst)[CT]) {
-  const int j0 = 2 * (threadIdx.x % 16);
-  const double* src = row + j0;
+// Load the thread's CT entries of one row (row points at the row start).
+template <int CT, class T>
+__device__ __forceinline__ void tile_load_row(const T* __restrict__ row, T (&dst)[CT]) {
+  constexpr int E = Vec16<T>::n;
+  const T* src = row + E * (threadIdx.x % 16);
 #pragma unroll
-  for (int c = 0; c < CT; c += 2) {
+  for (int c = 0; c < CT; c += E)
+    Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(src + 16 * c), dst + c);
+}
+
+// Same for a lower-triangular row i: vectors wholly above the diagonal are
+// zero in memory and are not loaded.
+template <int CT, class T>
+__device__ __forceinline__ void tile_load_row_lower(const T* __restrict__ row, int i,
+                                                    T (&dst)[CT]) {
+  constexpr int E = Vec16<T>::n;
+  const int j0 = E * (threadIdx.x % 16);
+  const T* src = row + j0;
+#pragma unroll
+  for (int c = 0; c < CT; c += E) {
     if (j0 + 16 * c <= i) {
-      const double2 v = *reinterpret_cast<const double2*>(src + 16 * c);
-      dst[c] = v.x;
-      dst[c + 1] = v.y;
+      Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(src + 16 * c), dst + c);
     } else {
-      dst[c] = 0.0;
-      dst[c + 1] = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[c + e] = T(0);
     }
   }
 }
 
-__device__ __forceinline__ double tile_sum16(double v) {
+template <class T>
+__device__ __forceinline__ T tile_sum16(T v) {
   v += __shfl_xor(v, 8, kWave);
   v += __shfl_xor(v, 4, kWave);
   v += __shfl_xor(v, 2, kWave);
@@ -64,15 +91,15 @@ __device__ __forceinline__ double tile_sum16(double v) {
   return v;
 }
 
-template <int RT, int CT>
+template <int RT, int CT, class T = double>
 struct TiledSolve {
   static constexpr int P = 32 * RT;
   static_assert(P == 16 * CT, "tile shape");
   static constexpr int kThreads = kTiledThreads;
 
   struct Regs {
-    double nt[RT][CT];
-    double gt[RT][CT];
+    T nt[RT][CT];
+    T gt[RT][CT];
   };
   // LDS scratch (doubles): t, s, then three [waves][P] reduction slabs.
   static constexpr size_t kScratch = 2 * P + 3 * kTiledWaves * P;
@@ -85,21 +112,21 @@ struct TiledSolve {
 
   __device__ __forceinline__ static void load_n(const LevelView& L, long long kk, Regs& R) {
     const int r0 = RT * (threadIdx.x / 16);
-    const double* __restrict__ Nk = L.N + kk * L.sN;
+    const T* __restrict__ Nk = Mats<T>::N(L) + kk * L.sN;
 #pragma unroll
-    for (int r = 0; r < RT; ++r) tile_load_row<CT>(Nk + (long long)(r0 + r) * P, R.nt[r]);
+    for (int r = 0; r < RT; ++r) tile_load_row<CT, T>(Nk + (long long)(r0 + r) * P, R.nt[r]);
   }
 
   __device__ __forceinline__ static void load_g(const LevelView& L, long long kk, Regs& R) {
     const int r0 = RT * (threadIdx.x / 16);
-    const double* __restrict__ Gk = L.Gi + kk * (long long)P * P;
+    const T* __restrict__ Gk = Mats<T>::Gi(L) + kk * (long long)P * P;
 #pragma unroll
     for (int r = 0; r < RT; ++r)
-      tile_load_row_lower<CT>(Gk + (long long)(r0 + r) * P, r0 + r, R.gt[r]);
+      tile_load_row_lower<CT, T>(Gk + (long long)(r0 + r) * P, r0 + r, R.gt[r]);
   }
 
   // Column partials of one thread -> per-wave slot of red (lanes 0..15).
-  __device__ __forceinline__ static void col_partial(double (&v)[CT], double* red) {
+  __device__ __forceinline__ static void col_partial(T (&v)[CT], T* red) {
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
@@ -108,12 +135,12 @@ struct TiledSolve {
     }
     if (lane < 16) {
 #pragma unroll
-      for (int c = 0; c < CT; ++c) red[w * P + tile_col(c)] = v[c];
+      for (int c = 0; c < CT; ++c) red[w * P + tile_col<T>(c)] = v[c];
     }
   }
 
-  __device__ __forceinline__ static double col_total(const double* red, int j) {
-    double s = 0.0;
+  __device__ __forceinline__ static T col_total(const T* red, int j) {
+    T s = 0;
 #pragma unroll
     for (int w = 0; w < kTiledWaves; ++w) s += red[w * P + j];
     return s;
@@ -123,32 +150,32 @@ struct TiledSolve {
   // r_m unused when !hv).  Results: lambda in ol; N^T lambda, Z^T lambda and
   // V^T lambda are left in the reduction slabs and combined by finish().
   __device__ __forceinline__ static void solve(const LevelView& L, long long kk, bool hv,
-                                               const Regs& R, const double* sru,
-                                               const double* srz, const double* srm,
-                                               const double* srl, double* ol, double* scr) {
+                                               const Regs& R, const T* sru,
+                                               const T* srz, const T* srm,
+                                               const T* srl, T* ol, T* scr) {
     const int tid = threadIdx.x, a = tid / 16, bq = tid % 16;
     const int r0 = RT * a;
-    double* st = scr;
-    double* ss = scr + P;
-    double* red = scr + 2 * P;
-    const double* __restrict__ Vk = L.V + kk * L.sV;
-    const double* __restrict__ Zk = L.Z + kk * L.sZ;
+    T* st = scr;
+    T* ss = scr + P;
+    T* red = scr + 2 * P;
+    const T* __restrict__ Vk = Mats<T>::V(L) + kk * L.sV;
+    const T* __restrict__ Zk = Mats<T>::Z(L) + kk * L.sZ;
     // t = N r_u + Z r_z - V r_m - r_l
-    double acc[RT];
+    T acc[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += R.nt[r][c] * sru[tile_col(c)];
-      double zr[CT];
-      tile_load_row<CT>(Zk + (long long)(r0 + r) * P, zr);
+      for (int c = 0; c < CT; ++c) s += R.nt[r][c] * sru[tile_col<T>(c)];
+      T zr[CT];
+      tile_load_row<CT, T>(Zk + (long long)(r0 + r) * P, zr);
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += zr[c] * srz[tile_col(c)];
+      for (int c = 0; c < CT; ++c) s += zr[c] * srz[tile_col<T>(c)];
       if (hv) {
-        double vr[CT];
-        tile_load_row<CT>(Vk + (long long)(r0 + r) * P, vr);
+        T vr[CT];
+        tile_load_row<CT, T>(Vk + (long long)(r0 + r) * P, vr);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) s -= vr[c] * srm[tile_col(c)];
+        for (int c = 0; c < CT; ++c) s -= vr[c] * srm[tile_col<T>(c)];
       }
       acc[r] = tile_sum16(s);
     }
@@ -160,9 +187,9 @@ struct TiledSolve {
     // s = G^{-1} t
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += R.gt[r][c] * st[tile_col(c)];
+      for (int c = 0; c < CT; ++c) s += R.gt[r][c] * st[tile_col<T>(c)];
       acc[r] = tile_sum16(s);
     }
     if (bq == 0) {
@@ -171,10 +198,10 @@ struct TiledSolve {
     }
     __syncthreads();
     // lambda = G^{-T} s
-    double cacc[CT];
+    T cacc[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
       for (int r = 0; r < RT; ++r) s += R.gt[r][c] * ss[r0 + r];
       cacc[c] = s;
@@ -186,33 +213,33 @@ struct TiledSolve {
     // N^T lambda, Z^T lambda, V^T lambda -> slabs 0, 1, 2
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
       for (int r = 0; r < RT; ++r) s += R.nt[r][c] * ol[r0 + r];
       cacc[c] = s;
     }
     col_partial(cacc, red);
     {
-      double zacc[CT];
+      T zacc[CT];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) zacc[c] = 0.0;
+      for (int c = 0; c < CT; ++c) zacc[c] = 0;
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        double zr[CT];
-        tile_load_row<CT>(Zk + (long long)(r0 + r) * P, zr);
+        T zr[CT];
+        tile_load_row<CT, T>(Zk + (long long)(r0 + r) * P, zr);
 #pragma unroll
         for (int c = 0; c < CT; ++c) zacc[c] += zr[c] * ol[r0 + r];
       }
       col_partial(zacc, red + kTiledWaves * P);
     }
     if (hv) {
-      double vacc[CT];
+      T vacc[CT];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) vacc[c] = 0.0;
+      for (int c = 0; c < CT; ++c) vacc[c] = 0;
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        double vr[CT];
-        tile_load_row<CT>(Vk + (long long)(r0 + r) * P, vr);
+        T vr[CT];
+        tile_load_row<CT, T>(Vk + (long long)(r0 + r) * P, vr);
 #pragma unroll
         for (int c = 0; c < CT; ++c) vacc[c] += vr[c] * ol[r0 + r];
       }
@@ -224,14 +251,13 @@ struct TiledSolve {
   // Component i of the solution after solve():
   //   u = r_u - N^T lambda, z = r_z - Z^T lambda, mu = V^T lambda - r_m - r_v,
   //   v = -r_m   (lambda is ol[i]).
-  __device__ __forceinline__ static double u_of(const double* scr, const double* sru, int i) {
+  __device__ __forceinline__ static T u_of(const T* scr, const T* sru, int i) {
     return sru[i] - col_total(scr + 2 * P, i);
   }
-  __device__ __forceinline__ static double z_of(const double* scr, const double* srz, int i) {
+  __device__ __forceinline__ static T z_of(const T* scr, const T* srz, int i) {
     return srz[i] - col_total(scr + 2 * P + kTiledWaves * P, i);
   }
-  __device__ __forceinline__ static double mu_of(const double* scr, const double* srm,
-                                                 const double* srv, int i) {
+  __device__ __forceinline__ static T mu_of(const T* scr, const T* srm, const T* srv, int i) {
     return col_total(scr + 2 * P + 2 * kTiledWaves * P, i) - srm[i] - srv[i];
   }
 };

@@ -40,7 +40,8 @@ class pitmg_problem(C.Structure):
 class pitmg_options(C.Structure):
     _fields_ = [("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_tol", C.c_double),
                 ("coarse_maxit", C.c_int), ("coarse_fixed_its", C.c_int),
-                ("restart", C.c_int), ("maxit", C.c_int), ("transfer_variant", C.c_int)]
+                ("restart", C.c_int), ("maxit", C.c_int), ("transfer_variant", C.c_int),
+                ("smoother_fp32", C.c_int)]
 
 
 class pitmg_stats(C.Structure):
