@@ -10,7 +10,15 @@ by one parallel-in-time V-cycle per step, from x0 = 0 to ||b - A~x|| <=
 The roofline object covers the dominant kernel, the block Jacobi sweep: its
 algorithmic bytes (every Jacobian / factor block read once per sweep plus the
 vectors, shared blocks once per launch) over its launch durations, measured
-with HIP events on the solver's stream during the timed steps.
+during the timed steps with start/stop events that the sweep's own kernel
+dispatches record on the solver's stream.  "traffic" is the HBM traffic per
+sweep launch from the committed FETCH_SIZE / WRITE_SIZE counter summary
+(calibrated against a copy kernel), and null once the sweep's sources differ
+from those the counters were taken with; the counter runs use --counters.
+
+Beside the FP64 solve, the line reports the V-cycle's algorithmic HBM rate
+with the FP64 smoother and with the FP32 smoother (every level above the
+coarsest), and one FP32-smoother solve of the same system.
 """
 import argparse
 import json
@@ -23,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+COUNTERS = os.path.join(ROOT, "profiles", "k_jacobi_shared_burgers128_hbm_counters.md")
 
 WORKLOADS = {
     # the measured workload: viscous Burgers, 128 nodes, 1024 steps
@@ -36,23 +45,45 @@ WORKLOADS = {
 }
 
 
-def sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse):
+def sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8):
     """Algorithmic HBM bytes of one block Jacobi sweep on a level of n steps.
 
     Per time-step block: N_k (p*p), V_k (p*p, unless shared), Z~_k (p*q,
-    unless shared), the lower triangle of G_k^{-1} (p(p+1)/2), the right-hand
-    side block (4p+q) read and the new iterate block (4p+q) written, and the
-    two coupling values u_{k-1}, mu_k of the previous iterate (2p; doubled
-    when the interpolated coarse correction is folded in).  Shared blocks
-    count once per launch.  FP64 throughout.
+    unless shared), the lower triangle of G_k^{-1} (p(p+1)/2), each of
+    mat_bytes per entry; the right-hand side block (4p+q) read and the new
+    iterate block (4p+q) written, and the two coupling values u_{k-1}, mu_k of
+    the previous iterate (2p; doubled when the interpolated coarse correction
+    is folded in), FP64.  Shared blocks count once per launch.
     """
-    per = p * p + (0 if shared_V else p * p) + (0 if shared_Z else p * q) + p * (p + 1) // 2
-    per += 2 * (4 * p + q) + 2 * p
-    total = n * per + (2 * p + 2 * p)                       # block n+1
+    mats = p * p + (0 if shared_V else p * p) + (0 if shared_Z else p * q) + p * (p + 1) // 2
+    vecs = 2 * (4 * p + q) + 2 * p
+    total = n * (mats * mat_bytes + vecs * 8) + (2 * p + 2 * p) * 8        # block n+1
     if with_coarse:
-        total += n * 2 * p                                   # coarse coupling values
-    total += (p * p if shared_V else 0) + (p * q if shared_Z else 0)
-    return 8.0 * total
+        total += n * 2 * p * 8                                # coarse coupling values
+    total += ((p * p if shared_V else 0) + (p * q if shared_Z else 0)) * mat_bytes
+    return float(total)
+
+
+def vcycle_bytes(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, mat_bytes=8, fp64_residual=False):
+    """Algorithmic bytes of one V-cycle: the sweeps of every level above the
+    coarsest, the restrictions (coupling values of two iterates read, coarse
+    right-hand side written), the coarse right-hand side and correction, and,
+    with an FP32 smoother, the explicit FP64 finest residual (blocks and two
+    vectors read, one written)."""
+    tot = 0.0
+    for lev in range(L - 1):
+        nl = n >> lev
+        for s_ in range(nu_pre):
+            tot += sweep_bytes(p, q, nl, shared_V, shared_Z, False, mat_bytes)
+        for s_ in range(nu_post):
+            tot += sweep_bytes(p, q, nl, shared_V, shared_Z, s_ == 0, mat_bytes)
+        tot += 8.0 * (4 * p * nl + (4 * p + q) * (nl // 2))
+    nc = n >> (L - 1)
+    tot += 8.0 * 2 * (4 * p + q) * nc
+    if fp64_residual:
+        mats = p * p + (0 if shared_V else p * p) + (0 if shared_Z else p * q)
+        tot += 8.0 * (n * mats + 3 * (4 * p + q) * n)
+    return tot
 
 
 def cpu_baseline(name, iters_full, budget_s=25.0):
@@ -103,8 +134,15 @@ def main():
     ap.add_argument("--workload", default="burgers128", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
-                    help="do not bracket launches with events (value only)")
+                    help="do not time the sweep launches (value only)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-smoother leg")
+    ap.add_argument("--counters", action="store_true",
+                    help="counter-collection run: one solve cut at 40 FGMRES steps (the same "
+                         "launches per V-cycle), then a 256 MiB copy kernel for calibration")
     args = ap.parse_args()
+    if args.counters:
+        args.steps, args.warmup = 1, 0
+        args.no_cpu_baseline = args.no_profile = args.no_fp32 = True
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
               "supported (the time-parallel path shards by time blocks, see the design "
@@ -118,7 +156,8 @@ def main():
 
     wl = WORKLOADS[args.workload]
     prob, b = config_problem(wl["cfg"])
-    opts = pm.default_options(restart=wl["restart"], maxit=wl["maxit"])
+    its_cap = 40 if args.counters else wl["maxit"]
+    opts = pm.default_options(restart=min(wl["restart"], its_cap), maxit=its_cap)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     solver = pm.Solver(prob.levels, opts, device="cuda:0")
@@ -162,6 +201,18 @@ def main():
     p, q, n, L = prob.p, prob.q, prob.n, prob.n_levels
     shared_V, shared_Z = solver.shared_V, solver.shared_Z
 
+    if args.counters:
+        # plain copy kernel of known size for calibrating FETCH_SIZE / WRITE_SIZE
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "fgmres_iters": iters,
+                          "copy_bytes": src.numel() * 8}))
+        solver.close()
+        return
+
     roofline = None
     kern = None
     if prof:
@@ -177,12 +228,63 @@ def main():
         launches, ms = prof["jacobi"]
         alg_bytes = per_vcycle * nvc
         achieved = alg_bytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        from paper_2405_04808_amd.rocprof_summary import read_traffic
+        rec = read_traffic(COUNTERS)
+        kname = ("k_jacobi_shared<%d, %d, double>" % (p // 32, p // 16)
+                 if p == q and p in (64, 128) and shared_V and shared_Z else "k_jacobi")
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "k_jacobi (block Jacobi sweep)",
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": rec["traffic_bytes_per_launch"] if rec else None,
+                    "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
+                    "kernel": kname + " (block Jacobi sweep, all levels)",
                     "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
                     "alg_bytes_per_launch": round(alg_bytes / max(launches, 1))}
         kern = {k: {"launches": v[0], "ms_total": round(v[1], 3)} for k, v in prof.items()}
+
+    def vcycle_rate(s_, mat_bytes, fp64_res, reps=20):
+        """ms per V-cycle (back-to-back calls on the solver's stream) and its
+        algorithmic GB/s."""
+        g = torch.Generator(device="cpu").manual_seed(7)
+        r = torch.randn(prob.size, generator=g, dtype=torch.float64).to(dev)
+        e = s_.empty(0)
+        s_.vcycle(r, out=e)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            s_.vcycle(r, out=e)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_ = ev0.elapsed_time(ev1) / reps
+        by = vcycle_bytes(p, q, n, L, opts.nu_pre, opts.nu_post, shared_V, shared_Z, mat_bytes,
+                          fp64_res)
+        return {"ms": round(ms_, 4), "alg_GB": round(by / 1e9, 4),
+                "GBps": round(by / (ms_ * 1e-3) / 1e9, 1)}
+
+    vc = {"fp64": vcycle_rate(solver, 8, False)}
+    fp32 = None
+    if not args.no_fp32:
+        s32 = pm.Solver(prob.levels, pm.default_options(restart=wl["restart"], maxit=wl["maxit"],
+                                                        smoother_fp32=99), device="cuda:0")
+        vc["fp32"] = vcycle_rate(s32, 4, True)
+        x32 = s32.empty(0)
+        _, st32, _ = s32.solve(db, tol=1e-10, out=x32)           # warm-up
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        st32s = []
+        for _ in range(2):
+            s32.refactor_device()
+            _, st32, _ = s32.solve(db, tol=1e-10, out=x32)
+            st32s.append(st32)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        diff = float(torch.linalg.vector_norm(x32 - x) / torch.linalg.vector_norm(x))
+        fp32 = {"smoother": "FP32 on every level above the coarsest; FP64 finest residual, "
+                            "coarse solve, Arnoldi and FGMRES",
+                "ms_per_step": round((tb - ta) * 1e3 / 2, 3), "fgmres_iters": [t["iters"] for t in st32s],
+                "relres_true": max(t["relres_true"] for t in st32s),
+                "rel_diff_vs_fp64_solution": diff}
+        s32.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -208,6 +310,8 @@ def main():
         "converged_1e-10": ok,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "vcycle_hbm": vc,
+        "fp32_smoother": fp32,
         "kernel_ms": kern,
     }
     print(json.dumps(out))

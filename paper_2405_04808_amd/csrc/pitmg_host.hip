@@ -49,6 +49,11 @@ constexpr int kNumClasses = 6;
 
 }  // namespace
 
+KernelEvents& pitmg::kernel_events() {
+  static thread_local KernelEvents ev;
+  return ev;
+}
+
 struct pitmg_handle {
   hipStream_t stream = nullptr;
   int p = 0, q = 0, n = 0, L = 0;
@@ -149,6 +154,34 @@ int timed(pitmg_handle* h, int cls, F&& launch) {
   HIPCHK(h, hipEventRecord(r.a, h->stream));
   HIPCHK(h, launch());
   HIPCHK(h, hipEventRecord(r.b, h->stream));
+  h->pending.push_back(r);
+  if (h->pending.size() > 4096) drain(h);
+  return PITMG_OK;
+}
+
+// Time a launcher whose kernels go through launch_k: the kernels' own
+// dispatches record the start and end times.
+template <class F>
+int timed_kernel(pitmg_handle* h, int cls, F&& launch) {
+  if (!h->prof) {
+    HIPCHK(h, launch());
+    return PITMG_OK;
+  }
+  ProfRec r{cls, take_event(h), take_event(h)};
+  KernelEvents& ev = kernel_events();
+  ev.start = r.a;
+  ev.stop = r.b;
+  ev.taken = 0;
+  const hipError_t e = launch();
+  const int taken = ev.taken;
+  ev = KernelEvents{};
+  if (e != hipSuccess)
+    return set_err(h, PITMG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  if (taken == 0) {
+    h->pool.push_back(r.a);
+    h->pool.push_back(r.b);
+    return set_err(h, PITMG_ERR_HIP, "profiling: the launcher issued no timed kernel");
+  }
   h->pending.push_back(r);
   if (h->pending.size() > 4096) drain(h);
   return PITMG_OK;
@@ -353,7 +386,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   for (int s = 0; s < o.nu_pre; ++s) {
     double* dst = bufs[s & 1];
     const double* yo = ycur;
-    rc = timed(h, 1, [&] { return launch_jacobi(v, b, yo, nullptr, var, dst, h->stream); });
+    rc = timed_kernel(h, 1, [&] { return launch_jacobi(v, b, yo, nullptr, var, dst, h->stream); });
     if (rc) return rc;
     yprev = ycur;
     ycur = dst;
@@ -390,7 +423,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
     double* dst = (s == o.nu_post - 1) ? out : (ycur == bufs[0] ? bufs[1] : bufs[0]);
     const double* yo = ycur;
     const double* ec = s == 0 ? C.out : nullptr;
-    rc = timed(h, 1, [&] { return launch_jacobi(v, b, yo, ec, var, dst, h->stream); });
+    rc = timed_kernel(h, 1, [&] { return launch_jacobi(v, b, yo, ec, var, dst, h->stream); });
     if (rc) return rc;
     ycur = dst;
   }

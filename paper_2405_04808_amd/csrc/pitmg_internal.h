@@ -1,6 +1,7 @@
 // Internal declarations shared by the kernel and host translation units.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 
 namespace pitmg {
@@ -50,6 +51,30 @@ struct TypeMajor {
     m = l + (long long)p * n; len = m + (long long)p * n;
   }
 };
+
+// Events armed by the host's kernel timer.  A launcher that issues its kernel
+// through launch_k lets the kernel's own dispatch record the start (first
+// kernel only) and the end (every kernel, so the last one counts), with no
+// marker packets around it; the start slot is cleared once taken.
+struct KernelEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+  int taken = 0;
+};
+KernelEvents& kernel_events();   // per host thread (pitmg_host.hip)
+
+template <class F, class... Args>
+hipError_t launch_k(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                    Args... args) {
+  KernelEvents& ev = kernel_events();
+  hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, s, ev.start, ev.stop, 0u,
+                        args...);
+  if (ev.stop) {
+    ev.start = nullptr;
+    ev.taken += 1;
+  }
+  return hipGetLastError();
+}
 
 // ---- launchers (pitmg_kernels.hip) ---------------------------------------
 // Factor every block of one level: S_k = N_k N_k^T + Z_k Z_k^T, Cholesky

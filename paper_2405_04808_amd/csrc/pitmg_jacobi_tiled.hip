@@ -81,11 +81,11 @@ static hipError_t launch_tiled_t(const LevelView& L, const double* b, const doub
                                  const double* ecoarse, int variant, double* ynew,
                                  hipStream_t s) {
   if (L.p == 128 && L.q == 128) {
-    hipLaunchKernelGGL((k_jacobi_tiled<4, 8, T>), dim3(L.n + 1), dim3(kTiledThreads), 0, s, L,
-                       b, yold, ecoarse, variant, ynew);
+    return launch_k(k_jacobi_tiled<4, 8, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b, yold,
+                    ecoarse, variant, ynew);
   } else if (L.p == 64 && L.q == 64) {
-    hipLaunchKernelGGL((k_jacobi_tiled<2, 4, T>), dim3(L.n + 1), dim3(kTiledThreads), 0, s, L,
-                       b, yold, ecoarse, variant, ynew);
+    return launch_k(k_jacobi_tiled<2, 4, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b, yold,
+                    ecoarse, variant, ynew);
   } else {
     return hipErrorInvalidValue;
   }
@@ -328,11 +328,11 @@ static hipError_t launch_shared_t(const LevelView& L, const double* b, const dou
                                   hipStream_t s) {
   const int nwg = (L.n + per - 1) / per;
   if (L.p == 128) {
-    hipLaunchKernelGGL((k_jacobi_shared<4, 8, T>), dim3(nwg), dim3(kTiledThreads), 0, s, L, b,
-                       yold, ecoarse, variant, ynew, per);
+    return launch_k(k_jacobi_shared<4, 8, T>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
+                    ecoarse, variant, ynew, per);
   } else if (L.p == 64) {
-    hipLaunchKernelGGL((k_jacobi_shared<2, 4, T>), dim3(nwg), dim3(kTiledThreads), 0, s, L, b,
-                       yold, ecoarse, variant, ynew, per);
+    return launch_k(k_jacobi_shared<2, 4, T>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
+                    ecoarse, variant, ynew, per);
   } else {
     return hipErrorInvalidValue;
   }

@@ -245,9 +245,8 @@ static hipError_t launch_jacobi_generic(const LevelView& L, const double* b, con
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_jacobi<kSweepThreads, T>), dim3(L.n + 1), dim3(kSweepThreads), lds, s,
-                     L, b, yold, ecoarse, variant, ynew);
-  return hipGetLastError();
+  return launch_k(k_jacobi<kSweepThreads, T>, dim3(L.n + 1), dim3(kSweepThreads), lds, s, L, b,
+                  yold, ecoarse, variant, ynew);
 }
 
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,

@@ -1,0 +1,229 @@
+"""Summaries of rocprofv3 CSV output for the profiles kept with the sources.
+
+Two kinds of run are summarised:
+
+* a kernel trace (``rocprofv3 --kernel-trace --stats -f csv``): the per-kernel
+  table of ``*_kernel_stats.csv`` (calls, total, average, min, max);
+* two counter runs (``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``,
+  ``-f csv``) of a program that launches the block Jacobi sweep and then a
+  plain copy kernel of known size.  The counters are in KiB per dispatch; the
+  copy kernel reads and writes a known number of bytes, so
+  bytes = counter * 1024 * (known KiB / copy counter) calibrates each counter
+  against the device.  The result is the HBM traffic per sweep launch,
+  averaged over every sweep dispatch of the run, beside the algorithmic
+  bytes.
+
+The counter summary ends with one machine-readable line,
+``traffic: {json}``, which bench.py reads together with a hash of the sweep
+kernel's sources; the figure is only used while that hash matches.
+
+    python -m paper_2405_04808_amd.rocprof_summary stats DIR --title T --command C
+    python -m paper_2405_04808_amd.rocprof_summary counters --fetch DIR --write DIR \\
+        --kernel k_jacobi_shared --copy-kernel elementwise --copy-bytes B ...
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SWEEP_SOURCES = ("csrc/pitmg_jacobi_tiled.hip", "csrc/pitmg_tiled.h", "csrc/pitmg_device.h")
+
+
+def sweep_source_hash() -> str:
+    """sha256 over the sources of the register-tiled sweep kernels."""
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find(directory: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {directory}")
+    return hits[-1]
+
+
+def _short(name: str, width: int = 60) -> str:
+    name = re.sub(r"\s+", " ", name).replace("(anonymous namespace)::", "")
+    name = re.sub(r"^void ", "", name)
+    name = re.sub(r"\(.*$", "", name).replace("pitmg::", "")
+    return name if len(name) <= width else name[: width - 3] + "..."
+
+
+def stats_table(directory: str, top: int = 25) -> str:
+    path = _find(directory, "kernel_stats.csv")
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | total ms | avg us | % | min us | max us |",
+           "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append("| `{}` | {} | {:.1f} | {:.2f} | {:.1f} | {:.2f} | {:.2f} |".format(
+            _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e3, float(r["Percentage"]), float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3))
+    return "\n".join(out)
+
+
+def counter_means(directory: str, counter: str):
+    """{kernel name: {grid size: [values]}} for one counter."""
+    path = _find(directory, "counter_collection.csv")
+    out = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        out[r["Kernel_Name"]][int(r["Grid_Size"])].append(float(r["Counter_Value"]))
+    return out
+
+
+def _select(table, pattern: str, exclude_grids=()):
+    rx = re.compile(pattern)
+    names = [k for k in table if rx.search(k)]
+    if not names:
+        raise KeyError(f"no kernel matches {pattern!r}")
+    merged = defaultdict(list)
+    for k in names:
+        for g, vals in table[k].items():
+            if g not in exclude_grids:
+                merged[g].extend(vals)
+    return names, merged
+
+
+def per_grid_durations(directory: str, pattern: str):
+    """{grid size: [durations in us]} of the dispatches of kernels matching
+    pattern, from *_kernel_trace.csv."""
+    path = _find(directory, "kernel_trace.csv")
+    rx = re.compile(pattern)
+    out = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if rx.search(r["Kernel_Name"]):
+            g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            out[g].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return out
+
+
+def summarise_counters(fetch_dir, write_dir, kernel, copy_kernel, copy_bytes, exclude_grids=()):
+    f_tab = counter_means(fetch_dir, "FETCH_SIZE")
+    w_tab = counter_means(write_dir, "WRITE_SIZE")
+    names, f_sweep = _select(f_tab, kernel, exclude_grids)
+    _, w_sweep = _select(w_tab, kernel, exclude_grids)
+    _, f_copy = _select(f_tab, copy_kernel)
+    _, w_copy = _select(w_tab, copy_kernel)
+    known_kib = copy_bytes / 1024.0
+    f_copy_all = [v for vals in f_copy.values() for v in vals]
+    w_copy_all = [v for vals in w_copy.values() for v in vals]
+    cf = known_kib / (sum(f_copy_all) / len(f_copy_all))
+    cw = known_kib / (sum(w_copy_all) / len(w_copy_all))
+    rows = []
+    tot_f = tot_w = cnt = 0.0
+    for g in sorted(f_sweep, reverse=True):
+        fv, wv = f_sweep[g], w_sweep.get(g, [])
+        mf = sum(fv) / len(fv)
+        mw = sum(wv) / len(wv) if wv else float("nan")
+        rows.append((g, len(fv), mf, mw, mf * 1024 * cf, mw * 1024 * cw))
+        tot_f += sum(fv)
+        tot_w += sum(wv)
+        cnt += len(fv)
+    per_launch = (tot_f / cnt) * 1024 * cf + (tot_w / cnt) * 1024 * cw
+    return {"kernels": names, "rows": rows, "fetch_factor": cf, "write_factor": cw,
+            "copy_fetch_kib": sum(f_copy_all) / len(f_copy_all),
+            "copy_write_kib": sum(w_copy_all) / len(w_copy_all), "copy_known_kib": known_kib,
+            "dispatches": int(cnt), "traffic_bytes_per_launch": per_launch}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("dir")
+    a.add_argument("--title", required=True)
+    a.add_argument("--command", required=True)
+    a.add_argument("--note", default="")
+    a.add_argument("--per-grid", default=None,
+                   help="kernel regex: add its dispatch durations grouped by grid size")
+    a.add_argument("--exclude-grid", type=int, action="append", default=[])
+    a.add_argument("--out", required=True)
+    b = sub.add_parser("counters")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--kernel", required=True)
+    b.add_argument("--copy-kernel", required=True)
+    b.add_argument("--copy-bytes", type=float, required=True)
+    b.add_argument("--title", required=True)
+    b.add_argument("--command", action="append", required=True)
+    b.add_argument("--note", default="")
+    b.add_argument("--exclude-grid", type=int, action="append", default=[],
+                   help="grid size (work-items) whose dispatches are left out")
+    b.add_argument("--out", required=True)
+    args = ap.parse_args(argv)
+
+    if args.cmd == "stats":
+        txt = [f"# {args.title}", "", "Command (from the repository root, MI355X, ROCm 7.2):", "",
+               "```", args.command, "```", ""]
+        if args.note:
+            txt += [args.note, ""]
+        txt += [stats_table(args.dir), ""]
+        if args.per_grid:
+            d = per_grid_durations(args.dir, args.per_grid)
+            txt += [f"Dispatches of `{args.per_grid}` by grid size (work-items):", "",
+                    "| grid | dispatches | avg us | total ms |", "|---|---|---|---|"]
+            keep = []
+            for g in sorted(d, reverse=True):
+                v = d[g]
+                mark = " (left out below)" if g in args.exclude_grid else ""
+                txt.append(f"| {g}{mark} | {len(v)} | {sum(v) / len(v):.2f} | {sum(v) / 1e3:.1f} |")
+                if g not in args.exclude_grid:
+                    keep += v
+            txt += ["", "Average over the {} dispatches not left out: {:.2f} us.".format(
+                len(keep), sum(keep) / max(len(keep), 1)), ""]
+        open(args.out, "w").write("\n".join(txt))
+        return 0
+
+    s = summarise_counters(args.fetch, args.write, args.kernel, args.copy_kernel,
+                           args.copy_bytes, tuple(args.exclude_grid))
+    txt = [f"# {args.title}", "", "Commands (from the repository root, MI355X, ROCm 7.2):", "",
+           "```"] + args.command + ["```", ""]
+    if args.note:
+        txt += [args.note, ""]
+    txt += ["Calibration: the copy kernel moves {:.0f} KiB each way; FETCH_SIZE read {:.0f} KiB "
+            "and WRITE_SIZE {:.0f} KiB per dispatch, so the factors are {:.4f} (fetch) and "
+            "{:.4f} (write).".format(s["copy_known_kib"], s["copy_fetch_kib"],
+                                     s["copy_write_kib"], s["fetch_factor"], s["write_factor"]),
+            "", "Sweep kernel(s): " + ", ".join(f"`{_short(k, 80)}`" for k in s["kernels"]), "",
+            "| grid (work-groups x threads) | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB "
+            "| fetched MB (calibrated) | written MB (calibrated) |",
+            "|---|---|---|---|---|---|"]
+    for g, c, mf, mw, bf, bw in s["rows"]:
+        txt.append(f"| {g} | {c} | {mf:.0f} | {mw:.0f} | {bf / 1e6:.2f} | {bw / 1e6:.2f} |")
+    rec = {"kernel": args.kernel, "traffic_bytes_per_launch": round(s["traffic_bytes_per_launch"]),
+           "dispatches": s["dispatches"], "fetch_factor": round(s["fetch_factor"], 5),
+           "write_factor": round(s["write_factor"], 5), "sources_sha256": sweep_source_hash()}
+    txt += ["", "Average over all {} sweep dispatches: {:.2f} MB per launch.".format(
+        s["dispatches"], s["traffic_bytes_per_launch"] / 1e6), "", "traffic: " + json.dumps(rec),
+        ""]
+    open(args.out, "w").write("\n".join(txt))
+    return 0
+
+
+def read_traffic(path: str):
+    """The traffic record of a counter summary, or None if absent or stale."""
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic: "):
+            rec = json.loads(line[len("traffic: "):])
+            return rec if rec.get("sources_sha256") == sweep_source_hash() else None
+    return None
+
+
+if __name__ == "__main__":
+    sys.exit(main())
