@@ -104,6 +104,13 @@ typedef struct {
                                   the finest-level residual, the coarse solve,
                                   FGMRES and Arnoldi stay FP64.  0: all FP64.
                                   Fixed at setup.                               */
+  int coarse_mode;             /* 0: GMRES + SGS on the coarsest grid; 1: the
+                                  attached network (pitmg_coarse_net_attach)
+                                  replaces it until the stall rule falls back
+                                  to GMRES + SGS for the rest of the solve      */
+  double stall_ratio;          /* stall rule: FGMRES residual-estimate ratio
+                                  est_j / est_{j-1} above this ...             */
+  int stall_steps;             /* ... on this many consecutive steps           */
 } pitmg_options;
 
 typedef struct {
@@ -114,10 +121,14 @@ typedef struct {
   int coarse_calls;            /* coarse solves in this call                   */
   int coarse_its_total;        /* their GMRES steps, summed                    */
   double ms_solve;             /* wall time of the call, ms                    */
+  int net_calls;               /* coarse corrections given by the network      */
+  int fallback_at;             /* first FGMRES step (0-based) that used GMRES +
+                                  SGS after the stall rule fired, or -1        */
 } pitmg_stats;
 
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
- * transfer_variant 0, smoother_fp32 0. */
+ * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
+ * stall_steps 2. */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and
@@ -166,6 +177,81 @@ int pitmg_profile_reset(pitmg_handle* h);
 /* After PITMG_ERR_SINGULAR: the (level, step k, 1-based) of the first
  * failing block. */
 int pitmg_failed_block(const pitmg_handle* h, int* level, int* k);
+
+/* ------------------------------------------------------------------------
+ * Learned coarse-grid correction (a project extension: the paper has no
+ * learned component; FGMRES admits a preconditioner that changes from step
+ * to step, Sec. 5.3.4, which is what makes replacing the coarse solve safe).
+ *
+ * Network over the T coarse steps, C = 4p+q channels, H hidden channels:
+ *     x = r_c / s,  s = ||r_c||_2 / sqrt(T C)        (s = 0 gives e_c = 0)
+ *     h1 = tanh(conv(W1,b1,x)), h2 = tanh(conv(W2,b2,h1)), y = conv(W3,b3,h2)
+ *     e_c = s y
+ * conv(W,b,x)[t][o] = b[o] + sum_{c,d} W[o][c][d] x[t+d-1][c], zero padded in
+ * time; W1 [H][C][3], W2 [H][H][3], W3 [C][H][3].  Samples are node-major FP32
+ * [T][C] rows (u_t, v_t, z_t, lambda_t, mu_t).  Parameters: one flat FP32
+ * vector [W1, b1, W2, b2, W3, b3] (pitmg_net_param_count entries), the master
+ * copy; products run on bfloat16 operands (weights, layer inputs, layer
+ * output gradients, rounded to nearest even) with FP32 accumulation.
+ * Training: mean squared error over all entries, Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8, bias-corrected).  All pointers below are DEVICE pointers
+ * unless marked host.  A network runs on its own stream for training and on
+ * the handle's stream when attached; do not train a network while a handle
+ * it is attached to is solving.
+ * ---------------------------------------------------------------------- */
+typedef struct pitmg_net pitmg_net;
+
+long long pitmg_net_param_count(int C, int H);
+
+/* Create a network for C channels over T steps with H hidden channels that
+ * trains on batches of up to max_batch samples.  Parameters start at zero:
+ * set them with pitmg_net_set_params. */
+int pitmg_net_create(pitmg_net** net, int C, int T, int H, int max_batch, void* stream);
+
+/* Copy the FP32 master parameters in (device pointer if on_device, else
+ * host) and reset the Adam state. */
+int pitmg_net_set_params(pitmg_net* net, const float* theta, int on_device);
+/* Copy the FP32 master parameters out to host memory. */
+int pitmg_net_get_params(pitmg_net* net, float* theta_host);
+
+/* y = net(x) for batch samples: x, y [batch][T][C] FP32. */
+int pitmg_net_forward(pitmg_net* net, int batch, const float* x, float* y);
+
+/* grad = d(loss)/d(theta) for a loss whose gradient w.r.t. y = net(x) is dy
+ * (all [batch][T][C] FP32); grad: FP32 [param_count]. */
+int pitmg_net_backward(pitmg_net* net, int batch, const float* x, const float* dy,
+                       float* grad);
+
+/* One Adam step of the master parameters with the given gradient. */
+int pitmg_net_adam(pitmg_net* net, const float* grad, float lr);
+
+/* One training step on the samples idx[0..batch) (device int32 indices into
+ * X, Y: [count][T][C] FP32 inputs and targets): forward, mean squared error,
+ * backward, Adam.  An index outside [0, count) reads as a zero sample.
+ * *loss (host, may be NULL) receives the batch loss before the step. */
+int pitmg_net_train_step(pitmg_net* net, int batch, const int* idx, int count,
+                         const float* X, const float* Y, float lr, double* loss);
+
+/* Training samples from count type-major coarse pairs (r_c, e_c), each of
+ * length C T with C = 4p+q: X[i] = node-major r_c / s, Y[i] = e_c / s. */
+int pitmg_net_make_samples(pitmg_net* net, int count, int p, int q, const double* r,
+                           const double* e, float* X, float* Y);
+
+const char* pitmg_net_last_error(const pitmg_net* net);
+void pitmg_net_destroy(pitmg_net* net);
+
+/* Use net for the coarse solve of h when coarse_mode = 1 (NULL detaches).
+ * The network's C and T must be 4p+q and the coarsest step count.  The
+ * handle borrows the network: keep it alive while attached. */
+int pitmg_coarse_net_attach(pitmg_handle* h, pitmg_net* net);
+
+/* Record the (right-hand side, solution) pairs of the next GMRES + SGS
+ * coarse solves into r, e ([cap][len_c] FP64 type-major, len_c = (4p+q) T),
+ * until cap pairs are held; cap = 0 stops recording.  Buffers are
+ * caller-owned and must stay alive while recording. */
+int pitmg_coarse_pairs_arm(pitmg_handle* h, double* r, double* e, int cap);
+/* Pairs recorded since the last arm. */
+int pitmg_coarse_pairs_count(const pitmg_handle* h);
 
 /* Bytes of device memory held by the handle. */
 long long pitmg_device_bytes(const pitmg_handle* h);

@@ -89,6 +89,14 @@ struct pitmg_handle {
   std::vector<hipEvent_t> pool;
   int prof_launches[kNumClasses] = {0};
   double prof_ms[kNumClasses] = {0};
+  // learned coarse correction
+  pitmg_net* net = nullptr;          // borrowed
+  bool fell_back = false;            // stall rule fired in this solve
+  bool last_plain = false;           // last coarse correction was GMRES + SGS
+  int net_calls = 0;
+  double* pair_r = nullptr;          // caller-owned pair buffers
+  double* pair_e = nullptr;
+  int pair_cap = 0, pair_count = 0;
 };
 
 namespace {
@@ -220,6 +228,10 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
   if (o.transfer_variant != 0 && o.transfer_variant != 1)
     return set_err(h, PITMG_ERR_INVALID, "transfer_variant must be 0 or 1");
   if (o.smoother_fp32 < 0) return set_err(h, PITMG_ERR_INVALID, "smoother_fp32 must be >= 0");
+  if (o.coarse_mode != 0 && o.coarse_mode != 1)
+    return set_err(h, PITMG_ERR_INVALID, "coarse_mode must be 0 or 1");
+  if (!(o.stall_ratio > 0.0) || o.stall_steps < 1)
+    return set_err(h, PITMG_ERR_INVALID, "stall_ratio must be > 0 and stall_steps >= 1");
   return PITMG_OK;
 }
 
@@ -371,12 +383,38 @@ int coarse_solve(pitmg_handle* h, const double* b, double* out) {
   });
 }
 
+// Coarsest level inside a V-cycle: the attached network while coarse_mode
+// is 1 and the stall rule has not fired, else GMRES + SGS (recording the
+// pair when armed).
+int coarse_dispatch(pitmg_handle* h, const double* b, double* out) {
+  if (h->opt.coarse_mode == 1 && !h->fell_back) {
+    if (!h->net) return set_err(h, PITMG_ERR_INVALID, "coarse_mode 1 needs an attached network");
+    h->last_plain = false;
+    h->net_calls++;
+    return timed(h, 4, [&] {
+      return net_coarse_correction(h->net, b, out, h->p, h->q, h->stream);
+    });
+  }
+  h->last_plain = true;
+  int rc = coarse_solve(h, b, out);
+  if (rc) return rc;
+  if (h->pair_count < h->pair_cap) {
+    const long long len = h->lv[h->L - 1].len;
+    HIPCHK(h, hipMemcpyAsync(h->pair_r + (size_t)h->pair_count * len, b, len * 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->pair_e + (size_t)h->pair_count * len, out, len * 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+    h->pair_count++;
+  }
+  return PITMG_OK;
+}
+
 // MG_l(b) -> out (Alg. 1 recursed; zero initial guess on every level).
 int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   const pitmg_options& o = h->opt;
   const int var = o.transfer_variant;
   LevelView v = view(h, l);
-  if (l == h->L - 1) return coarse_solve(h, b, out);
+  if (l == h->L - 1) return coarse_dispatch(h, b, out);
   LevelBuf& B = h->lv[l];
   LevelBuf& C = h->lv[l + 1];
   double* bufs[2] = {B.y0, B.y1};
@@ -494,7 +532,32 @@ void pitmg_default_options(pitmg_options* o) {
   o->maxit = 300;
   o->transfer_variant = 0;
   o->smoother_fp32 = 0;
+  o->coarse_mode = 0;
+  o->stall_ratio = 0.9;
+  o->stall_steps = 2;
 }
+
+int pitmg_coarse_net_attach(pitmg_handle* h, pitmg_net* net) {
+  if (!h) return PITMG_ERR_INVALID;
+  const int L = h->L - 1;
+  if (net && !net_matches(net, 4 * h->p + h->q, h->lv[L].n))
+    return set_err(h, PITMG_ERR_INVALID,
+                   "the network's channels and steps must be 4p+q and the coarsest step count");
+  h->net = net;
+  return PITMG_OK;
+}
+
+int pitmg_coarse_pairs_arm(pitmg_handle* h, double* r, double* e, int cap) {
+  if (!h || cap < 0) return PITMG_ERR_INVALID;
+  if (cap > 0 && (!r || !e)) return set_err(h, PITMG_ERR_INVALID, "pair buffers are NULL");
+  h->pair_r = r;
+  h->pair_e = e;
+  h->pair_cap = cap;
+  h->pair_count = 0;
+  return PITMG_OK;
+}
+
+int pitmg_coarse_pairs_count(const pitmg_handle* h) { return h ? h->pair_count : 0; }
 
 int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options* opt,
                 void* stream) {
@@ -657,7 +720,7 @@ int pitmg_jacobi_sweep(pitmg_handle* h, int level, const double* b, const double
 
 int pitmg_coarse_solve(pitmg_handle* h, const double* b, double* x, int* its) {
   if (!h || !b || !x) return PITMG_ERR_INVALID;
-  int rc = vcycle_level(h, h->L - 1, b, x);
+  int rc = coarse_solve(h, b, x);
   if (rc) return rc;
   int hv = 0;
   HIPCHK(h, hipMemcpyAsync(&hv, h->coarse_its + ((h->coarse_calls - 1) % h->coarse_log_cap),
@@ -670,6 +733,7 @@ int pitmg_coarse_solve(pitmg_handle* h, const double* b, double* x, int* its) {
 int pitmg_vcycle(pitmg_handle* h, const double* r, double* e) {
   if (!h || !r || !e) return PITMG_ERR_INVALID;
   if (r == e) return set_err(h, PITMG_ERR_INVALID, "r and e must differ");
+  h->fell_back = false;
   return vcycle_level(h, 0, r, e);
 }
 
@@ -688,7 +752,13 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
   const long long len = h->lv[0].len;
   const int m = h->opt.restart, maxit = h->opt.maxit;
   const int calls0 = h->coarse_calls;
+  const int net0 = h->net_calls;
   const int ns = krylov_slices(len);
+  if (h->opt.coarse_mode == 1 && !h->net)
+    return set_err(h, PITMG_ERR_INVALID, "coarse_mode 1 needs an attached network");
+  h->fell_back = false;
+  int fallback_at = -1, stalled = 0;
+  double est_prev = 1.0;
   LevelView v0 = view(h, 0);
   int rc;
   double bnorm = 0.0;
@@ -741,13 +811,15 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
       if ((rc = vcycle_level(h, 0, Vp(j), Zp(j)))) return rc;
       if ((rc = timed(h, 2, [&] { return launch_apply(v0, Zp(j), nullptr, 1.0, 0.0, h->w, h->stream); })))
         return rc;
-      HIPCHK(h, hipMemcpyAsync(h->its_pinned,
-                               h->coarse_its + ((h->coarse_calls - 1) % h->coarse_log_cap),
-                               sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      const bool plain = h->last_plain;
+      if (plain)
+        HIPCHK(h, hipMemcpyAsync(h->its_pinned,
+                                 h->coarse_its + ((h->coarse_calls - 1) % h->coarse_log_cap),
+                                 sizeof(int), hipMemcpyDeviceToHost, h->stream));
       // one pass: s = Q^T v_j, hh = Q^T w, v_j.v_j, v_j.w, w.w
       if ((rc = dots(h, h->Vk, j, Vp(j), h->w, len))) return rc;
       if ((rc = fetch_coef(h, 2 * j + 3))) return rc;
-      h->coarse_k = std::max(1, h->its_pinned[0]);   // coarse steps to enqueue next time
+      if (plain) h->coarse_k = std::max(1, h->its_pinned[0]);   // coarse steps to enqueue next time
       const double* cb = h->hbuf;
       const double vv = cb[2 * j], vw = cb[2 * j + 1], ww = cb[2 * j + 2];
       double alpha = 1.0, ss = 0.0, sh = 0.0;
@@ -783,6 +855,15 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
         for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += rho_prev * sv[i];
         H[(size_t)j * m + (j - 1)] = rho_prev * alpha;
         est = givens_column(H, m, j - 1, cs, sn, g) / bnorm;
+        // stall rule of the learned coarse correction
+        if (h->opt.coarse_mode == 1 && !h->fell_back) {
+          stalled = est > h->opt.stall_ratio * est_prev ? stalled + 1 : 0;
+          if (stalled >= h->opt.stall_steps) {
+            h->fell_back = true;
+            fallback_at = total + 1;      // first step to use GMRES + SGS
+          }
+        }
+        est_prev = est;
       }
       // column j as far as known: w = Q hh + cq q_j + rho v_{j+1}
       for (int i = 0; i < j; ++i) H[(size_t)i * m + j] = hv[i];
@@ -868,6 +949,8 @@ int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol
   S.coarse_calls = ncalls;
   S.coarse_its_total = (int)cits;
   S.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  S.net_calls = h->net_calls - net0;
+  S.fallback_at = fallback_at;
   if (st) *st = S;
   return converged ? PITMG_OK : PITMG_NOT_CONVERGED;
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_ext.h>
 #include <cstdint>
 
+struct pitmg_net;   // learned coarse correction (pitmg_net.hip)
+
 namespace pitmg {
 
 constexpr int kWave = 64;
@@ -169,5 +171,13 @@ hipError_t launch_scale(double* dst, const double* src, double alpha,
                         long long len, hipStream_t s);
 hipError_t launch_axpby(double* y, const double* x, double a, double b,
                         long long len, hipStream_t s);   // y = a*x + b*y
+
+// ---- learned coarse correction (pitmg_net.hip) ----------------------------
+// True if the network takes C channels over T steps.
+bool net_matches(const pitmg_net* n, int C, int T);
+// e = s * net(r / s) for one type-major coarse vector of the network's shape
+// (s = rms(r)), enqueued on stream s; uses the network's work buffers.
+hipError_t net_coarse_correction(pitmg_net* n, const double* r, double* e, int p, int q,
+                                 hipStream_t s);
 
 }  // namespace pitmg

@@ -41,13 +41,15 @@ class pitmg_options(C.Structure):
     _fields_ = [("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_tol", C.c_double),
                 ("coarse_maxit", C.c_int), ("coarse_fixed_its", C.c_int),
                 ("restart", C.c_int), ("maxit", C.c_int), ("transfer_variant", C.c_int),
-                ("smoother_fp32", C.c_int)]
+                ("smoother_fp32", C.c_int), ("coarse_mode", C.c_int), ("stall_ratio", C.c_double),
+                ("stall_steps", C.c_int)]
 
 
 class pitmg_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("relres_est", C.c_double),
                 ("relres_true", C.c_double), ("coarse_calls", C.c_int),
-                ("coarse_its_total", C.c_int), ("ms_solve", C.c_double)]
+                ("coarse_its_total", C.c_int), ("ms_solve", C.c_double),
+                ("net_calls", C.c_int), ("fallback_at", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -87,6 +89,20 @@ def load_library(path: str = LIB_PATH):
         "pitmg_profile_reset": (i, [vp]),
         "pitmg_failed_block": (i, [vp, C.POINTER(i), C.POINTER(i)]),
         "pitmg_device_bytes": (C.c_longlong, [vp]),
+        "pitmg_net_param_count": (C.c_longlong, [i, i]),
+        "pitmg_net_create": (i, [C.POINTER(vp), i, i, i, i, vp]),
+        "pitmg_net_set_params": (i, [vp, vp, i]),
+        "pitmg_net_get_params": (i, [vp, vp]),
+        "pitmg_net_forward": (i, [vp, i, vp, vp]),
+        "pitmg_net_backward": (i, [vp, i, vp, vp, vp]),
+        "pitmg_net_adam": (i, [vp, vp, C.c_float]),
+        "pitmg_net_train_step": (i, [vp, i, vp, i, vp, vp, C.c_float, C.POINTER(d)]),
+        "pitmg_net_make_samples": (i, [vp, i, i, i, vp, vp, vp, vp]),
+        "pitmg_net_last_error": (C.c_char_p, [vp]),
+        "pitmg_net_destroy": (None, [vp]),
+        "pitmg_coarse_net_attach": (i, [vp, vp]),
+        "pitmg_coarse_pairs_arm": (i, [vp, vp, vp, i]),
+        "pitmg_coarse_pairs_count": (i, [vp]),
         "pitmg_status_string": (C.c_char_p, [i]),
         "pitmg_last_error": (C.c_char_p, [vp]),
         "pitmg_destroy": (None, [vp]),
@@ -273,6 +289,21 @@ class Solver:
     def device_bytes(self) -> int:
         return self.lib.pitmg_device_bytes(self.h)
 
+    # -- learned coarse correction ------------------------------------------------
+    def attach_net(self, net: Optional["Net"]):
+        """Use net for the coarse solve when coarse_mode = 1 (None detaches)."""
+        self._net = net
+        self._check(self.lib.pitmg_coarse_net_attach(self.h, net.h if net is not None else None))
+
+    def arm_pairs(self, r, e, cap: int):
+        """Record (r_c, e_c) of the next GMRES+SGS coarse solves into r, e
+        (device FP64 [cap][len_c])."""
+        self._pairs = (r, e)
+        self._check(self.lib.pitmg_coarse_pairs_arm(self.h, _ptr(r), _ptr(e), int(cap)))
+
+    def pair_count(self) -> int:
+        return self.lib.pitmg_coarse_pairs_count(self.h)
+
     def close(self):
         if getattr(self, "h", None) and self.h.value:
             self.lib.pitmg_destroy(self.h)
@@ -283,3 +314,87 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """The learned coarse correction's network (pitmg_net_*): C channels over
+    T coarse steps, H hidden channels, batches up to max_batch.  Tensors are
+    torch device tensors; every computation runs in the HIP library."""
+
+    def __init__(self, C: int, T: int, H: int = 64, max_batch: int = 256, device: str = "cuda",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.C, self.T, self.H, self.max_batch = C, T, H, max_batch
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = _c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.pitmg_net_create(_byref(self.h), C, T, H, max_batch,
+                                           _c_void_p(self.stream.cuda_stream))
+        if rc < 0:
+            raise PitmgError(rc, "pitmg_net_create failed")
+        self.P = int(self.lib.pitmg_net_param_count(C, H))
+
+    def _check(self, rc):
+        if rc < 0:
+            msg = self.lib.pitmg_net_last_error(self.h)
+            raise PitmgError(rc, msg.decode() if msg else "")
+        return rc
+
+    def set_params(self, theta):
+        t = self.torch.as_tensor(theta, dtype=self.torch.float32).contiguous().to(self.device)
+        self._check(self.lib.pitmg_net_set_params(self.h, _ptr(t), 1))
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.P, dtype=np.float32)
+        self._check(self.lib.pitmg_net_get_params(self.h, out.ctypes.data))
+        return out
+
+    def forward(self, x, out=None):
+        b = x.shape[0]
+        y = out if out is not None else self.torch.empty_like(x)
+        self._check(self.lib.pitmg_net_forward(self.h, b, _ptr(x), _ptr(y)))
+        return y
+
+    def backward(self, x, dy, grad=None):
+        g = grad if grad is not None else self.torch.empty(self.P, dtype=self.torch.float32,
+                                                           device=self.device)
+        self._check(self.lib.pitmg_net_backward(self.h, x.shape[0], _ptr(x), _ptr(dy), _ptr(g)))
+        return g
+
+    def adam(self, grad, lr: float):
+        self._check(self.lib.pitmg_net_adam(self.h, _ptr(grad), float(lr)))
+
+    def train_step(self, idx, X, Y, lr: float) -> float:
+        loss = _c_double(0.0)
+        self._check(self.lib.pitmg_net_train_step(self.h, idx.shape[0], _ptr(idx), X.shape[0],
+                                                  _ptr(X), _ptr(Y), float(lr), _byref(loss)))
+        return loss.value
+
+    def make_samples(self, p: int, q: int, r, e):
+        """Normalised node-major samples (X, Y) from type-major pairs r, e."""
+        n = r.shape[0]
+        X = self.torch.empty((n, self.T, self.C), dtype=self.torch.float32, device=self.device)
+        Y = self.torch.empty_like(X)
+        self._check(self.lib.pitmg_net_make_samples(self.h, n, p, q, _ptr(r), _ptr(e), _ptr(X),
+                                                    _ptr(Y)))
+        return X, Y
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.pitmg_net_destroy(self.h)
+            self.h = _c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_c_void_p = C.c_void_p
+_c_double = C.c_double
+_byref = C.byref
