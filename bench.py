@@ -126,6 +126,47 @@ def cpu_baseline(name, iters_full, budget_s=25.0):
                       f"GPU solve took; SciPy/SuperLU single-threaded, numpy BLAS on {cores} threads"}
 
 
+def learned_leg(pm, torch, wl, train_seeds=range(50000, 50008), held_out=(60000, 60001)):
+    """Learned coarse correction on the benchmark workload: record the
+    coarsest-level pairs of plain solves on other linearisation points,
+    train the network, then solve held-out points four ways (plain, network,
+    network under a stall rule, zero correction)."""
+    from paper_2405_04808_amd import coarse_training as ct
+    from workloads import config_problem, coarse_net_params
+
+    def probs(seeds):
+        for sd in seeds:
+            prob, b = config_problem(wl["cfg"], seed=sd)
+            yield prob.levels, b
+
+    opts = pm.default_options(restart=wl["restart"], maxit=wl["maxit"])
+    t0 = time.perf_counter()
+    R, E, info = ct.collect_pairs(probs(train_seeds), opts, max_pairs=8000)
+    t_pairs = time.perf_counter() - t0
+    print(f"# learned: {R.shape[0]} pairs from {len(info)} solves in {t_pairs:.1f} s",
+          file=sys.stderr, flush=True)
+    prob0, _ = config_problem(wl["cfg"])
+    p, q = prob0.p, prob0.q
+    C, T, H = 4 * p + q, prob0.n >> (prob0.n_levels - 1), 64
+    net = pm.Net(C, T, H, max_batch=256)
+    net.set_params(coarse_net_params(C, H, 0).astype("float32"))
+    X, Y = net.make_samples(p, q, R, E)
+    del R, E
+    tr = ct.train(net, X, Y, epochs=30, batch=256, lr=1e-3, seed=1)
+    print(f"# learned: trained in {tr['train_s']:.1f} s, validation error "
+          f"{tr['history'][-1]['val_rel_err']:.3f}", file=sys.stderr, flush=True)
+    abl = ct.ablation(probs(held_out), opts, net, stall_ratio=0.999, time_coarse=True)
+    net.close()
+    return {"network": f"conv1d width 3: {C}->{H}->{H}->{C} channels over {T} coarse steps, "
+                       "tanh, bf16 MFMA products, FP32 accumulation and Adam",
+            "pairs": int(X.shape[0]), "pair_solves": len(info), "pairs_s": round(t_pairs, 1),
+            "train_samples": tr["train"], "val_samples": tr["val"], "epochs": 30,
+            "batch": 256, "lr": 1e-3, "train_s": round(tr["train_s"], 2),
+            "val_rel_err": round(tr["history"][-1]["val_rel_err"], 4),
+            "stall_rule": "ratio 0.999 on 2 consecutive steps",
+            "held_out": {str(sd): row for sd, row in zip(held_out, abl)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,13 +177,15 @@ def main():
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time the sweep launches (value only)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-smoother leg")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-coarse-correction leg (pairs, training, ablation)")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: one solve cut at 40 FGMRES steps (the same "
                          "launches per V-cycle), then a 256 MiB copy kernel for calibration")
     args = ap.parse_args()
     if args.counters:
         args.steps, args.warmup = 1, 0
-        args.no_cpu_baseline = args.no_profile = args.no_fp32 = True
+        args.no_cpu_baseline = args.no_profile = args.no_fp32 = args.no_learned = True
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
               "supported (the time-parallel path shards by time blocks, see the design "
@@ -286,6 +329,10 @@ def main():
                 "rel_diff_vs_fp64_solution": diff}
         s32.close()
 
+    learned = None
+    if not args.no_learned and args.workload == "burgers128":
+        learned = learned_leg(pm, torch, wl)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, int(round(float(np.mean(iters)))))
@@ -312,6 +359,7 @@ def main():
         "cpu_baseline": cpu,
         "vcycle_hbm": vc,
         "fp32_smoother": fp32,
+        "learned_coarse": learned,
         "kernel_ms": kern,
     }
     print(json.dumps(out))

@@ -36,6 +36,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from workloads import coarse_net_params
+
 WIDTH = 3
 
 
@@ -61,13 +63,8 @@ def unpack(theta: np.ndarray, C: int, H: int):
 
 
 def init_params(C: int, H: int, rng: np.random.Generator) -> np.ndarray:
-    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases (FP32 values)."""
-    parts = []
-    for (o, i) in ((H, C), (H, H), (C, H)):
-        a = 1.0 / np.sqrt(i * WIDTH)
-        parts.append(rng.uniform(-a, a, size=o * i * WIDTH))
-        parts.append(rng.uniform(-a, a, size=o))
-    return np.concatenate(parts).astype(np.float32).astype(np.float64)
+    """Seeded initial parameters (drawn by the shared input generators)."""
+    return coarse_net_params(C, H, int(rng.integers(0, 2 ** 31)), WIDTH)
 
 
 # ---------------------------------------------------------------------------

@@ -14,11 +14,14 @@ which cannot be reproduced.  Every level of the hierarchy is rediscretised
 at its own step 2^l * dt, at a linearisation point obtained from the finest
 one by injection (states) and averaging (controls), i.e. by the same
 restriction the multigrid cycle uses (Sec. 5.3.1).
+
+It also draws the seeded initial parameters of the learned coarse
+correction's network (coarse_net_params).
 """
 from .problems import (Problem, Level, vanderpol_jacobians, burgers_jacobians,
                        lifted_blocks, make_problem, make_rhs, config_problem,
-                       CONFIGS)
+                       coarse_net_params, CONFIGS)
 
 __all__ = ["Problem", "Level", "vanderpol_jacobians", "burgers_jacobians",
            "lifted_blocks", "make_problem", "make_rhs", "config_problem",
-           "CONFIGS"]
+           "coarse_net_params", "CONFIGS"]

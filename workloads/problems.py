@@ -273,3 +273,17 @@ def config_problem(name: str, **over):
     prob, rng = make_problem(**cfg)
     b = make_rhs(prob, rng)
     return prob, b
+
+
+def coarse_net_params(C: int, H: int, seed: int, width: int = 3) -> np.ndarray:
+    """Seeded initial parameters of the coarse-correction network: the flat
+    vector [W1 (H,C,width), b1 (H), W2 (H,H,width), b2 (H), W3 (C,H,width),
+    b3 (C)], each entry uniform in +-1/sqrt(fan_in) of its layer, rounded to
+    FP32.  Draw order: W1, b1, W2, b2, W3, b3 from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for (o, i) in ((H, C), (H, H), (C, H)):
+        a = 1.0 / np.sqrt(i * width)
+        parts.append(rng.uniform(-a, a, size=o * i * width))
+        parts.append(rng.uniform(-a, a, size=o))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
