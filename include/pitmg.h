@@ -111,6 +111,13 @@ typedef struct {
   double stall_ratio;          /* stall rule: FGMRES residual-estimate ratio
                                   est_j / est_{j-1} above this ...             */
   int stall_steps;             /* ... on this many consecutive steps           */
+  int vcycle_graph;            /* 1: inside FGMRES and pitmg_vcycle, replay the
+                                  finest-level V-cycle from a captured HIP
+                                  graph (captured on first use, again when the
+                                  coarse solve needs more steps than captured).
+                                  Needs a stream other than the null stream and
+                                  nu_post > 0; not used while profiling,
+                                  recording coarse pairs or with coarse_mode 1 */
 } pitmg_options;
 
 typedef struct {
@@ -128,7 +135,7 @@ typedef struct {
 
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
  * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
- * stall_steps 2. */
+ * stall_steps 2, vcycle_graph 0. */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and
@@ -165,6 +172,28 @@ int pitmg_vcycle(pitmg_handle* h, const double* r, double* e);
  * use_x0 != 0 (else ignored), out = solution.  st may be NULL. */
 int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x,
                        double tol, int use_x0, pitmg_stats* st);
+
+/* Solve count independent systems, one handle each (distinct handles; give
+ * each its own stream at setup for the solves to overlap on the device).
+ * Every solve runs the same FGMRES as pitmg_fgmres_solve, and with the same
+ * handle, options and inputs it produces the same iterates; the host
+ * interleaves their phases, so each solve's kernels are in flight while the
+ * host waits on the others.  rhs[i], x[i]: device vectors of system i (x[i]
+ * as in pitmg_fgmres_solve).  st, status: arrays of count (may be NULL);
+ * status[i] is system i's return code.  Returns the first error code of any
+ * system, else PITMG_NOT_CONVERGED if any did not converge, else PITMG_OK. */
+int pitmg_fgmres_solve_batch(pitmg_handle* const* h, int count, const double* const* rhs,
+                             double* const* x, double tol, int use_x0, pitmg_stats* st,
+                             int* status);
+
+/* Choose, per level above the coarsest, the block Jacobi sweep's launch
+ * shape by timing the candidates on this device: the number of consecutive
+ * time steps one work-group takes (1..4) where V and Z~ are shared by every
+ * step, and the one-step-per-group kernel.  cfg (host, n_levels entries, may
+ * be NULL) receives the choice per level: k >= 1 steps per group, -1 the
+ * one-step kernel, 0 the built-in rule (no candidates).  The results of a
+ * sweep do not depend on the choice beyond rounding.  Synchronises. */
+int pitmg_autotune(pitmg_handle* h, int* cfg);
 
 /* Kernel timing: while enabled, the library brackets every launch with HIP
  * events on its stream and accumulates per-kernel-class time.  Classes:

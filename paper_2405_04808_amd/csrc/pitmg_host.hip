@@ -38,6 +38,7 @@ struct LevelBuf {
   float* V32 = nullptr;
   float* Z32 = nullptr;
   float* Gi32 = nullptr;
+  int sweep_cfg = 0;                 // tuned sweep launch shape (LevelView)
 };
 
 struct ProfRec {
@@ -97,6 +98,15 @@ struct pitmg_handle {
   double* pair_r = nullptr;          // caller-owned pair buffers
   double* pair_e = nullptr;
   int pair_cap = 0, pair_count = 0;
+  int* last_its_slot = nullptr;      // device slot of the last coarse step count
+  // captured V-cycle
+  hipGraph_t g_graph = nullptr;
+  hipGraphExec_t g_exec = nullptr;
+  double* g_in = nullptr;            // fixed input / output of the captured cycle
+  double* g_out = nullptr;
+  int g_K = 0;                       // coarse steps enqueued in the capture
+  int* g_its_slot = nullptr;
+  long long graph_replays = 0;
 };
 
 namespace {
@@ -215,6 +225,7 @@ LevelView view(const pitmg_handle* h, int l) {
     v.Z32 = b.Z32;
     v.Gi32 = b.Gi32;
   }
+  v.sweep_cfg = b.sweep_cfg;
   return v;
 }
 
@@ -232,6 +243,10 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "coarse_mode must be 0 or 1");
   if (!(o.stall_ratio > 0.0) || o.stall_steps < 1)
     return set_err(h, PITMG_ERR_INVALID, "stall_ratio must be > 0 and stall_steps >= 1");
+  if (o.vcycle_graph != 0 && o.vcycle_graph != 1)
+    return set_err(h, PITMG_ERR_INVALID, "vcycle_graph must be 0 or 1");
+  if (o.vcycle_graph && h && h->stream == nullptr)
+    return set_err(h, PITMG_ERR_INVALID, "vcycle_graph needs a stream other than the null stream");
   return PITMG_OK;
 }
 
@@ -339,6 +354,7 @@ int coarse_solve(pitmg_handle* h, const double* b, double* out) {
   if (!h->coarse_fast) K = 0;
   int* its = h->coarse_its + (h->coarse_calls % h->coarse_log_cap);
   h->coarse_calls++;
+  h->last_its_slot = its;
   double* Vb = h->coarse_work;
   double* Zb = Vb + (size_t)(cap + 1) * len;
   double* W = Zb + (size_t)cap * len;
@@ -406,6 +422,62 @@ int coarse_dispatch(pitmg_handle* h, const double* b, double* out) {
                              hipMemcpyDeviceToDevice, h->stream));
     h->pair_count++;
   }
+  return PITMG_OK;
+}
+
+int vcycle_level(pitmg_handle* h, int l, const double* b, double* out);
+
+void drop_graph(pitmg_handle* h) {
+  if (h->g_exec) (void)hipGraphExecDestroy(h->g_exec);
+  if (h->g_graph) (void)hipGraphDestroy(h->g_graph);
+  h->g_exec = nullptr;
+  h->g_graph = nullptr;
+  h->g_K = 0;
+}
+
+// Capture MG_0(g_in) -> g_out on the handle's stream into a HIP graph.
+int capture_vcycle(pitmg_handle* h) {
+  drop_graph(h);
+  HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+  const int K = h->opt.coarse_fixed_its > 0 ? h->opt.coarse_fixed_its : h->coarse_k;
+  const int rc = vcycle_level(h, 0, h->g_in, h->g_out);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess)
+    return set_err(h, PITMG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  h->g_graph = g;
+  HIPCHK(h, hipGraphInstantiate(&h->g_exec, g, nullptr, nullptr, 0));
+  h->g_K = K;
+  h->g_its_slot = h->last_its_slot;
+  return PITMG_OK;
+}
+
+// MG_0(r) -> e, eagerly or by replaying the captured cycle.
+int vcycle_top(pitmg_handle* h, const double* r, double* e) {
+  const pitmg_options& o = h->opt;
+  const bool graph = o.vcycle_graph && h->stream != nullptr && !h->prof && o.nu_post > 0 &&
+                     o.coarse_mode == 0 && h->pair_count >= h->pair_cap;
+  if (!graph) return vcycle_level(h, 0, r, e);
+  const long long len = h->lv[0].len;
+  int rc;
+  if (!h->g_in) {
+    if ((rc = dalloc(h, (void**)&h->g_in, len * 8))) return rc;
+    if ((rc = dalloc(h, (void**)&h->g_out, len * 8))) return rc;
+  }
+  const int need = !h->coarse_fast ? 0
+                   : o.coarse_fixed_its > 0 ? o.coarse_fixed_its : h->coarse_k;
+  if (!h->g_exec || need > h->g_K)
+    if ((rc = capture_vcycle(h))) return rc;
+  HIPCHK(h, hipMemcpyAsync(h->g_in, r, len * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipGraphLaunch(h->g_exec, h->stream));
+  HIPCHK(h, hipMemcpyAsync(e, h->g_out, len * 8, hipMemcpyDeviceToDevice, h->stream));
+  h->last_plain = true;
+  h->last_its_slot = h->g_its_slot;
+  h->graph_replays++;
   return PITMG_OK;
 }
 
@@ -481,22 +553,6 @@ int dots(pitmg_handle* h, const double* basis, int nb, const double* x1, const d
   });
 }
 
-int fetch_coef(pitmg_handle* h, int count) {
-  HIPCHK(h, hipMemcpyAsync(h->hbuf, h->coef, count * sizeof(double), hipMemcpyDeviceToHost,
-                           h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (h->prof) drain(h);
-  return PITMG_OK;
-}
-
-int device_norm(pitmg_handle* h, const double* x, long long len, double* out) {
-  int rc = dots(h, nullptr, 0, x, nullptr, len);
-  if (rc) return rc;
-  if ((rc = fetch_coef(h, 1))) return rc;
-  *out = std::sqrt(h->hbuf[0]);
-  return PITMG_OK;
-}
-
 // Apply the stored rotations 0..j-1 to column j of H (leading dim m), make
 // rotation j and update g.  Returns |g[j+1]|.
 double givens_column(std::vector<double>& H, int m, int j, std::vector<double>& cs,
@@ -517,6 +573,362 @@ double givens_column(std::vector<double>& H, int m, int j, std::vector<double>& 
   return std::fabs(g[j + 1]);
 }
 
+// One FGMRES solve (Saad 1993) as a resumable sequence of phases.  The
+// Arnoldi basis is built by classical Gram-Schmidt with delayed
+// re-orthogonalisation: step j takes the dots of the finished basis
+// q_0..q_{j-1} with both the lagged vector v_j (the preconditioner input)
+// and w = A M(v_j) in one pass, then in one update pass re-orthogonalises
+// v_j into q_j and orthogonalises w against q_0..q_j.  The correction of v_j
+// is folded into Hessenberg column j-1, so A Z = Q H holds with the
+// preconditioned vectors actually used.
+//
+// advance() enqueues device work up to the next point where the host needs
+// device results (a coefficient copy into hbuf) and returns kWait; the
+// caller synchronises the handle's stream and calls advance() again.  A
+// single solve alternates the two; a batch interleaves the phases of many
+// solves, each on its own stream, so their kernels overlap on the device
+// while the host waits once per round for all of them.
+struct FgmresRun {
+  enum Phase { kStart, kAfterBnorm, kCycle, kAfterResid, kStepA, kStepB, kStepC, kStepEnd,
+               kCycleEnd, kFinal, kAfterFinal, kFinish, kDone };
+  static constexpr int kWait = 1;
+  static constexpr int kFinished = 0;
+
+  pitmg_handle* h = nullptr;
+  const double* rhs = nullptr;
+  double* x = nullptr;
+  double tol = 0.0;
+  int use_x0 = 0;
+  Phase ph = kStart;
+  long long len = 0;
+  int m = 0, maxit = 0, net0 = 0, ns = 0;
+  LevelView v0{};
+  std::chrono::steady_clock::time_point t0;
+  std::vector<double> H, cs, sn, g, y, hv, sv;
+  double bnorm = 0.0, beta = 0.0, est = 1.0, est_prev = 1.0, rho_prev = 0.0, rho = 0.0;
+  double ww = 0.0, alpha = 1.0, cq = 0.0, rn = 0.0;
+  bool converged = false, first = true, stop = false, plain = false, zero_rhs = false;
+  int total = 0, j = 0, k = 0, stalled = 0, fallback_at = -1;
+  int coarse_calls = 0;
+  long long coarse_its = 0;
+  int status = PITMG_OK;
+  pitmg_stats S{};
+
+  double* Vp(int i) const { return h->Vk + (size_t)i * len; }
+  double* Zp(int i) const { return h->Zk + (size_t)i * len; }
+
+  int start(pitmg_handle* hh, const double* b, double* xx, double tl, int x0) {
+    h = hh;
+    if (!h || !b || !xx) return PITMG_ERR_INVALID;
+    if (!(tl >= 0.0)) return set_err(h, PITMG_ERR_INVALID, "tol must be >= 0");
+    if (h->opt.coarse_mode == 1 && !h->net)
+      return set_err(h, PITMG_ERR_INVALID, "coarse_mode 1 needs an attached network");
+    rhs = b;
+    x = xx;
+    tol = tl;
+    use_x0 = x0;
+    t0 = std::chrono::steady_clock::now();
+    len = h->lv[0].len;
+    m = h->opt.restart;
+    maxit = h->opt.maxit;
+    net0 = h->net_calls;
+    ns = krylov_slices(len);
+    v0 = view(h, 0);
+    h->fell_back = false;
+    ph = kStart;
+    return PITMG_OK;
+  }
+
+  // enqueue the copy of count coefficients into hbuf, then wait
+  int wait_coef(int count) {
+    HIPCHK(h, hipMemcpyAsync(h->hbuf, h->coef, count * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    return kWait;
+  }
+
+  void begin_cycle() {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    k = 0;
+    j = 0;
+    stop = false;
+    rho_prev = 0.0;
+  }
+
+  int advance() {
+    int rc;
+    for (;;) {
+      switch (ph) {
+        case kStart:
+          if ((rc = dots(h, nullptr, 0, rhs, nullptr, len))) return rc;
+          ph = kAfterBnorm;
+          return wait_coef(1);
+        case kAfterBnorm:
+          bnorm = std::sqrt(h->hbuf[0]);
+          if (!std::isfinite(bnorm))
+            return set_err(h, PITMG_ERR_NONFINITE, "right-hand side not finite");
+          if (bnorm == 0.0) {
+            HIPCHK(h, hipMemsetAsync(x, 0, len * 8, h->stream));
+            zero_rhs = converged = true;
+            ph = kFinish;
+            break;
+          }
+          if (!use_x0) HIPCHK(h, hipMemsetAsync(x, 0, len * 8, h->stream));
+          H.assign((size_t)(m + 1) * m, 0.0);
+          cs.assign(m, 0.0);
+          sn.assign(m, 0.0);
+          g.assign(m + 1, 0.0);
+          y.assign(m, 0.0);
+          hv.assign(m + 1, 0.0);
+          sv.assign(m + 1, 0.0);
+          first = !use_x0;
+          ph = kCycle;
+          break;
+        case kCycle:
+          if (first) {
+            beta = bnorm;
+            if ((rc = timed(h, 5, [&] {
+                   return launch_scale(Vp(0), rhs, 1.0 / beta, len, h->stream);
+                 })))
+              return rc;
+            first = false;
+            begin_cycle();
+            ph = kStepA;
+            break;
+          }
+          if ((rc = timed(h, 2, [&] {
+                 return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream);
+               })))
+            return rc;
+          if ((rc = dots(h, nullptr, 0, h->r, nullptr, len))) return rc;
+          ph = kAfterResid;
+          return wait_coef(1);
+        case kAfterResid:
+          beta = std::sqrt(h->hbuf[0]);
+          if (!std::isfinite(beta)) return set_err(h, PITMG_ERR_NONFINITE, "residual not finite");
+          est = beta / bnorm;
+          if (beta <= tol * bnorm) {
+            converged = true;
+            ph = kFinal;
+            break;
+          }
+          if (total >= maxit) {
+            ph = kFinal;
+            break;
+          }
+          if ((rc = timed(h, 5, [&] {
+                 return launch_scale(Vp(0), h->r, 1.0 / beta, len, h->stream);
+               })))
+            return rc;
+          begin_cycle();
+          ph = kStepA;
+          break;
+        case kStepA:
+          if ((rc = vcycle_top(h, Vp(j), Zp(j)))) return rc;
+          if ((rc = timed(h, 2, [&] {
+                 return launch_apply(v0, Zp(j), nullptr, 1.0, 0.0, h->w, h->stream);
+               })))
+            return rc;
+          plain = h->last_plain;
+          if (plain)
+            HIPCHK(h, hipMemcpyAsync(h->its_pinned, h->last_its_slot, sizeof(int),
+                                     hipMemcpyDeviceToHost, h->stream));
+          // one pass: s = Q^T v_j, hh = Q^T w, v_j.v_j, v_j.w, w.w
+          if ((rc = dots(h, h->Vk, j, Vp(j), h->w, len))) return rc;
+          ph = kStepB;
+          return wait_coef(2 * j + 3);
+        case kStepB: {
+          if (plain) {
+            h->coarse_k = std::max(1, h->its_pinned[0]);   // coarse steps next time
+            coarse_calls += 1;
+            coarse_its += h->its_pinned[0];
+          }
+          const double* cb = h->hbuf;
+          const double vv = cb[2 * j], vw = cb[2 * j + 1];
+          ww = cb[2 * j + 2];
+          double ss = 0.0, sh = 0.0;
+          alpha = 1.0;
+          for (int i = 0; i < j; ++i) {
+            sv[i] = cb[i];
+            hv[i] = cb[j + i];
+            ss += sv[i] * sv[i];
+            sh += sv[i] * hv[i];
+          }
+          if (j > 0) {
+            const double a2 = vv - ss;
+            if (!(a2 > 0.0) || !std::isfinite(a2))
+              return set_err(h, PITMG_ERR_NONFINITE, "lost orthogonality in the Arnoldi basis");
+            alpha = std::sqrt(a2);
+          }
+          cq = (vw - sh) / alpha;
+          // one pass: q_j = (v_j - Q s)/alpha, w -= Q hh + cq q_j, |w|^2
+          if ((rc = timed(h, 5, [&] {
+                 return launch_update(h->Vk, j, Vp(j), h->w, h->coef, h->coef + j, alpha, cq,
+                                      j > 0 ? 1 : 0, len, h->partial, h->stream);
+               })))
+            return rc;
+          if ((rc = timed(h, 5, [&] {
+                 return launch_reduce_partials(h->partial, ns, 1, h->coef, h->stream);
+               })))
+            return rc;
+          ph = kStepC;
+          return wait_coef(1);
+        }
+        case kStepC: {
+          rho = std::sqrt(h->hbuf[0]);
+          if (!std::isfinite(rho) || !std::isfinite(ww))
+            return set_err(h, PITMG_ERR_NONFINITE, "Krylov vector not finite");
+          // finish column j-1: v_j = Q s + alpha q_j, scaled by rho_{j-1}
+          if (j > 0) {
+            for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += rho_prev * sv[i];
+            H[(size_t)j * m + (j - 1)] = rho_prev * alpha;
+            est = givens_column(H, m, j - 1, cs, sn, g) / bnorm;
+            // stall rule of the learned coarse correction
+            if (h->opt.coarse_mode == 1 && !h->fell_back) {
+              stalled = est > h->opt.stall_ratio * est_prev ? stalled + 1 : 0;
+              if (stalled >= h->opt.stall_steps) {
+                h->fell_back = true;
+                fallback_at = total + 1;      // first step to use GMRES + SGS
+              }
+            }
+            est_prev = est;
+          }
+          // column j as far as known: w = Q hh + cq q_j + rho v_{j+1}
+          for (int i = 0; i < j; ++i) H[(size_t)i * m + j] = hv[i];
+          H[(size_t)j * m + j] = cq;
+          H[(size_t)(j + 1) * m + j] = rho;
+          total++;
+          k = j + 1;
+          // estimate with the column as it stands (v_{j+1} not yet re-orthogonalised)
+          double prov;
+          {
+            std::vector<double> col(j + 2);
+            for (int i = 0; i <= j; ++i) col[i] = H[(size_t)i * m + j];
+            for (int i = 0; i < j; ++i) {
+              const double c0 = col[i], c1 = col[i + 1];
+              col[i] = cs[i] * c0 + sn[i] * c1;
+              col[i + 1] = -sn[i] * c0 + cs[i] * c1;
+            }
+            const double a0 = col[j], a1 = rho;
+            const double rr = std::hypot(a0, a1);
+            prov = rr > 0.0 ? std::fabs(a1 / rr * g[j]) : 0.0;
+          }
+          const bool breakdown = rho <= 1e-14 * std::sqrt(ww);
+          const bool end = prov <= tol * bnorm || breakdown || total >= maxit || j == m - 1;
+          if (!breakdown) {
+            if ((rc = timed(h, 5, [&] {
+                   return launch_scale(Vp(j + 1), h->w, 1.0 / rho, len, h->stream);
+                 })))
+              return rc;
+          }
+          if (end) {
+            if (!breakdown) {
+              // finish column j: re-orthogonalisation coefficients of v_{j+1}
+              if ((rc = dots(h, h->Vk, j + 1, Vp(j + 1), nullptr, len))) return rc;
+              ph = kStepEnd;
+              return wait_coef(j + 2);
+            }
+            est = givens_column(H, m, j, cs, sn, g) / bnorm;
+            if (total >= maxit) stop = true;
+            ph = kCycleEnd;
+            break;
+          }
+          rho_prev = rho;
+          ++j;
+          ph = kStepA;
+          break;
+        }
+        case kStepEnd: {
+          double s2 = 0.0;
+          for (int i = 0; i <= j; ++i) {
+            H[(size_t)i * m + j] += rho * h->hbuf[i];
+            s2 += h->hbuf[i] * h->hbuf[i];
+          }
+          const double a2 = h->hbuf[j + 1] - s2;
+          H[(size_t)(j + 1) * m + j] = rho * std::sqrt(a2 > 0.0 ? a2 : 0.0);
+          est = givens_column(H, m, j, cs, sn, g) / bnorm;
+          if (total >= maxit) stop = true;
+          ph = kCycleEnd;
+          break;
+        }
+        case kCycleEnd:
+          // y = H^{-1} g, x += Z y
+          for (int i = k - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int c = i + 1; c < k; ++c) acc -= H[(size_t)i * m + c] * y[c];
+            y[i] = acc / H[(size_t)i * m + i];
+          }
+          for (int i = 0; i < k; ++i) h->hbuf[i] = y[i];
+          HIPCHK(h, hipMemcpyAsync(h->coef, h->hbuf, k * sizeof(double), hipMemcpyHostToDevice,
+                                   h->stream));
+          if ((rc = timed(h, 5, [&] {
+                 return launch_multi_axpy(x, h->Zk, k, h->coef, 1.0, len, nullptr, h->stream);
+               })))
+            return rc;
+          ph = stop ? kFinal : kCycle;
+          break;
+        case kFinal:
+          // true residual (already known when the loop ended on it)
+          rn = est * bnorm;
+          if (converged) {
+            ph = kFinish;
+            break;
+          }
+          if ((rc = timed(h, 2, [&] {
+                 return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream);
+               })))
+            return rc;
+          if ((rc = dots(h, nullptr, 0, h->r, nullptr, len))) return rc;
+          ph = kAfterFinal;
+          return wait_coef(1);
+        case kAfterFinal:
+          rn = std::sqrt(h->hbuf[0]);
+          ph = kFinish;
+          break;
+        case kFinish: {
+          if (h->prof) drain(h);
+          S = pitmg_stats{};
+          S.fallback_at = -1;
+          if (zero_rhs) {
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            S.converged = 1;
+            status = PITMG_OK;
+            ph = kDone;
+            return kFinished;
+          }
+          S.iters = total;
+          S.converged = converged ? 1 : 0;
+          S.relres_est = est;
+          S.relres_true = rn / bnorm;
+          S.coarse_calls = coarse_calls;
+          S.coarse_its_total = (int)coarse_its;
+          S.ms_solve = std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t0).count();
+          S.net_calls = h->net_calls - net0;
+          S.fallback_at = fallback_at;
+          status = converged ? PITMG_OK : PITMG_NOT_CONVERGED;
+          ph = kDone;
+          return kFinished;
+        }
+        case kDone:
+          return kFinished;
+      }
+    }
+  }
+};
+
+// Run one solve to its end on the calling thread.
+int run_to_end(FgmresRun& run) {
+  for (;;) {
+    const int rc = run.advance();
+    if (rc < 0) return rc;
+    if (rc == FgmresRun::kFinished) return run.status;
+    HIPCHK(run.h, hipStreamSynchronize(run.h->stream));
+    if (run.h->prof) drain(run.h);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -535,6 +947,55 @@ void pitmg_default_options(pitmg_options* o) {
   o->coarse_mode = 0;
   o->stall_ratio = 0.9;
   o->stall_steps = 2;
+}
+
+int pitmg_autotune(pitmg_handle* h, int* cfg) {
+  if (!h) return PITMG_ERR_INVALID;
+  if (h->prof) return set_err(h, PITMG_ERR_INVALID, "turn profiling off before tuning");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  int rc = PITMG_OK;
+  constexpr int kReps = 10;
+  for (int l = 0; l < h->L; ++l) {
+    LevelBuf& B = h->lv[l];
+    if (cfg) cfg[l] = 0;
+    if (l == h->L - 1 || !B.y0 || !B.y1) continue;
+    B.sweep_cfg = 0;
+    LevelView v = view(h, l);
+    std::vector<int> cands;
+    if (jacobi_shared_supported(v))
+      cands = {1, 2, 3, 4};
+    if (jacobi_tiled_supported(h->p, h->q)) cands.push_back(-1);
+    if (cands.size() < 2) continue;
+    HIPCHK(h, hipMemsetAsync(B.y0, 0, B.len * 8, h->stream));
+    HIPCHK(h, hipMemsetAsync(B.y1, 0, B.len * 8, h->stream));
+    float best = 1e30f;
+    int pick = 0;
+    for (int c : cands) {
+      B.sweep_cfg = c;
+      v = view(h, l);
+      for (int r = 0; r < kReps + 2; ++r) {
+        if (r == 2) HIPCHK(h, hipEventRecord(e0, h->stream));
+        HIPCHK(h, launch_jacobi(v, B.y1, B.y1, nullptr, h->opt.transfer_variant, B.y0,
+                                h->stream));
+      }
+      HIPCHK(h, hipEventRecord(e1, h->stream));
+      HIPCHK(h, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        pick = c;
+      }
+    }
+    B.sweep_cfg = pick;
+    if (cfg) cfg[l] = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  drop_graph(h);
+  return rc;
 }
 
 int pitmg_coarse_net_attach(pitmg_handle* h, pitmg_net* net) {
@@ -564,6 +1025,7 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   if (!hp) return PITMG_ERR_INVALID;
   *hp = nullptr;
   pitmg_handle* h = new pitmg_handle();
+  h->stream = (hipStream_t)stream;
   int rc = check_problem(h, pb);
   pitmg_options o;
   pitmg_default_options(&o);
@@ -684,6 +1146,7 @@ int pitmg_refactor(pitmg_handle* h, const pitmg_problem* pb) {
   if (!h->blocks_on_device && (pb->N_stride != h->lv[0].sN || pb->V_stride != h->lv[0].sV ||
                                pb->Z_stride != h->lv[0].sZ))
     return set_err(h, PITMG_ERR_INVALID, "refactor of host blocks needs the strides of setup");
+  drop_graph(h);            // borrowed block pointers may have changed
   return load_and_factor(h, pb);
 }
 
@@ -697,6 +1160,7 @@ int pitmg_set_options(pitmg_handle* h, const pitmg_options* opt) {
   if (opt->smoother_fp32 != h->opt.smoother_fp32)
     return set_err(h, PITMG_ERR_INVALID, "smoother_fp32 is fixed at setup");
   h->opt = *opt;
+  drop_graph(h);            // the captured cycle depends on the options
   return PITMG_OK;
 }
 
@@ -734,225 +1198,73 @@ int pitmg_vcycle(pitmg_handle* h, const double* r, double* e) {
   if (!h || !r || !e) return PITMG_ERR_INVALID;
   if (r == e) return set_err(h, PITMG_ERR_INVALID, "r and e must differ");
   h->fell_back = false;
-  return vcycle_level(h, 0, r, e);
+  return vcycle_top(h, r, e);
 }
 
 int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol, int use_x0,
                        pitmg_stats* st) {
-  // Flexible GMRES (Saad 1993).  The Arnoldi basis is built by classical
-  // Gram-Schmidt with delayed re-orthogonalisation: step j takes the dots of
-  // the finished basis q_0..q_{j-1} with both the lagged vector v_j (used as
-  // the preconditioner input) and w = A M(v_j) in one pass, then in one
-  // update pass re-orthogonalises v_j into q_j and orthogonalises w against
-  // q_0..q_j.  The correction of v_j is folded into Hessenberg column j-1,
-  // so A Z = Q H holds with the preconditioned vectors actually used.
-  if (!h || !rhs || !x) return PITMG_ERR_INVALID;
-  if (!(tol >= 0.0)) return set_err(h, PITMG_ERR_INVALID, "tol must be >= 0");
-  const auto t0 = std::chrono::steady_clock::now();
-  const long long len = h->lv[0].len;
-  const int m = h->opt.restart, maxit = h->opt.maxit;
-  const int calls0 = h->coarse_calls;
-  const int net0 = h->net_calls;
-  const int ns = krylov_slices(len);
-  if (h->opt.coarse_mode == 1 && !h->net)
-    return set_err(h, PITMG_ERR_INVALID, "coarse_mode 1 needs an attached network");
-  h->fell_back = false;
-  int fallback_at = -1, stalled = 0;
-  double est_prev = 1.0;
-  LevelView v0 = view(h, 0);
-  int rc;
-  double bnorm = 0.0;
-  if ((rc = device_norm(h, rhs, len, &bnorm))) return rc;
-  if (!std::isfinite(bnorm)) return set_err(h, PITMG_ERR_NONFINITE, "right-hand side not finite");
-  pitmg_stats S{};
-  if (bnorm == 0.0) {
-    HIPCHK(h, hipMemsetAsync(x, 0, len * 8, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    S.converged = 1;
-    if (st) *st = S;
-    return PITMG_OK;
+  FgmresRun run;
+  int rc = run.start(h, rhs, x, tol, use_x0);
+  if (rc) return rc;
+  rc = run_to_end(run);
+  if (rc >= 0 && st) *st = run.S;
+  return rc;
+}
+
+int pitmg_fgmres_solve_batch(pitmg_handle* const* hs, int count, const double* const* rhs,
+                             double* const* x, double tol, int use_x0, pitmg_stats* st,
+                             int* status) {
+  if (!hs || !rhs || !x || count < 1) return PITMG_ERR_INVALID;
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i]) return PITMG_ERR_INVALID;
+    for (int k = 0; k < i; ++k)
+      if (hs[k] == hs[i]) return set_err(hs[i], PITMG_ERR_INVALID, "a handle appears twice");
   }
-  if (!use_x0) HIPCHK(h, hipMemsetAsync(x, 0, len * 8, h->stream));
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hv(m + 1),
-      sv(m + 1);
-  int total = 0;
-  bool converged = false, first = !use_x0;
-  double est = 1.0;
-  auto Vp = [&](int i) { return h->Vk + (size_t)i * len; };
-  auto Zp = [&](int i) { return h->Zk + (size_t)i * len; };
-  for (;;) {
-    double beta;
-    if (first) {
-      beta = bnorm;
-      if ((rc = timed(h, 5, [&] { return launch_scale(Vp(0), rhs, 1.0 / beta, len, h->stream); })))
-        return rc;
-    } else {
-      if ((rc = timed(h, 2, [&] { return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream); })))
-        return rc;
-      if ((rc = device_norm(h, h->r, len, &beta))) return rc;
-      if (!std::isfinite(beta)) return set_err(h, PITMG_ERR_NONFINITE, "residual not finite");
-      est = beta / bnorm;
-      if (beta <= tol * bnorm) {
-        converged = true;
-        break;
+  std::vector<FgmresRun> runs(count);
+  std::vector<int> rcs(count, PITMG_OK), live(count, 1);
+  int active = 0;
+  for (int i = 0; i < count; ++i) {
+    rcs[i] = runs[i].start(hs[i], rhs[i], x[i], tol, use_x0);
+    if (rcs[i] < 0)
+      live[i] = 0;
+    else
+      ++active;
+  }
+  std::vector<int> waiting(count, 0);
+  while (active > 0) {
+    // enqueue every live solve up to its next host wait ...
+    for (int i = 0; i < count; ++i) {
+      if (!live[i]) continue;
+      const int rc = runs[i].advance();
+      waiting[i] = rc == FgmresRun::kWait;
+      if (rc != FgmresRun::kWait) {
+        rcs[i] = rc < 0 ? rc : runs[i].status;
+        live[i] = 0;
+        --active;
       }
-      if (total >= maxit) break;
-      if ((rc = timed(h, 5, [&] { return launch_scale(Vp(0), h->r, 1.0 / beta, len, h->stream); })))
-        return rc;
     }
-    first = false;
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    bool stop = false;
-    double rho_prev = 0.0;
-    for (int j = 0; j < m; ++j) {
-      if ((rc = vcycle_level(h, 0, Vp(j), Zp(j)))) return rc;
-      if ((rc = timed(h, 2, [&] { return launch_apply(v0, Zp(j), nullptr, 1.0, 0.0, h->w, h->stream); })))
-        return rc;
-      const bool plain = h->last_plain;
-      if (plain)
-        HIPCHK(h, hipMemcpyAsync(h->its_pinned,
-                                 h->coarse_its + ((h->coarse_calls - 1) % h->coarse_log_cap),
-                                 sizeof(int), hipMemcpyDeviceToHost, h->stream));
-      // one pass: s = Q^T v_j, hh = Q^T w, v_j.v_j, v_j.w, w.w
-      if ((rc = dots(h, h->Vk, j, Vp(j), h->w, len))) return rc;
-      if ((rc = fetch_coef(h, 2 * j + 3))) return rc;
-      if (plain) h->coarse_k = std::max(1, h->its_pinned[0]);   // coarse steps to enqueue next time
-      const double* cb = h->hbuf;
-      const double vv = cb[2 * j], vw = cb[2 * j + 1], ww = cb[2 * j + 2];
-      double alpha = 1.0, ss = 0.0, sh = 0.0;
-      for (int i = 0; i < j; ++i) {
-        sv[i] = cb[i];
-        hv[i] = cb[j + i];
-        ss += sv[i] * sv[i];
-        sh += sv[i] * hv[i];
+    // ... then wait for each, while the others' work is in flight
+    for (int i = 0; i < count; ++i) {
+      if (!live[i] || !waiting[i]) continue;
+      const hipError_t e = hipStreamSynchronize(hs[i]->stream);
+      if (e != hipSuccess) {
+        rcs[i] = set_err(hs[i], PITMG_ERR_HIP, std::string("hipStreamSynchronize: ") +
+                                                   hipGetErrorString(e));
+        live[i] = 0;
+        --active;
+        continue;
       }
-      if (j > 0) {
-        const double a2 = vv - ss;
-        if (!(a2 > 0.0) || !std::isfinite(a2))
-          return set_err(h, PITMG_ERR_NONFINITE, "lost orthogonality in the Arnoldi basis");
-        alpha = std::sqrt(a2);
-      }
-      const double cq = (vw - sh) / alpha;
-      // one pass: q_j = (v_j - Q s)/alpha, w -= Q hh + cq q_j, |w|^2
-      if ((rc = timed(h, 5, [&] {
-             return launch_update(h->Vk, j, Vp(j), h->w, h->coef, h->coef + j, alpha, cq,
-                                  j > 0 ? 1 : 0, len, h->partial, h->stream);
-           })))
-        return rc;
-      if ((rc = timed(h, 5, [&] {
-             return launch_reduce_partials(h->partial, ns, 1, h->coef, h->stream);
-           })))
-        return rc;
-      if ((rc = fetch_coef(h, 1))) return rc;
-      const double rho = std::sqrt(h->hbuf[0]);
-      if (!std::isfinite(rho) || !std::isfinite(ww))
-        return set_err(h, PITMG_ERR_NONFINITE, "Krylov vector not finite");
-      // finish column j-1: v_j = Q s + alpha q_j, scaled by rho_{j-1}
-      if (j > 0) {
-        for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += rho_prev * sv[i];
-        H[(size_t)j * m + (j - 1)] = rho_prev * alpha;
-        est = givens_column(H, m, j - 1, cs, sn, g) / bnorm;
-        // stall rule of the learned coarse correction
-        if (h->opt.coarse_mode == 1 && !h->fell_back) {
-          stalled = est > h->opt.stall_ratio * est_prev ? stalled + 1 : 0;
-          if (stalled >= h->opt.stall_steps) {
-            h->fell_back = true;
-            fallback_at = total + 1;      // first step to use GMRES + SGS
-          }
-        }
-        est_prev = est;
-      }
-      // column j as far as known: w = Q hh + cq q_j + rho v_{j+1}
-      for (int i = 0; i < j; ++i) H[(size_t)i * m + j] = hv[i];
-      H[(size_t)j * m + j] = cq;
-      H[(size_t)(j + 1) * m + j] = rho;
-      total++;
-      k = j + 1;
-      // estimate with the column as it stands (v_{j+1} not yet re-orthogonalised)
-      double prov;
-      {
-        double a0 = H[(size_t)j * m + j], a1 = rho;
-        std::vector<double> col(j + 2);
-        for (int i = 0; i <= j; ++i) col[i] = H[(size_t)i * m + j];
-        for (int i = 0; i < j; ++i) {
-          const double c0 = col[i], c1 = col[i + 1];
-          col[i] = cs[i] * c0 + sn[i] * c1;
-          col[i + 1] = -sn[i] * c0 + cs[i] * c1;
-        }
-        a0 = col[j];
-        const double rr = std::hypot(a0, a1);
-        prov = rr > 0.0 ? std::fabs(a1 / rr * g[j]) : 0.0;
-      }
-      const bool breakdown = rho <= 1e-14 * std::sqrt(ww);
-      const bool end = prov <= tol * bnorm || breakdown || total >= maxit || j == m - 1;
-      if (!breakdown) {
-        if ((rc = timed(h, 5, [&] { return launch_scale(Vp(j + 1), h->w, 1.0 / rho, len, h->stream); })))
-          return rc;
-      }
-      if (end) {
-        // finish column j: re-orthogonalisation coefficients of v_{j+1}
-        if (!breakdown) {
-          if ((rc = dots(h, h->Vk, j + 1, Vp(j + 1), nullptr, len))) return rc;
-          if ((rc = fetch_coef(h, j + 2))) return rc;
-          double s2 = 0.0;
-          for (int i = 0; i <= j; ++i) {
-            H[(size_t)i * m + j] += rho * h->hbuf[i];
-            s2 += h->hbuf[i] * h->hbuf[i];
-          }
-          const double a2 = h->hbuf[j + 1] - s2;
-          H[(size_t)(j + 1) * m + j] = rho * std::sqrt(a2 > 0.0 ? a2 : 0.0);
-        }
-        est = givens_column(H, m, j, cs, sn, g) / bnorm;
-        if (total >= maxit) stop = true;
-        break;
-      }
-      rho_prev = rho;
+      if (hs[i]->prof) drain(hs[i]);
     }
-    // y = H^{-1} g, x += Z y
-    for (int i = k - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int c = i + 1; c < k; ++c) acc -= H[(size_t)i * m + c] * y[c];
-      y[i] = acc / H[(size_t)i * m + i];
-    }
-    for (int i = 0; i < k; ++i) h->hbuf[i] = y[i];
-    HIPCHK(h, hipMemcpyAsync(h->coef, h->hbuf, k * sizeof(double), hipMemcpyHostToDevice,
-                             h->stream));
-    if ((rc = timed(h, 5, [&] {
-           return launch_multi_axpy(x, h->Zk, k, h->coef, 1.0, len, nullptr, h->stream);
-         })))
-      return rc;
-    if (stop) break;
   }
-  // true residual (already known when the loop ended on it)
-  double rn = est * bnorm;
-  if (!converged) {
-    if ((rc = timed(h, 2, [&] { return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream); })))
-      return rc;
-    if ((rc = device_norm(h, h->r, len, &rn))) return rc;
+  int worst = PITMG_OK;
+  for (int i = 0; i < count; ++i) {
+    if (status) status[i] = rcs[i];
+    if (st) st[i] = rcs[i] >= 0 ? runs[i].S : pitmg_stats{};
+    if (rcs[i] < 0 && worst >= 0) worst = rcs[i];
+    if (rcs[i] == PITMG_NOT_CONVERGED && worst == PITMG_OK) worst = PITMG_NOT_CONVERGED;
   }
-  if (h->prof) drain(h);
-  const int ncalls = h->coarse_calls - calls0;
-  long long cits = 0;
-  if (ncalls > 0) {
-    std::vector<int> log(h->coarse_log_cap);
-    HIPCHK(h, hipMemcpy(log.data(), h->coarse_its, h->coarse_log_cap * sizeof(int),
-                        hipMemcpyDeviceToHost));
-    for (int c = calls0; c < h->coarse_calls; ++c) cits += log[c % h->coarse_log_cap];
-  }
-  S.iters = total;
-  S.converged = converged ? 1 : 0;
-  S.relres_est = est;
-  S.relres_true = rn / bnorm;
-  S.coarse_calls = ncalls;
-  S.coarse_its_total = (int)cits;
-  S.ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  S.net_calls = h->net_calls - net0;
-  S.fallback_at = fallback_at;
-  if (st) *st = S;
-  return converged ? PITMG_OK : PITMG_NOT_CONVERGED;
+  return worst;
 }
 
 int pitmg_profile_enable(pitmg_handle* h, int on) {
@@ -1016,6 +1328,9 @@ void pitmg_destroy(pitmg_handle* h) {
   if (h->stream) hipStreamSynchronize(h->stream);
   else hipDeviceSynchronize();
   drain(h);
+  drop_graph(h);
+  hipFree(h->g_in);
+  hipFree(h->g_out);
   for (auto e : h->pool) hipEventDestroy(e);
   for (auto& b : h->lv) {
     hipFree(b.N_own);

@@ -25,6 +25,9 @@ struct LevelView {
   const float* Z32 = nullptr;
   const float* Gi32 = nullptr;
   int fp32 = 0;
+  // sweep launch shape: 0 built-in rule, k >= 1 steps per work-group of the
+  // shared-block kernel, -1 the one-step kernel
+  int sweep_cfg = 0;
 };
 
 // Block pointers of a level in the arithmetic of the smoother.

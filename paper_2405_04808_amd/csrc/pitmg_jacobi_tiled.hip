@@ -342,8 +342,9 @@ static hipError_t launch_shared_t(const LevelView& L, const double* b, const dou
 hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* ynew,
                                 hipStream_t s) {
-  // steps per work-group: enough to keep the grid near one work-group per CU
-  int per = (L.n + 255) / 256;
+  // steps per work-group: the tuned choice, else enough to keep the grid
+  // near one work-group per CU
+  int per = L.sweep_cfg > 0 ? L.sweep_cfg : (L.n + 255) / 256;
   if (per > kMaxSteps) per = kMaxSteps;
   if (per < 1) per = 1;
   return L.fp32 ? launch_shared_t<float>(L, b, yold, ecoarse, variant, ynew, per, s)

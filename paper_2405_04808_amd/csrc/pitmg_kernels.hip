@@ -254,7 +254,7 @@ hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold
   const bool al = L.fp32 ? aligned16(L.N32) && aligned16(L.V32) && aligned16(L.Z32) &&
                                aligned16(L.Gi32)
                          : aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi);
-  if (al && jacobi_shared_supported(L))
+  if (al && jacobi_shared_supported(L) && L.sweep_cfg >= 0)
     return launch_jacobi_shared(L, b, yold, ecoarse, variant, ynew, s);
   if (al && jacobi_tiled_supported(L.p, L.q))
     return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, s);

@@ -42,7 +42,7 @@ class pitmg_options(C.Structure):
                 ("coarse_maxit", C.c_int), ("coarse_fixed_its", C.c_int),
                 ("restart", C.c_int), ("maxit", C.c_int), ("transfer_variant", C.c_int),
                 ("smoother_fp32", C.c_int), ("coarse_mode", C.c_int), ("stall_ratio", C.c_double),
-                ("stall_steps", C.c_int)]
+                ("stall_steps", C.c_int), ("vcycle_graph", C.c_int)]
 
 
 class pitmg_stats(C.Structure):
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
         "pitmg_coarse_solve": (i, [vp, vp, vp, C.POINTER(i)]),
         "pitmg_vcycle": (i, [vp, vp, vp]),
         "pitmg_fgmres_solve": (i, [vp, vp, vp, d, i, C.POINTER(pitmg_stats)]),
+        "pitmg_fgmres_solve_batch": (i, [C.POINTER(vp), i, C.POINTER(vp), C.POINTER(vp), d, i,
+                                         C.POINTER(pitmg_stats), C.POINTER(i)]),
         "pitmg_profile_enable": (i, [vp, i]),
         "pitmg_profile_read": (i, [vp, i, C.POINTER(i), C.POINTER(d), C.POINTER(d)]),
         "pitmg_profile_reset": (i, [vp]),
@@ -103,6 +105,7 @@ def load_library(path: str = LIB_PATH):
         "pitmg_coarse_net_attach": (i, [vp, vp]),
         "pitmg_coarse_pairs_arm": (i, [vp, vp, vp, i]),
         "pitmg_coarse_pairs_count": (i, [vp]),
+        "pitmg_autotune": (i, [vp, C.POINTER(i)]),
         "pitmg_status_string": (C.c_char_p, [i]),
         "pitmg_last_error": (C.c_char_p, [vp]),
         "pitmg_destroy": (None, [vp]),
@@ -156,6 +159,9 @@ class Solver:
         self.options = options if options is not None else default_options()
         self.h = C.c_void_p()
         self._upload(levels)
+        # the library works on self.stream: the uploads (on the current
+        # stream) must be complete before setup reads the blocks
+        self._order()
         pb = self._problem()
         with torch.cuda.device(self.device):
             rc = self.lib.pitmg_setup(C.byref(self.h), C.byref(pb), C.byref(self.options),
@@ -211,6 +217,13 @@ class Solver:
         self._check(self.lib.pitmg_refactor(self.h, C.byref(self._problem())))
 
     # -- calls ------------------------------------------------------------------
+    def _order(self):
+        """Make the solver's stream wait for work queued on the current stream
+        (inputs written there); a no-op when they are the same stream."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
     def _check(self, rc):
         if rc < 0:
             raise PitmgError(rc, self.last_error())
@@ -233,22 +246,26 @@ class Solver:
 
     def apply(self, x, level: int = 0, out=None):
         out = self.empty(level) if out is None else out
+        self._order()
         self._check(self.lib.pitmg_apply(self.h, level, _ptr(x), _ptr(out)))
         return out
 
     def jacobi_sweep(self, b, y_in=None, level: int = 0, out=None):
         out = self.empty(level) if out is None else out
+        self._order()
         self._check(self.lib.pitmg_jacobi_sweep(self.h, level, _ptr(b), _ptr(y_in), _ptr(out)))
         return out
 
     def coarse_solve(self, b, out=None):
         out = self.empty(self.n_levels - 1) if out is None else out
         its = C.c_int(0)
+        self._order()
         self._check(self.lib.pitmg_coarse_solve(self.h, _ptr(b), _ptr(out), C.byref(its)))
         return out, its.value
 
     def vcycle(self, r, out=None):
         out = self.empty(0) if out is None else out
+        self._order()
         self._check(self.lib.pitmg_vcycle(self.h, _ptr(r), _ptr(out)))
         return out
 
@@ -260,6 +277,7 @@ class Solver:
             x.copy_(x0)
             use_x0 = 1
         st = pitmg_stats()
+        self._order()
         rc = self._check(self.lib.pitmg_fgmres_solve(self.h, _ptr(b), _ptr(x), float(tol),
                                                      use_x0, C.byref(st)))
         return x, st.as_dict(), rc
@@ -289,6 +307,12 @@ class Solver:
     def device_bytes(self) -> int:
         return self.lib.pitmg_device_bytes(self.h)
 
+    def autotune(self):
+        """Pick each level's sweep launch shape by timing; returns the choices."""
+        cfg = (C.c_int * self.n_levels)()
+        self._check(self.lib.pitmg_autotune(self.h, cfg))
+        return list(cfg)
+
     # -- learned coarse correction ------------------------------------------------
     def attach_net(self, net: Optional["Net"]):
         """Use net for the coarse solve when coarse_mode = 1 (None detaches)."""
@@ -314,6 +338,27 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch(solvers: Sequence["Solver"], bs, tol: float = 1e-10, outs=None):
+    """pitmg_fgmres_solve_batch over distinct solvers: returns (xs, stats
+    dicts, status codes, overall code).  bs: device FP64 right-hand sides."""
+    lib = load_library()
+    n = len(solvers)
+    xs = list(outs) if outs is not None else [s.empty(0) for s in solvers]
+    H = (C.c_void_p * n)(*[s.h.value for s in solvers])
+    R = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    X = (C.c_void_p * n)(*[x_.data_ptr() for x_ in xs])
+    st = (pitmg_stats * n)()
+    status = (C.c_int * n)()
+    for s_ in solvers:
+        s_._order()
+    rc = lib.pitmg_fgmres_solve_batch(H, n, R, X, float(tol), 0, st, status)
+    if rc < 0:
+        bad = [i for i in range(n) if status[i] < 0]
+        msg = solvers[bad[0]].last_error() if bad else ""
+        raise PitmgError(rc, f"system {bad[0] if bad else '?'}: {msg}")
+    return xs, [st[i].as_dict() for i in range(n)], [status[i] for i in range(n)], rc
 
 
 class Net:

@@ -1,0 +1,174 @@
+"""GPU checks of batched solves, the captured V-cycle and the sweep autotuner.
+
+A batch interleaves the phases of independent FGMRES solves, each on its own
+stream; every kernel is deterministic, so each system's iterates must be
+bitwise those of its own solve on an identical handle.  Each batch member
+is also checked against the oracle's operator (true relative residual at
+most 1e-10).  The captured V-cycle is replayed several times with eager work
+and synchronisations between the replays, and every replay is compared with
+the eager cycle; with a fixed number of coarse steps the captured and eager
+cycles run the same kernels on the same data, so they agree bitwise.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from workloads import make_problem, make_rhs
+from oracle import OracleLevel
+import paper_2405_04808_amd as pm
+
+pytestmark = pytest.mark.gpu
+
+MIX = [
+    dict(kind="vanderpol", n=64, n_levels=4, seed=31),
+    dict(kind="vanderpol", n=128, n_levels=5, seed=32),
+    dict(kind="burgers", nx=12, nu=0.01, n=32, n_levels=3, seed=33),
+    dict(kind="burgers", nx=64, nu=0.01, n=32, n_levels=3, seed=34),
+    dict(kind="burgers", nx=128, nu=0.01, n=64, n_levels=4, seed=35),
+    dict(kind="burgers", nx=150, nu=0.02, n=8, n_levels=2, seed=36),
+]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def build(cfgs, **opt):
+    probs, bs, solvers = [], [], []
+    for c in cfgs:
+        prob, rng = make_problem(**c)
+        probs.append(prob)
+        bs.append(make_rhs(prob, rng))
+        o = pm.default_options(restart=400, maxit=400, **opt)
+        solvers.append(pm.Solver(prob.levels, o, stream=torch.cuda.Stream()))
+    torch.cuda.synchronize()
+    return probs, bs, solvers
+
+
+def test_batch_equals_individual_solves_bitwise():
+    probs, bs, single = build(MIX)
+    xs1, st1 = [], []
+    for s, b in zip(single, bs):
+        x, st, rc = s.solve(dev(b), tol=1e-10)
+        xs1.append(host(x))
+        st1.append(st)
+    _, _, batch = build(MIX)
+    dbs = [dev(b) for b in bs]
+    torch.cuda.synchronize()
+    xs2, st2, status, rc = pm.solve_batch(batch, dbs, tol=1e-10)
+    assert rc == pm.PITMG_OK and all(s_ == pm.PITMG_OK for s_ in status)
+    for i, prob in enumerate(probs):
+        assert st2[i]["iters"] == st1[i]["iters"], i
+        assert st2[i]["coarse_its_total"] == st1[i]["coarse_its_total"], i
+        x2 = host(xs2[i])
+        assert np.array_equal(x2, xs1[i]), i
+        lv = prob.levels[0]
+        A = OracleLevel(lv.N, lv.V, lv.Z).A
+        assert np.linalg.norm(bs[i] - A @ x2) <= 1.01e-10 * np.linalg.norm(bs[i]), i
+    for s in single + batch:
+        s.close()
+
+
+def test_batch_zero_rhs_member_and_single_member():
+    probs, bs, solvers = build(MIX[:3])
+    dbs = [dev(bs[0]), torch.zeros(probs[1].size, dtype=torch.float64, device="cuda"),
+           dev(bs[2])]
+    torch.cuda.synchronize()
+    xs, st, status, rc = pm.solve_batch(solvers, dbs, tol=1e-10)
+    assert rc == pm.PITMG_OK
+    assert st[1]["converged"] == 1 and st[1]["iters"] == 0
+    assert not torch.any(xs[1] != 0)
+    xs1, st1, _, rc1 = pm.solve_batch(solvers[:1], dbs[:1], tol=1e-10)
+    assert rc1 == pm.PITMG_OK and st1[0]["iters"] == st[0]["iters"]
+    for s in solvers:
+        s.close()
+
+
+def test_batch_rejects_a_repeated_handle():
+    probs, bs, solvers = build(MIX[:1])
+    db = dev(bs[0])
+    with pytest.raises(pm.PitmgError):
+        pm.solve_batch([solvers[0], solvers[0]], [db, db], tol=1e-10)
+    solvers[0].close()
+
+
+@pytest.mark.parametrize("idx", [0, 4])
+def test_graph_vcycle_replays_match_eager(idx):
+    probs, bs, (s,) = build([MIX[idx]], coarse_fixed_its=3)
+    rng = np.random.default_rng(40)
+    r = dev(rng.normal(size=probs[0].size))
+    eager = host(s.vcycle(r))
+    s.set_options(vcycle_graph=1)
+    for rep in range(4):
+        e = host(s.vcycle(r))
+        assert np.array_equal(e, eager), rep
+        # eager work and a synchronisation between replays
+        s.set_options(vcycle_graph=0)
+        assert np.array_equal(host(s.vcycle(r)), eager)
+        s.set_options(vcycle_graph=1)
+        torch.cuda.synchronize()
+    # a second input through the same capture
+    r2 = dev(rng.normal(size=probs[0].size))
+    s.set_options(vcycle_graph=0)
+    eager2 = host(s.vcycle(r2))
+    s.set_options(vcycle_graph=1)
+    assert np.array_equal(host(s.vcycle(r2)), eager2)
+    assert np.array_equal(host(s.vcycle(r)), eager)
+    s.close()
+
+
+def test_graph_fgmres_matches_eager_with_fixed_coarse_steps():
+    probs, bs, (s,) = build([MIX[4]], coarse_fixed_its=2)
+    b = dev(bs[0])
+    x1, st1, _ = s.solve(b, tol=1e-10)
+    x1 = host(x1)
+    s.set_options(restart=400, maxit=400, coarse_fixed_its=2, vcycle_graph=1)
+    x2, st2, _ = s.solve(b, tol=1e-10)
+    assert st2["iters"] == st1["iters"] and np.array_equal(host(x2), x1)
+    s.close()
+
+
+def test_graph_fgmres_adaptive_coarse_converges():
+    probs, bs, (s,) = build([MIX[3]], vcycle_graph=1)
+    x, st, rc = s.solve(dev(bs[0]), tol=1e-10)
+    lv = probs[0].levels[0]
+    A = OracleLevel(lv.N, lv.V, lv.Z).A
+    assert rc == pm.PITMG_OK
+    assert np.linalg.norm(bs[0] - A @ host(x)) <= 1.01e-10 * np.linalg.norm(bs[0])
+    s.close()
+
+
+def test_graph_needs_a_stream():
+    prob, rng = make_problem(**MIX[0])
+    s = pm.Solver(prob.levels, pm.default_options(), stream=None)
+    if s.stream.cuda_stream == 0:
+        with pytest.raises(pm.PitmgError):
+            s.set_options(vcycle_graph=1)
+    s.close()
+
+
+@pytest.mark.parametrize("idx", [3, 4])
+def test_autotune_keeps_results(idx):
+    probs, bs, (s,) = build([MIX[idx]], coarse_fixed_its=3)
+    rng = np.random.default_rng(41)
+    prob = probs[0]
+    before = []
+    for lev in range(prob.n_levels - 1):
+        m = (4 * prob.p + prob.q) * (prob.n >> lev)
+        bb, yy = dev(rng.normal(size=m)), dev(rng.normal(size=m))
+        before.append((bb, yy, host(s.jacobi_sweep(bb, yy, level=lev))))
+    cfg = s.autotune()
+    assert len(cfg) == prob.n_levels and cfg[-1] == 0
+    assert all(c in (-1, 1, 2, 3, 4) for c in cfg[:-1])
+    for lev, (bb, yy, ref) in enumerate(before):
+        got = host(s.jacobi_sweep(bb, yy, level=lev))
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), (lev, cfg)
+    x, st, rc = s.solve(dev(bs[0]), tol=1e-10)
+    assert rc == pm.PITMG_OK
+    s.close()
