@@ -67,6 +67,7 @@ struct pitmg_handle {
   double* w = nullptr;
   double* r = nullptr;
   double* partial = nullptr;         // [blocks][restart+2]
+  double* upd = nullptr;             // [groups][2][len] for the grouped update, or NULL
   double* coef = nullptr;            // device scalars, 2*(restart+1)+4
   double* hbuf = nullptr;            // pinned host mirror of coef
   double* coarse_work = nullptr;     // coarse Krylov bases
@@ -765,7 +766,7 @@ struct FgmresRun {
           // one pass: q_j = (v_j - Q s)/alpha, w -= Q hh + cq q_j, |w|^2
           if ((rc = timed(h, 5, [&] {
                  return launch_update(h->Vk, j, Vp(j), h->w, h->coef, h->coef + j, alpha, cq,
-                                      j > 0 ? 1 : 0, len, h->partial, h->stream);
+                                      j > 0 ? 1 : 0, len, h->partial, h->upd, h->stream);
                })))
             return rc;
           if ((rc = timed(h, 5, [&] {
@@ -1094,6 +1095,13 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   const int nb = krylov_slices(len) > krylov_partial_blocks(len) ? krylov_slices(len)
                                                                    : krylov_partial_blocks(len);
   if ((rc = dalloc(h, (void**)&h->partial, (size_t)nb * (2 * m + 4) * 8))) return fail(rc);
+  {
+    int gmax = 1;
+    for (int nbv = 1; nbv <= m + 1; ++nbv) gmax = std::max(gmax, krylov_groups(len, nbv));
+    if (gmax > 1 &&
+        (rc = dalloc(h, (void**)&h->upd, (size_t)gmax * 2 * len * 8)))
+      return fail(rc);
+  }
   const int ncoef = 2 * (m + 2) + 8;   // >= 2m+3 dot values
   if ((rc = dalloc(h, (void**)&h->coef, (size_t)ncoef * 8))) return fail(rc);
   if (hipHostMalloc((void**)&h->hbuf, (size_t)ncoef * 8, hipHostMallocDefault) != hipSuccess)
@@ -1331,6 +1339,7 @@ void pitmg_destroy(pitmg_handle* h) {
   drop_graph(h);
   hipFree(h->g_in);
   hipFree(h->g_out);
+  hipFree(h->upd);
   for (auto e : h->pool) hipEventDestroy(e);
   for (auto& b : h->lv) {
     hipFree(b.N_own);

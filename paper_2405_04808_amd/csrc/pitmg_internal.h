@@ -160,10 +160,15 @@ int krylov_partial_blocks(long long len);
 hipError_t launch_dots(const double* basis, int nb, const double* x1, const double* x2,
                        long long len, double* partial, hipStream_t s);
 // x1 <- (x1 - basis^T s)/alpha if reorth;  x2 <- x2 - basis^T h - cq*x1;
-// norm_partial[slice] = |x2|^2 over the slice
+// norm_partial[slice] = |x2|^2 over the slice.  scratch: 2*len doubles per
+// basis group (krylov_groups) when there is more than one; NULL forces the
+// single-pass kernel.
 hipError_t launch_update(const double* basis, int nb, double* x1, double* x2,
                          const double* scoef, const double* hcoef, double alpha, double cq,
-                         int reorth, long long len, double* norm_partial, hipStream_t s);
+                         int reorth, long long len, double* norm_partial, double* scratch,
+                         hipStream_t s);
+// Basis groups the dot and update passes split nb vectors of length len into.
+int krylov_groups(long long len, int nb);
 hipError_t launch_reduce_partials(const double* partial, int nblk, int nval,
                                   double* out, hipStream_t s);
 // w += sign * basis^T coef; optional per-slice sums of the new w squared.
@@ -174,6 +179,13 @@ hipError_t launch_scale(double* dst, const double* src, double alpha,
                         long long len, hipStream_t s);
 hipError_t launch_axpby(double* y, const double* x, double a, double b,
                         long long len, hipStream_t s);   // y = a*x + b*y
+
+// ---- small blocks (pitmg_small.hip): one thread per time step -------------
+bool small_supported(int p, int q);
+hipError_t launch_jacobi_small(const LevelView& L, const double* b, const double* yold,
+                               const double* ecoarse, int variant, double* ynew, hipStream_t s);
+hipError_t launch_apply_small(const LevelView& L, const double* x, const double* b, double alpha,
+                              double beta, double* out, hipStream_t s);
 
 // ---- learned coarse correction (pitmg_net.hip) ----------------------------
 // True if the network takes C channels over T steps.

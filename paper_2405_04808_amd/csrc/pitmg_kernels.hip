@@ -22,6 +22,7 @@
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
 #include "pitmg_blocks.h"
+#include <algorithm>
 #include <climits>
 
 namespace pitmg {
@@ -251,6 +252,8 @@ static hipError_t launch_jacobi_generic(const LevelView& L, const double* b, con
 
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
                          const double* ecoarse, int variant, double* ynew, hipStream_t s) {
+  if (small_supported(L.p, L.q))
+    return launch_jacobi_small(L, b, yold, ecoarse, variant, ynew, s);
   const bool al = L.fp32 ? aligned16(L.N32) && aligned16(L.V32) && aligned16(L.Z32) &&
                                aligned16(L.Gi32)
                          : aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi);
@@ -279,6 +282,7 @@ __global__ __launch_bounds__(NT) void k_apply(LevelView L, const double* __restr
 
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b, double alpha,
                         double beta, double* out, hipStream_t s) {
+  if (small_supported(L.p, L.q)) return launch_apply_small(L, x, b, alpha, beta, out, s);
   const size_t lds = apply_lds_doubles(L.p, L.q, kApplyThreads) * sizeof(double);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_apply<kApplyThreads>,
@@ -444,6 +448,10 @@ __global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const int nblk = gridDim.x;
   const bool two = x2 != nullptr;
+  // blockIdx.y: a contiguous group of basis vectors (short vectors with
+  // long bases would otherwise leave most of the device idle)
+  const int per = (nb + gridDim.y - 1) / gridDim.y;
+  const int i0 = blockIdx.y * per, i1 = min(nb, i0 + per);
   double a[kPerLane], c[kPerLane];
 #pragma unroll
   for (int t = 0; t < kPerLane; ++t) {
@@ -451,7 +459,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__
     a[t] = e < len ? x1[e] : 0.0;
     c[t] = (two && e < len) ? x2[e] : 0.0;
   }
-  for (int i = wv; i < nb; i += kVecThreads / kWave) {
+  for (int i = i0 + wv; i < i1; i += kVecThreads / kWave) {
     const double* __restrict__ bi = basis + (size_t)i * len;
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -468,7 +476,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__
       if (two) partial[(size_t)(nb + i) * nblk + blockIdx.x] = s2;
     }
   }
-  if (wv == 0) {
+  if (wv == 0 && blockIdx.y == 0) {
     double s11 = 0.0, s12 = 0.0, s22 = 0.0;
 #pragma unroll
     for (int t = 0; t < kPerLane; ++t) {
@@ -551,6 +559,91 @@ __global__ __launch_bounds__(kVecThreads) void k_update(const double* __restrict
   }
 }
 
+// The update for short vectors, in two passes.  Pass 1, grid (slices,
+// groups): part[g][0][e] = sum_{i in group g} s_i basis_i[e] and
+// part[g][1][e] = sum h_i basis_i[e].  Pass 2, grid (slices): the group sums
+// in order, then the same update and norm partials as k_update.
+__global__ __launch_bounds__(kVecThreads) void k_update_part(const double* __restrict__ basis,
+                                                             int nb,
+                                                             const double* __restrict__ scoef,
+                                                             const double* __restrict__ hcoef,
+                                                             long long len,
+                                                             double* __restrict__ part) {
+  constexpr int kPer = kSliceLen / kVecThreads;
+  const long long e0 = (long long)blockIdx.x * kSliceLen;
+  const int per = (nb + gridDim.y - 1) / gridDim.y;
+  const int i0 = blockIdx.y * per, i1 = min(nb, i0 + per);
+  double a1[kPer], a2[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    a1[t] = 0.0;
+    a2[t] = 0.0;
+  }
+  for (int i = i0; i < i1; ++i) {
+    const double* __restrict__ bi = basis + (size_t)i * len;
+    const double si = scoef[i], hi = hcoef[i];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const long long e = e0 + threadIdx.x + (long long)kVecThreads * t;
+      const double bv = e < len ? bi[e] : 0.0;
+      a1[t] += si * bv;
+      a2[t] += hi * bv;
+    }
+  }
+  double* p1 = part + (size_t)blockIdx.y * 2 * len;
+  double* p2 = p1 + len;
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const long long e = e0 + threadIdx.x + (long long)kVecThreads * t;
+    if (e < len) {
+      p1[e] = a1[t];
+      p2[e] = a2[t];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_update_apply(double* __restrict__ x1,
+                                                              double* __restrict__ x2,
+                                                              const double* __restrict__ part,
+                                                              int ngroups, double alpha,
+                                                              double cq, int reorth,
+                                                              long long len,
+                                                              double* __restrict__ norm_partial) {
+  __shared__ double red[kVecThreads / kWave];
+  constexpr int kPer = kSliceLen / kVecThreads;
+  const long long e0 = (long long)blockIdx.x * kSliceLen;
+  double nrm = 0.0;
+  const double inv = 1.0 / alpha;
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const long long e = e0 + threadIdx.x + (long long)kVecThreads * t;
+    if (e < len) {
+      double a1 = 0.0, a2 = 0.0;
+      for (int g = 0; g < ngroups; ++g) {
+        a1 += part[(size_t)g * 2 * len + e];
+        a2 += part[(size_t)g * 2 * len + len + e];
+      }
+      double q = x1[e];
+      if (reorth) {
+        q = (q - a1) * inv;
+        x1[e] = q;
+      }
+      const double u = x2[e] - a2 - cq * q;
+      x2[e] = u;
+      nrm += u * u;
+    }
+  }
+  nrm = wave_sum(nrm);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kVecThreads / kWave; ++q) t += red[q];
+    norm_partial[blockIdx.x] = t;
+  }
+}
+
 // out[i] = sum over slices of partial[i * nblk + slice]; one wave per value.
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial,
                                                          int nblk, int nval,
@@ -617,18 +710,39 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, do
     y[e] = a * x[e] + b * y[e];
 }
 
+// Groups of basis vectors per launch of the dot and update passes: one when
+// the vector alone gives enough work-groups, else enough groups of at least
+// 8 vectors to bring the grid to about 1024 work-groups.
+int krylov_groups(long long len, int nb) {
+  const int sl = krylov_slices(len);
+  if (sl >= 128 || nb < 16) return 1;
+  const int by_size = (nb + 7) / 8;
+  const int by_grid = (1024 + sl - 1) / sl;
+  return std::max(1, std::min(by_size, by_grid));
+}
+
 hipError_t launch_dots(const double* basis, int nb, const double* x1, const double* x2,
                        long long len, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3(krylov_slices(len)), dim3(kVecThreads), 0, s, basis, nb, x1,
-                     x2, len, partial);
+  const int ng = krylov_groups(len, nb);
+  hipLaunchKernelGGL(k_dots, dim3(krylov_slices(len), ng), dim3(kVecThreads), 0, s, basis, nb,
+                     x1, x2, len, partial);
   return hipGetLastError();
 }
 
 hipError_t launch_update(const double* basis, int nb, double* x1, double* x2,
                          const double* scoef, const double* hcoef, double alpha, double cq,
-                         int reorth, long long len, double* norm_partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(krylov_slices(len)), dim3(kVecThreads), 0, s, basis, nb, x1,
-                     x2, scoef, hcoef, alpha, cq, reorth, len, norm_partial);
+                         int reorth, long long len, double* norm_partial, double* scratch,
+                         hipStream_t s) {
+  const int ng = krylov_groups(len, nb);
+  if (ng == 1 || !scratch) {
+    hipLaunchKernelGGL(k_update, dim3(krylov_slices(len)), dim3(kVecThreads), 0, s, basis, nb,
+                       x1, x2, scoef, hcoef, alpha, cq, reorth, len, norm_partial);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_update_part, dim3(krylov_slices(len), ng), dim3(kVecThreads), 0, s, basis,
+                     nb, scoef, hcoef, len, scratch);
+  hipLaunchKernelGGL(k_update_apply, dim3(krylov_slices(len)), dim3(kVecThreads), 0, s, x1, x2,
+                     scratch, ng, alpha, cq, reorth, len, norm_partial);
   return hipGetLastError();
 }
 

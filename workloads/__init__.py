@@ -20,8 +20,8 @@ correction's network (coarse_net_params).
 """
 from .problems import (Problem, Level, vanderpol_jacobians, burgers_jacobians,
                        lifted_blocks, make_problem, make_rhs, config_problem,
-                       coarse_net_params, CONFIGS)
+                       coarse_net_params, batch_mix, CONFIGS)
 
 __all__ = ["Problem", "Level", "vanderpol_jacobians", "burgers_jacobians",
            "lifted_blocks", "make_problem", "make_rhs", "config_problem",
-           "coarse_net_params", "CONFIGS"]
+           "coarse_net_params", "batch_mix", "CONFIGS"]

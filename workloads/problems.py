@@ -287,3 +287,28 @@ def coarse_net_params(C: int, H: int, seed: int, width: int = 3) -> np.ndarray:
         parts.append(rng.uniform(-a, a, size=o * i * width))
         parts.append(rng.uniform(-a, a, size=o))
     return np.concatenate(parts).astype(np.float32).astype(np.float64)
+
+
+def batch_mix(seed: int = 4, count: int = 64, vdp_n=(256, 1024, 4096), burgers_nx=(32, 64, 128),
+              burgers_n=(256, 512)):
+    """An uneven batch of independent systems (make_problem keyword sets).
+
+    The first half are van der Pol with n drawn from vdp_n; the second half
+    viscous Burgers (nu = 0.01) with nx drawn from burgers_nx and n from
+    burgers_n.  Every system coarsens to 8 steps (n_levels = log2(n) - 2) and
+    takes seed 4000 + i.  Draw order from default_rng(seed): for each system
+    in turn, its n (van der Pol) or its nx then n (Burgers).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        if i < count // 2:
+            n = int(rng.choice(list(vdp_n)))
+            cfg = dict(kind="vanderpol", n=n, seed=4000 + i)
+        else:
+            nx = int(rng.choice(list(burgers_nx)))
+            n = int(rng.choice(list(burgers_n)))
+            cfg = dict(kind="burgers", nx=nx, nu=0.01, n=n, seed=4000 + i)
+        cfg["n_levels"] = int(np.log2(n)) - 2
+        out.append(cfg)
+    return out
