@@ -18,7 +18,9 @@ from those the counters were taken with; the counter runs use --counters.
 
 Beside the FP64 solve, the line reports the V-cycle's algorithmic HBM rate
 with the FP64 smoother and with the FP32 smoother (every level above the
-coarsest), and one FP32-smoother solve of the same system.
+coarsest), one FP32-smoother solve of the same system, the learned coarse
+correction (pairs, training, held-out ablation) and an uneven batch of
+independent systems solved one by one and as a batch.
 """
 import argparse
 import json
@@ -31,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
-COUNTERS = os.path.join(ROOT, "profiles", "k_jacobi_shared_burgers128_hbm_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "k_jacobi_burgers128_hbm_counters.md")
 
 WORKLOADS = {
     # the measured workload: viscous Burgers, 128 nodes, 1024 steps
@@ -167,6 +169,66 @@ def learned_leg(pm, torch, wl, train_seeds=range(50000, 50008), held_out=(60000,
             "held_out": {str(sd): row for sd, row in zip(held_out, abl)}}
 
 
+def batch_leg(pm, torch, count=32, vdp_n=(256, 1024)):
+    """Uneven batch: the same independent systems solved one after another,
+    as one batch (phases interleaved over one stream per system), and as a
+    batch with captured V-cycles and tuned sweeps.  Fresh handles for each
+    mode; setup and tuning are timed apart from the solves."""
+    from workloads import batch_mix, make_problem, make_rhs
+    cfgs = batch_mix(count=count, vdp_n=vdp_n)
+    probs = []
+    for c in cfgs:
+        prob, rng = make_problem(**c)
+        probs.append((prob, make_rhs(prob, rng)))
+    bs = [torch.from_numpy(b).to("cuda") for _, b in probs]
+    torch.cuda.synchronize()
+    out = {"systems": count,
+           "mix": f"{count // 2} van der Pol (n in {list(vdp_n)}), {count - count // 2} Burgers "
+                  "(nx in [32, 64, 128], n in [256, 512]); seeds 4000+i; coarsest 8 steps"}
+    seq_its = None
+    for mode in ("sequential", "batch", "batch_graph_tuned"):
+        ts = time.perf_counter()
+        ss = []
+        for prob, _ in probs:
+            m = 2 * prob.n + 100
+            o = pm.default_options(restart=m, maxit=m, vcycle_graph=1 if "graph" in mode else 0)
+            ss.append(pm.Solver(prob.levels, o, stream=torch.cuda.Stream()))
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - ts
+        tune = 0.0
+        if mode.endswith("tuned"):
+            ta = time.perf_counter()
+            for s_ in ss:
+                s_.autotune()
+            tune = time.perf_counter() - ta
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        if mode == "sequential":
+            st = [s_.solve(b, tol=1e-10)[1] for s_, b in zip(ss, bs)]
+        else:
+            _, st, _, _ = pm.solve_batch(ss, bs, tol=1e-10)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ta
+        its = [x["iters"] for x in st]
+        row = {"s": round(el, 3), "systems_per_s": round(count / el, 3),
+               "setup_s": round(setup, 2), "tune_s": round(tune, 2), "fgmres_iters_total": sum(its),
+               "all_converged_1e-10": all(x["converged"] == 1 and x["relres_true"] <= 1.01e-10
+                                          for x in st)}
+        if seq_its is None:
+            seq_its = its
+        else:
+            row["iters_same_as_sequential"] = its == seq_its
+        out[mode] = row
+        print(f"# batch {mode}: {el:.2f} s", file=sys.stderr, flush=True)
+        for s_ in ss:
+            s_.close()
+        del ss
+        torch.cuda.empty_cache()
+    out["speedup_batch"] = round(out["sequential"]["s"] / out["batch"]["s"], 2)
+    out["speedup_batch_graph_tuned"] = round(out["sequential"]["s"] / out["batch_graph_tuned"]["s"], 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +241,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-smoother leg")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-coarse-correction leg (pairs, training, ablation)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: one solve cut at 40 FGMRES steps (the same "
                          "launches per V-cycle), then a 256 MiB copy kernel for calibration")
@@ -186,6 +250,7 @@ def main():
     if args.counters:
         args.steps, args.warmup = 1, 0
         args.no_cpu_baseline = args.no_profile = args.no_fp32 = args.no_learned = True
+        args.no_batch = True
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
               "supported (the time-parallel path shards by time blocks, see the design "
@@ -204,6 +269,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     solver = pm.Solver(prob.levels, opts, device="cuda:0")
+    # setup-time tuning of each level's sweep launch shape (not timed)
+    sweep_shapes = solver.autotune()
     db = torch.from_numpy(b).to(dev)
     x = solver.empty(0)
     torch.cuda.synchronize()
@@ -273,13 +340,15 @@ def main():
         achieved = alg_bytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         from paper_2405_04808_amd.rocprof_summary import read_traffic
         rec = read_traffic(COUNTERS)
-        kname = ("k_jacobi_shared<%d, %d, double>" % (p // 32, p // 16)
-                 if p == q and p in (64, 128) and shared_V and shared_Z else "k_jacobi")
+        names = {0: "built-in", -1: "k_jacobi_tiled<%d, %d, double>" % (p // 32, p // 16)}
+        kname = "block Jacobi sweep, levels 0..%d: " % (L - 2) + ", ".join(
+            (names.get(c) or "k_jacobi_shared<%d, %d, double> x%d steps" % (p // 32, p // 16, c))
+            for c in sweep_shapes[:L - 1])
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": rec["traffic_bytes_per_launch"] if rec else None,
                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
-                    "kernel": kname + " (block Jacobi sweep, all levels)",
+                    "kernel": kname,
                     "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
                     "alg_bytes_per_launch": round(alg_bytes / max(launches, 1))}
         kern = {k: {"launches": v[0], "ms_total": round(v[1], 3)} for k, v in prof.items()}
@@ -333,6 +402,10 @@ def main():
     if not args.no_learned and args.workload == "burgers128":
         learned = learned_leg(pm, torch, wl)
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_leg(pm, torch, count=args.batch_count)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, int(round(float(np.mean(iters)))))
@@ -352,6 +425,7 @@ def main():
         "data": "synthetic (seeded linearisation point and N(0,1) right-hand side)",
         "config": {"workload": wl["desc"], "p": p, "q": q, "n": n, "levels": L,
                    "step": "refactor all levels + FGMRES solve from x0=0",
+                   "sweep_shapes": sweep_shapes,
                    "fgmres_restart": opts.restart, "vector_len": prob.size},
         "fgmres_iters": iters,
         "converged_1e-10": ok,
@@ -360,6 +434,7 @@ def main():
         "vcycle_hbm": vc,
         "fp32_smoother": fp32,
         "learned_coarse": learned,
+        "uneven_batch": batch,
         "kernel_ms": kern,
     }
     print(json.dumps(out))
