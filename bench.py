@@ -242,6 +242,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-coarse-correction leg (pairs, training, ablation)")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--sweep-shapes", default=None,
+                    help="comma-separated sweep launch shape per level instead of tuning "
+                         "(as reported in config.sweep_shapes)")
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: one solve cut at 40 FGMRES steps (the same "
@@ -270,7 +273,11 @@ def main():
     torch.cuda.set_device(dev)
     solver = pm.Solver(prob.levels, opts, device="cuda:0")
     # setup-time tuning of each level's sweep launch shape (not timed)
-    sweep_shapes = solver.autotune()
+    if args.sweep_shapes:
+        sweep_shapes = [int(c) for c in args.sweep_shapes.split(",")]
+        solver.set_sweep_shapes(sweep_shapes)
+    else:
+        sweep_shapes = solver.autotune()
     db = torch.from_numpy(b).to(dev)
     x = solver.empty(0)
     torch.cuda.synchronize()

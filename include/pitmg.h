@@ -195,6 +195,12 @@ int pitmg_fgmres_solve_batch(pitmg_handle* const* h, int count, const double* co
  * sweep do not depend on the choice beyond rounding.  Synchronises. */
 int pitmg_autotune(pitmg_handle* h, int* cfg);
 
+/* Set the sweep launch shapes directly (host array of n_levels entries, same
+ * meaning as pitmg_autotune's output; the coarsest entry must be 0): to reuse
+ * a tuned choice on another handle of the same shape, or to fix the launch
+ * mix of a profiled run.  A shape the level cannot use is an error. */
+int pitmg_set_sweep_shapes(pitmg_handle* h, const int* cfg);
+
 /* Kernel timing: while enabled, the library brackets every launch with HIP
  * events on its stream and accumulates per-kernel-class time.  Classes:
  * 0 factor, 1 jacobi, 2 apply, 3 transfer, 4 coarse, 5 krylov. */

@@ -97,3 +97,64 @@ def split_blocks(At: sp.csr_matrix, bounds: np.ndarray):
     def pick(mask):
         return sp.csr_matrix((C.data[mask], (C.row[mask], C.col[mask])), shape=At.shape)
     return pick(br == bc), pick(br > bc), pick(br < bc)
+
+
+# ---------------------------------------------------------------------------
+# One time-major block at a time (for sizes whose assembled matrix is too
+# large to form): indices, the dense diagonal block D_k and its right-hand
+# side, written from the operator rows of the lifted system (Fig. 4, Fig. 5).
+# ---------------------------------------------------------------------------
+
+def block_index(p: int, q: int, n: int, k: int) -> np.ndarray:
+    """Type-major indices of time-major block k (1-based), in the block's
+    order: block 1 (u_1, z_1, lambda_1); 2 <= k <= n (v_{k-1}, u_k, z_k,
+    lambda_k, mu_{k-1}); block n+1 (v_n, mu_n)."""
+    o = type_offsets(p, q, n)
+
+    def rng(t, kk, w):
+        s = o[t] + (kk - 1) * w
+        return np.arange(s, s + w)
+
+    if k == 1:
+        return np.concatenate([rng("u", 1, p), rng("z", 1, q), rng("lam", 1, p)])
+    if k == n + 1:
+        return np.concatenate([rng("v", n, p), rng("mu", n, p)])
+    return np.concatenate([rng("v", k - 1, p), rng("u", k, p), rng("z", k, q),
+                           rng("lam", k, p), rng("mu", k - 1, p)])
+
+
+def diagonal_block(Nk: np.ndarray, Vk: np.ndarray, Zk: np.ndarray, k: int, n: int) -> np.ndarray:
+    """Dense D_k from the rows of A~ restricted to block k's own unknowns:
+    u_k: u_k + N_k^T lambda_k;  v_{k-1}: v_{k-1} + V_k^T lambda_k - mu_{k-1};
+    z_k: z_k + Z_k^T lambda_k;  lambda_k: N_k u_k + V_k v_{k-1} + Z_k z_k;
+    mu_{k-1}: -v_{k-1} (its u_{k-1} term couples to block k-1).  Block n+1
+    holds v_n (v_n - mu_n, V_{n+1} := 0) and mu_n (-v_n)."""
+    p, q = Nk.shape[0], Zk.shape[1]
+    I = np.eye(p)
+    if k == n + 1:
+        return np.block([[I, -I], [-I, np.zeros((p, p))]])
+    if k == 1:
+        return np.block([[I, np.zeros((p, q)), Nk.T],
+                         [np.zeros((q, p)), np.eye(q), Zk.T],
+                         [Nk, Zk, np.zeros((p, p))]])
+    Zp, Zq, Zqp = np.zeros((p, p)), np.zeros((p, q)), np.zeros((q, p))
+    return np.block([
+        [I, Zp, Zq, Vk.T, -I],
+        [Zp, I, Zq, Nk.T, Zp],
+        [Zqp, Zqp, np.eye(q), Zk.T, Zqp],
+        [Vk, Nk, Zk, Zp, Zp],
+        [-I, Zp, Zq, Zp, Zp],
+    ])
+
+
+def block_coupling(y: np.ndarray, p: int, q: int, n: int, k: int) -> np.ndarray:
+    """((L + L^T) y) on block k: the u_k row sees +mu_k (block k+1) and the
+    mu_{k-1} row sees +u_{k-1} (block k-1); block n+1's mu_n row sees +u_n."""
+    o = type_offsets(p, q, n)
+    if k == n + 1:
+        return np.concatenate([np.zeros(p), y[o["u"] + (n - 1) * p: o["u"] + n * p]])
+    mu_k = y[o["mu"] + (k - 1) * p: o["mu"] + k * p]
+    if k == 1:
+        return np.concatenate([mu_k, np.zeros(q + p)])
+    u_km1 = y[o["u"] + (k - 2) * p: o["u"] + (k - 1) * p]
+    return np.concatenate([np.zeros(p), mu_k, np.zeros(q + p), u_km1])

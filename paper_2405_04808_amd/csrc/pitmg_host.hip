@@ -260,8 +260,8 @@ int check_problem(pitmg_handle* h, const pitmg_problem* pb) {
   const long long div = 1LL << (pb->n_levels - 1);
   if (pb->n % div != 0)
     return set_err(h, PITMG_ERR_INVALID, "n must be divisible by 2^(n_levels-1)");
-  if (pb->p > 256 || pb->q > 256)
-    return set_err(h, PITMG_ERR_UNSUPPORTED, "this build supports p, q <= 256");
+  if (pb->p > 512 || pb->q > 512)
+    return set_err(h, PITMG_ERR_UNSUPPORTED, "this build supports p, q <= 512");
   if (!pb->N || !pb->V || !pb->Z) return set_err(h, PITMG_ERR_INVALID, "block arrays are NULL");
   const long long pp = (long long)pb->p * pb->p, pq = (long long)pb->p * pb->q;
   if (pb->N_stride != pp && pb->N_stride != 0)
@@ -997,6 +997,27 @@ int pitmg_autotune(pitmg_handle* h, int* cfg) {
   (void)hipEventDestroy(e1);
   drop_graph(h);
   return rc;
+}
+
+int pitmg_set_sweep_shapes(pitmg_handle* h, const int* cfg) {
+  if (!h || !cfg) return PITMG_ERR_INVALID;
+  for (int l = 0; l < h->L; ++l) {
+    const int c = cfg[l];
+    if (c == 0) continue;
+    if (l == h->L - 1)
+      return set_err(h, PITMG_ERR_INVALID, "the coarsest level has no sweep shape");
+    LevelView v = view(h, l);
+    v.sweep_cfg = 0;
+    const bool ok = (c == -1 && jacobi_tiled_supported(h->p, h->q)) ||
+                    (c >= 1 && c <= 4 && jacobi_shared_supported(v));
+    if (!ok)
+      return set_err(h, PITMG_ERR_INVALID,
+                     "sweep shape " + std::to_string(c) + " is not available on level " +
+                         std::to_string(l));
+  }
+  for (int l = 0; l < h->L; ++l) h->lv[l].sweep_cfg = cfg[l];
+  drop_graph(h);
+  return PITMG_OK;
 }
 
 int pitmg_coarse_net_attach(pitmg_handle* h, pitmg_net* net) {

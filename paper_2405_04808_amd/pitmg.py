@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH):
         "pitmg_coarse_pairs_arm": (i, [vp, vp, vp, i]),
         "pitmg_coarse_pairs_count": (i, [vp]),
         "pitmg_autotune": (i, [vp, C.POINTER(i)]),
+        "pitmg_set_sweep_shapes": (i, [vp, C.POINTER(i)]),
         "pitmg_status_string": (C.c_char_p, [i]),
         "pitmg_last_error": (C.c_char_p, [vp]),
         "pitmg_destroy": (None, [vp]),
@@ -312,6 +313,11 @@ class Solver:
         cfg = (C.c_int * self.n_levels)()
         self._check(self.lib.pitmg_autotune(self.h, cfg))
         return list(cfg)
+
+    def set_sweep_shapes(self, cfg):
+        """Set each level's sweep launch shape (as returned by autotune)."""
+        arr = (C.c_int * self.n_levels)(*cfg)
+        self._check(self.lib.pitmg_set_sweep_shapes(self.h, arr))
 
     # -- learned coarse correction ------------------------------------------------
     def attach_net(self, net: Optional["Net"]):

@@ -74,12 +74,26 @@ def stats_table(directory: str, top: int = 25) -> str:
     return "\n".join(out)
 
 
-def counter_means(directory: str, counter: str):
-    """{kernel name: {grid size: [values]}} for one counter."""
+def _first_dispatch(rows, pattern):
+    """Smallest Dispatch_Id of the kernels matching pattern (0 if none or no
+    pattern).  With k_dots, whose first dispatch opens the first solve, the
+    dispatches before it (setup, factorisation, sweep tuning) are left out."""
+    if not pattern:
+        return 0
+    rx = re.compile(pattern)
+    ids = [int(r["Dispatch_Id"]) for r in rows if rx.search(r["Kernel_Name"])]
+    return min(ids) if ids else 0
+
+
+def counter_means(directory: str, counter: str, after_first: str = None):
+    """{kernel name: {grid size: [values]}} for one counter, over the
+    dispatches after the first one of the kernels matching after_first."""
     path = _find(directory, "counter_collection.csv")
+    rows = list(csv.DictReader(open(path)))
+    first = _first_dispatch(rows, after_first)
     out = defaultdict(lambda: defaultdict(list))
-    for r in csv.DictReader(open(path)):
-        if r["Counter_Name"] != counter:
+    for r in rows:
+        if r["Counter_Name"] != counter or int(r["Dispatch_Id"]) <= first:
             continue
         out[r["Kernel_Name"]][int(r["Grid_Size"])].append(float(r["Counter_Value"]))
     return out
@@ -98,22 +112,26 @@ def _select(table, pattern: str, exclude_grids=()):
     return names, merged
 
 
-def per_grid_durations(directory: str, pattern: str):
+def per_grid_durations(directory: str, pattern: str, after_first: str = None):
     """{grid size: [durations in us]} of the dispatches of kernels matching
-    pattern, from *_kernel_trace.csv."""
+    pattern, from *_kernel_trace.csv, after the first dispatch matching
+    after_first (if given)."""
     path = _find(directory, "kernel_trace.csv")
+    rows = list(csv.DictReader(open(path)))
+    first = _first_dispatch(rows, after_first)
     rx = re.compile(pattern)
     out = defaultdict(list)
-    for r in csv.DictReader(open(path)):
-        if rx.search(r["Kernel_Name"]):
+    for r in rows:
+        if int(r["Dispatch_Id"]) > first and rx.search(r["Kernel_Name"]):
             g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
             out[g].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     return out
 
 
-def summarise_counters(fetch_dir, write_dir, kernel, copy_kernel, copy_bytes, exclude_grids=()):
-    f_tab = counter_means(fetch_dir, "FETCH_SIZE")
-    w_tab = counter_means(write_dir, "WRITE_SIZE")
+def summarise_counters(fetch_dir, write_dir, kernel, copy_kernel, copy_bytes, exclude_grids=(),
+                       after_first=None):
+    f_tab = counter_means(fetch_dir, "FETCH_SIZE", after_first)
+    w_tab = counter_means(write_dir, "WRITE_SIZE", after_first)
     names, f_sweep = _select(f_tab, kernel, exclude_grids)
     _, w_sweep = _select(w_tab, kernel, exclude_grids)
     _, f_copy = _select(f_tab, copy_kernel)
@@ -151,6 +169,8 @@ def main(argv=None):
     a.add_argument("--per-grid", default=None,
                    help="kernel regex: add its dispatch durations grouped by grid size")
     a.add_argument("--exclude-grid", type=int, action="append", default=[])
+    a.add_argument("--after-first", default=None,
+                   help="kernel regex: count only dispatches after its first dispatch")
     a.add_argument("--out", required=True)
     b = sub.add_parser("counters")
     b.add_argument("--fetch", required=True)
@@ -163,6 +183,8 @@ def main(argv=None):
     b.add_argument("--note", default="")
     b.add_argument("--exclude-grid", type=int, action="append", default=[],
                    help="grid size (work-items) whose dispatches are left out")
+    b.add_argument("--after-first", default=None,
+                   help="kernel regex: count only dispatches after its first dispatch")
     b.add_argument("--out", required=True)
     args = ap.parse_args(argv)
 
@@ -173,7 +195,7 @@ def main(argv=None):
             txt += [args.note, ""]
         txt += [stats_table(args.dir), ""]
         if args.per_grid:
-            d = per_grid_durations(args.dir, args.per_grid)
+            d = per_grid_durations(args.dir, args.per_grid, args.after_first)
             txt += [f"Dispatches of `{args.per_grid}` by grid size (work-items):", "",
                     "| grid | dispatches | avg us | total ms |", "|---|---|---|---|"]
             keep = []
@@ -189,7 +211,7 @@ def main(argv=None):
         return 0
 
     s = summarise_counters(args.fetch, args.write, args.kernel, args.copy_kernel,
-                           args.copy_bytes, tuple(args.exclude_grid))
+                           args.copy_bytes, tuple(args.exclude_grid), args.after_first)
     txt = [f"# {args.title}", "", "Commands (from the repository root, MI355X, ROCm 7.2):", "",
            "```"] + args.command + ["```", ""]
     if args.note:

@@ -47,7 +47,7 @@ def _problem(p=2, q=1, n=16, levels=2, nstride=None):
     (dict(p=0), pm.PITMG_ERR_INVALID),
     (dict(n=12, levels=4), pm.PITMG_ERR_INVALID),        # 12 % 8 != 0
     (dict(nstride=3), pm.PITMG_ERR_INVALID),
-    (dict(p=300, q=1), pm.PITMG_ERR_UNSUPPORTED),
+    (dict(p=600, q=1), pm.PITMG_ERR_UNSUPPORTED),          # p, q <= 512
 ])
 def test_setup_rejects_bad_problems_on_host(kw, code):
     lib = pm.load_library()

@@ -172,3 +172,21 @@ def test_autotune_keeps_results(idx):
     x, st, rc = s.solve(dev(bs[0]), tol=1e-10)
     assert rc == pm.PITMG_OK
     s.close()
+
+
+def test_set_sweep_shapes_checks_and_applies():
+    probs, bs, (s,) = build([MIX[4]], coarse_fixed_its=3)
+    L = probs[0].n_levels
+    cfg = s.autotune()
+    s.set_sweep_shapes([0] * L)
+    s.set_sweep_shapes(cfg)
+    with pytest.raises(pm.PitmgError):
+        s.set_sweep_shapes([9] + [0] * (L - 1))
+    with pytest.raises(pm.PitmgError):
+        s.set_sweep_shapes([0] * (L - 1) + [1])
+    s.close()
+    # a p = 2 system has neither tiled shape
+    probs2, _, (s2,) = build([MIX[0]])
+    with pytest.raises(pm.PitmgError):
+        s2.set_sweep_shapes([-1] + [0] * (probs2[0].n_levels - 1))
+    s2.close()

@@ -455,3 +455,28 @@ def test_coarse_solve_tolerance_and_counts():
     if its > 1:
         x1, _ = gmres_right(lv.At, bt, lv.sgs, 0.0, 50, fixed_its=its - 1)
         assert np.linalg.norm(bt - lv.At @ x1) > 1e-3 * np.linalg.norm(bt)
+
+
+def test_single_block_helpers_match_the_assembled_operator():
+    # block indices, dense diagonal blocks and couplings written one block at
+    # a time agree with the assembled A~ and its time-major splitting
+    from oracle.system import (block_index, diagonal_block, block_coupling, assemble_A,
+                               time_major_perm, block_bounds, split_blocks)
+    prob, rng = make_problem(kind="burgers", nx=4, nu=0.01, n=6, n_levels=1, seed=77)
+    lv = prob.levels[0]
+    p, q, n = prob.p, prob.q, lv.N.shape[0]
+    A = assemble_A(lv.N, lv.V_full(), lv.Z_full()).toarray()
+    perm = time_major_perm(p, q, n)
+    bounds = block_bounds(p, q, n)
+    assert np.array_equal(np.concatenate([block_index(p, q, n, k) for k in range(1, n + 2)]),
+                          perm)
+    y = rng.normal(size=A.shape[0])
+    Vf, Zf = lv.V_full(), lv.Z_full()
+    for k in range(1, n + 2):
+        idx = block_index(p, q, n, k)
+        kk = min(k, n) - 1
+        D = diagonal_block(lv.N[kk], Vf[kk], Zf[kk], k, n)
+        assert np.array_equal(D, A[np.ix_(idx, idx)])
+        # the coupling is the rest of block k's rows of A~ y
+        full = A[idx] @ y
+        assert np.allclose(D @ y[idx] + block_coupling(y, p, q, n, k), full, rtol=0, atol=1e-12)
