@@ -118,6 +118,12 @@ typedef struct {
                                   Needs a stream other than the null stream and
                                   nu_post > 0; not used while profiling,
                                   recording coarse pairs or with coarse_mode 1 */
+  int apply_from_sweep;        /* 1: when the preconditioner's last step was an
+                                  FP64 block Jacobi sweep z = D^{-1}(b - (L+L^T)
+                                  y) on the finest level (nu_post >= 2), FGMRES
+                                  forms A~ z as b - (L+L^T)(y - z), equal in
+                                  exact arithmetic and free of block reads;
+                                  0: always the explicit product             */
 } pitmg_options;
 
 typedef struct {
@@ -135,7 +141,7 @@ typedef struct {
 
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
  * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
- * stall_steps 2, vcycle_graph 0. */
+ * stall_steps 2, vcycle_graph 0, apply_from_sweep 1. */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and

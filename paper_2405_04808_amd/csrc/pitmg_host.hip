@@ -108,6 +108,9 @@ struct pitmg_handle {
   int g_K = 0;                       // coarse steps enqueued in the capture
   int* g_its_slot = nullptr;
   long long graph_replays = 0;
+  // previous iterate of the finest level's last sweep, when that sweep was
+  // FP64 without a folded coarse correction (A~ z from the sweep identity)
+  const double* top_prev = nullptr;
 };
 
 namespace {
@@ -244,6 +247,8 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "coarse_mode must be 0 or 1");
   if (!(o.stall_ratio > 0.0) || o.stall_steps < 1)
     return set_err(h, PITMG_ERR_INVALID, "stall_ratio must be > 0 and stall_steps >= 1");
+  if (o.apply_from_sweep != 0 && o.apply_from_sweep != 1)
+    return set_err(h, PITMG_ERR_INVALID, "apply_from_sweep must be 0 or 1");
   if (o.vcycle_graph != 0 && o.vcycle_graph != 1)
     return set_err(h, PITMG_ERR_INVALID, "vcycle_graph must be 0 or 1");
   if (o.vcycle_graph && h && h->stream == nullptr)
@@ -487,6 +492,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   const pitmg_options& o = h->opt;
   const int var = o.transfer_variant;
   LevelView v = view(h, l);
+  if (l == 0) h->top_prev = nullptr;
   if (l == h->L - 1) return coarse_dispatch(h, b, out);
   LevelBuf& B = h->lv[l];
   LevelBuf& C = h->lv[l + 1];
@@ -536,6 +542,8 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
     const double* ec = s == 0 ? C.out : nullptr;
     rc = timed_kernel(h, 1, [&] { return launch_jacobi(v, b, yo, ec, var, dst, h->stream); });
     if (rc) return rc;
+    if (l == 0 && s == o.nu_post - 1 && ec == nullptr && !v.fp32 && yo != nullptr)
+      h->top_prev = yo;
     ycur = dst;
   }
   return PITMG_OK;
@@ -727,10 +735,17 @@ struct FgmresRun {
           break;
         case kStepA:
           if ((rc = vcycle_top(h, Vp(j), Zp(j)))) return rc;
-          if ((rc = timed(h, 2, [&] {
-                 return launch_apply(v0, Zp(j), nullptr, 1.0, 0.0, h->w, h->stream);
-               })))
+          if (h->opt.apply_from_sweep && h->top_prev) {
+            if ((rc = timed(h, 2, [&] {
+                   return launch_apply_identity(h->p, h->q, h->n, Vp(j), h->top_prev, Zp(j),
+                                                h->w, h->stream);
+                 })))
+              return rc;
+          } else if ((rc = timed(h, 2, [&] {
+                        return launch_apply(v0, Zp(j), nullptr, 1.0, 0.0, h->w, h->stream);
+                      }))) {
             return rc;
+          }
           plain = h->last_plain;
           if (plain)
             HIPCHK(h, hipMemcpyAsync(h->its_pinned, h->last_its_slot, sizeof(int),
@@ -948,6 +963,8 @@ void pitmg_default_options(pitmg_options* o) {
   o->coarse_mode = 0;
   o->stall_ratio = 0.9;
   o->stall_steps = 2;
+  o->vcycle_graph = 0;
+  o->apply_from_sweep = 1;
 }
 
 int pitmg_autotune(pitmg_handle* h, int* cfg) {

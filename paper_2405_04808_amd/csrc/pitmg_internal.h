@@ -180,6 +180,11 @@ hipError_t launch_scale(double* dst, const double* src, double alpha,
 hipError_t launch_axpby(double* y, const double* x, double a, double b,
                         long long len, hipStream_t s);   // y = a*x + b*y
 
+// w = A~ z from the last sweep z = D^{-1}(b - (L+L^T) yprev) of a cycle:
+// w = b - (L+L^T)(yprev - z) (nonzero corrections in the u and mu slots only).
+hipError_t launch_apply_identity(int p, int q, int n, const double* b, const double* yprev,
+                                 const double* z, double* w, hipStream_t s);
+
 // ---- small blocks (pitmg_small.hip): one thread per time step -------------
 bool small_supported(int p, int q);
 hipError_t launch_jacobi_small(const LevelView& L, const double* b, const double* yold,

@@ -377,6 +377,40 @@ static inline int grid_for(long long len, int nt) {
   return (int)g;
 }
 
+// ---------------------------------------------------------------------------
+// A~ z after a sweep.  When z = D^{-1}(b - (L+L^T) yprev) was the last sweep
+// of a cycle, A~ z = D z + (L+L^T) z = b - (L+L^T)(yprev - z).  The only
+// couplings are +I between u_k and mu_k, so the result is b except in the u
+// and mu slots: w_u = b_u - (yprev_mu - z_mu), w_mu = b_mu - (yprev_u - z_u).
+// ---------------------------------------------------------------------------
+
+__global__ void k_apply_identity(int p, int q, int n, const double* __restrict__ b,
+                                 const double* __restrict__ yprev,
+                                 const double* __restrict__ z, double* __restrict__ w) {
+  const TypeMajor T(p, q, n);
+  const long long np = (long long)n * p;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < T.len;
+       e += (long long)gridDim.x * blockDim.x) {
+    double v = b[e];
+    if (e < np) {
+      v -= yprev[T.m + e] - z[T.m + e];
+    } else if (e >= T.m) {
+      const long long i = e - T.m;
+      v -= yprev[T.u + i] - z[T.u + i];
+    }
+    w[e] = v;
+  }
+}
+
+hipError_t launch_apply_identity(int p, int q, int n, const double* b, const double* yprev,
+                                 const double* z, double* w, hipStream_t s) {
+  const TypeMajor T(p, q, n);
+  hipLaunchKernelGGL(k_apply_identity, dim3(grid_for(T.len, 256)), dim3(256), 0, s, p, q, n, b,
+                     yprev, z, w);
+  return hipGetLastError();
+}
+
+
 hipError_t launch_restrict_delta(int p, int q, int nf, const double* yprev, const double* y,
                                  int variant, double* bc, hipStream_t s) {
   const TypeMajor Tc(p, q, nf / 2);

@@ -296,3 +296,24 @@ def test_full_burgers128_operator_and_sweep():
     assert abs(true - st["relres_true"]) <= 1e-8 * true
     assert st["iters"] == 4
     s.close()
+
+
+@pytest.mark.parametrize("name", ["vdp64", "burgers_p12", "burgers_p64", "burgers_p150"])
+@pytest.mark.parametrize("nu_post", [1, 2, 3])
+def test_fgmres_apply_from_sweep_matches_explicit_apply(name, nu_post):
+    # A~ z formed from the last sweep (b - (L+L^T)(y - z)) agrees with the
+    # explicit product to rounding: both solves reach 1e-10 against the
+    # oracle's operator and their step counts differ by at most one
+    prob, rng, b, s = setup_case(name, restart=400, maxit=400, nu_post=nu_post)
+    lv = prob.levels[0]
+    A = OracleLevel(lv.N, lv.V, lv.Z).A
+    res = {}
+    for flag in (0, 1):
+        s.set_options(restart=400, maxit=400, nu_post=nu_post, apply_from_sweep=flag)
+        x, st, rc = s.solve(dev(b), tol=1e-10)
+        x = host(x)
+        assert rc == pm.PITMG_OK
+        assert np.linalg.norm(b - A @ x) <= 1.01e-10 * np.linalg.norm(b), (flag, name)
+        res[flag] = (x, st["iters"])
+    assert abs(res[0][1] - res[1][1]) <= 1
+    s.close()
