@@ -207,10 +207,16 @@ int pitmg_autotune(pitmg_handle* h, int* cfg);
  * mix of a profiled run.  A shape the level cannot use is an error. */
 int pitmg_set_sweep_shapes(pitmg_handle* h, const int* cfg);
 
-/* Kernel timing: while enabled, the library brackets every launch with HIP
- * events on its stream and accumulates per-kernel-class time.  Classes:
- * 0 factor, 1 jacobi, 2 apply, 3 transfer, 4 coarse, 5 krylov. */
+/* Kernel timing: on = 1 brackets every launch with HIP events on the
+ * handle's stream and accumulates per-kernel-class time; on = 2 times only
+ * the block Jacobi sweep (class 1), whose kernels record their own start and
+ * end, and leaves every other launch unbracketed; 0 turns timing off.
+ * Classes: 0 factor, 1 jacobi, 2 apply, 3 transfer, 4 coarse, 5 krylov. */
 int pitmg_profile_enable(pitmg_handle* h, int on);
+/* Time the sweeps of every `every`-th finest-level V-cycle only (default 1):
+ * every V-cycle launches the same sweeps, so a sample gives the same average
+ * launch duration at a fraction of the event cost. */
+int pitmg_profile_sample(pitmg_handle* h, int every);
 int pitmg_profile_read(pitmg_handle* h, int cls, int* launches, double* ms,
                        double* bytes);
 int pitmg_profile_reset(pitmg_handle* h);

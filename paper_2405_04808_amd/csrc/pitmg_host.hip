@@ -86,7 +86,9 @@ struct pitmg_handle {
   int fail_code = INT_MAX;
   long long dev_bytes = 0;
   std::string err;
-  bool prof = false;
+  int prof = 0;                      // 0 off, 1 every launch, 2 the sweep only
+  int prof_every = 1;                // time the sweeps of every n-th V-cycle
+  long long vcycles = 0;             // finest-level V-cycles run
   std::vector<ProfRec> pending;
   std::vector<hipEvent_t> pool;
   int prof_launches[kNumClasses] = {0};
@@ -152,6 +154,23 @@ hipEvent_t take_event(pitmg_handle* h) {
   return e;
 }
 
+// Accumulate the elapsed time of the recorded launches that have already
+// finished (in order), without waiting: called while the device is busy.
+void drain_ready(pitmg_handle* h) {
+  size_t done = 0;
+  for (; done < h->pending.size(); ++done) {
+    const ProfRec& r = h->pending[done];
+    if (hipEventQuery(r.b) != hipSuccess) break;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    h->prof_ms[r.cls] += ms;
+    h->prof_launches[r.cls] += 1;
+    h->pool.push_back(r.a);
+    h->pool.push_back(r.b);
+  }
+  h->pending.erase(h->pending.begin(), h->pending.begin() + done);
+}
+
 // Accumulate the elapsed time of every recorded launch (waits for them).
 void drain(pitmg_handle* h) {
   for (auto& r : h->pending) {
@@ -168,7 +187,7 @@ void drain(pitmg_handle* h) {
 
 template <class F>
 int timed(pitmg_handle* h, int cls, F&& launch) {
-  if (!h->prof) {
+  if (h->prof != 1) {            // level 2 times the sweep only
     HIPCHK(h, launch());
     return PITMG_OK;
   }
@@ -177,7 +196,10 @@ int timed(pitmg_handle* h, int cls, F&& launch) {
   HIPCHK(h, launch());
   HIPCHK(h, hipEventRecord(r.b, h->stream));
   h->pending.push_back(r);
-  if (h->pending.size() > 4096) drain(h);
+  if (h->pending.size() > 4096) {
+    drain_ready(h);
+    if (h->pending.size() > 16384) drain(h);   // bound the records in flight
+  }
   return PITMG_OK;
 }
 
@@ -185,7 +207,7 @@ int timed(pitmg_handle* h, int cls, F&& launch) {
 // dispatches record the start and end times.
 template <class F>
 int timed_kernel(pitmg_handle* h, int cls, F&& launch) {
-  if (!h->prof) {
+  if (!h->prof || (h->prof_every > 1 && (h->vcycles - 1) % h->prof_every != 0)) {
     HIPCHK(h, launch());
     return PITMG_OK;
   }
@@ -205,7 +227,10 @@ int timed_kernel(pitmg_handle* h, int cls, F&& launch) {
     return set_err(h, PITMG_ERR_HIP, "profiling: the launcher issued no timed kernel");
   }
   h->pending.push_back(r);
-  if (h->pending.size() > 4096) drain(h);
+  if (h->pending.size() > 4096) {
+    drain_ready(h);
+    if (h->pending.size() > 16384) drain(h);   // bound the records in flight
+  }
   return PITMG_OK;
 }
 
@@ -465,6 +490,7 @@ int capture_vcycle(pitmg_handle* h) {
 // MG_0(r) -> e, eagerly or by replaying the captured cycle.
 int vcycle_top(pitmg_handle* h, const double* r, double* e) {
   const pitmg_options& o = h->opt;
+  h->vcycles++;
   const bool graph = o.vcycle_graph && h->stream != nullptr && !h->prof && o.nu_post > 0 &&
                      o.coarse_mode == 0 && h->pair_count >= h->pair_cap;
   if (!graph) return vcycle_level(h, 0, r, e);
@@ -940,8 +966,8 @@ int run_to_end(FgmresRun& run) {
     const int rc = run.advance();
     if (rc < 0) return rc;
     if (rc == FgmresRun::kFinished) return run.status;
+    if (run.h->prof) drain_ready(run.h);   // host work while the device is busy
     HIPCHK(run.h, hipStreamSynchronize(run.h->stream));
-    if (run.h->prof) drain(run.h);
   }
 }
 
@@ -1290,6 +1316,8 @@ int pitmg_fgmres_solve_batch(pitmg_handle* const* hs, int count, const double* c
       }
     }
     // ... then wait for each, while the others' work is in flight
+    for (int i = 0; i < count; ++i)
+      if (live[i] && waiting[i] && hs[i]->prof) drain_ready(hs[i]);
     for (int i = 0; i < count; ++i) {
       if (!live[i] || !waiting[i]) continue;
       const hipError_t e = hipStreamSynchronize(hs[i]->stream);
@@ -1300,7 +1328,6 @@ int pitmg_fgmres_solve_batch(pitmg_handle* const* hs, int count, const double* c
         --active;
         continue;
       }
-      if (hs[i]->prof) drain(hs[i]);
     }
   }
   int worst = PITMG_OK;
@@ -1315,8 +1342,15 @@ int pitmg_fgmres_solve_batch(pitmg_handle* const* hs, int count, const double* c
 
 int pitmg_profile_enable(pitmg_handle* h, int on) {
   if (!h) return PITMG_ERR_INVALID;
-  if (!on && h->prof) drain(h);
-  h->prof = on != 0;
+  if (on < 0 || on > 2) return set_err(h, PITMG_ERR_INVALID, "profiling level must be 0, 1 or 2");
+  if (h->prof) drain(h);
+  h->prof = on;
+  return PITMG_OK;
+}
+
+int pitmg_profile_sample(pitmg_handle* h, int every) {
+  if (!h || every < 1) return PITMG_ERR_INVALID;
+  h->prof_every = every;
   return PITMG_OK;
 }
 

@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "pitmg_profile_enable": (i, [vp, i]),
         "pitmg_profile_read": (i, [vp, i, C.POINTER(i), C.POINTER(d), C.POINTER(d)]),
         "pitmg_profile_reset": (i, [vp]),
+        "pitmg_profile_sample": (i, [vp, i]),
         "pitmg_failed_block": (i, [vp, C.POINTER(i), C.POINTER(i)]),
         "pitmg_device_bytes": (C.c_longlong, [vp]),
         "pitmg_net_param_count": (C.c_longlong, [i, i]),
@@ -285,8 +286,14 @@ class Solver:
         return x, st.as_dict(), rc
 
     # -- profiling --------------------------------------------------------------
-    def profile(self, on: bool = True):
-        self._check(self.lib.pitmg_profile_enable(self.h, 1 if on else 0))
+    def profile(self, on=True):
+        """True / 1: time every launch; 2: the block Jacobi sweep only; False / 0: off."""
+        level = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        self._check(self.lib.pitmg_profile_enable(self.h, level))
+
+    def profile_sample(self, every: int):
+        """Time the sweeps of every `every`-th V-cycle only."""
+        self._check(self.lib.pitmg_profile_sample(self.h, int(every)))
 
     def profile_reset(self):
         self._check(self.lib.pitmg_profile_reset(self.h))
