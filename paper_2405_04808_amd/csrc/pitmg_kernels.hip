@@ -33,6 +33,71 @@ namespace pitmg {
 
 constexpr int kFactorThreads = 256;
 
+// S = X X^T with X = [N_k | Z_k] (p x (p+q)) on the matrix cores: one
+// work-group per block, each wave accumulating 16x16 tiles of the lower
+// triangle with v_mfma_f64_16x16x4f64 (v_mfma_f32_16x16x4f32 for FP32).
+// Lane l supplies X[I0 + l%16][k0 + l/16] as the A operand and
+// X[J0 + l%16][k0 + l/16] as the B operand (B = X^T).  Element i of lane l's
+// result is S[I0 + row(l/16, i)][J0 + l%16], with row = l/16 + 4i for the
+// FP64 instruction and 4(l/16) + i for the FP32 one (the layouts of the two
+// instructions differ).  Rows beyond p and columns beyond p+q read as zero.
+// S goes to the factor buffer (lower triangle; the factorisation kernel
+// reads it from there).
+template <class T>
+struct Mfma4;
+template <>
+struct Mfma4<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 step(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int group, int i) { return group + 4 * i; }
+};
+template <>
+struct Mfma4<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 step(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int group, int i) { return 4 * group + i; }
+};
+
+template <class T>
+__global__ __launch_bounds__(kFactorThreads) void k_syrk_mfma(LevelView L, T* Gi) {
+  const int p = L.p, q = L.q, K = p + q;
+  const int k = blockIdx.x;
+  const T* __restrict__ Nk = Mats<T>::N(L) + (long long)k * L.sN;
+  const T* __restrict__ Zk = Mats<T>::Z(L) + (long long)k * L.sZ;
+  T* S = Gi + (long long)k * p * p;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int r = lane & 15, kq = lane >> 4;
+  const int nt = (p + 15) / 16;
+  auto x = [&](int row, int col) -> T {
+    if (row >= p || col >= K) return T(0);
+    return col < p ? Nk[(long long)row * p + col] : Zk[(long long)row * q + (col - p)];
+  };
+  // tiles (I, J) with J <= I, numbered row by row
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int t = w; t < ntiles; t += kFactorThreads / kWave) {
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    const int I0 = 16 * I, J0 = 16 * J;
+    typename Mfma4<T>::v4 acc = {0, 0, 0, 0};
+#pragma unroll 8
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const T a = x(I0 + r, k0 + kq);
+      const T b = x(J0 + r, k0 + kq);
+      acc = Mfma4<T>::step(a, b, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = I0 + Mfma4<T>::row(kq, i), col = J0 + r;
+      if (row < p && col <= row) S[(long long)row * p + col] = acc[i];
+    }
+  }
+}
+
 template <class T, bool USE_LDS>
 __global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, T* Gi,
                                                            int level, int* fail) {
@@ -48,18 +113,14 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, T* Gi,
   T* S = USE_LDS ? smem : Gk;
   T* tmp = USE_LDS ? smem + (size_t)p * ld : smem;
 
-  // S = N N^T + Z Z^T (lower triangle)
-  for (int idx = tid; idx < p * p; idx += kFactorThreads) {
-    const int i = idx / p, j = idx % p;
-    if (j > i) continue;
-    T acc = 0;
-    const T* Ni = Nk + (long long)i * p;
-    const T* Nj = Nk + (long long)j * p;
-    for (int m = 0; m < p; ++m) acc += Ni[m] * Nj[m];
-    const T* Zi = Zk + (long long)i * q;
-    const T* Zj = Zk + (long long)j * q;
-    for (int m = 0; m < q; ++m) acc += Zi[m] * Zj[m];
-    S[(long long)i * ld + j] = acc;
+  // S = N N^T + Z Z^T (lower triangle) was formed by k_syrk_mfma in Gk
+  (void)Nk;
+  (void)Zk;
+  if (USE_LDS) {
+    for (int idx = tid; idx < p * p; idx += kFactorThreads) {
+      const int i = idx / p, j = idx % p;
+      if (j <= i) S[(long long)i * ld + j] = Gk[idx];
+    }
   }
   // Cholesky, right-looking, column by column
   for (int j = 0; j < p; ++j) {
@@ -113,6 +174,7 @@ static size_t factor_lds(int p) {
 
 template <class T>
 static hipError_t launch_factor_t(const LevelView& L, T* Gi, int level, int* fail, hipStream_t s) {
+  hipLaunchKernelGGL(k_syrk_mfma<T>, dim3(L.n), dim3(kFactorThreads), 0, s, L, Gi);
   const size_t lds = factor_lds<T>(L.p);
   if (L.p <= 128) {
     hipError_t e = hipFuncSetAttribute((const void*)k_factor<T, true>,
