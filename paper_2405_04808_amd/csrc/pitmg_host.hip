@@ -255,6 +255,10 @@ LevelView view(const pitmg_handle* h, int l) {
     v.Gi32 = b.Gi32;
   }
   v.sweep_cfg = b.sweep_cfg;
+  // the coarsest level's block solves (inside the coarse SGS) take one step
+  // per work-group: at 8 steps the one-step kernel has the shorter latency
+  if (l == h->L - 1 && v.sweep_cfg == 0 && jacobi_tiled_supported(h->p, h->q))
+    v.sweep_cfg = -1;
   return v;
 }
 

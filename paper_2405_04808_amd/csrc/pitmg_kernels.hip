@@ -535,7 +535,11 @@ __device__ __forceinline__ void slice_of(long long len, long long& e0, long long
 constexpr int kSliceLen = 1024;
 constexpr int kPerLane = kSliceLen / kWave;
 
-__global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__ basis, int nb,
+// The dot pass runs 8 waves per slice: every wave holds the slice of x1 and
+// x2, and the waves share out the basis vectors.
+constexpr int kDotThreads = 512;
+
+__global__ __launch_bounds__(kDotThreads) void k_dots(const double* __restrict__ basis, int nb,
                                                       const double* __restrict__ x1,
                                                       const double* __restrict__ x2,
                                                       long long len,
@@ -555,7 +559,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__
     a[t] = e < len ? x1[e] : 0.0;
     c[t] = (two && e < len) ? x2[e] : 0.0;
   }
-  for (int i = i0 + wv; i < i1; i += kVecThreads / kWave) {
+  for (int i = i0 + wv; i < i1; i += kDotThreads / kWave) {
     const double* __restrict__ bi = basis + (size_t)i * len;
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -820,7 +824,7 @@ int krylov_groups(long long len, int nb) {
 hipError_t launch_dots(const double* basis, int nb, const double* x1, const double* x2,
                        long long len, double* partial, hipStream_t s) {
   const int ng = krylov_groups(len, nb);
-  hipLaunchKernelGGL(k_dots, dim3(krylov_slices(len), ng), dim3(kVecThreads), 0, s, basis, nb,
+  hipLaunchKernelGGL(k_dots, dim3(krylov_slices(len), ng), dim3(kDotThreads), 0, s, basis, nb,
                      x1, x2, len, partial);
   return hipGetLastError();
 }
