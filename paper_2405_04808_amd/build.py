@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpitmg.so")
 SOURCES = ["pitmg_kernels.hip", "pitmg_jacobi_tiled.hip", "pitmg_coarse.hip",
-           "pitmg_small.hip", "pitmg_net.hip", "pitmg_host.hip"]
+           "pitmg_small.hip", "pitmg_split.hip", "pitmg_net.hip", "pitmg_host.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -19,6 +19,8 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+# plain library GEMMs of the split sweep (shared V, Z~ products over all steps)
+LINK_FLAGS = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def hipcc_path() -> str:
@@ -32,7 +34,7 @@ def build_library(verbose: bool = False) -> str:
     """Compile every HIP source into paper_2405_04808_amd/libpitmg.so."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc_path()] + HIPCC_FLAGS + ["-o", tmp] + srcs
+    cmd = [hipcc_path()] + HIPCC_FLAGS + ["-o", tmp] + srcs + LINK_FLAGS
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -39,6 +39,8 @@ struct LevelBuf {
   float* Z32 = nullptr;
   float* Gi32 = nullptr;
   int sweep_cfg = 0;                 // tuned sweep launch shape (LevelView)
+  bool split = false;                // split sweep buffers allocated
+  SplitBuffers sp;
 };
 
 struct ProfRec {
@@ -110,6 +112,7 @@ struct pitmg_handle {
   int g_K = 0;                       // coarse steps enqueued in the capture
   int* g_its_slot = nullptr;
   long long graph_replays = 0;
+  void* blas = nullptr;              // rocBLAS handle of the split sweeps
   // previous iterate of the finest level's last sweep, when that sweep was
   // FP64 without a folded coarse correction (A~ z from the sweep identity)
   const double* top_prev = nullptr;
@@ -255,6 +258,7 @@ LevelView view(const pitmg_handle* h, int l) {
     v.Gi32 = b.Gi32;
   }
   v.sweep_cfg = b.sweep_cfg;
+  if (b.split) v.split = &b.sp;
   // the coarsest level's block solves (inside the coarse SGS) take one step
   // per work-group: at 8 steps the one-step kernel has the shorter latency
   if (l == h->L - 1 && v.sweep_cfg == 0 && jacobi_tiled_supported(h->p, h->q))
@@ -496,7 +500,7 @@ int vcycle_top(pitmg_handle* h, const double* r, double* e) {
   const pitmg_options& o = h->opt;
   h->vcycles++;
   const bool graph = o.vcycle_graph && h->stream != nullptr && !h->prof && o.nu_post > 0 &&
-                     o.coarse_mode == 0 && h->pair_count >= h->pair_cap;
+                     o.coarse_mode == 0 && h->pair_count >= h->pair_cap && !h->blas;
   if (!graph) return vcycle_level(h, 0, r, e);
   const long long len = h->lv[0].len;
   int rc;
@@ -1153,6 +1157,26 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
       if ((rc = dalloc(h, (void**)&b.y0, b.len * 8))) return fail(rc);
       if ((rc = dalloc(h, (void**)&b.y1, b.len * 8))) return fail(rc);
     }
+    // split sweep for large blocks whose V and Z~ are shared by every step
+    if ((h->p == 256 || h->p == 512) && pb->V_stride == 0 && pb->Z_stride == 0) {
+      if (!h->blas) {
+        const hipError_t e = split_blas_create(&h->blas, h->stream);
+        if (e != hipSuccess)
+          return fail(set_err(h, PITMG_ERR_HIP, "rocBLAS handle could not be created"));
+      }
+      const long long pn = (long long)h->p * b.n, qn = (long long)h->q * b.n;
+      if ((rc = dalloc(h, (void**)&b.sp.Rm, (pn + h->p) * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.sp.U, pn * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.sp.Wz, qn * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.sp.Wv, pn * 8))) return fail(rc);
+      if (b.fp32) {
+        float** f32[6] = {&b.sp.Rm32, &b.sp.U32, &b.sp.L32, &b.sp.Wv32, &b.sp.Rz32, &b.sp.Wz32};
+        for (int i = 0; i < 6; ++i)
+          if ((rc = dalloc(h, (void**)f32[i], (i < 4 ? pn : qn) * 4))) return fail(rc);
+      }
+      b.sp.blas = h->blas;
+      b.split = true;
+    }
   }
   const long long len = h->lv[0].len;
   const int m = h->restart_cap;
@@ -1416,6 +1440,12 @@ void pitmg_destroy(pitmg_handle* h) {
   hipFree(h->g_in);
   hipFree(h->g_out);
   hipFree(h->upd);
+  for (auto& b : h->lv) {
+    void* sp[] = {b.sp.Rm, b.sp.U, b.sp.Wz, b.sp.Wv, b.sp.Rm32, b.sp.Rz32,
+                  b.sp.U32, b.sp.L32, b.sp.Wz32, b.sp.Wv32};
+    for (void* ptr : sp) hipFree(ptr);
+  }
+  split_blas_destroy(h->blas);
   for (auto e : h->pool) hipEventDestroy(e);
   for (auto& b : h->lv) {
     hipFree(b.N_own);

@@ -10,6 +10,17 @@ namespace pitmg {
 
 constexpr int kWave = 64;
 
+// Work buffers of the split sweep for large blocks (pitmg_split.hip): the
+// coupled right-hand sides R_mu [n+1][p], U = Z~ R_z - V R_mu [n][p],
+// W_z = Z~^T Lambda [n][q], W_v = V^T Lambda [n][p] (column-major, FP64), their
+// FP32 counterparts for an FP32 level, and the rocBLAS handle.
+struct SplitBuffers {
+  void* blas = nullptr;
+  double *Rm = nullptr, *U = nullptr, *Wz = nullptr, *Wv = nullptr;
+  float *Rm32 = nullptr, *Rz32 = nullptr, *U32 = nullptr, *L32 = nullptr, *Wz32 = nullptr,
+        *Wv32 = nullptr;
+};
+
 // One level of the hierarchy as the kernels see it.
 struct LevelView {
   int n;                       // steps on this level
@@ -28,6 +39,9 @@ struct LevelView {
   // sweep launch shape: 0 built-in rule, k >= 1 steps per work-group of the
   // shared-block kernel, -1 the one-step kernel
   int sweep_cfg = 0;
+  // host-side: split-sweep buffers of this level, or NULL (never read on the
+  // device)
+  const SplitBuffers* split = nullptr;
 };
 
 // Block pointers of a level in the arithmetic of the smoother.
@@ -184,6 +198,13 @@ hipError_t launch_axpby(double* y, const double* x, double a, double b,
 // w = b - (L+L^T)(yprev - z) (nonzero corrections in the u and mu slots only).
 hipError_t launch_apply_identity(int p, int q, int n, const double* b, const double* yprev,
                                  const double* z, double* w, hipStream_t s);
+
+// ---- large blocks with shared V, Z~ (pitmg_split.hip) ----------------------
+bool split_supported(const LevelView& L);
+hipError_t launch_jacobi_split(const LevelView& L, const double* b, const double* yold,
+                               const double* ecoarse, int variant, double* ynew, hipStream_t s);
+hipError_t split_blas_create(void** blas, hipStream_t s);
+void split_blas_destroy(void* blas);
 
 // ---- small blocks (pitmg_small.hip): one thread per time step -------------
 bool small_supported(int p, int q);

@@ -323,6 +323,8 @@ hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold
     return launch_jacobi_shared(L, b, yold, ecoarse, variant, ynew, s);
   if (al && jacobi_tiled_supported(L.p, L.q))
     return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, s);
+  if (al && split_supported(L))
+    return launch_jacobi_split(L, b, yold, ecoarse, variant, ynew, s);
   return L.fp32 ? launch_jacobi_generic<float>(L, b, yold, ecoarse, variant, ynew, s)
                 : launch_jacobi_generic<double>(L, b, yold, ecoarse, variant, ynew, s);
 }

@@ -30,6 +30,8 @@ CASES = {
     "burgers_p64": dict(kind="burgers", nx=64, nu=0.01, n=32, n_levels=3, seed=16),
     "burgers_p64_theta05": dict(kind="burgers", nx=64, nu=0.01, n=16, n_levels=2, seed=15,
                                 theta=0.5),
+    # split sweep (p = 256, shared V/Z~: products of all steps as GEMMs)
+    "burgers_p256": dict(kind="burgers", nx=256, nu=0.01, n=8, n_levels=2, seed=18),
 }
 
 
