@@ -123,6 +123,9 @@ typedef struct {
                                   y) on the finest level (nu_post >= 2), FGMRES
                                   forms A~ z as b - (L+L^T)(y - z), equal in
                                   exact arithmetic and free of block reads;
+                                  likewise the coarse GMRES forms A~ z of an
+                                  SGS result z = a + d (forward sweep a,
+                                  backward correction d) as v + L d;
                                   0: always the explicit product             */
 } pitmg_options;
 

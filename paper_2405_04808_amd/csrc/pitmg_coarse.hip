@@ -410,6 +410,22 @@ __global__ void k_add(double* __restrict__ z, const double* __restrict__ a,
     z[e] = a[e] + d[e];
 }
 
+// z = a + d and, from the same sweeps, w = A~ z without reading the blocks.
+// With (D + L) a = v (forward sweep) and (D + L^T) z = D a (backward sweep,
+// d = z - a), D z = v - L a - L^T z, so A~ z = (D + L + L^T) z = v + L d.
+// L is the identity from u_k into row mu_k (k = 1..n), hence w = v except
+// w_mu = v_mu + d_u.
+__global__ void k_add_identity(double* __restrict__ z, const double* __restrict__ a,
+                               const double* __restrict__ d, const double* __restrict__ v,
+                               double* __restrict__ w, long long mu0, long long len) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < len;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double de = d[e];
+    z[e] = a[e] + de;
+    w[e] = e >= mu0 ? v[e] + d[e - mu0] : v[e];
+  }
+}
+
 using FinishPol = GenericPolicy<512>;
 
 size_t finish_lds_doubles(int p, int q) {
@@ -482,6 +498,16 @@ hipError_t launch_add(double* z, const double* a, const double* d, long long len
   long long g = (len + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_add, dim3((unsigned)g), dim3(256), 0, s, z, a, d, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_identity(int p, int q, int n, double* z, const double* a, const double* d,
+                               const double* v, double* w, hipStream_t s) {
+  const TypeMajor T(p, q, n);
+  long long g = (T.len + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_add_identity, dim3((unsigned)g), dim3(256), 0, s, z, a, d, v, w, T.m,
+                     T.len);
   return hipGetLastError();
 }
 

@@ -164,6 +164,9 @@ hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, 
 hipError_t launch_gemv_tri(const double* M, int nc, int p, int upper, const double* x, double* y,
                            hipStream_t s);
 hipError_t launch_add(double* z, const double* a, const double* d, long long len, hipStream_t s);
+// z = a + d and w = v + L d (the coarse SGS result and its product with A~)
+hipError_t launch_add_identity(int p, int q, int n, double* z, const double* a, const double* d,
+                               const double* v, double* w, hipStream_t s);
 
 // Krylov helpers.  Basis vectors are rows of a [k][len] array.  Dot and
 // update kernels work on krylov_slices(len) slices of 1024 elements and store

@@ -537,9 +537,9 @@ __device__ __forceinline__ void slice_of(long long len, long long& e0, long long
 constexpr int kSliceLen = 1024;
 constexpr int kPerLane = kSliceLen / kWave;
 
-// The dot pass runs 8 waves per slice: every wave holds the slice of x1 and
+// The dot pass runs 4 waves per slice: every wave holds the slice of x1 and
 // x2, and the waves share out the basis vectors.
-constexpr int kDotThreads = 512;
+constexpr int kDotThreads = 256;
 
 __global__ __launch_bounds__(kDotThreads) void k_dots(const double* __restrict__ basis, int nb,
                                                       const double* __restrict__ x1,
@@ -550,8 +550,9 @@ __global__ __launch_bounds__(kDotThreads) void k_dots(const double* __restrict__
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const int nblk = gridDim.x;
   const bool two = x2 != nullptr;
-  // blockIdx.y: a contiguous group of basis vectors (short vectors with
-  // long bases would otherwise leave most of the device idle)
+  // blockIdx.y: a contiguous group of basis vectors (short-lived work-groups
+  // that drain evenly; for short vectors also enough of them to fill the
+  // device)
   const int per = (nb + gridDim.y - 1) / gridDim.y;
   const int i0 = blockIdx.y * per, i1 = min(nb, i0 + per);
   double a[kPerLane], c[kPerLane];
@@ -823,9 +824,19 @@ int krylov_groups(long long len, int nb) {
   return std::max(1, std::min(by_size, by_grid));
 }
 
+// Basis groups of the dot pass: at most kDotGroup vectors per work-group.
+// Each work-group then lives for a short stretch of the pass, so the grid
+// drains evenly instead of ending on a partial round of long-lived groups
+// (the slices of x1 and x2 are re-read per group, 2 / kDotGroup extra).
+constexpr int kDotGroup = 32;
+
+int dot_groups(long long len, int nb) {
+  return std::max(krylov_groups(len, nb), (nb + kDotGroup - 1) / kDotGroup);
+}
+
 hipError_t launch_dots(const double* basis, int nb, const double* x1, const double* x2,
                        long long len, double* partial, hipStream_t s) {
-  const int ng = krylov_groups(len, nb);
+  const int ng = dot_groups(len, nb);
   hipLaunchKernelGGL(k_dots, dim3(krylov_slices(len), ng), dim3(kDotThreads), 0, s, basis, nb,
                      x1, x2, len, partial);
   return hipGetLastError();

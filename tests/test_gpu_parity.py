@@ -128,8 +128,26 @@ def test_coarse_solve_tolerance_mode(name):
     s.close()
 
 
+def coarse_identity_tol(prob):
+    """Tolerance of a V-cycle whose coarse GMRES forms A~ z from its SGS sweeps.
+
+    The library takes A~ z = v + L d (forward sweep a, backward correction
+    d = z - a), exact in exact arithmetic.  In floating point it carries the
+    residual of the coarse block solves, which go through the Schur
+    complement S_k = N_k N_k^T + Z~_k Z~_k^T: about u cond(S_k) relative
+    (u = 2^-53), so the bound is 8 u max_k cond(S_k) on the coarsest level,
+    and never tighter than the 1e-10 of the explicit product.
+    """
+    lv = prob.levels[-1]
+    blk = lambda a, k: a[0] if a.shape[0] == 1 else a[k]
+    kappa = max(np.linalg.cond(lv.N[k] @ lv.N[k].T + blk(lv.Z, k) @ blk(lv.Z, k).T)
+                for k in range(lv.N.shape[0]))
+    return max(1e-10, 8 * 2.0 ** -53 * kappa)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("opt", [dict(coarse_fixed_its=2),
+                                 dict(coarse_fixed_its=2, apply_from_sweep=0),
                                  dict(coarse_fixed_its=2, nu_pre=1, nu_post=3),
                                  dict(coarse_fixed_its=1, nu_pre=0, nu_post=2),
                                  dict(coarse_fixed_its=1, nu_pre=2, nu_post=0),
@@ -140,7 +158,10 @@ def test_vcycle_fixed_coarse_steps(name, opt):
     r = rng.normal(size=prob.size)
     ref = H.vcycle(r)
     got = host(s.vcycle(dev(r)))
-    assert rel(got, ref) <= 1e-10, rel(got, ref)
+    # the explicit coarse product matches to 1e-10; the sweep identity to
+    # the conditioning bound of the coarse block solves
+    tol = 1e-10 if opt.get("apply_from_sweep", 1) == 0 else coarse_identity_tol(prob)
+    assert rel(got, ref) <= tol, (rel(got, ref), tol)
     s.close()
 
 
