@@ -1,8 +1,6 @@
 // Block Jacobi sweep for p = q in {64, 128}: one work-group of 512 threads
 // per time-major block, with N_k and G_k^{-1} in registers (pitmg_tiled.h),
-// so each Jacobian / factor entry is read from HBM once per sweep.  The
-// trivial block n+1 is done by the work-group of step n, so a level of n
-// steps is n work-groups (n = 256 fills the device in one round).
+// so each Jacobian / factor entry is read from HBM once per sweep.
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
 #include "pitmg_tiled.h"
@@ -35,13 +33,14 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
     return v;
   };
 
-  if (kb == n - 1) {                           // block n+1 = (v_n, mu_n), with step n
+  if (kb == n) {                               // block n+1 = (v_n, mu_n)
     for (int i = tid; i < P; i += kTiledThreads) {
       const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
       const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
       ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
       ynew[Tm.m + (long long)(n - 1) * P + i] = -rmm - rvv;
     }
+    return;
   }
   const int k = kb + 1;
   const bool hv = k >= 2;
@@ -82,10 +81,10 @@ static hipError_t launch_tiled_t(const LevelView& L, const double* b, const doub
                                  const double* ecoarse, int variant, double* ynew,
                                  hipStream_t s) {
   if (L.p == 128 && L.q == 128) {
-    return launch_k(k_jacobi_tiled<4, 8, T>, dim3(L.n), dim3(kTiledThreads), 0, s, L, b, yold,
+    return launch_k(k_jacobi_tiled<4, 8, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b, yold,
                     ecoarse, variant, ynew);
   } else if (L.p == 64 && L.q == 64) {
-    return launch_k(k_jacobi_tiled<2, 4, T>, dim3(L.n), dim3(kTiledThreads), 0, s, L, b, yold,
+    return launch_k(k_jacobi_tiled<2, 4, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b, yold,
                     ecoarse, variant, ynew);
   } else {
     return hipErrorInvalidValue;

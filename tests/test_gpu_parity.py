@@ -97,6 +97,39 @@ def test_jacobi_sweep_matches_oracle(name):
     s.close()
 
 
+SHARED_CASES = {
+    "p64_n32": dict(kind="burgers", nx=64, nu=0.01, n=32, n_levels=3, seed=21),
+    "p128_n24": dict(kind="burgers", nx=128, nu=0.01, n=24, n_levels=2, seed=22),
+}
+
+
+@pytest.mark.parametrize("name", list(SHARED_CASES))
+@pytest.mark.parametrize("per", [1, 2, 3, 4])
+def test_shared_sweep_steps_per_group(name, per):
+    """The shared-block sweep with 1..4 steps per work-group (the next
+    step's blocks in flight from the second step on; a ragged last group
+    when per does not divide n), against the oracle's block Jacobi sweep."""
+    prob, rng = make_problem(**SHARED_CASES[name])
+    s = pm.Solver(prob.levels, pm.default_options())
+    s.set_sweep_shapes([per] * (prob.n_levels - 1) + [0])
+    for lev, lv in enumerate(prob.levels[:-1]):
+        ol = OracleLevel(lv.N, lv.V, lv.Z)
+        m = ol.A.shape[0]
+        bb = rng.normal(size=m)
+        y = rng.normal(size=m)
+        yt = ol.jacobi(bb[ol.perm], y[ol.perm])
+        ref = np.empty_like(yt)
+        ref[ol.perm] = yt
+        got = host(s.jacobi_sweep(dev(bb), dev(y), level=lev))
+        assert rel(got, ref) <= 1e-11, (name, per, lev, rel(got, ref))
+        zt = ol.jacobi(bb[ol.perm], np.zeros(m))
+        ref0 = np.empty_like(zt)
+        ref0[ol.perm] = zt
+        got0 = host(s.jacobi_sweep(dev(bb), None, level=lev))
+        assert rel(got0, ref0) <= 1e-11, (name, per, lev, rel(got0, ref0))
+    s.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("fixed", [1, 3])
 def test_coarse_solve_fixed_steps(name, fixed):
