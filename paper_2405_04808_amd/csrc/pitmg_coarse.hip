@@ -386,7 +386,9 @@ __global__ __launch_bounds__(512) void k_propagators(int p, int nc, const double
 }
 
 // y = M x for a block-lower (upper = 0) or block-upper (upper = 1) matrix of
-// nc x nc blocks of p x p; one wave per row.
+// nc x nc blocks of p x p whose diagonal blocks are the identity (the
+// propagators): y_r = x_r + the off-diagonal blocks of row r times x.  One
+// wave per row, eight independent loads in flight per lane.
 __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ M, int nc, int p,
                                                   int upper, const double* __restrict__ x,
                                                   double* __restrict__ y) {
@@ -395,12 +397,21 @@ __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ M, 
   const int lane = threadIdx.x % kWave;
   if (r >= ld) return;
   const int s = (int)(r / p);
-  const long long c0 = upper ? (long long)s * p : 0;
-  const long long c1 = upper ? ld : (long long)(s + 1) * p;
-  double acc = 0.0;
-  for (long long c = c0 + lane; c < c1; c += kWave) acc += M[r * ld + c] * x[c];
+  const long long c0 = upper ? (long long)(s + 1) * p : 0;
+  const long long c1 = upper ? ld : (long long)s * p;
+  const double* __restrict__ Mr = M + r * ld;
+  double a[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) a[t] = 0.0;
+  long long c = c0 + lane;
+  for (; c + 7 * kWave < c1; c += 8 * kWave) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) a[t] += Mr[c + t * kWave] * x[c + t * kWave];
+  }
+  for (; c < c1; c += kWave) a[0] += Mr[c] * x[c];
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   acc = wave_sum(acc);
-  if (lane == 0) y[r] = acc;
+  if (lane == 0) y[r] = x[r] + acc;
 }
 
 __global__ void k_add(double* __restrict__ z, const double* __restrict__ a,
