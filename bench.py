@@ -47,7 +47,7 @@ WORKLOADS = {
 }
 
 
-def sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8):
+def sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8, with_restrict=False):
     """Algorithmic HBM bytes of one block Jacobi sweep on a level of n steps.
 
     Per time-step block: N_k (p*p), V_k (p*p, unless shared), Z~_k (p*q,
@@ -55,13 +55,18 @@ def sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8):
     mat_bytes per entry; the right-hand side block (4p+q) read and the new
     iterate block (4p+q) written, and the two coupling values u_{k-1}, mu_k of
     the previous iterate (2p; doubled when the interpolated coarse correction
-    is folded in), FP64.  Shared blocks count once per launch.
+    is folded in), FP64.  Shared blocks count once per launch.  With the
+    restriction fused into the sweep (the last pre-smoothing sweep), per
+    coarse step also u and mu of the previous iterate at the injected fine
+    step (2p) read and the coarse block (4p+q) written.
     """
     mats = p * p + (0 if shared_V else p * p) + (0 if shared_Z else p * q) + p * (p + 1) // 2
     vecs = 2 * (4 * p + q) + 2 * p
     total = n * (mats * mat_bytes + vecs * 8) + (2 * p + 2 * p) * 8        # block n+1
     if with_coarse:
         total += n * 2 * p * 8                                # coarse coupling values
+    if with_restrict:
+        total += (n // 2) * (2 * p + 4 * p + q) * 8           # fused restriction
     total += ((p * p if shared_V else 0) + (p * q if shared_Z else 0)) * mat_bytes
     return float(total)
 
@@ -75,11 +80,16 @@ def vcycle_bytes(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, mat_bytes=8, f
     tot = 0.0
     for lev in range(L - 1):
         nl = n >> lev
+        # the restriction rides on the last pre-smoothing sweep, except on the
+        # finest level when its residual is formed explicitly in FP64
+        fused = nu_pre > 0 and not (fp64_residual and lev == 0)
         for s_ in range(nu_pre):
-            tot += sweep_bytes(p, q, nl, shared_V, shared_Z, False, mat_bytes)
+            tot += sweep_bytes(p, q, nl, shared_V, shared_Z, False, mat_bytes,
+                               with_restrict=fused and s_ == nu_pre - 1)
         for s_ in range(nu_post):
             tot += sweep_bytes(p, q, nl, shared_V, shared_Z, s_ == 0, mat_bytes)
-        tot += 8.0 * (4 * p * nl + (4 * p + q) * (nl // 2))
+        if not fused:
+            tot += 8.0 * (4 * p * nl + (4 * p + q) * (nl // 2))
     nc = n >> (L - 1)
     tot += 8.0 * 2 * (4 * p + q) * nc
     if fp64_residual:
@@ -347,7 +357,8 @@ def main():
         for lev in range(L - 1):
             nl = n >> lev
             for sidx in range(opts.nu_pre):
-                per_vcycle += sweep_bytes(p, q, nl, shared_V, shared_Z, False)
+                per_vcycle += sweep_bytes(p, q, nl, shared_V, shared_Z, False,
+                                          with_restrict=sidx == opts.nu_pre - 1)
             for sidx in range(opts.nu_post):
                 per_vcycle += sweep_bytes(p, q, nl, shared_V, shared_Z, sidx == 0)
         launches, ms = prof["jacobi"]

@@ -540,15 +540,18 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   LevelBuf& B = h->lv[l];
   LevelBuf& C = h->lv[l + 1];
   double* bufs[2] = {B.y0, B.y1};
-  const double* yprev = nullptr;
   double* ycur = nullptr;
   int rc;
   for (int s = 0; s < o.nu_pre; ++s) {
     double* dst = bufs[s & 1];
     const double* yo = ycur;
-    rc = timed_kernel(h, 1, [&] { return launch_jacobi(v, b, yo, nullptr, var, dst, h->stream); });
+    // the last pre-smoothing sweep also restricts the residual it leaves,
+    // R (L+L^T)(y_prev - y), except where the finest residual is formed in FP64
+    double* rc_out = (s == o.nu_pre - 1 && !B.res) ? C.b : nullptr;
+    rc = timed_kernel(h, 1, [&] {
+      return launch_jacobi(v, b, yo, nullptr, var, dst, h->stream, rc_out);
+    });
     if (rc) return rc;
-    yprev = ycur;
     ycur = dst;
   }
   if (ycur == nullptr) {
@@ -562,10 +565,6 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
       rc = timed(h, 3, [&] {
         return launch_restrict(h->p, h->q, v.n, B.res, var, C.b, h->stream);
       });
-  } else {
-    rc = timed(h, 3, [&] {
-      return launch_restrict_delta(h->p, h->q, v.n, yprev, ycur, var, C.b, h->stream);
-    });
   }
   if (rc) return rc;
   rc = vcycle_level(h, l + 1, C.b, C.out);

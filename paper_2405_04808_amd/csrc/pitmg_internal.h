@@ -110,22 +110,27 @@ hipError_t launch_to_f32(float* dst, const double* src, long long count, hipStre
 // One block Jacobi sweep: ynew = D^{-1}(b - (L+L^T) yc) where the coupling
 // values yc are taken from yold (NULL = 0) plus, if ecoarse != NULL, the
 // interpolation of the coarse vector ecoarse (variant as in the options).
+// If restrict_out != NULL (only with ecoarse == NULL), also the restricted
+// residual R (L+L^T)(yold - ynew) of the next coarser level, as
+// launch_restrict_delta computes it: inside the sweep where the kernel
+// supports it, else by that kernel after the sweep.
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
                          const double* ecoarse, int variant, double* ynew,
-                         hipStream_t s);
+                         hipStream_t s, double* restrict_out = nullptr);
 
 // Register-tiled sweep for p == q in {64, 128} (16-byte aligned blocks); the
-// launchers follow L.fp32 for the arithmetic.
+// launchers follow L.fp32 for the arithmetic.  restrict_out as in
+// launch_jacobi (the restriction fused into the sweep).
 bool jacobi_tiled_supported(int p, int q);
 hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
                                const double* ecoarse, int variant, double* ynew,
-                               hipStream_t s);
+                               double* restrict_out, hipStream_t s);
 
 // Sweep for V and Z~ shared by every step (stride 0), p == q in {64, 128}.
 bool jacobi_shared_supported(const LevelView& L);
 hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* ynew,
-                                hipStream_t s);
+                                double* restrict_out, hipStream_t s);
 
 // out = beta*b + alpha*(A~ x) on one level (b may be NULL when beta == 0).
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b,

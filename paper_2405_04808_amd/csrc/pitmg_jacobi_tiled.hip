@@ -7,10 +7,35 @@
 
 namespace pitmg {
 
+// Restriction of the residual after the last pre-smoothing sweep, fused
+// into that sweep: r = (L+L^T)(y_old - y) is nonzero only in the u and mu
+// slots (r_u,k = mu_k^old - mu_k, r_mu,k = u_k^old - u_k), and the coarse
+// vector takes fine step kf = 2m-1 (variant 0) or 2m (variant 1) for coarse
+// step m.  The work-group that produces u_kf writes the coarse mu entry and
+// the zero v, z, lambda entries of m; the one that produces mu_kf (block
+// kf+1) writes the coarse u entry.  Same doubles as k_restrict_delta.
+struct FusedRestrict {
+  double* rc;                  // coarse vector, or NULL (no restriction)
+  int variant;
+  // coarse step m (1-based) whose mu, v, z, lambda block k writes, else 0
+  __device__ int mu_writer(int k) const {
+    if (!rc) return 0;
+    if (variant == 0) return (k & 1) ? (k + 1) / 2 : 0;
+    return (k & 1) ? 0 : k / 2;
+  }
+  // coarse step m whose u entry block k (producing mu_{k-1}) writes, else 0
+  __device__ int u_writer(int k) const {
+    if (!rc || k < 2) return 0;
+    const int kf = k - 1;
+    if (variant == 0) return (kf & 1) ? (kf + 1) / 2 : 0;
+    return (kf & 1) ? 0 : kf / 2;
+  }
+};
+
 template <int RT, int CT, class T>
 __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
     LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
-    const double* __restrict__ ec, int variant, double* __restrict__ ynew) {
+    const double* __restrict__ ec, int variant, double* __restrict__ ynew, FusedRestrict fr) {
   using TS = TiledSolve<RT, CT, T>;
   constexpr int P = TS::P;
   __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P];
@@ -34,11 +59,16 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   };
 
   if (kb == n) {                               // block n+1 = (v_n, mu_n)
+    const int mu_m = fr.u_writer(n + 1);
     for (int i = tid; i < P; i += kTiledThreads) {
       const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
       const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
+      const double mo = -rmm - rvv;
       ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
-      ynew[Tm.m + (long long)(n - 1) * P + i] = -rmm - rvv;
+      ynew[Tm.m + (long long)(n - 1) * P + i] = mo;
+      if (mu_m)
+        fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] =
+            (yold ? yold[Tm.m + (long long)(n - 1) * P + i] : 0.0) - mo;
     }
     return;
   }
@@ -63,13 +93,26 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   }
   __syncthreads();
   TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
+  const int rm_m = fr.mu_writer(k), ru_m = fr.u_writer(k);
   for (int i = tid; i < P; i += kTiledThreads) {
-    ynew[Tm.u + kk * P + i] = (double)TS::u_of(scr, sru, i);
+    const double uo = (double)TS::u_of(scr, sru, i);
+    ynew[Tm.u + kk * P + i] = uo;
     ynew[Tm.z + kk * P + i] = (double)TS::z_of(scr, srz, i);
     ynew[Tm.l + kk * P + i] = (double)slam[i];
     if (hv) {
-      ynew[Tm.m + (kk - 1) * P + i] = (double)TS::mu_of(scr, srm, srv, i);
+      const double mo = (double)TS::mu_of(scr, srm, srv, i);
+      ynew[Tm.m + (kk - 1) * P + i] = mo;
       ynew[Tm.v + (kk - 1) * P + i] = -(double)srm[i];
+      if (ru_m)
+        fr.rc[Tc.u + (long long)(ru_m - 1) * P + i] =
+            (yold ? yold[Tm.m + (kk - 1) * P + i] : 0.0) - mo;
+    }
+    if (rm_m) {
+      const long long o = (long long)(rm_m - 1) * P + i;
+      fr.rc[Tc.m + o] = (yold ? yold[Tm.u + kk * P + i] : 0.0) - uo;
+      fr.rc[Tc.v + o] = 0.0;
+      fr.rc[Tc.z + o] = 0.0;
+      fr.rc[Tc.l + o] = 0.0;
     }
   }
 }
@@ -79,13 +122,13 @@ bool jacobi_tiled_supported(int p, int q) { return p == q && (p == 128 || p == 6
 template <class T>
 static hipError_t launch_tiled_t(const LevelView& L, const double* b, const double* yold,
                                  const double* ecoarse, int variant, double* ynew,
-                                 hipStream_t s) {
+                                 FusedRestrict fr, hipStream_t s) {
   if (L.p == 128 && L.q == 128) {
     return launch_k(k_jacobi_tiled<4, 8, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b, yold,
-                    ecoarse, variant, ynew);
+                    ecoarse, variant, ynew, fr);
   } else if (L.p == 64 && L.q == 64) {
     return launch_k(k_jacobi_tiled<2, 4, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b, yold,
-                    ecoarse, variant, ynew);
+                    ecoarse, variant, ynew, fr);
   } else {
     return hipErrorInvalidValue;
   }
@@ -94,9 +137,10 @@ static hipError_t launch_tiled_t(const LevelView& L, const double* b, const doub
 
 hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
                                const double* ecoarse, int variant, double* ynew,
-                               hipStream_t s) {
-  return L.fp32 ? launch_tiled_t<float>(L, b, yold, ecoarse, variant, ynew, s)
-                : launch_tiled_t<double>(L, b, yold, ecoarse, variant, ynew, s);
+                               double* restrict_out, hipStream_t s) {
+  const FusedRestrict fr{restrict_out, variant};
+  return L.fp32 ? launch_tiled_t<float>(L, b, yold, ecoarse, variant, ynew, fr, s)
+                : launch_tiled_t<double>(L, b, yold, ecoarse, variant, ynew, fr, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -120,7 +164,8 @@ constexpr int kMaxSteps = 4;
 template <int RT, int CT, class T>
 __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
-    const double* __restrict__ ec, int variant, double* __restrict__ ynew, int per_wg) {
+    const double* __restrict__ ec, int variant, double* __restrict__ ynew, int per_wg,
+    FusedRestrict fr) {
   using TS = TiledSolve<RT, CT, T>;
   constexpr int P = TS::P;
   constexpr int G = kTiledThreads / P;                   // row groups of the post pass
@@ -170,11 +215,16 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     }
   }
   if (k0 + nb - 1 == n) {                                // block n+1 = (v_n, mu_n)
+    const int mu_m = fr.u_writer(n + 1);
     for (int i = tid; i < P; i += kTiledThreads) {
       const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
       const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
+      const double mo = -rmm - rvv;
       ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
-      ynew[Tm.m + (long long)(n - 1) * P + i] = -rmm - rvv;
+      ynew[Tm.m + (long long)(n - 1) * P + i] = mo;
+      if (mu_m)
+        fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] =
+            (yold ? yold[Tm.m + (long long)(n - 1) * P + i] : 0.0) - mo;
     }
   }
   __syncthreads();
@@ -267,9 +317,18 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     TS::col_partial(cacc, red);
     __syncthreads();
     if (bi + 1 < nb) TS::load_n(L, kk + 1, R);             // N of the next step
+    const int rm_m = fr.mu_writer((int)kk + 1);
     for (int i = tid; i < P; i += kTiledThreads) {
-      ynew[Tm.u + kk * P + i] = (double)(sru[bi][i] - TS::col_total(red, i));
+      const double uo = (double)(sru[bi][i] - TS::col_total(red, i));
+      ynew[Tm.u + kk * P + i] = uo;
       ynew[Tm.l + kk * P + i] = (double)slam[bi][i];
+      if (rm_m) {
+        const long long o = (long long)(rm_m - 1) * P + i;
+        fr.rc[Tc.m + o] = (yold ? yold[Tm.u + kk * P + i] : 0.0) - uo;
+        fr.rc[Tc.v + o] = 0.0;
+        fr.rc[Tc.z + o] = 0.0;
+        fr.rc[Tc.l + o] = 0.0;
+      }
     }
     __syncthreads();
   }
@@ -312,8 +371,13 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     }
     ynew[Tm.z + kk * P + i] = (double)(srz[s][i] - zt);
     if (kk >= 1) {
-      ynew[Tm.m + (kk - 1) * P + i] = (double)(vt - srm[s][i] - srv[s][i]);
+      const double mo = (double)(vt - srm[s][i] - srv[s][i]);
+      ynew[Tm.m + (kk - 1) * P + i] = mo;
       ynew[Tm.v + (kk - 1) * P + i] = -(double)srm[s][i];
+      const int ru_m = fr.u_writer((int)kk + 1);
+      if (ru_m)
+        fr.rc[Tc.u + (long long)(ru_m - 1) * P + i] =
+            (yold ? yold[Tm.m + (kk - 1) * P + i] : 0.0) - mo;
     }
   }
 }
@@ -325,14 +389,14 @@ bool jacobi_shared_supported(const LevelView& L) {
 template <class T>
 static hipError_t launch_shared_t(const LevelView& L, const double* b, const double* yold,
                                   const double* ecoarse, int variant, double* ynew, int per,
-                                  hipStream_t s) {
+                                  FusedRestrict fr, hipStream_t s) {
   const int nwg = (L.n + per - 1) / per;
   if (L.p == 128) {
     return launch_k(k_jacobi_shared<4, 8, T>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
-                    ecoarse, variant, ynew, per);
+                    ecoarse, variant, ynew, per, fr);
   } else if (L.p == 64) {
     return launch_k(k_jacobi_shared<2, 4, T>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
-                    ecoarse, variant, ynew, per);
+                    ecoarse, variant, ynew, per, fr);
   } else {
     return hipErrorInvalidValue;
   }
@@ -341,14 +405,15 @@ static hipError_t launch_shared_t(const LevelView& L, const double* b, const dou
 
 hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* ynew,
-                                hipStream_t s) {
+                                double* restrict_out, hipStream_t s) {
+  const FusedRestrict fr{restrict_out, variant};
   // steps per work-group: the tuned choice, else enough to keep the grid
   // near one work-group per CU
   int per = L.sweep_cfg > 0 ? L.sweep_cfg : (L.n + 255) / 256;
   if (per > kMaxSteps) per = kMaxSteps;
   if (per < 1) per = 1;
-  return L.fp32 ? launch_shared_t<float>(L, b, yold, ecoarse, variant, ynew, per, s)
-                : launch_shared_t<double>(L, b, yold, ecoarse, variant, ynew, per, s);
+  return L.fp32 ? launch_shared_t<float>(L, b, yold, ecoarse, variant, ynew, per, fr, s)
+                : launch_shared_t<double>(L, b, yold, ecoarse, variant, ynew, per, fr, s);
 }
 
 }  // namespace pitmg

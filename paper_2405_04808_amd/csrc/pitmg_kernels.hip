@@ -313,20 +313,27 @@ static hipError_t launch_jacobi_generic(const LevelView& L, const double* b, con
 }
 
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
-                         const double* ecoarse, int variant, double* ynew, hipStream_t s) {
-  if (small_supported(L.p, L.q))
-    return launch_jacobi_small(L, b, yold, ecoarse, variant, ynew, s);
+                         const double* ecoarse, int variant, double* ynew, hipStream_t s,
+                         double* restrict_out) {
+  if (restrict_out && ecoarse) return hipErrorInvalidValue;
   const bool al = L.fp32 ? aligned16(L.N32) && aligned16(L.V32) && aligned16(L.Z32) &&
                                aligned16(L.Gi32)
                          : aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi);
-  if (al && jacobi_shared_supported(L) && L.sweep_cfg >= 0)
-    return launch_jacobi_shared(L, b, yold, ecoarse, variant, ynew, s);
-  if (al && jacobi_tiled_supported(L.p, L.q))
-    return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, s);
-  if (al && split_supported(L))
-    return launch_jacobi_split(L, b, yold, ecoarse, variant, ynew, s);
-  return L.fp32 ? launch_jacobi_generic<float>(L, b, yold, ecoarse, variant, ynew, s)
-                : launch_jacobi_generic<double>(L, b, yold, ecoarse, variant, ynew, s);
+  const bool small = small_supported(L.p, L.q);
+  if (!small && al && jacobi_shared_supported(L) && L.sweep_cfg >= 0)
+    return launch_jacobi_shared(L, b, yold, ecoarse, variant, ynew, restrict_out, s);
+  if (!small && al && jacobi_tiled_supported(L.p, L.q))
+    return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, restrict_out, s);
+  hipError_t e;
+  if (small)
+    e = launch_jacobi_small(L, b, yold, ecoarse, variant, ynew, s);
+  else if (al && split_supported(L))
+    e = launch_jacobi_split(L, b, yold, ecoarse, variant, ynew, s);
+  else
+    e = L.fp32 ? launch_jacobi_generic<float>(L, b, yold, ecoarse, variant, ynew, s)
+               : launch_jacobi_generic<double>(L, b, yold, ecoarse, variant, ynew, s);
+  if (e != hipSuccess || !restrict_out) return e;
+  return launch_restrict_delta(L.p, L.q, L.n, yold, ynew, variant, restrict_out, s);
 }
 
 // ---------------------------------------------------------------------------
