@@ -34,7 +34,7 @@ template <int NT>
 struct GenericPolicy {
   static constexpr int kThreads = NT;
   struct Regs {};
-  __host__ __device__ static size_t scratch(int p, int q) { return (size_t)2 * p + NT; }
+  __host__ __device__ static size_t scratch(int p, int /*q*/) { return (size_t)2 * p + NT; }
   __device__ static void load(const LevelView&, long long, Regs&) {}
   __device__ static void solve(const LevelView& L, long long kk, bool hv, Regs&,
                                const double* rv, const double* ru, const double* rz,

@@ -153,8 +153,29 @@ hipEvent_t take_event(pitmg_handle* h) {
     return e;
   }
   hipEvent_t e = nullptr;
-  hipEventCreate(&e);
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
+}
+
+// Add one finished launch's time to its class (a failed query leaves the
+// totals as they are) and return its events to the pool.
+void account(pitmg_handle* h, const ProfRec& r) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+    h->prof_ms[r.cls] += ms;
+    h->prof_launches[r.cls] += 1;
+  }
+  h->pool.push_back(r.a);
+  h->pool.push_back(r.b);
+}
+
+// Events for one timed launch, or an error if the runtime cannot make them.
+int take_pair(pitmg_handle* h, int cls, ProfRec& r) {
+  r = ProfRec{cls, take_event(h), take_event(h)};
+  if (r.a && r.b) return PITMG_OK;
+  if (r.a) h->pool.push_back(r.a);
+  if (r.b) h->pool.push_back(r.b);
+  return set_err(h, PITMG_ERR_HIP, "profiling: hipEventCreate failed");
 }
 
 // Accumulate the elapsed time of the recorded launches that have already
@@ -164,12 +185,7 @@ void drain_ready(pitmg_handle* h) {
   for (; done < h->pending.size(); ++done) {
     const ProfRec& r = h->pending[done];
     if (hipEventQuery(r.b) != hipSuccess) break;
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, r.a, r.b);
-    h->prof_ms[r.cls] += ms;
-    h->prof_launches[r.cls] += 1;
-    h->pool.push_back(r.a);
-    h->pool.push_back(r.b);
+    account(h, r);
   }
   h->pending.erase(h->pending.begin(), h->pending.begin() + done);
 }
@@ -177,13 +193,8 @@ void drain_ready(pitmg_handle* h) {
 // Accumulate the elapsed time of every recorded launch (waits for them).
 void drain(pitmg_handle* h) {
   for (auto& r : h->pending) {
-    hipEventSynchronize(r.b);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, r.a, r.b);
-    h->prof_ms[r.cls] += ms;
-    h->prof_launches[r.cls] += 1;
-    h->pool.push_back(r.a);
-    h->pool.push_back(r.b);
+    (void)hipEventSynchronize(r.b);     // a failed wait fails the query below
+    account(h, r);
   }
   h->pending.clear();
 }
@@ -194,7 +205,8 @@ int timed(pitmg_handle* h, int cls, F&& launch) {
     HIPCHK(h, launch());
     return PITMG_OK;
   }
-  ProfRec r{cls, take_event(h), take_event(h)};
+  ProfRec r;
+  if (int rc = take_pair(h, cls, r)) return rc;
   HIPCHK(h, hipEventRecord(r.a, h->stream));
   HIPCHK(h, launch());
   HIPCHK(h, hipEventRecord(r.b, h->stream));
@@ -214,7 +226,8 @@ int timed_kernel(pitmg_handle* h, int cls, F&& launch) {
     HIPCHK(h, launch());
     return PITMG_OK;
   }
-  ProfRec r{cls, take_event(h), take_event(h)};
+  ProfRec r;
+  if (int rc = take_pair(h, cls, r)) return rc;
   KernelEvents& ev = kernel_events();
   ev.start = r.a;
   ev.stop = r.b;
@@ -1441,58 +1454,62 @@ const char* pitmg_last_error(const pitmg_handle* h) { return h ? h->err.c_str() 
 
 void pitmg_destroy(pitmg_handle* h) {
   if (!h) return;
-  if (h->stream) hipStreamSynchronize(h->stream);
-  else hipDeviceSynchronize();
+  // teardown: nothing is left to report to, so failed calls are ignored
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  auto release = [](void* ptr) {
+    if (ptr) (void)hipFree(ptr);
+  };
   drain(h);
   drop_graph(h);
-  hipFree(h->g_in);
-  hipFree(h->g_out);
-  hipFree(h->upd);
+  release(h->g_in);
+  release(h->g_out);
+  release(h->upd);
   for (auto& b : h->lv) {
     void* sp[] = {b.sp.Rm, b.sp.U, b.sp.Wz, b.sp.Wv, b.sp.Rm32, b.sp.Rz32,
                   b.sp.U32, b.sp.L32, b.sp.Wz32, b.sp.Wv32};
-    for (void* ptr : sp) hipFree(ptr);
+    for (void* ptr : sp) release(ptr);
   }
   split_blas_destroy(h->blas);
-  for (auto e : h->pool) hipEventDestroy(e);
+  for (auto e : h->pool) (void)hipEventDestroy(e);
   for (auto& b : h->lv) {
-    hipFree(b.N_own);
-    hipFree(b.V_own);
-    hipFree(b.Z_own);
-    hipFree(b.Gi);
-    hipFree(b.b);
-    hipFree(b.y0);
-    hipFree(b.y1);
-    hipFree(b.out);
-    hipFree(b.res);
-    hipFree(b.N32);
-    hipFree(b.V32);
-    hipFree(b.Z32);
-    hipFree(b.Gi32);
+    release(b.N_own);
+    release(b.V_own);
+    release(b.Z_own);
+    release(b.Gi);
+    release(b.b);
+    release(b.y0);
+    release(b.y1);
+    release(b.out);
+    release(b.res);
+    release(b.N32);
+    release(b.V32);
+    release(b.Z32);
+    release(b.Gi32);
   }
-  hipFree(h->Vk);
-  hipFree(h->Zk);
-  hipFree(h->w);
-  hipFree(h->r);
-  hipFree(h->partial);
-  hipFree(h->coef);
-  if (h->hbuf) hipHostFree(h->hbuf);
-  hipFree(h->coarse_work);
-  hipFree(h->coarse_its);
-  hipFree(h->cst);
-  hipFree(h->ist);
-  hipFree(h->cC);
-  hipFree(h->cA);
-  hipFree(h->cD);
-  hipFree(h->cY);
-  hipFree(h->cY2);
-  hipFree(h->czero);
-  hipFree(h->Phi);
-  hipFree(h->pscr);
-  hipFree(h->Pf);
-  hipFree(h->Qb);
-  if (h->its_pinned) hipHostFree(h->its_pinned);
-  hipFree(h->fail);
+  release(h->Vk);
+  release(h->Zk);
+  release(h->w);
+  release(h->r);
+  release(h->partial);
+  release(h->coef);
+  if (h->hbuf) (void)hipHostFree(h->hbuf);
+  release(h->coarse_work);
+  release(h->coarse_its);
+  release(h->cst);
+  release(h->ist);
+  release(h->cC);
+  release(h->cA);
+  release(h->cD);
+  release(h->cY);
+  release(h->cY2);
+  release(h->czero);
+  release(h->Phi);
+  release(h->pscr);
+  release(h->Pf);
+  release(h->Qb);
+  if (h->its_pinned) (void)hipHostFree(h->its_pinned);
+  release(h->fail);
   delete h;
 }
 

@@ -84,7 +84,6 @@ __global__ __launch_bounds__(kFactorThreads) void k_syrk_mfma(LevelView L, T* Gi
     const int J = t - I * (I + 1) / 2;
     const int I0 = 16 * I, J0 = 16 * J;
     typename Mfma4<T>::v4 acc = {0, 0, 0, 0};
-#pragma unroll 8
     for (int k0 = 0; k0 < K; k0 += 4) {
       const T a = x(I0 + r, k0 + kq);
       const T b = x(J0 + r, k0 + kq);
@@ -103,7 +102,7 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(LevelView L, T* Gi,
                                                            int level, int* fail) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const int p = L.p, q = L.q;
+  const int p = L.p;
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
   const T* __restrict__ Nk = Mats<T>::N(L) + (long long)k * L.sN;
@@ -514,7 +513,6 @@ hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant,
 // ---------------------------------------------------------------------------
 
 constexpr int kVecThreads = 256;
-constexpr int kDotChunk = 8;
 constexpr long long kSliceTarget = 1024;
 
 int krylov_partial_blocks(long long len) {
