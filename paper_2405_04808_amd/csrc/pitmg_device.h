@@ -4,11 +4,62 @@
 
 namespace pitmg {
 
+// Cross-lane sums that stay in the vector ALU (no trip through the LDS
+// crossbar): DPP row rotations inside each row of 16 lanes, and the gfx950
+// permlane swaps between rows (lane ^ 16) and between the two halves of the
+// wave (lane ^ 32).  Every lane ends with the sum.  All lanes of the wave
+// must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 16 lanes of each row (DPP row_ror 8, 4, 2, 1)
+template <class T>
+__device__ __forceinline__ T row_sum16(T v) {
+  v += dpp_move<0x128>(v);
+  v += dpp_move<0x124>(v);
+  v += dpp_move<0x122>(v);
+  v += dpp_move<0x121>(v);
+  return v;
+}
+
+// v + v[lane ^ 16]: the swap leaves rows (0,0,2,2) in one register and
+// rows (1,1,3,3) in the other
+__device__ __forceinline__ float xor16_sum(float v) {
+  const unsigned b = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double xor16_sum(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
+// v + v[lane ^ 32] (halves of the wave)
+__device__ __forceinline__ float xor32_sum(float v) {
+  const unsigned b = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane32_swap(b, b, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double xor32_sum(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  return xor32_sum(xor16_sum(row_sum16(v)));
 }
 
 // Value of the interpolated coarse vector (one node-type segment of nc coarse

@@ -5,6 +5,8 @@
 #include "pitmg_device.h"
 #include "pitmg_tiled.h"
 
+#include <type_traits>
+
 namespace pitmg {
 
 // Restriction of the residual after the last pre-smoothing sweep, fused
@@ -382,6 +384,282 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 shared-block sweep with the next step's N_k in flight.
+//
+// As k_jacobi_shared (register tiles of N_k and G_k^{-1}, products with the
+// shared V and Z~ for all steps of the group in one pass each), except that
+// N of the next step is requested at the start of the current one: it is
+// moved by direct global-to-LDS loads into a staging buffer (128 KB at
+// p = 128) and copied into the register tile when its step begins, so the
+// HBM stream of N runs under the current step's arithmetic.  G^{-1} of the
+// next step is loaded into its register tile once lambda is formed.
+// Results stay in LDS and are written after the last step: stores count in
+// the same vector-memory counter as the loads the step start waits for.
+// ---------------------------------------------------------------------------
+
+template <int RT, int CT>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl(
+    LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
+    const double* __restrict__ ec, int variant, double* __restrict__ ynew, int per_wg,
+    FusedRestrict fr) {
+  using TS = TiledSolve<RT, CT, double>;
+  constexpr int P = TS::P;
+  constexpr int G = kTiledThreads / P;                   // row groups of the post pass
+  constexpr int kUnits = P * P / 2;                      // 16-byte units of N_k
+  constexpr int kChunks = kUnits / kWave;                // one wave load (1 KB) each
+  static_assert(kChunks % kTiledWaves == 0, "whole chunks per wave");
+  static_assert(2 * G * kMaxSteps * P <= P * P, "post-pass slabs fit");
+  static_assert(3 * kMaxSteps * P <= P * P, "gathered right-hand sides fit");
+  static_assert(RT % 2 == 0, "row pairs of st");
+  __shared__ double nbuf[P * P];                         // staged N of the next step
+  __shared__ double sru[kMaxSteps][P], sT[kMaxSteps][P], slam[kMaxSteps][P], sou[kMaxSteps][P];
+  __shared__ double st[P], ss[P], red[kTiledWaves * P];
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  const int a = tid / 16, bq = tid % 16, r0 = RT * a;
+  const int n = L.n;
+  const TypeMajor Tm(P, P, n);
+  const int nc = n / 2;
+  const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
+  const int k0 = blockIdx.x * per_wg + 1;                // first step (1-based)
+  const int nb = min(per_wg, n - k0 + 1);                // steps of this work-group
+  const double* __restrict__ Vs = L.V;                   // shared blocks
+  const double* __restrict__ Zs = L.Z;
+
+  auto cu = [&](int k1, int i) -> double {
+    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
+    if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
+    return v;
+  };
+  auto cm = [&](int k1, int i) -> double {
+    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
+    if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
+    return v;
+  };
+  // N_k (row-major, contiguous) into nbuf: wave w moves chunks w, w + 8, ...
+  auto stage_n = [&](long long kk) {
+    const double* Nk = L.N + kk * L.sN;
+#pragma unroll
+    for (int t = 0; t < kChunks / kTiledWaves; ++t) {
+      const int c = wv + kTiledWaves * t;
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(Nk + 2 * (kWave * c + lane)),
+          (__attribute__((address_space(3))) void*)(nbuf + 2 * kWave * c), 16, 0, 0);
+    }
+  };
+  // the thread's register tile of N from the staged copy
+  auto unstage_n = [&](typename TS::Regs& R) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r) tile_load_row<CT, double>(nbuf + (r0 + r) * P, R.nt[r]);
+  };
+  // barrier inside a step: LDS accesses complete (lgkmcnt(0)); no wait on
+  // the vector-memory counter, which holds the staged N in flight
+  auto lds_barrier = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);                  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+
+  // tiles of the first step in flight while the right-hand sides are gathered
+  typename TS::Regs R;
+  TS::load(L, k0 - 1, R);
+  double* srz = nbuf;                                    // pre-pass only
+  double* srm = nbuf + kMaxSteps * P;
+  double* srl = nbuf + 2 * kMaxSteps * P;
+  for (int bi = 0; bi < nb; ++bi) {
+    const int k = k0 + bi;
+    const long long kk = k - 1;
+    for (int i = tid; i < P; i += kTiledThreads) {
+      sru[bi][i] = b[Tm.u + kk * P + i] - cm(k, i);
+      srl[bi * P + i] = b[Tm.l + kk * P + i];
+      srz[bi * P + i] = b[Tm.z + kk * P + i];
+      srm[bi * P + i] = k >= 2 ? b[Tm.m + (kk - 1) * P + i] - cu(k - 1, i) : 0.0;
+    }
+  }
+  if (k0 + nb - 1 == n) {                                // block n+1 = (v_n, mu_n)
+    const int mu_m = fr.u_writer(n + 1);
+    for (int i = tid; i < P; i += kTiledThreads) {
+      const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
+      const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
+      const double mo = -rmm - rvv;
+      ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+      ynew[Tm.m + (long long)(n - 1) * P + i] = mo;
+      if (mu_m)
+        fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] =
+            (yold ? yold[Tm.m + (long long)(n - 1) * P + i] : 0.0) - mo;
+    }
+  }
+  __syncthreads();
+
+  // sT[s] = Z~ r_z[s] - V r_mu[s] - r_lambda[s] for every step
+  {
+    double acc[kMaxSteps][RT];
+#pragma unroll
+    for (int s2 = 0; s2 < kMaxSteps; ++s2)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[s2][r] = 0;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      double zr[CT], vr[CT];
+      tile_load_row<CT, double>(Zs + (long long)(r0 + r) * P, zr);
+      tile_load_row<CT, double>(Vs + (long long)(r0 + r) * P, vr);
+#pragma unroll
+      for (int s2 = 0; s2 < kMaxSteps; ++s2) {
+        if (s2 < nb) {
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+            acc[s2][r] += zr[c] * srz[s2 * P + tile_col<double>(c)] -
+                          vr[c] * srm[s2 * P + tile_col<double>(c)];
+        }
+      }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < kMaxSteps; ++s2) {
+      if (s2 < nb) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const double v = tile_sum16(acc[s2][r]);
+          if (bq == 0) sT[s2][r0 + r] = v - srl[s2 * P + r0 + r];
+        }
+      }
+    }
+  }
+  __syncthreads();                                       // staging buffer free
+
+  for (int bi = 0; bi < nb; ++bi) {
+    // N (staged, or loaded directly for the first step) and G^{-1} of this
+    // step have arrived; waiting on every path leaves no load of this step
+    // pending once the next step's loads are issued
+    __builtin_amdgcn_s_waitcnt(0x0F70);                  // vmcnt(0)
+    __syncthreads();
+    if (bi > 0) {
+      unstage_n(R);
+      lds_barrier();                                     // every wave has its tile
+    }
+    if (bi + 1 < nb) stage_n(k0 + bi);                   // N of the next step
+    // t = N r_u + (Z~ r_z - V r_mu - r_lambda)
+    double acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      double sum = 0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) sum += R.nt[r][c] * sru[bi][tile_col<double>(c)];
+      acc[r] = tile_sum16(sum);
+    }
+    if (bq == 0) {
+#pragma unroll
+      for (int r = 0; r < RT; r += 2)
+        *reinterpret_cast<double2*>(st + r0 + r) =
+            make_double2(acc[r] + sT[bi][r0 + r], acc[r + 1] + sT[bi][r0 + r + 1]);
+    }
+    lds_barrier();
+    // s = G^{-1} t
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      double sum = 0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) sum += R.gt[r][c] * st[tile_col<double>(c)];
+      acc[r] = tile_sum16(sum);
+    }
+    if (bq == 0) {
+#pragma unroll
+      for (int r = 0; r < RT; r += 2)
+        *reinterpret_cast<double2*>(ss + r0 + r) = make_double2(acc[r], acc[r + 1]);
+    }
+    lds_barrier();
+    // lambda = G^{-T} s
+    double cacc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      double sum = 0;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) sum += R.gt[r][c] * ss[r0 + r];
+      cacc[c] = sum;
+    }
+    TS::col_partial(cacc, red);
+    lds_barrier();
+    for (int j = tid; j < P; j += kTiledThreads) slam[bi][j] = TS::col_total(red, j);
+    lds_barrier();
+    if (bi + 1 < nb) TS::load_g(L, k0 + bi, R);          // G^{-1} of the next step
+    // u = r_u - N^T lambda
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      double sum = 0;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) sum += R.nt[r][c] * slam[bi][r0 + r];
+      cacc[c] = sum;
+    }
+    TS::col_partial(cacc, red);
+    lds_barrier();
+    for (int i = tid; i < P; i += kTiledThreads) sou[bi][i] = sru[bi][i] - TS::col_total(red, i);
+  }
+  __syncthreads();
+
+  // Z~^T lambda and V^T lambda for every step (slabs in the idle staging
+  // buffer), then every output of the work-group
+  double* pz = nbuf;                                     // [G][kMaxSteps][P]
+  double* pv = nbuf + G * kMaxSteps * P;
+  {
+    const int j = tid % P, g = tid / P;
+    double za[kMaxSteps], va[kMaxSteps];
+#pragma unroll
+    for (int s2 = 0; s2 < kMaxSteps; ++s2) {
+      za[s2] = 0;
+      va[s2] = 0;
+    }
+    for (int i = g; i < P; i += G) {
+      const double zi = Zs[(long long)i * P + j], vi = Vs[(long long)i * P + j];
+#pragma unroll
+      for (int s2 = 0; s2 < kMaxSteps; ++s2) {
+        if (s2 < nb) {
+          za[s2] += zi * slam[s2][i];
+          va[s2] += vi * slam[s2][i];
+        }
+      }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < kMaxSteps; ++s2) {
+      pz[(g * kMaxSteps + s2) * P + j] = za[s2];
+      pv[(g * kMaxSteps + s2) * P + j] = va[s2];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * P; idx += kTiledThreads) {
+    const int s2 = idx / P, i = idx % P;
+    const int k = k0 + s2;
+    const long long kk = k - 1;
+    double zt = 0, vt = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      zt += pz[(g * kMaxSteps + s2) * P + i];
+      vt += pv[(g * kMaxSteps + s2) * P + i];
+    }
+    const double uo = sou[s2][i];
+    ynew[Tm.u + kk * P + i] = uo;
+    ynew[Tm.l + kk * P + i] = slam[s2][i];
+    ynew[Tm.z + kk * P + i] = b[Tm.z + kk * P + i] - zt;
+    const int rm_m = fr.mu_writer(k);
+    if (rm_m) {
+      const long long o = (long long)(rm_m - 1) * P + i;
+      fr.rc[Tc.m + o] = (yold ? yold[Tm.u + kk * P + i] : 0.0) - uo;
+      fr.rc[Tc.v + o] = 0.0;
+      fr.rc[Tc.z + o] = 0.0;
+      fr.rc[Tc.l + o] = 0.0;
+    }
+    if (k >= 2) {
+      const double rm = b[Tm.m + (kk - 1) * P + i] - cu(k - 1, i);
+      const double mo = vt - rm - b[Tm.v + (kk - 1) * P + i];
+      ynew[Tm.m + (kk - 1) * P + i] = mo;
+      ynew[Tm.v + (kk - 1) * P + i] = -rm;
+      const int ru_m = fr.u_writer(k);
+      if (ru_m)
+        fr.rc[Tc.u + (long long)(ru_m - 1) * P + i] =
+            (yold ? yold[Tm.m + (kk - 1) * P + i] : 0.0) - mo;
+    }
+  }
+}
+
 bool jacobi_shared_supported(const LevelView& L) {
   return L.sV == 0 && L.sZ == 0 && L.p == L.q && (L.p == 128 || L.p == 64);
 }
@@ -391,6 +669,15 @@ static hipError_t launch_shared_t(const LevelView& L, const double* b, const dou
                                   const double* ecoarse, int variant, double* ynew, int per,
                                   FusedRestrict fr, hipStream_t s) {
   const int nwg = (L.n + per - 1) / per;
+  if (std::is_same<T, double>::value) {
+    if (L.p == 128)
+      return launch_k(k_jacobi_shared_nl<4, 8>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
+                      ecoarse, variant, ynew, per, fr);
+    if (L.p == 64)
+      return launch_k(k_jacobi_shared_nl<2, 4>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
+                      ecoarse, variant, ynew, per, fr);
+    return hipErrorInvalidValue;
+  }
   if (L.p == 128) {
     return launch_k(k_jacobi_shared<4, 8, T>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
                     ecoarse, variant, ynew, per, fr);

@@ -145,8 +145,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_split_blocks(LevelView L, Cou
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      acc[c] += __shfl_xor(acc[c], 16, kWave);
-      acc[c] += __shfl_xor(acc[c], 32, kWave);
+      acc[c] = xor32_sum(xor16_sum(acc[c]));
     }
     if (lane < 16) {
 #pragma unroll

@@ -84,11 +84,7 @@ __device__ __forceinline__ void tile_load_row_lower(const T* __restrict__ row, i
 
 template <class T>
 __device__ __forceinline__ T tile_sum16(T v) {
-  v += __shfl_xor(v, 8, kWave);
-  v += __shfl_xor(v, 4, kWave);
-  v += __shfl_xor(v, 2, kWave);
-  v += __shfl_xor(v, 1, kWave);
-  return v;
+  return row_sum16(v);
 }
 
 template <int RT, int CT, class T = double>
@@ -130,8 +126,7 @@ struct TiledSolve {
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      v[c] += __shfl_xor(v[c], 16, kWave);
-      v[c] += __shfl_xor(v[c], 32, kWave);
+      v[c] = xor32_sum(xor16_sum(v[c]));
     }
     if (lane < 16) {
 #pragma unroll
