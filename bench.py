@@ -371,7 +371,7 @@ def main():
         rec = read_traffic(COUNTERS)
         names = {0: "built-in", -1: "k_jacobi_tiled<%d, %d, double>" % (p // 32, p // 16)}
         kname = "block Jacobi sweep, levels 0..%d: " % (L - 2) + ", ".join(
-            (names.get(c) or "k_jacobi_shared<%d, %d, double> x%d steps" % (p // 32, p // 16, c))
+            (names.get(c) or "k_jacobi_shared_nl<%d, %d> x%d steps" % (p // 32, p // 16, c))
             for c in sweep_shapes[:L - 1])
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
