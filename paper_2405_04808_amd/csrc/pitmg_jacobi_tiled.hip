@@ -608,13 +608,25 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl(
       za[s2] = 0;
       va[s2] = 0;
     }
-    for (int i = g; i < P; i += G) {
-      const double zi = Zs[(long long)i * P + j], vi = Vs[(long long)i * P + j];
+    // rows g, g + G, ... in batches of 8: every load of a batch is issued
+    // before any of its products, so the L2 latency is paid once per batch;
+    // every step slot is formed (slots past nb are never written out)
+    constexpr int kRowBatch = 8;
+    static_assert((P / G) % kRowBatch == 0, "whole row batches");
+#pragma unroll 1
+    for (int i0 = g; i0 < P; i0 += G * kRowBatch) {
+      double zr[kRowBatch], vr[kRowBatch];
 #pragma unroll
-      for (int s2 = 0; s2 < kMaxSteps; ++s2) {
-        if (s2 < nb) {
-          za[s2] += zi * slam[s2][i];
-          va[s2] += vi * slam[s2][i];
+      for (int u = 0; u < kRowBatch; ++u) {
+        zr[u] = Zs[(long long)(i0 + u * G) * P + j];
+        vr[u] = Vs[(long long)(i0 + u * G) * P + j];
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+#pragma unroll
+        for (int s2 = 0; s2 < kMaxSteps; ++s2) {
+          za[s2] += zr[u] * slam[s2][i0 + u * G];
+          va[s2] += vr[u] * slam[s2][i0 + u * G];
         }
       }
     }
@@ -669,7 +681,7 @@ static hipError_t launch_shared_t(const LevelView& L, const double* b, const dou
                                   const double* ecoarse, int variant, double* ynew, int per,
                                   FusedRestrict fr, hipStream_t s) {
   const int nwg = (L.n + per - 1) / per;
-  if (std::is_same<T, double>::value) {
+  if constexpr (std::is_same<T, double>::value) {
     if (L.p == 128)
       return launch_k(k_jacobi_shared_nl<4, 8>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
                       ecoarse, variant, ynew, per, fr);
@@ -677,8 +689,7 @@ static hipError_t launch_shared_t(const LevelView& L, const double* b, const dou
       return launch_k(k_jacobi_shared_nl<2, 4>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
                       ecoarse, variant, ynew, per, fr);
     return hipErrorInvalidValue;
-  }
-  if (L.p == 128) {
+  } else if (L.p == 128) {
     return launch_k(k_jacobi_shared<4, 8, T>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
                     ecoarse, variant, ynew, per, fr);
   } else if (L.p == 64) {
