@@ -198,6 +198,26 @@ def test_vcycle_fixed_coarse_steps(name, opt):
     s.close()
 
 
+@pytest.mark.parametrize("nx", [64, 128])
+@pytest.mark.parametrize("per", [2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_vcycle_shared_sweep_groups(nx, per, variant):
+    """V-cycle with the shared-block sweep at 2..4 steps per work-group on
+    both smoothed levels (n = 20, 10: ragged last groups), so the restriction
+    that the last pre-smoothing sweep writes is checked for both transfer
+    variants, including the entry of block n+1 (variant 1)."""
+    prob, rng = make_problem(kind="burgers", nx=nx, nu=0.01, n=20, n_levels=3, seed=23)
+    s = pm.Solver(prob.levels, pm.default_options(coarse_fixed_its=2, transfer_variant=variant))
+    s.set_sweep_shapes([per] * (prob.n_levels - 1) + [0])
+    H = Hierarchy(prob.levels, mg_opts(s.options))
+    r = rng.normal(size=prob.size)
+    ref = H.vcycle(r)
+    got = host(s.vcycle(dev(r)))
+    tol = coarse_identity_tol(prob)
+    assert rel(got, ref) <= tol, (nx, per, variant, rel(got, ref), tol)
+    s.close()
+
+
 @pytest.mark.parametrize("name", ["vdp64", "burgers_p12", "burgers_ragged_p70", "burgers_p64",
                                   "burgers_p64_theta05"])
 def test_fgmres_matches_oracle(name):
