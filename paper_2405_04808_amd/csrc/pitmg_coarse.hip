@@ -240,6 +240,29 @@ __global__ __launch_bounds__(kCtrlThreads) void k_coarse_arnoldi(int j, double* 
                              red, &sflag);
 }
 
+// The same step, with the SGS result and its product formed first from the
+// two sweeps: z_j = a + d and A~ z_j without reading the blocks.  With
+// (D + L) a = v (forward sweep) and (D + L^T) z = D a (backward sweep,
+// d = z - a), D z = v - L a - L^T z, so A~ z = (D + L + L^T) z = v + L d;
+// L is the identity from u_k into row mu_k (k = 1..n), hence w = v except
+// w_mu = v_mu + d_u (mu0 = offset of the mu segment).
+__global__ __launch_bounds__(kCtrlThreads) void k_coarse_arnoldi_sgs(
+    int j, double* wv, double* Vb, double* __restrict__ zj, const double* __restrict__ a,
+    const double* __restrict__ d, long long mu0, long long len, double* cst, int* ist, int cap,
+    double tol, int fixed_its, int nsteps) {
+  __shared__ double red[kCtrlThreads / kWave];
+  __shared__ int sflag;
+  if (ist[1]) return;                          // solved at an earlier step
+  const double* v = Vb + (size_t)j * len;
+  for (long long e = threadIdx.x; e < len; e += kCtrlThreads) {
+    zj[e] = a[e] + d[e];
+    wv[e] = e >= mu0 ? v[e] + d[e - mu0] : v[e];
+  }
+  __syncthreads();
+  arnoldi_step<kCtrlThreads>(j, wv, Vb, len, cst, ist, CState{cap}, tol, fixed_its, nsteps,
+                             red, &sflag);
+}
+
 // Finish the coarse solve: continue block by block if the enqueued steps did
 // not meet the test, then x = Z y with H y = g.
 template <class Pol>
@@ -421,22 +444,6 @@ __global__ void k_add(double* __restrict__ z, const double* __restrict__ a,
     z[e] = a[e] + d[e];
 }
 
-// z = a + d and, from the same sweeps, w = A~ z without reading the blocks.
-// With (D + L) a = v (forward sweep) and (D + L^T) z = D a (backward sweep,
-// d = z - a), D z = v - L a - L^T z, so A~ z = (D + L + L^T) z = v + L d.
-// L is the identity from u_k into row mu_k (k = 1..n), hence w = v except
-// w_mu = v_mu + d_u.
-__global__ void k_add_identity(double* __restrict__ z, const double* __restrict__ a,
-                               const double* __restrict__ d, const double* __restrict__ v,
-                               double* __restrict__ w, long long mu0, long long len) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < len;
-       e += (long long)gridDim.x * blockDim.x) {
-    const double de = d[e];
-    z[e] = a[e] + de;
-    w[e] = e >= mu0 ? v[e] + d[e - mu0] : v[e];
-  }
-}
-
 using FinishPol = GenericPolicy<512>;
 
 size_t finish_lds_doubles(int p, int q) {
@@ -469,6 +476,16 @@ hipError_t launch_coarse_arnoldi(int j, double* w, double* Vb, long long len, do
                                  hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_arnoldi, dim3(1), dim3(kCtrlThreads), 0, s, j, w, Vb, len, cst,
                      ist, cap, tol, fixed_its, nsteps);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_arnoldi_sgs(int j, double* w, double* Vb, double* zj, const double* a,
+                                     const double* d, int p, int q, int n, double* cst, int* ist,
+                                     int cap, double tol, int fixed_its, int nsteps,
+                                     hipStream_t s) {
+  const TypeMajor T(p, q, n);
+  hipLaunchKernelGGL(k_coarse_arnoldi_sgs, dim3(1), dim3(kCtrlThreads), 0, s, j, w, Vb, zj, a, d,
+                     T.m, T.len, cst, ist, cap, tol, fixed_its, nsteps);
   return hipGetLastError();
 }
 
@@ -509,16 +526,6 @@ hipError_t launch_add(double* z, const double* a, const double* d, long long len
   long long g = (len + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_add, dim3((unsigned)g), dim3(256), 0, s, z, a, d, len);
-  return hipGetLastError();
-}
-
-hipError_t launch_add_identity(int p, int q, int n, double* z, const double* a, const double* d,
-                               const double* v, double* w, hipStream_t s) {
-  const TypeMajor T(p, q, n);
-  long long g = (T.len + 255) / 256;
-  if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_add_identity, dim3((unsigned)g), dim3(256), 0, s, z, a, d, v, w, T.m,
-                     T.len);
   return hipGetLastError();
 }
 

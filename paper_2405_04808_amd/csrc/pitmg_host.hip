@@ -437,17 +437,20 @@ int coarse_solve(pitmg_handle* h, const double* b, double* out) {
          })))
       return rc;
     if (o.apply_from_sweep) {
-      // w = A~ z from the two sweeps' identities (no pass over the blocks)
+      // z = a + d and w = A~ z from the two sweeps' identities (no pass over
+      // the blocks), inside the Arnoldi step's own launch
       if ((rc = timed(h, 4, [&] {
-             return launch_add_identity(h->p, h->q, v.n, zj, h->cA, h->cD, vj, W, h->stream);
+             return launch_coarse_arnoldi_sgs(j, W, Vb, zj, h->cA, h->cD, h->p, h->q, v.n,
+                                              h->cst, h->ist, cap, o.coarse_tol,
+                                              o.coarse_fixed_its, nsteps, h->stream);
            })))
         return rc;
-    } else {
-      if ((rc = timed(h, 4, [&] { return launch_add(zj, h->cA, h->cD, len, h->stream); })))
-        return rc;
-      if ((rc = timed(h, 4, [&] { return launch_apply(v, zj, nullptr, 1.0, 0.0, W, h->stream); })))
-        return rc;
+      continue;
     }
+    if ((rc = timed(h, 4, [&] { return launch_add(zj, h->cA, h->cD, len, h->stream); })))
+      return rc;
+    if ((rc = timed(h, 4, [&] { return launch_apply(v, zj, nullptr, 1.0, 0.0, W, h->stream); })))
+      return rc;
     if ((rc = timed(h, 4, [&] {
            return launch_coarse_arnoldi(j, W, Vb, len, h->cst, h->ist, cap, o.coarse_tol,
                                         o.coarse_fixed_its, nsteps, h->stream);

@@ -158,6 +158,12 @@ hipError_t launch_coarse_init(const double* b, long long len, double* Vb, double
 hipError_t launch_coarse_arnoldi(int j, double* w, double* Vb, long long len, double* cst,
                                  int* ist, int cap, double tol, int fixed_its, int nsteps,
                                  hipStream_t s);
+// The Arnoldi step of an SGS application z_j = a + d (forward sweep a,
+// backward correction d): forms z_j and w = A~ z_j = v_j + L d, then the step.
+hipError_t launch_coarse_arnoldi_sgs(int j, double* w, double* Vb, double* zj, const double* a,
+                                     const double* d, int p, int q, int n, double* cst, int* ist,
+                                     int cap, double tol, int fixed_its, int nsteps,
+                                     hipStream_t s);
 hipError_t launch_coarse_finish(const LevelView& L, double* x, double tol, int fixed_its,
                                 int nsteps, double* work, double* cst, int* ist, int cap,
                                 int* its_out, hipStream_t s);
@@ -169,9 +175,6 @@ hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, 
 hipError_t launch_gemv_tri(const double* M, int nc, int p, int upper, const double* x, double* y,
                            hipStream_t s);
 hipError_t launch_add(double* z, const double* a, const double* d, long long len, hipStream_t s);
-// z = a + d and w = v + L d (the coarse SGS result and its product with A~)
-hipError_t launch_add_identity(int p, int q, int n, double* z, const double* a, const double* d,
-                               const double* v, double* w, hipStream_t s);
 
 // Krylov helpers.  Basis vectors are rows of a [k][len] array.  Dot and
 // update kernels work on krylov_slices(len) slices of 1024 elements and store
