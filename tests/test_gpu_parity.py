@@ -374,6 +374,29 @@ def test_full_burgers128_operator_and_sweep():
     s.close()
 
 
+def test_full_burgers128_restarted_solve_residual():
+    # the benchmark's solve (FGMRES(550), tuned sweep shapes) on the full
+    # Burgers nx=128, n=1024 system: its final iterate's residual, formed
+    # by the oracle's CSR matvec, meets 1e-10 and equals the reported one
+    prob, b = config_problem("burgers128")
+    s = pm.Solver(prob.levels, pm.default_options(restart=550, maxit=3000))
+    s.set_sweep_shapes([4, 3, -1, -1, -1, -1, -1, 0])
+    xg, st, rc = s.solve(dev(b), tol=1e-10)
+    assert rc == pm.PITMG_OK and st["converged"] == 1
+    assert st["iters"] > 550            # at least one restart happened
+    ol = OracleLevel(prob.levels[0].N, prob.levels[0].V, prob.levels[0].Z)
+    x = host(xg)
+    true = np.linalg.norm(b - ol.A @ x) / np.linalg.norm(b)
+    assert true <= 1.0e-10
+    # both residuals round each row's sum of at most k products: they differ
+    # by at most 2 k u || |A| |x| || (relative to ||b||)
+    A = ol.A.tocsr()
+    k = int(np.diff(A.indptr).max())
+    bound = 2 * k * np.finfo(float).eps / 2 * np.linalg.norm(abs(A) @ np.abs(x)) / np.linalg.norm(b)
+    assert abs(true - st["relres_true"]) <= bound
+    s.close()
+
+
 @pytest.mark.parametrize("name", ["vdp64", "burgers_p12", "burgers_p64", "burgers_p150"])
 @pytest.mark.parametrize("nu_post", [1, 2, 3])
 def test_fgmres_apply_from_sweep_matches_explicit_apply(name, nu_post):
