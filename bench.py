@@ -74,25 +74,60 @@ def sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8, with_rest
     return float(total)
 
 
-def vcycle_bytes(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, mat_bytes=8, fp64_residual=False):
+def pair_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8, with_restrict=False):
+    """Algorithmic HBM bytes of two consecutive sweeps in one launch (the
+    two-sweep tiled kernel): the blocks and the right-hand side are read once,
+    the first sweep's iterate is written and its two coupling values per
+    block read back by the neighbours, the second sweep's iterate is written.
+    The couplings of the previous iterate (and of the coarse correction) and
+    the fused restriction count as in sweep_bytes."""
+    one = sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes, with_restrict)
+    # second sweep: its own iterate written and the first's couplings read
+    return one + float(n * ((4 * p + q) + 2 * p) * 8 + (2 * p + p) * 8)
+
+
+def level_pairs(p, q, L, shapes, pair_sweeps):
+    """Per level above the coarsest: True where two sweeps share a launch
+    (levels swept by the one-step tiled kernel, p = q in {64, 128})."""
+    ok = pair_sweeps and p == q and p in (64, 128)
+    return [bool(ok and shapes[lev] == -1) for lev in range(L - 1)]
+
+
+def vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes=8,
+                  fp64_residual=False):
+    """(bytes, launches) of the sweeps of one V-cycle, with the launch
+    pattern of the library: on a paired level sweeps go two per launch, an
+    odd one last on its own; the restriction rides on the last pre-smoothing
+    sweep, except on the finest level when its residual is formed in FP64."""
+    tot, launches = 0.0, 0
+    for lev in range(L - 1):
+        nl = n >> lev
+        fused = nu_pre > 0 and not (fp64_residual and lev == 0)
+        for nu, pre in ((nu_pre, True), (nu_post, False)):
+            s_ = 0
+            while s_ < nu:
+                two = pairs[lev] and s_ + 1 < nu
+                last = s_ + 1 if two else s_
+                kw = dict(with_coarse=(not pre) and s_ == 0, mat_bytes=mat_bytes,
+                          with_restrict=pre and fused and last == nu - 1)
+                tot += (pair_bytes if two else sweep_bytes)(p, q, nl, shared_V, shared_Z, **kw)
+                launches += 1
+                s_ = last + 1
+        if not fused:
+            tot += 8.0 * (4 * p * nl + (4 * p + q) * (nl // 2))
+    return tot, launches
+
+
+def vcycle_bytes(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, mat_bytes=8, fp64_residual=False,
+                 pairs=None):
     """Algorithmic bytes of one V-cycle: the sweeps of every level above the
     coarsest, the restrictions (coupling values of two iterates read, coarse
     right-hand side written), the coarse right-hand side and correction, and,
     with an FP32 smoother, the explicit FP64 finest residual (blocks and two
     vectors read, one written)."""
-    tot = 0.0
-    for lev in range(L - 1):
-        nl = n >> lev
-        # the restriction rides on the last pre-smoothing sweep, except on the
-        # finest level when its residual is formed explicitly in FP64
-        fused = nu_pre > 0 and not (fp64_residual and lev == 0)
-        for s_ in range(nu_pre):
-            tot += sweep_bytes(p, q, nl, shared_V, shared_Z, False, mat_bytes,
-                               with_restrict=fused and s_ == nu_pre - 1)
-        for s_ in range(nu_post):
-            tot += sweep_bytes(p, q, nl, shared_V, shared_Z, s_ == 0, mat_bytes)
-        if not fused:
-            tot += 8.0 * (4 * p * nl + (4 * p + q) * (nl // 2))
+    pairs = pairs or [False] * (L - 1)
+    tot, _ = vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes,
+                           fp64_residual)
     nc = n >> (L - 1)
     tot += 8.0 * 2 * (4 * p + q) * nc
     if fp64_residual:
@@ -339,6 +374,7 @@ def main():
     ok = all(s["converged"] == 1 and s["relres_true"] <= 1.01e-10 for s in stats)
     p, q, n, L = prob.p, prob.q, prob.n, prob.n_levels
     shared_V, shared_Z = solver.shared_V, solver.shared_Z
+    pairs = level_pairs(p, q, L, sweep_shapes, opts.pair_sweeps)
 
     if args.counters:
         # plain copy kernel of known size for calibrating FETCH_SIZE / WRITE_SIZE
@@ -356,26 +392,22 @@ def main():
     kern = None
     if prof:
         # algorithmic bytes of every Jacobi launch of the timed steps
-        per_vcycle = 0.0
-        for lev in range(L - 1):
-            nl = n >> lev
-            for sidx in range(opts.nu_pre):
-                per_vcycle += sweep_bytes(p, q, nl, shared_V, shared_Z, False,
-                                          with_restrict=sidx == opts.nu_pre - 1)
-            for sidx in range(opts.nu_post):
-                per_vcycle += sweep_bytes(p, q, nl, shared_V, shared_Z, sidx == 0)
+        per_vcycle, per_vcycle_launches = vcycle_sweeps(p, q, n, L, opts.nu_pre, opts.nu_post,
+                                                        shared_V, shared_Z, pairs)
         launches, ms = prof["jacobi"]
         # the timed launches are whole V-cycles' sweeps: bytes per launch is
         # the V-cycle's algorithmic bytes over its sweep launches
-        per_launch = per_vcycle / ((opts.nu_pre + opts.nu_post) * (L - 1))
+        per_launch = per_vcycle / per_vcycle_launches
         alg_bytes = per_launch * launches
         achieved = alg_bytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         from paper_2405_04808_amd.rocprof_summary import read_traffic
         rec = read_traffic(COUNTERS)
         names = {0: "built-in", -1: "k_jacobi_tiled<%d, %d, double>" % (p // 32, p // 16)}
         kname = "block Jacobi sweep, levels 0..%d: " % (L - 2) + ", ".join(
-            (names.get(c) or "k_jacobi_shared_nl<%d, %d> x%d steps" % (p // 32, p // 16, c))
-            for c in sweep_shapes[:L - 1])
+            ("k_jacobi_tiled2<%d, %d, double> (two sweeps per launch)" % (p // 32, p // 16)
+             if pairs[lev] else
+             names.get(c) or "k_jacobi_shared_nl<%d, %d> x%d steps" % (p // 32, p // 16, c))
+            for lev, c in enumerate(sweep_shapes[:L - 1]))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": rec["traffic_bytes_per_launch"] if rec else None,
@@ -387,7 +419,7 @@ def main():
         kern = {k: {"launches": v[0], "ms_total": round(v[1], 3)} for k, v in classes.items()}
         kern["note"] = "one extra untimed step with every launch bracketed by events"
 
-    def vcycle_rate(s_, mat_bytes, fp64_res, reps=20):
+    def vcycle_rate(s_, mat_bytes, fp64_res, lev_pairs=None, reps=20):
         """ms per V-cycle (back-to-back calls on the solver's stream) and its
         algorithmic GB/s."""
         g = torch.Generator(device="cpu").manual_seed(7)
@@ -403,11 +435,11 @@ def main():
         torch.cuda.synchronize()
         ms_ = ev0.elapsed_time(ev1) / reps
         by = vcycle_bytes(p, q, n, L, opts.nu_pre, opts.nu_post, shared_V, shared_Z, mat_bytes,
-                          fp64_res)
+                          fp64_res, lev_pairs)
         return {"ms": round(ms_, 4), "alg_GB": round(by / 1e9, 4),
                 "GBps": round(by / (ms_ * 1e-3) / 1e9, 1)}
 
-    vc = {"fp64": vcycle_rate(solver, 8, False)}
+    vc = {"fp64": vcycle_rate(solver, 8, False, pairs)}
     fp32 = None
     if not args.no_fp32:
         s32 = pm.Solver(prob.levels, pm.default_options(restart=wl["restart"], maxit=wl["maxit"],

@@ -127,6 +127,17 @@ typedef struct {
                                   SGS result z = a + d (forward sweep a,
                                   backward correction d) as v + L d;
                                   0: always the explicit product             */
+  int pair_sweeps;             /* 1: on levels that sweep with the one-step
+                                  tiled kernel (p = q in {64, 128}), run two
+                                  consecutive sweeps in one launch: each
+                                  work-group keeps its step's N_k and G_k^{-1}
+                                  in registers and takes the second sweep's
+                                  two coupling values from its neighbours'
+                                  first sweep (the permuted system of Sec. 5.2
+                                  is block tridiagonal, so a block Jacobi
+                                  sweep of Sec. 5.3.2 couples block k only to
+                                  k-1 and k+1).  Results are bitwise those of
+                                  two launches.  0: one sweep per launch.      */
 } pitmg_options;
 
 typedef struct {
@@ -144,7 +155,7 @@ typedef struct {
 
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
  * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
- * stall_steps 2, vcycle_graph 0, apply_from_sweep 1. */
+ * stall_steps 2, vcycle_graph 0, apply_from_sweep 1, pair_sweeps 1. */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and

@@ -116,6 +116,12 @@ struct pitmg_handle {
   // previous iterate of the finest level's last sweep, when that sweep was
   // FP64 without a folded coarse correction (A~ z from the sweep identity)
   const double* top_prev = nullptr;
+  // two-sweep launches: ticket counter, per-block epochs, timeout word
+  unsigned long long* hand_ticket = nullptr;
+  unsigned long long* hand_flag = nullptr;
+  int* hand_timeout = nullptr;
+  unsigned long long hand_tickets = 0;   // tickets issued so far (host mirror)
+  unsigned long long hand_epoch = 0;     // last epoch issued
 };
 
 namespace {
@@ -295,6 +301,8 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "stall_ratio must be > 0 and stall_steps >= 1");
   if (o.apply_from_sweep != 0 && o.apply_from_sweep != 1)
     return set_err(h, PITMG_ERR_INVALID, "apply_from_sweep must be 0 or 1");
+  if (o.pair_sweeps != 0 && o.pair_sweeps != 1)
+    return set_err(h, PITMG_ERR_INVALID, "pair_sweeps must be 0 or 1");
   if (o.vcycle_graph != 0 && o.vcycle_graph != 1)
     return set_err(h, PITMG_ERR_INVALID, "vcycle_graph must be 0 or 1");
   if (o.vcycle_graph && h && h->stream == nullptr)
@@ -547,6 +555,21 @@ int vcycle_top(pitmg_handle* h, const double* r, double* e) {
 }
 
 // MG_l(b) -> out (Alg. 1 recursed; zero initial guess on every level).
+// Two consecutive sweeps of a level in one launch (y1 then y2), taking the
+// next tickets and epoch of the handle's hand-off state.
+hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, const double* yo,
+                      const double* ec, double* y1, double* y2, double* rc_out) {
+  const PairSync ps{h->hand_ticket, h->hand_tickets, h->hand_flag, h->hand_epoch + 1,
+                    h->hand_timeout};
+  const hipError_t e = launch_jacobi_pair(v, b, yo, ec, h->opt.transfer_variant, y1, y2,
+                                          rc_out, ps, h->stream);
+  if (e == hipSuccess) {
+    h->hand_tickets += (unsigned long long)v.n + 1;
+    h->hand_epoch += 1;
+  }
+  return e;
+}
+
 int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   const pitmg_options& o = h->opt;
   const int var = o.transfer_variant;
@@ -558,17 +581,29 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   double* bufs[2] = {B.y0, B.y1};
   double* ycur = nullptr;
   int rc;
-  for (int s = 0; s < o.nu_pre; ++s) {
-    double* dst = bufs[s & 1];
-    const double* yo = ycur;
+  const bool pairs = o.pair_sweeps && jacobi_pair_supported(v, h->stream);
+  for (int s = 0; s < o.nu_pre;) {
     // the last pre-smoothing sweep also restricts the residual it leaves,
     // R (L+L^T)(y_prev - y), except where the finest residual is formed in FP64
-    double* rc_out = (s == o.nu_pre - 1 && !B.res) ? C.b : nullptr;
+    const int last = pairs && s + 1 < o.nu_pre ? s + 1 : s;
+    double* rc_out = (last == o.nu_pre - 1 && !B.res) ? C.b : nullptr;
+    const double* yo = ycur;
+    if (last > s) {
+      double* d1 = bufs[s & 1];
+      double* d2 = bufs[last & 1];
+      rc = timed_kernel(h, 1, [&] { return sweep_pair(h, v, b, yo, nullptr, d1, d2, rc_out); });
+      if (rc) return rc;
+      ycur = d2;
+      s += 2;
+      continue;
+    }
+    double* dst = bufs[s & 1];
     rc = timed_kernel(h, 1, [&] {
       return launch_jacobi(v, b, yo, nullptr, var, dst, h->stream, rc_out);
     });
     if (rc) return rc;
     ycur = dst;
+    ++s;
   }
   if (ycur == nullptr) {
     rc = timed(h, 3, [&] { return launch_restrict(h->p, h->q, v.n, b, var, C.b, h->stream); });
@@ -594,15 +629,26 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
       return launch_interp_add(h->p, h->q, v.n, C.out, var, out, h->stream);
     });
   }
-  for (int s = 0; s < o.nu_post; ++s) {
+  for (int s = 0; s < o.nu_post;) {
     double* dst = (s == o.nu_post - 1) ? out : (ycur == bufs[0] ? bufs[1] : bufs[0]);
     const double* yo = ycur;
     const double* ec = s == 0 ? C.out : nullptr;
+    if (pairs && s + 1 < o.nu_post) {
+      // second sweep: into out if it is the last, else the other buffer
+      double* d2 = (s + 1 == o.nu_post - 1) ? out : (dst == bufs[0] ? bufs[1] : bufs[0]);
+      rc = timed_kernel(h, 1, [&] { return sweep_pair(h, v, b, yo, ec, dst, d2, nullptr); });
+      if (rc) return rc;
+      if (l == 0 && s + 1 == o.nu_post - 1 && !v.fp32) h->top_prev = dst;
+      ycur = d2;
+      s += 2;
+      continue;
+    }
     rc = timed_kernel(h, 1, [&] { return launch_jacobi(v, b, yo, ec, var, dst, h->stream); });
     if (rc) return rc;
     if (l == 0 && s == o.nu_post - 1 && ec == nullptr && !v.fp32 && yo != nullptr)
       h->top_prev = yo;
     ycur = dst;
+    ++s;
   }
   return PITMG_OK;
 }
@@ -962,6 +1008,19 @@ struct FgmresRun {
           break;
         case kFinish: {
           if (h->prof) drain(h);
+          {
+            // a two-sweep launch whose hand-off failed leaves a nonzero word
+            int to = 0;
+            HIPCHK(h, hipMemcpyAsync(&to, h->hand_timeout, sizeof(int), hipMemcpyDeviceToHost,
+                                     h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            if (to) {
+              HIPCHK(h, hipMemsetAsync(h->hand_timeout, 0, sizeof(int), h->stream));
+              return set_err(h, PITMG_ERR_HIP,
+                             to & 2 ? "two-sweep launch: ticket out of range"
+                                    : "two-sweep launch: a hand-off wait timed out");
+            }
+          }
           S = pitmg_stats{};
           S.fallback_at = -1;
           if (zero_rhs) {
@@ -1023,6 +1082,7 @@ void pitmg_default_options(pitmg_options* o) {
   o->stall_steps = 2;
   o->vcycle_graph = 0;
   o->apply_from_sweep = 1;
+  o->pair_sweeps = 1;
 }
 
 int pitmg_autotune(pitmg_handle* h, int* cfg) {
@@ -1255,6 +1315,15 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   if ((rc = dalloc(h, (void**)&h->coarse_its, (size_t)h->coarse_log_cap * sizeof(int))))
     return fail(rc);
   if ((rc = dalloc(h, (void**)&h->fail, sizeof(int)))) return fail(rc);
+  if ((rc = dalloc(h, (void**)&h->hand_ticket, sizeof(unsigned long long))) ||
+      (rc = dalloc(h, (void**)&h->hand_flag, (size_t)(h->n + 1) * sizeof(unsigned long long))) ||
+      (rc = dalloc(h, (void**)&h->hand_timeout, sizeof(int))))
+    return fail(rc);
+  if (hipMemsetAsync(h->hand_ticket, 0, sizeof(unsigned long long), h->stream) != hipSuccess ||
+      hipMemsetAsync(h->hand_flag, 0, (size_t)(h->n + 1) * sizeof(unsigned long long),
+                     h->stream) != hipSuccess ||
+      hipMemsetAsync(h->hand_timeout, 0, sizeof(int), h->stream) != hipSuccess)
+    return fail(set_err(h, PITMG_ERR_HIP, "hipMemsetAsync failed"));
   rc = load_and_factor(h, pb);
   *hp = h;
   return rc;
@@ -1513,6 +1582,9 @@ void pitmg_destroy(pitmg_handle* h) {
   release(h->Qb);
   if (h->its_pinned) (void)hipHostFree(h->its_pinned);
   release(h->fail);
+  release(h->hand_ticket);
+  release(h->hand_flag);
+  release(h->hand_timeout);
   delete h;
 }
 

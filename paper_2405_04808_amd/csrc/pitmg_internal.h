@@ -122,6 +122,27 @@ hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold
 // launchers follow L.fp32 for the arithmetic.  restrict_out as in
 // launch_jacobi (the restriction fused into the sweep).
 bool jacobi_tiled_supported(int p, int q);
+// Hand-off state of the two-sweep kernel (device words owned by the handle).
+struct PairSync {
+  unsigned long long* ticket;  // ticket counter; only grows
+  unsigned long long base;     // its value when this launch starts
+  unsigned long long* flag;    // [n+1]: epoch of each block's published first sweep
+  unsigned long long epoch;    // this launch's epoch, above every earlier one
+  int* timeout;                // bit 0: a wait ran out; bit 1: a ticket out of range
+};
+// Two consecutive sweeps in one launch (y1 = first, y2 = second sweep; the
+// coarse correction, if any, folds into the first, the restriction, if any,
+// comes from the second) for levels that sweep with the one-step tiled
+// kernel.  jacobi_pair_supported says whether launch_jacobi_pair applies
+// (never while the stream is being captured: the tickets and epochs are
+// launch arguments).
+bool jacobi_pair_supported(const LevelView& L, hipStream_t s);
+hipError_t launch_jacobi_pair(const LevelView& L, const double* b, const double* yold,
+                              const double* ecoarse, int variant, double* y1, double* y2,
+                              double* restrict_out, const PairSync& ps, hipStream_t s);
+hipError_t launch_jacobi_tiled2(const LevelView& L, const double* b, const double* yold,
+                                const double* ecoarse, int variant, double* y1, double* y2,
+                                double* restrict_out, const PairSync& ps, hipStream_t s);
 hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
                                const double* ecoarse, int variant, double* ynew,
                                double* restrict_out, hipStream_t s);

@@ -146,6 +146,218 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
 }
 
 // ---------------------------------------------------------------------------
+// Two consecutive sweeps in one launch, one step per work-group.  The second
+// sweep of block k needs only two values of the first: mu_k (block k+1) and
+// u_{k-1} (block k-1), so the work-group keeps N_k and G_k^{-1} in registers,
+// publishes its first-sweep block, waits for its two neighbours' and solves
+// again.  Same arithmetic in the same order as two k_jacobi_tiled launches.
+//
+// The two coupling values a neighbour reads (u_k, mu_{k-1}) are stored and
+// loaded as device-scope relaxed atomics, which the L2 of each XCD does not
+// hold back: a store is acknowledged once it is visible device-wide, and a
+// load reads the device-wide value.  A work-group waits for the
+// acknowledgement of its coupling stores (vmcnt(0)) before its flag goes out,
+// and reads the neighbours' only after their flags, so no cache-wide
+// write-back or invalidation is needed.  The other first-sweep values are
+// read by no other work-group of the launch and are plain stores.
+//
+// y2 may be the buffer of yold: a work-group writes its second-sweep block
+// only after both readers of that block's first-sweep couplings (the
+// neighbours) have published, i.e. finished reading yold.
+//
+// Work-groups take their block from a ticket counter that only grows (the
+// handle's launches are stream-ordered, so this launch owns tickets base ..
+// base+n).  A work-group waits only for first sweeps, which never wait, of
+// blocks whose tickets are drawn (t-1) or will be drawn once a lower ticket's
+// work-group has finished (t+1); the grid therefore drains whatever number
+// of work-groups is resident.  Each wait also ends after kPairSpinTicks of
+// the 100 MHz clock and raises *timeout, so every wave exits.
+// ---------------------------------------------------------------------------
+
+namespace {
+constexpr unsigned long long kPairSpinTicks = 200000000ull;   // 2 s
+
+__device__ __forceinline__ void coherent_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double coherent_load(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// thread 0: wait until *f >= epoch; returns false on timeout
+__device__ bool pair_wait(const unsigned long long* f, unsigned long long epoch) {
+  const unsigned long long t0 = wall_clock64();
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    if (wall_clock64() - t0 > kPairSpinTicks) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+}  // namespace
+
+template <int RT, int CT, class T>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
+    LevelView L, const double* __restrict__ b, const double* yold,
+    const double* __restrict__ ec, int variant, double* y1, double* y2, FusedRestrict fr,
+    PairSync ps) {
+  using TS = TiledSolve<RT, CT, T>;
+  constexpr int P = TS::P;
+  static_assert(P <= kTiledThreads, "one entry per thread");
+  __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P];
+  __shared__ T scr[TS::kScratch];
+  __shared__ int skb;
+  const int tid = threadIdx.x;
+  const int n = L.n;
+  const TypeMajor Tm(P, P, n);
+  const int nc = n / 2;
+  const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
+  if (tid == 0) {
+    const unsigned long long t = atomicAdd(ps.ticket, 1ull) - ps.base;
+    skb = t <= (unsigned long long)n ? (int)t : -1;
+  }
+  __syncthreads();
+  const int kb = skb;
+  if (kb < 0) {                                // more tickets than blocks: a fault
+    if (tid == 0) atomicOr(ps.timeout, 2);
+    return;
+  }
+  const bool on = tid < P;
+  const int i = tid;
+
+  // first sweep's couplings: previous iterate plus the interpolated coarse
+  // correction (first post-smoothing sweep)
+  auto cu = [&](int k1) -> double {
+    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
+    if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
+    return v;
+  };
+  auto cm = [&](int k1) -> double {
+    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
+    if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
+    return v;
+  };
+  // publish this block's first sweep, then wait for the neighbours' (lo, hi:
+  // block indices kb-1 and kb+1, or -1)
+  auto hand_off = [&](int lo, int hi) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);        // vmcnt(0): coupling stores acknowledged
+    __syncthreads();
+    if (tid == 0) {
+      __hip_atomic_store(ps.flag + kb, ps.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bool ok = true;
+      if (lo >= 0) ok = pair_wait(ps.flag + lo, ps.epoch) && ok;
+      if (hi >= 0) ok = pair_wait(ps.flag + hi, ps.epoch) && ok;
+      if (!ok) atomicOr(ps.timeout, 1);
+    }
+    __syncthreads();
+  };
+
+  if (kb == n) {                               // block n+1 = (v_n, mu_n)
+    double rvv = 0.0, mo1 = 0.0;
+    if (on) {
+      rvv = b[Tm.v + (long long)(n - 1) * P + i];
+      const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n);
+      mo1 = -rmm - rvv;
+      y1[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+      coherent_store(y1 + Tm.m + (long long)(n - 1) * P + i, mo1);   // read by block n
+    }
+    hand_off(n - 1, -1);
+    const int mu_m = fr.u_writer(n + 1);
+    if (on) {
+      const double rmm =
+          b[Tm.m + (long long)(n - 1) * P + i] - coherent_load(y1 + Tm.u + (long long)(n - 1) * P + i);
+      const double mo = -rmm - rvv;
+      y2[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+      y2[Tm.m + (long long)(n - 1) * P + i] = mo;
+      if (mu_m) fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] = mo1 - mo;
+    }
+    return;
+  }
+  const int k = kb + 1;
+  const bool hv = k >= 2;
+  const long long kk = k - 1;
+  typename TS::Regs R;
+  TS::load(L, kk, R);
+  double bu = 0.0, bm = 0.0;
+  if (on) {
+    bu = b[Tm.u + kk * P + i];
+    sru[i] = (T)(bu - cm(k));
+    srl[i] = (T)b[Tm.l + kk * P + i];
+    srz[i] = (T)b[Tm.z + kk * P + i];
+    if (hv) {
+      srv[i] = (T)b[Tm.v + (kk - 1) * P + i];
+      bm = b[Tm.m + (kk - 1) * P + i];
+      srm[i] = (T)(bm - cu(k - 1));
+    } else {
+      srv[i] = 0;
+      srm[i] = 0;
+    }
+  }
+  __syncthreads();
+  TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
+  double uo1 = 0.0, mo1 = 0.0;
+  if (on) {
+    uo1 = (double)TS::u_of(scr, sru, i);
+    coherent_store(y1 + Tm.u + kk * P + i, uo1);                    // read by block k+1
+    y1[Tm.z + kk * P + i] = (double)TS::z_of(scr, srz, i);
+    y1[Tm.l + kk * P + i] = (double)slam[i];
+    if (hv) {
+      mo1 = (double)TS::mu_of(scr, srm, srv, i);
+      coherent_store(y1 + Tm.m + (kk - 1) * P + i, mo1);            // read by block k-1
+      y1[Tm.v + (kk - 1) * P + i] = -(double)srm[i];
+    }
+  }
+  hand_off(hv ? kb - 1 : -1, kb + 1);
+  // second sweep: r_u = b_u,k - mu_k, r_mu = b_mu,k-1 - u_{k-1} of the first
+  if (on) {
+    sru[i] = (T)(bu - coherent_load(y1 + Tm.m + kk * P + i));
+    if (hv) srm[i] = (T)(bm - coherent_load(y1 + Tm.u + (kk - 1) * P + i));
+  }
+  __syncthreads();
+  TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
+  const int rm_m = fr.mu_writer(k), ru_m = fr.u_writer(k);
+  if (on) {
+    const double uo = (double)TS::u_of(scr, sru, i);
+    y2[Tm.u + kk * P + i] = uo;
+    y2[Tm.z + kk * P + i] = (double)TS::z_of(scr, srz, i);
+    y2[Tm.l + kk * P + i] = (double)slam[i];
+    if (hv) {
+      const double mo = (double)TS::mu_of(scr, srm, srv, i);
+      y2[Tm.m + (kk - 1) * P + i] = mo;
+      y2[Tm.v + (kk - 1) * P + i] = -(double)srm[i];
+      if (ru_m) fr.rc[Tc.u + (long long)(ru_m - 1) * P + i] = mo1 - mo;
+    }
+    if (rm_m) {
+      const long long o = (long long)(rm_m - 1) * P + i;
+      fr.rc[Tc.m + o] = uo1 - uo;
+      fr.rc[Tc.v + o] = 0.0;
+      fr.rc[Tc.z + o] = 0.0;
+      fr.rc[Tc.l + o] = 0.0;
+    }
+  }
+}
+
+template <class T>
+static hipError_t launch_tiled2_t(const LevelView& L, const double* b, const double* yold,
+                                  const double* ecoarse, int variant, double* y1, double* y2,
+                                  FusedRestrict fr, const PairSync& ps, hipStream_t s) {
+  if (L.p == 128 && L.q == 128)
+    return launch_k(k_jacobi_tiled2<4, 8, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b,
+                    yold, ecoarse, variant, y1, y2, fr, ps);
+  if (L.p == 64 && L.q == 64)
+    return launch_k(k_jacobi_tiled2<2, 4, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b,
+                    yold, ecoarse, variant, y1, y2, fr, ps);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_jacobi_tiled2(const LevelView& L, const double* b, const double* yold,
+                                const double* ecoarse, int variant, double* y1, double* y2,
+                                double* restrict_out, const PairSync& ps, hipStream_t s) {
+  const FusedRestrict fr{restrict_out, variant};
+  return L.fp32 ? launch_tiled2_t<float>(L, b, yold, ecoarse, variant, y1, y2, fr, ps, s)
+                : launch_tiled2_t<double>(L, b, yold, ecoarse, variant, y1, y2, fr, ps, s);
+}
+
+// ---------------------------------------------------------------------------
 // Sweep for V_k and Z~_k shared by every step (stride 0, the theta = 1 case).
 //
 // A work-group takes up to kMaxSteps consecutive steps.  The products with

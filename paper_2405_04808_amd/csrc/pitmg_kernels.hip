@@ -335,6 +335,30 @@ hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold
   return launch_restrict_delta(L.p, L.q, L.n, yold, ynew, variant, restrict_out, s);
 }
 
+static bool sweeps_tiled(const LevelView& L) {
+  const bool al = L.fp32 ? aligned16(L.N32) && aligned16(L.V32) && aligned16(L.Z32) &&
+                               aligned16(L.Gi32)
+                         : aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi);
+  if (small_supported(L.p, L.q) || !al) return false;
+  if (jacobi_shared_supported(L) && L.sweep_cfg >= 0) return false;
+  return jacobi_tiled_supported(L.p, L.q);
+}
+
+bool jacobi_pair_supported(const LevelView& L, hipStream_t s) {
+  if (!sweeps_tiled(L)) return false;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st == hipStreamCaptureStatusNone;
+}
+
+hipError_t launch_jacobi_pair(const LevelView& L, const double* b, const double* yold,
+                              const double* ecoarse, int variant, double* y1, double* y2,
+                              double* restrict_out, const PairSync& ps, hipStream_t s) {
+  if (!sweeps_tiled(L) || !ps.ticket || !ps.flag || !ps.timeout) return hipErrorNotSupported;
+  if (y1 == y2 || y1 == yold || y1 == b || y2 == b) return hipErrorInvalidValue;
+  return launch_jacobi_tiled2(L, b, yold, ecoarse, variant, y1, y2, restrict_out, ps, s);
+}
+
 // ---------------------------------------------------------------------------
 // K4: out = beta*b + alpha*(A~ x), one work-group per time step
 // ---------------------------------------------------------------------------

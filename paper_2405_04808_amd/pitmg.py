@@ -43,7 +43,8 @@ class pitmg_options(C.Structure):
                 ("restart", C.c_int), ("maxit", C.c_int), ("transfer_variant", C.c_int),
                 ("smoother_fp32", C.c_int), ("coarse_mode", C.c_int), ("stall_ratio", C.c_double),
                 ("stall_steps", C.c_int), ("vcycle_graph", C.c_int),
-                ("apply_from_sweep", C.c_int)]
+                ("apply_from_sweep", C.c_int),
+                ("pair_sweeps", C.c_int)]
 
 
 class pitmg_stats(C.Structure):
