@@ -564,7 +564,7 @@ hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, cons
   const hipError_t e = launch_jacobi_pair(v, b, yo, ec, h->opt.transfer_variant, y1, y2,
                                           rc_out, ps, h->stream);
   if (e == hipSuccess) {
-    h->hand_tickets += (unsigned long long)v.n + 1;
+    h->hand_tickets += (unsigned long long)v.n;   // one work-group per block 1..n
     h->hand_epoch += 1;
   }
   return e;

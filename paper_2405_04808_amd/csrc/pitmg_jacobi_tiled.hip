@@ -167,7 +167,7 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
 //
 // Work-groups take their block from a ticket counter that only grows (the
 // handle's launches are stream-ordered, so this launch owns tickets base ..
-// base+n).  A work-group waits only for first sweeps, which never wait, of
+// base+n-1; the work-group of block n also takes block n+1).  A work-group waits only for first sweeps, which never wait, of
 // blocks whose tickets are drawn (t-1) or will be drawn once a lower ticket's
 // work-group has finished (t+1); the grid therefore drains whatever number
 // of work-groups is resident.  Each wait also ends after kPairSpinTicks of
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
   if (tid == 0) {
     const unsigned long long t = atomicAdd(ps.ticket, 1ull) - ps.base;
-    skb = t <= (unsigned long long)n ? (int)t : -1;
+    skb = t < (unsigned long long)n ? (int)t : -1;
   }
   __syncthreads();
   const int kb = skb;
@@ -251,27 +251,6 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
     __syncthreads();
   };
 
-  if (kb == n) {                               // block n+1 = (v_n, mu_n)
-    double rvv = 0.0, mo1 = 0.0;
-    if (on) {
-      rvv = b[Tm.v + (long long)(n - 1) * P + i];
-      const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n);
-      mo1 = -rmm - rvv;
-      y1[Tm.v + (long long)(n - 1) * P + i] = -rmm;
-      coherent_store(y1 + Tm.m + (long long)(n - 1) * P + i, mo1);   // read by block n
-    }
-    hand_off(n - 1, -1);
-    const int mu_m = fr.u_writer(n + 1);
-    if (on) {
-      const double rmm =
-          b[Tm.m + (long long)(n - 1) * P + i] - coherent_load(y1 + Tm.u + (long long)(n - 1) * P + i);
-      const double mo = -rmm - rvv;
-      y2[Tm.v + (long long)(n - 1) * P + i] = -rmm;
-      y2[Tm.m + (long long)(n - 1) * P + i] = mo;
-      if (mu_m) fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] = mo1 - mo;
-    }
-    return;
-  }
   const int k = kb + 1;
   const bool hv = k >= 2;
   const long long kk = k - 1;
@@ -294,6 +273,18 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   }
   __syncthreads();
   TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
+  // the work-group of block n also takes block n+1 = (v_n, mu_n), whose
+  // only coupling is u_n of block n: no other work-group reads it, and
+  // block n's second sweep takes mu_n from this thread's register
+  const bool tail = kb == n - 1;
+  double rvn = 0.0, mon1 = 0.0;
+  if (tail && on) {
+    rvn = b[Tm.v + (long long)(n - 1) * P + i];
+    const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n);
+    mon1 = -rmm - rvn;
+    y1[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+    y1[Tm.m + (long long)(n - 1) * P + i] = mon1;
+  }
   double uo1 = 0.0, mo1 = 0.0;
   if (on) {
     uo1 = (double)TS::u_of(scr, sru, i);
@@ -306,10 +297,10 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
       y1[Tm.v + (kk - 1) * P + i] = -(double)srm[i];
     }
   }
-  hand_off(hv ? kb - 1 : -1, kb + 1);
+  hand_off(hv ? kb - 1 : -1, tail ? -1 : kb + 1);
   // second sweep: r_u = b_u,k - mu_k, r_mu = b_mu,k-1 - u_{k-1} of the first
   if (on) {
-    sru[i] = (T)(bu - coherent_load(y1 + Tm.m + kk * P + i));
+    sru[i] = (T)(bu - (tail ? mon1 : coherent_load(y1 + Tm.m + kk * P + i)));
     if (hv) srm[i] = (T)(bm - coherent_load(y1 + Tm.u + (kk - 1) * P + i));
   }
   __syncthreads();
@@ -334,6 +325,14 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
       fr.rc[Tc.l + o] = 0.0;
     }
   }
+  if (tail && on) {                            // block n+1, second sweep
+    const int mu_m = fr.u_writer(n + 1);
+    const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - uo1;
+    const double mo = -rmm - rvn;
+    y2[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+    y2[Tm.m + (long long)(n - 1) * P + i] = mo;
+    if (mu_m) fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] = mon1 - mo;
+  }
 }
 
 template <class T>
@@ -341,10 +340,10 @@ static hipError_t launch_tiled2_t(const LevelView& L, const double* b, const dou
                                   const double* ecoarse, int variant, double* y1, double* y2,
                                   FusedRestrict fr, const PairSync& ps, hipStream_t s) {
   if (L.p == 128 && L.q == 128)
-    return launch_k(k_jacobi_tiled2<4, 8, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b,
+    return launch_k(k_jacobi_tiled2<4, 8, T>, dim3(L.n), dim3(kTiledThreads), 0, s, L, b,
                     yold, ecoarse, variant, y1, y2, fr, ps);
   if (L.p == 64 && L.q == 64)
-    return launch_k(k_jacobi_tiled2<2, 4, T>, dim3(L.n + 1), dim3(kTiledThreads), 0, s, L, b,
+    return launch_k(k_jacobi_tiled2<2, 4, T>, dim3(L.n), dim3(kTiledThreads), 0, s, L, b,
                     yold, ecoarse, variant, y1, y2, fr, ps);
   return hipErrorInvalidValue;
 }
