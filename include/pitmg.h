@@ -137,7 +137,12 @@ typedef struct {
                                   is block tridiagonal, so a block Jacobi
                                   sweep of Sec. 5.3.2 couples block k only to
                                   k-1 and k+1).  Results are bitwise those of
-                                  two launches.  0: one sweep per launch.      */
+                                  two launches.  Each neighbour wait is
+                                  bounded (2 s); one that runs out marks the
+                                  handle, and the FGMRES solve that contains
+                                  it returns PITMG_ERR_HIP.  Streams under
+                                  capture get one sweep per launch.
+                                  0: one sweep per launch.                     */
 } pitmg_options;
 
 typedef struct {

@@ -1108,13 +1108,23 @@ int pitmg_autotune(pitmg_handle* h, int* cfg) {
     HIPCHK(h, hipMemsetAsync(B.y1, 0, B.len * 8, h->stream));
     float best = 1e30f;
     int pick = 0;
+    // second output of a two-sweep launch (contents are scratch here)
+    double* y2 = l == 0 ? h->r : B.out;
     for (int c : cands) {
       B.sweep_cfg = c;
       v = view(h, l);
-      for (int r = 0; r < kReps + 2; ++r) {
+      // the one-step shape runs two sweeps per launch when the V-cycle would:
+      // time kReps sweeps either way
+      const bool two = c == -1 && h->opt.pair_sweeps && y2 &&
+                       jacobi_pair_supported(v, h->stream);
+      const int launches = two ? kReps / 2 : kReps;
+      for (int r = 0; r < launches + 2; ++r) {
         if (r == 2) HIPCHK(h, hipEventRecord(e0, h->stream));
-        HIPCHK(h, launch_jacobi(v, B.y1, B.y1, nullptr, h->opt.transfer_variant, B.y0,
-                                h->stream));
+        if (two)
+          HIPCHK(h, sweep_pair(h, v, B.y1, B.y1, nullptr, B.y0, y2, nullptr));
+        else
+          HIPCHK(h, launch_jacobi(v, B.y1, B.y1, nullptr, h->opt.transfer_variant, B.y0,
+                                  h->stream));
       }
       HIPCHK(h, hipEventRecord(e1, h->stream));
       HIPCHK(h, hipEventSynchronize(e1));
