@@ -86,11 +86,25 @@ def pair_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8, with_restr
     return one + float(n * ((4 * p + q) + 2 * p) * 8 + (2 * p + p) * 8)
 
 
-def level_pairs(p, q, L, shapes, pair_sweeps):
-    """Per level above the coarsest: True where two sweeps share a launch
-    (levels swept by the one-step tiled kernel, p = q in {64, 128})."""
+def level_pairs(p, q, L, shapes, pair_sweeps, shared=True, fp32_levels=0):
+    """Per level above the coarsest: how two sweeps share a launch, or None.
+    "tiled": the one-step kernel (p = q in {64, 128}), which keeps each
+    step's blocks in registers for both sweeps; "shared": the FP64
+    shared-block kernel (shape 1-4, or the built-in rule 0, with shared V
+    and Z~), which reads its blocks again for the second sweep."""
     ok = pair_sweeps and p == q and p in (64, 128)
-    return [bool(ok and shapes[lev] == -1) for lev in range(L - 1)]
+    out = []
+    for lev in range(L - 1):
+        c = shapes[lev]
+        if not ok:
+            out.append(None)
+        elif c == -1 or not shared:
+            out.append("tiled")
+        elif lev >= fp32_levels:
+            out.append("shared")
+        else:
+            out.append(None)
+    return out
 
 
 def vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes=8,
@@ -106,11 +120,19 @@ def vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_by
         for nu, pre in ((nu_pre, True), (nu_post, False)):
             s_ = 0
             while s_ < nu:
-                two = pairs[lev] and s_ + 1 < nu
+                two = pairs[lev] is not None and s_ + 1 < nu
                 last = s_ + 1 if two else s_
                 kw = dict(with_coarse=(not pre) and s_ == 0, mat_bytes=mat_bytes,
                           with_restrict=pre and fused and last == nu - 1)
-                tot += (pair_bytes if two else sweep_bytes)(p, q, nl, shared_V, shared_Z, **kw)
+                if two and pairs[lev] == "tiled":
+                    tot += pair_bytes(p, q, nl, shared_V, shared_Z, **kw)
+                elif two:                  # shared-block pair: two sweeps' bytes
+                    tot += sweep_bytes(p, q, nl, shared_V, shared_Z, kw["with_coarse"],
+                                       mat_bytes)
+                    tot += sweep_bytes(p, q, nl, shared_V, shared_Z, False, mat_bytes,
+                                       kw["with_restrict"])
+                else:
+                    tot += sweep_bytes(p, q, nl, shared_V, shared_Z, **kw)
                 launches += 1
                 s_ = last + 1
         if not fused:
@@ -125,7 +147,7 @@ def vcycle_bytes(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, mat_bytes=8, f
     right-hand side written), the coarse right-hand side and correction, and,
     with an FP32 smoother, the explicit FP64 finest residual (blocks and two
     vectors read, one written)."""
-    pairs = pairs or [False] * (L - 1)
+    pairs = pairs or [None] * (L - 1)
     tot, _ = vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes,
                            fp64_residual)
     nc = n >> (L - 1)
@@ -374,7 +396,7 @@ def main():
     ok = all(s["converged"] == 1 and s["relres_true"] <= 1.01e-10 for s in stats)
     p, q, n, L = prob.p, prob.q, prob.n, prob.n_levels
     shared_V, shared_Z = solver.shared_V, solver.shared_Z
-    pairs = level_pairs(p, q, L, sweep_shapes, opts.pair_sweeps)
+    pairs = level_pairs(p, q, L, sweep_shapes, opts.pair_sweeps, shared=shared_V and shared_Z)
 
     if args.counters:
         # plain copy kernel of known size for calibrating FETCH_SIZE / WRITE_SIZE
@@ -405,7 +427,9 @@ def main():
         names = {0: "built-in", -1: "k_jacobi_tiled<%d, %d, double>" % (p // 32, p // 16)}
         kname = "block Jacobi sweep, levels 0..%d: " % (L - 2) + ", ".join(
             ("k_jacobi_tiled2<%d, %d, double> (two sweeps per launch)" % (p // 32, p // 16)
-             if pairs[lev] else
+             if pairs[lev] == "tiled" else
+             "k_jacobi_shared_nl2<%d, %d> x%d steps (two sweeps per launch)" % (p // 32, p // 16, c)
+             if pairs[lev] == "shared" else
              names.get(c) or "k_jacobi_shared_nl<%d, %d> x%d steps" % (p // 32, p // 16, c))
             for lev, c in enumerate(sweep_shapes[:L - 1]))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -561,10 +561,11 @@ hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, cons
                       const double* ec, double* y1, double* y2, double* rc_out) {
   const PairSync ps{h->hand_ticket, h->hand_tickets, h->hand_flag, h->hand_epoch + 1,
                     h->hand_timeout};
+  int groups = 0;
   const hipError_t e = launch_jacobi_pair(v, b, yo, ec, h->opt.transfer_variant, y1, y2,
-                                          rc_out, ps, h->stream);
+                                          rc_out, ps, &groups, h->stream);
   if (e == hipSuccess) {
-    h->hand_tickets += (unsigned long long)v.n;   // one work-group per block 1..n
+    h->hand_tickets += (unsigned long long)groups;
     h->hand_epoch += 1;
   }
   return e;
@@ -1113,10 +1114,9 @@ int pitmg_autotune(pitmg_handle* h, int* cfg) {
     for (int c : cands) {
       B.sweep_cfg = c;
       v = view(h, l);
-      // the one-step shape runs two sweeps per launch when the V-cycle would:
+      // a shape runs two sweeps per launch when the V-cycle would pair it:
       // time kReps sweeps either way
-      const bool two = c == -1 && h->opt.pair_sweeps && y2 &&
-                       jacobi_pair_supported(v, h->stream);
+      const bool two = h->opt.pair_sweeps && y2 && jacobi_pair_supported(v, h->stream);
       const int launches = two ? kReps / 2 : kReps;
       for (int r = 0; r < launches + 2; ++r) {
         if (r == 2) HIPCHK(h, hipEventRecord(e0, h->stream));

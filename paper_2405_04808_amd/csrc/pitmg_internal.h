@@ -133,13 +133,19 @@ struct PairSync {
 // Two consecutive sweeps in one launch (y1 = first, y2 = second sweep; the
 // coarse correction, if any, folds into the first, the restriction, if any,
 // comes from the second) for levels that sweep with the one-step tiled
-// kernel.  jacobi_pair_supported says whether launch_jacobi_pair applies
+// kernel or, in FP64, the shared-block kernel.  jacobi_pair_supported says whether launch_jacobi_pair applies
 // (never while the stream is being captured: the tickets and epochs are
 // launch arguments).
 bool jacobi_pair_supported(const LevelView& L, hipStream_t s);
+// *groups: work-groups (tickets) of the launch, set whenever it is issued.
 hipError_t launch_jacobi_pair(const LevelView& L, const double* b, const double* yold,
                               const double* ecoarse, int variant, double* y1, double* y2,
-                              double* restrict_out, const PairSync& ps, hipStream_t s);
+                              double* restrict_out, const PairSync& ps, int* groups,
+                              hipStream_t s);
+hipError_t launch_jacobi_shared2(const LevelView& L, const double* b, const double* yold,
+                                 const double* ecoarse, int variant, double* y1, double* y2,
+                                 double* restrict_out, const PairSync& ps, int* groups,
+                                 hipStream_t s);
 hipError_t launch_jacobi_tiled2(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* y1, double* y2,
                                 double* restrict_out, const PairSync& ps, hipStream_t s);

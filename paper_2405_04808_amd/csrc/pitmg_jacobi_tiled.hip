@@ -609,11 +609,16 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
 // the same vector-memory counter as the loads the step start waits for.
 // ---------------------------------------------------------------------------
 
+// One sweep of steps k0 .. k0+nb-1 (and block n+1 when the group ends at
+// step n).  In a two-sweep launch, pub makes the two first-sweep values that
+// neighbouring groups read (u of the last step, mu_{k0-1} of the first)
+// device-coherent stores, and xin makes the second sweep read those two
+// couplings of the neighbours with device-coherent loads; every other
+// coupling comes from this work-group's own first sweep.
 template <int RT, int CT>
-__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl(
-    LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
-    const double* __restrict__ ec, int variant, double* __restrict__ ynew, int per_wg,
-    FusedRestrict fr) {
+__device__ __forceinline__ void shared_nl_sweep(
+    const LevelView& L, const double* __restrict__ b, const double* yold, const double* ec,
+    int variant, double* ynew, int k0, int nb, FusedRestrict fr, bool pub, bool xin) {
   using TS = TiledSolve<RT, CT, double>;
   constexpr int P = TS::P;
   constexpr int G = kTiledThreads / P;                   // row groups of the post pass
@@ -632,18 +637,27 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl(
   const TypeMajor Tm(P, P, n);
   const int nc = n / 2;
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
-  const int k0 = blockIdx.x * per_wg + 1;                // first step (1-based)
-  const int nb = min(per_wg, n - k0 + 1);                // steps of this work-group
+  const int klast = k0 + nb - 1;                         // last step of the group
   const double* __restrict__ Vs = L.V;                   // shared blocks
   const double* __restrict__ Zs = L.Z;
 
+  // couplings of the previous iterate; u_{k0-1} and mu_klast (klast < n)
+  // belong to the neighbouring groups
   auto cu = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
+    double v = 0.0;
+    if (yold) {
+      const double* p = yold + Tm.u + (long long)(k1 - 1) * P + i;
+      v = xin && k1 == k0 - 1 ? coherent_load(p) : *p;
+    }
     if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
     return v;
   };
   auto cm = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
+    double v = 0.0;
+    if (yold) {
+      const double* p = yold + Tm.m + (long long)(k1 - 1) * P + i;
+      v = xin && k1 == klast && klast < n ? coherent_load(p) : *p;
+    }
     if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
     return v;
   };
@@ -859,7 +873,10 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl(
       vt += pv[(g * kMaxSteps + s2) * P + i];
     }
     const double uo = sou[s2][i];
-    ynew[Tm.u + kk * P + i] = uo;
+    if (pub && k == klast)
+      coherent_store(ynew + Tm.u + kk * P + i, uo);      // read by the next group
+    else
+      ynew[Tm.u + kk * P + i] = uo;
     ynew[Tm.l + kk * P + i] = slam[s2][i];
     ynew[Tm.z + kk * P + i] = b[Tm.z + kk * P + i] - zt;
     const int rm_m = fr.mu_writer(k);
@@ -873,7 +890,10 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl(
     if (k >= 2) {
       const double rm = b[Tm.m + (kk - 1) * P + i] - cu(k - 1, i);
       const double mo = vt - rm - b[Tm.v + (kk - 1) * P + i];
-      ynew[Tm.m + (kk - 1) * P + i] = mo;
+      if (pub && k == k0)
+        coherent_store(ynew + Tm.m + (kk - 1) * P + i, mo);   // read by the previous group
+      else
+        ynew[Tm.m + (kk - 1) * P + i] = mo;
       ynew[Tm.v + (kk - 1) * P + i] = -rm;
       const int ru_m = fr.u_writer(k);
       if (ru_m)
@@ -881,6 +901,57 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl(
             (yold ? yold[Tm.m + (kk - 1) * P + i] : 0.0) - mo;
     }
   }
+}
+
+template <int RT, int CT>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl(
+    LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
+    const double* __restrict__ ec, int variant, double* __restrict__ ynew, int per_wg,
+    FusedRestrict fr) {
+  const int k0 = blockIdx.x * per_wg + 1;                // first step (1-based)
+  shared_nl_sweep<RT, CT>(L, b, yold, ec, variant, ynew, k0, min(per_wg, L.n - k0 + 1), fr,
+                          false, false);
+}
+
+// Two consecutive sweeps of the shared-block kernel in one launch: the
+// group's second sweep needs, besides its own first sweep, only u at the
+// previous group's last step and mu at the next group's first block.
+// Groups draw their index from the ticket counter and hand off as in
+// k_jacobi_tiled2 (same deadlock-freedom argument, bounded waits); the
+// group's tiles are loaded again for the second sweep.
+template <int RT, int CT>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl2(
+    LevelView L, const double* __restrict__ b, const double* yold,
+    const double* __restrict__ ec, int variant, double* y1, double* y2, int per_wg,
+    FusedRestrict fr, PairSync ps) {
+  __shared__ int sg;
+  const int tid = threadIdx.x;
+  const int ng = (L.n + per_wg - 1) / per_wg;
+  if (tid == 0) {
+    const unsigned long long t = atomicAdd(ps.ticket, 1ull) - ps.base;
+    sg = t < (unsigned long long)ng ? (int)t : -1;
+  }
+  __syncthreads();
+  const int g = sg;
+  if (g < 0) {                                 // more tickets than groups: a fault
+    if (tid == 0) atomicOr(ps.timeout, 2);
+    return;
+  }
+  const int k0 = g * per_wg + 1;
+  const int nb = min(per_wg, L.n - k0 + 1);
+  shared_nl_sweep<RT, CT>(L, b, yold, ec, variant, y1, k0, nb, FusedRestrict{nullptr, variant},
+                          true, false);
+  __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): boundary stores acknowledged
+  __syncthreads();
+  if (tid == 0) {
+    __hip_atomic_store(ps.flag + g, ps.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool ok = true;
+    if (g > 0) ok = pair_wait(ps.flag + g - 1, ps.epoch) && ok;
+    if (g + 1 < ng) ok = pair_wait(ps.flag + g + 1, ps.epoch) && ok;
+    if (!ok) atomicOr(ps.timeout, 1);
+  }
+  __syncthreads();
+  shared_nl_sweep<RT, CT>(L, b, y1, nullptr, variant, y2, k0, nb, fr, false, true);
 }
 
 bool jacobi_shared_supported(const LevelView& L) {
@@ -912,15 +983,38 @@ static hipError_t launch_shared_t(const LevelView& L, const double* b, const dou
   return hipGetLastError();
 }
 
+// steps per work-group of the shared-block sweep: the tuned choice, else
+// enough to keep the grid near one work-group per CU
+int shared_steps_per_group(const LevelView& L) {
+  int per = L.sweep_cfg > 0 ? L.sweep_cfg : (L.n + 255) / 256;
+  if (per > kMaxSteps) per = kMaxSteps;
+  if (per < 1) per = 1;
+  return per;
+}
+
+hipError_t launch_jacobi_shared2(const LevelView& L, const double* b, const double* yold,
+                                 const double* ecoarse, int variant, double* y1, double* y2,
+                                 double* restrict_out, const PairSync& ps, int* groups,
+                                 hipStream_t s) {
+  const FusedRestrict fr{restrict_out, variant};
+  const int per = shared_steps_per_group(L);
+  const int nwg = (L.n + per - 1) / per;
+  *groups = nwg;
+  if (L.fp32) return hipErrorNotSupported;
+  if (L.p == 128)
+    return launch_k(k_jacobi_shared_nl2<4, 8>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
+                    ecoarse, variant, y1, y2, per, fr, ps);
+  if (L.p == 64)
+    return launch_k(k_jacobi_shared_nl2<2, 4>, dim3(nwg), dim3(kTiledThreads), 0, s, L, b, yold,
+                    ecoarse, variant, y1, y2, per, fr, ps);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* ynew,
                                 double* restrict_out, hipStream_t s) {
   const FusedRestrict fr{restrict_out, variant};
-  // steps per work-group: the tuned choice, else enough to keep the grid
-  // near one work-group per CU
-  int per = L.sweep_cfg > 0 ? L.sweep_cfg : (L.n + 255) / 256;
-  if (per > kMaxSteps) per = kMaxSteps;
-  if (per < 1) per = 1;
+  const int per = shared_steps_per_group(L);
   return L.fp32 ? launch_shared_t<float>(L, b, yold, ecoarse, variant, ynew, per, fr, s)
                 : launch_shared_t<double>(L, b, yold, ecoarse, variant, ynew, per, fr, s);
 }

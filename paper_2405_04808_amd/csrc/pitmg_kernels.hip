@@ -344,8 +344,14 @@ static bool sweeps_tiled(const LevelView& L) {
   return jacobi_tiled_supported(L.p, L.q);
 }
 
+static bool sweeps_shared_fp64(const LevelView& L) {
+  if (L.fp32 || small_supported(L.p, L.q)) return false;
+  if (!(aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi))) return false;
+  return jacobi_shared_supported(L) && L.sweep_cfg >= 0;
+}
+
 bool jacobi_pair_supported(const LevelView& L, hipStream_t s) {
-  if (!sweeps_tiled(L)) return false;
+  if (!sweeps_tiled(L) && !sweeps_shared_fp64(L)) return false;
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
   return st == hipStreamCaptureStatusNone;
@@ -353,9 +359,16 @@ bool jacobi_pair_supported(const LevelView& L, hipStream_t s) {
 
 hipError_t launch_jacobi_pair(const LevelView& L, const double* b, const double* yold,
                               const double* ecoarse, int variant, double* y1, double* y2,
-                              double* restrict_out, const PairSync& ps, hipStream_t s) {
-  if (!sweeps_tiled(L) || !ps.ticket || !ps.flag || !ps.timeout) return hipErrorNotSupported;
+                              double* restrict_out, const PairSync& ps, int* groups,
+                              hipStream_t s) {
+  *groups = 0;
+  if (!ps.ticket || !ps.flag || !ps.timeout) return hipErrorNotSupported;
   if (y1 == y2 || y1 == yold || y1 == b || y2 == b) return hipErrorInvalidValue;
+  if (sweeps_shared_fp64(L))
+    return launch_jacobi_shared2(L, b, yold, ecoarse, variant, y1, y2, restrict_out, ps, groups,
+                                 s);
+  if (!sweeps_tiled(L)) return hipErrorNotSupported;
+  *groups = L.n;                                   // one work-group per block 1..n
   return launch_jacobi_tiled2(L, b, yold, ecoarse, variant, y1, y2, restrict_out, ps, s);
 }
 

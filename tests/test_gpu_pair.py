@@ -27,15 +27,15 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
-def tiled_everywhere(s, n_levels):
-    s.set_sweep_shapes([-1] * (n_levels - 1) + [0])
+def tiled_everywhere(s, n_levels, shape=-1):
+    s.set_sweep_shapes([shape] * (n_levels - 1) + [0])
 
 
-def vcycle_pair(prob, r, **opt):
+def vcycle_pair(prob, r, shape=-1, **opt):
     outs = []
     for pair in (0, 1):
         s = pm.Solver(prob.levels, pm.default_options(pair_sweeps=pair, **opt))
-        tiled_everywhere(s, prob.n_levels)
+        tiled_everywhere(s, prob.n_levels, shape)
         outs.append(s.vcycle(dev(r)))
         torch.cuda.synchronize()
         s.close()
@@ -54,6 +54,23 @@ def test_pair_vcycle_bitwise(nx, n, n_levels, nu, variant):
     a, b = vcycle_pair(prob, r, nu_pre=nu[0], nu_post=nu[1], coarse_fixed_its=2,
                        transfer_variant=variant)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("nx,n,n_levels", [(64, 40, 3), (128, 20, 3), (128, 1024, 8)])
+@pytest.mark.parametrize("per", [1, 2, 3, 4])
+@pytest.mark.parametrize("nu", [(2, 2), (3, 1)])
+def test_pair_vcycle_bitwise_shared_block_groups(nx, n, n_levels, per, nu):
+    # the FP64 shared-block sweep with 1-4 steps per work-group, two sweeps
+    # per launch (ragged last groups at n = 20, 40)
+    if n == 1024 and (per not in (3, 4) or nu != (2, 2)):
+        pytest.skip("the large grid runs with the benchmark's sweep counts")
+    prob, rng = make_problem(kind="burgers", nx=nx, nu=0.01, n=n, n_levels=n_levels, seed=36)
+    r = rng.normal(size=prob.size)
+    print(f"pair shared vcycle nx={nx} n={n} per={per} nu={nu}", flush=True)
+    for variant in (0, 1):
+        a, b = vcycle_pair(prob, r, shape=per, nu_pre=nu[0], nu_post=nu[1], coarse_fixed_its=2,
+                           transfer_variant=variant)
+        assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("case", ["fp32", "theta05"])
@@ -94,13 +111,14 @@ def test_pair_vcycle_matches_oracle():
     s.close()
 
 
-def test_pair_fgmres_bitwise():
+@pytest.mark.parametrize("shape", [-1, 3])
+def test_pair_fgmres_bitwise(shape):
     prob, rng = make_problem(kind="burgers", nx=64, nu=0.01, n=64, n_levels=4, seed=35)
     b = make_rhs(prob, rng)
     res = []
     for pair in (0, 1):
         s = pm.Solver(prob.levels, pm.default_options(restart=200, maxit=400, pair_sweeps=pair))
-        tiled_everywhere(s, prob.n_levels)
+        tiled_everywhere(s, prob.n_levels, shape)
         x, st, rc = s.solve(dev(b), tol=1e-10)
         torch.cuda.synchronize()
         assert rc == pm.PITMG_OK
