@@ -127,21 +127,25 @@ typedef struct {
                                   SGS result z = a + d (forward sweep a,
                                   backward correction d) as v + L d;
                                   0: always the explicit product             */
-  int pair_sweeps;             /* 1: on levels that sweep with the one-step
-                                  tiled kernel (p = q in {64, 128}), run two
-                                  consecutive sweeps in one launch: each
-                                  work-group keeps its step's N_k and G_k^{-1}
-                                  in registers and takes the second sweep's
-                                  two coupling values from its neighbours'
-                                  first sweep (the permuted system of Sec. 5.2
-                                  is block tridiagonal, so a block Jacobi
-                                  sweep of Sec. 5.3.2 couples block k only to
-                                  k-1 and k+1).  Results are bitwise those of
-                                  two launches.  Each neighbour wait is
-                                  bounded (2 s); one that runs out marks the
-                                  handle, and the FGMRES solve that contains
-                                  it returns PITMG_ERR_HIP.  Streams under
-                                  capture get one sweep per launch.
+  int pair_sweeps;             /* 1: run two consecutive sweeps of a level in
+                                  one launch where the level sweeps with the
+                                  register-tiled kernels (p = q in {64, 128}:
+                                  the one-step kernel, and in FP64 the kernel
+                                  for V, Z~ shared by every step).  The
+                                  permuted system of Sec. 5.2 is block
+                                  tridiagonal, so a block Jacobi sweep of
+                                  Sec. 5.3.2 couples block k only to k-1 and
+                                  k+1: a work-group takes the second sweep's
+                                  couplings from its own first sweep and, at
+                                  its edges, from its neighbours'.  The
+                                  one-step kernel also keeps N_k and G_k^{-1}
+                                  in registers for both sweeps.  Results are
+                                  bitwise those of two launches.  Each
+                                  neighbour wait is bounded (2 s); one that
+                                  runs out marks the handle, and the FGMRES
+                                  solve that contains it returns
+                                  PITMG_ERR_HIP.  Streams under capture get
+                                  one sweep per launch.
                                   0: one sweep per launch.                     */
 } pitmg_options;
 
