@@ -158,7 +158,8 @@ struct CState {
 // against v_0..v_j (modified Gram-Schmidt), column j of H is rotated, and
 // the stopping test is taken.  ist = {steps done, stop}.  Returns stop.
 template <int NT>
-__device__ bool arnoldi_step(int j, double* wv, double* Vb, long long len, double* cst,
+__device__ bool arnoldi_step(int j, double* __restrict__ wv, double* __restrict__ Vb,
+                             long long len, double* cst,
                              int* ist, CState S, double tol, int fixed_its, int nsteps,
                              double* red, int* sflag) {
   const int tid = threadIdx.x;
@@ -247,13 +248,13 @@ __global__ __launch_bounds__(kCtrlThreads) void k_coarse_arnoldi(int j, double* 
 // L is the identity from u_k into row mu_k (k = 1..n), hence w = v except
 // w_mu = v_mu + d_u (mu0 = offset of the mu segment).
 __global__ __launch_bounds__(kCtrlThreads) void k_coarse_arnoldi_sgs(
-    int j, double* wv, double* Vb, double* __restrict__ zj, const double* __restrict__ a,
-    const double* __restrict__ d, long long mu0, long long len, double* cst, int* ist, int cap,
-    double tol, int fixed_its, int nsteps) {
+    int j, double* __restrict__ wv, double* __restrict__ Vb, double* __restrict__ zj,
+    const double* __restrict__ a, const double* __restrict__ d, long long mu0, long long len,
+    double* cst, int* ist, int cap, double tol, int fixed_its, int nsteps) {
   __shared__ double red[kCtrlThreads / kWave];
   __shared__ int sflag;
   if (ist[1]) return;                          // solved at an earlier step
-  const double* v = Vb + (size_t)j * len;
+  const double* __restrict__ v = Vb + (size_t)j * len;
   for (long long e = threadIdx.x; e < len; e += kCtrlThreads) {
     zj[e] = a[e] + d[e];
     wv[e] = e >= mu0 ? v[e] + d[e - mu0] : v[e];
