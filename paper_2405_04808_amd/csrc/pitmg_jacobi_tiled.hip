@@ -1,6 +1,9 @@
 // Block Jacobi sweep for p = q in {64, 128}: one work-group of 512 threads
-// per time-major block, with N_k and G_k^{-1} in registers (pitmg_tiled.h),
-// so each Jacobian / factor entry is read from HBM once per sweep.
+// per time-major block (or per group of 1-4 blocks when V and Z~ are shared
+// by every step), with N_k and G_k^{-1} in registers (pitmg_tiled.h), so
+// each Jacobian / factor entry is read from HBM once per sweep.  Each kernel
+// also has a form that runs two consecutive sweeps in one launch, handing
+// the two coupling values a neighbour needs across work-groups.
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
 #include "pitmg_tiled.h"
@@ -167,10 +170,11 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
 //
 // Work-groups take their block from a ticket counter that only grows (the
 // handle's launches are stream-ordered, so this launch owns tickets base ..
-// base+n-1; the work-group of block n also takes block n+1).  A work-group waits only for first sweeps, which never wait, of
-// blocks whose tickets are drawn (t-1) or will be drawn once a lower ticket's
-// work-group has finished (t+1); the grid therefore drains whatever number
-// of work-groups is resident.  Each wait also ends after kPairSpinTicks of
+// base+n-1; the work-group of block n also takes block n+1).  A work-group
+// waits only for first sweeps, which never wait, of blocks whose tickets are
+// drawn (t-1) or will be drawn once a lower ticket's work-group has finished
+// (t+1); the grid therefore drains whatever number of work-groups is
+// resident.  Each wait also ends after kPairSpinTicks of
 // the 100 MHz clock and raises *timeout, so every wave exits.
 // ---------------------------------------------------------------------------
 

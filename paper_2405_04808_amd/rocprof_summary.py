@@ -37,12 +37,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SWEEP_SOURCES = ("csrc/pitmg_jacobi_tiled.hip", "csrc/pitmg_tiled.h", "csrc/pitmg_device.h")
 
 
+def _code_only(text: str) -> str:
+    """The source without comments and whitespace: what the compiler sees
+    (string literals in these kernels contain no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return re.sub(r"\s+", "", text)
+
+
 def sweep_source_hash() -> str:
-    """sha256 over the sources of the register-tiled sweep kernels."""
+    """sha256 over the code of the register-tiled sweep kernels (comments and
+    whitespace left out, so documentation edits keep the counters valid)."""
     h = hashlib.sha256()
     for rel in SWEEP_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(HERE, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
