@@ -224,6 +224,14 @@ int pitmg_fgmres_solve_batch(pitmg_handle* const* h, int count, const double* co
  * sweep do not depend on the choice beyond rounding.  Synchronises. */
 int pitmg_autotune(pitmg_handle* h, int* cfg);
 
+/* Bound of each neighbour wait of the two-sweep launches (pair_sweeps), in
+ * seconds; default 2.  For callers that test the error path: a bound of 0
+ * makes a wait fail as soon as its neighbour is not already done, so that
+ * FGMRES solves return PITMG_ERR_HIP ("a hand-off wait timed out") while
+ * every kernel still exits.  Results after a failed wait are not valid.
+ * PITMG_ERR_INVALID outside [0, 60]. */
+int pitmg_set_handoff_wait(pitmg_handle* h, double seconds);
+
 /* Set the sweep launch shapes directly (host array of n_levels entries, same
  * meaning as pitmg_autotune's output; the coarsest entry must be 0): to reuse
  * a tuned choice on another handle of the same shape, or to fix the launch

@@ -122,6 +122,7 @@ struct pitmg_handle {
   int* hand_timeout = nullptr;
   unsigned long long hand_tickets = 0;   // tickets issued so far (host mirror)
   unsigned long long hand_epoch = 0;     // last epoch issued
+  unsigned long long hand_spin = 200000000ull;   // wait bound: 2 s at 100 MHz
 };
 
 namespace {
@@ -499,6 +500,19 @@ int coarse_dispatch(pitmg_handle* h, const double* b, double* out) {
 
 int vcycle_level(pitmg_handle* h, int l, const double* b, double* out);
 
+// A two-sweep launch whose neighbour wait ran out leaves a nonzero word in
+// the handle: report it (and clear it) as the error of the call it ends.
+int handoff_check(pitmg_handle* h) {
+  int to = 0;
+  HIPCHK(h, hipMemcpyAsync(&to, h->hand_timeout, sizeof(int), hipMemcpyDeviceToHost,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (!to) return PITMG_OK;
+  HIPCHK(h, hipMemsetAsync(h->hand_timeout, 0, sizeof(int), h->stream));
+  return set_err(h, PITMG_ERR_HIP, to & 2 ? "two-sweep launch: ticket out of range"
+                                          : "two-sweep launch: a hand-off wait timed out");
+}
+
 void drop_graph(pitmg_handle* h) {
   if (h->g_exec) (void)hipGraphExecDestroy(h->g_exec);
   if (h->g_graph) (void)hipGraphDestroy(h->g_graph);
@@ -560,7 +574,7 @@ int vcycle_top(pitmg_handle* h, const double* r, double* e) {
 hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, const double* yo,
                       const double* ec, double* y1, double* y2, double* rc_out) {
   const PairSync ps{h->hand_ticket, h->hand_tickets, h->hand_flag, h->hand_epoch + 1,
-                    h->hand_timeout};
+                    h->hand_timeout, h->hand_spin};
   int groups = 0;
   const hipError_t e = launch_jacobi_pair(v, b, yo, ec, h->opt.transfer_variant, y1, y2,
                                           rc_out, ps, &groups, h->stream);
@@ -1009,19 +1023,7 @@ struct FgmresRun {
           break;
         case kFinish: {
           if (h->prof) drain(h);
-          {
-            // a two-sweep launch whose hand-off failed leaves a nonzero word
-            int to = 0;
-            HIPCHK(h, hipMemcpyAsync(&to, h->hand_timeout, sizeof(int), hipMemcpyDeviceToHost,
-                                     h->stream));
-            HIPCHK(h, hipStreamSynchronize(h->stream));
-            if (to) {
-              HIPCHK(h, hipMemsetAsync(h->hand_timeout, 0, sizeof(int), h->stream));
-              return set_err(h, PITMG_ERR_HIP,
-                             to & 2 ? "two-sweep launch: ticket out of range"
-                                    : "two-sweep launch: a hand-off wait timed out");
-            }
-          }
+          if (int rc2 = handoff_check(h)) return rc2;
           S = pitmg_stats{};
           S.fallback_at = -1;
           if (zero_rhs) {
@@ -1056,7 +1058,12 @@ struct FgmresRun {
 int run_to_end(FgmresRun& run) {
   for (;;) {
     const int rc = run.advance();
-    if (rc < 0) return rc;
+    if (rc < 0) {
+      // an error that follows a failed hand-off is reported as that failure
+      if (rc == PITMG_ERR_HIP) return rc;
+      const int rh = handoff_check(run.h);
+      return rh ? rh : rc;
+    }
     if (rc == FgmresRun::kFinished) return run.status;
     if (run.h->prof) drain_ready(run.h);   // host work while the device is busy
     HIPCHK(run.h, hipStreamSynchronize(run.h->stream));
@@ -1142,6 +1149,14 @@ int pitmg_autotune(pitmg_handle* h, int* cfg) {
   (void)hipEventDestroy(e1);
   drop_graph(h);
   return rc;
+}
+
+int pitmg_set_handoff_wait(pitmg_handle* h, double seconds) {
+  if (!h) return PITMG_ERR_INVALID;
+  if (!(seconds >= 0.0) || !(seconds <= 60.0))
+    return set_err(h, PITMG_ERR_INVALID, "the hand-off wait bound must be in [0, 60] s");
+  h->hand_spin = (unsigned long long)(seconds * 1e8);   // 100 MHz clock
+  return PITMG_OK;
 }
 
 int pitmg_set_sweep_shapes(pitmg_handle* h, const int* cfg) {

@@ -174,12 +174,12 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
 // waits only for first sweeps, which never wait, of blocks whose tickets are
 // drawn (t-1) or will be drawn once a lower ticket's work-group has finished
 // (t+1); the grid therefore drains whatever number of work-groups is
-// resident.  Each wait also ends after kPairSpinTicks of
-// the 100 MHz clock and raises *timeout, so every wave exits.
+// resident.  Each wait also ends after ps.spin ticks of the 100 MHz clock
+// (2 s unless a test of the error path shortens it) and raises *timeout, so
+// every wave exits.
 // ---------------------------------------------------------------------------
 
 namespace {
-constexpr unsigned long long kPairSpinTicks = 200000000ull;   // 2 s
 
 __device__ __forceinline__ void coherent_store(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -188,11 +188,12 @@ __device__ __forceinline__ double coherent_load(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// thread 0: wait until *f >= epoch; returns false on timeout
-__device__ bool pair_wait(const unsigned long long* f, unsigned long long epoch) {
+// thread 0: wait until *f >= epoch; returns false after spin ticks
+__device__ bool pair_wait(const unsigned long long* f, unsigned long long epoch,
+                          unsigned long long spin) {
   const unsigned long long t0 = wall_clock64();
   while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-    if (wall_clock64() - t0 > kPairSpinTicks) return false;
+    if (wall_clock64() - t0 > spin) return false;
     __builtin_amdgcn_s_sleep(2);
   }
   return true;
@@ -248,8 +249,8 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
     if (tid == 0) {
       __hip_atomic_store(ps.flag + kb, ps.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       bool ok = true;
-      if (lo >= 0) ok = pair_wait(ps.flag + lo, ps.epoch) && ok;
-      if (hi >= 0) ok = pair_wait(ps.flag + hi, ps.epoch) && ok;
+      if (lo >= 0) ok = pair_wait(ps.flag + lo, ps.epoch, ps.spin) && ok;
+      if (hi >= 0) ok = pair_wait(ps.flag + hi, ps.epoch, ps.spin) && ok;
       if (!ok) atomicOr(ps.timeout, 1);
     }
     __syncthreads();
@@ -950,8 +951,8 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl2(
   if (tid == 0) {
     __hip_atomic_store(ps.flag + g, ps.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bool ok = true;
-    if (g > 0) ok = pair_wait(ps.flag + g - 1, ps.epoch) && ok;
-    if (g + 1 < ng) ok = pair_wait(ps.flag + g + 1, ps.epoch) && ok;
+    if (g > 0) ok = pair_wait(ps.flag + g - 1, ps.epoch, ps.spin) && ok;
+    if (g + 1 < ng) ok = pair_wait(ps.flag + g + 1, ps.epoch, ps.spin) && ok;
     if (!ok) atomicOr(ps.timeout, 1);
   }
   __syncthreads();

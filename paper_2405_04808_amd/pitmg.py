@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "pitmg_coarse_pairs_count": (i, [vp]),
         "pitmg_autotune": (i, [vp, C.POINTER(i)]),
         "pitmg_set_sweep_shapes": (i, [vp, C.POINTER(i)]),
+        "pitmg_set_handoff_wait": (i, [vp, C.c_double]),
         "pitmg_status_string": (C.c_char_p, [i]),
         "pitmg_last_error": (C.c_char_p, [vp]),
         "pitmg_destroy": (None, [vp]),
@@ -322,6 +323,10 @@ class Solver:
         cfg = (C.c_int * self.n_levels)()
         self._check(self.lib.pitmg_autotune(self.h, cfg))
         return list(cfg)
+
+    def set_handoff_wait(self, seconds: float):
+        """Bound of each neighbour wait of the two-sweep launches (seconds)."""
+        self._check(self.lib.pitmg_set_handoff_wait(self.h, C.c_double(seconds)))
 
     def set_sweep_shapes(self, cfg):
         """Set each level's sweep launch shape (as returned by autotune)."""

@@ -126,3 +126,26 @@ def test_pair_fgmres_bitwise(shape):
         s.close()
     assert res[0][1] == res[1][1]
     assert torch.equal(res[0][0], res[1][0])
+
+
+def test_pair_handoff_wait_bound_reports_error():
+    # force the hand-off's own bounded wait to run out from the host (a bound
+    # of zero): every kernel still exits, and the solve reports the failure;
+    # with the bound restored the same handle solves normally again
+    prob, rng = make_problem(kind="burgers", nx=128, nu=0.01, n=1024, n_levels=8, seed=37)
+    b = make_rhs(prob, rng)
+    s = pm.Solver(prob.levels, pm.default_options(restart=8, maxit=8, pair_sweeps=1))
+    tiled_everywhere(s, prob.n_levels)
+    with pytest.raises(pm.PitmgError):
+        s.set_handoff_wait(-1.0)
+    s.set_handoff_wait(0.0)
+    with pytest.raises(pm.PitmgError) as err:
+        s.solve(dev(b), tol=1e-10)
+    torch.cuda.synchronize()
+    assert err.value.code == pm.PITMG_ERR_HIP
+    assert "hand-off" in str(err.value)
+    s.set_handoff_wait(2.0)
+    x, st, rc = s.solve(dev(b), tol=1e-10)
+    torch.cuda.synchronize()
+    assert rc in (pm.PITMG_OK, pm.PITMG_NOT_CONVERGED) and st["iters"] == 8
+    s.close()
