@@ -339,7 +339,8 @@ __global__ __launch_bounds__(Pol::kThreads) void k_coarse_finish(
 // ---------------------------------------------------------------------------
 
 // out_s = G_s^{-1} M_s for every step s of the level (M = N or V).
-__global__ __launch_bounds__(512) void k_gi_times(LevelView L, int which, double* __restrict__ out) {
+__global__ __launch_bounds__(512) void k_gi_times(LevelView L, int which,
+                                                  double* __restrict__ out) {
   const int p = L.p;
   const long long s = blockIdx.x;
   const double* __restrict__ Gk = L.Gi + s * p * p;

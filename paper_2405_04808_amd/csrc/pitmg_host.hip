@@ -428,13 +428,17 @@ int coarse_solve(pitmg_handle* h, const double* b, double* out) {
     double* vj = Vb + (size_t)j * len;
     double* zj = Zb + (size_t)j * len;
     // forward sweep: c = D^{-1} v, a_u = P c_u, a = D^{-1}(v - L a)
-    if ((rc = timed(h, 4, [&] { return launch_jacobi(v, vj, nullptr, nullptr, var, h->cC, h->stream); })))
+    if ((rc = timed(h, 4, [&] {
+           return launch_jacobi(v, vj, nullptr, nullptr, var, h->cC, h->stream);
+         })))
       return rc;
     if ((rc = timed(h, 4, [&] {
            return launch_gemv_tri(h->Pf, v.n, h->p, 0, h->cC + T.u, h->cY + T.u, h->stream);
          })))
       return rc;
-    if ((rc = timed(h, 4, [&] { return launch_jacobi(v, vj, h->cY, nullptr, var, h->cA, h->stream); })))
+    if ((rc = timed(h, 4, [&] {
+           return launch_jacobi(v, vj, h->cY, nullptr, var, h->cA, h->stream);
+         })))
       return rc;
     // backward sweep: y_mu = Q a_mu, z = a - D^{-1} L^T y
     if ((rc = timed(h, 4, [&] {

@@ -134,7 +134,8 @@ struct PairSync {
 // Two consecutive sweeps in one launch (y1 = first, y2 = second sweep; the
 // coarse correction, if any, folds into the first, the restriction, if any,
 // comes from the second) for levels that sweep with the one-step tiled
-// kernel or, in FP64, the shared-block kernel.  jacobi_pair_supported says whether launch_jacobi_pair applies
+// kernel or, in FP64, the shared-block kernel.  jacobi_pair_supported says
+// whether launch_jacobi_pair applies
 // (never while the stream is being captured: the tickets and epochs are
 // launch arguments).
 bool jacobi_pair_supported(const LevelView& L, hipStream_t s);
