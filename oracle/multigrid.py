@@ -3,7 +3,9 @@
 Everything here acts on time-major vectors y = Q x, b~ = P b (eq. (augsysp2))
 of one level, with A~ = P A Q^T split as L + D + L^T (Sec. 5.3.2):
 
-  block Jacobi (eq. (jacobi)):  y <- y + D^{-1} (b~ - A~ y)
+  block Jacobi (eq. (jacobi)), with weight omega:
+        y <- y + omega D^{-1} (b~ - A~ y)
+  (omega = 1 is the printed, undamped sweep; see MGOptions.omega)
   symmetric block Gauss-Seidel (Sec. 5.3.4), used as the right
   preconditioner of the coarse GMRES:
         M = (D + L) D^{-1} (D + L^T),   M^{-1} r = (D+L^T)^{-1} D (D+L)^{-1} r
@@ -53,9 +55,10 @@ class OracleLevel:
         self.sgs_up = spla.splu((self.D + self.U).tocsc())
 
     # -- smoothers ----------------------------------------------------------
-    def jacobi(self, b: np.ndarray, y: np.ndarray) -> np.ndarray:
-        """One undamped block Jacobi sweep, first form of eq. (jacobi)."""
-        return y + self.D_lu.solve(b - self.At @ y)
+    def jacobi(self, b: np.ndarray, y: np.ndarray, omega: float = 1.0) -> np.ndarray:
+        """One block Jacobi sweep, first form of eq. (jacobi), with the
+        correction D^{-1}(b - A~ y) weighted by omega (1 = as printed)."""
+        return y + omega * self.D_lu.solve(b - self.At @ y)
 
     def sgs(self, r: np.ndarray) -> np.ndarray:
         """M^{-1} r for the symmetric block Gauss-Seidel splitting."""
@@ -71,12 +74,30 @@ class OracleLevel:
 
 @dataclass
 class MGOptions:
+    """Cycle parameters.
+
+    omega: weight of the block Jacobi correction.  The permuted matrix is
+    block tridiagonal (Fig. 5), so conjugating I - D^{-1} A~ by the block
+    sign pattern diag((-1)^k) negates it: its spectrum is symmetric about 0,
+    and each slow smooth error mode (eigenvalue near +1) has an oscillating
+    twin near -1 that no coarse grid represents.  The printed sweep
+    (omega = 1) leaves that twin as slow as the smooth mode, and the cycle
+    converges no faster than its smoother.  omega = 1/2 maps the spectrum
+    [-rho, rho] into [(1-rho)/2, (1+rho)/2]: every oscillating twin is damped
+    by at least 1/2 per sweep, and the smooth modes are left to the coarse
+    grid (the weighted Jacobi smoother of the multigrid texts cited in
+    Sec. 5.3).
+    mu_scale: scale of the interface multiplier in the transfers (see
+    oracle.transfer); 1 = the printed transfers.
+    """
     nu_pre: int = 2
     nu_post: int = 2
     coarse_tol: float = 1e-3
     coarse_maxit: int = 50
     coarse_fixed_its: int = 0
     transfer_variant: int = 0
+    omega: float = 0.5
+    mu_scale: float = 2.0
 
 
 class Hierarchy:
@@ -95,8 +116,10 @@ class Hierarchy:
             f, c = self.levels[i], self.levels[i + 1]
             if c.n * 2 != f.n:
                 raise ValueError("levels must halve the step count")
-            Rt = restriction(f.p, f.q, f.n, self.opts.transfer_variant)
-            Pt = interpolation(f.p, f.q, f.n, self.opts.transfer_variant)
+            Rt = restriction(f.p, f.q, f.n, self.opts.transfer_variant,
+                             self.opts.mu_scale)
+            Pt = interpolation(f.p, f.q, f.n, self.opts.transfer_variant,
+                               self.opts.mu_scale)
             # time-major transfers: R~ = P_c R Q_f^T, P~ = P_f P Q_c^T
             self.R.append(Rt[c.perm][:, f.perm].tocsr())
             self.P.append(Pt[f.perm][:, c.perm].tocsr())
@@ -119,12 +142,12 @@ class Hierarchy:
         o = self.opts
         y = np.zeros_like(b)
         for _ in range(o.nu_pre):                 # pre-smooth
-            y = lv.jacobi(b, y)
+            y = lv.jacobi(b, y, o.omega)
         r = b - lv.At @ y                         # residual
         e = self.mg(lev + 1, self.R[lev] @ r)     # restrict + coarse solve
         y = y + self.P[lev] @ e                   # interpolate and add
         for _ in range(o.nu_post):                # post-smooth
-            y = lv.jacobi(b, y)
+            y = lv.jacobi(b, y, o.omega)
         return y
 
     # -- type-major front end -------------------------------------------------

@@ -13,6 +13,19 @@ does not exist.  variant 0 (default) keeps the printed formulas and takes
 s^c_{n/2+1} := s^c_{n/2}.  variant 1 aligns coarse step k with fine step 2k
 (both end at time 2k*dt): s^c_k = s^f_{2k}, s^f_{2k} = s^c_k,
 s^f_{2k-1} = (s^c_{k-1} + s^c_k)/2 with s^c_0 := 0.
+
+Scale of the interface multiplier (mu_scale).  Sec. 5.3.1 leaves the
+transfers open ("supports alternatives"); the printed formulas fix only the
+pattern.  In the Euclidean variables of Sec. 4.1 every type except mu is
+sqrt(dt) times a function of time, so a common factor between the grids
+cancels in P MG R (the coarse GMRES is homogeneous).  The u_k row of the
+lifted system balances N_k^T lambda_k + mu_k, and N_k = (M - theta dt du f)/dt,
+so mu is 1/dt times a lambda-sized function: the same function on the grid
+of step 2 dt has half the mu coefficient relative to the other types.
+mu_scale multiplies the mu block of the interpolation (coarse -> fine) and,
+keeping R proportional to the transpose pattern of P, the mu rows of the
+restriction.  mu_scale = 1 is the printed, unscaled transfer; 2 is the
+step ratio.
 """
 from __future__ import annotations
 
@@ -63,19 +76,23 @@ def _ctrl_P(nf: int) -> sp.csr_matrix:
     return P.tocsr()
 
 
-def restriction(p: int, q: int, nf: int, variant: int = 0) -> sp.csr_matrix:
-    """Type-major restriction from nf steps to nf/2 steps."""
+def restriction(p: int, q: int, nf: int, variant: int = 0,
+                mu_scale: float = 1.0) -> sp.csr_matrix:
+    """Type-major restriction from nf steps to nf/2 steps; the mu rows are
+    multiplied by mu_scale."""
     if nf % 2:
         raise ValueError("n must be even to coarsen")
     Rs = sp.kron(_node_R(nf, variant), sp.identity(p))
     Rz = sp.kron(_ctrl_R(nf), sp.identity(q))
-    return sp.block_diag([Rs, Rs, Rz, Rs, Rs], format="csr")
+    return sp.block_diag([Rs, Rs, Rz, Rs, mu_scale * Rs], format="csr")
 
 
-def interpolation(p: int, q: int, nf: int, variant: int = 0) -> sp.csr_matrix:
-    """Type-major interpolation from nf/2 steps to nf steps."""
+def interpolation(p: int, q: int, nf: int, variant: int = 0,
+                  mu_scale: float = 1.0) -> sp.csr_matrix:
+    """Type-major interpolation from nf/2 steps to nf steps; the mu block is
+    multiplied by mu_scale."""
     if nf % 2:
         raise ValueError("n must be even to coarsen")
     Ps = sp.kron(_node_P(nf, variant), sp.identity(p))
     Pz = sp.kron(_ctrl_P(nf), sp.identity(q))
-    return sp.block_diag([Ps, Ps, Pz, Ps, Ps], format="csr")
+    return sp.block_diag([Ps, Ps, Pz, Ps, mu_scale * Ps], format="csr")

@@ -1,0 +1,207 @@
+"""Pins of the oracle's multigrid cycle: the convergence behaviour the paper
+reports (Sec. 6, Tables 3-5) and the mathematics behind the two readings
+the cycle takes where the paper is silent (the smoother weight omega and the
+scale of the interface multiplier in the transfers; see oracle.multigrid
+.MGOptions and oracle.transfer).
+
+The paper's counts are averages over the augmented-system solves of an SQP
+run whose iterates are not given, so these tests compare trends and orders
+of magnitude: a constant linearisation point, a least-squares right-hand
+side [chi; 0] (eq. (augsysls)) and the tolerance 1e-6 of Sec. 6 stand in.
+The printed, undamped cycle is pinned too, as the experiment that shows why
+it cannot reach those counts.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from workloads.problems import (lifted_blocks, vanderpol_jacobians, burgers_jacobians,
+                                coarsen_point)
+from oracle import Hierarchy, type_offsets
+from oracle.multigrid import MGOptions
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+PRINTED = dict(omega=1.0, mu_scale=1.0)       # eq. (jacobi) and Sec. 5.3.1 as printed
+WEIGHTED = dict(omega=0.5, mu_scale=2.0)      # the readings (oracle defaults)
+
+
+def _tables():
+    out = {"T3": {}, "T4": {}, "T5": {}}
+    for line in open(os.path.join(GOLDEN, "mg_iteration_tables.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        t, *vals = line.split()
+        out[t][int(vals[0])] = [float(v) for v in vals[1:]]
+    return out
+
+
+def vdp_levels(n, gamma=100.0):
+    """Van der Pol hierarchy of Sec. 6.1 (T = 8, theta = 1/2, damping 0.1,
+    two controls) at the constant point w = 0, zeta = 0, coarsest 8 steps."""
+    jac = vanderpol_jacobians(mu=0.1, q=2)
+    levels, w, z = [], np.zeros((n, 2)), np.zeros((n, 2))
+    while True:
+        nl = w.shape[0]
+        levels.append(lifted_blocks(w, z, np.ones(2), 8.0 / nl, 0.5, gamma, jac,
+                                    compress=False))
+        if nl == 8:
+            return levels
+        w, z = coarsen_point(w, z)
+
+
+def burgers_levels(n, nx=16, gamma=100.0):
+    """Viscous Burgers hierarchy of Sec. 6.2 (nu = 0.01, T = 1, backward
+    Euler) on nx interior nodes at the constant point sin(pi x), zeta = 0.
+    (With nx = 16 the grid Peclet number at the printed step profile exceeds
+    2 and its linearisation has growing modes; the smooth profile keeps the
+    time-step blocks those of a stable step.)"""
+    jac = burgers_jacobians(nx, 0.01)
+    x = np.arange(1, nx + 1) / (nx + 1)
+    w0 = np.sin(np.pi * x)
+    levels, w, z = [], np.tile(w0, (n, 1)), np.zeros((n, nx))
+    while True:
+        nl = w.shape[0]
+        levels.append(lifted_blocks(w, z, w0, 1.0 / nl, 1.0, gamma, jac, compress=False))
+        if nl == 8:
+            return levels
+        w, z = coarsen_point(w, z)
+
+
+def ls_rhs(p, q, n, seed=0):
+    """Least-squares right-hand side [chi; 0]: random primal part, zero
+    constraint part (eq. (augsysls)), type-major."""
+    o = type_offsets(p, q, n)
+    b = np.zeros(o["end"])
+    b[:o["lam"]] = np.random.default_rng(seed).normal(size=o["lam"])
+    return b
+
+
+def fgmres_count(levels, p, q, nu, tol=1e-6, **opt):
+    H = Hierarchy(levels, MGOptions(nu_pre=nu, nu_post=nu, **opt))
+    n = levels[0].N.shape[0]
+    x, info = H.solve(ls_rhs(p, q, n), tol=tol, restart=400, maxit=400)
+    assert info["converged"]
+    return info["iters"], float(np.mean(info["coarse_its"]))
+
+
+def two_grid_rate(n, nu, omega, mu_scale):
+    """Spectral radius of S^nu (I - P A_c^{-1} R A~) S^nu for van der Pol
+    with an exact coarse solve (Alg. 1), S = I - omega D^{-1} A~."""
+    H = Hierarchy(vdp_levels(n)[:2], MGOptions(omega=omega, mu_scale=mu_scale))
+    f, c = H.levels
+    A, D = f.At.toarray(), f.D.toarray()
+    m = A.shape[0]
+    S = np.eye(m) - omega * np.linalg.solve(D, A)
+    Sn = np.linalg.matrix_power(S, nu)
+    CG = np.eye(m) - H.P[0].toarray() @ np.linalg.solve(c.At.toarray(), H.R[0].toarray() @ A)
+    rho = lambda M: float(np.max(np.abs(np.linalg.eigvals(M))))
+    return rho(Sn @ CG @ Sn), rho(Sn @ Sn)
+
+
+# ---------------------------------------------------------------------------
+# Why the printed sweep cannot smooth: the sign symmetry of block Jacobi
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("levels", ["vdp", "burgers"])
+def test_block_jacobi_iteration_is_sign_symmetric(levels):
+    """A~ is block tridiagonal (Fig. 5), so with J = diag((-1)^k I_k) over the
+    time-major blocks, J (I - D^{-1} A~) J = -(I - D^{-1} A~) exactly: the
+    spectrum of the printed iteration is symmetric about zero, and each
+    smooth error mode has an oscillating twin that decays just as slowly."""
+    lv = (vdp_levels(16) if levels == "vdp" else burgers_levels(16, nx=3))[0]
+    H = Hierarchy([lv])
+    ol = H.levels[0]
+    A, D = ol.At.toarray(), ol.D.toarray()
+    S = np.eye(A.shape[0]) - np.linalg.solve(D, A)
+    sign = np.concatenate([np.full(ol.bounds[k + 1] - ol.bounds[k], (-1.0) ** k)
+                           for k in range(len(ol.bounds) - 1)])
+    np.testing.assert_allclose(sign[:, None] * S * sign[None, :], -S, rtol=0, atol=1e-12)
+    ev = np.linalg.eigvals(S)
+    top = ev[np.argmax(np.abs(ev))]
+    assert np.min(np.abs(ev + top)) <= 1e-8 * abs(top)
+
+
+def test_printed_cycle_reduces_to_its_smoother():
+    """Experiment: with the printed sweep and transfers the two-grid cycle
+    converges exactly as fast as its 2 nu sweeps alone, and both slow down as
+    n grows (the coarse-grid correction removes nothing that matters)."""
+    prev = 0.0
+    for n in (16, 32, 64):
+        tg, smooth = two_grid_rate(n, 4, **PRINTED)
+        assert tg >= 0.95 * smooth
+        assert tg > prev + 0.1
+        prev = tg
+    assert prev >= 0.5
+
+
+def test_weighted_cycle_rate_is_nearly_mesh_independent():
+    """With omega = 1/2 and the step-ratio scale of mu the two-grid rate of a
+    V(4,4) stays near 0.1 while the printed cycle's climbs toward 1."""
+    rates = [two_grid_rate(n, 4, **WEIGHTED)[0] for n in (16, 32, 64)]
+    assert max(rates) <= 0.2
+    assert rates[2] - rates[0] <= 0.08
+    # each reading alone is not enough
+    assert two_grid_rate(64, 4, omega=0.5, mu_scale=1.0)[0] >= 0.4
+    assert two_grid_rate(64, 4, omega=1.0, mu_scale=2.0)[0] >= 0.6
+
+
+# ---------------------------------------------------------------------------
+# Tables 3-5: FGMRES counts per solve
+# ---------------------------------------------------------------------------
+
+def test_table3_trend_vanderpol():
+    """Table 3 (gamma = 100, V(4,4)): FGMRES counts stay small and grow
+    slowly with n (4.21 .. 6.67 for n = 64 .. 512).  The weighted cycle gives
+    counts within 2.5x of the printed averages with a spread of at most 2;
+    the printed cycle's counts roughly double with every doubling of n."""
+    T3 = _tables()["T3"]
+    counts = {n: fgmres_count(vdp_levels(n), 2, 2, 4, **WEIGHTED)[0]
+              for n in (64, 128, 256, 512)}
+    for n, c in counts.items():
+        assert c <= 2.5 * T3[n][1], (n, c)
+    assert max(counts.values()) - min(counts.values()) <= 2
+    printed = [fgmres_count(vdp_levels(n), 2, 2, 4, **PRINTED)[0] for n in (64, 128, 256)]
+    assert printed[1] >= 1.6 * printed[0] and printed[2] >= 1.6 * printed[1]
+    assert printed[0] >= 2 * counts[64]
+
+
+def test_table4_coarse_sgs_counts_fall_with_gamma():
+    """Table 4's SGS column: the coarse GMRES + SGS solve needs about six
+    steps per call with gamma = 1 and one with gamma = 100."""
+    T4 = _tables()["T4"]
+    sgs1 = fgmres_count(burgers_levels(64, gamma=1.0), 16, 16, 4, **WEIGHTED)[1]
+    sgs100 = fgmres_count(burgers_levels(64, gamma=100.0), 16, 16, 4, **WEIGHTED)[1]
+    assert sgs100 <= 1.5 and sgs1 >= 2.5
+    assert T4[64][2] / T4[64][0] < 0.5 and sgs100 / sgs1 < 0.5
+
+
+def test_table5_trend_burgers_sweeps():
+    """Table 5: more block Jacobi sweeps per level give fewer FGMRES steps,
+    mildly (3.58 -> 1.87 at n = 64 for 4 -> 16 sweeps), and the counts grow
+    slowly with n at every sweep count."""
+    T5 = _tables()["T5"]
+    for n in (64, 256):
+        counts = [fgmres_count(burgers_levels(n), 16, 16, nu, **WEIGHTED)[0]
+                  for nu in (4, 8, 12, 16)]
+        assert all(a >= b for a, b in zip(counts, counts[1:])), (n, counts)
+        assert counts[-1] < counts[0]
+        assert counts[0] <= 2.5 * T5[4][0 if n == 64 else 2], (n, counts)
+    c64 = fgmres_count(burgers_levels(64), 16, 16, 4, **WEIGHTED)[0]
+    c512 = fgmres_count(burgers_levels(512), 16, 16, 4, **WEIGHTED)[0]
+    assert c512 - c64 <= 3
+
+
+def test_gamma_one_fgmres_counts_not_reproduced():
+    """Experiment, recorded as a deviation: Tables 3 and 4 show gamma = 1
+    needing 6-20x more FGMRES steps than gamma = 100.  Under the weighted
+    cycle gamma changes the coarse SGS count (Table 4) but hardly the FGMRES
+    count; the printed gamma effect is that of the undamped sweep, whose
+    radius for gamma = 1 sits at or above 1 (Table 2)."""
+    T3 = _tables()["T3"]
+    for n in (64, 256):
+        c1 = fgmres_count(vdp_levels(n, gamma=1.0), 2, 2, 4, **WEIGHTED)[0]
+        c100 = fgmres_count(vdp_levels(n, gamma=100.0), 2, 2, 4, **WEIGHTED)[0]
+        assert abs(c1 - c100) <= 3
+        assert T3[n][0] / T3[n][1] >= 6

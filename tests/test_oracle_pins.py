@@ -276,6 +276,15 @@ def test_transfers(variant):
     ur = (R @ y)[o_c["u"]:o_c["v"]].reshape(nc, p)
     yu = y[o_f["u"]:o_f["v"]].reshape(nf, p)
     np.testing.assert_array_equal(ur, yu[0::2] if variant == 0 else yu[1::2])
+    # mu_scale multiplies exactly the mu rows of R and the mu block of P
+    R2 = restriction(p, q, nf, variant, mu_scale=2.0)
+    P2 = interpolation(p, q, nf, variant, mu_scale=2.0)
+    dR = (R2 - R).toarray()
+    dP = (P2 - P).toarray()
+    np.testing.assert_array_equal(dR[:o_c["mu"]], 0.0)
+    np.testing.assert_array_equal(dR[o_c["mu"]:], R.toarray()[o_c["mu"]:])
+    np.testing.assert_array_equal(dP[:, :o_c["mu"]], 0.0)
+    np.testing.assert_array_equal(dP[:, o_c["mu"]:], P.toarray()[:, o_c["mu"]:])
 
 
 # ---------------------------------------------------------------------------
@@ -419,7 +428,7 @@ def test_vcycle_is_consistent_two_grid():
     A = H.levels[0].At.toarray()
     m = A.shape[0]
     E = np.column_stack([H.mg(0, e) for e in np.eye(m)])
-    S = np.eye(m) - np.linalg.solve(H.levels[0].D.toarray(), A)
+    S = np.eye(m) - H.opts.omega * np.linalg.solve(H.levels[0].D.toarray(), A)
     Ac = H.levels[1].At.toarray()
     CG = np.eye(m) - H.P[0].toarray() @ np.linalg.solve(Ac, H.R[0].toarray() @ A)
     T = S @ CG @ S @ S
