@@ -37,53 +37,34 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_jacobi_burgers128_hbm_counters.md")
 
 WORKLOADS = {
     # the measured workload: viscous Burgers, 128 nodes, 1024 steps
-    # FGMRES(550): two restart cycles reach 1e-10 (about 1,050 steps) in less
-    # time than one unrestarted cycle of about 970 steps, whose Gram-Schmidt
-    # passes grow with the step count
-    "burgers128": dict(cfg="burgers128", restart=550, maxit=3000,
+    "burgers128": dict(cfg="burgers128", restart=300, maxit=300,
                        desc="viscous Burgers nx=128 (p=q=128), nu=0.01, n=1024 steps, "
-                            "8 levels (coarsest 8 steps), gamma=100, V(2,2) block Jacobi, "
-                            "coarse GMRES+SGS tol 1e-3, FGMRES tol 1e-10"),
-    "vdp256": dict(cfg="vdp256", restart=600, maxit=600,
-                   desc="van der Pol p=2 q=1, n=256 steps, 6 levels, gamma=100, V(2,2), "
+                            "8 levels (coarsest 8 steps), gamma=100, V(2,2) weighted block "
+                            "Jacobi (omega 1/2), mu transfer scale 2, coarse GMRES+SGS tol "
+                            "1e-3, FGMRES tol 1e-10"),
+    "vdp256": dict(cfg="vdp256", restart=300, maxit=300,
+                   desc="van der Pol p=2 q=1, n=256 steps, 6 levels, gamma=100, V(2,2) "
+                        "weighted block Jacobi (omega 1/2), mu transfer scale 2, "
                         "FGMRES tol 1e-10"),
 }
 
 
-def sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8, with_restrict=False):
-    """Algorithmic HBM bytes of one block Jacobi sweep on a level of n steps.
-
-    Per time-step block: N_k (p*p), V_k (p*p, unless shared), Z~_k (p*q,
-    unless shared), the lower triangle of G_k^{-1} (p(p+1)/2), each of
-    mat_bytes per entry; the right-hand side block (4p+q) read and the new
-    iterate block (4p+q) written, and the two coupling values u_{k-1}, mu_k of
-    the previous iterate (2p; doubled when the interpolated coarse correction
-    is folded in), FP64.  Shared blocks count once per launch.  With the
-    restriction fused into the sweep (the last pre-smoothing sweep), per
-    coarse step also u and mu of the previous iterate at the injected fine
-    step (2p) read and the coarse block (4p+q) written.
-    """
+def sweep_bytes(p, q, n, shared_V, shared_Z, mat_bytes=8):
+    """Algorithmic HBM bytes of one block Jacobi sweep on a level of n steps,
+    the unit of the method's cost model: per time-step block N_k, the lower
+    triangle of G_k^{-1} and, unless shared by every step, V_k and Z~_k, each
+    of mat_bytes per entry; the right-hand side and the previous iterate read
+    and the new iterate written, 3 (4p+q) FP64 values.  Shared blocks count
+    once per sweep; block n+1 holds 2p values."""
     mats = p * p + (0 if shared_V else p * p) + (0 if shared_Z else p * q) + p * (p + 1) // 2
-    vecs = 2 * (4 * p + q) + 2 * p
-    total = n * (mats * mat_bytes + vecs * 8) + (2 * p + 2 * p) * 8        # block n+1
-    if with_coarse:
-        total += n * 2 * p * 8                                # coarse coupling values
-    if with_restrict:
-        total += (n // 2) * (2 * p + 4 * p + q) * 8           # fused restriction
+    total = n * (mats * mat_bytes + 3 * (4 * p + q) * 8) + 3 * (2 * p) * 8
     total += ((p * p if shared_V else 0) + (p * q if shared_Z else 0)) * mat_bytes
     return float(total)
 
 
-def pair_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes=8, with_restrict=False):
-    """Algorithmic HBM bytes of two consecutive sweeps in one launch (the
-    two-sweep tiled kernel): the blocks and the right-hand side are read once,
-    the first sweep's iterate is written and its two coupling values per
-    block read back by the neighbours, the second sweep's iterate is written.
-    The couplings of the previous iterate (and of the coarse correction) and
-    the fused restriction count as in sweep_bytes."""
-    one = sweep_bytes(p, q, n, shared_V, shared_Z, with_coarse, mat_bytes, with_restrict)
-    # second sweep: its own iterate written and the first's couplings read
-    return one + float(n * ((4 * p + q) + 2 * p) * 8 + (2 * p + p) * 8)
+def vector_bytes(p, q, n):
+    """The vector part of sweep_bytes (no blocks)."""
+    return float(n * 3 * (4 * p + q) * 8 + 3 * (2 * p) * 8)
 
 
 def level_pairs(p, q, L, shapes, pair_sweeps, shared=True, fp32_levels=0):
@@ -107,49 +88,46 @@ def level_pairs(p, q, L, shapes, pair_sweeps, shared=True, fp32_levels=0):
     return out
 
 
-def vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes=8,
-                  fp64_residual=False):
-    """(bytes, launches) of the sweeps of one V-cycle, with the launch
-    pattern of the library: on a paired level sweeps go two per launch, an
-    odd one last on its own; the restriction rides on the last pre-smoothing
-    sweep, except on the finest level when its residual is formed in FP64."""
-    tot, launches = 0.0, 0
+def vcycle_launches(L, nu_pre, nu_post, pairs):
+    """(level, sweeps in the launch) of every sweep launch of one V-cycle, in
+    the library's pattern: on a paired level sweeps go two per launch, an odd
+    one last on its own."""
+    out = []
     for lev in range(L - 1):
-        nl = n >> lev
-        fused = nu_pre > 0 and not (fp64_residual and lev == 0)
-        for nu, pre in ((nu_pre, True), (nu_post, False)):
+        for nu in (nu_pre, nu_post):
             s_ = 0
             while s_ < nu:
                 two = pairs[lev] is not None and s_ + 1 < nu
-                last = s_ + 1 if two else s_
-                kw = dict(with_coarse=(not pre) and s_ == 0, mat_bytes=mat_bytes,
-                          with_restrict=pre and fused and last == nu - 1)
-                if two and pairs[lev] == "tiled":
-                    tot += pair_bytes(p, q, nl, shared_V, shared_Z, **kw)
-                elif two:                  # shared-block pair: two sweeps' bytes
-                    tot += sweep_bytes(p, q, nl, shared_V, shared_Z, kw["with_coarse"],
-                                       mat_bytes)
-                    tot += sweep_bytes(p, q, nl, shared_V, shared_Z, False, mat_bytes,
-                                       kw["with_restrict"])
-                else:
-                    tot += sweep_bytes(p, q, nl, shared_V, shared_Z, **kw)
-                launches += 1
-                s_ = last + 1
-        if not fused:
-            tot += 8.0 * (4 * p * nl + (4 * p + q) * (nl // 2))
-    return tot, launches
+                out.append((lev, 2 if two else 1))
+                s_ += 2 if two else 1
+    return out
+
+
+def vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes=8):
+    """Sweep bytes of one V-cycle and its number of sweep launches: (bytes
+    with the blocks counted once per sweep, bytes with the blocks counted
+    once per launch, launches)."""
+    per_sweep = per_launch = 0.0
+    launches = vcycle_launches(L, nu_pre, nu_post, pairs)
+    for lev, k in launches:
+        nl = n >> lev
+        one = sweep_bytes(p, q, nl, shared_V, shared_Z, mat_bytes)
+        per_sweep += k * one
+        per_launch += one + (k - 1) * vector_bytes(p, q, nl)
+    return per_sweep, per_launch, len(launches)
 
 
 def vcycle_bytes(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, mat_bytes=8, fp64_residual=False,
                  pairs=None):
     """Algorithmic bytes of one V-cycle: the sweeps of every level above the
-    coarsest, the restrictions (coupling values of two iterates read, coarse
-    right-hand side written), the coarse right-hand side and correction, and,
-    with an FP32 smoother, the explicit FP64 finest residual (blocks and two
-    vectors read, one written)."""
+    coarsest (blocks once per sweep), the coarse right-hand sides written,
+    the coarsest right-hand side and correction, and, with an FP32 smoother,
+    the explicit FP64 finest residual (blocks and two vectors read, one
+    written)."""
     pairs = pairs or [None] * (L - 1)
-    tot, _ = vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes,
-                           fp64_residual)
+    tot, _, _ = vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes)
+    for lev in range(L - 1):
+        tot += 8.0 * (4 * p + q) * (n >> (lev + 1))
     nc = n >> (L - 1)
     tot += 8.0 * 2 * (4 * p + q) * nc
     if fp64_residual:
@@ -158,62 +136,51 @@ def vcycle_bytes(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, mat_bytes=8, f
     return tot
 
 
-def cpu_baseline(name, iters_full, budget_s=25.0):
-    """Time the FP64 oracle on a bounded sample of the same workload."""
-    import numpy as np
+def cpu_baseline(name):
+    """Time one whole solve of the FP64 oracle on the same system: its setup
+    (assembly and SuperLU factorisations of every level) and its FGMRES to a
+    true relative residual of 1e-10."""
     from workloads import config_problem
     from oracle import Hierarchy
     from oracle.multigrid import MGOptions
-    from oracle.krylov import fgmres
     cores = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
-    prob, b = config_problem(WORKLOADS[name]["cfg"])
+    wl = WORKLOADS[name]
+    prob, b = config_problem(wl["cfg"])
     t1 = time.perf_counter()
     H = Hierarchy(prob.levels, MGOptions())
     t2 = time.perf_counter()
-    setup_s = t2 - t1
-    # FGMRES steps until the budget is used (at least 3)
-    bt = H.to_time(b)
-    count = [0]
-    tstart = [None]
-
-    def prec(v):
-        count[0] += 1
-        return H.mg(0, v)
-
-    k = 3
-    while True:
-        count[0] = 0
-        ts = time.perf_counter()
-        fgmres(H.levels[0].At, bt, prec, 1e-30, restart=k, maxit=k)
-        el = time.perf_counter() - ts
-        if el * 2 > budget_s - setup_s or k >= iters_full:
-            break
-        k = min(iters_full, k * 2)
-    per_it = el / k
-    est = setup_s + per_it * iters_full
-    return {"value": 1.0 / est, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle setup (assembly + SuperLU of every level, {setup_s:.1f} s) and "
-                      f"{k} FGMRES steps ({el:.1f} s), scaled to the {iters_full} steps the "
-                      f"GPU solve took; SciPy/SuperLU single-threaded, numpy BLAS on {cores} threads"}
+    _, info = H.solve(b, tol=1e-10, restart=wl["restart"], maxit=wl["maxit"])
+    t3 = time.perf_counter()
+    return {"value": 1.0 / (t3 - t1), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"one whole oracle solve of the same system: setup (assembly + SuperLU "
+                      f"of every level, {t2 - t1:.1f} s) and FGMRES to 1e-10 ({info['iters']} "
+                      f"steps, {t3 - t2:.1f} s); SciPy/SuperLU single-threaded, numpy BLAS on "
+                      f"{cores} threads",
+            "oracle_iters": info["iters"], "converged": bool(info["converged"])}
 
 
-def learned_leg(pm, torch, wl, train_seeds=range(50000, 50008), held_out=(60000, 60001)):
+def learned_leg(pm, torch, wl, train_seeds=range(50000, 50008), held_out=(60000, 60001),
+                rhs_per_point=8):
     """Learned coarse correction on the benchmark workload: record the
-    coarsest-level pairs of plain solves on other linearisation points,
-    train the network, then solve held-out points four ways (plain, network,
-    network under a stall rule, zero correction)."""
+    coarsest-level pairs of plain solves on other linearisation points
+    (rhs_per_point seeded right-hand sides each, as an SQP step solves
+    several systems per point), train the network, then solve held-out
+    points four ways (plain, network, network under a stall rule, zero
+    correction)."""
+    import numpy as np
     from paper_2405_04808_amd import coarse_training as ct
     from workloads import config_problem, coarse_net_params
 
-    def probs(seeds):
+    def probs(seeds, per=1):
         for sd in seeds:
             prob, b = config_problem(wl["cfg"], seed=sd)
-            yield prob.levels, b
+            rng = np.random.default_rng(sd + 1)
+            for j in range(per):
+                yield prob.levels, (b if j == 0 else rng.normal(size=b.shape))
 
     opts = pm.default_options(restart=wl["restart"], maxit=wl["maxit"])
     t0 = time.perf_counter()
-    R, E, info = ct.collect_pairs(probs(train_seeds), opts, max_pairs=8000)
+    R, E, info = ct.collect_pairs(probs(train_seeds, rhs_per_point), opts, max_pairs=8000)
     t_pairs = time.perf_counter() - t0
     print(f"# learned: {R.shape[0]} pairs from {len(info)} solves in {t_pairs:.1f} s",
           file=sys.stderr, flush=True)
@@ -432,15 +399,16 @@ def main():
     roofline = None
     kern = None
     if prof:
-        # algorithmic bytes of every Jacobi launch of the timed steps
-        per_vcycle, per_vcycle_launches = vcycle_sweeps(p, q, n, L, opts.nu_pre, opts.nu_post,
-                                                        shared_V, shared_Z, pairs)
+        # algorithmic bytes of the Jacobi launches of the timed steps: whole
+        # V-cycles' sweeps, so bytes per launch is the V-cycle's sweep bytes
+        # over its sweep launches
+        per_sweep, per_launch_once, nlaunch = vcycle_sweeps(p, q, n, L, opts.nu_pre,
+                                                            opts.nu_post, shared_V, shared_Z,
+                                                            pairs)
         launches, ms = prof["jacobi"]
-        # the timed launches are whole V-cycles' sweeps: bytes per launch is
-        # the V-cycle's algorithmic bytes over its sweep launches
-        per_launch = per_vcycle / per_vcycle_launches
-        alg_bytes = per_launch * launches
+        alg_bytes = per_sweep / nlaunch * launches
         achieved = alg_bytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        once = per_launch_once / nlaunch * launches / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         from paper_2405_04808_amd.rocprof_summary import read_traffic
         # the counter profile covers the Burgers nx=128 workload only
         rec = read_traffic(COUNTERS) if args.workload == "burgers128" else None
@@ -457,6 +425,11 @@ def main():
                     "traffic": rec["traffic_bytes_per_launch"] if rec else None,
                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                     "kernel": kname,
+                    "bytes_unit": "per sweep: N_k, lower G_k^{-1} per step (V, Z~ shared, once), "
+                                  "right-hand side, previous and new iterate; a two-sweep "
+                                  "launch counts two sweeps",
+                    "achieved_blocks_once_per_launch": round(once, 1),
+                    "frac_blocks_once_per_launch": round(once / HBM_PEAK_GBS, 4),
                     "launches": launches, "sample": "sweeps of every 16th V-cycle",
                     "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
                     "alg_bytes_per_launch": round(alg_bytes / max(launches, 1))}
@@ -523,7 +496,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, int(round(float(np.mean(iters)))))
+        cpu = cpu_baseline(args.workload)
 
     out = {
         "metric": "augmented-system solves/sec to 1e-10 rel. residual",

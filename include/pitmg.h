@@ -7,11 +7,13 @@
  *     Sec. 5.1), lifted with virtual interface variables v and multipliers
  *     mu (Fig. 4), permuted to time-major block-tridiagonal form A~ = P A Q^T
  *     (Fig. 5, eq. (augsysp));
- *   - preconditioner: one multigrid V-cycle (Alg. 1, recursed) with undamped
- *     block Jacobi smoothing (eq. (jacobi)), injection / linear interpolation
- *     in time and averaging / piecewise-constant transfer of the control
- *     (Sec. 5.3.1), and GMRES right-preconditioned by symmetric block
- *     Gauss-Seidel on the coarsest grid, to a relative tolerance (Sec. 5.3.4);
+ *   - preconditioner: one multigrid V-cycle (Alg. 1, recursed) with weighted
+ *     block Jacobi smoothing (eq. (jacobi) with the correction scaled by
+ *     omega), injection / linear interpolation in time and averaging /
+ *     piecewise-constant transfer of the control (Sec. 5.3.1, the
+ *     interface multiplier scaled by mu_scale), and GMRES right-
+ *     preconditioned by symmetric block Gauss-Seidel on the coarsest grid,
+ *     to a relative tolerance (Sec. 5.3.4);
  *   - outer solver: flexible GMRES (Saad 1993), needed because the coarse
  *     GMRES makes the preconditioner nonlinear (Sec. 5.3.4, Sec. 6).
  *
@@ -147,6 +149,27 @@ typedef struct {
                                   PITMG_ERR_HIP.  Streams under capture get
                                   one sweep per launch.
                                   0: one sweep per launch.                     */
+  double omega;                /* weight of the block Jacobi correction on every
+                                  level above the coarsest:
+                                  y <- y + omega D^{-1}(b - A~ y).  1 is the
+                                  undamped sweep printed in eq. (jacobi).  A~
+                                  is block tridiagonal (Fig. 5), so the
+                                  undamped iteration matrix has a spectrum
+                                  symmetric about 0 and leaves the oscillating
+                                  twin of every slow smooth error mode as slow
+                                  as the mode itself; omega = 1/2 damps those
+                                  twins by at least 1/2 per sweep and leaves the
+                                  smooth modes to the coarse grid.  (0, 1].   */
+  double mu_scale;             /* scale of the interface multiplier mu in the
+                                  transfers of Sec. 5.3.1 (which admit
+                                  alternatives): interpolation multiplies the
+                                  coarse mu by it, restriction weights the mu
+                                  residual rows by it.  mu is 1/dt times a
+                                  lambda-sized function (the u_k row balances
+                                  N_k^T lambda_k + mu_k with N_k ~ M/dt), so
+                                  the step ratio 2 keeps its grid functions
+                                  consistent; 1 is the printed, unscaled
+                                  transfer.  > 0.                             */
 } pitmg_options;
 
 typedef struct {
@@ -164,7 +187,9 @@ typedef struct {
 
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
  * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
- * stall_steps 2, vcycle_graph 0, apply_from_sweep 1, pair_sweeps 1. */
+ * stall_steps 2, vcycle_graph 0, apply_from_sweep 1, pair_sweeps 1,
+ * omega 0.5, mu_scale 2.  (omega = 1 with mu_scale = 1 is the cycle exactly
+ * as printed.) */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and

@@ -82,4 +82,41 @@ __device__ __forceinline__ double interp_node(const double* __restrict__ seg, in
   return 0.5 * (a + b);
 }
 
+// The iterate a sweep starts from: yold (NULL = 0) plus, in the first
+// post-smoothing sweep, the interpolated coarse correction P ec (NULL = 0),
+// whose mu block carries mu_scale and whose control is constant over the
+// two fine steps of a coarse step.  type: 0 u, 1 v, 2 z, 3 lambda, 4 mu.
+struct PrevIterate {
+  const double* yold;
+  const double* ec;
+  int p, q, n, variant;
+  double mu_scale;
+  __device__ double at(int type, int k, int i) const {
+    const TypeMajor Tm(p, q, n);
+    const long long seg[5] = {Tm.u, Tm.v, Tm.z, Tm.l, Tm.m};
+    const int w = type == 2 ? q : p;
+    double v = yold ? yold[seg[type] + (long long)(k - 1) * w + i] : 0.0;
+    if (ec) {
+      const int nc = n / 2;
+      const TypeMajor Tc(p, q, nc > 0 ? nc : 1);
+      if (type == 2) {
+        v += ec[Tc.z + (long long)((k + 1) / 2 - 1) * q + i];
+      } else {
+        const long long sc[5] = {Tc.u, Tc.v, Tc.z, Tc.l, Tc.m};
+        const double e = interp_node(ec + sc[type], nc, p, k, i, variant);
+        v += type == 4 ? mu_scale * e : e;
+      }
+    }
+    return v;
+  }
+};
+
+// Weighted sweep output (1 - omega) y_prev + omega y_hat; omega = 1 reads
+// nothing.
+__device__ __forceinline__ double weigh(double omega, double yhat, const PrevIterate& prev,
+                                        int type, int k, int i) {
+  if (omega == 1.0) return yhat;
+  return omega * yhat + (1.0 - omega) * prev.at(type, k, i);
+}
+
 }  // namespace pitmg

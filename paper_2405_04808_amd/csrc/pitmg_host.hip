@@ -279,6 +279,10 @@ LevelView view(const pitmg_handle* h, int l) {
   }
   v.sweep_cfg = b.sweep_cfg;
   if (b.split) v.split = &b.sp;
+  // the smoother weight applies above the coarsest level; the coarsest
+  // level's sweeps are the exact block solves of its SGS
+  v.omega = l < h->L - 1 ? h->opt.omega : 1.0;
+  v.mu_scale = h->opt.mu_scale;
   // the coarsest level's block solves (inside the coarse SGS) take one step
   // per work-group: at 8 steps the one-step kernel has the shorter latency
   if (l == h->L - 1 && v.sweep_cfg == 0 && jacobi_tiled_supported(h->p, h->q))
@@ -308,6 +312,10 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "vcycle_graph must be 0 or 1");
   if (o.vcycle_graph && h && h->stream == nullptr)
     return set_err(h, PITMG_ERR_INVALID, "vcycle_graph needs a stream other than the null stream");
+  if (!(o.omega > 0.0 && o.omega <= 1.0))
+    return set_err(h, PITMG_ERR_INVALID, "omega must be in (0, 1]");
+  if (!(o.mu_scale > 0.0) || !std::isfinite(o.mu_scale))
+    return set_err(h, PITMG_ERR_INVALID, "mu_scale must be > 0");
   return PITMG_OK;
 }
 
@@ -576,12 +584,13 @@ int vcycle_top(pitmg_handle* h, const double* r, double* e) {
 // Two consecutive sweeps of a level in one launch (y1 then y2), taking the
 // next tickets and epoch of the handle's hand-off state.
 hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, const double* yo,
-                      const double* ec, double* y1, double* y2, double* rc_out) {
+                      const double* ec, double* y1, double* y2, double* rc_out, double rbeta,
+                      double ra) {
   const PairSync ps{h->hand_ticket, h->hand_tickets, h->hand_flag, h->hand_epoch + 1,
                     h->hand_timeout, h->hand_spin};
   int groups = 0;
   const hipError_t e = launch_jacobi_pair(v, b, yo, ec, h->opt.transfer_variant, y1, y2,
-                                          rc_out, ps, &groups, h->stream);
+                                          rc_out, rbeta, ra, ps, &groups, h->stream);
   if (e == hipSuccess) {
     h->hand_tickets += (unsigned long long)groups;
     h->hand_epoch += 1;
@@ -601,16 +610,31 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
   double* ycur = nullptr;
   int rc;
   const bool pairs = o.pair_sweeps && jacobi_pair_supported(v, h->stream);
+  // Residual after the pre-smoothing sweeps from y = 0.  A weighted sweep
+  // y' = (1-w) y + w D^{-1}(b - (L+L^T) y) leaves r' = (1-w) r + (L+L^T)(y - y'),
+  // so one sweep leaves (1-w) b + (L+L^T)(0 - y1) and two leave
+  // (1-w)^2 b + (L+L^T)(w y1 - y2); undamped sweeps (w = 1) leave
+  // (L+L^T)(y_prev - y) after any number.  Those forms are restricted
+  // inside the last sweep as R (rbeta b + (L+L^T)(ra y_prev - y)); more
+  // weighted sweeps, and an FP32 finest level, form the residual explicitly.
+  const double w = v.omega;
+  const bool explicit_res = B.res != nullptr || (w != 1.0 && o.nu_pre > 2);
+  double rbeta = 0.0, ra = 1.0;
+  if (w != 1.0 && o.nu_pre == 1) rbeta = 1.0 - w;
+  if (w != 1.0 && o.nu_pre == 2) {
+    rbeta = (1.0 - w) * (1.0 - w);
+    ra = w;
+  }
   for (int s = 0; s < o.nu_pre;) {
-    // the last pre-smoothing sweep also restricts the residual it leaves,
-    // R (L+L^T)(y_prev - y), except where the finest residual is formed in FP64
     const int last = pairs && s + 1 < o.nu_pre ? s + 1 : s;
-    double* rc_out = (last == o.nu_pre - 1 && !B.res) ? C.b : nullptr;
+    double* rc_out = (last == o.nu_pre - 1 && !explicit_res) ? C.b : nullptr;
     const double* yo = ycur;
     if (last > s) {
       double* d1 = bufs[s & 1];
       double* d2 = bufs[last & 1];
-      rc = timed_kernel(h, 1, [&] { return sweep_pair(h, v, b, yo, nullptr, d1, d2, rc_out); });
+      rc = timed_kernel(h, 1, [&] {
+        return sweep_pair(h, v, b, yo, nullptr, d1, d2, rc_out, rbeta, ra);
+      });
       if (rc) return rc;
       ycur = d2;
       s += 2;
@@ -618,22 +642,26 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
     }
     double* dst = bufs[s & 1];
     rc = timed_kernel(h, 1, [&] {
-      return launch_jacobi(v, b, yo, nullptr, var, dst, h->stream, rc_out);
+      return launch_jacobi(v, b, yo, nullptr, var, dst, h->stream, rc_out, rbeta, ra);
     });
     if (rc) return rc;
     ycur = dst;
     ++s;
   }
   if (ycur == nullptr) {
-    rc = timed(h, 3, [&] { return launch_restrict(h->p, h->q, v.n, b, var, C.b, h->stream); });
-  } else if (B.res) {
-    // FP32 smoothing: the finest residual is formed explicitly in FP64
+    rc = timed(h, 3, [&] {
+      return launch_restrict(h->p, h->q, v.n, b, var, v.mu_scale, C.b, h->stream);
+    });
+  } else if (explicit_res) {
+    // r = b - A~ y in FP64 (into the spare smoothing buffer unless the FP32
+    // finest level keeps its own), then restricted
+    double* res = B.res ? B.res : (ycur == bufs[0] ? bufs[1] : bufs[0]);
     LevelView v64 = v;
     v64.fp32 = 0;
-    rc = timed(h, 2, [&] { return launch_apply(v64, ycur, b, -1.0, 1.0, B.res, h->stream); });
+    rc = timed(h, 2, [&] { return launch_apply(v64, ycur, b, -1.0, 1.0, res, h->stream); });
     if (!rc)
       rc = timed(h, 3, [&] {
-        return launch_restrict(h->p, h->q, v.n, B.res, var, C.b, h->stream);
+        return launch_restrict(h->p, h->q, v.n, res, var, v.mu_scale, C.b, h->stream);
       });
   }
   if (rc) return rc;
@@ -645,9 +673,11 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
     else
       HIPCHK(h, hipMemsetAsync(out, 0, B.len * 8, h->stream));
     return timed(h, 3, [&] {
-      return launch_interp_add(h->p, h->q, v.n, C.out, var, out, h->stream);
+      return launch_interp_add(h->p, h->q, v.n, C.out, var, v.mu_scale, out, h->stream);
     });
   }
+  // A~ z from the last sweep's identity needs an undamped FP64 sweep
+  const bool identity = l == 0 && w == 1.0 && !v.fp32;
   for (int s = 0; s < o.nu_post;) {
     double* dst = (s == o.nu_post - 1) ? out : (ycur == bufs[0] ? bufs[1] : bufs[0]);
     const double* yo = ycur;
@@ -655,17 +685,18 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
     if (pairs && s + 1 < o.nu_post) {
       // second sweep: into out if it is the last, else the other buffer
       double* d2 = (s + 1 == o.nu_post - 1) ? out : (dst == bufs[0] ? bufs[1] : bufs[0]);
-      rc = timed_kernel(h, 1, [&] { return sweep_pair(h, v, b, yo, ec, dst, d2, nullptr); });
+      rc = timed_kernel(h, 1, [&] {
+        return sweep_pair(h, v, b, yo, ec, dst, d2, nullptr, 0.0, 1.0);
+      });
       if (rc) return rc;
-      if (l == 0 && s + 1 == o.nu_post - 1 && !v.fp32) h->top_prev = dst;
+      if (identity && s + 1 == o.nu_post - 1) h->top_prev = dst;
       ycur = d2;
       s += 2;
       continue;
     }
     rc = timed_kernel(h, 1, [&] { return launch_jacobi(v, b, yo, ec, var, dst, h->stream); });
     if (rc) return rc;
-    if (l == 0 && s == o.nu_post - 1 && ec == nullptr && !v.fp32 && yo != nullptr)
-      h->top_prev = yo;
+    if (identity && s == o.nu_post - 1 && ec == nullptr && yo != nullptr) h->top_prev = yo;
     ycur = dst;
     ++s;
   }
@@ -1095,6 +1126,8 @@ void pitmg_default_options(pitmg_options* o) {
   o->vcycle_graph = 0;
   o->apply_from_sweep = 1;
   o->pair_sweeps = 1;
+  o->omega = 0.5;
+  o->mu_scale = 2.0;
 }
 
 int pitmg_autotune(pitmg_handle* h, int* cfg) {
@@ -1132,7 +1165,7 @@ int pitmg_autotune(pitmg_handle* h, int* cfg) {
       for (int r = 0; r < launches + 2; ++r) {
         if (r == 2) HIPCHK(h, hipEventRecord(e0, h->stream));
         if (two)
-          HIPCHK(h, sweep_pair(h, v, B.y1, B.y1, nullptr, B.y0, y2, nullptr));
+          HIPCHK(h, sweep_pair(h, v, B.y1, B.y1, nullptr, B.y0, y2, nullptr, 0.0, 1.0));
         else
           HIPCHK(h, launch_jacobi(v, B.y1, B.y1, nullptr, h->opt.transfer_variant, B.y0,
                                   h->stream));

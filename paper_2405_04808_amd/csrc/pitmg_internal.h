@@ -42,6 +42,14 @@ struct LevelView {
   // host-side: split-sweep buffers of this level, or NULL (never read on the
   // device)
   const SplitBuffers* split = nullptr;
+  // weight of the block Jacobi correction, y <- (1-omega) y + omega D^{-1}(b -
+  // (L+L^T) y); 1 on the coarsest level, whose sweeps are the exact block
+  // solves of the coarse SGS
+  double omega = 1.0;
+  // scale of the mu block in the transfers between this level and the next
+  // coarser one (interpolation multiplies coarse mu by it, restriction
+  // weights the mu residual rows by it)
+  double mu_scale = 1.0;
 };
 
 // Block pointers of a level in the arithmetic of the smoother.
@@ -107,16 +115,19 @@ hipError_t launch_factor32(const LevelView& L, float* Gi32, int level, int* fail
 // dst = (float) src
 hipError_t launch_to_f32(float* dst, const double* src, long long count, hipStream_t s);
 
-// One block Jacobi sweep: ynew = D^{-1}(b - (L+L^T) yc) where the coupling
-// values yc are taken from yold (NULL = 0) plus, if ecoarse != NULL, the
-// interpolation of the coarse vector ecoarse (variant as in the options).
+// One weighted block Jacobi sweep from yc = yold (NULL = 0) plus, if
+// ecoarse != NULL, the interpolation of the coarse vector ecoarse (variant as
+// in the options, mu scaled by L.mu_scale):
+//     ynew = (1 - w) yc + w D^{-1}(b - (L+L^T) yc),   w = L.omega.
 // If restrict_out != NULL (only with ecoarse == NULL), also the restricted
-// residual R (L+L^T)(yold - ynew) of the next coarser level, as
-// launch_restrict_delta computes it: inside the sweep where the kernel
-// supports it, else by that kernel after the sweep.
+// residual R (rbeta b + (L+L^T)(ra yold - ynew)) of the next coarser level,
+// as launch_restrict_delta computes it: inside the sweep where the kernel
+// supports it, else by that kernel after the sweep.  The caller picks
+// (rbeta, ra) so that this is the residual b - A~ ynew (see vcycle_level).
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
                          const double* ecoarse, int variant, double* ynew,
-                         hipStream_t s, double* restrict_out = nullptr);
+                         hipStream_t s, double* restrict_out = nullptr, double rbeta = 0.0,
+                         double ra = 1.0);
 
 // Register-tiled sweep for p == q in {64, 128} (16-byte aligned blocks); the
 // launchers follow L.fp32 for the arithmetic.  restrict_out as in
@@ -133,49 +144,55 @@ struct PairSync {
 };
 // Two consecutive sweeps in one launch (y1 = first, y2 = second sweep; the
 // coarse correction, if any, folds into the first, the restriction, if any,
-// comes from the second) for levels that sweep with the one-step tiled
-// kernel or, in FP64, the shared-block kernel.  jacobi_pair_supported says
-// whether launch_jacobi_pair applies
+// comes from the second and is R (rbeta b + (L+L^T)(ra y1 - y2))) for levels
+// that sweep with the one-step tiled kernel or, in FP64, the shared-block
+// kernel.  jacobi_pair_supported says whether launch_jacobi_pair applies
 // (never while the stream is being captured: the tickets and epochs are
 // launch arguments).
 bool jacobi_pair_supported(const LevelView& L, hipStream_t s);
 // *groups: work-groups (tickets) of the launch, set whenever it is issued.
 hipError_t launch_jacobi_pair(const LevelView& L, const double* b, const double* yold,
                               const double* ecoarse, int variant, double* y1, double* y2,
-                              double* restrict_out, const PairSync& ps, int* groups,
-                              hipStream_t s);
+                              double* restrict_out, double rbeta, double ra,
+                              const PairSync& ps, int* groups, hipStream_t s);
 hipError_t launch_jacobi_shared2(const LevelView& L, const double* b, const double* yold,
                                  const double* ecoarse, int variant, double* y1, double* y2,
-                                 double* restrict_out, const PairSync& ps, int* groups,
-                                 hipStream_t s);
+                                 double* restrict_out, double rbeta, double ra,
+                                 const PairSync& ps, int* groups, hipStream_t s);
 hipError_t launch_jacobi_tiled2(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* y1, double* y2,
-                                double* restrict_out, const PairSync& ps, hipStream_t s);
+                                double* restrict_out, double rbeta, double ra,
+                                const PairSync& ps, hipStream_t s);
 hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
                                const double* ecoarse, int variant, double* ynew,
-                               double* restrict_out, hipStream_t s);
+                               double* restrict_out, double rbeta, double ra, hipStream_t s);
 
 // Sweep for V and Z~ shared by every step (stride 0), p == q in {64, 128}.
 bool jacobi_shared_supported(const LevelView& L);
 hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* ynew,
-                                double* restrict_out, hipStream_t s);
+                                double* restrict_out, double rbeta, double ra, hipStream_t s);
 
 // out = beta*b + alpha*(A~ x) on one level (b may be NULL when beta == 0).
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b,
                         double alpha, double beta, double* out, hipStream_t s);
 
 // Coarse right-hand side from the last pre-smoothing sweep:
-// bc = R (L+L^T)(yprev - y)  (yprev NULL = 0).
-hipError_t launch_restrict_delta(int p, int q, int nf, const double* yprev,
-                                 const double* y, int variant, double* bc,
-                                 hipStream_t s);
+// bc = R (beta b + (L+L^T)(a ya - y))  (ya NULL = 0; b unread if beta == 0),
+// the mu rows of R scaled by mu_scale.
+hipError_t launch_restrict_delta(int p, int q, int nf, const double* b, double beta,
+                                 const double* ya, double a, const double* y, int variant,
+                                 double mu_scale, double* bc, hipStream_t s);
 // bc = R r (general restriction of a full fine vector).
 hipError_t launch_restrict(int p, int q, int nf, const double* r, int variant,
-                           double* bc, hipStream_t s);
+                           double mu_scale, double* bc, hipStream_t s);
 // y += P e  (interpolate and add).
 hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant,
-                             double* y, hipStream_t s);
+                             double mu_scale, double* y, hipStream_t s);
+// y = w y + (1 - w)(yold + P ec)  (yold, ec NULL = 0): the weighting of a
+// sweep written unweighted by a kernel that does not weight itself.
+hipError_t launch_weight(int p, int q, int n, double w, const double* yold, const double* ec,
+                         int variant, double mu_scale, double* y, hipStream_t s);
 
 // Coarse GMRES + SGS (pitmg_coarse.hip).  work: coarse_work_doubles(...)
 // doubles holding the coarse Krylov bases; cst: coarse_state_doubles(cap)

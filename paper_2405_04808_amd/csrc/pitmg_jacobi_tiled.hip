@@ -13,15 +13,21 @@
 namespace pitmg {
 
 // Restriction of the residual after the last pre-smoothing sweep, fused
-// into that sweep: r = (L+L^T)(y_old - y) is nonzero only in the u and mu
-// slots (r_u,k = mu_k^old - mu_k, r_mu,k = u_k^old - u_k), and the coarse
+// into that sweep.  With y_A the iterate before the sweep (single sweep) or
+// the first sweep's result (two-sweep launch) and y its output, the caller
+// chooses (beta, a) so that the residual is r = beta b + (L+L^T)(a y_A - y):
+// beta = 0, a = 1 for undamped sweeps; for weighted sweeps from a zero
+// iterate beta = (1-w)^s, a = w (s = 1, 2 sweeps).  (L+L^T) c is nonzero
+// only in the u and mu rows (r_u,k = c_mu,k, r_mu,k = c_u,k), and the coarse
 // vector takes fine step kf = 2m-1 (variant 0) or 2m (variant 1) for coarse
-// step m.  The work-group that produces u_kf writes the coarse mu entry and
-// the zero v, z, lambda entries of m; the one that produces mu_kf (block
-// kf+1) writes the coarse u entry.  Same doubles as k_restrict_delta.
+// step m, the mean of fine steps 2m-1, 2m for the control, and mu_scale on
+// the mu rows.  The work-group that produces u_kf writes the coarse mu, v,
+// z, lambda entries of m; the one that produces mu_kf (block kf+1) writes
+// the coarse u entry.  Same doubles as k_restrict_delta.  p = q here.
 struct FusedRestrict {
   double* rc;                  // coarse vector, or NULL (no restriction)
   int variant;
+  double beta, a, mu_scale;
   // coarse step m (1-based) whose mu, v, z, lambda block k writes, else 0
   __device__ int mu_writer(int k) const {
     if (!rc) return 0;
@@ -34,6 +40,31 @@ struct FusedRestrict {
     const int kf = k - 1;
     if (variant == 0) return (kf & 1) ? (kf + 1) / 2 : 0;
     return (kf & 1) ? 0 : kf / 2;
+  }
+  __device__ int fine(int m) const { return variant == 0 ? 2 * m - 1 : 2 * m; }
+  // coarse mu, v, z, lambda of step m from c_u = a y_A,u - y_u at fine step kf
+  __device__ void put_mu(int m, int i, double cu, const double* __restrict__ b,
+                         const TypeMajor& Tm, const TypeMajor& Tc, int P) const {
+    const long long o = (long long)(m - 1) * P + i;
+    const long long f = (long long)(fine(m) - 1) * P + i;
+    if (beta != 0.0) {
+      rc[Tc.m + o] = mu_scale * (beta * b[Tm.m + f] + cu);
+      rc[Tc.v + o] = beta * b[Tm.v + f];
+      rc[Tc.l + o] = beta * b[Tm.l + f];
+      rc[Tc.z + o] = 0.5 * beta * (b[Tm.z + (long long)(2 * m - 2) * P + i] +
+                                   b[Tm.z + (long long)(2 * m - 1) * P + i]);
+    } else {
+      rc[Tc.m + o] = mu_scale * cu;
+      rc[Tc.v + o] = 0.0;
+      rc[Tc.z + o] = 0.0;
+      rc[Tc.l + o] = 0.0;
+    }
+  }
+  // coarse u of step m from c_mu = a y_A,mu - y_mu at fine step kf
+  __device__ void put_u(int m, int i, double cmu, const double* __restrict__ b,
+                        const TypeMajor& Tm, const TypeMajor& Tc, int P) const {
+    const long long f = (long long)(fine(m) - 1) * P + i;
+    rc[Tc.u + (long long)(m - 1) * P + i] = (beta != 0.0 ? beta * b[Tm.u + f] : 0.0) + cmu;
   }
 };
 
@@ -51,29 +82,21 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   const int nc = n / 2;
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
   const int kb = blockIdx.x;
-
-  auto cu = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
-    return v;
-  };
-  auto cm = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
-    return v;
-  };
+  const double w = L.omega;
+  const PrevIterate prev{yold, ec, P, P, n, variant, L.mu_scale};
+  auto cu = [&](int k1, int i) -> double { return prev.at(0, k1, i); };
+  auto cm = [&](int k1, int i) -> double { return prev.at(4, k1, i); };
+  auto ya = [&](long long idx) -> double { return yold ? fr.a * yold[idx] : 0.0; };
 
   if (kb == n) {                               // block n+1 = (v_n, mu_n)
     const int mu_m = fr.u_writer(n + 1);
     for (int i = tid; i < P; i += kTiledThreads) {
       const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
       const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
-      const double mo = -rmm - rvv;
-      ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+      const double mo = weigh(w, -rmm - rvv, prev, 4, n, i);
+      ynew[Tm.v + (long long)(n - 1) * P + i] = weigh(w, -rmm, prev, 1, n, i);
       ynew[Tm.m + (long long)(n - 1) * P + i] = mo;
-      if (mu_m)
-        fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] =
-            (yold ? yold[Tm.m + (long long)(n - 1) * P + i] : 0.0) - mo;
+      if (mu_m) fr.put_u(mu_m, i, ya(Tm.m + (long long)(n - 1) * P + i) - mo, b, Tm, Tc, P);
     }
     return;
   }
@@ -100,25 +123,17 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
   const int rm_m = fr.mu_writer(k), ru_m = fr.u_writer(k);
   for (int i = tid; i < P; i += kTiledThreads) {
-    const double uo = (double)TS::u_of(scr, sru, i);
+    const double uo = weigh(w, (double)TS::u_of(scr, sru, i), prev, 0, k, i);
     ynew[Tm.u + kk * P + i] = uo;
-    ynew[Tm.z + kk * P + i] = (double)TS::z_of(scr, srz, i);
-    ynew[Tm.l + kk * P + i] = (double)slam[i];
+    ynew[Tm.z + kk * P + i] = weigh(w, (double)TS::z_of(scr, srz, i), prev, 2, k, i);
+    ynew[Tm.l + kk * P + i] = weigh(w, (double)slam[i], prev, 3, k, i);
     if (hv) {
-      const double mo = (double)TS::mu_of(scr, srm, srv, i);
+      const double mo = weigh(w, (double)TS::mu_of(scr, srm, srv, i), prev, 4, k - 1, i);
       ynew[Tm.m + (kk - 1) * P + i] = mo;
-      ynew[Tm.v + (kk - 1) * P + i] = -(double)srm[i];
-      if (ru_m)
-        fr.rc[Tc.u + (long long)(ru_m - 1) * P + i] =
-            (yold ? yold[Tm.m + (kk - 1) * P + i] : 0.0) - mo;
+      ynew[Tm.v + (kk - 1) * P + i] = weigh(w, -(double)srm[i], prev, 1, k - 1, i);
+      if (ru_m) fr.put_u(ru_m, i, ya(Tm.m + (kk - 1) * P + i) - mo, b, Tm, Tc, P);
     }
-    if (rm_m) {
-      const long long o = (long long)(rm_m - 1) * P + i;
-      fr.rc[Tc.m + o] = (yold ? yold[Tm.u + kk * P + i] : 0.0) - uo;
-      fr.rc[Tc.v + o] = 0.0;
-      fr.rc[Tc.z + o] = 0.0;
-      fr.rc[Tc.l + o] = 0.0;
-    }
+    if (rm_m) fr.put_mu(rm_m, i, ya(Tm.u + kk * P + i) - uo, b, Tm, Tc, P);
   }
 }
 
@@ -142,8 +157,8 @@ static hipError_t launch_tiled_t(const LevelView& L, const double* b, const doub
 
 hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double* yold,
                                const double* ecoarse, int variant, double* ynew,
-                               double* restrict_out, hipStream_t s) {
-  const FusedRestrict fr{restrict_out, variant};
+                               double* restrict_out, double rbeta, double ra, hipStream_t s) {
+  const FusedRestrict fr{restrict_out, variant, rbeta, ra, L.mu_scale};
   return L.fp32 ? launch_tiled_t<float>(L, b, yold, ecoarse, variant, ynew, fr, s)
                 : launch_tiled_t<double>(L, b, yold, ecoarse, variant, ynew, fr, s);
 }
@@ -216,6 +231,7 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   const TypeMajor Tm(P, P, n);
   const int nc = n / 2;
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
+  const double w = L.omega;
   if (tid == 0) {
     const unsigned long long t = atomicAdd(ps.ticket, 1ull) - ps.base;
     skb = t < (unsigned long long)n ? (int)t : -1;
@@ -229,17 +245,12 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   const bool on = tid < P;
   const int i = tid;
 
-  // first sweep's couplings: previous iterate plus the interpolated coarse
+  // first sweep: from the previous iterate plus the interpolated coarse
   // correction (first post-smoothing sweep)
-  auto cu = [&](int k1) -> double {
-    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
-    return v;
-  };
-  auto cm = [&](int k1) -> double {
-    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
-    return v;
+  const PrevIterate prev{yold, ec, P, P, n, variant, L.mu_scale};
+  // second sweep: weighted against this block's own first-sweep values
+  auto weigh1 = [&](double yhat, double y1v) -> double {
+    return w == 1.0 ? yhat : w * yhat + (1.0 - w) * y1v;
   };
   // publish this block's first sweep, then wait for the neighbours' (lo, hi:
   // block indices kb-1 and kb+1, or -1)
@@ -264,13 +275,13 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   double bu = 0.0, bm = 0.0;
   if (on) {
     bu = b[Tm.u + kk * P + i];
-    sru[i] = (T)(bu - cm(k));
+    sru[i] = (T)(bu - prev.at(4, k, i));
     srl[i] = (T)b[Tm.l + kk * P + i];
     srz[i] = (T)b[Tm.z + kk * P + i];
     if (hv) {
       srv[i] = (T)b[Tm.v + (kk - 1) * P + i];
       bm = b[Tm.m + (kk - 1) * P + i];
-      srm[i] = (T)(bm - cu(k - 1));
+      srm[i] = (T)(bm - prev.at(0, k - 1, i));
     } else {
       srv[i] = 0;
       srm[i] = 0;
@@ -282,24 +293,29 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   // only coupling is u_n of block n: no other work-group reads it, and
   // block n's second sweep takes mu_n from this thread's register
   const bool tail = kb == n - 1;
-  double rvn = 0.0, mon1 = 0.0;
+  double rvn = 0.0, mon1 = 0.0, von1 = 0.0;
   if (tail && on) {
     rvn = b[Tm.v + (long long)(n - 1) * P + i];
-    const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n);
-    mon1 = -rmm - rvn;
-    y1[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+    const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - prev.at(0, n, i);
+    mon1 = weigh(w, -rmm - rvn, prev, 4, n, i);
+    von1 = weigh(w, -rmm, prev, 1, n, i);
+    y1[Tm.v + (long long)(n - 1) * P + i] = von1;
     y1[Tm.m + (long long)(n - 1) * P + i] = mon1;
   }
-  double uo1 = 0.0, mo1 = 0.0;
+  // this block's first-sweep values stay in registers for the second sweep
+  double uo1 = 0.0, mo1 = 0.0, zo1 = 0.0, lo1 = 0.0, vo1 = 0.0;
   if (on) {
-    uo1 = (double)TS::u_of(scr, sru, i);
+    uo1 = weigh(w, (double)TS::u_of(scr, sru, i), prev, 0, k, i);
+    zo1 = weigh(w, (double)TS::z_of(scr, srz, i), prev, 2, k, i);
+    lo1 = weigh(w, (double)slam[i], prev, 3, k, i);
     coherent_store(y1 + Tm.u + kk * P + i, uo1);                    // read by block k+1
-    y1[Tm.z + kk * P + i] = (double)TS::z_of(scr, srz, i);
-    y1[Tm.l + kk * P + i] = (double)slam[i];
+    y1[Tm.z + kk * P + i] = zo1;
+    y1[Tm.l + kk * P + i] = lo1;
     if (hv) {
-      mo1 = (double)TS::mu_of(scr, srm, srv, i);
+      mo1 = weigh(w, (double)TS::mu_of(scr, srm, srv, i), prev, 4, k - 1, i);
+      vo1 = weigh(w, -(double)srm[i], prev, 1, k - 1, i);
       coherent_store(y1 + Tm.m + (kk - 1) * P + i, mo1);            // read by block k-1
-      y1[Tm.v + (kk - 1) * P + i] = -(double)srm[i];
+      y1[Tm.v + (kk - 1) * P + i] = vo1;
     }
   }
   hand_off(hv ? kb - 1 : -1, tail ? -1 : kb + 1);
@@ -312,31 +328,25 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
   const int rm_m = fr.mu_writer(k), ru_m = fr.u_writer(k);
   if (on) {
-    const double uo = (double)TS::u_of(scr, sru, i);
+    const double uo = weigh1((double)TS::u_of(scr, sru, i), uo1);
     y2[Tm.u + kk * P + i] = uo;
-    y2[Tm.z + kk * P + i] = (double)TS::z_of(scr, srz, i);
-    y2[Tm.l + kk * P + i] = (double)slam[i];
+    y2[Tm.z + kk * P + i] = weigh1((double)TS::z_of(scr, srz, i), zo1);
+    y2[Tm.l + kk * P + i] = weigh1((double)slam[i], lo1);
     if (hv) {
-      const double mo = (double)TS::mu_of(scr, srm, srv, i);
+      const double mo = weigh1((double)TS::mu_of(scr, srm, srv, i), mo1);
       y2[Tm.m + (kk - 1) * P + i] = mo;
-      y2[Tm.v + (kk - 1) * P + i] = -(double)srm[i];
-      if (ru_m) fr.rc[Tc.u + (long long)(ru_m - 1) * P + i] = mo1 - mo;
+      y2[Tm.v + (kk - 1) * P + i] = weigh1(-(double)srm[i], vo1);
+      if (ru_m) fr.put_u(ru_m, i, fr.a * mo1 - mo, b, Tm, Tc, P);
     }
-    if (rm_m) {
-      const long long o = (long long)(rm_m - 1) * P + i;
-      fr.rc[Tc.m + o] = uo1 - uo;
-      fr.rc[Tc.v + o] = 0.0;
-      fr.rc[Tc.z + o] = 0.0;
-      fr.rc[Tc.l + o] = 0.0;
-    }
+    if (rm_m) fr.put_mu(rm_m, i, fr.a * uo1 - uo, b, Tm, Tc, P);
   }
   if (tail && on) {                            // block n+1, second sweep
     const int mu_m = fr.u_writer(n + 1);
     const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - uo1;
-    const double mo = -rmm - rvn;
-    y2[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+    const double mo = weigh1(-rmm - rvn, mon1);
+    y2[Tm.v + (long long)(n - 1) * P + i] = weigh1(-rmm, von1);
     y2[Tm.m + (long long)(n - 1) * P + i] = mo;
-    if (mu_m) fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] = mon1 - mo;
+    if (mu_m) fr.put_u(mu_m, i, fr.a * mon1 - mo, b, Tm, Tc, P);
   }
 }
 
@@ -355,8 +365,9 @@ static hipError_t launch_tiled2_t(const LevelView& L, const double* b, const dou
 
 hipError_t launch_jacobi_tiled2(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* y1, double* y2,
-                                double* restrict_out, const PairSync& ps, hipStream_t s) {
-  const FusedRestrict fr{restrict_out, variant};
+                                double* restrict_out, double rbeta, double ra,
+                                const PairSync& ps, hipStream_t s) {
+  const FusedRestrict fr{restrict_out, variant, rbeta, ra, L.mu_scale};
   return L.fp32 ? launch_tiled2_t<float>(L, b, yold, ecoarse, variant, y1, y2, fr, ps, s)
                 : launch_tiled2_t<double>(L, b, yold, ecoarse, variant, y1, y2, fr, ps, s);
 }
@@ -402,16 +413,11 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
   const T* __restrict__ Vs = Mats<T>::V(L);             // shared blocks
   const T* __restrict__ Zs = Mats<T>::Z(L);
 
-  auto cu = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
-    return v;
-  };
-  auto cm = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
-    return v;
-  };
+  const double w = L.omega;
+  const PrevIterate prev{yold, ec, P, P, n, variant, L.mu_scale};
+  auto cu = [&](int k1, int i) -> double { return prev.at(0, k1, i); };
+  auto cm = [&](int k1, int i) -> double { return prev.at(4, k1, i); };
+  auto ya = [&](long long idx) -> double { return yold ? fr.a * yold[idx] : 0.0; };
 
   // tiles of the first step in flight while the right-hand sides are gathered
   typename TS::Regs R;
@@ -437,12 +443,10 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     for (int i = tid; i < P; i += kTiledThreads) {
       const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
       const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
-      const double mo = -rmm - rvv;
-      ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+      const double mo = weigh(w, -rmm - rvv, prev, 4, n, i);
+      ynew[Tm.v + (long long)(n - 1) * P + i] = weigh(w, -rmm, prev, 1, n, i);
       ynew[Tm.m + (long long)(n - 1) * P + i] = mo;
-      if (mu_m)
-        fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] =
-            (yold ? yold[Tm.m + (long long)(n - 1) * P + i] : 0.0) - mo;
+      if (mu_m) fr.put_u(mu_m, i, ya(Tm.m + (long long)(n - 1) * P + i) - mo, b, Tm, Tc, P);
     }
   }
   __syncthreads();
@@ -537,16 +541,11 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     if (bi + 1 < nb) TS::load_n(L, kk + 1, R);             // N of the next step
     const int rm_m = fr.mu_writer((int)kk + 1);
     for (int i = tid; i < P; i += kTiledThreads) {
-      const double uo = (double)(sru[bi][i] - TS::col_total(red, i));
+      const double uo =
+          weigh(w, (double)(sru[bi][i] - TS::col_total(red, i)), prev, 0, (int)kk + 1, i);
       ynew[Tm.u + kk * P + i] = uo;
-      ynew[Tm.l + kk * P + i] = (double)slam[bi][i];
-      if (rm_m) {
-        const long long o = (long long)(rm_m - 1) * P + i;
-        fr.rc[Tc.m + o] = (yold ? yold[Tm.u + kk * P + i] : 0.0) - uo;
-        fr.rc[Tc.v + o] = 0.0;
-        fr.rc[Tc.z + o] = 0.0;
-        fr.rc[Tc.l + o] = 0.0;
-      }
+      ynew[Tm.l + kk * P + i] = weigh(w, (double)slam[bi][i], prev, 3, (int)kk + 1, i);
+      if (rm_m) fr.put_mu(rm_m, i, ya(Tm.u + kk * P + i) - uo, b, Tm, Tc, P);
     }
     __syncthreads();
   }
@@ -587,15 +586,14 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
       zt += pz[g][s][i];
       vt += pv[g][s][i];
     }
-    ynew[Tm.z + kk * P + i] = (double)(srz[s][i] - zt);
+    const int k = (int)kk + 1;
+    ynew[Tm.z + kk * P + i] = weigh(w, (double)(srz[s][i] - zt), prev, 2, k, i);
     if (kk >= 1) {
-      const double mo = (double)(vt - srm[s][i] - srv[s][i]);
+      const double mo = weigh(w, (double)(vt - srm[s][i] - srv[s][i]), prev, 4, k - 1, i);
       ynew[Tm.m + (kk - 1) * P + i] = mo;
-      ynew[Tm.v + (kk - 1) * P + i] = -(double)srm[s][i];
-      const int ru_m = fr.u_writer((int)kk + 1);
-      if (ru_m)
-        fr.rc[Tc.u + (long long)(ru_m - 1) * P + i] =
-            (yold ? yold[Tm.m + (kk - 1) * P + i] : 0.0) - mo;
+      ynew[Tm.v + (kk - 1) * P + i] = weigh(w, -(double)srm[s][i], prev, 1, k - 1, i);
+      const int ru_m = fr.u_writer(k);
+      if (ru_m) fr.put_u(ru_m, i, ya(Tm.m + (kk - 1) * P + i) - mo, b, Tm, Tc, P);
     }
   }
 }
@@ -663,8 +661,24 @@ __device__ __forceinline__ void shared_nl_sweep(
       const double* p = yold + Tm.m + (long long)(k1 - 1) * P + i;
       v = xin && k1 == klast && klast < n ? coherent_load(p) : *p;
     }
-    if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
+    if (ec) v += L.mu_scale * interp_node(ec + Tc.m, nc, P, k1, i, variant);
     return v;
+  };
+  // the previous iterate at this group's own slots, for the weighted update
+  // and the fused restriction; the two slots the first sweep published with
+  // device-coherent stores are read back the same way
+  const double w = L.omega;
+  const PrevIterate prev{yold, ec, P, P, n, variant, L.mu_scale};
+  auto own = [&](int type, int k1, int i) -> double {
+    if (xin && yold && ((type == 0 && k1 == klast) || (type == 4 && k1 == k0 - 1)))
+      return coherent_load(yold + (type == 0 ? Tm.u : Tm.m) + (long long)(k1 - 1) * P + i);
+    return prev.at(type, k1, i);
+  };
+  auto wt = [&](double yhat, int type, int k1, int i) -> double {
+    return w == 1.0 ? yhat : w * yhat + (1.0 - w) * own(type, k1, i);
+  };
+  auto ya = [&](int type, int k1, int i) -> double {
+    return yold ? fr.a * own(type, k1, i) : 0.0;
   };
   // N_k (row-major, contiguous) into nbuf: wave w moves chunks w, w + 8, ...
   auto stage_n = [&](long long kk) {
@@ -712,12 +726,13 @@ __device__ __forceinline__ void shared_nl_sweep(
     for (int i = tid; i < P; i += kTiledThreads) {
       const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
       const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
-      const double mo = -rmm - rvv;
-      ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
+      const double mo = wt(-rmm - rvv, 4, n, i);
+      const double vo = wt(-rmm, 1, n, i);
+      // the old values are read before this thread's stores replace them
+      const double ca = mu_m ? ya(4, n, i) : 0.0;
+      ynew[Tm.v + (long long)(n - 1) * P + i] = vo;
       ynew[Tm.m + (long long)(n - 1) * P + i] = mo;
-      if (mu_m)
-        fr.rc[Tc.u + (long long)(mu_m - 1) * P + i] =
-            (yold ? yold[Tm.m + (long long)(n - 1) * P + i] : 0.0) - mo;
+      if (mu_m) fr.put_u(mu_m, i, ca - mo, b, Tm, Tc, P);
     }
   }
   __syncthreads();
@@ -877,33 +892,36 @@ __device__ __forceinline__ void shared_nl_sweep(
       zt += pz[(g * kMaxSteps + s2) * P + i];
       vt += pv[(g * kMaxSteps + s2) * P + i];
     }
-    const double uo = sou[s2][i];
+    const int rm_m = fr.mu_writer(k);
+    const int ru_m = k >= 2 ? fr.u_writer(k) : 0;
+    // every old value of the block is read before any store of this thread
+    // replaces it (ynew may be the buffer of yold only in the second sweep of
+    // a two-sweep launch, where yold is this group's own first sweep)
+    const double uo = wt(sou[s2][i], 0, k, i);
+    const double lo = wt(slam[s2][i], 3, k, i);
+    const double zo = wt(b[Tm.z + kk * P + i] - zt, 2, k, i);
+    const double cua = rm_m ? ya(0, k, i) : 0.0;
+    double mo = 0.0, vo = 0.0, cma = 0.0;
+    if (k >= 2) {
+      const double rm = b[Tm.m + (kk - 1) * P + i] - cu(k - 1, i);
+      mo = wt(vt - rm - b[Tm.v + (kk - 1) * P + i], 4, k - 1, i);
+      vo = wt(-rm, 1, k - 1, i);
+      cma = ru_m ? ya(4, k - 1, i) : 0.0;
+    }
     if (pub && k == klast)
       coherent_store(ynew + Tm.u + kk * P + i, uo);      // read by the next group
     else
       ynew[Tm.u + kk * P + i] = uo;
-    ynew[Tm.l + kk * P + i] = slam[s2][i];
-    ynew[Tm.z + kk * P + i] = b[Tm.z + kk * P + i] - zt;
-    const int rm_m = fr.mu_writer(k);
-    if (rm_m) {
-      const long long o = (long long)(rm_m - 1) * P + i;
-      fr.rc[Tc.m + o] = (yold ? yold[Tm.u + kk * P + i] : 0.0) - uo;
-      fr.rc[Tc.v + o] = 0.0;
-      fr.rc[Tc.z + o] = 0.0;
-      fr.rc[Tc.l + o] = 0.0;
-    }
+    ynew[Tm.l + kk * P + i] = lo;
+    ynew[Tm.z + kk * P + i] = zo;
+    if (rm_m) fr.put_mu(rm_m, i, cua - uo, b, Tm, Tc, P);
     if (k >= 2) {
-      const double rm = b[Tm.m + (kk - 1) * P + i] - cu(k - 1, i);
-      const double mo = vt - rm - b[Tm.v + (kk - 1) * P + i];
       if (pub && k == k0)
         coherent_store(ynew + Tm.m + (kk - 1) * P + i, mo);   // read by the previous group
       else
         ynew[Tm.m + (kk - 1) * P + i] = mo;
-      ynew[Tm.v + (kk - 1) * P + i] = -rm;
-      const int ru_m = fr.u_writer(k);
-      if (ru_m)
-        fr.rc[Tc.u + (long long)(ru_m - 1) * P + i] =
-            (yold ? yold[Tm.m + (kk - 1) * P + i] : 0.0) - mo;
+      ynew[Tm.v + (kk - 1) * P + i] = vo;
+      if (ru_m) fr.put_u(ru_m, i, cma - mo, b, Tm, Tc, P);
     }
   }
 }
@@ -944,8 +962,8 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl2(
   }
   const int k0 = g * per_wg + 1;
   const int nb = min(per_wg, L.n - k0 + 1);
-  shared_nl_sweep<RT, CT>(L, b, yold, ec, variant, y1, k0, nb, FusedRestrict{nullptr, variant},
-                          true, false);
+  shared_nl_sweep<RT, CT>(L, b, yold, ec, variant, y1, k0, nb,
+                          FusedRestrict{nullptr, variant, 0.0, 1.0, L.mu_scale}, true, false);
   __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): boundary stores acknowledged
   __syncthreads();
   if (tid == 0) {
@@ -999,9 +1017,9 @@ int shared_steps_per_group(const LevelView& L) {
 
 hipError_t launch_jacobi_shared2(const LevelView& L, const double* b, const double* yold,
                                  const double* ecoarse, int variant, double* y1, double* y2,
-                                 double* restrict_out, const PairSync& ps, int* groups,
-                                 hipStream_t s) {
-  const FusedRestrict fr{restrict_out, variant};
+                                 double* restrict_out, double rbeta, double ra,
+                                 const PairSync& ps, int* groups, hipStream_t s) {
+  const FusedRestrict fr{restrict_out, variant, rbeta, ra, L.mu_scale};
   const int per = shared_steps_per_group(L);
   const int nwg = (L.n + per - 1) / per;
   *groups = nwg;
@@ -1017,8 +1035,8 @@ hipError_t launch_jacobi_shared2(const LevelView& L, const double* b, const doub
 
 hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const double* yold,
                                 const double* ecoarse, int variant, double* ynew,
-                                double* restrict_out, hipStream_t s) {
-  const FusedRestrict fr{restrict_out, variant};
+                                double* restrict_out, double rbeta, double ra, hipStream_t s) {
+  const FusedRestrict fr{restrict_out, variant, rbeta, ra, L.mu_scale};
   const int per = shared_steps_per_group(L);
   return L.fp32 ? launch_shared_t<float>(L, b, yold, ecoarse, variant, ynew, per, fr, s)
                 : launch_shared_t<double>(L, b, yold, ecoarse, variant, ynew, per, fr, s);

@@ -227,28 +227,18 @@ __global__ __launch_bounds__(NT) void k_jacobi(LevelView L, const double* __rest
   T* sm = reinterpret_cast<T*>(sm_raw);
   const int p = L.p, q = L.q, n = L.n;
   const TypeMajor Tm(p, q, n);
-  const int nc = n / 2;
-  const TypeMajor Tc(p, q, nc > 0 ? nc : 1);
   const int kb = blockIdx.x, tid = threadIdx.x;
-
-  // coupling values of the previous iterate: yold + P ec (u and mu only)
-  auto cu = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * p + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.u, nc, p, k1, i, variant);
-    return v;
-  };
-  auto cm = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * p + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.m, nc, p, k1, i, variant);
-    return v;
-  };
+  const double w = L.omega;
+  // the iterate the sweep starts from: yold + P ec; its u and mu slots are
+  // the couplings, and every slot enters the weighted update
+  const PrevIterate prev{yold, ec, p, q, n, variant, L.mu_scale};
 
   if (kb == n) {                               // block n+1 = (v_n, mu_n)
     for (int i = tid; i < p; i += NT) {
       const double rvv = b[Tm.v + (long long)(n - 1) * p + i];
-      const double rmm = b[Tm.m + (long long)(n - 1) * p + i] - cu(n, i);
-      ynew[Tm.v + (long long)(n - 1) * p + i] = -rmm;
-      ynew[Tm.m + (long long)(n - 1) * p + i] = -rmm - rvv;
+      const double rmm = b[Tm.m + (long long)(n - 1) * p + i] - prev.at(0, n, i);
+      ynew[Tm.v + (long long)(n - 1) * p + i] = weigh(w, -rmm, prev, 1, n, i);
+      ynew[Tm.m + (long long)(n - 1) * p + i] = weigh(w, -rmm - rvv, prev, 4, n, i);
     }
     return;
   }
@@ -268,11 +258,11 @@ __global__ __launch_bounds__(NT) void k_jacobi(LevelView L, const double* __rest
   T* s = t + p;
   T* part = s + p;
   for (int i = tid; i < p; i += NT) {
-    ru[i] = (T)(b[Tm.u + (long long)(k - 1) * p + i] - cm(k, i));
+    ru[i] = (T)(b[Tm.u + (long long)(k - 1) * p + i] - prev.at(4, k, i));
     rl[i] = (T)b[Tm.l + (long long)(k - 1) * p + i];
     if (hv) {
       rv[i] = (T)b[Tm.v + (long long)(k - 2) * p + i];
-      rm[i] = (T)(b[Tm.m + (long long)(k - 2) * p + i] - cu(k - 1, i));
+      rm[i] = (T)(b[Tm.m + (long long)(k - 2) * p + i] - prev.at(0, k - 1, i));
     } else {
       rv[i] = 0;
       rm[i] = 0;
@@ -282,17 +272,17 @@ __global__ __launch_bounds__(NT) void k_jacobi(LevelView L, const double* __rest
   __syncthreads();
   const long long kk = k - 1;
   block_solve<NT, T>(p, q, Mats<T>::N(L) + kk * L.sN, Mats<T>::V(L) + kk * L.sV,
-                     Mats<T>::Z(L) + kk * L.sZ, Mats<T>::Gi(L) + kk * p * p, hv, rv, ru, rz, rl, rm, ov, ou, oz, ol, om, t, s,
-                  part);
+                     Mats<T>::Z(L) + kk * L.sZ, Mats<T>::Gi(L) + kk * p * p, hv, rv, ru, rz, rl,
+                     rm, ov, ou, oz, ol, om, t, s, part);
   for (int i = tid; i < p; i += NT) {
-    ynew[Tm.u + kk * p + i] = (double)ou[i];
-    ynew[Tm.l + kk * p + i] = (double)ol[i];
+    ynew[Tm.u + kk * p + i] = weigh(w, (double)ou[i], prev, 0, k, i);
+    ynew[Tm.l + kk * p + i] = weigh(w, (double)ol[i], prev, 3, k, i);
     if (hv) {
-      ynew[Tm.v + (kk - 1) * p + i] = (double)ov[i];
-      ynew[Tm.m + (kk - 1) * p + i] = (double)om[i];
+      ynew[Tm.v + (kk - 1) * p + i] = weigh(w, (double)ov[i], prev, 1, k - 1, i);
+      ynew[Tm.m + (kk - 1) * p + i] = weigh(w, (double)om[i], prev, 4, k - 1, i);
     }
   }
-  for (int i = tid; i < q; i += NT) ynew[Tm.z + kk * q + i] = (double)oz[i];
+  for (int i = tid; i < q; i += NT) ynew[Tm.z + kk * q + i] = weigh(w, (double)oz[i], prev, 2, k, i);
 }
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -313,26 +303,31 @@ static hipError_t launch_jacobi_generic(const LevelView& L, const double* b, con
 
 hipError_t launch_jacobi(const LevelView& L, const double* b, const double* yold,
                          const double* ecoarse, int variant, double* ynew, hipStream_t s,
-                         double* restrict_out) {
+                         double* restrict_out, double rbeta, double ra) {
   if (restrict_out && ecoarse) return hipErrorInvalidValue;
   const bool al = L.fp32 ? aligned16(L.N32) && aligned16(L.V32) && aligned16(L.Z32) &&
                                aligned16(L.Gi32)
                          : aligned16(L.N) && aligned16(L.V) && aligned16(L.Z) && aligned16(L.Gi);
   const bool small = small_supported(L.p, L.q);
   if (!small && al && jacobi_shared_supported(L) && L.sweep_cfg >= 0)
-    return launch_jacobi_shared(L, b, yold, ecoarse, variant, ynew, restrict_out, s);
+    return launch_jacobi_shared(L, b, yold, ecoarse, variant, ynew, restrict_out, rbeta, ra, s);
   if (!small && al && jacobi_tiled_supported(L.p, L.q))
-    return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, restrict_out, s);
+    return launch_jacobi_tiled(L, b, yold, ecoarse, variant, ynew, restrict_out, rbeta, ra, s);
   hipError_t e;
-  if (small)
+  if (small) {
     e = launch_jacobi_small(L, b, yold, ecoarse, variant, ynew, s);
-  else if (al && split_supported(L))
+  } else if (al && split_supported(L)) {
+    // the split sweep writes the unweighted block solves; weight afterwards
     e = launch_jacobi_split(L, b, yold, ecoarse, variant, ynew, s);
-  else
+    if (e == hipSuccess && L.omega != 1.0)
+      e = launch_weight(L.p, L.q, L.n, L.omega, yold, ecoarse, variant, L.mu_scale, ynew, s);
+  } else {
     e = L.fp32 ? launch_jacobi_generic<float>(L, b, yold, ecoarse, variant, ynew, s)
                : launch_jacobi_generic<double>(L, b, yold, ecoarse, variant, ynew, s);
+  }
   if (e != hipSuccess || !restrict_out) return e;
-  return launch_restrict_delta(L.p, L.q, L.n, yold, ynew, variant, restrict_out, s);
+  return launch_restrict_delta(L.p, L.q, L.n, b, rbeta, yold, ra, ynew, variant, L.mu_scale,
+                               restrict_out, s);
 }
 
 static bool sweeps_tiled(const LevelView& L) {
@@ -359,17 +354,18 @@ bool jacobi_pair_supported(const LevelView& L, hipStream_t s) {
 
 hipError_t launch_jacobi_pair(const LevelView& L, const double* b, const double* yold,
                               const double* ecoarse, int variant, double* y1, double* y2,
-                              double* restrict_out, const PairSync& ps, int* groups,
-                              hipStream_t s) {
+                              double* restrict_out, double rbeta, double ra,
+                              const PairSync& ps, int* groups, hipStream_t s) {
   *groups = 0;
   if (!ps.ticket || !ps.flag || !ps.timeout) return hipErrorNotSupported;
   if (y1 == y2 || y1 == yold || y1 == b || y2 == b) return hipErrorInvalidValue;
   if (sweeps_shared_fp64(L))
-    return launch_jacobi_shared2(L, b, yold, ecoarse, variant, y1, y2, restrict_out, ps, groups,
-                                 s);
+    return launch_jacobi_shared2(L, b, yold, ecoarse, variant, y1, y2, restrict_out, rbeta, ra,
+                                 ps, groups, s);
   if (!sweeps_tiled(L)) return hipErrorNotSupported;
   *groups = L.n;                                   // one work-group per block 1..n
-  return launch_jacobi_tiled2(L, b, yold, ecoarse, variant, y1, y2, restrict_out, ps, s);
+  return launch_jacobi_tiled2(L, b, yold, ecoarse, variant, y1, y2, restrict_out, rbeta, ra,
+                              ps, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -419,30 +415,44 @@ __device__ __forceinline__ void locate(long long idx, const TypeMajor& T, int p,
   i = (int)(off % p);
 }
 
-__global__ void k_restrict_delta(int p, int q, int nf, const double* __restrict__ yprev,
-                                 const double* __restrict__ y, int variant,
+// Coarse step m of the restriction takes fine step kf = 2m-1 (variant 0) or
+// 2m (variant 1) for u, v, lambda, mu and the mean of fine steps 2m-1, 2m
+// for the control; the mu rows are weighted by mu_scale.
+__device__ __forceinline__ int restrict_fine_step(int m, int variant) {
+  return variant == 0 ? 2 * m - 1 : 2 * m;
+}
+
+__global__ void k_restrict_delta(int p, int q, int nf, const double* __restrict__ b, double beta,
+                                 const double* __restrict__ ya, double a,
+                                 const double* __restrict__ y, int variant, double mu_scale,
                                  double* __restrict__ bc) {
   const int nc = nf / 2;
   const TypeMajor Tf(p, q, nf), Tc(p, q, nc);
+  const long long segf[5] = {Tf.u, Tf.v, Tf.z, Tf.l, Tf.m};
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Tc.len;
        idx += (long long)gridDim.x * blockDim.x) {
     int type, m, i;
     locate(idx, Tc, p, q, type, m, i);
+    const int kf = restrict_fine_step(m, variant);
     double v = 0.0;
-    const int kf = variant == 0 ? 2 * m - 1 : 2 * m;
-    if (type == 0) {            // r_u,k = mu_k^prev - mu_k
-      const long long f = Tf.m + (long long)(kf - 1) * p + i;
-      v = (yprev ? yprev[f] : 0.0) - y[f];
-    } else if (type == 4) {     // r_mu,k = u_k^prev - u_k
-      const long long f = Tf.u + (long long)(kf - 1) * p + i;
-      v = (yprev ? yprev[f] : 0.0) - y[f];
+    if (beta != 0.0) {
+      if (type == 2)
+        v = 0.5 * beta * (b[Tf.z + (long long)(2 * m - 2) * q + i] +
+                          b[Tf.z + (long long)(2 * m - 1) * q + i]);
+      else
+        v = beta * b[segf[type] + (long long)(kf - 1) * p + i];
     }
-    bc[idx] = v;
+    // (L+L^T) c: the u_k row couples mu_k, the mu_k row couples u_k
+    if (type == 0 || type == 4) {
+      const long long f = (type == 0 ? Tf.m : Tf.u) + (long long)(kf - 1) * p + i;
+      v += (ya ? a * ya[f] : 0.0) - y[f];
+    }
+    bc[idx] = type == 4 ? mu_scale * v : v;
   }
 }
 
 __global__ void k_restrict(int p, int q, int nf, const double* __restrict__ r, int variant,
-                           double* __restrict__ bc) {
+                           double mu_scale, double* __restrict__ bc) {
   const int nc = nf / 2;
   const TypeMajor Tf(p, q, nf), Tc(p, q, nc);
   const long long segf[5] = {Tf.u, Tf.v, Tf.z, Tf.l, Tf.m};
@@ -454,15 +464,15 @@ __global__ void k_restrict(int p, int q, int nf, const double* __restrict__ r, i
     if (type == 2) {
       v = 0.5 * (r[Tf.z + (long long)(2 * m - 2) * q + i] + r[Tf.z + (long long)(2 * m - 1) * q + i]);
     } else {
-      const int kf = variant == 0 ? 2 * m - 1 : 2 * m;
+      const int kf = restrict_fine_step(m, variant);
       v = r[segf[type] + (long long)(kf - 1) * p + i];
     }
-    bc[idx] = v;
+    bc[idx] = type == 4 ? mu_scale * v : v;
   }
 }
 
 __global__ void k_interp_add(int p, int q, int nf, const double* __restrict__ e, int variant,
-                             double* __restrict__ y) {
+                             double mu_scale, double* __restrict__ y) {
   const int nc = nf / 2;
   const TypeMajor Tf(p, q, nf), Tc(p, q, nc);
   const long long segc[5] = {Tc.u, Tc.v, Tc.z, Tc.l, Tc.m};
@@ -473,7 +483,21 @@ __global__ void k_interp_add(int p, int q, int nf, const double* __restrict__ e,
     double v;
     if (type == 2) v = e[Tc.z + (long long)((k + 1) / 2 - 1) * q + i];
     else v = interp_node(e + segc[type], nc, p, k, i, variant);
-    y[idx] += v;
+    y[idx] += type == 4 ? mu_scale * v : v;
+  }
+}
+
+// y = w y + (1 - w)(yold + P ec)
+__global__ void k_weight(int p, int q, int n, double w, const double* __restrict__ yold,
+                         const double* __restrict__ ec, int variant, double mu_scale,
+                         double* __restrict__ y) {
+  const TypeMajor Tm(p, q, n);
+  const PrevIterate prev{yold, ec, p, q, n, variant, mu_scale};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Tm.len;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int type, k, i;
+    locate(idx, Tm, p, q, type, k, i);
+    y[idx] = w * y[idx] + (1.0 - w) * prev.at(type, k, i);
   }
 }
 
@@ -518,27 +542,36 @@ hipError_t launch_apply_identity(int p, int q, int n, const double* b, const dou
 }
 
 
-hipError_t launch_restrict_delta(int p, int q, int nf, const double* yprev, const double* y,
-                                 int variant, double* bc, hipStream_t s) {
+hipError_t launch_restrict_delta(int p, int q, int nf, const double* b, double beta,
+                                 const double* ya, double a, const double* y, int variant,
+                                 double mu_scale, double* bc, hipStream_t s) {
   const TypeMajor Tc(p, q, nf / 2);
   hipLaunchKernelGGL(k_restrict_delta, dim3(grid_for(Tc.len, 256)), dim3(256), 0, s, p, q, nf,
-                     yprev, y, variant, bc);
+                     b, beta, ya, a, y, variant, mu_scale, bc);
   return hipGetLastError();
 }
 
-hipError_t launch_restrict(int p, int q, int nf, const double* r, int variant, double* bc,
-                           hipStream_t s) {
+hipError_t launch_restrict(int p, int q, int nf, const double* r, int variant, double mu_scale,
+                           double* bc, hipStream_t s) {
   const TypeMajor Tc(p, q, nf / 2);
   hipLaunchKernelGGL(k_restrict, dim3(grid_for(Tc.len, 256)), dim3(256), 0, s, p, q, nf, r,
-                     variant, bc);
+                     variant, mu_scale, bc);
   return hipGetLastError();
 }
 
-hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant, double* y,
-                             hipStream_t s) {
+hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant,
+                             double mu_scale, double* y, hipStream_t s) {
   const TypeMajor Tf(p, q, nf);
   hipLaunchKernelGGL(k_interp_add, dim3(grid_for(Tf.len, 256)), dim3(256), 0, s, p, q, nf, e,
-                     variant, y);
+                     variant, mu_scale, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_weight(int p, int q, int n, double w, const double* yold, const double* ec,
+                         int variant, double mu_scale, double* y, hipStream_t s) {
+  const TypeMajor Tm(p, q, n);
+  hipLaunchKernelGGL(k_weight, dim3(grid_for(Tm.len, 256)), dim3(256), 0, s, p, q, n, w, yold,
+                     ec, variant, mu_scale, y);
   return hipGetLastError();
 }
 

@@ -29,26 +29,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi_small(LevelView L,
   const int kb = blockIdx.x * kSmallThreads + threadIdx.x;
   if (kb > n) return;
   const TypeMajor Tm(P, Q, n);
-  const int nc = n / 2;
-  const TypeMajor Tc(P, Q, nc > 0 ? nc : 1);
-  // coupling values of the previous iterate: yold + P ec (u and mu only)
-  auto cu = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * P + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.u, nc, P, k1, i, variant);
-    return v;
-  };
-  auto cm = [&](int k1, int i) -> double {
-    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * P + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.m, nc, P, k1, i, variant);
-    return v;
-  };
+  const double w = L.omega;
+  // the iterate the sweep starts from: yold + P ec (couplings in u and mu)
+  const PrevIterate prev{yold, ec, P, Q, n, variant, L.mu_scale};
+  auto cu = [&](int k1, int i) -> double { return prev.at(0, k1, i); };
+  auto cm = [&](int k1, int i) -> double { return prev.at(4, k1, i); };
   if (kb == n) {                                 // block n+1 = (v_n, mu_n)
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
       const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
-      ynew[Tm.v + (long long)(n - 1) * P + i] = -rmm;
-      ynew[Tm.m + (long long)(n - 1) * P + i] = -rmm - rvv;
+      ynew[Tm.v + (long long)(n - 1) * P + i] = weigh(w, -rmm, prev, 1, n, i);
+      ynew[Tm.m + (long long)(n - 1) * P + i] = weigh(w, -rmm - rvv, prev, 4, n, i);
     }
     return;
   }
@@ -105,11 +97,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi_small(LevelView L,
       nu += N[i * P + j] * lam[i];
       if (hv) vu += V[i * P + j] * lam[i];
     }
-    ynew[Tm.u + kk * P + j] = (double)(ru[j] - nu);
-    ynew[Tm.l + kk * P + j] = (double)lam[j];
+    ynew[Tm.u + kk * P + j] = weigh(w, (double)(ru[j] - nu), prev, 0, k, j);
+    ynew[Tm.l + kk * P + j] = weigh(w, (double)lam[j], prev, 3, k, j);
     if (hv) {
-      ynew[Tm.v + (kk - 1) * P + j] = (double)(-rm[j]);
-      ynew[Tm.m + (kk - 1) * P + j] = (double)(vu - rm[j] - rv[j]);
+      ynew[Tm.v + (kk - 1) * P + j] = weigh(w, (double)(-rm[j]), prev, 1, k - 1, j);
+      ynew[Tm.m + (kk - 1) * P + j] = weigh(w, (double)(vu - rm[j] - rv[j]), prev, 4, k - 1, j);
     }
   }
 #pragma unroll
@@ -117,7 +109,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi_small(LevelView L,
     T zu = 0;
 #pragma unroll
     for (int i = 0; i < P; ++i) zu += Z[i * Q + j] * lam[i];
-    ynew[Tm.z + kk * Q + j] = (double)(rz[j] - zu);
+    ynew[Tm.z + kk * Q + j] = weigh(w, (double)(rz[j] - zu), prev, 2, k, j);
   }
 }
 

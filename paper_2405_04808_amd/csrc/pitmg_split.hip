@@ -12,7 +12,8 @@
 //   5. finish:  z = r_z - W_z,  mu = W_v - r_mu - r_v,  v = -r_mu
 //
 // so every block reads only its own N_k and G_k^{-1}, and V, Z~ are read once
-// per sweep by the GEMMs (the matrix cores, through the library).
+// per sweep by the GEMMs (the matrix cores, through the library).  The
+// output is the unweighted sweep; launch_jacobi weights it afterwards.
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
 #include "pitmg_tiled.h"
@@ -27,28 +28,16 @@ constexpr int kSplitWaves = kSplitThreads / kWave;
 
 // coupling values of the previous iterate: yold + P ec (u and mu only)
 struct Coupling {
-  const double* yold;
-  const double* ec;
-  int variant, p, q, n;
-  __device__ double cu(int k1, int i) const {
-    const TypeMajor Tm(p, q, n), Tc(p, q, n / 2 > 0 ? n / 2 : 1);
-    double v = yold ? yold[Tm.u + (long long)(k1 - 1) * p + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.u, n / 2, p, k1, i, variant);
-    return v;
-  }
-  __device__ double cm(int k1, int i) const {
-    const TypeMajor Tm(p, q, n), Tc(p, q, n / 2 > 0 ? n / 2 : 1);
-    double v = yold ? yold[Tm.m + (long long)(k1 - 1) * p + i] : 0.0;
-    if (ec) v += interp_node(ec + Tc.m, n / 2, p, k1, i, variant);
-    return v;
-  }
+  PrevIterate prev;
+  __device__ double cu(int k1, int i) const { return prev.at(0, k1, i); }
+  __device__ double cm(int k1, int i) const { return prev.at(4, k1, i); }
 };
 
 // R_mu (p x (n+1), column k-1 for block k; column 0 is zero) and, for the
 // FP32 smoother, FP32 copies of R_mu and R_z (q x n).
 __global__ void k_split_prepare(Coupling C, const double* __restrict__ b, double* __restrict__ Rm,
                                 float* __restrict__ Rm32, float* __restrict__ Rz32) {
-  const int p = C.p, q = C.q, n = C.n;
+  const int p = C.prev.p, q = C.prev.q, n = C.prev.n;
   const TypeMajor Tm(p, q, n);
   const long long total = (long long)p * (n + 1);
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
@@ -233,7 +222,7 @@ hipError_t run_split(const LevelView& L, const SplitBuffers& S, const double* b,
   const bool f32 = sizeof(T) == 4;
   const TypeMajor Tm(P, q, n);
   rocblas_handle blas = (rocblas_handle)S.blas;
-  Coupling C{yold, ecoarse, variant, P, q, n};
+  Coupling C{PrevIterate{yold, ecoarse, P, q, n, variant, L.mu_scale}};
   hipError_t e = launch_k(k_split_prepare, dim3(grid_for_split((long long)P * (n + 1))),
                           dim3(256), 0, s, C, b, S.Rm, f32 ? S.Rm32 : (float*)nullptr,
                           f32 ? S.Rz32 : (float*)nullptr);

@@ -44,7 +44,9 @@ class pitmg_options(C.Structure):
                 ("smoother_fp32", C.c_int), ("coarse_mode", C.c_int), ("stall_ratio", C.c_double),
                 ("stall_steps", C.c_int), ("vcycle_graph", C.c_int),
                 ("apply_from_sweep", C.c_int),
-                ("pair_sweeps", C.c_int)]
+                ("pair_sweeps", C.c_int),
+                ("omega", C.c_double),
+                ("mu_scale", C.c_double)]
 
 
 class pitmg_stats(C.Structure):

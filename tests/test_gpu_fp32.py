@@ -68,7 +68,7 @@ def test_fp32_sweep_within_rounding_of_fp64_oracle(name):
         m = ol.A.shape[0]
         bb = rng.normal(size=m)
         y = rng.normal(size=m)
-        yt = ol.jacobi(bb[ol.perm], y[ol.perm])
+        yt = ol.jacobi(bb[ol.perm], y[ol.perm], s.options.omega)
         ref = np.empty_like(yt)
         ref[ol.perm] = yt
         got = host(s.jacobi_sweep(dev(bb), dev(y), level=lev))

@@ -17,8 +17,8 @@ torch = pytest.importorskip("torch")
 
 from workloads import make_problem, make_rhs
 from oracle import Hierarchy
-from oracle.multigrid import MGOptions
 import paper_2405_04808_amd as pm
+from parity_util import mg_opts, READINGS
 
 pytestmark = pytest.mark.gpu
 
@@ -45,14 +45,15 @@ def vcycle_pair(prob, r, shape=-1, **opt):
 @pytest.mark.parametrize("nx,n,n_levels", [(64, 40, 3), (128, 20, 3), (128, 1024, 8)])
 @pytest.mark.parametrize("nu", [(2, 2), (3, 3), (1, 2), (4, 4)])
 @pytest.mark.parametrize("variant", [0, 1])
-def test_pair_vcycle_bitwise(nx, n, n_levels, nu, variant):
+@pytest.mark.parametrize("reading", list(READINGS))
+def test_pair_vcycle_bitwise(nx, n, n_levels, nu, variant, reading):
     if n == 1024 and (nu != (2, 2) or variant != 0):
-        pytest.skip("the large grid runs once, with the benchmark's sweep counts")
+        pytest.skip("the large grid runs once per reading, with the benchmark's sweep counts")
     prob, rng = make_problem(kind="burgers", nx=nx, nu=0.01, n=n, n_levels=n_levels, seed=31)
     r = rng.normal(size=prob.size)
-    print(f"pair vcycle nx={nx} n={n} nu={nu} variant={variant}", flush=True)
+    print(f"pair vcycle nx={nx} n={n} nu={nu} variant={variant} {reading}", flush=True)
     a, b = vcycle_pair(prob, r, nu_pre=nu[0], nu_post=nu[1], coarse_fixed_its=2,
-                       transfer_variant=variant)
+                       transfer_variant=variant, **READINGS[reading])
     assert torch.equal(a, b)
 
 
@@ -92,11 +93,7 @@ def test_pair_vcycle_matches_oracle():
     prob, rng = make_problem(kind="burgers", nx=128, nu=0.01, n=24, n_levels=3, seed=34)
     s = pm.Solver(prob.levels, pm.default_options(coarse_fixed_its=2, pair_sweeps=1))
     tiled_everywhere(s, prob.n_levels)
-    o = s.options
-    H = Hierarchy(prob.levels, MGOptions(nu_pre=o.nu_pre, nu_post=o.nu_post,
-                                         coarse_tol=o.coarse_tol, coarse_maxit=o.coarse_maxit,
-                                         coarse_fixed_its=o.coarse_fixed_its,
-                                         transfer_variant=o.transfer_variant))
+    H = Hierarchy(prob.levels, mg_opts(s.options))
     r = rng.normal(size=prob.size)
     got = s.vcycle(dev(r)).cpu().numpy()
     ref = H.vcycle(r)
