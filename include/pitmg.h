@@ -218,6 +218,23 @@ int pitmg_jacobi_sweep(pitmg_handle* h, int level, const double* b,
  * n_levels-1; *its receives the step count (host int, may be NULL). */
 int pitmg_coarse_solve(pitmg_handle* h, const double* b, double* x, int* its);
 
+/* pitmg_coarse_solve without a device buffer of the handle: for callers that
+ * cannot allocate or own device memory around the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and result as pitmg_coarse_solve, the same kernels; the coarse
+ * Krylov bases, GMRES state and SGS work vectors live in a static device
+ * array of 32 MiB that each GPU the library runs on holds until the process
+ * ends.  The scratch of one coarse solve is about (2c + 9)(4p+q) n_c
+ * doubles (c = coarse_fixed_its if set, else coarse_maxit; n_c the coarsest
+ * step count); a solve that needs more than the array returns
+ * PITMG_ERR_UNSUPPORTED.  The call allocates nothing (no hipMalloc, hipFree
+ * or allocating library routine); it clears the parts of the array that must
+ * start at zero with a kernel.  All calls on one GPU share its array, so
+ * calls that overlap in time on one GPU (any handles, any streams) race.
+ * its may be NULL; otherwise the stream is synchronised and the step count
+ * returned. */
+int pitmg_coarse_solve_noalloc(pitmg_handle* h, const double* b, double* x, int* its);
+
 /* e = MG(r): one V-cycle from a zero initial guess on the finest level. */
 int pitmg_vcycle(pitmg_handle* h, const double* r, double* e);
 

@@ -10,10 +10,43 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace pitmg;
+
+// Scratch of pitmg_coarse_solve_noalloc: one array per GPU the library runs
+// on, held until the process ends.  In host code `scratch` only names the
+// array; its device address on each GPU comes from hipGetSymbolAddress with
+// that GPU current, and only that address is ever passed to a kernel.
+constexpr size_t kNoallocScratchDoubles = (size_t)4 << 20;      // 32 MiB
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch array, resolved once per GPU.
+hipError_t noalloc_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -408,10 +441,21 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
   return PITMG_OK;
 }
 
+// Device buffers of one coarse solve: the Krylov bases and GMRES state, the
+// block-parallel SGS work vectors (cY, cY2 and czero zero outside the slots
+// the sweeps write), and the slot that receives the step count.
+struct CoarseWork {
+  double* work;
+  double* cst;
+  int* ist;
+  double *cC, *cA, *cD, *cY, *cY2, *czero;
+  int* its;
+};
+
 // Coarsest level: GMRES + SGS.  Enqueue coarse_k steps with the
 // block-parallel SGS (no host wait), then a finish kernel that continues
 // block by block if the test was not met and forms x = Z y.
-int coarse_solve(pitmg_handle* h, const double* b, double* out) {
+int coarse_solve_with(pitmg_handle* h, const double* b, double* out, const CoarseWork& cw) {
   const pitmg_options& o = h->opt;
   const int l = h->L - 1;
   LevelView v = view(h, l);
@@ -421,15 +465,12 @@ int coarse_solve(pitmg_handle* h, const double* b, double* out) {
   const int nsteps = o.coarse_fixed_its > 0 ? o.coarse_fixed_its : o.coarse_maxit;
   int K = o.coarse_fixed_its > 0 ? o.coarse_fixed_its : std::min(h->coarse_k, nsteps);
   if (!h->coarse_fast) K = 0;
-  int* its = h->coarse_its + (h->coarse_calls % h->coarse_log_cap);
-  h->coarse_calls++;
-  h->last_its_slot = its;
-  double* Vb = h->coarse_work;
+  double* Vb = cw.work;
   double* Zb = Vb + (size_t)(cap + 1) * len;
   double* W = Zb + (size_t)cap * len;
   const int var = o.transfer_variant;
   int rc = timed(h, 4, [&] {
-    return launch_coarse_init(b, len, Vb, h->cst, h->ist, cap, h->stream);
+    return launch_coarse_init(b, len, Vb, cw.cst, cw.ist, cap, h->stream);
   });
   if (rc) return rc;
   for (int j = 0; j < K; ++j) {
@@ -437,51 +478,61 @@ int coarse_solve(pitmg_handle* h, const double* b, double* out) {
     double* zj = Zb + (size_t)j * len;
     // forward sweep: c = D^{-1} v, a_u = P c_u, a = D^{-1}(v - L a)
     if ((rc = timed(h, 4, [&] {
-           return launch_jacobi(v, vj, nullptr, nullptr, var, h->cC, h->stream);
+           return launch_jacobi(v, vj, nullptr, nullptr, var, cw.cC, h->stream);
          })))
       return rc;
     if ((rc = timed(h, 4, [&] {
-           return launch_gemv_tri(h->Pf, v.n, h->p, 0, h->cC + T.u, h->cY + T.u, h->stream);
+           return launch_gemv_tri(h->Pf, v.n, h->p, 0, cw.cC + T.u, cw.cY + T.u, h->stream);
          })))
       return rc;
     if ((rc = timed(h, 4, [&] {
-           return launch_jacobi(v, vj, h->cY, nullptr, var, h->cA, h->stream);
+           return launch_jacobi(v, vj, cw.cY, nullptr, var, cw.cA, h->stream);
          })))
       return rc;
     // backward sweep: y_mu = Q a_mu, z = a - D^{-1} L^T y
     if ((rc = timed(h, 4, [&] {
-           return launch_gemv_tri(h->Qb, v.n, h->p, 1, h->cA + T.m, h->cY2 + T.m, h->stream);
+           return launch_gemv_tri(h->Qb, v.n, h->p, 1, cw.cA + T.m, cw.cY2 + T.m, h->stream);
          })))
       return rc;
     if ((rc = timed(h, 4, [&] {
-           return launch_jacobi(v, h->czero, h->cY2, nullptr, var, h->cD, h->stream);
+           return launch_jacobi(v, cw.czero, cw.cY2, nullptr, var, cw.cD, h->stream);
          })))
       return rc;
     if (o.apply_from_sweep) {
       // z = a + d and w = A~ z from the two sweeps' identities (no pass over
       // the blocks), inside the Arnoldi step's own launch
       if ((rc = timed(h, 4, [&] {
-             return launch_coarse_arnoldi_sgs(j, W, Vb, zj, h->cA, h->cD, h->p, h->q, v.n,
-                                              h->cst, h->ist, cap, o.coarse_tol,
+             return launch_coarse_arnoldi_sgs(j, W, Vb, zj, cw.cA, cw.cD, h->p, h->q, v.n,
+                                              cw.cst, cw.ist, cap, o.coarse_tol,
                                               o.coarse_fixed_its, nsteps, h->stream);
            })))
         return rc;
       continue;
     }
-    if ((rc = timed(h, 4, [&] { return launch_add(zj, h->cA, h->cD, len, h->stream); })))
+    if ((rc = timed(h, 4, [&] { return launch_add(zj, cw.cA, cw.cD, len, h->stream); })))
       return rc;
     if ((rc = timed(h, 4, [&] { return launch_apply(v, zj, nullptr, 1.0, 0.0, W, h->stream); })))
       return rc;
     if ((rc = timed(h, 4, [&] {
-           return launch_coarse_arnoldi(j, W, Vb, len, h->cst, h->ist, cap, o.coarse_tol,
+           return launch_coarse_arnoldi(j, W, Vb, len, cw.cst, cw.ist, cap, o.coarse_tol,
                                         o.coarse_fixed_its, nsteps, h->stream);
          })))
       return rc;
   }
   return timed(h, 4, [&] {
-    return launch_coarse_finish(v, out, o.coarse_tol, o.coarse_fixed_its, nsteps,
-                                h->coarse_work, h->cst, h->ist, cap, its, h->stream);
+    return launch_coarse_finish(v, out, o.coarse_tol, o.coarse_fixed_its, nsteps, cw.work,
+                                cw.cst, cw.ist, cap, cw.its, h->stream);
   });
+}
+
+// The coarse solve on the handle's own buffers, logging its step count.
+int coarse_solve(pitmg_handle* h, const double* b, double* out) {
+  int* its = h->coarse_its + (h->coarse_calls % h->coarse_log_cap);
+  h->coarse_calls++;
+  h->last_its_slot = its;
+  const CoarseWork cw{h->coarse_work, h->cst, h->ist, h->cC, h->cA, h->cD,
+                      h->cY, h->cY2, h->czero, its};
+  return coarse_solve_with(h, b, out, cw);
 }
 
 // Coarsest level inside a V-cycle: the attached network while coarse_mode
@@ -1386,6 +1437,12 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
                      h->stream) != hipSuccess ||
       hipMemsetAsync(h->hand_timeout, 0, sizeof(int), h->stream) != hipSuccess)
     return fail(set_err(h, PITMG_ERR_HIP, "hipMemsetAsync failed"));
+  {
+    // resolve this GPU's static scratch (pitmg_coarse_solve_noalloc) while
+    // setting up; a failure is reported by that entry point, which retries
+    double* scr = nullptr;
+    (void)noalloc_scratch(&scr);
+  }
   rc = load_and_factor(h, pb);
   *hp = h;
   return rc;
@@ -1446,6 +1503,43 @@ int pitmg_coarse_solve(pitmg_handle* h, const double* b, double* x, int* its) {
                            sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   if (its) *its = hv;
+  return PITMG_OK;
+}
+
+int pitmg_coarse_solve_noalloc(pitmg_handle* h, const double* b, double* x, int* its) {
+  if (!h || !b || !x) return PITMG_ERR_INVALID;
+  const int l = h->L - 1;
+  const long long len = h->lv[l].len;
+  const int cap = h->coarse_cap;
+  // layout: Krylov bases | GMRES state | 6 SGS work vectors | 3 ints
+  const size_t nwork = coarse_work_doubles(h->p, h->q, h->lv[l].n, cap);
+  const size_t nstate = coarse_state_doubles(cap);
+  const size_t nvec = h->coarse_fast ? 6 * (size_t)len : 0;
+  const size_t need = nwork + nstate + nvec + 2;
+  if (need > kNoallocScratchDoubles)
+    return set_err(h, PITMG_ERR_UNSUPPORTED,
+                   "coarse solve needs " + std::to_string(need * 8) +
+                       " bytes of scratch; the static scratch holds " +
+                       std::to_string(kNoallocScratchDoubles * 8));
+  double* base = nullptr;
+  HIPCHK(h, noalloc_scratch(&base));
+  double* vecs = base + nwork + nstate;
+  int* ints = reinterpret_cast<int*>(vecs + nvec);          // {steps done, stop}, its
+  CoarseWork cw{base, base + nwork, ints, nullptr, nullptr, nullptr, nullptr, nullptr,
+                nullptr, ints + 2};
+  if (h->coarse_fast) {
+    double** slot[6] = {&cw.cC, &cw.cA, &cw.cD, &cw.cY, &cw.cY2, &cw.czero};
+    for (int i = 0; i < 6; ++i) *slot[i] = vecs + (size_t)i * len;
+    // the array keeps the last call's contents: the vectors whose unwritten
+    // slots must read as zero are cleared
+    HIPCHK(h, launch_fill(cw.cY, 0.0, 3 * len, h->stream));
+  }
+  int rc = coarse_solve_with(h, b, x, cw);
+  if (rc) return rc;
+  if (its) {
+    HIPCHK(h, hipMemcpyAsync(its, cw.its, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
   return PITMG_OK;
 }
 

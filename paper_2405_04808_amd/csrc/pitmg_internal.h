@@ -248,6 +248,8 @@ hipError_t launch_multi_axpy(double* w, const double* basis, int nvec,
                              double* norm_partial, hipStream_t s);
 hipError_t launch_scale(double* dst, const double* src, double alpha,
                         long long len, hipStream_t s);
+// dst[0 .. len) = value (a kernel, so that it may be captured in a graph)
+hipError_t launch_fill(double* dst, double value, long long len, hipStream_t s);
 hipError_t launch_axpby(double* y, const double* x, double a, double b,
                         long long len, hipStream_t s);   // y = a*x + b*y
 

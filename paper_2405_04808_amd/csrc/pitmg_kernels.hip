@@ -955,6 +955,18 @@ hipError_t launch_scale(double* dst, const double* src, double alpha, long long 
   return hipGetLastError();
 }
 
+__global__ void k_fill(double* __restrict__ dst, double value, long long len) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < len;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = value;
+}
+
+hipError_t launch_fill(double* dst, double value, long long len, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(len, 256)), dim3(256), 0, s, dst, value, len);
+  return hipGetLastError();
+}
+
 hipError_t launch_axpby(double* y, const double* x, double a, double b, long long len,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_axpby, dim3(grid_for(len, 256)), dim3(256), 0, s, y, x, a, b, len);

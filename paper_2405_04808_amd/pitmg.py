@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "pitmg_apply": (i, [vp, i, vp, vp]),
         "pitmg_jacobi_sweep": (i, [vp, i, vp, vp, vp]),
         "pitmg_coarse_solve": (i, [vp, vp, vp, C.POINTER(i)]),
+        "pitmg_coarse_solve_noalloc": (i, [vp, vp, vp, C.POINTER(i)]),
         "pitmg_vcycle": (i, [vp, vp, vp]),
         "pitmg_fgmres_solve": (i, [vp, vp, vp, d, i, C.POINTER(pitmg_stats)]),
         "pitmg_fgmres_solve_batch": (i, [C.POINTER(vp), i, C.POINTER(vp), C.POINTER(vp), d, i,
