@@ -404,8 +404,32 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
   }
   const int big = INT_MAX;
   HIPCHK(h, hipMemcpyAsync(h->fail, &big, sizeof(int), hipMemcpyHostToDevice, h->stream));
+  // the FP64 levels in one launch on the matrix cores where the block size
+  // allows, the others level by level
+  const bool batched = factor_mfma_supported(h->p);
+  if (batched) {
+    FactorBatch F;
+    F.p = h->p;
+    F.q = h->q;
+    F.sN = pb->N_stride;
+    F.sZ = pb->Z_stride;
+    for (int l = 0; l < h->L; ++l) {
+      const LevelBuf& b = h->lv[l];
+      if (b.fp32) continue;
+      F.N[F.nlev] = b.N;
+      F.Z[F.nlev] = b.Z;
+      F.Gi[F.nlev] = b.Gi;
+      F.start[F.nlev + 1] = F.start[F.nlev] + b.n;
+      F.nlev++;
+    }
+    // FP32 levels are the finest ones, so the FP64 levels are level0 .. L-1
+    F.level0 = h->L - F.nlev;
+    int rc = timed(h, 0, [&] { return launch_factor_mfma(F, h->fail, h->stream); });
+    if (rc) return rc;
+  }
   for (int l = 0; l < h->L; ++l) {
     LevelBuf& b = h->lv[l];
+    if (!b.fp32 && batched) continue;
     if (b.fp32) {
       const long long cN = (b.sN ? b.n : 1) * pp, cV = (b.sV ? b.n : 1) * pp,
                       cZ = (b.sZ ? b.n : 1) * pq;

@@ -109,6 +109,21 @@ hipError_t launch_k(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
 // with (level << 20 | k) on a non-positive pivot.
 hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail,
                          hipStream_t s);
+// Every FP64 level of a hierarchy in one launch on the matrix cores
+// (pitmg_factor.hip) for p in {64, 128}: block b of the launch is block
+// b - start[l] of level l for start[l] <= b < start[l+1].
+struct FactorBatch {
+  int nlev = 0;
+  int level0 = 0;              // hierarchy level of entry 0 (failure codes)
+  int p = 0, q = 0;
+  long long sN = 0, sZ = 0;
+  int start[21] = {0};
+  const double* N[20] = {};
+  const double* Z[20] = {};
+  double* Gi[20] = {};
+};
+bool factor_mfma_supported(int p);
+hipError_t launch_factor_mfma(const FactorBatch& F, int* fail, hipStream_t s);
 // Same in FP32 from L.N32 / L.Z32 into Gi32.
 hipError_t launch_factor32(const LevelView& L, float* Gi32, int level, int* fail,
                            hipStream_t s);
@@ -176,6 +191,12 @@ hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const doubl
 // out = beta*b + alpha*(A~ x) on one level (b may be NULL when beta == 0).
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b,
                         double alpha, double beta, double* out, hipStream_t s);
+// The same for p = q in {64, 128} with V and Z~ shared by every step
+// (register tiles of N_k, pitmg_jacobi_tiled.hip); apply_shared_supported
+// says whether it applies.
+bool apply_shared_supported(const LevelView& L);
+hipError_t launch_apply_shared(const LevelView& L, const double* x, const double* b,
+                               double alpha, double beta, double* out, hipStream_t s);
 
 // Coarse right-hand side from the last pre-smoothing sweep:
 // bc = R (beta b + (L+L^T)(a ya - y))  (ya NULL = 0; b unread if beta == 0),

@@ -1042,4 +1042,179 @@ hipError_t launch_jacobi_shared(const LevelView& L, const double* b, const doubl
                 : launch_shared_t<double>(L, b, yold, ecoarse, variant, ynew, per, fr, s);
 }
 
+
+// ---------------------------------------------------------------------------
+// out = beta b + alpha A~ x for p = q in {64, 128} with V and Z~ shared by
+// every step: a work-group takes up to kMaxSteps consecutive steps, N_k in
+// the register tile of the sweep (pitmg_tiled.h) serving both its row
+// product N u_k and its column product N^T lambda_k, so each N_k is read
+// from HBM once; the products with the shared V and Z~ are formed for all
+// steps of the group in one pass over each (rows before, columns after).
+// Rows of time-major block k: lambda_k = N u_k + V v_{k-1} + Z z_k,
+// u_k + N^T lambda_k + mu_k, z_k + Z^T lambda_k, v_{k-1} + V^T lambda_k -
+// mu_{k-1}, u_{k-1} - v_{k-1}; block n+1 (with step n): v_n - mu_n, u_n - v_n.
+// ---------------------------------------------------------------------------
+
+template <int RT, int CT>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_apply_shared(
+    LevelView L, const double* __restrict__ x, const double* __restrict__ b, double alpha,
+    double beta, double* __restrict__ out, int per_wg) {
+  using TS = TiledSolve<RT, CT, double>;
+  constexpr int P = TS::P;
+  constexpr int G = kTiledThreads / P;
+  __shared__ double su[kMaxSteps][P], sl[kMaxSteps][P], svz[kMaxSteps][P];
+  __shared__ double sxv[kMaxSteps][P], sxz[kMaxSteps][P];
+  __shared__ double red[kTiledWaves * P];
+  __shared__ double pz[G][kMaxSteps][P], pv[G][kMaxSteps][P];
+  const int tid = threadIdx.x, a = tid / 16, bq = tid % 16;
+  const int r0 = RT * a;
+  const int n = L.n;
+  const TypeMajor Tm(P, P, n);
+  const int k0 = blockIdx.x * per_wg + 1;
+  const int nb = min(per_wg, n - k0 + 1);
+  const double* __restrict__ Vs = L.V;
+  const double* __restrict__ Zs = L.Z;
+  auto put = [&](long long idx, double val) {
+    out[idx] = (beta != 0.0 ? beta * b[idx] : 0.0) + alpha * val;
+  };
+
+  typename TS::Regs R;
+  TS::load_n(L, k0 - 1, R);
+  for (int s = 0; s < nb; ++s) {
+    const long long kk = k0 + s - 1;
+    for (int i = tid; i < P; i += kTiledThreads) {
+      su[s][i] = x[Tm.u + kk * P + i];
+      sl[s][i] = x[Tm.l + kk * P + i];
+      sxz[s][i] = x[Tm.z + kk * P + i];
+      sxv[s][i] = kk >= 1 ? x[Tm.v + (kk - 1) * P + i] : 0.0;
+    }
+  }
+  __syncthreads();
+  // svz[s] = V v_{k-1} + Z z_k for every step: one pass over V and Z~
+  {
+    double acc[kMaxSteps][RT];
+#pragma unroll
+    for (int s = 0; s < kMaxSteps; ++s)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[s][r] = 0;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      double zr[CT], vr[CT];
+      tile_load_row<CT, double>(Zs + (long long)(r0 + r) * P, zr);
+      tile_load_row<CT, double>(Vs + (long long)(r0 + r) * P, vr);
+#pragma unroll
+      for (int s = 0; s < kMaxSteps; ++s) {
+        if (s < nb) {
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+            acc[s][r] += zr[c] * sxz[s][tile_col<double>(c)] + vr[c] * sxv[s][tile_col<double>(c)];
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxSteps; ++s) {
+      if (s < nb) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const double v = tile_sum16(acc[s][r]);
+          if (bq == 0) svz[s][r0 + r] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < nb; ++s) {
+    const long long kk = k0 + s - 1;
+    // lambda row: N u_k + (V v_{k-1} + Z z_k)
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      double sum = 0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) sum += R.nt[r][c] * su[s][tile_col<double>(c)];
+      sum = tile_sum16(sum);
+      if (bq == 0) put(Tm.l + kk * P + r0 + r, sum + svz[s][r0 + r]);
+    }
+    // u row: u_k + N^T lambda_k + mu_k
+    double cacc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      double sum = 0;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) sum += R.nt[r][c] * sl[s][r0 + r];
+      cacc[c] = sum;
+    }
+    TS::col_partial(cacc, red);
+    __syncthreads();
+    if (s + 1 < nb) TS::load_n(L, kk + 1, R);           // N of the next step
+    for (int i = tid; i < P; i += kTiledThreads)
+      put(Tm.u + kk * P + i, su[s][i] + TS::col_total(red, i) + x[Tm.m + kk * P + i]);
+    __syncthreads();
+  }
+  // Z^T lambda and V^T lambda for every step: one pass over Z~ and V
+  {
+    const int j = tid % P, g = tid / P;
+    double za[kMaxSteps], va[kMaxSteps];
+#pragma unroll
+    for (int s = 0; s < kMaxSteps; ++s) {
+      za[s] = 0;
+      va[s] = 0;
+    }
+    for (int i = g; i < P; i += G) {
+      const double zi = Zs[(long long)i * P + j], vi = Vs[(long long)i * P + j];
+#pragma unroll
+      for (int s = 0; s < kMaxSteps; ++s) {
+        if (s < nb) {
+          za[s] += zi * sl[s][i];
+          va[s] += vi * sl[s][i];
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxSteps; ++s) {
+      pz[g][s][j] = za[s];
+      pv[g][s][j] = va[s];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * P; idx += kTiledThreads) {
+    const int s = idx / P, i = idx % P;
+    const long long kk = k0 + s - 1;
+    double zt = 0, vt = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      zt += pz[g][s][i];
+      vt += pv[g][s][i];
+    }
+    put(Tm.z + kk * P + i, sxz[s][i] + zt);
+    if (kk >= 1) {
+      put(Tm.v + (kk - 1) * P + i, sxv[s][i] + vt - x[Tm.m + (kk - 1) * P + i]);
+      put(Tm.m + (kk - 1) * P + i, x[Tm.u + (kk - 1) * P + i] - sxv[s][i]);
+    }
+    if (kk == n - 1) {                                    // block n+1
+      const double vn = x[Tm.v + kk * P + i], mn = x[Tm.m + kk * P + i];
+      put(Tm.v + kk * P + i, vn - mn);
+      put(Tm.m + kk * P + i, su[s][i] - vn);
+    }
+  }
+}
+
+bool apply_shared_supported(const LevelView& L) {
+  return !L.fp32 && jacobi_shared_supported(L) && (reinterpret_cast<uintptr_t>(L.N) & 15u) == 0 &&
+         (reinterpret_cast<uintptr_t>(L.V) & 15u) == 0 &&
+         (reinterpret_cast<uintptr_t>(L.Z) & 15u) == 0;
+}
+
+hipError_t launch_apply_shared(const LevelView& L, const double* x, const double* b, double alpha,
+                               double beta, double* out, hipStream_t s) {
+  const int per = L.n >= 1024 ? kMaxSteps : (L.n + 255) / 256 > 0 ? (L.n + 255) / 256 : 1;
+  const int nwg = (L.n + per - 1) / per;
+  if (L.p == 128)
+    return launch_k(k_apply_shared<4, 8>, dim3(nwg), dim3(kTiledThreads), 0, s, L, x, b, alpha,
+                    beta, out, per);
+  if (L.p == 64)
+    return launch_k(k_apply_shared<2, 4>, dim3(nwg), dim3(kTiledThreads), 0, s, L, x, b, alpha,
+                    beta, out, per);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace pitmg

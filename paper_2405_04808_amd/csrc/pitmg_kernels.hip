@@ -386,6 +386,7 @@ __global__ __launch_bounds__(NT) void k_apply(LevelView L, const double* __restr
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b, double alpha,
                         double beta, double* out, hipStream_t s) {
   if (small_supported(L.p, L.q)) return launch_apply_small(L, x, b, alpha, beta, out, s);
+  if (apply_shared_supported(L)) return launch_apply_shared(L, x, b, alpha, beta, out, s);
   const size_t lds = apply_lds_doubles(L.p, L.q, kApplyThreads) * sizeof(double);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_apply<kApplyThreads>,
