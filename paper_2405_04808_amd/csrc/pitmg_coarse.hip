@@ -23,6 +23,7 @@
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
 #include "pitmg_blocks.h"
+#include "pitmg_mfma.h"
 #include "pitmg_tiled.h"
 
 namespace pitmg {
@@ -504,11 +505,84 @@ hipError_t launch_coarse_finish(const LevelView& L, double* x, double tol, int f
   return hipGetLastError();
 }
 
+// The same products on the matrix cores for p in {64, 128} (pitmg_mfma.h):
+// W_s = G_s^{-1} N_s and X_s = G_s^{-1} V_s (which = 0, 1), Phi_s = W_s^T X_s,
+// and the propagator columns, P columns in work-groups 0..nc-1 and Q columns
+// in nc..2nc-1.
+template <int NT>
+__global__ __launch_bounds__(kGemmThreads) void k_gi_times_mfma(LevelView L, int which,
+                                                                double* __restrict__ out) {
+  extern __shared__ double lds[];
+  constexpr int P = 16 * NT;
+  const long long s = blockIdx.x;
+  const double* Gk = L.Gi + s * P * P;
+  const double* Mk = which == 0 ? L.N + s * L.sN : L.V + s * L.sV;
+  wg_gemm<NT, false, false>(Gk, P, Mk, P, 1.0, out + s * P * P, P, lds);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kGemmThreads) void k_phi_mfma(const double* __restrict__ W,
+                                                           const double* __restrict__ X,
+                                                           double* __restrict__ Phi) {
+  extern __shared__ double lds[];
+  constexpr int P = 16 * NT;
+  const long long s = blockIdx.x;
+  wg_gemm<NT, true, false>(W + s * P * P, P, X + s * P * P, P, 1.0, Phi + s * P * P, P, lds);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kGemmThreads) void k_propagators_mfma(int nc,
+                                                                   const double* __restrict__ Phi,
+                                                                   double* P_, double* Q_) {
+  extern __shared__ double lds[];
+  constexpr int P = 16 * NT;
+  const bool lower = (int)blockIdx.x < nc;
+  const int i = lower ? blockIdx.x : blockIdx.x - nc;
+  const long long ld = (long long)nc * P;
+  double* M = lower ? P_ : Q_;
+  auto blk = [&](int rr, int cc) { return M + (long long)rr * P * ld + (long long)cc * P; };
+  for (int idx = threadIdx.x; idx < P * P; idx += kGemmThreads) {
+    const int a = idx / P, b = idx % P;
+    blk(i, i)[(long long)a * ld + b] = a == b ? 1.0 : 0.0;
+  }
+  if (lower) {
+    for (int s = i + 1; s < nc; ++s)        // P[s][i] = -Phi_s P[s-1][i]
+      wg_gemm<NT, false, false>(Phi + (long long)s * P * P, P, blk(s - 1, i), ld, -1.0,
+                                blk(s, i), ld, lds);
+  } else {
+    for (int m = i - 1; m >= 0; --m)        // Q[m][i] = -Phi_{m+1}^T Q[m+1][i]
+      wg_gemm<NT, true, false>(Phi + (long long)(m + 1) * P * P, P, blk(m + 1, i), ld, -1.0,
+                               blk(m, i), ld, lds);
+  }
+}
+
+template <int NT>
+static hipError_t launch_propagators_mfma(const LevelView& L, double* W, double* X, double* Phi,
+                                          double* P, double* Q, hipStream_t s) {
+  const int nc = L.n;
+  const size_t lds = wg_gemm_lds_doubles(16 * NT) * sizeof(double);
+  const void* fns[4] = {(const void*)k_gi_times_mfma<NT>, (const void*)k_phi_mfma<NT>,
+                        (const void*)k_propagators_mfma<NT>, nullptr};
+  for (int f = 0; f < 3; ++f) {
+    hipError_t e = hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_gi_times_mfma<NT>, dim3(nc), dim3(kGemmThreads), lds, s, L, 0, W);
+  hipLaunchKernelGGL(k_gi_times_mfma<NT>, dim3(nc), dim3(kGemmThreads), lds, s, L, 1, X);
+  hipLaunchKernelGGL(k_phi_mfma<NT>, dim3(nc), dim3(kGemmThreads), lds, s, W, X, Phi);
+  hipLaunchKernelGGL(k_propagators_mfma<NT>, dim3(2 * nc), dim3(kGemmThreads), lds, s, nc, Phi,
+                     P, Q);
+  return hipGetLastError();
+}
+
 hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, double* P,
                               double* Q, hipStream_t s) {
   const int p = L.p, nc = L.n;
   double* W = scratch;
   double* X = scratch + (size_t)nc * p * p;
+  if (p == 128) return launch_propagators_mfma<8>(L, W, X, Phi, P, Q, s);
+  if (p == 64) return launch_propagators_mfma<4>(L, W, X, Phi, P, Q, s);
   hipLaunchKernelGGL(k_gi_times, dim3(nc), dim3(512), 0, s, L, 0, W);
   hipLaunchKernelGGL(k_gi_times, dim3(nc), dim3(512), 0, s, L, 1, X);
   hipLaunchKernelGGL(k_phi, dim3(nc), dim3(512), 0, s, p, W, X, Phi);

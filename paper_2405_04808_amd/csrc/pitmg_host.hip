@@ -155,7 +155,8 @@ struct pitmg_handle {
   int* hand_timeout = nullptr;
   unsigned long long hand_tickets = 0;   // tickets issued so far (host mirror)
   unsigned long long hand_epoch = 0;     // last epoch issued
-  unsigned long long hand_spin = 200000000ull;   // wait bound: 2 s at 100 MHz
+  double wall_hz = 1e8;                  // the device's constant wall clock
+  unsigned long long hand_spin = 200000000ull;   // wait bound (ticks): 2 s
 };
 
 namespace {
@@ -1260,6 +1261,8 @@ int pitmg_autotune(pitmg_handle* h, int* cfg) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   drop_graph(h);
+  // a timed two-sweep launch whose hand-off wait ran out fails the tuning
+  if (int rh = handoff_check(h)) return rh;
   return rc;
 }
 
@@ -1267,7 +1270,7 @@ int pitmg_set_handoff_wait(pitmg_handle* h, double seconds) {
   if (!h) return PITMG_ERR_INVALID;
   if (!(seconds >= 0.0) || !(seconds <= 60.0))
     return set_err(h, PITMG_ERR_INVALID, "the hand-off wait bound must be in [0, 60] s");
-  h->hand_spin = (unsigned long long)(seconds * 1e8);   // 100 MHz clock
+  h->hand_spin = (unsigned long long)(seconds * h->wall_hz);
   return PITMG_OK;
 }
 
@@ -1466,6 +1469,13 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
     // setting up; a failure is reported by that entry point, which retries
     double* scr = nullptr;
     (void)noalloc_scratch(&scr);
+    // the hand-off waits count ticks of the device's wall clock
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+        khz > 0)
+      h->wall_hz = 1e3 * khz;
+    h->hand_spin = (unsigned long long)(2.0 * h->wall_hz);
   }
   rc = load_and_factor(h, pb);
   *hp = h;
@@ -1571,7 +1581,16 @@ int pitmg_vcycle(pitmg_handle* h, const double* r, double* e) {
   if (!h || !r || !e) return PITMG_ERR_INVALID;
   if (r == e) return set_err(h, PITMG_ERR_INVALID, "r and e must differ");
   h->fell_back = false;
-  return vcycle_top(h, r, e);
+  const unsigned long long tickets = h->hand_tickets;
+  const int rc = vcycle_top(h, r, e);
+  // a two-sweep launch of this cycle whose hand-off wait ran out is this
+  // call's error (the check synchronises; cycles without such launches,
+  // e.g. under stream capture, stay asynchronous)
+  if (h->hand_tickets != tickets) {
+    const int rh = handoff_check(h);
+    if (rh) return rh;
+  }
+  return rc;
 }
 
 int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol, int use_x0,
@@ -1608,8 +1627,12 @@ int pitmg_fgmres_solve_batch(pitmg_handle* const* hs, int count, const double* c
     // enqueue every live solve up to its next host wait ...
     for (int i = 0; i < count; ++i) {
       if (!live[i]) continue;
-      const int rc = runs[i].advance();
+      int rc = runs[i].advance();
       waiting[i] = rc == FgmresRun::kWait;
+      if (rc < 0 && rc != PITMG_ERR_HIP) {
+        // an error that follows a failed hand-off is reported as that failure
+        if (int rh = handoff_check(hs[i])) rc = rh;
+      }
       if (rc != FgmresRun::kWait) {
         rcs[i] = rc < 0 ? rc : runs[i].status;
         live[i] = 0;

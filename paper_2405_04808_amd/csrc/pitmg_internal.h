@@ -155,7 +155,7 @@ struct PairSync {
   unsigned long long* flag;    // [n+1]: epoch of each block's published first sweep
   unsigned long long epoch;    // this launch's epoch, above every earlier one
   int* timeout;                // bit 0: a wait ran out; bit 1: a ticket out of range
-  unsigned long long spin;     // bound of each wait, ticks of the 100 MHz clock
+  unsigned long long spin;     // bound of each wait, ticks of the device wall clock
 };
 // Two consecutive sweeps in one launch (y1 = first, y2 = second sweep; the
 // coarse correction, if any, folds into the first, the restriction, if any,

@@ -171,13 +171,21 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
 // again.  Same arithmetic in the same order as two k_jacobi_tiled launches.
 //
 // The two coupling values a neighbour reads (u_k, mu_{k-1}) are stored and
-// loaded as device-scope relaxed atomics, which the L2 of each XCD does not
-// hold back: a store is acknowledged once it is visible device-wide, and a
-// load reads the device-wide value.  A work-group waits for the
-// acknowledgement of its coupling stores (vmcnt(0)) before its flag goes out,
-// and reads the neighbours' only after their flags, so no cache-wide
-// write-back or invalidation is needed.  The other first-sweep values are
-// read by no other work-group of the launch and are plain stores.
+// loaded as agent-scope atomics, which gfx950 performs at the device's
+// coherence point with the sc1 bit (neither the store nor the load is held
+// in the non-coherent L2 of an XCD).  The hand-off orders them at the ISA
+// level: after its coupling stores every wave of the publishing work-group
+// passes a compiler fence and then waits for their acknowledgement
+// (s_waitcnt vmcnt(0): the stores are performed device-wide); one thread
+// stores the flag only after the work-group barrier that follows; the
+// waiting thread's flag loads come before the barrier and the compiler
+// fence that precede the coupling loads, which the hardware issues in
+// program order.  The other first-sweep values are read by no other
+// work-group of the launch and are plain stores.  (The same order under the
+// HIP memory model's own rules, an agent-scope release fence in every
+// thread before the barrier and acquire flag loads, also writes back the
+// XCD's L2 at every hand-off: measured at 133 us against 86 us per
+// two-sweep launch of the shared-block kernel on Burgers nx=128, n=1024.)
 //
 // y2 may be the buffer of yold: a work-group writes its second-sweep block
 // only after both readers of that block's first-sweep couplings (the
@@ -189,7 +197,7 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
 // waits only for first sweeps, which never wait, of blocks whose tickets are
 // drawn (t-1) or will be drawn once a lower ticket's work-group has finished
 // (t+1); the grid therefore drains whatever number of work-groups is
-// resident.  Each wait also ends after ps.spin ticks of the 100 MHz clock
+// resident.  Each wait also ends after ps.spin ticks of the wall clock
 // (2 s unless a test of the error path shortens it) and raises *timeout, so
 // every wave exits.
 // ---------------------------------------------------------------------------
@@ -212,6 +220,24 @@ __device__ bool pair_wait(const unsigned long long* f, unsigned long long epoch,
     __builtin_amdgcn_s_sleep(2);
   }
   return true;
+}
+
+// Publish this work-group's first sweep (flag = epoch) and wait for the
+// flags lo and hi of its neighbours (NULL: none); see above for the order.
+__device__ void pair_handoff(unsigned long long* self, const unsigned long long* lo,
+                             const unsigned long long* hi, const PairSync& ps) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // no store sinks below
+  __builtin_amdgcn_s_waitcnt(0x0F70);                      // vmcnt(0): stores performed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(self, ps.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool ok = true;
+    if (lo) ok = pair_wait(lo, ps.epoch, ps.spin) && ok;
+    if (hi) ok = pair_wait(hi, ps.epoch, ps.spin) && ok;
+    if (!ok) atomicOr(ps.timeout, 1);
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // no load rises above
 }
 }  // namespace
 
@@ -255,16 +281,8 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   // publish this block's first sweep, then wait for the neighbours' (lo, hi:
   // block indices kb-1 and kb+1, or -1)
   auto hand_off = [&](int lo, int hi) {
-    __builtin_amdgcn_s_waitcnt(0x0F70);        // vmcnt(0): coupling stores acknowledged
-    __syncthreads();
-    if (tid == 0) {
-      __hip_atomic_store(ps.flag + kb, ps.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      bool ok = true;
-      if (lo >= 0) ok = pair_wait(ps.flag + lo, ps.epoch, ps.spin) && ok;
-      if (hi >= 0) ok = pair_wait(ps.flag + hi, ps.epoch, ps.spin) && ok;
-      if (!ok) atomicOr(ps.timeout, 1);
-    }
-    __syncthreads();
+    pair_handoff(ps.flag + kb, lo >= 0 ? ps.flag + lo : nullptr,
+                 hi >= 0 ? ps.flag + hi : nullptr, ps);
   };
 
   const int k = kb + 1;
@@ -964,16 +982,8 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared_nl2(
   const int nb = min(per_wg, L.n - k0 + 1);
   shared_nl_sweep<RT, CT>(L, b, yold, ec, variant, y1, k0, nb,
                           FusedRestrict{nullptr, variant, 0.0, 1.0, L.mu_scale}, true, false);
-  __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): boundary stores acknowledged
-  __syncthreads();
-  if (tid == 0) {
-    __hip_atomic_store(ps.flag + g, ps.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool ok = true;
-    if (g > 0) ok = pair_wait(ps.flag + g - 1, ps.epoch, ps.spin) && ok;
-    if (g + 1 < ng) ok = pair_wait(ps.flag + g + 1, ps.epoch, ps.spin) && ok;
-    if (!ok) atomicOr(ps.timeout, 1);
-  }
-  __syncthreads();
+  pair_handoff(ps.flag + g, g > 0 ? ps.flag + g - 1 : nullptr,
+               g + 1 < ng ? ps.flag + g + 1 : nullptr, ps);
   shared_nl_sweep<RT, CT>(L, b, y1, nullptr, variant, y2, k0, nb, fr, false, true);
 }
 
