@@ -158,3 +158,38 @@ def block_coupling(y: np.ndarray, p: int, q: int, n: int, k: int) -> np.ndarray:
         return np.concatenate([mu_k, np.zeros(q + p)])
     u_km1 = y[o["u"] + (k - 2) * p: o["u"] + (k - 1) * p]
     return np.concatenate([np.zeros(p), mu_k, np.zeros(q + p), u_km1])
+
+
+def apply_blocks(N, V, Z, x: np.ndarray) -> np.ndarray:
+    """A~ x in type-major order from the operator rows of the lifted system
+    (Fig. 4), step by step with dense products, for sizes whose assembled
+    matrix is too large to form.  N: (n,p,p), V: (n,p,p), Z: (n,p,q), each
+    possibly of leading size 1 (shared by every step):
+      u_k:      u_k + N_k^T lambda_k + mu_k
+      v_k:      v_k + V_{k+1}^T lambda_{k+1} - mu_k      (V_{n+1} := 0)
+      z_k:      z_k + Z_k^T lambda_k
+      lambda_k: N_k u_k + V_k v_{k-1} + Z_k z_k          (v_0 := 0)
+      mu_k:     u_k - v_k
+    """
+    N = np.asarray(N)
+    n, p, _ = N.shape
+    q = Z.shape[2]
+    o = type_offsets(p, q, n)
+    u = x[o["u"]:o["v"]].reshape(n, p)
+    v = x[o["v"]:o["z"]].reshape(n, p)
+    z = x[o["z"]:o["lam"]].reshape(n, q)
+    lam = x[o["lam"]:o["mu"]].reshape(n, p)
+    mu = x[o["mu"]:o["end"]].reshape(n, p)
+    vprev = np.vstack([np.zeros((1, p)), v[:-1]])
+    Vb = np.broadcast_to(V, (n, p, p))
+    Zb = np.broadcast_to(Z, (n, p, q))
+    out = np.empty_like(x)
+    out[o["u"]:o["v"]] = (u + np.einsum("kij,ki->kj", N, lam) + mu).ravel()
+    vt = np.einsum("kij,ki->kj", Vb[1:], lam[1:])
+    out[o["v"]:o["z"]] = (v - mu + np.vstack([vt, np.zeros((1, p))])).ravel()
+    out[o["z"]:o["lam"]] = (z + np.einsum("kij,ki->kj", Zb, lam)).ravel()
+    lrow = np.einsum("kij,kj->ki", N, u) + np.einsum("kij,kj->ki", Zb, z)
+    lrow[1:] += np.einsum("kij,kj->ki", Vb[1:], vprev[1:])
+    out[o["lam"]:o["mu"]] = lrow.ravel()
+    out[o["mu"]:o["end"]] = (u - v).ravel()
+    return out

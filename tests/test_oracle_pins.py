@@ -489,3 +489,13 @@ def test_single_block_helpers_match_the_assembled_operator():
         # the coupling is the rest of block k's rows of A~ y
         full = A[idx] @ y
         assert np.allclose(D @ y[idx] + block_coupling(y, p, q, n, k), full, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_blockwise_apply_matches_the_assembled_operator(shared):
+    # the step-by-step product used where the assembled matrix is too large
+    from oracle.system import apply_blocks
+    lv = random_level(7, 3, 2, 21, shared=shared)
+    A = assemble_A(lv.N, lv.V_full(), lv.Z_full())
+    x = np.random.default_rng(5).normal(size=A.shape[0])
+    np.testing.assert_allclose(apply_blocks(lv.N, lv.V, lv.Z, x), A @ x, rtol=1e-13, atol=1e-13)
