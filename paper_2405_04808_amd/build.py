@@ -20,8 +20,7 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
-# plain library GEMMs of the split sweep (shared V, Z~ products over all steps)
-LINK_FLAGS = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+LINK_FLAGS = []
 
 
 def hipcc_path() -> str:

@@ -145,7 +145,6 @@ struct pitmg_handle {
   int g_K = 0;                       // coarse steps enqueued in the capture
   int* g_its_slot = nullptr;
   long long graph_replays = 0;
-  void* blas = nullptr;              // rocBLAS handle of the split sweeps
   // previous iterate of the finest level's last sweep, when that sweep was
   // FP64 without a folded coarse correction (A~ z from the sweep identity)
   const double* top_prev = nullptr;
@@ -635,7 +634,7 @@ int vcycle_top(pitmg_handle* h, const double* r, double* e) {
   const pitmg_options& o = h->opt;
   h->vcycles++;
   const bool graph = o.vcycle_graph && h->stream != nullptr && !h->prof && o.nu_post > 0 &&
-                     o.coarse_mode == 0 && h->pair_count >= h->pair_cap && !h->blas;
+                     o.coarse_mode == 0 && h->pair_count >= h->pair_cap;
   if (!graph) return vcycle_level(h, 0, r, e);
   const long long len = h->lv[0].len;
   int rc;
@@ -1383,11 +1382,6 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
     }
     // split sweep for large blocks whose V and Z~ are shared by every step
     if ((h->p == 256 || h->p == 512) && pb->V_stride == 0 && pb->Z_stride == 0) {
-      if (!h->blas) {
-        const hipError_t e = split_blas_create(&h->blas, h->stream);
-        if (e != hipSuccess)
-          return fail(set_err(h, PITMG_ERR_HIP, "rocBLAS handle could not be created"));
-      }
       const long long pn = (long long)h->p * b.n, qn = (long long)h->q * b.n;
       if ((rc = dalloc(h, (void**)&b.sp.Rm, (pn + h->p) * 8))) return fail(rc);
       if ((rc = dalloc(h, (void**)&b.sp.U, pn * 8))) return fail(rc);
@@ -1398,7 +1392,6 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
         for (int i = 0; i < 6; ++i)
           if ((rc = dalloc(h, (void**)f32[i], (i < 4 ? pn : qn) * 4))) return fail(rc);
       }
-      b.sp.blas = h->blas;
       b.split = true;
     }
   }
@@ -1745,7 +1738,6 @@ void pitmg_destroy(pitmg_handle* h) {
                   b.sp.U32, b.sp.L32, b.sp.Wz32, b.sp.Wv32};
     for (void* ptr : sp) release(ptr);
   }
-  split_blas_destroy(h->blas);
   for (auto e : h->pool) (void)hipEventDestroy(e);
   for (auto& b : h->lv) {
     release(b.N_own);

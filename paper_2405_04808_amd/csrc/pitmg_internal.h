@@ -12,10 +12,9 @@ constexpr int kWave = 64;
 
 // Work buffers of the split sweep for large blocks (pitmg_split.hip): the
 // coupled right-hand sides R_mu [n+1][p], U = Z~ R_z - V R_mu [n][p],
-// W_z = Z~^T Lambda [n][q], W_v = V^T Lambda [n][p] (column-major, FP64), their
-// FP32 counterparts for an FP32 level, and the rocBLAS handle.
+// W_z = Z~^T Lambda [n][q], W_v = V^T Lambda [n][p] (one row per step, FP64)
+// and their FP32 counterparts for an FP32 level.
 struct SplitBuffers {
-  void* blas = nullptr;
   double *Rm = nullptr, *U = nullptr, *Wz = nullptr, *Wv = nullptr;
   float *Rm32 = nullptr, *Rz32 = nullptr, *U32 = nullptr, *L32 = nullptr, *Wz32 = nullptr,
         *Wv32 = nullptr;
@@ -283,8 +282,6 @@ hipError_t launch_apply_identity(int p, int q, int n, const double* b, const dou
 bool split_supported(const LevelView& L);
 hipError_t launch_jacobi_split(const LevelView& L, const double* b, const double* yold,
                                const double* ecoarse, int variant, double* ynew, hipStream_t s);
-hipError_t split_blas_create(void** blas, hipStream_t s);
-void split_blas_destroy(void* blas);
 
 // ---- small blocks (pitmg_small.hip): one thread per time step -------------
 bool small_supported(int p, int q);

@@ -22,6 +22,7 @@
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
 #include "pitmg_blocks.h"
+#include "pitmg_mfma.h"
 #include <algorithm>
 #include <climits>
 
@@ -43,25 +44,6 @@ constexpr int kFactorThreads = 256;
 // instructions differ).  Rows beyond p and columns beyond p+q read as zero.
 // S goes to the factor buffer (lower triangle; the factorisation kernel
 // reads it from there).
-template <class T>
-struct Mfma4;
-template <>
-struct Mfma4<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  __device__ static v4 step(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static int row(int group, int i) { return group + 4 * i; }
-};
-template <>
-struct Mfma4<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  __device__ static v4 step(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static int row(int group, int i) { return 4 * group + i; }
-};
-
 template <class T>
 __global__ __launch_bounds__(kFactorThreads) void k_syrk_mfma(LevelView L, T* Gi) {
   const int p = L.p, q = L.q, K = p + q;

@@ -14,6 +14,29 @@
 
 namespace pitmg {
 
+// One step of a 16x16 product with K = 4 on the matrix cores in the element
+// type's arithmetic.  Lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// element i of its result is C[row(l/16, i)][l%16] (the FP64 and FP32
+// instructions lay rows out differently).
+template <class T>
+struct Mfma4;
+template <>
+struct Mfma4<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 step(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int group, int i) { return group + 4 * i; }
+};
+template <>
+struct Mfma4<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 step(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int group, int i) { return 4 * group + i; }
+};
+
 constexpr int kGemmThreads = 512;
 constexpr int kGemmPanel = 32;
 

@@ -5,20 +5,20 @@
 // therefore split (Schur form as in pitmg_kernels.hip):
 //
 //   1. prepare: R_mu[:, k] = r_mu of block k+1 (b_mu minus the u coupling);
-//   2. GEMM:    U = Z~ R_z - V R_mu          (all steps at once, rocBLAS)
+//   2. GEMM:    U = Z~ R_z - V R_mu          (all steps at once)
 //   3. blocks:  t = N r_u + U_k - r_l, lambda = G^{-T} G^{-1} t,
 //               u = r_u - N^T lambda          (N_k, G_k^{-1} streamed twice)
 //   4. GEMM:    W_z = Z~^T Lambda,  W_v = V^T Lambda
 //   5. finish:  z = r_z - W_z,  mu = W_v - r_mu - r_v,  v = -r_mu
 //
 // so every block reads only its own N_k and G_k^{-1}, and V, Z~ are read once
-// per sweep by the GEMMs (the matrix cores, through the library).  The
-// output is the unweighted sweep; launch_jacobi weights it afterwards.
+// per 64-step tile of the GEMMs, which run on the matrix cores (k_gemm_rows).
+// The output is the unweighted sweep; launch_jacobi weights it afterwards.
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
 #include "pitmg_tiled.h"
+#include "pitmg_mfma.h"
 
-#include <rocblas/rocblas.h>
 
 namespace pitmg {
 namespace {
@@ -194,23 +194,79 @@ int grid_for_split(long long len) {
 
 size_t split_lds(int p, size_t elem) { return (size_t)(5 + kSplitWaves) * p * elem; }
 
-// column-major GEMM through rocBLAS in the level's arithmetic
-hipError_t gemm(rocblas_handle h, bool transA, int m, int nn, int kd, double alpha,
-                const double* A, int lda, const double* B, int ldb, double beta, double* C,
-                int ldc) {
-  const rocblas_status st = rocblas_dgemm(
-      h, transA ? rocblas_operation_transpose : rocblas_operation_none, rocblas_operation_none,
-      m, nn, kd, &alpha, A, lda, B, ldb, &beta, C, ldc);
-  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+// C (m x P, row-major, ld P) = alpha A op(B) + beta C with A (m x K, row-major,
+// ld lda) and op(B) = B (K x P, row-major) or B^T (B: P x K, row-major): the
+// per-step products of the split sweep, one 64 x 64 tile of C per work-group
+// of 256 threads (four waves of 32 x 32), K in panels of 32 staged in LDS.
+// Rows of A beyond m and columns beyond K read as zero.  FP64 on
+// v_mfma_f64_16x16x4f64, FP32 on v_mfma_f32_16x16x4f32 (Mfma4 layouts).
+constexpr int kGemmTile = 64;
+constexpr int kGemmK = 32;
+
+template <class T, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_rows(int m, int P, int K, double alpha,
+                                                   const T* __restrict__ A, long long lda,
+                                                   const T* __restrict__ B, double beta,
+                                                   T* __restrict__ C) {
+  __shared__ T As[kGemmTile][kGemmK + 1];
+  __shared__ T Bs[kGemmK][kGemmTile + 1];
+  const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+  const int r = lane & 15, g = lane >> 4;
+  const int row0 = blockIdx.x * kGemmTile, col0 = blockIdx.y * kGemmTile;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;          // the wave's 32 x 32
+  typename Mfma4<T>::v4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += kGemmK) {
+    __syncthreads();
+    for (int e = tid; e < kGemmTile * kGemmK; e += 256) {
+      const int i = e / kGemmK, kk = e % kGemmK;            // A: rows of 32
+      const int gi = row0 + i, gk = k0 + kk;
+      As[i][kk] = gi < m && gk < K ? A[(long long)gi * lda + gk] : T(0);
+      if (!TB) {                                            // B: rows of 64
+        const int k2 = e / kGemmTile, j = e % kGemmTile;
+        Bs[k2][j] = k0 + k2 < K ? B[(long long)(k0 + k2) * P + col0 + j] : T(0);
+      } else {                                              // B^T: rows of 32
+        const int j = e / kGemmK, k2 = e % kGemmK;
+        Bs[k2][j] = k0 + k2 < K ? B[(long long)(col0 + j) * K + k0 + k2] : T(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kGemmK / 4; ++s) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T av = As[wr + 16 * a + r][4 * s + g];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = Mfma4<T>::step(av, Bs[4 * s + g][wc + 16 * b + r], acc[a][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gi = row0 + wr + 16 * a + Mfma4<T>::row(g, i);
+        const int gj = col0 + wc + 16 * b + r;
+        if (gi < m) {
+          T* c = C + (long long)gi * P + gj;
+          *c = (T)(alpha * (double)acc[a][b][i] + (beta != 0.0 ? beta * (double)*c : 0.0));
+        }
+      }
 }
-hipError_t gemm(rocblas_handle h, bool transA, int m, int nn, int kd, double alpha,
-                const float* A, int lda, const float* B, int ldb, double beta, float* C,
-                int ldc) {
-  const float af = (float)alpha, bf = (float)beta;
-  const rocblas_status st = rocblas_sgemm(
-      h, transA ? rocblas_operation_transpose : rocblas_operation_none, rocblas_operation_none,
-      m, nn, kd, &af, A, lda, B, ldb, &bf, C, ldc);
-  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+
+template <class T, bool TB>
+hipError_t gemm_rows(int m, int P, int K, double alpha, const T* A, long long lda, const T* B,
+                     double beta, T* C, hipStream_t s) {
+  if (P % kGemmTile) return hipErrorInvalidValue;
+  const dim3 grid((m + kGemmTile - 1) / kGemmTile, P / kGemmTile);
+  return launch_k(k_gemm_rows<T, TB>, grid, dim3(256), 0, s, m, P, K, alpha, A, lda, B, beta,
+                  C);
 }
 
 template <int RT, int CT, class T>
@@ -221,7 +277,6 @@ hipError_t run_split(const LevelView& L, const SplitBuffers& S, const double* b,
   const int n = L.n, q = L.q;
   const bool f32 = sizeof(T) == 4;
   const TypeMajor Tm(P, q, n);
-  rocblas_handle blas = (rocblas_handle)S.blas;
   Coupling C{PrevIterate{yold, ecoarse, P, q, n, variant, L.mu_scale}};
   hipError_t e = launch_k(k_split_prepare, dim3(grid_for_split((long long)P * (n + 1))),
                           dim3(256), 0, s, C, b, S.Rm, f32 ? S.Rm32 : (float*)nullptr,
@@ -234,9 +289,9 @@ hipError_t run_split(const LevelView& L, const SplitBuffers& S, const double* b,
   T* Wv = f32 ? (T*)S.Wv32 : (T*)S.Wv;
   const T* Rz = f32 ? (const T*)S.Rz32 : (const T*)(b + Tm.z);
   const T* Rm = f32 ? (const T*)S.Rm32 : (const T*)S.Rm;
-  // U = Z~ R_z - V R_mu   (row-major Z~ (P x q) is column-major Z~^T, lda q)
-  if ((e = gemm(blas, true, P, n, q, 1.0, Z, q, Rz, q, 0.0, U, P))) return e;
-  if ((e = gemm(blas, true, P, n, P, -1.0, V, P, Rm, P, 1.0, U, P))) return e;
+  // per step k (rows): U_k = Z~ r_z,k - V r_mu,k, i.e. U = R_z Z~^T - R_mu V^T
+  if ((e = gemm_rows<T, true>(n, P, q, 1.0, Rz, q, Z, 0.0, U, s))) return e;
+  if ((e = gemm_rows<T, true>(n, P, P, -1.0, Rm, P, V, 1.0, U, s))) return e;
   const size_t lds = split_lds(P, sizeof(T));
   e = hipFuncSetAttribute((const void*)k_split_blocks<RT, CT, T>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -244,10 +299,10 @@ hipError_t run_split(const LevelView& L, const SplitBuffers& S, const double* b,
   e = launch_k(k_split_blocks<RT, CT, T>, dim3(n), dim3(kSplitThreads), lds, s, L, C, b,
                (const T*)U, ynew, f32 ? (T*)S.L32 : (T*)nullptr);
   if (e != hipSuccess) return e;
-  // W_z = Z~^T Lambda, W_v = V^T Lambda   (Lambda: the lambda part of ynew)
+  // W_z,k = Z~^T lambda_k, W_v,k = V^T lambda_k: W = Lambda Z~, Lambda V
   const T* Lam = f32 ? (const T*)S.L32 : (const T*)(ynew + Tm.l);
-  if ((e = gemm(blas, false, q, n, P, 1.0, Z, q, Lam, P, 0.0, Wz, q))) return e;
-  if ((e = gemm(blas, false, P, n, P, 1.0, V, P, Lam, P, 0.0, Wv, P))) return e;
+  if ((e = gemm_rows<T, false>(n, q, P, 1.0, Lam, P, Z, 0.0, Wz, s))) return e;
+  if ((e = gemm_rows<T, false>(n, P, P, 1.0, Lam, P, V, 0.0, Wv, s))) return e;
   return launch_k(k_split_finish<T>, dim3(grid_for_split((long long)(P + q) * n)), dim3(256), 0,
                   s, P, q, n, b, (const double*)S.Rm, (const T*)Wz, (const T*)Wv, ynew);
 }
@@ -255,7 +310,7 @@ hipError_t run_split(const LevelView& L, const SplitBuffers& S, const double* b,
 }  // namespace
 
 bool split_supported(const LevelView& L) {
-  return L.split && L.split->blas && L.sV == 0 && L.sZ == 0 && (L.p == 256 || L.p == 512);
+  return L.split && L.sV == 0 && L.sZ == 0 && (L.p == 256 || L.p == 512) && L.q % 64 == 0;
 }
 
 hipError_t launch_jacobi_split(const LevelView& L, const double* b, const double* yold,
@@ -266,21 +321,6 @@ hipError_t launch_jacobi_split(const LevelView& L, const double* b, const double
                   : run_split<16, 32, double>(L, S, b, yold, ecoarse, variant, ynew, s);
   return L.fp32 ? run_split<8, 16, float>(L, S, b, yold, ecoarse, variant, ynew, s)
                 : run_split<8, 16, double>(L, S, b, yold, ecoarse, variant, ynew, s);
-}
-
-hipError_t split_blas_create(void** blas, hipStream_t s) {
-  rocblas_handle h = nullptr;
-  if (rocblas_create_handle(&h) != rocblas_status_success) return hipErrorInitializationError;
-  if (rocblas_set_stream(h, s) != rocblas_status_success) {
-    rocblas_destroy_handle(h);
-    return hipErrorInitializationError;
-  }
-  *blas = h;
-  return hipSuccess;
-}
-
-void split_blas_destroy(void* blas) {
-  if (blas) rocblas_destroy_handle((rocblas_handle)blas);
 }
 
 }  // namespace pitmg
