@@ -160,7 +160,7 @@ def block_coupling(y: np.ndarray, p: int, q: int, n: int, k: int) -> np.ndarray:
     return np.concatenate([np.zeros(p), mu_k, np.zeros(q + p), u_km1])
 
 
-def apply_blocks(N, V, Z, x: np.ndarray) -> np.ndarray:
+def apply_blocks(N, V, Z, x: np.ndarray, magnitude: bool = False) -> np.ndarray:
     """A~ x in type-major order from the operator rows of the lifted system
     (Fig. 4), step by step with dense products, for sizes whose assembled
     matrix is too large to form.  N: (n,p,p), V: (n,p,p), Z: (n,p,q), each
@@ -170,8 +170,13 @@ def apply_blocks(N, V, Z, x: np.ndarray) -> np.ndarray:
       z_k:      z_k + Z_k^T lambda_k
       lambda_k: N_k u_k + V_k v_{k-1} + Z_k z_k          (v_0 := 0)
       mu_k:     u_k - v_k
+    magnitude=True gives |A~| |x| instead (every entry and every sign taken
+    positive), the scale of the rounding error of a computed product.
     """
     N = np.asarray(N)
+    sg = -1.0
+    if magnitude:
+        N, V, Z, x, sg = np.abs(N), np.abs(V), np.abs(Z), np.abs(x), 1.0
     n, p, _ = N.shape
     q = Z.shape[2]
     o = type_offsets(p, q, n)
@@ -186,10 +191,10 @@ def apply_blocks(N, V, Z, x: np.ndarray) -> np.ndarray:
     out = np.empty_like(x)
     out[o["u"]:o["v"]] = (u + np.einsum("kij,ki->kj", N, lam) + mu).ravel()
     vt = np.einsum("kij,ki->kj", Vb[1:], lam[1:])
-    out[o["v"]:o["z"]] = (v - mu + np.vstack([vt, np.zeros((1, p))])).ravel()
+    out[o["v"]:o["z"]] = (v + sg * mu + np.vstack([vt, np.zeros((1, p))])).ravel()
     out[o["z"]:o["lam"]] = (z + np.einsum("kij,ki->kj", Zb, lam)).ravel()
     lrow = np.einsum("kij,kj->ki", N, u) + np.einsum("kij,kj->ki", Zb, z)
     lrow[1:] += np.einsum("kij,kj->ki", Vb[1:], vprev[1:])
     out[o["lam"]:o["mu"]] = lrow.ravel()
-    out[o["mu"]:o["end"]] = (u - v).ravel()
+    out[o["mu"]:o["end"]] = (u + sg * v).ravel()
     return out

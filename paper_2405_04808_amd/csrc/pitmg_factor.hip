@@ -1,13 +1,16 @@
-// Factorisation of the time-step blocks on the matrix cores, every level in
-// one launch: for each block k of each level (p = 16 NT <= 128, FP64)
+// Factorisation of the time-step blocks on the matrix cores, every level of
+// one element type in one launch: for each block k of each level
 //
 //     S_k = N_k N_k^T + Z~_k Z~_k^T,   S_k = G_k G_k^T (Cholesky),   G_k^{-1},
 //
 // written row-major into the factor buffer with zeros above the diagonal.
 // (Block algebra: pitmg_kernels.hip; S_k is positive definite when N_k is
-// invertible, Thm. 1.)  One work-group of 512 threads per block keeps S_k and
-// then G_k^{-1} in LDS as 16x16 tiles of the lower triangle and works tile by
-// tile with v_mfma_f64_16x16x4f64:
+// invertible, Thm. 1.)  FP64 blocks use v_mfma_f64_16x16x4f64, FP32 blocks
+// (the FP32 smoother's levels) v_mfma_f32_16x16x4f32.  One work-group of 512
+// threads per block.
+//
+// p = 16 NT <= 128 (k_factor_mfma): S_k and then G_k^{-1} stay in LDS as
+// 16x16 tiles of the lower triangle, worked on tile by tile:
 //
 //   1. S = X X^T, X = [N_k | Z~_k]: column panels of X staged in LDS through
 //      coalesced row loads, each wave accumulating its lower tiles in
@@ -20,11 +23,28 @@
 //      X_IJ = -X_II sum_{K=J}^{I-1} G_IK X_KJ (matrix cores);
 //   4. X to global memory, row-major, zero above the diagonal.
 //
-// Tiles are stored row-major with the column index rotated by the row
+// p = 128 NB, NB in {2, 4} (k_factor_big): the same algorithm one level up,
+// on 128 x 128 super-blocks kept in the factor buffer itself (global
+// memory; the block's 0.5-2 MB mostly stays in the caches), each product a
+// 128 x 128 matrix-core GEMM of the work-group (Gemm128):
+//
+//   1. S_IJ = N_I N_J^T + Z~_I Z~_J^T for J <= I (N_I: rows 128I.. of N_k),
+//      zeros above;
+//   2. for K = 0 .. NB-1: the diagonal super-block through steps 2-3 above
+//      in LDS (G_KK and X_KK = G_KK^{-1}), X_KK stored in its place (G_KK is
+//      not needed again), the panel G_IK = S_IK X_KK^T, the trailing update
+//      S_IJ -= G_IK G_JK^T;
+//   3. the inverse in place, super-block column J from right to left and
+//      within it I from the bottom up: from X G = I,
+//      X_IJ = -(sum_{K=J+1}^{I} X_IK G_KJ) X_JJ, where the sum reads G_KJ
+//      only for K <= I, none of which the bottom-up order has overwritten.
+//
+// Tiles in LDS are stored row-major with the column index rotated by the row
 // ((c + r) mod 16), so a wave's operand reads (16 rows at one column, or 16
 // columns of one row) fall in distinct banks.
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
+#include "pitmg_mfma.h"
 
 namespace pitmg {
 namespace {
@@ -32,12 +52,6 @@ namespace {
 constexpr int kFacThreads = 512;
 constexpr int kFacWaves = kFacThreads / kWave;
 constexpr int kPanel = 32;                     // columns of X staged per pass
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // Element (r, c) of a 16x16 tile.
 __device__ __forceinline__ int tix(int r, int c) { return r * 16 + ((c + r) & 15); }
@@ -49,38 +63,172 @@ struct Tiles {
   __device__ static int id(int I, int J) { return I * (I + 1) / 2 + J; }
 };
 
-}  // namespace
+// Row of element i of a lane of group g in a matrix-core result tile.
+template <class T>
+__device__ __forceinline__ int arow(int g, int i) { return Mfma4<T>::row(g, i); }
 
-template <int NT>
-__global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatch F, int* fail) {
+// Steps 2 and 3 on the lower tiles of a P x P symmetric matrix in St:
+// Cholesky in place (St then holds G), the inverse of G into Xt.  Returns
+// false (uniformly, after a barrier) when a pivot is not positive.
+template <class T, int NT>
+__device__ bool tile_cholesky_inverse(T* St, T* Xt, int* sfail) {
   using TL = Tiles<NT>;
-  constexpr int P = TL::P;
-  extern __shared__ double lds[];
-  double* St = lds;                                     // S, then G: kTiles tiles
-  double* Xt = lds + TL::kTiles * 256;                  // G^{-1} tiles
-  double* stage = Xt;                                   // X panel (before step 3)
-  __shared__ int sfail;
+  typedef typename Mfma4<T>::v4 v4;
   const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
   const int r = lane & 15, g = lane >> 4;
 
-  // which level and block this work-group factors
-  int lev = 0;
+  // ---- blocked Cholesky, right-looking ------------------------------------
+  for (int Kt = 0; Kt < NT; ++Kt) {
+    T* D = St + TL::id(Kt, Kt) * 256;
+    if (w == 0) {
+      // unblocked Cholesky of the diagonal tile by one wave (lanes in order)
+      for (int j = 0; j < 16; ++j) {
+        const T d = D[tix(j, j)];
+        if (!(d > T(0)) || !isfinite(d)) {
+          if (lane == 0) *sfail = 1;
+          break;                                         // uniform in the wave
+        }
+        const T s = sqrt(d), inv = T(1) / s;
+        if (lane > j && lane < 16) D[tix(lane, j)] *= inv;
+        if (lane == 0) D[tix(j, j)] = s;
+        // rank-1 update of the trailing part of the tile (rows, columns > j)
+        for (int e = lane; e < 256; e += kWave) {
+          const int i = e >> 4, c = e & 15;
+          if (i > j && c > j && c <= i) D[tix(i, c)] -= D[tix(i, j)] * D[tix(c, j)];
+        }
+      }
+    }
+    __syncthreads();
+    if (*sfail) return false;                            // uniform: after the barrier
+    // panel: G_IK = S_IK G_KK^{-T}, one thread per row of the tiles below
+    {
+      const int row = tid;                               // row within the panel
+      const int I = Kt + 1 + row / 16;
+      if (I < NT) {
+        T* Tp = St + TL::id(I, Kt) * 256;
+        const int rr = row & 15;
+        T x[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          T v = Tp[tix(rr, c)];
+#pragma unroll
+          for (int j = 0; j < c; ++j) v -= x[j] * D[tix(c, j)];
+          x[c] = v / D[tix(c, c)];
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Tp[tix(rr, c)] = x[c];
+      }
+    }
+    __syncthreads();
+    // trailing update S_IJ -= G_IK G_JK^T, Kt < J <= I
+    const int m = NT - 1 - Kt;
+    const int ntr = m * (m + 1) / 2;
+    for (int t = w; t < ntr; t += kFacWaves) {
+      int ii = 0;
+      while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+      const int I = Kt + 1 + ii, J = Kt + 1 + (t - ii * (ii + 1) / 2);
+      T* C = St + TL::id(I, J) * 256;
+      const T* A = St + TL::id(I, Kt) * 256;
+      const T* B = St + TL::id(J, Kt) * 256;
+      v4 c4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) c4[i] = C[tix(arow<T>(g, i), r)];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        c4 = Mfma4<T>::step(-A[tix(r, 4 * s + g)], B[tix(r, 4 * s + g)], c4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) C[tix(arow<T>(g, i), r)] = c4[i];
+    }
+    __syncthreads();
+  }
+
+  // ---- X = G^{-1}, blocked -------------------------------------------------
+  // diagonal tiles: column j of X_KK solves G_KK x = e_j (lane j of a wave)
+  for (int Kt = w; Kt < NT; Kt += kFacWaves) {
+    if (lane < 16) {
+      const T* D = St + TL::id(Kt, Kt) * 256;
+      T* X = Xt + TL::id(Kt, Kt) * 256;
+      const int j = lane;
+      T x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        T v = i == j ? T(1) : T(0);
+#pragma unroll
+        for (int c = 0; c < i; ++c) v -= D[tix(i, c)] * x[c];
+        x[i] = i < j ? T(0) : v / D[tix(i, i)];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) X[tix(i, j)] = x[i];
+    }
+  }
+  __syncthreads();
+  // off-diagonal tiles by diagonals d = I - J
+  for (int d = 1; d < NT; ++d) {
+    for (int J = w; J + d < NT; J += kFacWaves) {
+      const int I = J + d;
+      v4 t4 = v4{0, 0, 0, 0};
+      for (int Kt = J; Kt < I; ++Kt) {
+        const T* A = St + TL::id(I, Kt) * 256;           // G_IK
+        const T* B = Xt + TL::id(Kt, J) * 256;           // X_KJ
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          t4 = Mfma4<T>::step(A[tix(r, 4 * s + g)], B[tix(4 * s + g, r)], t4);
+      }
+      // X_IJ = -X_II T with T's accumulator as the B operand: element s of
+      // the lane is T[arow(g, s)][r], so k-chunk s takes the inner indices
+      // arow(g, s) of the A operand too
+      const T* A = Xt + TL::id(I, I) * 256;
+      v4 x4 = v4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) x4 = Mfma4<T>::step(-A[tix(r, arow<T>(g, s))], t4[s], x4);
+      T* X = Xt + TL::id(I, J) * 256;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) X[tix(arow<T>(g, i), r)] = x4[i];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// Which level and block a work-group of a batch launch factors.
+template <class T>
+__device__ void batch_block(const FactorBatchT<T>& F, int& lev, int& k) {
+  lev = 0;
   while (lev + 1 < F.nlev && (int)blockIdx.x >= F.start[lev + 1]) ++lev;
-  const int k = blockIdx.x - F.start[lev];
+  k = blockIdx.x - F.start[lev];
+}
+
+}  // namespace
+
+template <class T, int NT>
+__global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatchT<T> F, int* fail) {
+  using TL = Tiles<NT>;
+  typedef typename Mfma4<T>::v4 v4;
+  constexpr int P = TL::P;
+  extern __shared__ double lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  T* St = lds;                                          // S, then G: kTiles tiles
+  T* Xt = lds + TL::kTiles * 256;                       // G^{-1} tiles
+  T* stage = Xt;                                        // X panel (before step 3)
+  __shared__ int sfail;
+  const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+  const int r = lane & 15, g = lane >> 4;
+  int lev, k;
+  batch_block(F, lev, k);
   const int q = F.q;
-  const double* __restrict__ Nk = F.N[lev] + (long long)k * F.sN;
-  const double* __restrict__ Zk = F.Z[lev] + (long long)k * F.sZ;
-  double* __restrict__ Gk = F.Gi[lev] + (long long)k * P * P;
+  const T* __restrict__ Nk = F.N[lev] + (long long)k * F.sN;
+  const T* __restrict__ Zk = F.Z[lev] + (long long)k * F.sZ;
+  T* __restrict__ Gk = F.Gi[lev] + (long long)k * P * P;
   if (tid == 0) sfail = 0;
 
   // ---- 1. S = X X^T --------------------------------------------------------
   // lower tiles t = w, w + 8, ... of this wave, numbered row by row
   constexpr int kMine = (TL::kTiles + kFacWaves - 1) / kFacWaves;
-  f64x4 acc[kMine];
+  v4 acc[kMine];
   int tI[kMine], tJ[kMine];
 #pragma unroll
   for (int m = 0; m < kMine; ++m) {
-    acc[m] = f64x4{0, 0, 0, 0};
+    acc[m] = v4{0, 0, 0, 0};
     int t = w + m * kFacWaves, I = 0;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     tI[m] = I;
@@ -92,7 +240,7 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatch F, i
     // stage X[:, c0 .. c0+31] as [row][32] (zero past the last column)
     for (int e = tid; e < P * kPanel; e += kFacThreads) {
       const int i = e / kPanel, c = c0 + e % kPanel;
-      double v = 0.0;
+      T v = T(0);
       if (c < P) v = Nk[(long long)i * P + c];
       else if (c < K) v = Zk[(long long)i * q + (c - P)];
       stage[i * (kPanel + 1) + e % kPanel] = v;
@@ -101,10 +249,11 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatch F, i
 #pragma unroll
     for (int m = 0; m < kMine; ++m) {
       if (w + m * kFacWaves < TL::kTiles) {
-        const double* A = stage + (16 * tI[m] + r) * (kPanel + 1);
-        const double* B = stage + (16 * tJ[m] + r) * (kPanel + 1);
+        const T* A = stage + (16 * tI[m] + r) * (kPanel + 1);
+        const T* B = stage + (16 * tJ[m] + r) * (kPanel + 1);
 #pragma unroll
-        for (int s = 0; s < kPanel / 4; ++s) acc[m] = mfma(A[4 * s + g], B[4 * s + g], acc[m]);
+        for (int s = 0; s < kPanel / 4; ++s)
+          acc[m] = Mfma4<T>::step(A[4 * s + g], B[4 * s + g], acc[m]);
       }
     }
   }
@@ -112,159 +261,146 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatch F, i
 #pragma unroll
   for (int m = 0; m < kMine; ++m) {
     if (w + m * kFacWaves < TL::kTiles) {
-      double* T = St + TL::id(tI[m], tJ[m]) * 256;
+      T* Tp = St + TL::id(tI[m], tJ[m]) * 256;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) T[tix(g + 4 * i, r)] = acc[m][i];
+      for (int i = 0; i < 4; ++i) Tp[tix(arow<T>(g, i), r)] = acc[m][i];
     }
   }
   __syncthreads();
 
-  // ---- 2. blocked Cholesky, right-looking ---------------------------------
-  for (int Kt = 0; Kt < NT; ++Kt) {
-    double* D = St + TL::id(Kt, Kt) * 256;
-    if (w == 0) {
-      // unblocked Cholesky of the diagonal tile by one wave (lanes in order)
-      for (int j = 0; j < 16; ++j) {
-        const double d = D[tix(j, j)];
-        if (!(d > 0.0) || !isfinite(d)) {
-          if (lane == 0) sfail = 1;
-          break;                                         // uniform in the wave
-        }
-        const double s = sqrt(d), inv = 1.0 / s;
-        if (lane > j && lane < 16) D[tix(lane, j)] *= inv;
-        if (lane == 0) D[tix(j, j)] = s;
-        // rank-1 update of the trailing part of the tile (rows, columns > j)
-        for (int e = lane; e < 256; e += kWave) {
-          const int i = e >> 4, c = e & 15;
-          if (i > j && c > j && c <= i) D[tix(i, c)] -= D[tix(i, j)] * D[tix(c, j)];
-        }
-      }
-    }
-    __syncthreads();
-    if (sfail) {
-      if (tid == 0) atomicMin(fail, (F.level0 + lev) << 20 | k);
-      return;                                            // uniform: after the barrier
-    }
-    // panel: G_IK = S_IK G_KK^{-T}, one thread per row of the tiles below
-    {
-      const int row = tid;                               // row within the panel
-      const int I = Kt + 1 + row / 16;
-      if (I < NT) {
-        double* T = St + TL::id(I, Kt) * 256;
-        const int rr = row & 15;
-        double x[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          double v = T[tix(rr, c)];
-#pragma unroll
-          for (int j = 0; j < c; ++j) v -= x[j] * D[tix(c, j)];
-          x[c] = v / D[tix(c, c)];
-        }
-#pragma unroll
-        for (int c = 0; c < 16; ++c) T[tix(rr, c)] = x[c];
-      }
-    }
-    __syncthreads();
-    // trailing update S_IJ -= G_IK G_JK^T, Kt < J <= I
-    const int m = NT - 1 - Kt;
-    const int ntr = m * (m + 1) / 2;
-    for (int t = w; t < ntr; t += kFacWaves) {
-      int ii = 0;
-      while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
-      const int I = Kt + 1 + ii, J = Kt + 1 + (t - ii * (ii + 1) / 2);
-      double* C = St + TL::id(I, J) * 256;
-      const double* A = St + TL::id(I, Kt) * 256;
-      const double* B = St + TL::id(J, Kt) * 256;
-      f64x4 c4;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) c4[i] = C[tix(g + 4 * i, r)];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) c4 = mfma(-A[tix(r, 4 * s + g)], B[tix(r, 4 * s + g)], c4);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) C[tix(g + 4 * i, r)] = c4[i];
-    }
-    __syncthreads();
-  }
-
-  // ---- 3. X = G^{-1}, blocked ---------------------------------------------
-  // diagonal tiles: column j of X_KK solves G_KK x = e_j (lane j of a wave)
-  for (int Kt = w; Kt < NT; Kt += kFacWaves) {
-    if (lane < 16) {
-      const double* D = St + TL::id(Kt, Kt) * 256;
-      double* X = Xt + TL::id(Kt, Kt) * 256;
-      const int j = lane;
-      double x[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        double v = i == j ? 1.0 : 0.0;
-#pragma unroll
-        for (int c = 0; c < i; ++c) v -= D[tix(i, c)] * x[c];
-        x[i] = i < j ? 0.0 : v / D[tix(i, i)];
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) X[tix(i, j)] = x[i];
-    }
-  }
-  __syncthreads();
-  // off-diagonal tiles by diagonals d = I - J
-  for (int d = 1; d < NT; ++d) {
-    for (int J = w; J + d < NT; J += kFacWaves) {
-      const int I = J + d;
-      f64x4 t4 = f64x4{0, 0, 0, 0};
-      for (int Kt = J; Kt < I; ++Kt) {
-        const double* A = St + TL::id(I, Kt) * 256;      // G_IK
-        const double* B = Xt + TL::id(Kt, J) * 256;      // X_KJ
-#pragma unroll
-        for (int s = 0; s < 4; ++s) t4 = mfma(A[tix(r, 4 * s + g)], B[tix(4 * s + g, r)], t4);
-      }
-      // X_IJ = -X_II T: T's accumulator element s is its row 4s + g, column
-      // r, which is the B operand of the k-chunk s
-      const double* A = Xt + TL::id(I, I) * 256;
-      f64x4 x4 = f64x4{0, 0, 0, 0};
-#pragma unroll
-      for (int s = 0; s < 4; ++s) x4 = mfma(-A[tix(r, 4 * s + g)], t4[s], x4);
-      double* X = Xt + TL::id(I, J) * 256;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) X[tix(g + 4 * i, r)] = x4[i];
-    }
-    __syncthreads();
+  // ---- 2-3. Cholesky and inverse ------------------------------------------
+  if (!tile_cholesky_inverse<T, NT>(St, Xt, &sfail)) {
+    if (tid == 0) atomicMin(fail, (F.level0 + lev) << 20 | k);
+    return;
   }
 
   // ---- 4. G^{-1} to global memory, zero above the diagonal ----------------
   for (int e = tid; e < P * P; e += kFacThreads) {
     const int i = e / P, j = e % P;
     const int I = i >> 4, J = j >> 4;
-    double v = 0.0;
+    T v = T(0);
     if (J < I) v = Xt[TL::id(I, J) * 256 + tix(i & 15, j & 15)];
     else if (J == I && (j & 15) <= (i & 15)) v = Xt[TL::id(I, I) * 256 + tix(i & 15, j & 15)];
     Gk[e] = v;
   }
 }
 
-bool factor_mfma_supported(int p) { return p == 64 || p == 128; }
+template <class T>
+__global__ __launch_bounds__(kFacThreads, 1) void k_factor_big(FactorBatchT<T> F, int* fail) {
+  using TL = Tiles<8>;
+  extern __shared__ double lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  T* St = lds;                                          // diagonal super-block
+  T* Xt = lds + TL::kTiles * 256;                       // its inverse
+  __shared__ int sfail;
+  const int tid = threadIdx.x;
+  int lev, k;
+  batch_block(F, lev, k);
+  const int P = F.p, q = F.q, NB = P / 128;
+  const T* __restrict__ Nk = F.N[lev] + (long long)k * F.sN;
+  const T* __restrict__ Zk = F.Z[lev] + (long long)k * F.sZ;
+  T* __restrict__ Gk = F.Gi[lev] + (long long)k * P * P;
+  auto at = [&](int I, int J) { return Gk + (long long)128 * I * P + 128 * J; };
+  if (tid == 0) sfail = 0;
+  Gemm128<T> gm;
 
-size_t factor_mfma_lds(int p) {
-  const int nt = p / 16;
-  return (size_t)nt * (nt + 1) * 256 * sizeof(double);   // S tiles + X tiles
+  // ---- 1. S_IJ = N_I N_J^T + Z~_I Z~_J^T, J <= I; zeros above ---------------
+  for (int I = 0; I < NB; ++I) {
+    for (int J = 0; J <= I; ++J) {
+      gm.zero();
+      gm.template mul<false, true>(Nk + (long long)128 * I * P, P, Nk + (long long)128 * J * P, P,
+                                   P, lds);
+      gm.template mul<false, true>(Zk + (long long)128 * I * q, q, Zk + (long long)128 * J * q, q,
+                                   q, lds);
+      gm.store(at(I, J), P, T(1), T(0));
+    }
+    for (int J = I + 1; J < NB; ++J)
+      for (int e = tid; e < 128 * 128; e += kFacThreads) at(I, J)[(long long)(e >> 7) * P + (e & 127)] = T(0);
+  }
+
+  // ---- 2. blocked Cholesky by super-blocks ---------------------------------
+  for (int K = 0; K < NB; ++K) {
+    __syncthreads();                                    // S_KK written, LDS free
+    const T* Skk = at(K, K);
+    for (int e = tid; e < TL::kTiles * 256; e += kFacThreads) {
+      const int t = e >> 8, rc = e & 255;
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      const int J = t - I * (I + 1) / 2, rr = rc >> 4, cc = rc & 15;
+      St[t * 256 + tix(rr, cc)] = Skk[(long long)(16 * I + rr) * P + 16 * J + cc];
+    }
+    __syncthreads();
+    if (!tile_cholesky_inverse<T, 8>(St, Xt, &sfail)) {
+      if (tid == 0) atomicMin(fail, (F.level0 + lev) << 20 | k);
+      return;
+    }
+    // X_KK in place of S_KK, zero above the diagonal
+    T* Xkk = at(K, K);
+    for (int e = tid; e < 128 * 128; e += kFacThreads) {
+      const int i = e >> 7, j = e & 127, I = i >> 4, J = j >> 4;
+      T v = T(0);
+      if (J < I) v = Xt[TL::id(I, J) * 256 + tix(i & 15, j & 15)];
+      else if (J == I && (j & 15) <= (i & 15)) v = Xt[TL::id(I, I) * 256 + tix(i & 15, j & 15)];
+      Xkk[(long long)i * P + j] = v;
+    }
+    // panel: G_IK = S_IK X_KK^T (in place)
+    for (int I = K + 1; I < NB; ++I) {
+      gm.zero();
+      gm.template mul<false, true>(at(I, K), P, Xkk, P, 128, lds);
+      gm.store(at(I, K), P, T(1), T(0));
+    }
+    // trailing: S_IJ -= G_IK G_JK^T, K < J <= I
+    for (int I = K + 1; I < NB; ++I)
+      for (int J = K + 1; J <= I; ++J) {
+        gm.zero();
+        gm.template mul<false, true>(at(I, K), P, at(J, K), P, 128, lds);
+        gm.store(at(I, J), P, T(-1), T(1));
+      }
+  }
+
+  // ---- 3. X = G^{-1} in place by super-blocks ------------------------------
+  for (int J = NB - 2; J >= 0; --J) {
+    for (int I = NB - 1; I > J; --I) {
+      gm.zero();
+      for (int K = J + 1; K <= I; ++K)
+        gm.template mul<false, false>(at(I, K), P, at(K, J), P, 128, lds);
+      gm.store(at(I, J), P, T(1), T(0));                // the sum, over G_IJ
+      gm.zero();
+      gm.template mul<false, false>(at(I, J), P, at(J, J), P, 128, lds);
+      gm.store(at(I, J), P, T(-1), T(0));
+    }
+  }
 }
 
-hipError_t launch_factor_mfma(const FactorBatch& F, int* fail, hipStream_t s) {
+bool factor_mfma_supported(int p, int q) {
+  if (p == 64 || p == 128) return true;
+  return (p == 256 || p == 512) && q > 0 && q % kPanel == 0;
+}
+
+template <class T>
+static hipError_t launch_t(const FactorBatchT<T>& F, int* fail, hipStream_t s) {
   const int total = F.start[F.nlev];
   if (total <= 0) return hipSuccess;
-  const size_t lds = factor_mfma_lds(F.p);
-  if (F.p == 128) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_factor_mfma<8>,
+  if (!factor_mfma_supported(F.p, F.q)) return hipErrorInvalidValue;
+  const int nt = F.p <= 128 ? F.p / 16 : 8;
+  const size_t lds = (size_t)nt * (nt + 1) * 256 * sizeof(T);   // S tiles + X tiles
+  auto go = [&](auto kern) -> hipError_t {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return launch_k(k_factor_mfma<8>, dim3(total), dim3(kFacThreads), lds, s, F, fail);
-  }
-  if (F.p == 64) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_factor_mfma<4>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return launch_k(k_factor_mfma<4>, dim3(total), dim3(kFacThreads), lds, s, F, fail);
-  }
-  return hipErrorInvalidValue;
+    return launch_k(kern, dim3(total), dim3(kFacThreads), lds, s, F, fail);
+  };
+  if (F.p == 64) return go(k_factor_mfma<T, 4>);
+  if (F.p == 128) return go(k_factor_mfma<T, 8>);
+  return go(k_factor_big<T>);
+}
+
+hipError_t launch_factor_mfma(const FactorBatchT<double>& F, int* fail, hipStream_t s) {
+  return launch_t(F, fail, s);
+}
+
+hipError_t launch_factor_mfma(const FactorBatchT<float>& F, int* fail, hipStream_t s) {
+  return launch_t(F, fail, s);
 }
 
 }  // namespace pitmg

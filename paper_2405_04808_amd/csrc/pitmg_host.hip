@@ -404,45 +404,54 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
   }
   const int big = INT_MAX;
   HIPCHK(h, hipMemcpyAsync(h->fail, &big, sizeof(int), hipMemcpyHostToDevice, h->stream));
-  // the FP64 levels in one launch on the matrix cores where the block size
-  // allows, the others level by level
-  const bool batched = factor_mfma_supported(h->p);
-  if (batched) {
-    FactorBatch F;
-    F.p = h->p;
-    F.q = h->q;
-    F.sN = pb->N_stride;
-    F.sZ = pb->Z_stride;
-    for (int l = 0; l < h->L; ++l) {
-      const LevelBuf& b = h->lv[l];
-      if (b.fp32) continue;
-      F.N[F.nlev] = b.N;
-      F.Z[F.nlev] = b.Z;
-      F.Gi[F.nlev] = b.Gi;
-      F.start[F.nlev + 1] = F.start[F.nlev] + b.n;
-      F.nlev++;
-    }
-    // FP32 levels are the finest ones, so the FP64 levels are level0 .. L-1
-    F.level0 = h->L - F.nlev;
-    int rc = timed(h, 0, [&] { return launch_factor_mfma(F, h->fail, h->stream); });
-    if (rc) return rc;
-  }
+  // FP32 copies of the blocks of the FP32 levels
   for (int l = 0; l < h->L; ++l) {
     LevelBuf& b = h->lv[l];
-    if (!b.fp32 && batched) continue;
-    if (b.fp32) {
-      const long long cN = (b.sN ? b.n : 1) * pp, cV = (b.sV ? b.n : 1) * pp,
-                      cZ = (b.sZ ? b.n : 1) * pq;
-      int rc = timed(h, 0, [&] { return launch_to_f32(b.N32, b.N, cN, h->stream); });
-      if (!rc) rc = timed(h, 0, [&] { return launch_to_f32(b.V32, b.V, cV, h->stream); });
-      if (!rc) rc = timed(h, 0, [&] { return launch_to_f32(b.Z32, b.Z, cZ, h->stream); });
-      if (rc) return rc;
+    if (!b.fp32) continue;
+    const long long cN = (b.sN ? b.n : 1) * pp, cV = (b.sV ? b.n : 1) * pp,
+                    cZ = (b.sZ ? b.n : 1) * pq;
+    int rc = timed(h, 0, [&] { return launch_to_f32(b.N32, b.N, cN, h->stream); });
+    if (!rc) rc = timed(h, 0, [&] { return launch_to_f32(b.V32, b.V, cV, h->stream); });
+    if (!rc) rc = timed(h, 0, [&] { return launch_to_f32(b.Z32, b.Z, cZ, h->stream); });
+    if (rc) return rc;
+  }
+  if (factor_mfma_supported(h->p, h->q)) {
+    // the levels of each element type in one launch on the matrix cores; the
+    // FP32 levels are the finest ones, so the FP64 levels are level0 .. L-1
+    FactorBatchT<double> F;
+    FactorBatchT<float> F32;
+    F.p = F32.p = h->p;
+    F.q = F32.q = h->q;
+    F.sN = F32.sN = pb->N_stride;
+    F.sZ = F32.sZ = pb->Z_stride;
+    for (int l = 0; l < h->L; ++l) {
+      const LevelBuf& b = h->lv[l];
+      if (b.fp32) {
+        F32.N[F32.nlev] = b.N32;
+        F32.Z[F32.nlev] = b.Z32;
+        F32.Gi[F32.nlev] = b.Gi32;
+        F32.start[F32.nlev + 1] = F32.start[F32.nlev] + b.n;
+        F32.nlev++;
+      } else {
+        F.N[F.nlev] = b.N;
+        F.Z[F.nlev] = b.Z;
+        F.Gi[F.nlev] = b.Gi;
+        F.start[F.nlev + 1] = F.start[F.nlev] + b.n;
+        F.nlev++;
+      }
+    }
+    F32.level0 = 0;
+    F.level0 = h->L - F.nlev;
+    int rc = F32.nlev ? timed(h, 0, [&] { return launch_factor_mfma(F32, h->fail, h->stream); })
+                      : 0;
+    if (!rc) rc = timed(h, 0, [&] { return launch_factor_mfma(F, h->fail, h->stream); });
+    if (rc) return rc;
+  } else {
+    for (int l = 0; l < h->L; ++l) {
+      LevelBuf& b = h->lv[l];
       LevelView v = view(h, l);
-      rc = timed(h, 0, [&] { return launch_factor32(v, b.Gi32, l, h->fail, h->stream); });
-      if (rc) return rc;
-    } else {
-      LevelView v = view(h, l);
-      int rc = timed(h, 0, [&] { return launch_factor(v, b.Gi, l, h->fail, h->stream); });
+      int rc = b.fp32 ? timed(h, 0, [&] { return launch_factor32(v, b.Gi32, l, h->fail, h->stream); })
+                      : timed(h, 0, [&] { return launch_factor(v, b.Gi, l, h->fail, h->stream); });
       if (rc) return rc;
     }
   }

@@ -108,21 +108,25 @@ hipError_t launch_k(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
 // with (level << 20 | k) on a non-positive pivot.
 hipError_t launch_factor(const LevelView& L, double* Gi, int level, int* fail,
                          hipStream_t s);
-// Every FP64 level of a hierarchy in one launch on the matrix cores
-// (pitmg_factor.hip) for p in {64, 128}: block b of the launch is block
-// b - start[l] of level l for start[l] <= b < start[l+1].
-struct FactorBatch {
+// Every level of one element type in one launch on the matrix cores
+// (pitmg_factor.hip) for p in {64, 128}, and for p in {256, 512} with q a
+// multiple of 32: block b of the launch is block b - start[l] of level l for
+// start[l] <= b < start[l+1].  FP64 from N / Z~ into Gi, FP32 from the FP32
+// copies into Gi32.
+template <class T>
+struct FactorBatchT {
   int nlev = 0;
   int level0 = 0;              // hierarchy level of entry 0 (failure codes)
   int p = 0, q = 0;
   long long sN = 0, sZ = 0;
   int start[21] = {0};
-  const double* N[20] = {};
-  const double* Z[20] = {};
-  double* Gi[20] = {};
+  const T* N[20] = {};
+  const T* Z[20] = {};
+  T* Gi[20] = {};
 };
-bool factor_mfma_supported(int p);
-hipError_t launch_factor_mfma(const FactorBatch& F, int* fail, hipStream_t s);
+bool factor_mfma_supported(int p, int q);
+hipError_t launch_factor_mfma(const FactorBatchT<double>& F, int* fail, hipStream_t s);
+hipError_t launch_factor_mfma(const FactorBatchT<float>& F, int* fail, hipStream_t s);
 // Same in FP32 from L.N32 / L.Z32 into Gi32.
 hipError_t launch_factor32(const LevelView& L, float* Gi32, int level, int* fail,
                            hipStream_t s);

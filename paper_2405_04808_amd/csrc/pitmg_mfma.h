@@ -107,4 +107,80 @@ __device__ void wg_gemm(const double* __restrict__ A, long long lda,
   }
 }
 
+// A 128 x 128 block of a product for one work-group of 512 threads, in the
+// element type's arithmetic, accumulated in registers over any number of
+// calls (K a multiple of 32 per call):
+//
+//     acc += op(A) op(B),   op(A): 128 x K,  op(B): K x 128,
+//
+// with K-panels of op(A) (128 x 32) and op(B) (32 x 128) staged in LDS
+// through coalesced loads.  Wave w holds the eight 16x16 tiles of tile
+// column w, so each B operand it reads serves eight matrix-core steps.
+// Every call starts with a barrier, so consecutive calls may reuse the
+// staging area and read what an earlier store() of the work-group wrote;
+// a store() may overwrite the operands of the call before it (all of that
+// call's global reads precede its last barrier).
+template <class T>
+struct Gemm128 {
+  typedef typename Mfma4<T>::v4 v4;
+  static constexpr int kPadA = kGemmPanel + 1, kPadB = 128 + 1;
+  static constexpr int kLdsElems = 128 * kPadA + kGemmPanel * kPadB;
+  v4 acc[8];
+
+  __device__ void zero() {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) acc[m] = v4{0, 0, 0, 0};
+  }
+
+  template <bool TA, bool TB>
+  __device__ void mul(const T* __restrict__ A, long long lda, const T* __restrict__ B,
+                      long long ldb, int K, T* lds) {
+    T* As = lds;                                  // [128][33]
+    T* Bs = lds + 128 * kPadA;                    // [32][129]
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, g = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += kGemmPanel) {
+      __syncthreads();
+      for (int e = tid; e < 128 * kGemmPanel; e += kGemmThreads) {
+        if (!TA) {                                // rows of 32
+          const int i = e / kGemmPanel, kk = e % kGemmPanel;
+          As[i * kPadA + kk] = A[(long long)i * lda + k0 + kk];
+        } else {                                  // columns of 128
+          const int kk = e / 128, i = e % 128;
+          As[i * kPadA + kk] = A[(long long)(k0 + kk) * lda + i];
+        }
+        if (!TB) {
+          const int kk = e / 128, j = e % 128;
+          Bs[kk * kPadB + j] = B[(long long)(k0 + kk) * ldb + j];
+        } else {
+          const int j = e / kGemmPanel, kk = e % kGemmPanel;
+          Bs[kk * kPadB + j] = B[(long long)j * ldb + k0 + kk];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < kGemmPanel / 4; ++s) {
+        const T b = Bs[(4 * s + g) * kPadB + 16 * w + r];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+          acc[m] = Mfma4<T>::step(As[(16 * m + r) * kPadA + 4 * s + g], b, acc[m]);
+      }
+    }
+  }
+
+  // C = alpha acc + beta C (C is not read when beta is 0)
+  __device__ void store(T* C, long long ldc, T alpha, T beta) const {
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        T* c = C + (long long)(16 * m + Mfma4<T>::row(g, i)) * ldc + 16 * w + r;
+        const T v = alpha * acc[m][i];
+        *c = beta != T(0) ? v + beta * *c : v;
+      }
+  }
+};
+
 }  // namespace pitmg

@@ -3,6 +3,8 @@ cycle options that mirror the library's, and comparisons of type-major
 vectors one variable type at a time (u, v, z, lambda, mu), so that an error
 confined to a small slot (z carries 1/gamma; v and mu can be small) cannot
 hide in one global norm."""
+import functools
+
 import numpy as np
 
 from oracle import type_offsets
@@ -101,3 +103,11 @@ def coarse_identity_tol(prob):
     1e-10 of the explicit product.
     """
     return max(1e-10, 8 * 2.0 ** -53 * cond_S_max(prob.levels[-1]))
+
+
+@functools.lru_cache(maxsize=2)
+def full_config(name):
+    """config_problem(name), built once per test session: the 512-node Burgers
+    workload takes about half a minute and 20 GB of host memory to build."""
+    from workloads import config_problem
+    return config_problem(name)

@@ -16,7 +16,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from workloads import config_problem
+from parity_util import full_config
 from oracle.system import block_index, diagonal_block, block_coupling
 import paper_2405_04808_amd as pm
 
@@ -47,7 +47,7 @@ def sampled(n, rng):
 
 @pytest.mark.parametrize("name,modes", [("burgers512", (0, 99)), ("burgers256", (0,))])
 def test_fullsize_sweep_and_apply_on_sampled_blocks(name, modes):
-    prob, _ = config_problem(name)
+    prob, _ = full_config(name)
     lv = prob.levels[0]
     p, q, n = prob.p, prob.q, lv.N.shape[0]
     m = (4 * p + q) * n

@@ -293,12 +293,8 @@ def test_error_paths():
     s.close()
 
 
-def test_singular_block_location_reported():
-    prob, rng = make_problem(**CASES["vdp64"])
-    bad = [Level(n=l.n, dt=l.dt, N=l.N.copy(), V=l.V_full().copy(), Z=l.Z_full().copy())
-           for l in prob.levels]
-    bad[2].N[5] = 0.0
-    bad[2].Z[5] = 0.0
+def _setup_rc(levels, opts):
+    """pitmg_setup's return code on these blocks, and the handle's solver."""
     lib = pm.load_library()
     import ctypes as C
     s = object.__new__(pm.Solver)
@@ -306,14 +302,35 @@ def test_singular_block_location_reported():
     s.lib = lib
     s.device = torch.device("cuda")
     s.stream = torch.cuda.current_stream()
-    s.options = pm.default_options()
+    s.options = opts
     s.h = C.c_void_p()
-    s._upload(bad)
+    s._upload(levels)
     pb = s._problem()
     rc = lib.pitmg_setup(C.byref(s.h), C.byref(pb), C.byref(s.options),
                          C.c_void_p(s.stream.cuda_stream))
+    return rc, s
+
+
+# the per-level scalar factorisation (p = 2), the one-launch matrix-core
+# factorisation with the block in LDS (p = 64) and by super-blocks in global
+# memory (p = 256), FP64 and FP32 levels
+@pytest.mark.parametrize("case,fp32,level,step", [("vdp64", 0, 2, 6), ("p64", 0, 1, 3),
+                                                  ("p64", 2, 0, 9), ("p256", 0, 2, 2),
+                                                  ("p256", 2, 1, 4)])
+def test_singular_block_location_reported(case, fp32, level, step):
+    cfg = {"vdp64": CASES["vdp64"],
+           "p64": dict(kind="burgers", nx=64, nu=0.01, n=16, n_levels=3, seed=19),
+           "p256": dict(kind="burgers", nx=256, nu=0.01, n=16, n_levels=3, seed=19)}[case]
+    prob, rng = make_problem(**cfg)
+    bad = [Level(n=l.n, dt=l.dt, N=l.N.copy(), V=l.V_full().copy(), Z=l.Z_full().copy())
+           for l in prob.levels]
+    # S_k = N_k N_k^T + Z~_k Z~_k^T is singular when both blocks vanish
+    bad[level].N[step - 1] = 0.0
+    bad[level].Z[step - 1] = 0.0
+    print(f"singular block {case} fp32={fp32} level {level} step {step}", flush=True)
+    rc, s = _setup_rc(bad, pm.default_options(smoother_fp32=fp32))
     assert rc == pm.PITMG_ERR_SINGULAR
-    assert s.failed_block() == (2, 6)
+    assert s.failed_block() == (level, step)
     s.close()
 
 

@@ -499,3 +499,5 @@ def test_blockwise_apply_matches_the_assembled_operator(shared):
     A = assemble_A(lv.N, lv.V_full(), lv.Z_full())
     x = np.random.default_rng(5).normal(size=A.shape[0])
     np.testing.assert_allclose(apply_blocks(lv.N, lv.V, lv.Z, x), A @ x, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(apply_blocks(lv.N, lv.V, lv.Z, x, magnitude=True),
+                               abs(A) @ abs(x), rtol=1e-13, atol=1e-13)
