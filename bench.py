@@ -42,6 +42,14 @@ WORKLOADS = {
                             "8 levels (coarsest 8 steps), gamma=100, V(2,2) weighted block "
                             "Jacobi (omega 1/2), mu transfer scale 2, coarse GMRES+SGS tol "
                             "1e-3, FGMRES tol 1e-10"),
+    # the large-block workload (FP64 and FP32 smoothers); its assembled system
+    # (10.5 M unknowns, about 3e9 nonzeros) is beyond the oracle, so it has no
+    # CPU baseline
+    "burgers512": dict(cfg="burgers512", restart=200, maxit=800,
+                       desc="viscous Burgers nx=512 (p=q=512), nu=0.005, n=4096 steps, "
+                            "10 levels (coarsest 8 steps), gamma=100, V(2,2) weighted block "
+                            "Jacobi (omega 1/2), mu transfer scale 2, coarse GMRES+SGS tol "
+                            "1e-3, FGMRES(200) tol 1e-10"),
     "vdp256": dict(cfg="vdp256", restart=300, maxit=300,
                    desc="van der Pol p=2 q=1, n=256 steps, 6 levels, gamma=100, V(2,2) "
                         "weighted block Jacobi (omega 1/2), mu transfer scale 2, "
@@ -495,7 +503,7 @@ def main():
         batch = batch_leg(pm, torch, count=args.batch_count)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload != "burgers512":
         cpu = cpu_baseline(args.workload)
 
     out = {

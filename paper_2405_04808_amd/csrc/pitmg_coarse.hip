@@ -576,6 +576,89 @@ static hipError_t launch_propagators_mfma(const LevelView& L, double* W, double*
   return hipGetLastError();
 }
 
+// p = 128 NB (NB >= 2): every P x P product split into NB^2 super-blocks of
+// 128 x 128, one work-group each (Gemm128, K = P).
+//   k_batched_gemm128: C_s = op(A_s) B_s for every step s (W, X, Phi);
+//   k_propagator_step: chain step j of both propagators, P[j][i] for i < j
+//   (from P[j-1][i]) and Q[nc-1-j][i] for i > nc-1-j (from Q[nc-j][i]), each
+//   column's super-blocks in parallel; the host launches j = 1 .. nc-1 in
+//   order, so every launch reads blocks the previous one wrote.
+template <bool TA>
+__global__ __launch_bounds__(kGemmThreads) void k_batched_gemm128(
+    int P, const double* __restrict__ A, long long sA, const double* __restrict__ B,
+    long long sB, double* __restrict__ C) {
+  extern __shared__ double lds[];
+  const int NB = P / 128, per = NB * NB;
+  const long long s = blockIdx.x / per;
+  const int t = blockIdx.x % per, R = t / NB, Cc = t % NB;
+  const double* a = A + s * sA + (TA ? 128LL * R : 128LL * R * P);
+  Gemm128<double> gm;
+  gm.zero();
+  gm.template mul<TA, false>(a, P, B + s * sB + 128 * Cc, P, P, lds);
+  gm.store(C + s * (long long)P * P + 128LL * R * P + 128 * Cc, P, 1.0, 0.0);
+}
+
+__global__ __launch_bounds__(kGemmThreads) void k_propagator_step(
+    int P, int nc, int j, const double* __restrict__ Phi, double* P_, double* Q_) {
+  extern __shared__ double lds[];
+  const int NB = P / 128, per = NB * NB;
+  const int c = blockIdx.x / per, t = blockIdx.x % per, R = t / NB, Cc = t % NB;
+  const bool lower = c < j;
+  const long long ld = (long long)nc * P;
+  auto blk = [&](double* M, int rr, int cc) {
+    return M + (long long)rr * P * ld + (long long)cc * P;
+  };
+  Gemm128<double> gm;
+  gm.zero();
+  double* out;
+  if (lower) {                                 // P[j][i] = -Phi_j P[j-1][i], i = c
+    const double* a = Phi + (long long)j * P * P + 128LL * R * P;
+    gm.template mul<false, false>(a, P, blk(P_, j - 1, c) + 128 * Cc, ld, P, lds);
+    out = blk(P_, j, c);
+  } else {                                     // Q[m][i] = -Phi_{m+1}^T Q[m+1][i]
+    const int m = nc - 1 - j, i = m + 1 + (c - j);
+    const double* a = Phi + (long long)(m + 1) * P * P + 128 * R;
+    gm.template mul<true, false>(a, P, blk(Q_, m + 1, i) + 128 * Cc, ld, P, lds);
+    out = blk(Q_, m, i);
+  }
+  gm.store(out + 128LL * R * ld + 128 * Cc, ld, -1.0, 0.0);
+}
+
+__global__ void k_propagator_identity(int P, int nc, double* P_, double* Q_) {
+  const long long ld = (long long)nc * P;
+  const long long total = (long long)nc * P * P;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ((long long)P * P)), a = (int)(e / P % P), b = (int)(e % P);
+    const long long off = (long long)i * P * ld + (long long)i * P + (long long)a * ld + b;
+    const double v = a == b ? 1.0 : 0.0;
+    P_[off] = v;
+    Q_[off] = v;
+  }
+}
+
+static hipError_t launch_propagators_big(const LevelView& L, double* W, double* X, double* Phi,
+                                         double* P, double* Q, hipStream_t s) {
+  const int p = L.p, nc = L.n, per = (p / 128) * (p / 128);
+  const size_t lds = Gemm128<double>::kLdsElems * sizeof(double);
+  const void* fns[3] = {(const void*)k_batched_gemm128<false>,
+                        (const void*)k_batched_gemm128<true>, (const void*)k_propagator_step};
+  for (int f = 0; f < 3; ++f) {
+    hipError_t e = hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 g(nc * per), b(kGemmThreads);
+  const long long pp = (long long)p * p;
+  hipLaunchKernelGGL(k_batched_gemm128<false>, g, b, lds, s, p, L.Gi, pp, L.N, L.sN, W);
+  hipLaunchKernelGGL(k_batched_gemm128<false>, g, b, lds, s, p, L.Gi, pp, L.V, L.sV, X);
+  hipLaunchKernelGGL(k_batched_gemm128<true>, g, b, lds, s, p, W, pp, X, pp, Phi);
+  hipLaunchKernelGGL(k_propagator_identity, dim3(nc * 8), dim3(256), 0, s, p, nc, P, Q);
+  for (int j = 1; j < nc; ++j)
+    hipLaunchKernelGGL(k_propagator_step, dim3(2 * j * per), b, lds, s, p, nc, j, Phi, P, Q);
+  return hipGetLastError();
+}
+
 hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, double* P,
                               double* Q, hipStream_t s) {
   const int p = L.p, nc = L.n;
@@ -583,6 +666,7 @@ hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, 
   double* X = scratch + (size_t)nc * p * p;
   if (p == 128) return launch_propagators_mfma<8>(L, W, X, Phi, P, Q, s);
   if (p == 64) return launch_propagators_mfma<4>(L, W, X, Phi, P, Q, s);
+  if (p >= 256 && p % 128 == 0) return launch_propagators_big(L, W, X, Phi, P, Q, s);
   hipLaunchKernelGGL(k_gi_times, dim3(nc), dim3(512), 0, s, L, 0, W);
   hipLaunchKernelGGL(k_gi_times, dim3(nc), dim3(512), 0, s, L, 1, X);
   hipLaunchKernelGGL(k_phi, dim3(nc), dim3(512), 0, s, p, W, X, Phi);

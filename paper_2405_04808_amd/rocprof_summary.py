@@ -13,6 +13,13 @@ Two kinds of run are summarised:
   averaged over every sweep dispatch of the run, beside the algorithmic
   bytes.
 
+* a matrix-core run (``rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F64
+  SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE``):
+  per kernel, the matrix-core FLOP per dispatch (MOPS x 512), the rate over
+  the dispatch's duration against the device's dense peak for the type, and
+  the busy fraction SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / XCDs x
+  SIMDs) (GRBM_GUI_ACTIVE is summed over the XCDs).
+
 The counter summary ends with one machine-readable line,
 ``traffic: {json}``, which bench.py reads together with a hash of the sweep
 kernel's sources; the figure is only used while that hash matches.
@@ -167,6 +174,44 @@ def summarise_counters(fetch_dir, write_dir, kernel, copy_kernel, copy_bytes, ex
             "dispatches": int(cnt), "traffic_bytes_per_launch": per_launch}
 
 
+MFMA_PEAK_TFLOPS = {"F64": 78.6, "F32": 157.3}
+
+
+def mfma_table(directory: str, kernel: str) -> str:
+    """Per kernel matching `kernel`: dispatches, average duration, matrix-core
+    FLOP per dispatch, TFLOP/s and its fraction of the dense peak, busy %."""
+    path = _find(directory, "counter_collection.csv")
+    agent = list(csv.DictReader(open(_find(directory, "agent_info.csv"))))
+    gpu = [a for a in agent if int(a["Simd_Count"]) > 0][0]
+    simds, xcc = int(gpu["Simd_Count"]), int(gpu["Num_Xcc"])
+    rx = re.compile(kernel)
+    disp = defaultdict(dict)
+    for r in csv.DictReader(open(path)):
+        if not rx.search(r["Kernel_Name"]):
+            continue
+        d = disp[(r["Kernel_Name"], int(r["Grid_Size"]) // int(r["Workgroup_Size"]),
+                  r["Dispatch_Id"])]
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        d["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    per = defaultdict(list)
+    for (name, wgs, _), d in disp.items():
+        per[(name, wgs)].append(d)
+    out = ["| kernel | work-groups | dispatches | avg ms | MFMA GFLOP / dispatch | TFLOP/s | "
+           "peak | frac | MFMA busy |", "|---|---|---|---|---|---|---|---|---|"]
+    for (name, wgs), ds in sorted(per.items(), key=lambda kv: -sum(d["ns"] for d in kv[1])):
+        ns = sum(d["ns"] for d in ds) / len(ds)
+        f64 = sum(d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0) for d in ds) / len(ds) * 512
+        f32 = sum(d.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0) for d in ds) / len(ds) * 512
+        typ, flop = ("F64", f64) if f64 >= f32 else ("F32", f32)
+        busy = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0) for d in ds)
+        active = sum(d.get("GRBM_GUI_ACTIVE", 0) for d in ds) / xcc * simds
+        rate = flop / (ns * 1e-9) / 1e12
+        out.append("| `{}` | {} | {} | {:.3f} | {:.1f} | {:.2f} | {} {} | {:.3f} | {:.1f} % |".format(
+            _short(name), wgs, len(ds), ns / 1e6, flop / 1e9, rate, MFMA_PEAK_TFLOPS[typ], typ,
+            rate / MFMA_PEAK_TFLOPS[typ], 100.0 * busy / active if active else 0.0))
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -195,7 +240,25 @@ def main(argv=None):
     b.add_argument("--after-first", default=None,
                    help="kernel regex: count only dispatches after its first dispatch")
     b.add_argument("--out", required=True)
+    m = sub.add_parser("mfma")
+    m.add_argument("--dir", action="append", required=True, help="LABEL=DIR")
+    m.add_argument("--kernel", required=True)
+    m.add_argument("--title", required=True)
+    m.add_argument("--command", action="append", required=True)
+    m.add_argument("--note", default="")
+    m.add_argument("--out", required=True)
     args = ap.parse_args(argv)
+
+    if args.cmd == "mfma":
+        txt = [f"# {args.title}", "", "Commands (from the repository root, MI355X, ROCm 7.2):", "",
+               "```"] + args.command + ["```", ""]
+        if args.note:
+            txt += [args.note, ""]
+        for spec in args.dir:
+            label, d = spec.rsplit("=", 1)
+            txt += [f"## {label}", "", mfma_table(d, args.kernel), ""]
+        open(args.out, "w").write("\n".join(txt))
+        return 0
 
     if args.cmd == "stats":
         txt = [f"# {args.title}", "", "Command (from the repository root, MI355X, ROCm 7.2):", "",
