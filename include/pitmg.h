@@ -194,28 +194,51 @@ void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and
  * factor every block of every level (S_k = N_k N_k^T + Z~_k Z~_k^T, its
- * Cholesky factor G_k and G_k^{-1}).  stream: a hipStream_t or NULL. */
+ * Cholesky factor G_k and G_k^{-1}).  stream: a hipStream_t or NULL.
+ * Defined by: the blocks of the scaled constraint Jacobian (Sec. 4.1) with
+ * the lifting substitutions (Sec. 5.1); the diagonal blocks D_k of the
+ * permuted system (Sec. 5.2, Fig. 5), invertible when N_k is (Thm. 1), which
+ * is exactly when S_k is positive definite; the level hierarchy of
+ * Sec. 5.3.  PITMG_ERR_SINGULAR on a non-positive pivot of some S_k
+ * (pitmg_failed_block names it); PITMG_ERR_INVALID on sizes, strides or
+ * options out of range; PITMG_ERR_UNSUPPORTED for p or q above 512 or
+ * n >= 2^20; PITMG_ERR_OOM when device memory runs out.  *h is NULL on
+ * error. */
 int pitmg_setup(pitmg_handle** h, const pitmg_problem* pb,
                 const pitmg_options* opt, void* stream);
 
 /* New blocks of the same sizes and strides (a new linearisation point):
- * re-borrow or re-copy and re-factor without allocating. */
+ * re-borrow or re-copy and re-factor without allocating.  Defined by: each
+ * SQP iteration linearises the constraint at a new iterate and solves its
+ * augmented systems with the same preconditioner structure (Sec. 6).
+ * Errors as pitmg_setup; on error the handle keeps its sizes but its
+ * factors are not valid until a refactor succeeds. */
 int pitmg_refactor(pitmg_handle* h, const pitmg_problem* pb);
 
 /* Replace the options (sizes of the Krylov space may only shrink below the
  * values given at setup). */
 int pitmg_set_options(pitmg_handle* h, const pitmg_options* opt);
 
-/* y = A~ x on level `level` (type-major device vectors of that level). */
+/* y = A~ x on level `level` (type-major device vectors of that level):
+ * the lifted augmented operator of eq. (augsysp) (Sec. 5.1, Fig. 4; the
+ * time-major blocks of Fig. 5 are internal).  x and y must not overlap.
+ * PITMG_ERR_INVALID for a level out of range or a NULL vector. */
 int pitmg_apply(pitmg_handle* h, int level, const double* x, double* y);
 
-/* One block Jacobi sweep on level `level` (eq. (jacobi), second form):
- * y_out = D^{-1} (b - (L + L^T) y_in); y_in == NULL means y_in = 0. */
+/* One weighted block Jacobi sweep on level `level` (Sec. 5.3.2, the second
+ * form of eq. (jacobi), with the correction scaled by the option omega on
+ * every level above the coarsest):
+ * y_out = (1 - w) y_in + w D^{-1} (b - (L + L^T) y_in); y_in == NULL means
+ * y_in = 0.  y_out must not overlap b or y_in.  PITMG_ERR_INVALID for a
+ * level out of range or a NULL b or y_out. */
 int pitmg_jacobi_sweep(pitmg_handle* h, int level, const double* b,
                        const double* y_in, double* y_out);
 
-/* The coarsest-level solve on its own: GMRES + SGS from x0 = 0 on level
- * n_levels-1; *its receives the step count (host int, may be NULL). */
+/* The coarsest-level solve on its own (Sec. 5.3.4): GMRES right-
+ * preconditioned by symmetric block Gauss-Seidel, from x0 = 0 on level
+ * n_levels-1, to the relative tolerance coarse_tol (or exactly
+ * coarse_fixed_its steps); *its receives the step count (host int, may be
+ * NULL; the stream is synchronised when it is given). */
 int pitmg_coarse_solve(pitmg_handle* h, const double* b, double* x, int* its);
 
 /* pitmg_coarse_solve without a device buffer of the handle: for callers that
@@ -235,12 +258,22 @@ int pitmg_coarse_solve(pitmg_handle* h, const double* b, double* x, int* its);
  * returned. */
 int pitmg_coarse_solve_noalloc(pitmg_handle* h, const double* b, double* x, int* its);
 
-/* e = MG(r): one V-cycle from a zero initial guess on the finest level. */
+/* e = MG(r): one V-cycle from a zero initial guess on the finest level
+ * (Alg. 1, recursed to the coarsest level; Sec. 5.3: smoothing Sec. 5.3.2,
+ * transfers Sec. 5.3.1, coarse solve Sec. 5.3.4).  r and e are finest-level
+ * device vectors and must not overlap.  PITMG_ERR_HIP if a two-sweep launch
+ * reports a timed-out hand-off. */
 int pitmg_vcycle(pitmg_handle* h, const double* r, double* e);
 
 /* Solve A~ y = b~ (type-major x) by FGMRES preconditioned with one V-cycle
  * per step, to ||b - A~ x|| estimate <= tol ||b||.  x: in = initial guess if
- * use_x0 != 0 (else ignored), out = solution.  st may be NULL. */
+ * use_x0 != 0 (else ignored), out = solution.  st may be NULL.  Defined by:
+ * flexible GMRES (Saad 1993) with the multigrid preconditioner, needed
+ * because the coarse GMRES makes that preconditioner vary (Sec. 5.3.4,
+ * Sec. 6); the true residual of the returned iterate is recomputed and
+ * reported in st->relres_true.  Returns PITMG_NOT_CONVERGED (x = last
+ * iterate) when maxit steps do not reach tol, PITMG_ERR_NONFINITE on a
+ * non-finite residual. */
 int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x,
                        double tol, int use_x0, pitmg_stats* st);
 
