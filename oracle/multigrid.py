@@ -89,6 +89,14 @@ class MGOptions:
     Sec. 5.3).
     mu_scale: scale of the interface multiplier in the transfers (see
     oracle.transfer); 1 = the printed transfers.
+    cycle: "V" (the cycle of Alg. 1, one coarse correction per level), "W" or
+    "F" (Sec. 6 reports trying both): every level above the coarsest makes
+    two coarse corrections, the second from the coarse residual the first
+    leaves, e2 = MG_{l+1}(r_c - A~_{l+1} e1); W recurses with W in both, F
+    with F in the first and V in the second.  Counting a move down to the
+    next level and back up as two sequential steps, a 4-level V, F and W cycle
+    take 6, 18 and 28 (the counts Sec. 6 gives); Hierarchy.calls records the
+    levels entered.
     """
     nu_pre: int = 2
     nu_post: int = 2
@@ -98,6 +106,7 @@ class MGOptions:
     transfer_variant: int = 0
     omega: float = 0.5
     mu_scale: float = 2.0
+    cycle: str = "V"
 
 
 class Hierarchy:
@@ -124,6 +133,7 @@ class Hierarchy:
             self.R.append(Rt[c.perm][:, f.perm].tocsr())
             self.P.append(Pt[f.perm][:, c.perm].tocsr())
         self.coarse_its: List[int] = []
+        self.calls: List[int] = []                # levels entered by mg()
 
     # -- multigrid ------------------------------------------------------------
     def coarse_solve(self, b: np.ndarray) -> np.ndarray:
@@ -134,21 +144,33 @@ class Hierarchy:
         self.coarse_its.append(its)
         return x
 
-    def mg(self, lev: int, b: np.ndarray) -> np.ndarray:
-        """MG_lev(b): one V-cycle from a zero initial guess (Alg. 1)."""
+    def mg(self, lev: int, b: np.ndarray, cycle: Optional[str] = None) -> np.ndarray:
+        """MG_lev(b): one cycle from a zero initial guess (Alg. 1; the W and F
+        variants of MGOptions.cycle)."""
         if lev == len(self.levels) - 1:
             return self.coarse_solve(b)
+        cycle = cycle or self.opts.cycle
+        if cycle not in ("V", "W", "F"):
+            raise ValueError("cycle must be V, W or F")
         lv = self.levels[lev]
         o = self.opts
         y = np.zeros_like(b)
         for _ in range(o.nu_pre):                 # pre-smooth
             y = lv.jacobi(b, y, o.omega)
         r = b - lv.At @ y                         # residual
-        e = self.mg(lev + 1, self.R[lev] @ r)     # restrict + coarse solve
+        rc = self.R[lev] @ r                      # restrict
+        e = self._enter(lev + 1, rc, cycle)       # coarse correction
+        if cycle != "V":                          # the second one (W, F)
+            rc2 = rc - self.levels[lev + 1].At @ e
+            e = e + self._enter(lev + 1, rc2, "W" if cycle == "W" else "V")
         y = y + self.P[lev] @ e                   # interpolate and add
         for _ in range(o.nu_post):                # post-smooth
             y = lv.jacobi(b, y, o.omega)
         return y
+
+    def _enter(self, lev: int, b: np.ndarray, cycle: str) -> np.ndarray:
+        self.calls.append(lev)
+        return self.mg(lev, b, cycle)
 
     # -- type-major front end -------------------------------------------------
     def to_time(self, x: np.ndarray, lev: int = 0) -> np.ndarray:

@@ -205,3 +205,79 @@ def test_gamma_one_fgmres_counts_not_reproduced():
         c100 = fgmres_count(vdp_levels(n, gamma=100.0), 2, 2, 4, **WEIGHTED)[0]
         assert abs(c1 - c100) <= 3
         assert T3[n][0] / T3[n][1] >= 6
+
+
+# ---------------------------------------------------------------------------
+# W and F cycles (Sec. 6: tried, no significant gain over V)
+# ---------------------------------------------------------------------------
+
+def sequential_steps(H, cycle):
+    """Moves between levels of one cycle: every entry of a coarser level is a
+    move down and, on return, one up."""
+    H.calls = []
+    n = H.levels[0].n
+    p, q = H.levels[0].p, H.levels[0].q
+    H.mg(0, np.zeros((4 * p + q) * n) + 1.0, cycle)
+    return 2 * len(H.calls)
+
+
+@pytest.mark.parametrize("nlev", [2, 3, 4, 5])
+def test_cycle_sequential_steps(nlev):
+    """Sec. 6 counts the sequential steps of a 4-level cycle: 6 for V, 18 for
+    F, 28 for W.  The same recursion gives 2(L-1), L^2 + L - 2 and
+    2^(L+1) - 4 for L levels."""
+    levels = vdp_levels(8 << (nlev - 1))
+    H = Hierarchy(levels, MGOptions(coarse_fixed_its=1))
+    steps = {c: sequential_steps(H, c) for c in "VFW"}
+    L = nlev
+    assert steps == {"V": 2 * (L - 1), "F": L * L + L - 2, "W": 2 ** (L + 1) - 4}
+    if L == 4:
+        assert (steps["V"], steps["F"], steps["W"]) == (6, 18, 28)
+
+
+def test_w_cycle_squares_the_coarse_error_propagation():
+    """With an exact coarsest solve every cycle is linear.  On three levels
+    the level-1 correction of the W and F cycles is two level-1 cycles, the
+    second on the residual the first leaves, so its error propagation is the
+    square of the V-cycle's: A1^{-1} r - e_W = (I - B1 A1)^2 A1^{-1} r, with
+    B1 the level-1 V-cycle (a wrong residual or sign in the second correction
+    breaks this)."""
+    import scipy.sparse.linalg as spla
+    levels = vdp_levels(32)[:3]
+    H = Hierarchy(levels, MGOptions(coarse_tol=1e-14, coarse_maxit=500))
+    A1 = H.levels[1].At
+    lu = spla.splu(A1.tocsc())
+    r = np.random.default_rng(3).normal(size=A1.shape[0])
+    B1 = lambda v: H.mg(1, v, "V")
+    e1 = lu.solve(r)
+    once = e1 - B1(r)
+    twice = once - B1(A1 @ once)                  # (I - B1 A1)^2 A1^{-1} r
+    for cyc in ("W", "F"):
+        H.calls = []
+        # the level-1 part of a level-0 cycle: both corrections at level 1
+        e = H._enter(1, r, cyc)
+        e = e + H._enter(1, r - A1 @ e, "W" if cyc == "W" else "V")
+        np.testing.assert_allclose(e1 - e, twice, rtol=0, atol=1e-9 * np.linalg.norm(e1))
+    # and the V correction leaves the single factor
+    np.testing.assert_allclose(e1 - B1(r), once, rtol=0, atol=1e-12 * np.linalg.norm(e1))
+
+
+def test_two_levels_exact_coarse_solve_all_cycles_agree():
+    """On two levels with an exact coarse solve the second correction of W
+    and F is zero: all three cycles give the same result."""
+    levels = burgers_levels(16, nx=6)[:2]
+    H = Hierarchy(levels, MGOptions(coarse_tol=1e-14, coarse_maxit=500))
+    r = np.random.default_rng(4).normal(size=H.levels[0].At.shape[0])
+    v = H.mg(0, r, "V")
+    for cyc in ("W", "F"):
+        np.testing.assert_allclose(H.mg(0, r, cyc), v, rtol=0, atol=1e-10 * np.linalg.norm(v))
+
+
+def test_w_and_f_cycles_take_no_more_fgmres_steps_than_v():
+    """More coarse work per cycle: W and F need at most as many FGMRES steps
+    as V on the van der Pol settings of Sec. 6.1, and the gain is modest (the
+    paper found no significant advantage)."""
+    levels = vdp_levels(128)
+    counts = {c: fgmres_count(levels, 2, 2, 2, cycle=c, **WEIGHTED)[0] for c in "VFW"}
+    assert counts["W"] <= counts["V"] and counts["F"] <= counts["V"], counts
+    assert counts["W"] >= counts["V"] // 3, counts
