@@ -214,13 +214,15 @@ def learned_leg(pm, torch, wl, train_seeds=range(50000, 50008), held_out=(60000,
             "held_out": {str(sd): row for sd, row in zip(held_out, abl)}}
 
 
-def batch_leg(pm, torch, count=32, vdp_n=(256, 1024)):
-    """Uneven batch: the same independent systems solved one after another,
-    as one batch (phases interleaved over one stream per system), and as a
-    batch with captured V-cycles and tuned sweeps.  Fresh handles for each
-    mode; setup and tuning are timed apart from the solves."""
+def batch_leg(pm, torch, count=64):
+    """Uneven batch: 64 independent systems, half van der Pol (n in {256,
+    1024, 4096}), half viscous Burgers (nx in {64, 128, 256}, n in {512 ..
+    4096}), FP32 smoother and FP64 outer solve, solved one after another, as
+    one batch (phases interleaved over one stream per system), and as a batch
+    with captured V-cycles and tuned sweeps.  Fresh handles for each mode;
+    setup and tuning are timed apart from the solves."""
     from workloads import batch_mix, make_problem, make_rhs
-    cfgs = batch_mix(count=count, vdp_n=vdp_n)
+    cfgs = batch_mix(count=count)
     probs = []
     for c in cfgs:
         prob, rng = make_problem(**c)
@@ -228,15 +230,18 @@ def batch_leg(pm, torch, count=32, vdp_n=(256, 1024)):
     bs = [torch.from_numpy(b).to("cuda") for _, b in probs]
     torch.cuda.synchronize()
     out = {"systems": count,
-           "mix": f"{count // 2} van der Pol (n in {list(vdp_n)}), {count - count // 2} Burgers "
-                  "(nx in [32, 64, 128], n in [256, 512]); seeds 4000+i; coarsest 8 steps"}
+           "mix": f"{count // 2} van der Pol (n in [256, 1024, 4096]), {count - count // 2} "
+                  "viscous Burgers (nx in [64, 128, 256], n in [512, 1024, 2048, 4096]); seeds "
+                  "4000+i; coarsest 8 steps; FP32 smoother on every level above the coarsest, "
+                  "FGMRES(60) in FP64 to 1e-10",
+           "sizes": [[c["kind"], c.get("nx", 2), c["n"]] for c in cfgs]}
     seq_its = None
     for mode in ("sequential", "batch", "batch_graph_tuned"):
         ts = time.perf_counter()
         ss = []
         for prob, _ in probs:
-            m = 2 * prob.n + 100
-            o = pm.default_options(restart=m, maxit=m, vcycle_graph=1 if "graph" in mode else 0)
+            o = pm.default_options(restart=60, maxit=600, smoother_fp32=99,
+                                   vcycle_graph=1 if "graph" in mode else 0)
             ss.append(pm.Solver(prob.levels, o, stream=torch.cuda.Stream()))
         torch.cuda.synchronize()
         setup = time.perf_counter() - ts
@@ -292,7 +297,7 @@ def main():
     ap.add_argument("--sweep-shapes", default=None,
                     help="comma-separated sweep launch shape per level instead of tuning "
                          "(as reported in config.sweep_shapes)")
-    ap.add_argument("--batch-count", type=int, default=32)
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: one solve cut at 40 FGMRES steps (the same "
                          "launches per V-cycle), then a 256 MiB copy kernel for calibration")

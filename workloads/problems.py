@@ -289,8 +289,8 @@ def coarse_net_params(C: int, H: int, seed: int, width: int = 3) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32).astype(np.float64)
 
 
-def batch_mix(seed: int = 4, count: int = 64, vdp_n=(256, 1024, 4096), burgers_nx=(32, 64, 128),
-              burgers_n=(256, 512)):
+def batch_mix(seed: int = 4, count: int = 64, vdp_n=(256, 1024, 4096), burgers_nx=(64, 128, 256),
+              burgers_n=(512, 1024, 2048, 4096)):
     """An uneven batch of independent systems (make_problem keyword sets).
 
     The first half are van der Pol with n drawn from vdp_n; the second half
