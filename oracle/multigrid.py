@@ -71,6 +71,16 @@ class OracleLevel:
     def bgs(self, r: np.ndarray) -> np.ndarray:
         return self.sgs_up.solve(r)
 
+    def smooth(self, kind: str, b: np.ndarray, y: np.ndarray, omega: float) -> np.ndarray:
+        """One smoothing sweep y + omega M^{-1}(b - A~ y) of the given kind."""
+        if kind == "jacobi":
+            return self.jacobi(b, y, omega)
+        if self.sgs_lo is None:
+            self.factor_sgs()
+        r = b - self.At @ y
+        d = {"fgs": self.fgs, "bgs": self.bgs, "sgs": self.sgs}[kind](r)
+        return y + omega * d
+
 
 @dataclass
 class MGOptions:
@@ -97,6 +107,10 @@ class MGOptions:
     next level and back up as two sequential steps, a 4-level V, F and W cycle
     take 6, 18 and 28 (the counts Sec. 6 gives); Hierarchy.calls records the
     levels entered.
+    smoother: the fixed-point iteration of the smoothing sweeps,
+    y <- y + omega M^{-1} (b - A~ y), with the splittings of Sec. 5.3.4:
+    "jacobi" M = D, "fgs" M = D + L (forward block Gauss-Seidel), "bgs"
+    M = D + L^T (backward), "sgs" M = (D + L) D^{-1} (D + L^T).
     """
     nu_pre: int = 2
     nu_post: int = 2
@@ -107,6 +121,7 @@ class MGOptions:
     omega: float = 0.5
     mu_scale: float = 2.0
     cycle: str = "V"
+    smoother: str = "jacobi"
 
 
 class Hierarchy:
@@ -156,7 +171,7 @@ class Hierarchy:
         o = self.opts
         y = np.zeros_like(b)
         for _ in range(o.nu_pre):                 # pre-smooth
-            y = lv.jacobi(b, y, o.omega)
+            y = lv.smooth(o.smoother, b, y, o.omega)
         r = b - lv.At @ y                         # residual
         rc = self.R[lev] @ r                      # restrict
         e = self._enter(lev + 1, rc, cycle)       # coarse correction
@@ -165,7 +180,7 @@ class Hierarchy:
             e = e + self._enter(lev + 1, rc2, "W" if cycle == "W" else "V")
         y = y + self.P[lev] @ e                   # interpolate and add
         for _ in range(o.nu_post):                # post-smooth
-            y = lv.jacobi(b, y, o.omega)
+            y = lv.smooth(o.smoother, b, y, o.omega)
         return y
 
     def _enter(self, lev: int, b: np.ndarray, cycle: str) -> np.ndarray:
