@@ -170,6 +170,21 @@ typedef struct {
                                   the step ratio 2 keeps its grid functions
                                   consistent; 1 is the printed, unscaled
                                   transfer.  > 0.                             */
+  int cycle;                   /* 0: V-cycle (Alg. 1 recursed).  1: W, 2: F
+                                  (the variants Sec. 6 reports trying): every
+                                  level above the coarsest makes a second
+                                  coarse correction from the coarse residual
+                                  the first leaves, W recursing with W in
+                                  both, F with F then V.                      */
+  int smoother;                /* smoothing sweep y <- y + omega M^{-1}(b - A~ y)
+                                  with the splittings of Sec. 5.3.4: 0 block
+                                  Jacobi (M = D), 1 forward block Gauss-
+                                  Seidel (M = D + L), 2 backward (D + L^T),
+                                  3 symmetric ((D + L) D^{-1} (D + L^T)).
+                                  Gauss-Seidel sweeps are sequential in time
+                                  (a chain of n dependent p x p products per
+                                  sweep) and run in FP64 (smoother_fp32 must
+                                  be 0).  Fixed at setup.                     */
 } pitmg_options;
 
 typedef struct {
@@ -188,8 +203,8 @@ typedef struct {
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
  * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
  * stall_steps 2, vcycle_graph 0, apply_from_sweep 1, pair_sweeps 1,
- * omega 0.5, mu_scale 2.  (omega = 1 with mu_scale = 1 is the cycle exactly
- * as printed.) */
+ * omega 0.5, mu_scale 2, cycle 0 (V), smoother 0 (block Jacobi).  (omega =
+ * 1 with mu_scale = 1 is the cycle exactly as printed.) */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and

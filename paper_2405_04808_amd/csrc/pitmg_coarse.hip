@@ -674,6 +674,59 @@ hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, 
   return hipGetLastError();
 }
 
+// Phi_k = N_k^T S_k^{-1} V_k and its transpose for every step of a level
+// (the block Gauss-Seidel smoothers' coupling, see pitmg_gs.hip):
+// W = G^{-1} N, X = G^{-1} V, Phi = W^T X, Phi^T = X^T W.
+hipError_t launch_phi_pair(const LevelView& L, double* W, double* X, double* Phi, double* PhiT,
+                           hipStream_t s) {
+  const int p = L.p, n = L.n;
+  const long long pp = (long long)p * p;
+  if (p == 64 || p == 128) {
+    const size_t lds = wg_gemm_lds_doubles(p) * sizeof(double);
+    const void* fns[2] = {p == 128 ? (const void*)k_gi_times_mfma<8> : (const void*)k_gi_times_mfma<4>,
+                          p == 128 ? (const void*)k_phi_mfma<8> : (const void*)k_phi_mfma<4>};
+    for (int f = 0; f < 2; ++f) {
+      hipError_t e = hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    if (p == 128) {
+      hipLaunchKernelGGL(k_gi_times_mfma<8>, dim3(n), dim3(kGemmThreads), lds, s, L, 0, W);
+      hipLaunchKernelGGL(k_gi_times_mfma<8>, dim3(n), dim3(kGemmThreads), lds, s, L, 1, X);
+      hipLaunchKernelGGL(k_phi_mfma<8>, dim3(n), dim3(kGemmThreads), lds, s, W, X, Phi);
+      hipLaunchKernelGGL(k_phi_mfma<8>, dim3(n), dim3(kGemmThreads), lds, s, X, W, PhiT);
+    } else {
+      hipLaunchKernelGGL(k_gi_times_mfma<4>, dim3(n), dim3(kGemmThreads), lds, s, L, 0, W);
+      hipLaunchKernelGGL(k_gi_times_mfma<4>, dim3(n), dim3(kGemmThreads), lds, s, L, 1, X);
+      hipLaunchKernelGGL(k_phi_mfma<4>, dim3(n), dim3(kGemmThreads), lds, s, W, X, Phi);
+      hipLaunchKernelGGL(k_phi_mfma<4>, dim3(n), dim3(kGemmThreads), lds, s, X, W, PhiT);
+    }
+    return hipGetLastError();
+  }
+  if (p >= 256 && p % 128 == 0) {
+    const int per = (p / 128) * (p / 128);
+    const size_t lds = Gemm128<double>::kLdsElems * sizeof(double);
+    const void* fns[2] = {(const void*)k_batched_gemm128<false>,
+                          (const void*)k_batched_gemm128<true>};
+    for (int f = 0; f < 2; ++f) {
+      hipError_t e = hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    const dim3 g(n * per), b(kGemmThreads);
+    hipLaunchKernelGGL(k_batched_gemm128<false>, g, b, lds, s, p, L.Gi, pp, L.N, L.sN, W);
+    hipLaunchKernelGGL(k_batched_gemm128<false>, g, b, lds, s, p, L.Gi, pp, L.V, L.sV, X);
+    hipLaunchKernelGGL(k_batched_gemm128<true>, g, b, lds, s, p, W, pp, X, pp, Phi);
+    hipLaunchKernelGGL(k_batched_gemm128<true>, g, b, lds, s, p, X, pp, W, pp, PhiT);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_gi_times, dim3(n), dim3(512), 0, s, L, 0, W);
+  hipLaunchKernelGGL(k_gi_times, dim3(n), dim3(512), 0, s, L, 1, X);
+  hipLaunchKernelGGL(k_phi, dim3(n), dim3(512), 0, s, p, W, X, Phi);
+  hipLaunchKernelGGL(k_phi, dim3(n), dim3(512), 0, s, p, X, W, PhiT);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemv_tri(const double* M, int nc, int p, int upper, const double* x, double* y,
                            hipStream_t s) {
   const long long rows = (long long)nc * p;

@@ -66,6 +66,13 @@ struct LevelBuf {
   double* y1 = nullptr;
   double* out = nullptr;             // result of this level's cycle (l >= 1)
   double* res = nullptr;             // explicit FP64 residual (finest level, FP32 smoother)
+  double* b2 = nullptr;              // W / F cycles: second coarse right-hand side (l >= 1)
+  double* e2 = nullptr;              //   and its correction
+  // block Gauss-Seidel smoothers (levels above the coarsest)
+  double* Phi = nullptr;             // [n][p][p] N_k^T S_k^{-1} V_k
+  double* PhiT = nullptr;            // [n][p][p] its transpose
+  double *gs_r = nullptr, *gs_t = nullptr, *gs_d = nullptr, *gs_h = nullptr;
+  double *hat_u = nullptr, *hat_m = nullptr;   // chain results (zero elsewhere)
   bool fp32 = false;                 // this level smooths in FP32
   float* N32 = nullptr;
   float* V32 = nullptr;
@@ -114,6 +121,7 @@ struct pitmg_handle {
   double *cC = nullptr, *cA = nullptr, *cD = nullptr, *cY = nullptr, *cY2 = nullptr,
          *czero = nullptr;           // coarse work vectors
   double *Phi = nullptr, *Pf = nullptr, *Qb = nullptr, *pscr = nullptr;
+  double* gs_scr = nullptr;          // W, X of the smoothers' Phi products (finest size)
   int* coarse_its = nullptr;         // device log of coarse step counts
   int coarse_log_cap = 0;
   int coarse_calls = 0;
@@ -349,6 +357,12 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "omega must be in (0, 1]");
   if (!(o.mu_scale > 0.0) || !std::isfinite(o.mu_scale))
     return set_err(h, PITMG_ERR_INVALID, "mu_scale must be > 0");
+  if (o.cycle < 0 || o.cycle > 2)
+    return set_err(h, PITMG_ERR_INVALID, "cycle must be 0 (V), 1 (W) or 2 (F)");
+  if (o.smoother < 0 || o.smoother > 3)
+    return set_err(h, PITMG_ERR_INVALID, "smoother must be 0 (Jacobi), 1 (FGS), 2 (BGS) or 3 (SGS)");
+  if (o.smoother != 0 && o.smoother_fp32 != 0)
+    return set_err(h, PITMG_ERR_INVALID, "the Gauss-Seidel smoothers run in FP64 only");
   return PITMG_OK;
 }
 
@@ -469,6 +483,18 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
       return launch_propagators(vc, h->pscr, h->Phi, h->Pf, h->Qb, h->stream);
     });
     if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
+  if (h->opt.smoother != 0) {
+    // Phi_k = N_k^T S_k^{-1} V_k and its transpose on every smoothed level
+    for (int l = 0; l + 1 < h->L; ++l) {
+      LevelBuf& b = h->lv[l];
+      LevelView v = view(h, l);
+      double* W = h->gs_scr;
+      double* X = h->gs_scr + (size_t)b.n * h->p * h->p;
+      int rc = timed(h, 0, [&] { return launch_phi_pair(v, W, X, b.Phi, b.PhiT, h->stream); });
+      if (rc) return rc;
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
   }
   return PITMG_OK;
@@ -594,7 +620,7 @@ int coarse_dispatch(pitmg_handle* h, const double* b, double* out) {
   return PITMG_OK;
 }
 
-int vcycle_level(pitmg_handle* h, int l, const double* b, double* out);
+int vcycle_level(pitmg_handle* h, int l, const double* b, double* out, int cyc);
 
 // A two-sweep launch whose neighbour wait ran out leaves a nonzero word in
 // the handle: report it (and clear it) as the error of the call it ends.
@@ -622,7 +648,7 @@ int capture_vcycle(pitmg_handle* h) {
   drop_graph(h);
   HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
   const int K = h->opt.coarse_fixed_its > 0 ? h->opt.coarse_fixed_its : h->coarse_k;
-  const int rc = vcycle_level(h, 0, h->g_in, h->g_out);
+  const int rc = vcycle_level(h, 0, h->g_in, h->g_out, h->opt.cycle);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (rc) {
@@ -644,7 +670,7 @@ int vcycle_top(pitmg_handle* h, const double* r, double* e) {
   h->vcycles++;
   const bool graph = o.vcycle_graph && h->stream != nullptr && !h->prof && o.nu_post > 0 &&
                      o.coarse_mode == 0 && h->pair_count >= h->pair_cap;
-  if (!graph) return vcycle_level(h, 0, r, e);
+  if (!graph) return vcycle_level(h, 0, r, e, h->opt.cycle);
   const long long len = h->lv[0].len;
   int rc;
   if (!h->g_in) {
@@ -682,12 +708,149 @@ hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, cons
   return e;
 }
 
-int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
+// d = (D + L)^{-1} r (forward) or (D + L^T)^{-1} r (backward) on level l:
+// the block solves of D^{-1} r, the chain of the coupled slot through Phi_k,
+// then the block solves with the chain as the coupling iterate
+// (pitmg_gs.hip).
+int gs_solve(pitmg_handle* h, int l, bool forward, const double* r, double* d) {
+  LevelBuf& B = h->lv[l];
+  LevelView v1 = view(h, l);
+  v1.omega = 1.0;
+  const int var = h->opt.transfer_variant;
+  double* hat = forward ? B.hat_u : B.hat_m;
+  int rc = timed_kernel(h, 1, [&] {
+    return launch_jacobi(v1, r, nullptr, nullptr, var, B.gs_t, h->stream);
+  });
+  if (!rc)
+    rc = timed_kernel(h, 1, [&] {
+      return launch_gs_chain(h->p, h->q, B.n, forward ? B.PhiT : B.Phi, B.gs_t, hat, !forward,
+                             h->stream);
+    });
+  if (!rc)
+    rc = timed_kernel(h, 1, [&] {
+      return launch_jacobi(v1, r, hat, nullptr, var, d, h->stream);
+    });
+  return rc;
+}
+
+// One Gauss-Seidel smoothing sweep on level l (options.smoother 1-3):
+// y_out = y_in + w M^{-1}(b - A~ y_in), M = D + L (FGS), D + L^T (BGS), or
+// the symmetric sweep (forward, then backward from the forward result,
+// equal to M = (D + L) D^{-1} (D + L^T)); y_in NULL = 0; y_out != y_in.
+int gs_sweep(pitmg_handle* h, int l, const double* b, const double* y_in, double* y_out) {
+  LevelBuf& B = h->lv[l];
+  LevelView v = view(h, l);
+  const double w = v.omega;
+  const long long len = B.len;
+  const int kind = h->opt.smoother;
+  int rc = 0;
+  const double* r = b;
+  if (y_in) {
+    rc = timed(h, 2, [&] { return launch_apply(v, y_in, b, -1.0, 1.0, B.gs_r, h->stream); });
+    if (rc) return rc;
+    r = B.gs_r;
+  }
+  // ys = y_in + M^{-1} r into gs_h (the symmetric sweep's second half from
+  // the first half's result), or the correction alone into gs_d
+  double* corr = B.gs_d;
+  if (kind == 3) {
+    if ((rc = gs_solve(h, l, true, r, B.gs_d))) return rc;
+    if (y_in) {
+      HIPCHK(h, hipMemcpyAsync(B.gs_h, y_in, len * 8, hipMemcpyDeviceToDevice, h->stream));
+      rc = timed(h, 3, [&] { return launch_axpby(B.gs_h, B.gs_d, 1.0, 1.0, len, h->stream); });
+    } else {
+      HIPCHK(h, hipMemcpyAsync(B.gs_h, B.gs_d, len * 8, hipMemcpyDeviceToDevice, h->stream));
+    }
+    if (!rc) rc = timed(h, 2, [&] {
+      return launch_apply(v, B.gs_h, b, -1.0, 1.0, B.gs_r, h->stream);
+    });
+    if (!rc) rc = gs_solve(h, l, false, B.gs_r, B.gs_d);
+    if (!rc) rc = timed(h, 3, [&] {
+      return launch_axpby(B.gs_h, B.gs_d, 1.0, 1.0, len, h->stream);
+    });
+    if (rc) return rc;
+    // y_out = (1 - w) y_in + w ys
+    if (!y_in) return timed(h, 3, [&] { return launch_scale(y_out, B.gs_h, w, len, h->stream); });
+    HIPCHK(h, hipMemcpyAsync(y_out, y_in, len * 8, hipMemcpyDeviceToDevice, h->stream));
+    return timed(h, 3, [&] { return launch_axpby(y_out, B.gs_h, w, 1.0 - w, len, h->stream); });
+  }
+  if ((rc = gs_solve(h, l, kind == 1, r, corr))) return rc;
+  if (!y_in) return timed(h, 3, [&] { return launch_scale(y_out, corr, w, len, h->stream); });
+  HIPCHK(h, hipMemcpyAsync(y_out, y_in, len * 8, hipMemcpyDeviceToDevice, h->stream));
+  return timed(h, 3, [&] { return launch_axpby(y_out, corr, w, 1.0, len, h->stream); });
+}
+
+// The coarse correction of level l into C.out: one cycle of level l + 1
+// (V), or two, the second from the residual the first leaves (W: both W;
+// F: F, then V).
+int coarse_correction(pitmg_handle* h, int l, int cyc) {
+  LevelBuf& C = h->lv[l + 1];
+  int rc = vcycle_level(h, l + 1, C.b, C.out, cyc);
+  if (rc || cyc == 0) return rc;
+  LevelView vc = view(h, l + 1);
+  vc.fp32 = 0;
+  rc = timed(h, 2, [&] { return launch_apply(vc, C.out, C.b, -1.0, 1.0, C.b2, h->stream); });
+  if (!rc) rc = vcycle_level(h, l + 1, C.b2, C.e2, cyc == 1 ? 1 : 0);
+  if (!rc)
+    rc = timed(h, 3, [&] { return launch_axpby(C.out, C.e2, 1.0, 1.0, C.len, h->stream); });
+  return rc;
+}
+
+// MG_l(b) with Gauss-Seidel smoothing: explicit residual, restriction,
+// coarse correction, interpolation, explicit sweeps.
+int vcycle_level_gs(pitmg_handle* h, int l, const double* b, double* out, int cyc) {
+  const pitmg_options& o = h->opt;
+  const int var = o.transfer_variant;
+  LevelView v = view(h, l);
+  LevelBuf& B = h->lv[l];
+  LevelBuf& C = h->lv[l + 1];
+  double* bufs[2] = {B.y0, B.y1};
+  double* y = nullptr;
+  int rc = 0;
+  for (int s = 0; s < o.nu_pre; ++s) {
+    double* dst = bufs[s & 1];
+    if ((rc = gs_sweep(h, l, b, y, dst))) return rc;
+    y = dst;
+  }
+  if (!y) {
+    rc = timed(h, 3, [&] {
+      return launch_restrict(h->p, h->q, v.n, b, var, v.mu_scale, C.b, h->stream);
+    });
+  } else {
+    double* res = y == bufs[0] ? bufs[1] : bufs[0];
+    rc = timed(h, 2, [&] { return launch_apply(v, y, b, -1.0, 1.0, res, h->stream); });
+    if (!rc)
+      rc = timed(h, 3, [&] {
+        return launch_restrict(h->p, h->q, v.n, res, var, v.mu_scale, C.b, h->stream);
+      });
+  }
+  if (rc) return rc;
+  if ((rc = coarse_correction(h, l, cyc))) return rc;
+  if (!y) {
+    y = bufs[0];
+    if ((rc = timed(h, 3, [&] { return launch_fill(y, 0.0, B.len, h->stream); }))) return rc;
+  }
+  rc = timed(h, 3, [&] {
+    return launch_interp_add(h->p, h->q, v.n, C.out, var, v.mu_scale, y, h->stream);
+  });
+  if (rc) return rc;
+  for (int s = 0; s < o.nu_post; ++s) {
+    double* dst = s == o.nu_post - 1 ? out : (y == bufs[0] ? bufs[1] : bufs[0]);
+    if ((rc = gs_sweep(h, l, b, y, dst))) return rc;
+    y = dst;
+  }
+  if (o.nu_post == 0)
+    HIPCHK(h, hipMemcpyAsync(out, y, B.len * 8, hipMemcpyDeviceToDevice, h->stream));
+  return PITMG_OK;
+}
+
+int vcycle_level(pitmg_handle* h, int l, const double* b, double* out, int cyc) {
   const pitmg_options& o = h->opt;
   const int var = o.transfer_variant;
   LevelView v = view(h, l);
   if (l == 0) h->top_prev = nullptr;
   if (l == h->L - 1) return coarse_dispatch(h, b, out);
+  if (o.smoother != 0) return vcycle_level_gs(h, l, b, out, cyc);
   LevelBuf& B = h->lv[l];
   LevelBuf& C = h->lv[l + 1];
   double* bufs[2] = {B.y0, B.y1};
@@ -749,7 +912,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out) {
       });
   }
   if (rc) return rc;
-  rc = vcycle_level(h, l + 1, C.b, C.out);
+  rc = coarse_correction(h, l, cyc);
   if (rc) return rc;
   if (o.nu_post == 0) {
     if (ycur)
@@ -1212,6 +1375,8 @@ void pitmg_default_options(pitmg_options* o) {
   o->pair_sweeps = 1;
   o->omega = 0.5;
   o->mu_scale = 2.0;
+  o->cycle = 0;
+  o->smoother = 0;
 }
 
 int pitmg_autotune(pitmg_handle* h, int* cfg) {
@@ -1384,6 +1549,21 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
     if (l > 0) {
       if ((rc = dalloc(h, (void**)&b.b, b.len * 8))) return fail(rc);
       if ((rc = dalloc(h, (void**)&b.out, b.len * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.b2, b.len * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.e2, b.len * 8))) return fail(rc);
+    }
+    if (o.smoother != 0 && !coarsest) {
+      double** gs[6] = {&b.gs_r, &b.gs_t, &b.gs_d, &b.gs_h, &b.hat_u, &b.hat_m};
+      for (int i = 0; i < 6; ++i)
+        if ((rc = dalloc(h, (void**)gs[i], b.len * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.Phi, (size_t)b.n * pp * 8))) return fail(rc);
+      if ((rc = dalloc(h, (void**)&b.PhiT, (size_t)b.n * pp * 8))) return fail(rc);
+      // the chains write only the u (hat_u) or mu (hat_m) slots
+      if (launch_fill(b.hat_u, 0.0, b.len, h->stream) != hipSuccess ||
+          launch_fill(b.hat_m, 0.0, b.len, h->stream) != hipSuccess)
+        return fail(set_err(h, PITMG_ERR_HIP, "fill of the Gauss-Seidel buffers failed"));
+      if (l == 0 && (rc = dalloc(h, (void**)&h->gs_scr, (size_t)2 * b.n * pp * 8)))
+        return fail(rc);
     }
     if (!coarsest) {
       if ((rc = dalloc(h, (void**)&b.y0, b.len * 8))) return fail(rc);
@@ -1507,6 +1687,8 @@ int pitmg_set_options(pitmg_handle* h, const pitmg_options* opt) {
     return set_err(h, PITMG_ERR_INVALID, "restart / coarse steps exceed the setup capacity");
   if (opt->smoother_fp32 != h->opt.smoother_fp32)
     return set_err(h, PITMG_ERR_INVALID, "smoother_fp32 is fixed at setup");
+  if (opt->smoother != h->opt.smoother)
+    return set_err(h, PITMG_ERR_INVALID, "smoother is fixed at setup");
   h->opt = *opt;
   drop_graph(h);            // the captured cycle depends on the options
   return PITMG_OK;
@@ -1758,11 +1940,22 @@ void pitmg_destroy(pitmg_handle* h) {
     release(b.y1);
     release(b.out);
     release(b.res);
+    release(b.b2);
+    release(b.e2);
+    release(b.Phi);
+    release(b.PhiT);
+    release(b.gs_r);
+    release(b.gs_t);
+    release(b.gs_d);
+    release(b.gs_h);
+    release(b.hat_u);
+    release(b.hat_m);
     release(b.N32);
     release(b.V32);
     release(b.Z32);
     release(b.Gi32);
   }
+  release(h->gs_scr);
   release(h->Vk);
   release(h->Zk);
   release(h->w);

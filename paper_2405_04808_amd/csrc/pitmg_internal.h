@@ -242,6 +242,16 @@ hipError_t launch_coarse_finish(const LevelView& L, double* x, double tol, int f
 // scratch: 2 n p^2 doubles; P and Q must be zero-filled beforehand.
 hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, double* P,
                               double* Q, hipStream_t s);
+// Phi_k = N_k^T S_k^{-1} V_k and Phi_k^T for every step of level L (W, X:
+// scratch of n p^2 doubles each).
+hipError_t launch_phi_pair(const LevelView& L, double* W, double* X, double* Phi, double* PhiT,
+                           hipStream_t s);
+// The chain of a block Gauss-Seidel substitution (pitmg_gs.hip): from
+// t = D^{-1} r (type-major), hat's u slots (forward, M = Phi^T) or mu slots
+// (backward, M = Phi) receive the substituted values; its other slots are
+// not written.
+hipError_t launch_gs_chain(int p, int q, int n, const double* M, const double* t, double* hat,
+                           int backward, hipStream_t s);
 hipError_t launch_gemv_tri(const double* M, int nc, int p, int upper, const double* x, double* y,
                            hipStream_t s);
 hipError_t launch_add(double* z, const double* a, const double* d, long long len, hipStream_t s);

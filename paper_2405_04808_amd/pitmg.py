@@ -46,7 +46,9 @@ class pitmg_options(C.Structure):
                 ("apply_from_sweep", C.c_int),
                 ("pair_sweeps", C.c_int),
                 ("omega", C.c_double),
-                ("mu_scale", C.c_double)]
+                ("mu_scale", C.c_double),
+                ("cycle", C.c_int),
+                ("smoother", C.c_int)]
 
 
 class pitmg_stats(C.Structure):

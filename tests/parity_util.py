@@ -39,7 +39,8 @@ def mg_opts(o):
     return MGOptions(nu_pre=o.nu_pre, nu_post=o.nu_post, coarse_tol=o.coarse_tol,
                      coarse_maxit=o.coarse_maxit, coarse_fixed_its=o.coarse_fixed_its,
                      transfer_variant=o.transfer_variant, omega=o.omega,
-                     mu_scale=o.mu_scale)
+                     mu_scale=o.mu_scale, cycle="VWF"[o.cycle],
+                     smoother=("jacobi", "fgs", "bgs", "sgs")[o.smoother])
 
 
 def omega_at(o, lev, n_levels):
