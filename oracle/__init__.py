@@ -14,9 +14,12 @@ What it computes (arXiv 2405.04808):
   * krylov.py   -- right-preconditioned GMRES and flexible GMRES (Saad 1993),
                    written out with modified Gram-Schmidt and a dense
                    least-squares solve of the Hessenberg problem;
-  * multigrid.py-- block Jacobi (eq. (jacobi)), symmetric block Gauss-Seidel
-                   (Sec. 5.3.4), the recursive V-cycle (Alg. 1) and the
-                   preconditioned outer solve (Sec. 6).
+  * multigrid.py-- block Jacobi (eq. (jacobi)), forward / backward /
+                   symmetric block Gauss-Seidel (Sec. 5.3.4), the recursive
+                   V-cycle (Alg. 1) with its W and F variants, and the
+                   preconditioned outer solve (Sec. 6);
+  * unlifted.py -- the system without virtual variables (Fig. 2) and the
+                   lift / project maps that carry the lifted cycle to it.
 
 Everything is assembled scipy.sparse matrices and SuperLU factorisations of
 the block parts; no Schur complement or other derived block algebra is used,
