@@ -279,6 +279,37 @@ def batch_leg(pm, torch, count=64):
     return out
 
 
+def variants_leg(pm, torch, prob, db, wl, reps=2):
+    """The cycle and smoother variants of Sec. 5.3.4 and Sec. 6 on the
+    benchmark system: FGMRES steps and time per solve (blocks already
+    factored; the Gauss-Seidel handles also form N_k^T S_k^{-1} V_k at
+    setup, outside the timing)."""
+    out = {}
+    names = {0: "jacobi", 1: "fgs", 2: "bgs", 3: "sgs"}
+    for cycle, smoother in ((0, 0), (1, 0), (2, 0), (0, 1), (0, 2), (0, 3), (1, 3)):
+        key = f"{'VWF'[cycle]}-{names[smoother]}"
+        s_ = pm.Solver(prob.levels, pm.default_options(restart=wl["restart"], maxit=wl["maxit"],
+                                                        cycle=cycle, smoother=smoother),
+                       device="cuda:0")
+        x_ = s_.empty(0)
+        _, st, _ = s_.solve(db, tol=1e-10, out=x_)            # warm-up
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(reps):
+            _, st, rc = s_.solve(db, tol=1e-10, out=x_)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ta) * 1e3 / reps
+        out[key] = {"fgmres_iters": st["iters"], "ms_per_solve": round(ms, 2),
+                    "ms_per_fgmres_step": round(ms / max(st["iters"], 1), 3),
+                    "relres_true": st["relres_true"], "converged": st["converged"] == 1}
+        print(f"# variant {key}: {st['iters']} steps, {ms:.1f} ms", file=sys.stderr, flush=True)
+        s_.close()
+    out["note"] = ("V/W/F cycle with block Jacobi (jacobi), forward / backward / symmetric "
+                   "block Gauss-Seidel (fgs / bgs / sgs) smoothing, omega 1/2, V(2,2); "
+                   "solve only (no refactor); the Gauss-Seidel sweeps are chains in time")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +323,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-coarse-correction leg (pairs, training, ablation)")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the cycle / smoother variants leg")
     ap.add_argument("--no-setup6", action="store_true",
                     help="skip the refactor + 6 solves measurement")
     ap.add_argument("--sweep-shapes", default=None,
@@ -305,6 +338,7 @@ def main():
     if args.counters:
         args.steps, args.warmup = 1, 0
         args.no_cpu_baseline = args.no_profile = args.no_fp32 = args.no_learned = True
+        args.no_variants = True
         args.no_batch = True
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
@@ -503,6 +537,10 @@ def main():
     if not args.no_learned and args.workload == "burgers128":
         learned = learned_leg(pm, torch, wl)
 
+    variants = None
+    if not args.no_variants and args.workload == "burgers128":
+        variants = variants_leg(pm, torch, prob, db, wl)
+
     batch = None
     if not args.no_batch:
         batch = batch_leg(pm, torch, count=args.batch_count)
@@ -534,6 +572,7 @@ def main():
         "cpu_baseline": cpu,
         "vcycle_hbm": vc,
         "fp32_smoother": fp32,
+        "cycle_variants": variants,
         "learned_coarse": learned,
         "uneven_batch": batch,
         "kernel_ms": kern,

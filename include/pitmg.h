@@ -185,6 +185,16 @@ typedef struct {
                                   (a chain of n dependent p x p products per
                                   sweep) and run in FP64 (smoother_fp32 must
                                   be 0).  Fixed at setup.                     */
+  int unlifted;                /* 1: the handle also solves the augmented system
+                                  without virtual variables (Fig. 2, B = dF;
+                                  pitmg_unlifted_*).  Its hierarchy is then the
+                                  lifted system of the blocks sqrt2 N_k,
+                                  sqrt2 V_k, Z~_k (scaled on the device into
+                                  the handle's own copies), whose exact solve
+                                  read through the lift / project maps is the
+                                  unlifted inverse; the lifted entry points
+                                  act on that scaled system.  Fixed at
+                                  setup.  0: the lifted system only.          */
 } pitmg_options;
 
 typedef struct {
@@ -203,8 +213,8 @@ typedef struct {
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
  * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
  * stall_steps 2, vcycle_graph 0, apply_from_sweep 1, pair_sweeps 1,
- * omega 0.5, mu_scale 2, cycle 0 (V), smoother 0 (block Jacobi).  (omega =
- * 1 with mu_scale = 1 is the cycle exactly as printed.) */
+ * omega 0.5, mu_scale 2, cycle 0 (V), smoother 0 (block Jacobi), unlifted
+ * 0.  (omega = 1 with mu_scale = 1 is the cycle exactly as printed.) */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and
@@ -291,6 +301,22 @@ int pitmg_vcycle(pitmg_handle* h, const double* r, double* e);
  * non-finite residual. */
 int pitmg_fgmres_solve(pitmg_handle* h, const double* rhs, double* x,
                        double tol, int use_x0, pitmg_stats* st);
+
+/* The augmented system without virtual variables (Sec. 5, Fig. 2: the
+ * constraint Jacobian B = dF of the theta-method steps, blocks K_k = N_k,
+ * C_k = V_k, B_k = Z~_k of the lifted system at v = u), on type-major device
+ * vectors [u_1..u_n | z_1..z_n | lambda_1..lambda_n] of length (2p+q) n.
+ * Both need a handle set up with options.unlifted = 1 (else
+ * PITMG_ERR_INVALID).  y = A x (x and y must not overlap). */
+int pitmg_unlifted_apply(pitmg_handle* h, const double* x, double* y);
+/* FGMRES on A x = rhs preconditioned by one lifted cycle carried through
+ * the maps E r = (u/sqrt2, u/sqrt2, z, lambda, 0) and E^T y = ((u+v)/sqrt2,
+ * z, lambda): M r = E^T MG(E r), which is A^{-1} when the cycle is exact
+ * (the paper names lift / project preconditioning without giving maps;
+ * these are the exact ones for the scaled hierarchy).  Arguments, stopping
+ * rule, stats and return codes as pitmg_fgmres_solve. */
+int pitmg_unlifted_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol,
+                                int use_x0, pitmg_stats* st);
 
 /* Solve count independent systems, one handle each (distinct handles; give
  * each its own stream at setup for the solves to overlap on the device).

@@ -122,6 +122,7 @@ struct pitmg_handle {
          *czero = nullptr;           // coarse work vectors
   double *Phi = nullptr, *Pf = nullptr, *Qb = nullptr, *pscr = nullptr;
   double* gs_scr = nullptr;          // W, X of the smoothers' Phi products (finest size)
+  double *ul_in = nullptr, *ul_out = nullptr;   // lifted images in the unlifted solve
   int* coarse_its = nullptr;         // device log of coarse step counts
   int coarse_log_cap = 0;
   int coarse_calls = 0;
@@ -363,6 +364,8 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "smoother must be 0 (Jacobi), 1 (FGS), 2 (BGS) or 3 (SGS)");
   if (o.smoother != 0 && o.smoother_fp32 != 0)
     return set_err(h, PITMG_ERR_INVALID, "the Gauss-Seidel smoothers run in FP64 only");
+  if (o.unlifted != 0 && o.unlifted != 1)
+    return set_err(h, PITMG_ERR_INVALID, "unlifted must be 0 or 1");
   return PITMG_OK;
 }
 
@@ -414,6 +417,16 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
       b.N = b.N_own;
       b.V = b.V_own;
       b.Z = b.Z_own;
+    }
+    if (h->opt.unlifted) {
+      // the unlifted system's lifted hierarchy holds sqrt2 N_k and sqrt2 V_k
+      // (pitmg_unlifted.hip): scaled into the handle's own copies
+      const double r2 = std::sqrt(2.0);
+      if (launch_scale(b.N_own, b.N, r2, cN, h->stream) != hipSuccess ||
+          launch_scale(b.V_own, b.V, r2, cV, h->stream) != hipSuccess)
+        return set_err(h, PITMG_ERR_HIP, "scaling of the state blocks failed");
+      b.N = b.N_own;
+      b.V = b.V_own;
     }
   }
   const int big = INT_MAX;
@@ -1024,8 +1037,32 @@ struct FgmresRun {
   int status = PITMG_OK;
   pitmg_stats S{};
 
+  bool unl = false;                 // the system without virtual variables
+
   double* Vp(int i) const { return h->Vk + (size_t)i * len; }
   double* Zp(int i) const { return h->Zk + (size_t)i * len; }
+
+  // out = bb * b + a * (system) xin  (b may be NULL when bb = 0)
+  int apply_sys(const double* xin, const double* b, double a, double bb, double* out) {
+    if (unl)
+      return timed(h, 2, [&] {
+        return launch_unlifted_apply(v0, 1.0 / std::sqrt(2.0), xin, b, a, bb, out, h->stream);
+      });
+    return timed(h, 2, [&] { return launch_apply(v0, xin, b, a, bb, out, h->stream); });
+  }
+
+  // out = the preconditioner applied to in: one cycle, carried to the
+  // unlifted system by the lift / project maps
+  int precondition(const double* in, double* out) {
+    if (!unl) return vcycle_top(h, in, out);
+    int rc = timed(h, 3, [&] { return launch_lift(h->p, h->q, h->n, in, h->ul_in, h->stream); });
+    if (!rc) rc = vcycle_top(h, h->ul_in, h->ul_out);
+    if (!rc)
+      rc = timed(h, 3, [&] {
+        return launch_project(h->p, h->q, h->n, h->ul_out, out, h->stream);
+      });
+    return rc;
+  }
 
   int start(pitmg_handle* hh, const double* b, double* xx, double tl, int x0) {
     h = hh;
@@ -1038,7 +1075,7 @@ struct FgmresRun {
     tol = tl;
     use_x0 = x0;
     t0 = std::chrono::steady_clock::now();
-    len = h->lv[0].len;
+    len = unl ? (2LL * h->p + h->q) * h->n : h->lv[0].len;
     m = h->opt.restart;
     maxit = h->opt.maxit;
     net0 = h->net_calls;
@@ -1107,10 +1144,7 @@ struct FgmresRun {
             ph = kStepA;
             break;
           }
-          if ((rc = timed(h, 2, [&] {
-                 return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream);
-               })))
-            return rc;
+          if ((rc = apply_sys(x, rhs, -1.0, 1.0, h->r))) return rc;
           if ((rc = dots(h, nullptr, 0, h->r, nullptr, len))) return rc;
           ph = kAfterResid;
           return wait_coef(1);
@@ -1135,8 +1169,10 @@ struct FgmresRun {
           ph = kStepA;
           break;
         case kStepA:
-          if ((rc = vcycle_top(h, Vp(j), Zp(j)))) return rc;
-          if (h->opt.apply_from_sweep && h->top_prev) {
+          if ((rc = precondition(Vp(j), Zp(j)))) return rc;
+          if (unl) {
+            if ((rc = apply_sys(Zp(j), nullptr, 1.0, 0.0, h->w))) return rc;
+          } else if (h->opt.apply_from_sweep && h->top_prev) {
             if ((rc = timed(h, 2, [&] {
                    return launch_apply_identity(h->p, h->q, h->n, Vp(j), h->top_prev, Zp(j),
                                                 h->w, h->stream);
@@ -1292,10 +1328,7 @@ struct FgmresRun {
             ph = kFinish;
             break;
           }
-          if ((rc = timed(h, 2, [&] {
-                 return launch_apply(v0, x, rhs, -1.0, 1.0, h->r, h->stream);
-               })))
-            return rc;
+          if ((rc = apply_sys(x, rhs, -1.0, 1.0, h->r))) return rc;
           if ((rc = dots(h, nullptr, 0, h->r, nullptr, len))) return rc;
           ph = kAfterFinal;
           return wait_coef(1);
@@ -1377,6 +1410,7 @@ void pitmg_default_options(pitmg_options* o) {
   o->mu_scale = 2.0;
   o->cycle = 0;
   o->smoother = 0;
+  o->unlifted = 0;
 }
 
 int pitmg_autotune(pitmg_handle* h, int* cfg) {
@@ -1526,12 +1560,14 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
     LevelBuf& b = h->lv[l];
     b.n = h->n >> l;
     b.len = (4LL * h->p + h->q) * b.n;
-    if (!pb->blocks_on_device) {
+    if (!pb->blocks_on_device || o.unlifted) {
+      // own copies: host blocks, or the scaled state blocks of the unlifted
+      // system's lifted hierarchy
       const long long cN = (pb->N_stride ? b.n : 1) * pp, cV = (pb->V_stride ? b.n : 1) * pp,
                       cZ = (pb->Z_stride ? b.n : 1) * pq;
       if ((rc = dalloc(h, (void**)&b.N_own, cN * 8))) return fail(rc);
       if ((rc = dalloc(h, (void**)&b.V_own, cV * 8))) return fail(rc);
-      if ((rc = dalloc(h, (void**)&b.Z_own, cZ * 8))) return fail(rc);
+      if (!pb->blocks_on_device && (rc = dalloc(h, (void**)&b.Z_own, cZ * 8))) return fail(rc);
     }
     const bool coarsest = l == h->L - 1;
     b.fp32 = l < o.smoother_fp32 && !coarsest;
@@ -1590,6 +1626,10 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   if ((rc = dalloc(h, (void**)&h->Zk, (size_t)m * len * 8))) return fail(rc);
   if ((rc = dalloc(h, (void**)&h->w, len * 8))) return fail(rc);
   if ((rc = dalloc(h, (void**)&h->r, len * 8))) return fail(rc);
+  if (o.unlifted) {
+    if ((rc = dalloc(h, (void**)&h->ul_in, len * 8))) return fail(rc);
+    if ((rc = dalloc(h, (void**)&h->ul_out, len * 8))) return fail(rc);
+  }
   const int nb = krylov_slices(len) > krylov_partial_blocks(len) ? krylov_slices(len)
                                                                    : krylov_partial_blocks(len);
   if ((rc = dalloc(h, (void**)&h->partial, (size_t)nb * (2 * m + 4) * 8))) return fail(rc);
@@ -1689,6 +1729,8 @@ int pitmg_set_options(pitmg_handle* h, const pitmg_options* opt) {
     return set_err(h, PITMG_ERR_INVALID, "smoother_fp32 is fixed at setup");
   if (opt->smoother != h->opt.smoother)
     return set_err(h, PITMG_ERR_INVALID, "smoother is fixed at setup");
+  if (opt->unlifted != h->opt.unlifted)
+    return set_err(h, PITMG_ERR_INVALID, "unlifted is fixed at setup");
   h->opt = *opt;
   drop_graph(h);            // the captured cycle depends on the options
   return PITMG_OK;
@@ -1699,6 +1741,30 @@ int pitmg_apply(pitmg_handle* h, int level, const double* x, double* y) {
   if (level < 0 || level >= h->L) return set_err(h, PITMG_ERR_INVALID, "bad level");
   LevelView v = view(h, level);
   return timed(h, 2, [&] { return launch_apply(v, x, nullptr, 1.0, 0.0, y, h->stream); });
+}
+
+int pitmg_unlifted_apply(pitmg_handle* h, const double* x, double* y) {
+  if (!h || !x || !y) return PITMG_ERR_INVALID;
+  if (!h->opt.unlifted)
+    return set_err(h, PITMG_ERR_INVALID, "the handle was not set up with unlifted = 1");
+  LevelView v = view(h, 0);
+  return timed(h, 2, [&] {
+    return launch_unlifted_apply(v, 1.0 / std::sqrt(2.0), x, nullptr, 1.0, 0.0, y, h->stream);
+  });
+}
+
+int pitmg_unlifted_fgmres_solve(pitmg_handle* h, const double* rhs, double* x, double tol,
+                                int use_x0, pitmg_stats* st) {
+  if (!h) return PITMG_ERR_INVALID;
+  if (!h->opt.unlifted)
+    return set_err(h, PITMG_ERR_INVALID, "the handle was not set up with unlifted = 1");
+  FgmresRun run;
+  run.unl = true;
+  int rc = run.start(h, rhs, x, tol, use_x0);
+  if (rc) return rc;
+  rc = run_to_end(run);
+  if (rc >= 0 && st) *st = run.S;
+  return rc;
 }
 
 int pitmg_jacobi_sweep(pitmg_handle* h, int level, const double* b, const double* y_in,
@@ -1956,6 +2022,8 @@ void pitmg_destroy(pitmg_handle* h) {
     release(b.Gi32);
   }
   release(h->gs_scr);
+  release(h->ul_in);
+  release(h->ul_out);
   release(h->Vk);
   release(h->Zk);
   release(h->w);

@@ -252,6 +252,14 @@ hipError_t launch_phi_pair(const LevelView& L, double* W, double* X, double* Phi
 // not written.
 hipError_t launch_gs_chain(int p, int q, int n, const double* M, const double* t, double* hat,
                            int backward, hipStream_t s);
+// The system without virtual variables (pitmg_unlifted.hip): out = beta b +
+// alpha A x on unlifted type-major vectors [u | z | lambda] of L's size, the
+// N and V blocks of L multiplied by bscale; y = E r and x = E^T y.
+hipError_t launch_unlifted_apply(const LevelView& L, double bscale, const double* x,
+                                 const double* b, double alpha, double beta, double* out,
+                                 hipStream_t s);
+hipError_t launch_lift(int p, int q, int n, const double* r, double* y, hipStream_t s);
+hipError_t launch_project(int p, int q, int n, const double* y, double* x, hipStream_t s);
 hipError_t launch_gemv_tri(const double* M, int nc, int p, int upper, const double* x, double* y,
                            hipStream_t s);
 hipError_t launch_add(double* z, const double* a, const double* d, long long len, hipStream_t s);

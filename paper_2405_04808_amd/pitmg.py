@@ -48,7 +48,8 @@ class pitmg_options(C.Structure):
                 ("omega", C.c_double),
                 ("mu_scale", C.c_double),
                 ("cycle", C.c_int),
-                ("smoother", C.c_int)]
+                ("smoother", C.c_int),
+                ("unlifted", C.c_int)]
 
 
 class pitmg_stats(C.Structure):
@@ -91,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "pitmg_coarse_solve_noalloc": (i, [vp, vp, vp, C.POINTER(i)]),
         "pitmg_vcycle": (i, [vp, vp, vp]),
         "pitmg_fgmres_solve": (i, [vp, vp, vp, d, i, C.POINTER(pitmg_stats)]),
+        "pitmg_unlifted_apply": (i, [vp, vp, vp]),
+        "pitmg_unlifted_fgmres_solve": (i, [vp, vp, vp, d, i, C.POINTER(pitmg_stats)]),
         "pitmg_fgmres_solve_batch": (i, [C.POINTER(vp), i, C.POINTER(vp), C.POINTER(vp), d, i,
                                          C.POINTER(pitmg_stats), C.POINTER(i)]),
         "pitmg_profile_enable": (i, [vp, i]),
@@ -290,6 +293,34 @@ class Solver:
         self._order()
         rc = self._check(self.lib.pitmg_fgmres_solve(self.h, _ptr(b), _ptr(x), float(tol),
                                                      use_x0, C.byref(st)))
+        return x, st.as_dict(), rc
+
+    # -- the system without virtual variables (options.unlifted = 1) -----------
+    def unlifted_len(self) -> int:
+        return (2 * self.p + self.q) * self.n
+
+    def unlifted_apply(self, x, out=None):
+        """y = A x for the unlifted system (Fig. 2), vectors [u | z | lambda]."""
+        y = out if out is not None else self.torch.empty(self.unlifted_len(), dtype=self.torch.float64,
+                                                         device=self.device)
+        self._order()
+        self._check(self.lib.pitmg_unlifted_apply(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def unlifted_solve(self, b, tol: float = 1e-10, x0=None, out=None):
+        """FGMRES on the unlifted system with the lifted cycle through the
+        lift / project maps; returns (x, stats dict, status code >= 0)."""
+        x = out if out is not None else self.torch.empty(self.unlifted_len(),
+                                                         dtype=self.torch.float64,
+                                                         device=self.device)
+        use_x0 = 0
+        if x0 is not None:
+            x.copy_(x0)
+            use_x0 = 1
+        st = pitmg_stats()
+        self._order()
+        rc = self._check(self.lib.pitmg_unlifted_fgmres_solve(self.h, _ptr(b), _ptr(x),
+                                                              float(tol), use_x0, C.byref(st)))
         return x, st.as_dict(), rc
 
     # -- profiling --------------------------------------------------------------
