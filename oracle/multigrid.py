@@ -111,6 +111,8 @@ class MGOptions:
     y <- y + omega M^{-1} (b - A~ y), with the splittings of Sec. 5.3.4:
     "jacobi" M = D, "fgs" M = D + L (forward block Gauss-Seidel), "bgs"
     M = D + L^T (backward), "sgs" M = (D + L) D^{-1} (D + L^T).
+    coarsen: the step ratio between consecutive levels (2 as in Alg. 1;
+    larger powers of 2 as Sec. 6 reports trying), see oracle.transfer.
     """
     nu_pre: int = 2
     nu_post: int = 2
@@ -122,6 +124,7 @@ class MGOptions:
     mu_scale: float = 2.0
     cycle: str = "V"
     smoother: str = "jacobi"
+    coarsen: int = 2
 
 
 class Hierarchy:
@@ -138,12 +141,13 @@ class Hierarchy:
         self.R, self.P = [], []
         for i in range(len(self.levels) - 1):
             f, c = self.levels[i], self.levels[i + 1]
-            if c.n * 2 != f.n:
-                raise ValueError("levels must halve the step count")
+            cf = self.opts.coarsen
+            if c.n * cf != f.n:
+                raise ValueError("levels must divide the step count by the coarsening factor")
             Rt = restriction(f.p, f.q, f.n, self.opts.transfer_variant,
-                             self.opts.mu_scale)
+                             self.opts.mu_scale, cf)
             Pt = interpolation(f.p, f.q, f.n, self.opts.transfer_variant,
-                               self.opts.mu_scale)
+                               self.opts.mu_scale, cf)
             # time-major transfers: R~ = P_c R Q_f^T, P~ = P_f P Q_c^T
             self.R.append(Rt[c.perm][:, f.perm].tocsr())
             self.P.append(Pt[f.perm][:, c.perm].tocsr())

@@ -26,6 +26,15 @@ mu_scale multiplies the mu block of the interpolation (coarse -> fine) and,
 keeping R proportional to the transpose pattern of P, the mu rows of the
 restriction.  mu_scale = 1 is the printed, unscaled transfer; 2 is the
 step ratio.
+
+Coarsening by a factor c > 2 (Sec. 6 reports trying larger factors), with
+coarse steps 1..n/c and variant 0's alignment: injection
+s^c_k = s^f_{c(k-1)+1}, linear interpolation
+s^f_{c(k-1)+1+i} = ((c-i) s^c_k + i s^c_{k+1}) / c for i = 0..c-1 (with
+s^c_{n/c+1} := s^c_{n/c}), the control averaged over and copied to the c
+fine steps of a coarse step.  For c = 2 these are the formulas above.  The
+mu block takes mu_scale^(log2 c): one factor mu_scale per halving of the
+step.
 """
 from __future__ import annotations
 
@@ -76,23 +85,75 @@ def _ctrl_P(nf: int) -> sp.csr_matrix:
     return P.tocsr()
 
 
+def _node_R_c(nf: int, c: int) -> sp.csr_matrix:
+    nc = nf // c
+    R = sp.lil_matrix((nc, nf))
+    for k in range(1, nc + 1):
+        R[k - 1, c * (k - 1)] = 1.0                      # s^c_k = s^f_{c(k-1)+1}
+    return R.tocsr()
+
+
+def _node_P_c(nf: int, c: int) -> sp.csr_matrix:
+    nc = nf // c
+    P = sp.lil_matrix((nf, nc))
+    for k in range(1, nc + 1):
+        kk = k + 1 if k < nc else nc                     # s^c_{nc+1} := s^c_{nc}
+        for i in range(c):
+            P[c * (k - 1) + i, k - 1] += (c - i) / c
+            if i:
+                P[c * (k - 1) + i, kk - 1] += i / c
+    return P.tocsr()
+
+
+def _ctrl_R_c(nf: int, c: int) -> sp.csr_matrix:
+    nc = nf // c
+    R = sp.lil_matrix((nc, nf))
+    for k in range(1, nc + 1):
+        for i in range(c):
+            R[k - 1, c * (k - 1) + i] = 1.0 / c
+    return R.tocsr()
+
+
+def _ctrl_P_c(nf: int, c: int) -> sp.csr_matrix:
+    nc = nf // c
+    P = sp.lil_matrix((nf, nc))
+    for k in range(1, nc + 1):
+        for i in range(c):
+            P[c * (k - 1) + i, k - 1] = 1.0
+    return P.tocsr()
+
+
+def _mu_factor(mu_scale: float, c: int) -> float:
+    return float(mu_scale) ** np.log2(c)
+
+
+def _factor_parts(nf: int, variant: int, c: int):
+    if c < 2 or c & (c - 1):
+        raise ValueError("the coarsening factor must be a power of 2")
+    if nf % c:
+        raise ValueError("n must be divisible by the coarsening factor")
+    if c == 2:
+        return _node_R(nf, variant), _node_P(nf, variant), _ctrl_R(nf), _ctrl_P(nf)
+    if variant != 0:
+        raise ValueError("transfer variant 1 is defined for a factor of 2 only")
+    return _node_R_c(nf, c), _node_P_c(nf, c), _ctrl_R_c(nf, c), _ctrl_P_c(nf, c)
+
+
 def restriction(p: int, q: int, nf: int, variant: int = 0,
-                mu_scale: float = 1.0) -> sp.csr_matrix:
-    """Type-major restriction from nf steps to nf/2 steps; the mu rows are
-    multiplied by mu_scale."""
-    if nf % 2:
-        raise ValueError("n must be even to coarsen")
-    Rs = sp.kron(_node_R(nf, variant), sp.identity(p))
-    Rz = sp.kron(_ctrl_R(nf), sp.identity(q))
-    return sp.block_diag([Rs, Rs, Rz, Rs, mu_scale * Rs], format="csr")
+                mu_scale: float = 1.0, c: int = 2) -> sp.csr_matrix:
+    """Type-major restriction from nf steps to nf/c steps; the mu rows are
+    multiplied by mu_scale^(log2 c)."""
+    nR, _, zR, _ = _factor_parts(nf, variant, c)
+    Rs = sp.kron(nR, sp.identity(p))
+    Rz = sp.kron(zR, sp.identity(q))
+    return sp.block_diag([Rs, Rs, Rz, Rs, _mu_factor(mu_scale, c) * Rs], format="csr")
 
 
 def interpolation(p: int, q: int, nf: int, variant: int = 0,
-                  mu_scale: float = 1.0) -> sp.csr_matrix:
-    """Type-major interpolation from nf/2 steps to nf steps; the mu block is
-    multiplied by mu_scale."""
-    if nf % 2:
-        raise ValueError("n must be even to coarsen")
-    Ps = sp.kron(_node_P(nf, variant), sp.identity(p))
-    Pz = sp.kron(_ctrl_P(nf), sp.identity(q))
-    return sp.block_diag([Ps, Ps, Pz, Ps, mu_scale * Ps], format="csr")
+                  mu_scale: float = 1.0, c: int = 2) -> sp.csr_matrix:
+    """Type-major interpolation from nf/c steps to nf steps; the mu block is
+    multiplied by mu_scale^(log2 c)."""
+    _, nP, _, zP = _factor_parts(nf, variant, c)
+    Ps = sp.kron(nP, sp.identity(p))
+    Pz = sp.kron(zP, sp.identity(q))
+    return sp.block_diag([Ps, Ps, Pz, Ps, _mu_factor(mu_scale, c) * Ps], format="csr")

@@ -346,3 +346,20 @@ def test_smoother_variants_in_the_cycle(levels):
     if levels == "vdp":
         und = {n: fgmres_count(mk(n), p, q, 2, smoother="fgs", **PRINTED)[0] for n in (64, 256)}
         assert und[256] >= 3 * und[64], und
+
+
+def test_larger_coarsening_factors_converge_without_gain():
+    """Sec. 6: larger coarsening factors were tried and gave no significant
+    advantage.  With a step ratio of 4 the weighted cycle still converges in
+    a count flat in n, not below the factor-2 cycle's."""
+    from workloads import make_problem
+    counts = {}
+    for c, n, L in ((2, 256, 6), (4, 256, 4), (2, 1024, 8), (4, 1024, 5)):
+        prob, rng = make_problem(kind="vanderpol", n=n, n_levels=L, seed=7, coarsen=c)
+        assert prob.levels[-1].N.shape[0] == (8 if c == 2 else 4 if n == 256 else 4)
+        H = Hierarchy(prob.levels, MGOptions(coarsen=c))
+        x, info = H.solve(ls_rhs(2, 1, n), tol=1e-6, restart=200, maxit=200)
+        assert info["converged"]
+        counts[(c, n)] = info["iters"]
+    assert counts[(4, 1024)] <= counts[(4, 256)] + 3, counts
+    assert counts[(4, 256)] >= counts[(2, 256)] and counts[(4, 1024)] >= counts[(2, 1024)], counts

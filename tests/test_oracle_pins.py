@@ -501,3 +501,46 @@ def test_blockwise_apply_matches_the_assembled_operator(shared):
     np.testing.assert_allclose(apply_blocks(lv.N, lv.V, lv.Z, x), A @ x, rtol=1e-13, atol=1e-13)
     np.testing.assert_allclose(apply_blocks(lv.N, lv.V, lv.Z, x, magnitude=True),
                                abs(A) @ abs(x), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("c", [2, 4, 8])
+def test_transfers_coarsening_factor(c):
+    """Coarsening by c: R P = I, interpolation reproduces data linear in time
+    (coarse step k at fine step c(k-1)+1) away from the one-sided end,
+    control averaged over / copied to the c fine steps, and the mu block
+    scaled by mu_scale^(log2 c).  For c = 2 the factor-c forms are the
+    printed ones (variant 0)."""
+    p, q, nf = 2, 3, 32
+    nc = nf // c
+    R = restriction(p, q, nf, 0, c=c)
+    P = interpolation(p, q, nf, 0, c=c)
+    np.testing.assert_allclose((R @ P).toarray(), np.eye((4 * p + q) * nc), rtol=0, atol=1e-15)
+    if c == 2:
+        np.testing.assert_array_equal(R.toarray(), restriction(p, q, nf, 0).toarray())
+        np.testing.assert_array_equal(P.toarray(), interpolation(p, q, nf, 0).toarray())
+    o_f, o_c = type_offsets(p, q, nf), type_offsets(p, q, nc)
+    a = np.array([0.7, -0.4])
+    xc = np.zeros((4 * p + q) * nc)
+    kc = np.arange(1, nc + 1)
+    xc[o_c["lam"]:o_c["mu"]] = (kc[:, None] * a[None, :]).ravel()
+    zc = np.random.default_rng(1).normal(size=nc * q)
+    xc[o_c["z"]:o_c["lam"]] = zc
+    xf = P @ xc
+    lf = xf[o_f["lam"]:o_f["mu"]].reshape(nf, p)
+    kf = np.arange(1, nf + 1)
+    pos = (kf - 1) / c + 1.0                           # fine step in coarse units
+    good = slice(0, nf - c + 1)
+    np.testing.assert_allclose(lf[good], (pos[:, None] * a[None, :])[good], rtol=0, atol=1e-13)
+    zf = xf[o_f["z"]:o_f["lam"]].reshape(nc, c, q)
+    for i in range(c):
+        np.testing.assert_array_equal(zf[:, i, :].ravel(), zc)
+    y = np.random.default_rng(2).normal(size=(4 * p + q) * nf)
+    yz = y[o_f["z"]:o_f["lam"]].reshape(nc, c, q)
+    np.testing.assert_allclose((R @ y)[o_c["z"]:o_c["lam"]].reshape(nc, q), yz.mean(axis=1),
+                               rtol=0, atol=1e-15)
+    yu = y[o_f["v"]:o_f["z"]].reshape(nf, p)
+    np.testing.assert_array_equal((R @ y)[o_c["v"]:o_c["z"]].reshape(nc, p), yu[0::c])
+    Rm = restriction(p, q, nf, 0, mu_scale=2.0, c=c).toarray()
+    np.testing.assert_allclose(Rm[o_c["mu"]:], c * R.toarray()[o_c["mu"]:], rtol=0, atol=0)
+    with pytest.raises(ValueError):
+        restriction(p, q, nf, 1, c=4) if c != 2 else restriction(p, q, 30, 0, c=4)

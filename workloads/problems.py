@@ -182,15 +182,16 @@ class Problem:
         return (4 * self.p + self.q) * self.n
 
 
-def coarsen_point(w: np.ndarray, zeta: np.ndarray, variant: int = 0):
-    """Restrict a linearisation point to the grid of twice the step.
+def coarsen_point(w: np.ndarray, zeta: np.ndarray, variant: int = 0, c: int = 2):
+    """Restrict a linearisation point to the grid of c times the step.
 
     States by injection, controls by averaging (Sec. 5.3.1).  variant 0 takes
-    the odd fine step 2k-1 as printed; variant 1 takes step 2k, which sits at
-    the same time as coarse step k.
+    the first fine step c(k-1)+1 of coarse step k, as printed for c = 2;
+    variant 1 (c = 2 only) takes step 2k, which sits at the same time as
+    coarse step k.
     """
-    ws = w[0::2] if variant == 0 else w[1::2]
-    zc = 0.5 * (zeta[0::2] + zeta[1::2])
+    ws = w[0::c] if variant == 0 else w[c - 1::c]
+    zc = zeta.reshape(zeta.shape[0] // c, c, *zeta.shape[1:]).mean(axis=1)
     return ws, zc
 
 
@@ -199,8 +200,8 @@ def make_problem(kind: str, n: int, n_levels: int, seed: int, *, p: int = None,
                  gamma: float = 100.0, theta: float = 1.0, T: float = 1.0,
                  state_scale: float = 0.5, control_scale: float = 0.5,
                  noise: float = 0.1, transfer_variant: int = 0,
-                 compress: bool = True, rng: Optional[np.random.Generator] = None
-                 ) -> Tuple[Problem, np.random.Generator]:
+                 compress: bool = True, rng: Optional[np.random.Generator] = None,
+                 coarsen: int = 2) -> Tuple[Problem, np.random.Generator]:
     """Build a seeded problem hierarchy.
 
     Draw order with ``np.random.default_rng(seed)`` (the right-hand side is
@@ -209,8 +210,8 @@ def make_problem(kind: str, n: int, n_levels: int, seed: int, *, p: int = None,
       Burgers:     xi (n,nx) ~ N(0,1), w = sin(pi x) + noise*xi,
                    zeta (n,nx) ~ N(0, control_scale^2)
     """
-    if n % (1 << (n_levels - 1)) != 0:
-        raise ValueError("n must be divisible by 2^(n_levels-1)")
+    if n % (coarsen ** (n_levels - 1)) != 0:
+        raise ValueError("n must be divisible by coarsen^(n_levels-1)")
     if rng is None:
         rng = np.random.default_rng(seed)
     if kind == "vanderpol":
@@ -238,11 +239,11 @@ def make_problem(kind: str, n: int, n_levels: int, seed: int, *, p: int = None,
     levels = []
     wl, zl = w, zeta
     for lev in range(n_levels):
-        nl = n >> lev
+        nl = n // coarsen ** lev
         dt = T / nl
         levels.append(lifted_blocks(wl, zl, w0, dt, theta, gamma, jac, compress=compress))
         if lev + 1 < n_levels:
-            wl, zl = coarsen_point(wl, zl, transfer_variant)
+            wl, zl = coarsen_point(wl, zl, transfer_variant, coarsen)
     prob = Problem(kind=kind, p=p, q=q, n=n, n_levels=n_levels, gamma=gamma,
                    theta=theta, T=T, levels=levels, w=w, zeta=zeta, w0=w0,
                    params=params)
