@@ -24,7 +24,8 @@
  * length is (4p+q) n.  The library permutes to the time-major blocks of
  * Fig. 5 internally; callers never see the permutation.
  *
- * Blocks.  For level l (n_l = n / 2^l steps, l = 0 finest) the caller gives
+ * Blocks.  For level l (n_l = n / c^l steps, l = 0 finest, c the option
+ * coarsen, 2 by default) the caller gives
  * the Jacobian blocks of the lifted constraint (Sec. 4.1 eq. (blocks) with
  * the substitutions of Sec. 5.1), row-major FP64:
  *     N[l]: n_l blocks p x p  (N_k)
@@ -33,7 +34,7 @@
  *     Z[l]: n_l blocks p x q  (Z~_k)
  * Block k of level l starts at X[l] + k * X_stride.  A stride of 0 means one
  * block shared by every step (the natural form of V and Z~ for theta = 1).
- * Coarse levels are rediscretisations at step 2^l dt (geometric multigrid,
+ * Coarse levels are rediscretisations at step c^l dt (geometric multigrid,
  * Sec. 5.3): the caller supplies them.
  *
  * Streams and ownership.  All device work of a handle is ordered on the HIP
@@ -76,8 +77,9 @@ typedef struct {
   int p;                       /* states per step                              */
   int q;                       /* controls per step                            */
   int n;                       /* steps on the finest grid                     */
-  int n_levels;                /* grids l = 0..n_levels-1; n % 2^(n_levels-1)
-                                  must be 0 (coarsening by 2, Sec. 5.3.1)      */
+  int n_levels;                /* grids l = 0..n_levels-1; n % c^(n_levels-1)
+                                  must be 0 (c = options.coarsen, 2 by
+                                  default: Sec. 5.3.1)                         */
   const double* const* N;      /* n_levels pointers                            */
   const double* const* V;
   const double* const* Z;
@@ -195,6 +197,20 @@ typedef struct {
                                   unlifted inverse; the lifted entry points
                                   act on that scaled system.  Fixed at
                                   setup.  0: the lifted system only.          */
+  int coarsen;                 /* step ratio between consecutive levels: 2 (the
+                                  coarsening of Sec. 5.3), or 4, 8, 16 (the
+                                  larger factors Sec. 6 reports trying).  Level
+                                  l has n / coarsen^l steps, so n must be
+                                  divisible by coarsen^(n_levels-1), and the
+                                  caller's blocks are rediscretisations at
+                                  those steps.  For c != 2: injection of the
+                                  first fine step of each coarse step, linear
+                                  interpolation over its c fine steps, the
+                                  control averaged / copied, the mu block
+                                  scaled by mu_scale^(log2 c), transfer
+                                  variant 0 only, and stand-alone transfer
+                                  kernels instead of the ones folded into the
+                                  sweeps.  Fixed at setup.                    */
 } pitmg_options;
 
 typedef struct {
@@ -214,7 +230,8 @@ typedef struct {
  * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
  * stall_steps 2, vcycle_graph 0, apply_from_sweep 1, pair_sweeps 1,
  * omega 0.5, mu_scale 2, cycle 0 (V), smoother 0 (block Jacobi), unlifted
- * 0.  (omega = 1 with mu_scale = 1 is the cycle exactly as printed.) */
+ * 0, coarsen 2.  (omega = 1 with mu_scale = 1 is the cycle exactly as
+ * printed.) */
 void pitmg_default_options(pitmg_options* opt);
 
 /* Create a handle: validate, allocate, take the blocks (copy or borrow) and

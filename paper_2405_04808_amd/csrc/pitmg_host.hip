@@ -366,18 +366,23 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "the Gauss-Seidel smoothers run in FP64 only");
   if (o.unlifted != 0 && o.unlifted != 1)
     return set_err(h, PITMG_ERR_INVALID, "unlifted must be 0 or 1");
+  if (o.coarsen != 2 && o.coarsen != 4 && o.coarsen != 8 && o.coarsen != 16)
+    return set_err(h, PITMG_ERR_INVALID, "coarsen must be 2, 4, 8 or 16");
+  if (o.coarsen != 2 && o.transfer_variant != 0)
+    return set_err(h, PITMG_ERR_INVALID, "transfer_variant 1 is defined for coarsen = 2 only");
   return PITMG_OK;
 }
 
-int check_problem(pitmg_handle* h, const pitmg_problem* pb) {
+int check_problem(pitmg_handle* h, const pitmg_problem* pb, int coarsen) {
   if (!pb) return set_err(h, PITMG_ERR_INVALID, "problem is NULL");
   if (pb->p < 1 || pb->q < 1 || pb->n < 1 || pb->n_levels < 1)
     return set_err(h, PITMG_ERR_INVALID, "p, q, n and n_levels must be >= 1");
   if (pb->n_levels > 20) return set_err(h, PITMG_ERR_INVALID, "n_levels must be <= 20");
   if (pb->n >= (1 << 20)) return set_err(h, PITMG_ERR_UNSUPPORTED, "n must be < 2^20");
-  const long long div = 1LL << (pb->n_levels - 1);
-  if (pb->n % div != 0)
-    return set_err(h, PITMG_ERR_INVALID, "n must be divisible by 2^(n_levels-1)");
+  long long div = 1;
+  for (int l = 1; l < pb->n_levels && div <= pb->n; ++l) div *= coarsen;
+  if (div > pb->n || pb->n % div != 0)
+    return set_err(h, PITMG_ERR_INVALID, "n must be divisible by coarsen^(n_levels-1)");
   if (pb->p > 512 || pb->q > 512)
     return set_err(h, PITMG_ERR_UNSUPPORTED, "this build supports p, q <= 512");
   if (!pb->N || !pb->V || !pb->Z) return set_err(h, PITMG_ERR_INVALID, "block arrays are NULL");
@@ -721,6 +726,36 @@ hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, cons
   return e;
 }
 
+// The transfers between level l and l + 1 for the handle's step ratio:
+// R r into C.b-shaped bc, and y += P e.
+int restrict_level(pitmg_handle* h, int l, const double* r, double* bc) {
+  const LevelView v = view(h, l);
+  const int c = h->opt.coarsen;
+  if (c == 2)
+    return timed(h, 3, [&] {
+      return launch_restrict(h->p, h->q, v.n, r, h->opt.transfer_variant, v.mu_scale, bc,
+                             h->stream);
+    });
+  const double fac = std::pow(v.mu_scale, std::log2((double)c));
+  return timed(h, 3, [&] {
+    return launch_restrict_c(h->p, h->q, v.n, c, r, fac, bc, h->stream);
+  });
+}
+
+int interp_level(pitmg_handle* h, int l, const double* e, double* y) {
+  const LevelView v = view(h, l);
+  const int c = h->opt.coarsen;
+  if (c == 2)
+    return timed(h, 3, [&] {
+      return launch_interp_add(h->p, h->q, v.n, e, h->opt.transfer_variant, v.mu_scale, y,
+                               h->stream);
+    });
+  const double fac = std::pow(v.mu_scale, std::log2((double)c));
+  return timed(h, 3, [&] {
+    return launch_interp_add_c(h->p, h->q, v.n, c, e, fac, y, h->stream);
+  });
+}
+
 // d = (D + L)^{-1} r (forward) or (D + L^T)^{-1} r (backward) on level l:
 // the block solves of D^{-1} r, the chain of the coupled slot through Phi_k,
 // then the block solves with the chain as the coupling iterate
@@ -826,16 +861,11 @@ int vcycle_level_gs(pitmg_handle* h, int l, const double* b, double* out, int cy
     y = dst;
   }
   if (!y) {
-    rc = timed(h, 3, [&] {
-      return launch_restrict(h->p, h->q, v.n, b, var, v.mu_scale, C.b, h->stream);
-    });
+    rc = restrict_level(h, l, b, C.b);
   } else {
     double* res = y == bufs[0] ? bufs[1] : bufs[0];
     rc = timed(h, 2, [&] { return launch_apply(v, y, b, -1.0, 1.0, res, h->stream); });
-    if (!rc)
-      rc = timed(h, 3, [&] {
-        return launch_restrict(h->p, h->q, v.n, res, var, v.mu_scale, C.b, h->stream);
-      });
+    if (!rc) rc = restrict_level(h, l, res, C.b);
   }
   if (rc) return rc;
   if ((rc = coarse_correction(h, l, cyc))) return rc;
@@ -843,10 +873,7 @@ int vcycle_level_gs(pitmg_handle* h, int l, const double* b, double* out, int cy
     y = bufs[0];
     if ((rc = timed(h, 3, [&] { return launch_fill(y, 0.0, B.len, h->stream); }))) return rc;
   }
-  rc = timed(h, 3, [&] {
-    return launch_interp_add(h->p, h->q, v.n, C.out, var, v.mu_scale, y, h->stream);
-  });
-  if (rc) return rc;
+  if ((rc = interp_level(h, l, C.out, y))) return rc;
   for (int s = 0; s < o.nu_post; ++s) {
     double* dst = s == o.nu_post - 1 ? out : (y == bufs[0] ? bufs[1] : bufs[0]);
     if ((rc = gs_sweep(h, l, b, y, dst))) return rc;
@@ -878,7 +905,10 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out, int cyc) 
   // inside the last sweep as R (rbeta b + (L+L^T)(ra y_prev - y)); more
   // weighted sweeps, and an FP32 finest level, form the residual explicitly.
   const double w = v.omega;
-  const bool explicit_res = B.res != nullptr || (w != 1.0 && o.nu_pre > 2);
+  // step ratios other than 2 use the stand-alone transfers: explicit
+  // residual and restriction, interpolation added before the post-sweeps
+  const bool c2 = o.coarsen == 2;
+  const bool explicit_res = B.res != nullptr || (w != 1.0 && o.nu_pre > 2) || !c2;
   double rbeta = 0.0, ra = 1.0;
   if (w != 1.0 && o.nu_pre == 1) rbeta = 1.0 - w;
   if (w != 1.0 && o.nu_pre == 2) {
@@ -909,9 +939,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out, int cyc) 
     ++s;
   }
   if (ycur == nullptr) {
-    rc = timed(h, 3, [&] {
-      return launch_restrict(h->p, h->q, v.n, b, var, v.mu_scale, C.b, h->stream);
-    });
+    rc = restrict_level(h, l, b, C.b);
   } else if (explicit_res) {
     // r = b - A~ y in FP64 (into the spare smoothing buffer unless the FP32
     // finest level keeps its own), then restricted
@@ -919,10 +947,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out, int cyc) 
     LevelView v64 = v;
     v64.fp32 = 0;
     rc = timed(h, 2, [&] { return launch_apply(v64, ycur, b, -1.0, 1.0, res, h->stream); });
-    if (!rc)
-      rc = timed(h, 3, [&] {
-        return launch_restrict(h->p, h->q, v.n, res, var, v.mu_scale, C.b, h->stream);
-      });
+    if (!rc) rc = restrict_level(h, l, res, C.b);
   }
   if (rc) return rc;
   rc = coarse_correction(h, l, cyc);
@@ -932,16 +957,23 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out, int cyc) 
       HIPCHK(h, hipMemcpyAsync(out, ycur, B.len * 8, hipMemcpyDeviceToDevice, h->stream));
     else
       HIPCHK(h, hipMemsetAsync(out, 0, B.len * 8, h->stream));
-    return timed(h, 3, [&] {
-      return launch_interp_add(h->p, h->q, v.n, C.out, var, v.mu_scale, out, h->stream);
-    });
+    return interp_level(h, l, C.out, out);
+  }
+  if (!c2) {
+    // y + P e into the iterate the post-sweeps start from
+    if (!ycur) {
+      ycur = bufs[0];
+      if ((rc = timed(h, 3, [&] { return launch_fill(ycur, 0.0, B.len, h->stream); })))
+        return rc;
+    }
+    if ((rc = interp_level(h, l, C.out, ycur))) return rc;
   }
   // A~ z from the last sweep's identity needs an undamped FP64 sweep
   const bool identity = l == 0 && w == 1.0 && !v.fp32;
   for (int s = 0; s < o.nu_post;) {
     double* dst = (s == o.nu_post - 1) ? out : (ycur == bufs[0] ? bufs[1] : bufs[0]);
     const double* yo = ycur;
-    const double* ec = s == 0 ? C.out : nullptr;
+    const double* ec = s == 0 && c2 ? C.out : nullptr;
     if (pairs && s + 1 < o.nu_post) {
       // second sweep: into out if it is the last, else the other buffer
       double* d2 = (s + 1 == o.nu_post - 1) ? out : (dst == bufs[0] ? bufs[1] : bufs[0]);
@@ -1411,6 +1443,7 @@ void pitmg_default_options(pitmg_options* o) {
   o->cycle = 0;
   o->smoother = 0;
   o->unlifted = 0;
+  o->coarsen = 2;
 }
 
 int pitmg_autotune(pitmg_handle* h, int* cfg) {
@@ -1530,11 +1563,11 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   *hp = nullptr;
   pitmg_handle* h = new pitmg_handle();
   h->stream = (hipStream_t)stream;
-  int rc = check_problem(h, pb);
   pitmg_options o;
   pitmg_default_options(&o);
   if (opt) o = *opt;
-  if (!rc) rc = check_options(h, o);
+  int rc = check_options(h, o);
+  if (!rc) rc = check_problem(h, pb, o.coarsen);
   if (rc) {
     std::fprintf(stderr, "pitmg_setup: %s\n", h->err.c_str());
     delete h;
@@ -1558,7 +1591,7 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   };
   for (int l = 0; l < h->L; ++l) {
     LevelBuf& b = h->lv[l];
-    b.n = h->n >> l;
+    b.n = l == 0 ? h->n : h->lv[l - 1].n / o.coarsen;
     b.len = (4LL * h->p + h->q) * b.n;
     if (!pb->blocks_on_device || o.unlifted) {
       // own copies: host blocks, or the scaled state blocks of the unlifted
@@ -1706,7 +1739,7 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
 
 int pitmg_refactor(pitmg_handle* h, const pitmg_problem* pb) {
   if (!h) return PITMG_ERR_INVALID;
-  int rc = check_problem(h, pb);
+  int rc = check_problem(h, pb, h->opt.coarsen);
   if (rc) return rc;
   if (pb->p != h->p || pb->q != h->q || pb->n != h->n || pb->n_levels != h->L ||
       pb->blocks_on_device != h->blocks_on_device)
@@ -1731,6 +1764,8 @@ int pitmg_set_options(pitmg_handle* h, const pitmg_options* opt) {
     return set_err(h, PITMG_ERR_INVALID, "smoother is fixed at setup");
   if (opt->unlifted != h->opt.unlifted)
     return set_err(h, PITMG_ERR_INVALID, "unlifted is fixed at setup");
+  if (opt->coarsen != h->opt.coarsen)
+    return set_err(h, PITMG_ERR_INVALID, "coarsen is fixed at setup");
   h->opt = *opt;
   drop_graph(h);            // the captured cycle depends on the options
   return PITMG_OK;

@@ -211,6 +211,11 @@ hipError_t launch_restrict_delta(int p, int q, int nf, const double* b, double b
 hipError_t launch_restrict(int p, int q, int nf, const double* r, int variant,
                            double mu_scale, double* bc, hipStream_t s);
 // y += P e  (interpolate and add).
+// Transfers for a step ratio c (variant 0 alignment), mu block times mu_fac.
+hipError_t launch_restrict_c(int p, int q, int nf, int c, const double* r, double mu_fac,
+                             double* bc, hipStream_t s);
+hipError_t launch_interp_add_c(int p, int q, int nf, int c, const double* e, double mu_fac,
+                               double* y, hipStream_t s);
 hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant,
                              double mu_scale, double* y, hipStream_t s);
 // y = w y + (1 - w)(yold + P ec)  (yold, ec NULL = 0): the weighting of a

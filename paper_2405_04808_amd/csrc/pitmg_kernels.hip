@@ -470,6 +470,55 @@ __global__ void k_interp_add(int p, int q, int nf, const double* __restrict__ e,
   }
 }
 
+// Transfers for a step ratio c between levels (coarse step k at fine step
+// c(k-1)+1): injection for u, v, lambda, mu; the control averaged over the
+// c fine steps; interpolation linear over the c fine steps of a coarse step
+// (s^c_{nc+1} := s^c_{nc}) and the control copied.  The mu block is scaled
+// by mu_fac (mu_scale per halving of the step).
+__global__ void k_restrict_c(int p, int q, int nf, int c, const double* __restrict__ r,
+                             double mu_fac, double* __restrict__ bc) {
+  const int nc = nf / c;
+  const TypeMajor Tf(p, q, nf), Tc(p, q, nc);
+  const long long segf[5] = {Tf.u, Tf.v, Tf.z, Tf.l, Tf.m};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Tc.len;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int type, m, i;
+    locate(idx, Tc, p, q, type, m, i);
+    double v;
+    if (type == 2) {
+      v = 0.0;
+      for (int j = 0; j < c; ++j) v += r[Tf.z + (long long)(c * (m - 1) + j) * q + i];
+      v /= c;
+    } else {
+      v = r[segf[type] + (long long)(c * (m - 1)) * p + i];
+    }
+    bc[idx] = type == 4 ? mu_fac * v : v;
+  }
+}
+
+__global__ void k_interp_add_c(int p, int q, int nf, int c, const double* __restrict__ e,
+                               double mu_fac, double* __restrict__ y) {
+  const int nc = nf / c;
+  const TypeMajor Tf(p, q, nf), Tc(p, q, nc);
+  const long long segc[5] = {Tc.u, Tc.v, Tc.z, Tc.l, Tc.m};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < Tf.len;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int type, k, i;
+    locate(idx, Tf, p, q, type, k, i);
+    const int kc = (k - 1) / c + 1, j = (k - 1) % c;    // coarse step, position in it
+    double v;
+    if (type == 2) {
+      v = e[Tc.z + (long long)(kc - 1) * q + i];
+    } else {
+      const int kn = kc < nc ? kc + 1 : nc;
+      const double* seg = e + segc[type];
+      v = ((double)(c - j) * seg[(long long)(kc - 1) * p + i] +
+           (double)j * seg[(long long)(kn - 1) * p + i]) / c;
+    }
+    y[idx] += type == 4 ? mu_fac * v : v;
+  }
+}
+
 // y = w y + (1 - w)(yold + P ec)
 __global__ void k_weight(int p, int q, int n, double w, const double* __restrict__ yold,
                          const double* __restrict__ ec, int variant, double mu_scale,
@@ -547,6 +596,22 @@ hipError_t launch_interp_add(int p, int q, int nf, const double* e, int variant,
   const TypeMajor Tf(p, q, nf);
   hipLaunchKernelGGL(k_interp_add, dim3(grid_for(Tf.len, 256)), dim3(256), 0, s, p, q, nf, e,
                      variant, mu_scale, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_c(int p, int q, int nf, int c, const double* r, double mu_fac,
+                             double* bc, hipStream_t s) {
+  const TypeMajor Tc(p, q, nf / c);
+  hipLaunchKernelGGL(k_restrict_c, dim3(grid_for(Tc.len, 256)), dim3(256), 0, s, p, q, nf, c, r,
+                     mu_fac, bc);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_add_c(int p, int q, int nf, int c, const double* e, double mu_fac,
+                               double* y, hipStream_t s) {
+  const TypeMajor Tf(p, q, nf);
+  hipLaunchKernelGGL(k_interp_add_c, dim3(grid_for(Tf.len, 256)), dim3(256), 0, s, p, q, nf, c,
+                     e, mu_fac, y);
   return hipGetLastError();
 }
 

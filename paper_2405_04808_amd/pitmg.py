@@ -49,7 +49,8 @@ class pitmg_options(C.Structure):
                 ("mu_scale", C.c_double),
                 ("cycle", C.c_int),
                 ("smoother", C.c_int),
-                ("unlifted", C.c_int)]
+                ("unlifted", C.c_int),
+                ("coarsen", C.c_int)]
 
 
 class pitmg_stats(C.Structure):
@@ -194,12 +195,22 @@ class Solver:
         self.n_levels = len(levels)
         self.shared_V = lv0.V.shape[0] == 1 and self.n > 1
         self.shared_Z = lv0.Z.shape[0] == 1 and self.n > 1
+        # the library borrows these arrays with the sizes the options imply:
+        # level l holds n / coarsen^l steps
+        c = int(getattr(self.options, "coarsen", 2) or 2)
+        for l, lv in enumerate(levels):
+            nl = self.n // c ** l
+            ok = (self.n % c ** l == 0 and lv.N.shape[0] == nl
+                  and lv.V.shape[0] in ((1,) if self.shared_V else (nl,))
+                  and lv.Z.shape[0] in ((1,) if self.shared_Z else (nl,)))
+            if not ok:
+                raise ValueError(f"level {l} does not hold n / {c}^{l} = {nl} steps")
         self.dN, self.dV, self.dZ = [], [], []
         for lv in levels:
             self.dN.append(torch.as_tensor(lv.N, dtype=torch.float64).contiguous().to(self.device))
             self.dV.append(torch.as_tensor(lv.V, dtype=torch.float64).contiguous().to(self.device))
             self.dZ.append(torch.as_tensor(lv.Z, dtype=torch.float64).contiguous().to(self.device))
-        self.lens = [(4 * self.p + self.q) * (self.n >> l) for l in range(self.n_levels)]
+        self.lens = [(4 * self.p + self.q) * lv.N.shape[0] for lv in levels]
 
     def _problem(self) -> pitmg_problem:
         arr = C.c_void_p * self.n_levels

@@ -40,7 +40,8 @@ def mg_opts(o):
                      coarse_maxit=o.coarse_maxit, coarse_fixed_its=o.coarse_fixed_its,
                      transfer_variant=o.transfer_variant, omega=o.omega,
                      mu_scale=o.mu_scale, cycle="VWF"[o.cycle],
-                     smoother=("jacobi", "fgs", "bgs", "sgs")[o.smoother])
+                     smoother=("jacobi", "fgs", "bgs", "sgs")[o.smoother],
+                     coarsen=o.coarsen)
 
 
 def omega_at(o, lev, n_levels):

@@ -110,3 +110,62 @@ def test_variant_options_checked():
         s.set_options(smoother=0)
     s.set_options(cycle=2)                                    # the cycle may change
     s.close()
+
+
+COARSEN_CASES = {
+    "vdp64_c4": dict(kind="vanderpol", n=64, n_levels=3, seed=46, coarsen=4),
+    "burgers_p12_c8": dict(kind="burgers", nx=12, nu=0.01, n=64, n_levels=2, seed=47, coarsen=8),
+    "burgers_p64_c4": dict(kind="burgers", nx=64, nu=0.01, n=64, n_levels=3, seed=48, coarsen=4),
+    "burgers_p128_c4": dict(kind="burgers", nx=128, nu=0.01, n=32, n_levels=2, seed=49,
+                            coarsen=4),
+}
+
+
+@pytest.mark.parametrize("name", list(COARSEN_CASES))
+@pytest.mark.parametrize("cycle,smoother", [(0, 0), (1, 0), (0, 3)])
+@pytest.mark.parametrize("nu", [(2, 2), (1, 0), (0, 1)])
+def test_larger_coarsening_factors_match_oracle(name, cycle, smoother, nu):
+    cfg = COARSEN_CASES[name]
+    prob, rng = make_problem(**cfg)
+    s = pm.Solver(prob.levels, pm.default_options(coarsen=cfg["coarsen"], cycle=cycle,
+                                                    smoother=smoother, coarse_fixed_its=2,
+                                                    nu_pre=nu[0], nu_post=nu[1]))
+    H = Hierarchy(prob.levels, mg_opts(s.options))
+    print(f"coarsen {cfg['coarsen']} {name} cycle {'VWF'[cycle]} {SMOOTHERS[smoother]} nu={nu}",
+          flush=True)
+    r = rng.normal(size=prob.size)
+    got = host(s.vcycle(dev(r)))
+    assert_types(got, H.vcycle(r), prob.p, prob.q, prob.n, coarse_identity_tol(prob),
+                 (name, cycle, smoother, nu))
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["vdp64_c4", "burgers_p64_c4"])
+def test_fgmres_with_larger_coarsening_matches_oracle(name):
+    cfg = COARSEN_CASES[name]
+    prob, rng = make_problem(**cfg)
+    b = make_rhs(prob, rng)
+    s = pm.Solver(prob.levels, pm.default_options(restart=200, maxit=200,
+                                                    coarsen=cfg["coarsen"]))
+    xg, st, rc = s.solve(dev(b), tol=1e-10)
+    assert rc == pm.PITMG_OK and st["relres_true"] <= 1e-10
+    x = host(xg)
+    H = Hierarchy(prob.levels, mg_opts(s.options))
+    xr, info = H.solve(b, tol=1e-10, restart=200, maxit=200)
+    assert abs(st["iters"] - info["iters"]) <= 1, (st["iters"], info["iters"])
+    A = OracleLevel(prob.levels[0].N, prob.levels[0].V, prob.levels[0].Z).A
+    check_solution(x, st["iters"], xr, info["iters"], A, b, prob.p, prob.q, prob.n, name)
+    s.close()
+
+
+def test_coarsening_option_checked():
+    prob, rng = make_problem(**COARSEN_CASES["vdp64_c4"])
+    with pytest.raises(pm.PitmgError):
+        pm.Solver(prob.levels, pm.default_options(coarsen=4, transfer_variant=1))
+    # a factor that is not a power of 2: refused by the binding's size check
+    # or by the library's option check
+    with pytest.raises((pm.PitmgError, ValueError)):
+        pm.Solver(prob.levels, pm.default_options(coarsen=3))
+    # the binding refuses blocks whose level sizes do not follow the factor
+    with pytest.raises(ValueError):
+        pm.Solver(prob.levels, pm.default_options(coarsen=2))
