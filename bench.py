@@ -50,6 +50,15 @@ WORKLOADS = {
                             "10 levels (coarsest 8 steps), gamma=100, V(2,2) weighted block "
                             "Jacobi (omega 1/2), mu transfer scale 2, coarse GMRES+SGS tol "
                             "1e-3, FGMRES(200) tol 1e-10"),
+    # the learned-coarse-correction workload: the bench line is the plain
+    # solve; the learned leg trains on 20,000 pairs of this size.  Its
+    # assembled system (2.6 M unknowns, about 3e8 nonzeros) is beyond the
+    # oracle's direct factorisation, so it has no CPU baseline
+    "burgers256": dict(cfg="burgers256", restart=200, maxit=400,
+                       desc="viscous Burgers nx=256 (p=q=256), nu=0.01, n=2048 steps, "
+                            "9 levels (coarsest 8 steps), gamma=100, V(2,2) weighted block "
+                            "Jacobi (omega 1/2), mu transfer scale 2, coarse GMRES+SGS tol "
+                            "1e-3, FGMRES(200) tol 1e-10"),
     "vdp256": dict(cfg="vdp256", restart=300, maxit=300,
                    desc="van der Pol p=2 q=1, n=256 steps, 6 levels, gamma=100, V(2,2) "
                         "weighted block Jacobi (omega 1/2), mu transfer scale 2, "
@@ -168,7 +177,7 @@ def cpu_baseline(name):
 
 
 def learned_leg(pm, torch, wl, train_seeds=range(50000, 50008), held_out=(60000, 60001),
-                rhs_per_point=8):
+                rhs_per_point=8, max_pairs=8000):
     """Learned coarse correction on the benchmark workload: record the
     coarsest-level pairs of plain solves on other linearisation points
     (rhs_per_point seeded right-hand sides each, as an SQP step solves
@@ -188,13 +197,19 @@ def learned_leg(pm, torch, wl, train_seeds=range(50000, 50008), held_out=(60000,
 
     opts = pm.default_options(restart=wl["restart"], maxit=wl["maxit"])
     t0 = time.perf_counter()
-    R, E, info = ct.collect_pairs(probs(train_seeds, rhs_per_point), opts, max_pairs=8000)
+    def progress(solves, pairs):
+        if solves % 25 == 0:
+            print(f"# learned: {solves} solves, {pairs} pairs, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    R, E, info = ct.collect_pairs(probs(train_seeds, rhs_per_point), opts, max_pairs=max_pairs,
+                                  progress=progress)
     t_pairs = time.perf_counter() - t0
     print(f"# learned: {R.shape[0]} pairs from {len(info)} solves in {t_pairs:.1f} s",
           file=sys.stderr, flush=True)
     prob0, _ = config_problem(wl["cfg"])
     p, q = prob0.p, prob0.q
-    C, T, H = 4 * p + q, prob0.n >> (prob0.n_levels - 1), 64
+    C, T, H = 4 * p + q, prob0.levels[-1].N.shape[0], 64
     net = pm.Net(C, T, H, max_batch=256)
     net.set_params(coarse_net_params(C, H, 0).astype("float32"))
     X, Y = net.make_samples(p, q, R, E)
@@ -536,17 +551,20 @@ def main():
     learned = None
     if not args.no_learned and args.workload == "burgers128":
         learned = learned_leg(pm, torch, wl)
+    elif not args.no_learned and args.workload == "burgers256":
+        # 20,000 pairs: 8 points, up to 100 right-hand sides each
+        learned = learned_leg(pm, torch, wl, rhs_per_point=100, max_pairs=20000)
 
     variants = None
     if not args.no_variants and args.workload == "burgers128":
         variants = variants_leg(pm, torch, prob, db, wl)
 
     batch = None
-    if not args.no_batch:
+    if not args.no_batch and args.workload == "burgers128":
         batch = batch_leg(pm, torch, count=args.batch_count)
 
     cpu = None
-    if not args.no_cpu_baseline and args.workload != "burgers512":
+    if not args.no_cpu_baseline and args.workload not in ("burgers512", "burgers256"):
         cpu = cpu_baseline(args.workload)
 
     out = {

@@ -23,7 +23,7 @@ from . import pitmg as pm
 
 
 def collect_pairs(problems: Iterable[Tuple[Sequence, np.ndarray]], options, max_pairs: int,
-                  tol: float = 1e-10, device: str = "cuda"):
+                  tol: float = 1e-10, device: str = "cuda", progress=None):
     """Solve each problem with GMRES + SGS on the coarsest grid and record
     its coarsest-level (r_c, e_c) pairs, up to max_pairs in total.
 
@@ -33,9 +33,13 @@ def collect_pairs(problems: Iterable[Tuple[Sequence, np.ndarray]], options, max_
     R = E = None
     count = 0
     info = []
+    s, cur = None, None
     for levels, b in problems:
-        s = pm.Solver(levels, options, device=device)
-        lc = (4 * s.p + s.q) * (s.n >> (s.n_levels - 1))
+        if levels is not cur:            # consecutive right-hand sides of one point share a handle
+            if s is not None:
+                s.close()
+            s, cur = pm.Solver(levels, options, device=device), levels
+        lc = s.lens[-1]
         if R is None:
             R = torch.empty((max_pairs, lc), dtype=torch.float64, device=device)
             E = torch.empty_like(R)
@@ -46,9 +50,12 @@ def collect_pairs(problems: Iterable[Tuple[Sequence, np.ndarray]], options, max_
         got = s.pair_count()
         info.append({"iters": st["iters"], "pairs": got, "s": time.perf_counter() - t0})
         count += got
-        s.close()
+        if progress is not None:
+            progress(len(info), count)
         if count >= max_pairs:
             break
+    if s is not None:
+        s.close()
     return R[:count], E[:count], info
 
 
