@@ -467,6 +467,17 @@ int pitmg_coarse_pairs_count(const pitmg_handle* h);
 /* Bytes of device memory held by the handle. */
 long long pitmg_device_bytes(const pitmg_handle* h);
 
+/* Level `level` (0 = finest) of a set-up handle: *n its step count, *flags
+ * a bit set: PITMG_LEVEL_FP32 when its sweeps run in FP32, and
+ * PITMG_LEVEL_DIAG_VZ when V and Z~ are shared by every step and diagonal
+ * (theta = 1 with an identity mass matrix and distributed control, Sec. 6),
+ * so the sweeps and products use their diagonals alone.  Either pointer may
+ * be NULL.  Returns PITMG_ERR_INVALID for a NULL handle or a level out of
+ * range. */
+#define PITMG_LEVEL_FP32 1
+#define PITMG_LEVEL_DIAG_VZ 2
+int pitmg_level_info(const pitmg_handle* h, int level, int* n, int* flags);
+
 const char* pitmg_status_string(int code);
 const char* pitmg_last_error(const pitmg_handle* h);
 void pitmg_destroy(pitmg_handle* h);

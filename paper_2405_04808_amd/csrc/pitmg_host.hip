@@ -66,6 +66,9 @@ struct LevelBuf {
   double* y1 = nullptr;
   double* out = nullptr;             // result of this level's cycle (l >= 1)
   double* res = nullptr;             // explicit FP64 residual (finest level, FP32 smoother)
+  bool vz_diag = false;              // shared V, Z~ diagonal: their diagonals in vzd
+  double* vzd = nullptr;             // [Vd (p) | Zd (p)]
+  float* vzd32 = nullptr;            // FP32 copy (FP32 levels)
   double* b2 = nullptr;              // W / F cycles: second coarse right-hand side (l >= 1)
   double* e2 = nullptr;              //   and its correction
   // block Gauss-Seidel smoothers (levels above the coarsest)
@@ -325,6 +328,11 @@ LevelView view(const pitmg_handle* h, int l) {
   // level's sweeps are the exact block solves of its SGS
   v.omega = l < h->L - 1 ? h->opt.omega : 1.0;
   v.mu_scale = h->opt.mu_scale;
+  v.vz_diag = b.vz_diag ? 1 : 0;
+  v.Vd = b.vzd;
+  v.Zd = b.vzd ? b.vzd + h->p : nullptr;
+  v.Vd32 = b.vzd32;
+  v.Zd32 = b.vzd32 ? b.vzd32 + h->p : nullptr;
   // the coarsest level's block solves (inside the coarse SGS) take one step
   // per work-group: at 8 steps the one-step kernel has the shorter latency
   if (l == h->L - 1 && v.sweep_cfg == 0 && jacobi_tiled_supported(h->p, h->q))
@@ -446,6 +454,42 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
     if (!rc) rc = timed(h, 0, [&] { return launch_to_f32(b.V32, b.V, cV, h->stream); });
     if (!rc) rc = timed(h, 0, [&] { return launch_to_f32(b.Z32, b.Z, cZ, h->stream); });
     if (rc) return rc;
+  }
+  // shared V and Z~ that are diagonal (theta = 1 with an identity mass matrix
+  // and distributed control) are used through their diagonals
+  {
+    const bool cand = h->p == h->q && pb->V_stride == 0 && pb->Z_stride == 0;
+    std::vector<double> hv(cand ? pp : 0), hz(cand ? pp : 0), dg(2 * (size_t)h->p);
+    for (int l = 0; l < h->L; ++l) {
+      LevelBuf& b = h->lv[l];
+      b.vz_diag = false;
+      if (!cand) continue;
+      HIPCHK(h, hipMemcpyAsync(hv.data(), b.V, pp * 8, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipMemcpyAsync(hz.data(), b.Z, pp * 8, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      bool diag = true;
+      for (int i = 0; i < h->p && diag; ++i)
+        for (int j = 0; j < h->p; ++j)
+          if (i != j && (hv[(size_t)i * h->p + j] != 0.0 || hz[(size_t)i * h->p + j] != 0.0)) {
+            diag = false;
+            break;
+          }
+      if (!diag) continue;
+      for (int i = 0; i < h->p; ++i) {
+        dg[i] = hv[(size_t)i * h->p + i];
+        dg[h->p + i] = hz[(size_t)i * h->p + i];
+      }
+      HIPCHK(h, hipMemcpyAsync(b.vzd, dg.data(), 2 * (size_t)h->p * 8, hipMemcpyHostToDevice,
+                               h->stream));
+      if (b.fp32) {
+        const int rc = timed(h, 0, [&] {
+          return launch_to_f32(b.vzd32, b.vzd, 2LL * h->p, h->stream);
+        });
+        if (rc) return rc;
+      }
+      HIPCHK(h, hipStreamSynchronize(h->stream));        // dg is reused per level
+      b.vz_diag = true;
+    }
   }
   if (factor_mfma_supported(h->p, h->q)) {
     // the levels of each element type in one launch on the matrix cores; the
@@ -1615,6 +1659,8 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
     } else {
       if ((rc = dalloc(h, (void**)&b.Gi, (size_t)b.n * pp * 8))) return fail(rc);
     }
+    if ((rc = dalloc(h, (void**)&b.vzd, 2 * (size_t)h->p * 8))) return fail(rc);
+    if (b.fp32 && (rc = dalloc(h, (void**)&b.vzd32, 2 * (size_t)h->p * 4))) return fail(rc);
     if (l > 0) {
       if ((rc = dalloc(h, (void**)&b.b, b.len * 8))) return fail(rc);
       if ((rc = dalloc(h, (void**)&b.out, b.len * 8))) return fail(rc);
@@ -1996,6 +2042,14 @@ int pitmg_failed_block(const pitmg_handle* h, int* level, int* k) {
 
 long long pitmg_device_bytes(const pitmg_handle* h) { return h ? h->dev_bytes : 0; }
 
+int pitmg_level_info(const pitmg_handle* h, int level, int* n, int* flags) {
+  if (!h || level < 0 || level >= h->L) return PITMG_ERR_INVALID;
+  const LevelBuf& b = h->lv[level];
+  if (n) *n = b.n;
+  if (flags) *flags = (b.fp32 ? PITMG_LEVEL_FP32 : 0) | (b.vz_diag ? PITMG_LEVEL_DIAG_VZ : 0);
+  return PITMG_OK;
+}
+
 const char* pitmg_status_string(int code) {
   switch (code) {
     case PITMG_OK: return "ok";
@@ -2041,6 +2095,8 @@ void pitmg_destroy(pitmg_handle* h) {
     release(b.y1);
     release(b.out);
     release(b.res);
+    release(b.vzd);
+    release(b.vzd32);
     release(b.b2);
     release(b.e2);
     release(b.Phi);

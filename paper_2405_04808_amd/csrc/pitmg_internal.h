@@ -49,6 +49,14 @@ struct LevelView {
   // coarser one (interpolation multiplies coarse mu by it, restriction
   // weights the mu residual rows by it)
   double mu_scale = 1.0;
+  // V and Z~ shared by every step and diagonal (p == q; theta = 1 with an
+  // identity mass matrix and distributed control): the sweeps and the apply
+  // use their diagonals Vd, Zd (p values each) instead of the dense blocks
+  int vz_diag = 0;
+  const double* Vd = nullptr;
+  const double* Zd = nullptr;
+  const float* Vd32 = nullptr;
+  const float* Zd32 = nullptr;
 };
 
 // Block pointers of a level in the arithmetic of the smoother.
@@ -60,6 +68,8 @@ struct Mats<double> {
   __host__ __device__ static const double* V(const LevelView& L) { return L.V; }
   __host__ __device__ static const double* Z(const LevelView& L) { return L.Z; }
   __host__ __device__ static const double* Gi(const LevelView& L) { return L.Gi; }
+  __host__ __device__ static const double* Vd(const LevelView& L) { return L.Vd; }
+  __host__ __device__ static const double* Zd(const LevelView& L) { return L.Zd; }
 };
 template <>
 struct Mats<float> {
@@ -67,6 +77,8 @@ struct Mats<float> {
   __host__ __device__ static const float* V(const LevelView& L) { return L.V32; }
   __host__ __device__ static const float* Z(const LevelView& L) { return L.Z32; }
   __host__ __device__ static const float* Gi(const LevelView& L) { return L.Gi32; }
+  __host__ __device__ static const float* Vd(const LevelView& L) { return L.Vd32; }
+  __host__ __device__ static const float* Zd(const LevelView& L) { return L.Zd32; }
 };
 
 // Offsets of the five variable types in a type-major vector of n steps.

@@ -125,10 +125,10 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   for (int i = tid; i < P; i += kTiledThreads) {
     const double uo = weigh(w, (double)TS::u_of(scr, sru, i), prev, 0, k, i);
     ynew[Tm.u + kk * P + i] = uo;
-    ynew[Tm.z + kk * P + i] = weigh(w, (double)TS::z_of(scr, srz, i), prev, 2, k, i);
+    ynew[Tm.z + kk * P + i] = weigh(w, (double)TS::z_of(L, scr, srz, slam, i), prev, 2, k, i);
     ynew[Tm.l + kk * P + i] = weigh(w, (double)slam[i], prev, 3, k, i);
     if (hv) {
-      const double mo = weigh(w, (double)TS::mu_of(scr, srm, srv, i), prev, 4, k - 1, i);
+      const double mo = weigh(w, (double)TS::mu_of(L, scr, srm, srv, slam, i), prev, 4, k - 1, i);
       ynew[Tm.m + (kk - 1) * P + i] = mo;
       ynew[Tm.v + (kk - 1) * P + i] = weigh(w, -(double)srm[i], prev, 1, k - 1, i);
       if (ru_m) fr.put_u(ru_m, i, ya(Tm.m + (kk - 1) * P + i) - mo, b, Tm, Tc, P);
@@ -324,13 +324,13 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   double uo1 = 0.0, mo1 = 0.0, zo1 = 0.0, lo1 = 0.0, vo1 = 0.0;
   if (on) {
     uo1 = weigh(w, (double)TS::u_of(scr, sru, i), prev, 0, k, i);
-    zo1 = weigh(w, (double)TS::z_of(scr, srz, i), prev, 2, k, i);
+    zo1 = weigh(w, (double)TS::z_of(L, scr, srz, slam, i), prev, 2, k, i);
     lo1 = weigh(w, (double)slam[i], prev, 3, k, i);
     coherent_store(y1 + Tm.u + kk * P + i, uo1);                    // read by block k+1
     y1[Tm.z + kk * P + i] = zo1;
     y1[Tm.l + kk * P + i] = lo1;
     if (hv) {
-      mo1 = weigh(w, (double)TS::mu_of(scr, srm, srv, i), prev, 4, k - 1, i);
+      mo1 = weigh(w, (double)TS::mu_of(L, scr, srm, srv, slam, i), prev, 4, k - 1, i);
       vo1 = weigh(w, -(double)srm[i], prev, 1, k - 1, i);
       coherent_store(y1 + Tm.m + (kk - 1) * P + i, mo1);            // read by block k-1
       y1[Tm.v + (kk - 1) * P + i] = vo1;
@@ -348,10 +348,10 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   if (on) {
     const double uo = weigh1((double)TS::u_of(scr, sru, i), uo1);
     y2[Tm.u + kk * P + i] = uo;
-    y2[Tm.z + kk * P + i] = weigh1((double)TS::z_of(scr, srz, i), zo1);
+    y2[Tm.z + kk * P + i] = weigh1((double)TS::z_of(L, scr, srz, slam, i), zo1);
     y2[Tm.l + kk * P + i] = weigh1((double)slam[i], lo1);
     if (hv) {
-      const double mo = weigh1((double)TS::mu_of(scr, srm, srv, i), mo1);
+      const double mo = weigh1((double)TS::mu_of(L, scr, srm, srv, slam, i), mo1);
       y2[Tm.m + (kk - 1) * P + i] = mo;
       y2[Tm.v + (kk - 1) * P + i] = weigh1(-(double)srm[i], vo1);
       if (ru_m) fr.put_u(ru_m, i, fr.a * mo1 - mo, b, Tm, Tc, P);
@@ -470,7 +470,16 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
   __syncthreads();
 
   // sT[s] = Z~ r_z[s] - V r_mu[s] for every step: one pass over Z~ and V
-  {
+  // (elementwise when they are diagonal)
+  const bool dg = L.vz_diag != 0;
+  if (dg) {
+    const T* __restrict__ Vd = Mats<T>::Vd(L);
+    const T* __restrict__ Zd = Mats<T>::Zd(L);
+    for (int idx = tid; idx < nb * P; idx += kTiledThreads) {
+      const int s = idx / P, i = idx % P;
+      sT[s][i] = Zd[i] * srz[s][i] - Vd[i] * srm[s][i];
+    }
+  } else {
     T acc[kMaxSteps][RT];
 #pragma unroll
     for (int s = 0; s < kMaxSteps; ++s)
@@ -570,7 +579,7 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
 
   // Z~^T lambda and V^T lambda for every step: one pass over Z~ and V.
   // Thread (j, g) = (tid % P, tid / P) sums rows i = g, g+G, ...
-  {
+  if (!dg) {
     const int j = tid % P, g = tid / P;
     T za[kMaxSteps], va[kMaxSteps];
 #pragma unroll
@@ -599,10 +608,15 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_shared(
     const int s = idx / P, i = idx % P;
     const long long kk = k0 + s - 1;
     T zt = 0, vt = 0;
+    if (dg) {
+      zt = Mats<T>::Zd(L)[i] * slam[s][i];
+      vt = Mats<T>::Vd(L)[i] * slam[s][i];
+    } else {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      zt += pz[g][s][i];
-      vt += pv[g][s][i];
+      for (int g = 0; g < G; ++g) {
+        zt += pz[g][s][i];
+        vt += pv[g][s][i];
+      }
     }
     const int k = (int)kk + 1;
     ynew[Tm.z + kk * P + i] = weigh(w, (double)(srz[s][i] - zt), prev, 2, k, i);
@@ -755,8 +769,15 @@ __device__ __forceinline__ void shared_nl_sweep(
   }
   __syncthreads();
 
-  // sT[s] = Z~ r_z[s] - V r_mu[s] - r_lambda[s] for every step
-  {
+  // sT[s] = Z~ r_z[s] - V r_mu[s] - r_lambda[s] for every step (elementwise
+  // when V and Z~ are diagonal)
+  const bool dg = L.vz_diag != 0;
+  if (dg) {
+    for (int idx = tid; idx < nb * P; idx += kTiledThreads) {
+      const int s2 = idx / P, i = idx % P;
+      sT[s2][i] = L.Zd[i] * srz[s2 * P + i] - L.Vd[i] * srm[s2 * P + i] - srl[s2 * P + i];
+    }
+  } else {
     double acc[kMaxSteps][RT];
 #pragma unroll
     for (int s2 = 0; s2 < kMaxSteps; ++s2)
@@ -863,7 +884,7 @@ __device__ __forceinline__ void shared_nl_sweep(
   // buffer), then every output of the work-group
   double* pz = nbuf;                                     // [G][kMaxSteps][P]
   double* pv = nbuf + G * kMaxSteps * P;
-  {
+  if (!dg) {
     const int j = tid % P, g = tid / P;
     double za[kMaxSteps], va[kMaxSteps];
 #pragma unroll
@@ -905,10 +926,15 @@ __device__ __forceinline__ void shared_nl_sweep(
     const int k = k0 + s2;
     const long long kk = k - 1;
     double zt = 0, vt = 0;
+    if (dg) {
+      zt = L.Zd[i] * slam[s2][i];
+      vt = L.Vd[i] * slam[s2][i];
+    } else {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      zt += pz[(g * kMaxSteps + s2) * P + i];
-      vt += pv[(g * kMaxSteps + s2) * P + i];
+      for (int g = 0; g < G; ++g) {
+        zt += pz[(g * kMaxSteps + s2) * P + i];
+        vt += pv[(g * kMaxSteps + s2) * P + i];
+      }
     }
     const int rm_m = fr.mu_writer(k);
     const int ru_m = k >= 2 ? fr.u_writer(k) : 0;
@@ -1101,7 +1127,14 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_apply_shared(
   }
   __syncthreads();
   // svz[s] = V v_{k-1} + Z z_k for every step: one pass over V and Z~
-  {
+  // (elementwise when they are diagonal)
+  const bool dg = L.vz_diag != 0;
+  if (dg) {
+    for (int idx = tid; idx < nb * P; idx += kTiledThreads) {
+      const int s = idx / P, i = idx % P;
+      svz[s][i] = L.Vd[i] * sxv[s][i] + L.Zd[i] * sxz[s][i];
+    }
+  } else {
     double acc[kMaxSteps][RT];
 #pragma unroll
     for (int s = 0; s < kMaxSteps; ++s)
@@ -1161,7 +1194,7 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_apply_shared(
     __syncthreads();
   }
   // Z^T lambda and V^T lambda for every step: one pass over Z~ and V
-  {
+  if (!dg) {
     const int j = tid % P, g = tid / P;
     double za[kMaxSteps], va[kMaxSteps];
 #pragma unroll
@@ -1190,10 +1223,15 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_apply_shared(
     const int s = idx / P, i = idx % P;
     const long long kk = k0 + s - 1;
     double zt = 0, vt = 0;
+    if (dg) {
+      zt = L.Zd[i] * sl[s][i];
+      vt = L.Vd[i] * sl[s][i];
+    } else {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      zt += pz[g][s][i];
-      vt += pv[g][s][i];
+      for (int g = 0; g < G; ++g) {
+        zt += pz[g][s][i];
+        vt += pv[g][s][i];
+      }
     }
     put(Tm.z + kk * P + i, sxz[s][i] + zt);
     if (kk >= 1) {

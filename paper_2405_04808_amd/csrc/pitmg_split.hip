@@ -269,6 +269,31 @@ hipError_t gemm_rows(int m, int P, int K, double alpha, const T* A, long long ld
                   C);
 }
 
+// The same row products when V and Z~ are diagonal: C[r][j] = a A[r][j] d[j]
+// (+ a2 A2[r][j] d2[j] when A2 is given), for m rows of P.
+template <class T>
+__global__ void k_diag_rows(int m, int P, const T* __restrict__ A, long long lda,
+                            const T* __restrict__ d, double a, const T* __restrict__ A2,
+                            long long lda2, const T* __restrict__ d2, double a2,
+                            T* __restrict__ C) {
+  const long long total = (long long)m * P;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / P;
+    const int j = (int)(e % P);
+    double v = a * (double)A[r * lda + j] * (double)d[j];
+    if (A2) v += a2 * (double)A2[r * lda2 + j] * (double)d2[j];
+    C[r * P + j] = (T)v;
+  }
+}
+
+template <class T>
+hipError_t diag_rows(int m, int P, const T* A, long long lda, const T* d, double a, const T* A2,
+                     long long lda2, const T* d2, double a2, T* C, hipStream_t s) {
+  return launch_k(k_diag_rows<T>, dim3(grid_for_split((long long)m * P)), dim3(256), 0, s, m,
+                  P, A, lda, d, a, A2, lda2, d2, a2, C);
+}
+
 template <int RT, int CT, class T>
 hipError_t run_split(const LevelView& L, const SplitBuffers& S, const double* b,
                      const double* yold, const double* ecoarse, int variant, double* ynew,
@@ -290,8 +315,15 @@ hipError_t run_split(const LevelView& L, const SplitBuffers& S, const double* b,
   const T* Rz = f32 ? (const T*)S.Rz32 : (const T*)(b + Tm.z);
   const T* Rm = f32 ? (const T*)S.Rm32 : (const T*)S.Rm;
   // per step k (rows): U_k = Z~ r_z,k - V r_mu,k, i.e. U = R_z Z~^T - R_mu V^T
-  if ((e = gemm_rows<T, true>(n, P, q, 1.0, Rz, q, Z, 0.0, U, s))) return e;
-  if ((e = gemm_rows<T, true>(n, P, P, -1.0, Rm, P, V, 1.0, U, s))) return e;
+  // (elementwise when V and Z~ are diagonal)
+  const bool dg = L.vz_diag != 0;
+  if (dg) {
+    if ((e = diag_rows<T>(n, P, Rz, q, Mats<T>::Zd(L), 1.0, Rm, P, Mats<T>::Vd(L), -1.0, U, s)))
+      return e;
+  } else {
+    if ((e = gemm_rows<T, true>(n, P, q, 1.0, Rz, q, Z, 0.0, U, s))) return e;
+    if ((e = gemm_rows<T, true>(n, P, P, -1.0, Rm, P, V, 1.0, U, s))) return e;
+  }
   const size_t lds = split_lds(P, sizeof(T));
   e = hipFuncSetAttribute((const void*)k_split_blocks<RT, CT, T>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -301,8 +333,15 @@ hipError_t run_split(const LevelView& L, const SplitBuffers& S, const double* b,
   if (e != hipSuccess) return e;
   // W_z,k = Z~^T lambda_k, W_v,k = V^T lambda_k: W = Lambda Z~, Lambda V
   const T* Lam = f32 ? (const T*)S.L32 : (const T*)(ynew + Tm.l);
-  if ((e = gemm_rows<T, false>(n, q, P, 1.0, Lam, P, Z, 0.0, Wz, s))) return e;
-  if ((e = gemm_rows<T, false>(n, P, P, 1.0, Lam, P, V, 0.0, Wv, s))) return e;
+  if (dg) {
+    if ((e = diag_rows<T>(n, P, Lam, P, Mats<T>::Zd(L), 1.0, nullptr, 0, nullptr, 0.0, Wz, s)))
+      return e;
+    if ((e = diag_rows<T>(n, P, Lam, P, Mats<T>::Vd(L), 1.0, nullptr, 0, nullptr, 0.0, Wv, s)))
+      return e;
+  } else {
+    if ((e = gemm_rows<T, false>(n, q, P, 1.0, Lam, P, Z, 0.0, Wz, s))) return e;
+    if ((e = gemm_rows<T, false>(n, P, P, 1.0, Lam, P, V, 0.0, Wv, s))) return e;
+  }
   return launch_k(k_split_finish<T>, dim3(grid_for_split((long long)(P + q) * n)), dim3(256), 0,
                   s, P, q, n, b, (const double*)S.Rm, (const T*)Wz, (const T*)Wv, ynew);
 }

@@ -155,6 +155,9 @@ struct TiledSolve {
     T* red = scr + 2 * P;
     const T* __restrict__ Vk = Mats<T>::V(L) + kk * L.sV;
     const T* __restrict__ Zk = Mats<T>::Z(L) + kk * L.sZ;
+    const bool dg = L.vz_diag != 0;                      // diagonal shared V, Z~
+    const T* __restrict__ Vd = Mats<T>::Vd(L);
+    const T* __restrict__ Zd = Mats<T>::Zd(L);
     // t = N r_u + Z r_z - V r_m - r_l
     T acc[RT];
 #pragma unroll
@@ -162,21 +165,28 @@ struct TiledSolve {
       T s = 0;
 #pragma unroll
       for (int c = 0; c < CT; ++c) s += R.nt[r][c] * sru[tile_col<T>(c)];
-      T zr[CT];
-      tile_load_row<CT, T>(Zk + (long long)(r0 + r) * P, zr);
+      if (!dg) {
+        T zr[CT];
+        tile_load_row<CT, T>(Zk + (long long)(r0 + r) * P, zr);
 #pragma unroll
-      for (int c = 0; c < CT; ++c) s += zr[c] * srz[tile_col<T>(c)];
-      if (hv) {
-        T vr[CT];
-        tile_load_row<CT, T>(Vk + (long long)(r0 + r) * P, vr);
+        for (int c = 0; c < CT; ++c) s += zr[c] * srz[tile_col<T>(c)];
+        if (hv) {
+          T vr[CT];
+          tile_load_row<CT, T>(Vk + (long long)(r0 + r) * P, vr);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) s -= vr[c] * srm[tile_col<T>(c)];
+          for (int c = 0; c < CT; ++c) s -= vr[c] * srm[tile_col<T>(c)];
+        }
       }
       acc[r] = tile_sum16(s);
     }
     if (bq == 0) {
 #pragma unroll
-      for (int r = 0; r < RT; ++r) st[r0 + r] = acc[r] - srl[r0 + r];
+      for (int r = 0; r < RT; ++r) {
+        const int i = r0 + r;
+        T d = 0;
+        if (dg) d = Zd[i] * srz[i] - (hv ? Vd[i] * srm[i] : T(0));
+        st[i] = acc[r] + d - srl[i];
+      }
     }
     __syncthreads();
     // s = G^{-1} t
@@ -214,7 +224,7 @@ struct TiledSolve {
       cacc[c] = s;
     }
     col_partial(cacc, red);
-    {
+    if (!dg) {
       T zacc[CT];
 #pragma unroll
       for (int c = 0; c < CT; ++c) zacc[c] = 0;
@@ -227,7 +237,7 @@ struct TiledSolve {
       }
       col_partial(zacc, red + kTiledWaves * P);
     }
-    if (hv) {
+    if (hv && !dg) {
       T vacc[CT];
 #pragma unroll
       for (int c = 0; c < CT; ++c) vacc[c] = 0;
@@ -245,14 +255,19 @@ struct TiledSolve {
 
   // Component i of the solution after solve():
   //   u = r_u - N^T lambda, z = r_z - Z^T lambda, mu = V^T lambda - r_m - r_v,
-  //   v = -r_m   (lambda is ol[i]).
+  //   v = -r_m   (lambda is ol[i]; with diagonal V, Z~ their products with
+  //   lambda are elementwise).
   __device__ __forceinline__ static T u_of(const T* scr, const T* sru, int i) {
     return sru[i] - col_total(scr + 2 * P, i);
   }
-  __device__ __forceinline__ static T z_of(const T* scr, const T* srz, int i) {
+  __device__ __forceinline__ static T z_of(const LevelView& L, const T* scr, const T* srz,
+                                           const T* ol, int i) {
+    if (L.vz_diag) return srz[i] - Mats<T>::Zd(L)[i] * ol[i];
     return srz[i] - col_total(scr + 2 * P + kTiledWaves * P, i);
   }
-  __device__ __forceinline__ static T mu_of(const T* scr, const T* srm, const T* srv, int i) {
+  __device__ __forceinline__ static T mu_of(const LevelView& L, const T* scr, const T* srm,
+                                            const T* srv, const T* ol, int i) {
+    if (L.vz_diag) return Mats<T>::Vd(L)[i] * ol[i] - srm[i] - srv[i];
     return col_total(scr + 2 * P + 2 * kTiledWaves * P, i) - srm[i] - srv[i];
   }
 };

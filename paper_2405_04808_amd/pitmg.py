@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
         "pitmg_profile_sample": (i, [vp, i]),
         "pitmg_failed_block": (i, [vp, C.POINTER(i), C.POINTER(i)]),
         "pitmg_device_bytes": (C.c_longlong, [vp]),
+        "pitmg_level_info": (i, [vp, i, C.POINTER(i), C.POINTER(i)]),
         "pitmg_net_param_count": (C.c_longlong, [i, i]),
         "pitmg_net_create": (i, [C.POINTER(vp), i, i, i, i, vp]),
         "pitmg_net_set_params": (i, [vp, vp, i]),
@@ -364,6 +365,13 @@ class Solver:
 
     def device_bytes(self) -> int:
         return self.lib.pitmg_device_bytes(self.h)
+
+    def level_info(self, level: int) -> dict:
+        """Step count and sweep form of one level: fp32 (FP32 sweeps) and
+        diag_vz (shared diagonal V and Z~ used through their diagonals)."""
+        n, f = C.c_int(), C.c_int()
+        self._check(self.lib.pitmg_level_info(self.h, level, C.byref(n), C.byref(f)))
+        return dict(n=n.value, fp32=bool(f.value & 1), diag_vz=bool(f.value & 2))
 
     def autotune(self):
         """Pick each level's sweep launch shape by timing; returns the choices."""

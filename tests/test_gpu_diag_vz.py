@@ -1,0 +1,133 @@
+"""GPU parity of the two forms of the shared-block sweeps and products.
+
+With theta = 1, an identity mass matrix and distributed control, V_k = -I/dt
+and Z~_k = -I/gamma for every step (Sec. 6), and the library detects this at
+set-up and runs its sweeps and products on the diagonals alone.  A mass
+matrix with nearest-neighbour couplings makes V a dense shared block, which
+takes the general path.  Both are checked against the FP64 oracle (apply,
+sweep, V-cycle in fixed-coarse-step mode, FGMRES), and a problem whose mass
+matrix couplings are 1e-300 (dense path, same numbers to rounding) against
+the diagonal one, so that the two forms are seen to compute the same map.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from workloads import make_problem, make_rhs
+from oracle import Hierarchy, OracleLevel
+import paper_2405_04808_amd as pm
+from parity_util import (rel, dev, host, mg_opts, omega_at, sweep_ref, assert_types,
+                         sweep_tol, coarse_identity_tol)
+
+pytestmark = pytest.mark.gpu
+
+# p = 64, 128: register-tiled shared sweeps; p = 256: split sweep
+SHAPES = {
+    "p64": dict(kind="burgers", nx=64, nu=0.01, n=32, n_levels=3, seed=41),
+    "p128": dict(kind="burgers", nx=128, nu=0.01, n=16, n_levels=2, seed=42),
+    "p256": dict(kind="burgers", nx=256, nu=0.01, n=8, n_levels=2, seed=43),
+}
+
+
+def build(name, mass_offdiag=0.0, **opt):
+    prob, rng = make_problem(**SHAPES[name], mass_offdiag=mass_offdiag)
+    s = pm.Solver(prob.levels, pm.default_options(**opt))
+    return prob, rng, s
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_diagonal_detected_only_for_diagonal_blocks(name, fp32):
+    for md, want in ((0.0, True), (0.1, False), (1e-300, False)):
+        prob, _, s = build(name, md, smoother_fp32=fp32)
+        for lev in range(prob.n_levels):
+            info = s.level_info(lev)
+            assert info["n"] == prob.levels[lev].n
+            assert info["diag_vz"] is want, (name, md, lev)
+            assert info["fp32"] is bool(fp32 and lev < fp32), (name, lev, info)
+        s.close()
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+@pytest.mark.parametrize("md", [0.0, 0.1])
+def test_apply_and_sweep_match_oracle(name, md):
+    prob, rng, s = build(name, md)
+    for lev, lv in enumerate(prob.levels):
+        ol = OracleLevel(lv.N, lv.V, lv.Z)
+        m = ol.A.shape[0]
+        x = rng.normal(size=m)
+        assert_types(host(s.apply(dev(x), level=lev)), ol.A @ x, prob.p, prob.q, lv.n, 1e-13,
+                     (name, md, lev, "apply"))
+        w = omega_at(s.options, lev, prob.n_levels)
+        bb = rng.normal(size=m)
+        y = rng.normal(size=m)
+        tol = sweep_tol(lv)
+        got = host(s.jacobi_sweep(dev(bb), dev(y), level=lev))
+        assert_types(got, sweep_ref(ol, bb, y, w), prob.p, prob.q, lv.n, tol, (name, md, lev))
+        got0 = host(s.jacobi_sweep(dev(bb), None, level=lev))
+        assert_types(got0, sweep_ref(ol, bb, None, w), prob.p, prob.q, lv.n, tol,
+                     (name, md, lev, "zero"))
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["p64", "p256"])
+@pytest.mark.parametrize("md", [0.0, 0.1])
+@pytest.mark.parametrize("nu", [1, 2, 3])
+def test_vcycle_matches_oracle(name, md, nu):
+    """Fixed coarse steps make the cycle a fixed linear map; nu = 1, 2 take
+    the fused residual of the two-sweep kernels, nu = 3 the explicit one."""
+    prob, rng, s = build(name, md, coarse_fixed_its=2, nu_pre=nu, nu_post=nu)
+    H = Hierarchy(prob.levels, mg_opts(s.options))
+    r = rng.normal(size=H.levels[0].A.shape[0])
+    got = host(s.vcycle(dev(r)))
+    assert_types(got, H.vcycle(r), prob.p, prob.q, prob.n, coarse_identity_tol(prob),
+                 (name, md, nu))
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_fgmres_dense_mass_matrix(name, fp32):
+    """A dense shared V (non-diagonal mass matrix) solved to 1e-10 on the
+    true residual, FP64 and FP32 sweeps, iteration count near the oracle's."""
+    prob, rng, s = build(name, 0.1, smoother_fp32=fp32, restart=200, maxit=400)
+    b = make_rhs(prob, rng)
+    x, st, rc = s.solve(dev(b), tol=1e-10)
+    assert rc == pm.PITMG_OK and st["converged"] == 1, st
+    x = host(x)
+    A = OracleLevel(prob.levels[0].N, prob.levels[0].V, prob.levels[0].Z).A
+    true = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert true <= 1e-10 * 1.01, (name, fp32, st)
+    H = Hierarchy(prob.levels, mg_opts(s.options))
+    _, info = H.solve(b, tol=1e-10, restart=200, maxit=400)
+    print(f"{name} fp32={fp32}: gpu {st['iters']} steps, oracle {info['iters']}", flush=True)
+    assert abs(st["iters"] - info["iters"]) <= (1 if not fp32 else max(2, info["iters"] // 10))
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_diagonal_and_dense_forms_agree(name, fp32):
+    """The same problem through the diagonal form and (couplings of 1e-300,
+    below every rounding error) through the dense form: sweeps and cycles
+    agree to rounding (FP64) or to the FP32 smoother's precision."""
+    prob_d, rng, s_d = build(name, 0.0, coarse_fixed_its=2, smoother_fp32=fp32)
+    prob_g, _, s_g = build(name, 1e-300, coarse_fixed_its=2, smoother_fp32=fp32)
+    assert s_d.level_info(0)["diag_vz"] and not s_g.level_info(0)["diag_vz"]
+    tol = 1e-5 if fp32 else 1e-12
+    for lev, lv in enumerate(prob_d.levels[:-1]):
+        m = OracleLevel(lv.N, lv.V, lv.Z).A.shape[0]
+        bb = dev(rng.normal(size=m))
+        y = dev(rng.normal(size=m))
+        a = host(s_d.jacobi_sweep(bb, y, level=lev))
+        g = host(s_g.jacobi_sweep(bb, y, level=lev))
+        assert_types(a, g, prob_d.p, prob_d.q, lv.n, tol, (name, lev, "sweep"))
+        x = dev(rng.normal(size=m))
+        assert_types(host(s_d.apply(x, level=lev)), host(s_g.apply(x, level=lev)),
+                     prob_d.p, prob_d.q, lv.n, 1e-14, (name, lev, "apply"))
+    r = dev(rng.normal(size=OracleLevel(prob_d.levels[0].N, prob_d.levels[0].V,
+                                        prob_d.levels[0].Z).A.shape[0]))
+    assert rel(host(s_d.vcycle(r)), host(s_g.vcycle(r))) <= (1e-5 if fp32 else 1e-11)
+    s_d.close()
+    s_g.close()

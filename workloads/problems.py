@@ -201,7 +201,8 @@ def make_problem(kind: str, n: int, n_levels: int, seed: int, *, p: int = None,
                  state_scale: float = 0.5, control_scale: float = 0.5,
                  noise: float = 0.1, transfer_variant: int = 0,
                  compress: bool = True, rng: Optional[np.random.Generator] = None,
-                 coarsen: int = 2) -> Tuple[Problem, np.random.Generator]:
+                 coarsen: int = 2, mass_offdiag: float = 0.0
+                 ) -> Tuple[Problem, np.random.Generator]:
     """Build a seeded problem hierarchy.
 
     Draw order with ``np.random.default_rng(seed)`` (the right-hand side is
@@ -209,6 +210,9 @@ def make_problem(kind: str, n: int, n_levels: int, seed: int, *, p: int = None,
       van der Pol: w (n,2) ~ N(0, state_scale^2), zeta (n,q) ~ N(0, control_scale^2)
       Burgers:     xi (n,nx) ~ N(0,1), w = sin(pi x) + noise*xi,
                    zeta (n,nx) ~ N(0, control_scale^2)
+    mass_offdiag (Burgers): M = I + mass_offdiag * (the nearest-neighbour
+    couplings), a non-diagonal mass matrix (so V_k = -M/dt is a dense shared
+    block) for exercising the general block paths; 0 gives M = I.
     """
     if n % (coarsen ** (n_levels - 1)) != 0:
         raise ValueError("n must be divisible by coarsen^(n_levels-1)")
@@ -233,6 +237,9 @@ def make_problem(kind: str, n: int, n_levels: int, seed: int, *, p: int = None,
         jac = burgers_jacobians(nx, nu)
         w0 = np.sin(np.pi * x)
         params = dict(nu=nu, nx=nx)
+        if mass_offdiag:
+            M = np.eye(nx) + mass_offdiag * (np.eye(nx, k=1) + np.eye(nx, k=-1))
+            params["M"] = M
     else:
         raise ValueError(f"unknown problem kind {kind!r}")
 
@@ -241,7 +248,8 @@ def make_problem(kind: str, n: int, n_levels: int, seed: int, *, p: int = None,
     for lev in range(n_levels):
         nl = n // coarsen ** lev
         dt = T / nl
-        levels.append(lifted_blocks(wl, zl, w0, dt, theta, gamma, jac, compress=compress))
+        levels.append(lifted_blocks(wl, zl, w0, dt, theta, gamma, jac, M=params.get("M"),
+                                    compress=compress))
         if lev + 1 < n_levels:
             wl, zl = coarsen_point(wl, zl, transfer_variant, coarsen)
     prob = Problem(kind=kind, p=p, q=q, n=n, n_levels=n_levels, gamma=gamma,
