@@ -471,11 +471,14 @@ long long pitmg_device_bytes(const pitmg_handle* h);
  * a bit set: PITMG_LEVEL_FP32 when its sweeps run in FP32, and
  * PITMG_LEVEL_DIAG_VZ when V and Z~ are shared by every step and diagonal
  * (theta = 1 with an identity mass matrix and distributed control, Sec. 6),
- * so the sweeps and products use their diagonals alone.  Either pointer may
- * be NULL.  Returns PITMG_ERR_INVALID for a NULL handle or a level out of
- * range. */
+ * so the sweeps and products use their diagonals alone, and
+ * PITMG_LEVEL_GIN when the level also keeps W_k = G_k^{-1} N_k for its
+ * one-step sweeps (FP64, p = q in {64, 128}, diagonal V and Z~).  Either
+ * pointer may be NULL.  Returns PITMG_ERR_INVALID for a NULL handle or a
+ * level out of range. */
 #define PITMG_LEVEL_FP32 1
 #define PITMG_LEVEL_DIAG_VZ 2
+#define PITMG_LEVEL_GIN 4
 int pitmg_level_info(const pitmg_handle* h, int level, int* n, int* flags);
 
 const char* pitmg_status_string(int code);

@@ -674,6 +674,19 @@ hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, 
   return hipGetLastError();
 }
 
+hipError_t launch_gi_times_n(const LevelView& L, double* out, hipStream_t s) {
+  if (L.p != L.q || (L.p != 64 && L.p != 128)) return hipErrorInvalidValue;
+  const size_t lds = wg_gemm_lds_doubles(L.p) * sizeof(double);
+  const void* fn = L.p == 128 ? (const void*)k_gi_times_mfma<8> : (const void*)k_gi_times_mfma<4>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (L.p == 128)
+    hipLaunchKernelGGL(k_gi_times_mfma<8>, dim3(L.n), dim3(kGemmThreads), lds, s, L, 0, out);
+  else
+    hipLaunchKernelGGL(k_gi_times_mfma<4>, dim3(L.n), dim3(kGemmThreads), lds, s, L, 0, out);
+  return hipGetLastError();
+}
+
 // Phi_k = N_k^T S_k^{-1} V_k and its transpose for every step of a level
 // (the block Gauss-Seidel smoothers' coupling, see pitmg_gs.hip):
 // W = G^{-1} N, X = G^{-1} V, Phi = W^T X, Phi^T = X^T W.

@@ -82,6 +82,13 @@ __device__ __forceinline__ double interp_node(const double* __restrict__ seg, in
   return 0.5 * (a + b);
 }
 
+// The loads behind one entry of PrevIterate::at, issued together by
+// PrevIterate::fetch and combined by PrevIterate::value (same arithmetic as
+// at()), so that a kernel can request several entries before it needs any.
+struct PrevFetch {
+  double y = 0.0, a = 0.0, b = 0.0;
+};
+
 // The iterate a sweep starts from: yold (NULL = 0) plus, in the first
 // post-smoothing sweep, the interpolated coarse correction P ec (NULL = 0),
 // whose mu block carries mu_scale and whose control is constant over the
@@ -104,6 +111,68 @@ struct PrevIterate {
       } else {
         const long long sc[5] = {Tc.u, Tc.v, Tc.z, Tc.l, Tc.m};
         const double e = interp_node(ec + sc[type], nc, p, k, i, variant);
+        v += type == 4 ? mu_scale * e : e;
+      }
+    }
+    return v;
+  }
+
+  // Coarse steps (1-based) of the one or two terms interp_node averages for
+  // fine step k; *two = 0 when there is one term (then mb = ma).
+  __device__ __forceinline__ static void node_terms(int nc, int k, int variant, int* ma,
+                                                    int* mb, int* two) {
+    if (variant == 0) {
+      if (k & 1) {
+        *ma = *mb = (k + 1) / 2;
+        *two = 0;
+      } else {
+        const int m = k / 2;
+        *ma = m;
+        *mb = m < nc ? m + 1 : nc;
+        *two = 1;
+      }
+    } else if (!(k & 1)) {
+      *ma = *mb = k / 2;
+      *two = 0;
+    } else {
+      const int m = (k + 1) / 2;
+      *ma = m;
+      *mb = m >= 2 ? m - 1 : m;                 // coarse step 0 is zero
+      *two = m >= 2 ? 1 : 2;                    // 2: the second term is 0
+    }
+  }
+
+  __device__ __forceinline__ PrevFetch fetch(int type, int k, int i) const {
+    PrevFetch f;
+    const TypeMajor Tm(p, q, n);
+    const long long seg[5] = {Tm.u, Tm.v, Tm.z, Tm.l, Tm.m};
+    const int w = type == 2 ? q : p;
+    if (yold) f.y = yold[seg[type] + (long long)(k - 1) * w + i];
+    if (ec) {
+      const int nc = n / 2;
+      const TypeMajor Tc(p, q, nc > 0 ? nc : 1);
+      if (type == 2) {
+        f.a = ec[Tc.z + (long long)((k + 1) / 2 - 1) * q + i];
+      } else {
+        const long long sc[5] = {Tc.u, Tc.v, Tc.z, Tc.l, Tc.m};
+        int ma, mb, two;
+        node_terms(nc, k, variant, &ma, &mb, &two);
+        f.a = ec[sc[type] + (long long)(ma - 1) * p + i];
+        f.b = ec[sc[type] + (long long)(mb - 1) * p + i];
+      }
+    }
+    return f;
+  }
+
+  __device__ __forceinline__ double value(const PrevFetch& f, int type, int k) const {
+    double v = yold ? f.y : 0.0;
+    if (ec) {
+      if (type == 2) {
+        v += f.a;
+      } else {
+        int ma, mb, two;
+        node_terms(n / 2, k, variant, &ma, &mb, &two);
+        const double e = two == 0 ? f.a : 0.5 * (f.a + (two == 1 ? f.b : 0.0));
         v += type == 4 ? mu_scale * e : e;
       }
     }

@@ -69,6 +69,8 @@ struct LevelBuf {
   bool vz_diag = false;              // shared V, Z~ diagonal: their diagonals in vzd
   double* vzd = nullptr;             // [Vd (p) | Zd (p)]
   float* vzd32 = nullptr;            // FP32 copy (FP32 levels)
+  double* gin = nullptr;             // W_k = G_k^{-1} N_k (one-step sweeps), or NULL
+  bool gn = false;                   // gin holds W for the current blocks
   double* b2 = nullptr;              // W / F cycles: second coarse right-hand side (l >= 1)
   double* e2 = nullptr;              //   and its correction
   // block Gauss-Seidel smoothers (levels above the coarsest)
@@ -333,6 +335,7 @@ LevelView view(const pitmg_handle* h, int l) {
   v.Zd = b.vzd ? b.vzd + h->p : nullptr;
   v.Vd32 = b.vzd32;
   v.Zd32 = b.vzd32 ? b.vzd32 + h->p : nullptr;
+  v.GiN = b.gn ? b.gin : nullptr;
   // the coarsest level's block solves (inside the coarse SGS) take one step
   // per work-group: at 8 steps the one-step kernel has the shorter latency
   if (l == h->L - 1 && v.sweep_cfg == 0 && jacobi_tiled_supported(h->p, h->q))
@@ -539,6 +542,16 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
     return set_err(h, PITMG_ERR_SINGULAR,
                    "S_k not positive definite at level " + std::to_string(code >> 20) +
                        ", step " + std::to_string((code & 0xFFFFF) + 1));
+  // W_k = G_k^{-1} N_k where the one-step sweeps take it (diagonal V, Z~)
+  for (int l = 0; l < h->L; ++l) {
+    LevelBuf& b = h->lv[l];
+    b.gn = false;
+    if (!b.gin || !b.vz_diag) continue;
+    LevelView v = view(h, l);
+    const int rc = timed(h, 0, [&] { return launch_gi_times_n(v, b.gin, h->stream); });
+    if (rc) return rc;
+    b.gn = true;
+  }
   if (h->coarse_fast) {
     LevelView vc = view(h, h->L - 1);
     int rc = timed(h, 0, [&] {
@@ -1661,6 +1674,10 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
     }
     if ((rc = dalloc(h, (void**)&b.vzd, 2 * (size_t)h->p * 8))) return fail(rc);
     if (b.fp32 && (rc = dalloc(h, (void**)&b.vzd32, 2 * (size_t)h->p * 4))) return fail(rc);
+    // W_k = G_k^{-1} N_k, used if V and Z~ turn out diagonal at factorisation
+    if (!b.fp32 && h->p == h->q && (h->p == 64 || h->p == 128) && pb->V_stride == 0 &&
+        pb->Z_stride == 0 && (rc = dalloc(h, (void**)&b.gin, (size_t)b.n * pp * 8)))
+      return fail(rc);
     if (l > 0) {
       if ((rc = dalloc(h, (void**)&b.b, b.len * 8))) return fail(rc);
       if ((rc = dalloc(h, (void**)&b.out, b.len * 8))) return fail(rc);
@@ -2046,7 +2063,9 @@ int pitmg_level_info(const pitmg_handle* h, int level, int* n, int* flags) {
   if (!h || level < 0 || level >= h->L) return PITMG_ERR_INVALID;
   const LevelBuf& b = h->lv[level];
   if (n) *n = b.n;
-  if (flags) *flags = (b.fp32 ? PITMG_LEVEL_FP32 : 0) | (b.vz_diag ? PITMG_LEVEL_DIAG_VZ : 0);
+  if (flags)
+    *flags = (b.fp32 ? PITMG_LEVEL_FP32 : 0) | (b.vz_diag ? PITMG_LEVEL_DIAG_VZ : 0) |
+             (b.gn ? PITMG_LEVEL_GIN : 0);
   return PITMG_OK;
 }
 
@@ -2097,6 +2116,7 @@ void pitmg_destroy(pitmg_handle* h) {
     release(b.res);
     release(b.vzd);
     release(b.vzd32);
+    release(b.gin);
     release(b.b2);
     release(b.e2);
     release(b.Phi);

@@ -57,6 +57,10 @@ struct LevelView {
   const double* Zd = nullptr;
   const float* Vd32 = nullptr;
   const float* Zd32 = nullptr;
+  // W_k = G_k^{-1} N_k ([n][p][p] row-major) on FP64 levels with diagonal
+  // shared V, Z~ and p = q in {64, 128}, else NULL: the one-step sweeps then
+  // take s = W r_u + G^{-1} d and N^T lambda = W^T s (pitmg_tiled.h)
+  const double* GiN = nullptr;
 };
 
 // Block pointers of a level in the arithmetic of the smoother.
@@ -70,6 +74,7 @@ struct Mats<double> {
   __host__ __device__ static const double* Gi(const LevelView& L) { return L.Gi; }
   __host__ __device__ static const double* Vd(const LevelView& L) { return L.Vd; }
   __host__ __device__ static const double* Zd(const LevelView& L) { return L.Zd; }
+  __host__ __device__ static const double* GiN(const LevelView& L) { return L.GiN; }
 };
 template <>
 struct Mats<float> {
@@ -79,6 +84,7 @@ struct Mats<float> {
   __host__ __device__ static const float* Gi(const LevelView& L) { return L.Gi32; }
   __host__ __device__ static const float* Vd(const LevelView& L) { return L.Vd32; }
   __host__ __device__ static const float* Zd(const LevelView& L) { return L.Zd32; }
+  __host__ __device__ static const float* GiN(const LevelView&) { return nullptr; }
 };
 
 // Offsets of the five variable types in a type-major vector of n steps.
@@ -263,6 +269,9 @@ hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, 
 // scratch of n p^2 doubles each).
 hipError_t launch_phi_pair(const LevelView& L, double* W, double* X, double* Phi, double* PhiT,
                            hipStream_t s);
+// W_k = G_k^{-1} N_k for every step of level L (p in {64, 128}, FP64), on
+// the matrix cores; out: [n][p][p] row-major.
+hipError_t launch_gi_times_n(const LevelView& L, double* out, hipStream_t s);
 // The chain of a block Gauss-Seidel substitution (pitmg_gs.hip): from
 // t = D^{-1} r (type-major), hat's u slots (forward, M = Phi^T) or mu slots
 // (backward, M = Phi) receive the substituted values; its other slots are

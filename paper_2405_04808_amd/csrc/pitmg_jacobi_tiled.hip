@@ -74,10 +74,11 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
     const double* __restrict__ ec, int variant, double* __restrict__ ynew, FusedRestrict fr) {
   using TS = TiledSolve<RT, CT, T>;
   constexpr int P = TS::P;
-  __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P];
+  __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P], srd[P];
   __shared__ T scr[TS::kScratch];
   const int tid = threadIdx.x;
   const int n = L.n;
+  const bool gn = Mats<T>::GiN(L) != nullptr;   // W = G^{-1} N form (diagonal V, Z~)
   const TypeMajor Tm(P, P, n);
   const int nc = n / 2;
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
@@ -103,37 +104,86 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   const int k = kb + 1;
   const bool hv = k >= 2;
   const long long kk = k - 1;
-  typename TS::Regs R;
-  TS::load(L, kk, R);                          // HBM loads in flight during the gather
-  // right-hand side with the coupling values of the previous iterate:
-  // r_u = b_u,k - mu_k, r_mu = b_mu,k-1 - u_{k-1}
-  for (int i = tid; i < P; i += kTiledThreads) {
-    sru[i] = (T)(b[Tm.u + kk * P + i] - cm(k, i));
-    srl[i] = (T)b[Tm.l + kk * P + i];
-    srz[i] = (T)b[Tm.z + kk * P + i];
+  static_assert(P <= kTiledThreads, "one entry per thread");
+  const bool on = tid < P;
+  const int i = tid;
+  const int rm_m = fr.mu_writer(k), ru_m = fr.u_writer(k);
+  // right-hand side with the coupling values of the previous iterate,
+  // r_u = b_u,k - mu_k, r_mu = b_mu,k-1 - u_{k-1}, and the previous values
+  // that weigh the output, requested before the tiles (loads complete in
+  // order, so the gather waits for these alone)
+  double bu = 0.0, bm = 0.0, rl = 0.0, rz = 0.0, rv = 0.0, cmk = 0.0, cuk = 0.0;
+  double pu = 0.0, pz = 0.0, pl = 0.0, pm = 0.0, pv = 0.0;
+  typename TS::Diag dg;
+  PrevFetch fcm, fcu, fu, fz, fl, fm, fv;
+  if (on) {
+    bu = b[Tm.u + kk * P + i];
+    rl = b[Tm.l + kk * P + i];
+    rz = b[Tm.z + kk * P + i];
+    fcm = prev.fetch(4, k, i);
     if (hv) {
-      srv[i] = (T)b[Tm.v + (kk - 1) * P + i];
-      srm[i] = (T)(b[Tm.m + (kk - 1) * P + i] - cu(k - 1, i));
-    } else {
-      srv[i] = 0;
-      srm[i] = 0;
+      rv = b[Tm.v + (kk - 1) * P + i];
+      bm = b[Tm.m + (kk - 1) * P + i];
+      fcu = prev.fetch(0, k - 1, i);
     }
+    if (w != 1.0) {
+      fu = prev.fetch(0, k, i);
+      fz = prev.fetch(2, k, i);
+      fl = prev.fetch(3, k, i);
+      if (hv) {
+        fm = prev.fetch(4, k - 1, i);
+        fv = prev.fetch(1, k - 1, i);
+      }
+    }
+    dg = TS::diag_at(L, i);
+  }
+  // a y_A of the fused restriction (restricting launches only)
+  const double yau = on && rm_m ? ya(Tm.u + kk * P + i) : 0.0;
+  const double yam = on && ru_m && hv ? ya(Tm.m + (kk - 1) * P + i) : 0.0;
+  // (1 - omega) y_prev + omega y_hat, as weigh() forms it
+  auto weigh0 = [&](double yhat, double yp) -> double {
+    return w == 1.0 ? yhat : w * yhat + (1.0 - w) * yp;
+  };
+  typename TS::Regs R;
+  __builtin_amdgcn_sched_barrier(0);           // keep the loads above ahead of the tile's
+  TS::load_raw(L, kk, gn, R);
+  __builtin_amdgcn_sched_barrier(0);
+  if (on) {
+    cmk = prev.value(fcm, 4, k);
+    if (hv) cuk = prev.value(fcu, 0, k - 1);
+    if (w != 1.0) {
+      pu = prev.value(fu, 0, k);
+      pz = prev.value(fz, 2, k);
+      pl = prev.value(fl, 3, k);
+      if (hv) {
+        pm = prev.value(fm, 4, k - 1);
+        pv = prev.value(fv, 1, k - 1);
+      }
+    }
+    sru[i] = (T)(bu - cmk);
+    srl[i] = (T)rl;
+    srz[i] = (T)rz;
+    srv[i] = (T)rv;
+    srm[i] = (T)(bm - cuk);                    // 0 for the first block (no mu row)
+    if (gn) srd[i] = TS::d_of(dg, srz, srm, srl, i);
   }
   __syncthreads();
-  TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
-  const int rm_m = fr.mu_writer(k), ru_m = fr.u_writer(k);
-  for (int i = tid; i < P; i += kTiledThreads) {
-    const double uo = weigh(w, (double)TS::u_of(scr, sru, i), prev, 0, k, i);
+  __builtin_amdgcn_sched_barrier(0);           // the factor's zeros after the gather
+  TS::mask_g(R);
+  if (gn) TS::solve_gn(R, sru, srd, slam, scr);
+  else TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
+  if (on) {
+    const double uo = weigh0((double)TS::u_of(scr, sru, i), pu);
     ynew[Tm.u + kk * P + i] = uo;
-    ynew[Tm.z + kk * P + i] = weigh(w, (double)TS::z_of(L, scr, srz, slam, i), prev, 2, k, i);
-    ynew[Tm.l + kk * P + i] = weigh(w, (double)slam[i], prev, 3, k, i);
+    ynew[Tm.z + kk * P + i] = weigh0((double)TS::z_of(L, dg, scr, srz, slam, i), pz);
+    ynew[Tm.l + kk * P + i] = weigh0((double)slam[i], pl);
     if (hv) {
-      const double mo = weigh(w, (double)TS::mu_of(L, scr, srm, srv, slam, i), prev, 4, k - 1, i);
+      const double mo = weigh0((double)TS::mu_of(L, dg, scr, srm, srv, slam, i), pm);
       ynew[Tm.m + (kk - 1) * P + i] = mo;
-      ynew[Tm.v + (kk - 1) * P + i] = weigh(w, -(double)srm[i], prev, 1, k - 1, i);
-      if (ru_m) fr.put_u(ru_m, i, ya(Tm.m + (kk - 1) * P + i) - mo, b, Tm, Tc, P);
+      ynew[Tm.v + (kk - 1) * P + i] = weigh0(-(double)srm[i], pv);
+      if (ru_m) fr.put_u(ru_m, i, yam - mo, b, Tm, Tc, P);
     }
-    if (rm_m) fr.put_mu(rm_m, i, ya(Tm.u + kk * P + i) - uo, b, Tm, Tc, P);
+    if (rm_m) fr.put_mu(rm_m, i, yau - uo, b, Tm, Tc, P);
   }
 }
 
@@ -249,9 +299,10 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   using TS = TiledSolve<RT, CT, T>;
   constexpr int P = TS::P;
   static_assert(P <= kTiledThreads, "one entry per thread");
-  __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P];
+  __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P], srd[P];
   __shared__ T scr[TS::kScratch];
   __shared__ int skb;
+  const bool gn = Mats<T>::GiN(L) != nullptr;   // W = G^{-1} N form (diagonal V, Z~)
   const int tid = threadIdx.x;
   const int n = L.n;
   const TypeMajor Tm(P, P, n);
@@ -288,25 +339,66 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   const int k = kb + 1;
   const bool hv = k >= 2;
   const long long kk = k - 1;
-  typename TS::Regs R;
-  TS::load(L, kk, R);
-  double bu = 0.0, bm = 0.0;
+  // the block's right-hand side, its couplings and the previous values that
+  // weigh the first sweep are requested before the tiles: loads complete in
+  // order, so the gather waits for these alone and the tiles arrive during it
+  double bu = 0.0, bm = 0.0, rl = 0.0, rz = 0.0, rv = 0.0, cmk = 0.0, cuk = 0.0;
+  double pu = 0.0, pz = 0.0, pl = 0.0, pm = 0.0, pv = 0.0;
+  typename TS::Diag dg;
+  PrevFetch fcm, fcu, fu, fz, fl, fm, fv;
   if (on) {
     bu = b[Tm.u + kk * P + i];
-    sru[i] = (T)(bu - prev.at(4, k, i));
-    srl[i] = (T)b[Tm.l + kk * P + i];
-    srz[i] = (T)b[Tm.z + kk * P + i];
+    rl = b[Tm.l + kk * P + i];
+    rz = b[Tm.z + kk * P + i];
+    fcm = prev.fetch(4, k, i);
     if (hv) {
-      srv[i] = (T)b[Tm.v + (kk - 1) * P + i];
+      rv = b[Tm.v + (kk - 1) * P + i];
       bm = b[Tm.m + (kk - 1) * P + i];
-      srm[i] = (T)(bm - prev.at(0, k - 1, i));
-    } else {
-      srv[i] = 0;
-      srm[i] = 0;
+      fcu = prev.fetch(0, k - 1, i);
     }
+    if (w != 1.0) {
+      fu = prev.fetch(0, k, i);
+      fz = prev.fetch(2, k, i);
+      fl = prev.fetch(3, k, i);
+      if (hv) {
+        fm = prev.fetch(4, k - 1, i);
+        fv = prev.fetch(1, k - 1, i);
+      }
+    }
+    dg = TS::diag_at(L, i);
+  }
+  // first-sweep output (1 - omega) y_prev + omega y_hat, as weigh() forms it
+  auto weigh0 = [&](double yhat, double yp) -> double {
+    return w == 1.0 ? yhat : w * yhat + (1.0 - w) * yp;
+  };
+  typename TS::Regs R;
+  __builtin_amdgcn_sched_barrier(0);           // keep the loads above ahead of the tile's
+  TS::load_raw(L, kk, gn, R);
+  __builtin_amdgcn_sched_barrier(0);
+  if (on) {
+    cmk = prev.value(fcm, 4, k);
+    if (hv) cuk = prev.value(fcu, 0, k - 1);
+    if (w != 1.0) {
+      pu = prev.value(fu, 0, k);
+      pz = prev.value(fz, 2, k);
+      pl = prev.value(fl, 3, k);
+      if (hv) {
+        pm = prev.value(fm, 4, k - 1);
+        pv = prev.value(fv, 1, k - 1);
+      }
+    }
+    sru[i] = (T)(bu - cmk);
+    srl[i] = (T)rl;
+    srz[i] = (T)rz;
+    srv[i] = (T)rv;
+    srm[i] = (T)(bm - cuk);                    // 0 for the first block (no mu row)
+    if (gn) srd[i] = TS::d_of(dg, srz, srm, srl, i);
   }
   __syncthreads();
-  TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
+  __builtin_amdgcn_sched_barrier(0);           // the factor's zeros after the gather
+  TS::mask_g(R);
+  if (gn) TS::solve_gn(R, sru, srd, slam, scr);
+  else TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
   // the work-group of block n also takes block n+1 = (v_n, mu_n), whose
   // only coupling is u_n of block n: no other work-group reads it, and
   // block n's second sweep takes mu_n from this thread's register
@@ -323,15 +415,15 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   // this block's first-sweep values stay in registers for the second sweep
   double uo1 = 0.0, mo1 = 0.0, zo1 = 0.0, lo1 = 0.0, vo1 = 0.0;
   if (on) {
-    uo1 = weigh(w, (double)TS::u_of(scr, sru, i), prev, 0, k, i);
-    zo1 = weigh(w, (double)TS::z_of(L, scr, srz, slam, i), prev, 2, k, i);
-    lo1 = weigh(w, (double)slam[i], prev, 3, k, i);
+    uo1 = weigh0((double)TS::u_of(scr, sru, i), pu);
+    zo1 = weigh0((double)TS::z_of(L, dg, scr, srz, slam, i), pz);
+    lo1 = weigh0((double)slam[i], pl);
     coherent_store(y1 + Tm.u + kk * P + i, uo1);                    // read by block k+1
     y1[Tm.z + kk * P + i] = zo1;
     y1[Tm.l + kk * P + i] = lo1;
     if (hv) {
-      mo1 = weigh(w, (double)TS::mu_of(L, scr, srm, srv, slam, i), prev, 4, k - 1, i);
-      vo1 = weigh(w, -(double)srm[i], prev, 1, k - 1, i);
+      mo1 = weigh0((double)TS::mu_of(L, dg, scr, srm, srv, slam, i), pm);
+      vo1 = weigh0(-(double)srm[i], pv);
       coherent_store(y1 + Tm.m + (kk - 1) * P + i, mo1);            // read by block k-1
       y1[Tm.v + (kk - 1) * P + i] = vo1;
     }
@@ -341,17 +433,19 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   if (on) {
     sru[i] = (T)(bu - (tail ? mon1 : coherent_load(y1 + Tm.m + kk * P + i)));
     if (hv) srm[i] = (T)(bm - coherent_load(y1 + Tm.u + (kk - 1) * P + i));
+    if (gn) srd[i] = TS::d_of(dg, srz, srm, srl, i);
   }
   __syncthreads();
-  TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
+  if (gn) TS::solve_gn(R, sru, srd, slam, scr);
+  else TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
   const int rm_m = fr.mu_writer(k), ru_m = fr.u_writer(k);
   if (on) {
     const double uo = weigh1((double)TS::u_of(scr, sru, i), uo1);
     y2[Tm.u + kk * P + i] = uo;
-    y2[Tm.z + kk * P + i] = weigh1((double)TS::z_of(L, scr, srz, slam, i), zo1);
+    y2[Tm.z + kk * P + i] = weigh1((double)TS::z_of(L, dg, scr, srz, slam, i), zo1);
     y2[Tm.l + kk * P + i] = weigh1((double)slam[i], lo1);
     if (hv) {
-      const double mo = weigh1((double)TS::mu_of(L, scr, srm, srv, slam, i), mo1);
+      const double mo = weigh1((double)TS::mu_of(L, dg, scr, srm, srv, slam, i), mo1);
       y2[Tm.m + (kk - 1) * P + i] = mo;
       y2[Tm.v + (kk - 1) * P + i] = weigh1(-(double)srm[i], vo1);
       if (ru_m) fr.put_u(ru_m, i, fr.a * mo1 - mo, b, Tm, Tc, P);

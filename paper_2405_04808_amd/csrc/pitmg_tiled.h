@@ -64,7 +64,10 @@ __device__ __forceinline__ void tile_load_row(const T* __restrict__ row, T (&dst
 }
 
 // Same for a lower-triangular row i: vectors wholly above the diagonal are
-// zero in memory and are not loaded.
+// zero in memory and are not fetched.  Every lane still issues every load
+// (such a lane re-reads its first vector, a line it has just requested, and
+// zeroes the result), so the loads are straight-line code: the compiler can
+// then wait for loads issued before the tile without waiting for the tile.
 template <int CT, class T>
 __device__ __forceinline__ void tile_load_row_lower(const T* __restrict__ row, int i,
                                                     T (&dst)[CT]) {
@@ -73,12 +76,41 @@ __device__ __forceinline__ void tile_load_row_lower(const T* __restrict__ row, i
   const T* src = row + j0;
 #pragma unroll
   for (int c = 0; c < CT; c += E) {
-    if (j0 + 16 * c <= i) {
-      Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(src + 16 * c), dst + c);
-    } else {
+    const bool in = j0 + 16 * c <= i;
+    const T* a = in ? src + 16 * c : src;
+    T v[E];
+    Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(a), v);
 #pragma unroll
-      for (int e = 0; e < E; ++e) dst[c + e] = T(0);
-    }
+    for (int e = 0; e < E; ++e) dst[c + e] = in ? v[e] : T(0);
+  }
+}
+
+// tile_load_row_lower without the zeroing: lanes whose vector lies above the
+// diagonal hold a copy of their first vector until tile_mask_lower clears it.
+// A kernel calls that after the barrier that ends its gather, so that the
+// gather does not wait for the factor's loads.
+template <int CT, class T>
+__device__ __forceinline__ void tile_load_row_lower_raw(const T* __restrict__ row, int i,
+                                                        T (&dst)[CT]) {
+  constexpr int E = Vec16<T>::n;
+  const int j0 = E * (threadIdx.x % 16);
+  const T* src = row + j0;
+#pragma unroll
+  for (int c = 0; c < CT; c += E) {
+    const T* a = j0 + 16 * c <= i ? src + 16 * c : src;
+    Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(a), dst + c);
+  }
+}
+
+template <int CT, class T>
+__device__ __forceinline__ void tile_mask_lower(int i, T (&dst)[CT]) {
+  constexpr int E = Vec16<T>::n;
+  const int j0 = E * (threadIdx.x % 16);
+#pragma unroll
+  for (int c = 0; c < CT; c += E) {
+    const bool in = j0 + 16 * c <= i;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[c + e] = in ? dst[c + e] : T(0);
   }
 }
 
@@ -119,6 +151,26 @@ struct TiledSolve {
 #pragma unroll
     for (int r = 0; r < RT; ++r)
       tile_load_row_lower<CT, T>(Gk + (long long)(r0 + r) * P, r0 + r, R.gt[r]);
+  }
+
+  // The one-step kernels' tiles: W_k = G_k^{-1} N_k (gn, levels whose L.GiN
+  // is set) or N_k, and G_k^{-1} unmasked; mask_g() completes them.
+  __device__ __forceinline__ static void load_raw(const LevelView& L, long long kk, bool gn,
+                                                  Regs& R) {
+    const int r0 = RT * (threadIdx.x / 16);
+    const T* __restrict__ Nk =
+        gn ? Mats<T>::GiN(L) + kk * (long long)P * P : Mats<T>::N(L) + kk * L.sN;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) tile_load_row<CT, T>(Nk + (long long)(r0 + r) * P, R.nt[r]);
+    const T* __restrict__ Gk = Mats<T>::Gi(L) + kk * (long long)P * P;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      tile_load_row_lower_raw<CT, T>(Gk + (long long)(r0 + r) * P, r0 + r, R.gt[r]);
+  }
+  __device__ __forceinline__ static void mask_g(Regs& R) {
+    const int r0 = RT * (threadIdx.x / 16);
+#pragma unroll
+    for (int r = 0; r < RT; ++r) tile_mask_lower<CT, T>(r0 + r, R.gt[r]);
   }
 
   // Column partials of one thread -> per-wave slot of red (lanes 0..15).
@@ -253,21 +305,93 @@ struct TiledSolve {
     __syncthreads();
   }
 
+  // Entries i of the diagonals of Z~ and V when they are diagonal (else 0),
+  // read once by the thread that owns entry i of the block's vectors.
+  struct Diag {
+    T zd = 0, vd = 0;
+  };
+  __device__ __forceinline__ static Diag diag_at(const LevelView& L, int i) {
+    Diag g;
+    if (L.vz_diag) {
+      g.zd = Mats<T>::Zd(L)[i];
+      g.vd = Mats<T>::Vd(L)[i];
+    }
+    return g;
+  }
+
+  // Entry i of d = Z~ r_z - V r_mu - r_l when V and Z~ are diagonal (r_mu = 0
+  // in the first block, which has no mu row).
+  __device__ __forceinline__ static T d_of(const Diag& g, const T* srz, const T* srm,
+                                           const T* srl, int i) {
+    return g.zd * srz[i] - g.vd * srm[i] - srl[i];
+  }
+
+  // The same solve with W = G^{-1} N in the N tile (R from load_gn) and V,
+  // Z~ diagonal, d = Z~ r_z - V r_mu - r_l in srd.  With t = N r_u + d,
+  //     s = G^{-1} t = W r_u + G^{-1} d,   lambda = G^{-T} s,
+  //     N^T lambda = N^T G^{-T} s = W^T s,
+  // so one pass of row products and one of column products (two barriers)
+  // replace the four dependent phases of solve().  Results as for solve():
+  // lambda in ol, N^T lambda in slab 0; ol[j] is written by thread j only
+  // (no barrier after it: each thread reads back its own entries).
+  __device__ __forceinline__ static void solve_gn(const Regs& R, const T* sru, const T* srd,
+                                                  T* ol, T* scr) {
+    const int tid = threadIdx.x, a = tid / 16, bq = tid % 16;
+    const int r0 = RT * a;
+    T* ss = scr + P;
+    T* red = scr + 2 * P;
+    // s = W r_u + G^{-1} d
+    T acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int j = tile_col<T>(c);
+        s += R.nt[r][c] * sru[j] + R.gt[r][c] * srd[j];
+      }
+      acc[r] = tile_sum16(s);
+    }
+    if (bq == 0) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) ss[r0 + r] = acc[r];
+    }
+    __syncthreads();
+    // W^T s -> slab 0, lambda = G^{-T} s -> slab 1
+    T wacc[CT], lacc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      T sw = 0, sl = 0;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const T sv = ss[r0 + r];
+        sw += R.nt[r][c] * sv;
+        sl += R.gt[r][c] * sv;
+      }
+      wacc[c] = sw;
+      lacc[c] = sl;
+    }
+    col_partial(wacc, red);
+    col_partial(lacc, red + kTiledWaves * P);
+    __syncthreads();
+    for (int j = tid; j < P; j += kThreads) ol[j] = col_total(red + kTiledWaves * P, j);
+  }
+
   // Component i of the solution after solve():
   //   u = r_u - N^T lambda, z = r_z - Z^T lambda, mu = V^T lambda - r_m - r_v,
   //   v = -r_m   (lambda is ol[i]; with diagonal V, Z~ their products with
-  //   lambda are elementwise).
+  //   lambda are elementwise, g from diag_at).
   __device__ __forceinline__ static T u_of(const T* scr, const T* sru, int i) {
     return sru[i] - col_total(scr + 2 * P, i);
   }
-  __device__ __forceinline__ static T z_of(const LevelView& L, const T* scr, const T* srz,
-                                           const T* ol, int i) {
-    if (L.vz_diag) return srz[i] - Mats<T>::Zd(L)[i] * ol[i];
+  __device__ __forceinline__ static T z_of(const LevelView& L, const Diag& g, const T* scr,
+                                           const T* srz, const T* ol, int i) {
+    if (L.vz_diag) return srz[i] - g.zd * ol[i];
     return srz[i] - col_total(scr + 2 * P + kTiledWaves * P, i);
   }
-  __device__ __forceinline__ static T mu_of(const LevelView& L, const T* scr, const T* srm,
-                                            const T* srv, const T* ol, int i) {
-    if (L.vz_diag) return Mats<T>::Vd(L)[i] * ol[i] - srm[i] - srv[i];
+  __device__ __forceinline__ static T mu_of(const LevelView& L, const Diag& g, const T* scr,
+                                            const T* srm, const T* srv, const T* ol, int i) {
+    if (L.vz_diag) return g.vd * ol[i] - srm[i] - srv[i];
     return col_total(scr + 2 * P + 2 * kTiledWaves * P, i) - srm[i] - srv[i];
   }
 };

@@ -367,11 +367,13 @@ class Solver:
         return self.lib.pitmg_device_bytes(self.h)
 
     def level_info(self, level: int) -> dict:
-        """Step count and sweep form of one level: fp32 (FP32 sweeps) and
-        diag_vz (shared diagonal V and Z~ used through their diagonals)."""
+        """Step count and sweep form of one level: fp32 (FP32 sweeps),
+        diag_vz (shared diagonal V and Z~ used through their diagonals) and
+        gin (one-step sweeps on W = G^{-1} N)."""
         n, f = C.c_int(), C.c_int()
         self._check(self.lib.pitmg_level_info(self.h, level, C.byref(n), C.byref(f)))
-        return dict(n=n.value, fp32=bool(f.value & 1), diag_vz=bool(f.value & 2))
+        return dict(n=n.value, fp32=bool(f.value & 1), diag_vz=bool(f.value & 2),
+                    gin=bool(f.value & 4))
 
     def autotune(self):
         """Pick each level's sweep launch shape by timing; returns the choices."""

@@ -2,7 +2,9 @@
 
 With theta = 1, an identity mass matrix and distributed control, V_k = -I/dt
 and Z~_k = -I/gamma for every step (Sec. 6), and the library detects this at
-set-up and runs its sweeps and products on the diagonals alone.  A mass
+set-up and runs its sweeps and products on the diagonals alone; on FP64
+levels with p in {64, 128} its one-step sweeps also take W = G^{-1} N in
+place of N.  A mass
 matrix with nearest-neighbour couplings makes V a dense shared block, which
 takes the general path.  Both are checked against the FP64 oracle (apply,
 sweep, V-cycle in fixed-coarse-step mode, FGMRES), and a problem whose mass
@@ -30,9 +32,15 @@ SHAPES = {
 }
 
 
-def build(name, mass_offdiag=0.0, **opt):
+def build(name, mass_offdiag=0.0, one_step=False, **opt):
+    """one_step: the one-step sweep kernels on every level above the
+    coarsest (where the W = G^{-1} N form runs), else the built-in rule."""
+    if one_step and SHAPES[name]["nx"] > 128:
+        pytest.skip("p > 128 has the split sweep only")
     prob, rng = make_problem(**SHAPES[name], mass_offdiag=mass_offdiag)
     s = pm.Solver(prob.levels, pm.default_options(**opt))
+    if one_step:
+        s.set_sweep_shapes([-1] * (prob.n_levels - 1) + [0])
     return prob, rng, s
 
 
@@ -46,13 +54,16 @@ def test_diagonal_detected_only_for_diagonal_blocks(name, fp32):
             assert info["n"] == prob.levels[lev].n
             assert info["diag_vz"] is want, (name, md, lev)
             assert info["fp32"] is bool(fp32 and lev < fp32), (name, lev, info)
+            # W = G^{-1} N for the one-step sweeps: FP64 levels, p in {64, 128}
+            assert info["gin"] is (want and not info["fp32"] and prob.p <= 128), (name, lev)
         s.close()
 
 
 @pytest.mark.parametrize("name", list(SHAPES))
 @pytest.mark.parametrize("md", [0.0, 0.1])
-def test_apply_and_sweep_match_oracle(name, md):
-    prob, rng, s = build(name, md)
+@pytest.mark.parametrize("one_step", [False, True])
+def test_apply_and_sweep_match_oracle(name, md, one_step):
+    prob, rng, s = build(name, md, one_step)
     for lev, lv in enumerate(prob.levels):
         ol = OracleLevel(lv.N, lv.V, lv.Z)
         m = ol.A.shape[0]
@@ -71,13 +82,14 @@ def test_apply_and_sweep_match_oracle(name, md):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["p64", "p256"])
+@pytest.mark.parametrize("name", ["p64", "p128", "p256"])
 @pytest.mark.parametrize("md", [0.0, 0.1])
 @pytest.mark.parametrize("nu", [1, 2, 3])
-def test_vcycle_matches_oracle(name, md, nu):
+@pytest.mark.parametrize("one_step", [False, True])
+def test_vcycle_matches_oracle(name, md, nu, one_step):
     """Fixed coarse steps make the cycle a fixed linear map; nu = 1, 2 take
     the fused residual of the two-sweep kernels, nu = 3 the explicit one."""
-    prob, rng, s = build(name, md, coarse_fixed_its=2, nu_pre=nu, nu_post=nu)
+    prob, rng, s = build(name, md, one_step, coarse_fixed_its=2, nu_pre=nu, nu_post=nu)
     H = Hierarchy(prob.levels, mg_opts(s.options))
     r = rng.normal(size=H.levels[0].A.shape[0])
     got = host(s.vcycle(dev(r)))
@@ -108,15 +120,17 @@ def test_fgmres_dense_mass_matrix(name, fp32):
 
 @pytest.mark.parametrize("name", list(SHAPES))
 @pytest.mark.parametrize("fp32", [0, 1])
-def test_diagonal_and_dense_forms_agree(name, fp32):
+@pytest.mark.parametrize("one_step", [False, True])
+def test_diagonal_and_dense_forms_agree(name, fp32, one_step):
     """The same problem through the diagonal form and (couplings of 1e-300,
     below every rounding error) through the dense form: sweeps and cycles
-    agree to rounding (FP64) or to the FP32 smoother's precision."""
-    prob_d, rng, s_d = build(name, 0.0, coarse_fixed_its=2, smoother_fp32=fp32)
-    prob_g, _, s_g = build(name, 1e-300, coarse_fixed_its=2, smoother_fp32=fp32)
+    agree to rounding (FP64: the sweep's conditioning bound) or to the FP32
+    smoother's precision."""
+    prob_d, rng, s_d = build(name, 0.0, one_step, coarse_fixed_its=2, smoother_fp32=fp32)
+    prob_g, _, s_g = build(name, 1e-300, one_step, coarse_fixed_its=2, smoother_fp32=fp32)
     assert s_d.level_info(0)["diag_vz"] and not s_g.level_info(0)["diag_vz"]
-    tol = 1e-5 if fp32 else 1e-12
     for lev, lv in enumerate(prob_d.levels[:-1]):
+        tol = 1e-5 if fp32 and lev < fp32 else sweep_tol(lv)
         m = OracleLevel(lv.N, lv.V, lv.Z).A.shape[0]
         bb = dev(rng.normal(size=m))
         y = dev(rng.normal(size=m))
@@ -128,6 +142,7 @@ def test_diagonal_and_dense_forms_agree(name, fp32):
                      prob_d.p, prob_d.q, lv.n, 1e-14, (name, lev, "apply"))
     r = dev(rng.normal(size=OracleLevel(prob_d.levels[0].N, prob_d.levels[0].V,
                                         prob_d.levels[0].Z).A.shape[0]))
-    assert rel(host(s_d.vcycle(r)), host(s_g.vcycle(r))) <= (1e-5 if fp32 else 1e-11)
+    assert rel(host(s_d.vcycle(r)), host(s_g.vcycle(r))) <= (
+        1e-5 if fp32 else coarse_identity_tol(prob_d))
     s_d.close()
     s_g.close()
