@@ -182,7 +182,8 @@ struct PairSync {
 // coarse correction, if any, folds into the first, the restriction, if any,
 // comes from the second and is R (rbeta b + (L+L^T)(ra y1 - y2))) for levels
 // that sweep with the one-step tiled kernel or, in FP64, the shared-block
-// kernel.  jacobi_pair_supported says whether launch_jacobi_pair applies
+// kernel.  Only the u and mu entries of y1 are guaranteed (the one-step
+// kernel stores no others).  jacobi_pair_supported says whether launch_jacobi_pair applies
 // (never while the stream is being captured: the tickets and epochs are
 // launch arguments).
 bool jacobi_pair_supported(const LevelView& L, hipStream_t s);

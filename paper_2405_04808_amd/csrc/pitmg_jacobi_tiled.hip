@@ -230,8 +230,10 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
 // stores the flag only after the work-group barrier that follows; the
 // waiting thread's flag loads come before the barrier and the compiler
 // fence that precede the coupling loads, which the hardware issues in
-// program order.  The other first-sweep values are read by no other
-// work-group of the launch and are plain stores.  (The same order under the
+// program order.  The first sweep's other values stay in the work-group's
+// registers; of them only mu_n (block n+1) is stored, as a plain store.  The
+// first-sweep vector y1 therefore holds valid u and mu entries only, which
+// is all any later step reads of it.  (The same order under the
 // HIP memory model's own rules, an agent-scope release fence in every
 // thread before the barrier and acquire flag loads, also writes back the
 // XCD's L2 at every hand-off: measured at 133 us against 86 us per
@@ -409,23 +411,21 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
     const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - prev.at(0, n, i);
     mon1 = weigh(w, -rmm - rvn, prev, 4, n, i);
     von1 = weigh(w, -rmm, prev, 1, n, i);
-    y1[Tm.v + (long long)(n - 1) * P + i] = von1;
     y1[Tm.m + (long long)(n - 1) * P + i] = mon1;
   }
-  // this block's first-sweep values stay in registers for the second sweep
+  // this block's first-sweep values stay in registers for the second sweep;
+  // y1 receives only its u and mu entries (the couplings the neighbours read
+  // and what the product from the last sweep reads)
   double uo1 = 0.0, mo1 = 0.0, zo1 = 0.0, lo1 = 0.0, vo1 = 0.0;
   if (on) {
     uo1 = weigh0((double)TS::u_of(scr, sru, i), pu);
     zo1 = weigh0((double)TS::z_of(L, dg, scr, srz, slam, i), pz);
     lo1 = weigh0((double)slam[i], pl);
     coherent_store(y1 + Tm.u + kk * P + i, uo1);                    // read by block k+1
-    y1[Tm.z + kk * P + i] = zo1;
-    y1[Tm.l + kk * P + i] = lo1;
     if (hv) {
       mo1 = weigh0((double)TS::mu_of(L, dg, scr, srm, srv, slam, i), pm);
       vo1 = weigh0(-(double)srm[i], pv);
       coherent_store(y1 + Tm.m + (kk - 1) * P + i, mo1);            // read by block k-1
-      y1[Tm.v + (kk - 1) * P + i] = vo1;
     }
   }
   hand_off(hv ? kb - 1 : -1, tail ? -1 : kb + 1);
