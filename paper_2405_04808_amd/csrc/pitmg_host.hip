@@ -115,7 +115,7 @@ struct pitmg_handle {
   double* r = nullptr;
   double* partial = nullptr;         // [blocks][restart+2]
   double* upd = nullptr;             // [groups][2][len] for the grouped update, or NULL
-  double* coef = nullptr;            // device scalars, 2*(restart+1)+4
+  double* coef = nullptr;            // device scalars, 2*(restart+2)+8
   double* hbuf = nullptr;            // pinned host mirror of coef
   double* coarse_work = nullptr;     // coarse Krylov bases
   double* cst = nullptr;             // coarse GMRES state
@@ -1101,7 +1101,7 @@ double givens_column(std::vector<double>& H, int m, int j, std::vector<double>& 
 // solves, each on its own stream, so their kernels overlap on the device
 // while the host waits once per round for all of them.
 struct FgmresRun {
-  enum Phase { kStart, kAfterBnorm, kCycle, kAfterResid, kStepA, kStepB, kStepC, kStepEnd,
+  enum Phase { kStart, kAfterBnorm, kCycle, kAfterResid, kStepA, kStepB, kStepEnd,
                kCycleEnd, kFinal, kAfterFinal, kFinish, kDone };
   static constexpr int kWait = 1;
   static constexpr int kFinished = 0;
@@ -1276,10 +1276,31 @@ struct FgmresRun {
           if (plain)
             HIPCHK(h, hipMemcpyAsync(h->its_pinned, h->last_its_slot, sizeof(int),
                                      hipMemcpyDeviceToHost, h->stream));
-          // one pass: s = Q^T v_j, hh = Q^T w, v_j.v_j, v_j.w, w.w
+          // one pass: s = Q^T v_j, hh = Q^T w, v_j.v_j, v_j.w, w.w (coef[0 .. 2j+2])
           if ((rc = dots(h, h->Vk, j, Vp(j), h->w, len))) return rc;
-          ph = kStepB;
-          return wait_coef(2 * j + 3);
+          {
+            // alpha, cq and the orthogonality flag from those values on the
+            // device (coef[2j+3 .. 2j+5]), then one pass q_j = (v_j - Q s) /
+            // alpha, w -= Q hh + cq q_j, |w|^2 (coef[2j+6]): the host reads
+            // the step's scalars back in one copy
+            const int oa = 2 * j + 3;
+            if ((rc = timed(h, 5, [&] {
+                   return launch_arnoldi_coeffs(h->coef, j, h->coef + oa, h->stream);
+                 })))
+              return rc;
+            if ((rc = timed(h, 5, [&] {
+                   return launch_update(h->Vk, j, Vp(j), h->w, h->coef, h->coef + j,
+                                        h->coef + oa, j > 0 ? 1 : 0, len, h->partial, h->upd,
+                                        h->stream);
+                 })))
+              return rc;
+            if ((rc = timed(h, 5, [&] {
+                   return launch_reduce_partials(h->partial, ns, 1, h->coef + oa + 3, h->stream);
+                 })))
+              return rc;
+            ph = kStepB;
+            return wait_coef(oa + 4);
+          }
         case kStepB: {
           if (plain) {
             h->coarse_k = std::max(1, h->its_pinned[0]);   // coarse steps next time
@@ -1287,38 +1308,17 @@ struct FgmresRun {
             coarse_its += h->its_pinned[0];
           }
           const double* cb = h->hbuf;
-          const double vv = cb[2 * j], vw = cb[2 * j + 1];
+          const int oa = 2 * j + 3;
           ww = cb[2 * j + 2];
-          double ss = 0.0, sh = 0.0;
-          alpha = 1.0;
           for (int i = 0; i < j; ++i) {
             sv[i] = cb[i];
             hv[i] = cb[j + i];
-            ss += sv[i] * sv[i];
-            sh += sv[i] * hv[i];
           }
-          if (j > 0) {
-            const double a2 = vv - ss;
-            if (!(a2 > 0.0) || !std::isfinite(a2))
-              return set_err(h, PITMG_ERR_NONFINITE, "lost orthogonality in the Arnoldi basis");
-            alpha = std::sqrt(a2);
-          }
-          cq = (vw - sh) / alpha;
-          // one pass: q_j = (v_j - Q s)/alpha, w -= Q hh + cq q_j, |w|^2
-          if ((rc = timed(h, 5, [&] {
-                 return launch_update(h->Vk, j, Vp(j), h->w, h->coef, h->coef + j, alpha, cq,
-                                      j > 0 ? 1 : 0, len, h->partial, h->upd, h->stream);
-               })))
-            return rc;
-          if ((rc = timed(h, 5, [&] {
-                 return launch_reduce_partials(h->partial, ns, 1, h->coef, h->stream);
-               })))
-            return rc;
-          ph = kStepC;
-          return wait_coef(1);
-        }
-        case kStepC: {
-          rho = std::sqrt(h->hbuf[0]);
+          if (cb[oa + 2] != 0.0)
+            return set_err(h, PITMG_ERR_NONFINITE, "lost orthogonality in the Arnoldi basis");
+          alpha = cb[oa];
+          cq = cb[oa + 1];
+          rho = std::sqrt(cb[oa + 3]);
           if (!std::isfinite(rho) || !std::isfinite(ww))
             return set_err(h, PITMG_ERR_NONFINITE, "Krylov vector not finite");
           // finish column j-1: v_j = Q s + alpha q_j, scaled by rho_{j-1}
@@ -1736,7 +1736,7 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
         (rc = dalloc(h, (void**)&h->upd, (size_t)gmax * 2 * len * 8)))
       return fail(rc);
   }
-  const int ncoef = 2 * (m + 2) + 8;   // >= 2m+3 dot values
+  const int ncoef = 2 * (m + 2) + 8;   // >= 2m+5: dot values and the step scalars
   if ((rc = dalloc(h, (void**)&h->coef, (size_t)ncoef * 8))) return fail(rc);
   if (hipHostMalloc((void**)&h->hbuf, (size_t)ncoef * 8, hipHostMallocDefault) != hipSuccess)
     return fail(set_err(h, PITMG_ERR_OOM, "hipHostMalloc failed"));

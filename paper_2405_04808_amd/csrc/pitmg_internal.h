@@ -299,12 +299,16 @@ int krylov_partial_blocks(long long len);
 // values: basis_i.x1 (nb), basis_i.x2 (nb, if x2), x1.x1, [x1.x2, x2.x2]
 hipError_t launch_dots(const double* basis, int nb, const double* x1, const double* x2,
                        long long len, double* partial, hipStream_t s);
-// x1 <- (x1 - basis^T s)/alpha if reorth;  x2 <- x2 - basis^T h - cq*x1;
-// norm_partial[slice] = |x2|^2 over the slice.  scratch: 2*len doubles per
-// basis group (krylov_groups) when there is more than one; NULL forces the
-// single-pass kernel.
+// The Arnoldi step's alpha, cq and a lost-orthogonality flag (out[0..2])
+// from the dot values coef of step j (layout of launch_dots).
+hipError_t launch_arnoldi_coeffs(const double* coef, int j, double* out, hipStream_t s);
+// x1 <- (x1 - basis^T s)/alpha if reorth;  x2 <- x2 - basis^T h - cq*x1
+// with (alpha, cq) = acq[0..1] in device memory; norm_partial[slice] =
+// |x2|^2 over the slice.  scratch: 2*len doubles per basis group
+// (krylov_groups) when there is more than one; NULL forces the single-pass
+// kernel.
 hipError_t launch_update(const double* basis, int nb, double* x1, double* x2,
-                         const double* scoef, const double* hcoef, double alpha, double cq,
+                         const double* scoef, const double* hcoef, const double* acq,
                          int reorth, long long len, double* norm_partial, double* scratch,
                          hipStream_t s);
 // Basis groups the dot and update passes split nb vectors of length len into.

@@ -726,18 +726,44 @@ __global__ __launch_bounds__(kDotThreads) void k_dots(const double* __restrict__
   }
 }
 
+// The two scalars of one delayed re-orthogonalisation step from the dot
+// pass's results c (s = c[0..j), h = c[j..2j), v.v = c[2j], v.w = c[2j+1]):
+//   alpha = sqrt(v.v - |s|^2)  (1 for j = 0),   cq = (v.w - s.h) / alpha,
+// into out[0], out[1]; out[2] = 1 when v.v - |s|^2 is not positive and
+// finite (the basis lost orthogonality; alpha is then left at 1).  One
+// thread, the sums in index order.
+__global__ void k_arnoldi_coeffs(const double* __restrict__ c, int j, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double ss = 0.0, sh = 0.0;
+  for (int i = 0; i < j; ++i) {
+    ss += c[i] * c[i];
+    sh += c[i] * c[j + i];
+  }
+  double alpha = 1.0, bad = 0.0;
+  if (j > 0) {
+    const double a2 = c[2 * j] - ss;
+    if (a2 > 0.0 && isfinite(a2)) alpha = sqrt(a2);
+    else bad = 1.0;
+  }
+  out[0] = alpha;
+  out[1] = (c[2 * j + 1] - sh) / alpha;
+  out[2] = bad;
+}
+
 // Delayed re-orthogonalisation update over this work-group's slice:
 //   q  = (x1 - basis^T s) / alpha     (written back to x1 when reorth)
 //   x2 = x2 - basis^T h - c q
-// and norm_partial[slice] = sum of the new x2 squared.
+// with alpha = acq[0], c = acq[1] (device scalars), and norm_partial[slice]
+// = sum of the new x2 squared.
 __global__ __launch_bounds__(kVecThreads) void k_update(const double* __restrict__ basis, int nb,
                                                         double* __restrict__ x1,
                                                         double* __restrict__ x2,
                                                         const double* __restrict__ scoef,
                                                         const double* __restrict__ hcoef,
-                                                        double alpha, double cq, int reorth,
-                                                        long long len,
+                                                        const double* __restrict__ acq,
+                                                        int reorth, long long len,
                                                         double* __restrict__ norm_partial) {
+  const double alpha = acq[0], cq = acq[1];
   __shared__ double red[kVecThreads / kWave];
   constexpr int kPer = kSliceLen / kVecThreads;
   const long long e0 = (long long)blockIdx.x * kSliceLen;
@@ -831,10 +857,11 @@ __global__ __launch_bounds__(kVecThreads) void k_update_part(const double* __res
 __global__ __launch_bounds__(kVecThreads) void k_update_apply(double* __restrict__ x1,
                                                               double* __restrict__ x2,
                                                               const double* __restrict__ part,
-                                                              int ngroups, double alpha,
-                                                              double cq, int reorth,
-                                                              long long len,
+                                                              int ngroups,
+                                                              const double* __restrict__ acq,
+                                                              int reorth, long long len,
                                                               double* __restrict__ norm_partial) {
+  const double alpha = acq[0], cq = acq[1];
   __shared__ double red[kVecThreads / kWave];
   constexpr int kPer = kSliceLen / kVecThreads;
   const long long e0 = (long long)blockIdx.x * kSliceLen;
@@ -965,20 +992,25 @@ hipError_t launch_dots(const double* basis, int nb, const double* x1, const doub
   return hipGetLastError();
 }
 
+hipError_t launch_arnoldi_coeffs(const double* coef, int j, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_arnoldi_coeffs, dim3(1), dim3(kWave), 0, s, coef, j, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_update(const double* basis, int nb, double* x1, double* x2,
-                         const double* scoef, const double* hcoef, double alpha, double cq,
+                         const double* scoef, const double* hcoef, const double* acq,
                          int reorth, long long len, double* norm_partial, double* scratch,
                          hipStream_t s) {
   const int ng = krylov_groups(len, nb);
   if (ng == 1 || !scratch) {
     hipLaunchKernelGGL(k_update, dim3(krylov_slices(len)), dim3(kVecThreads), 0, s, basis, nb,
-                       x1, x2, scoef, hcoef, alpha, cq, reorth, len, norm_partial);
+                       x1, x2, scoef, hcoef, acq, reorth, len, norm_partial);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_update_part, dim3(krylov_slices(len), ng), dim3(kVecThreads), 0, s, basis,
                      nb, scoef, hcoef, len, scratch);
   hipLaunchKernelGGL(k_update_apply, dim3(krylov_slices(len)), dim3(kVecThreads), 0, s, x1, x2,
-                     scratch, ng, alpha, cq, reorth, len, norm_partial);
+                     scratch, ng, acq, reorth, len, norm_partial);
   return hipGetLastError();
 }
 
