@@ -365,10 +365,133 @@ __global__ __launch_bounds__(NT) void k_apply(LevelView L, const double* __restr
   apply_step<NT>(L, blockIdx.x + 1, x, b, alpha, beta, out, sm);
 }
 
+// The same product for p = q = 64 MB in {256, 512} with V and Z~ diagonal
+// (shared by every step), one work-group of 512 threads per step and one
+// pass over N_k: thread (r, c) = (tid / 32, tid % 32) takes row 16 i + r of
+// row panel i and the columns 2c + 64m + e (m < MB, e < 2, 16-byte loads, a
+// half-wave reading 512 contiguous bytes), so each entry of N_k serves the
+// row product (N u_k)_row, summed over the 32 lanes of the row, and the
+// column product N^T lambda_k, accumulated in registers over the panels and
+// summed over the rows at the end (lane ^ 32, then the 8 waves in LDS in a
+// fixed order).  The next panel's loads are issued before the current one is
+// used.  Rows of block k as in apply_step; the products with V and Z~ are
+// elementwise with their diagonals.
+template <int MB>
+__global__ __launch_bounds__(512) void k_apply_big(LevelView L, const double* __restrict__ x,
+                                                   const double* __restrict__ b, double alpha,
+                                                   double beta, double* __restrict__ out) {
+  constexpr int P = 64 * MB, CT = 2 * MB, NP = P / 16, NTH = 512, NW = NTH / kWave;
+  static_assert(NP % 2 == 0, "panels in pairs");
+  __shared__ double sxu[P], sxl[P], sxz[P], sxv[P], srow[P];
+  __shared__ double red[NW][P];
+  const int tid = threadIdx.x, r = tid / 32, c = tid % 32, w = tid / kWave;
+  const int n = L.n, k = blockIdx.x + 1;
+  const long long kk = k - 1;
+  const bool hv = k >= 2;
+  const TypeMajor T(P, P, n);
+  const double* __restrict__ Nk = L.N + kk * L.sN;
+  for (int i = tid; i < P; i += NTH) {
+    sxu[i] = x[T.u + kk * P + i];
+    sxl[i] = x[T.l + kk * P + i];
+    sxz[i] = x[T.z + kk * P + i];
+    sxv[i] = hv ? x[T.v + (kk - 1) * P + i] : 0.0;
+  }
+  // the thread's columns of u_k
+  double xu[CT];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const double2 v = *reinterpret_cast<const double2*>(x + T.u + kk * P + 2 * c + 64 * m);
+    xu[2 * m] = v.x;
+    xu[2 * m + 1] = v.y;
+  }
+  double acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = 0.0;
+  auto load = [&](int pn, double (&dst)[CT]) {
+    const double* row = Nk + (long long)(16 * pn + r) * P + 2 * c;
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      const double2 v = *reinterpret_cast<const double2*>(row + 64 * m);
+      dst[2 * m] = v.x;
+      dst[2 * m + 1] = v.y;
+    }
+  };
+  auto use = [&](int pn, const double (&cur)[CT]) {
+    const int row = 16 * pn + r;
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < CT; ++t) s += cur[t] * xu[t];
+    s = xor16_sum(row_sum16(s));                 // over the 32 lanes of the row
+    if (c == 0) srow[row] = s;
+    const double lr = sxl[row];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) acc[t] += cur[t] * lr;
+  };
+  double A[CT], B[CT];
+  load(0, A);
+  __syncthreads();                              // sxl, sxu, sxz, sxv
+#pragma unroll 1
+  for (int pn = 0; pn < NP; pn += 2) {
+    load(pn + 1, B);
+    use(pn, A);
+    if (pn + 2 < NP) load(pn + 2, A);
+    use(pn + 1, B);
+  }
+  // column sums: the two rows of a wave (lane ^ 32), then the waves
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = xor32_sum(acc[t]);
+  if (r % 2 == 0) {
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      red[w][2 * c + 64 * m] = acc[2 * m];
+      red[w][2 * c + 64 * m + 1] = acc[2 * m + 1];
+    }
+  }
+  __syncthreads();
+  const double* __restrict__ Vd = L.Vd;
+  const double* __restrict__ Zd = L.Zd;
+  auto put = [&](long long idx, double val) {
+    out[idx] = (beta != 0.0 ? beta * b[idx] : 0.0) + alpha * val;
+  };
+  for (int i = tid; i < P; i += NTH) {
+    double nl = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) nl += red[q][i];
+    const double lam = sxl[i];
+    // lambda_k = N u_k + V v_{k-1} + Z~ z_k
+    put(T.l + kk * P + i, srow[i] + (hv ? Vd[i] * sxv[i] : 0.0) + Zd[i] * sxz[i]);
+    // u_k = u_k + N^T lambda_k + mu_k;  z_k = z_k + Z~^T lambda_k
+    put(T.u + kk * P + i, sxu[i] + nl + x[T.m + kk * P + i]);
+    put(T.z + kk * P + i, sxz[i] + Zd[i] * lam);
+    if (hv) {
+      // v_{k-1} = v_{k-1} + V^T lambda_k - mu_{k-1};  mu_{k-1} = u_{k-1} - v_{k-1}
+      put(T.v + (kk - 1) * P + i, sxv[i] + Vd[i] * lam - x[T.m + (kk - 1) * P + i]);
+      put(T.m + (kk - 1) * P + i, x[T.u + (kk - 1) * P + i] - sxv[i]);
+    }
+    if (k == n) {
+      const double vn = x[T.v + kk * P + i], mn = x[T.m + kk * P + i];
+      put(T.v + kk * P + i, vn - mn);
+      put(T.m + kk * P + i, sxu[i] - vn);
+    }
+  }
+}
+
+static bool apply_big_supported(const LevelView& L, const double* x) {
+  return L.vz_diag && L.Vd && L.Zd && L.p == L.q && (L.p == 256 || L.p == 512) &&
+         aligned16(L.N) && aligned16(x);
+}
+
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b, double alpha,
                         double beta, double* out, hipStream_t s) {
   if (small_supported(L.p, L.q)) return launch_apply_small(L, x, b, alpha, beta, out, s);
   if (apply_shared_supported(L)) return launch_apply_shared(L, x, b, alpha, beta, out, s);
+  if (apply_big_supported(L, x)) {
+    if (L.p == 512)
+      hipLaunchKernelGGL(k_apply_big<8>, dim3(L.n), dim3(512), 0, s, L, x, b, alpha, beta, out);
+    else
+      hipLaunchKernelGGL(k_apply_big<4>, dim3(L.n), dim3(512), 0, s, L, x, b, alpha, beta, out);
+    return hipGetLastError();
+  }
   const size_t lds = apply_lds_doubles(L.p, L.q, kApplyThreads) * sizeof(double);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_apply<kApplyThreads>,
