@@ -19,7 +19,11 @@ What it computes (arXiv 2405.04808):
                    V-cycle (Alg. 1) with its W and F variants, and the
                    preconditioned outer solve (Sec. 6);
   * unlifted.py -- the system without virtual variables (Fig. 2) and the
-                   lift / project maps that carry the lifted cycle to it.
+                   lift / project maps that carry the lifted cycle to it;
+  * dogleg.py   -- the discrete Burgers equation F(u, z~) = 0, its Jacobian
+                   B = dF, minimum-norm Gauss-Newton steps from the augmented
+                   system (Sec. 3) and Powell's dogleg with viscosity
+                   continuation (Sec. 6, Sec. 6.2, Table 6).
 
 Everything is assembled scipy.sparse matrices and SuperLU factorisations of
 the block parts; no Schur complement or other derived block algebra is used,
