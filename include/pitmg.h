@@ -464,6 +464,77 @@ int pitmg_coarse_pairs_arm(pitmg_handle* h, double* r, double* e, int cap);
 /* Pairs recorded since the last arm. */
 int pitmg_coarse_pairs_count(const pitmg_handle* h);
 
+/* ------------------------------------------------------------------------
+ * Burgers' equation by Powell's dogleg (Sec. 6: the nonlinear solver whose
+ * Gauss-Newton steps are minimum-norm augmented solves, Sec. 3; Sec. 6.2 and
+ * Table 6: viscosity continuation down to the inviscid equation).
+ *
+ * Unknowns x = [u_1..u_n | z~_1..z~_n] on the device, FP64, 2 nx n values:
+ * the states at steps 1..n and the scaled controls z~ = gamma z.  The state
+ * equation is backward Euler on n steps of dt = T/n, upwind differences on
+ * nx interior nodes of [0, 1] (h = 1/(nx+1), zero Dirichlet values) with
+ * the convective term in flux form:
+ *     F_k = (u_k - u_{k-1})/dt - nu (u_{i+1} - 2u_i + u_{i-1})/h^2
+ *           + (u_i^2 - u_{i-1}^2)/(2h) - z~_k/gamma,   u_0 = w0.
+ * B = dF gives the unlifted augmented system of Fig. 2 (N_k tridiagonal,
+ * V = -I/dt, Z~ = -I/gamma, both diagonal), which the library solves with
+ * its lifted cycle (options.unlifted is forced to 1).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int nx;                      /* interior nodes: p = q = nx                   */
+  int n;                       /* time steps of the finest grid                */
+  int n_levels;                /* multigrid levels (n % coarsen^(n_levels-1) = 0) */
+  double T;                    /* final time                                   */
+  double gamma;                /* control scaling: x holds z~ = gamma z        */
+  const double* w0;            /* host, nx values: the state at t = 0          */
+} pitmg_burgers;
+
+typedef struct {
+  double ftol;                 /* stop when |F(x)| <= ftol |F(x_start)|, per
+                                  viscosity (default 1e-8)                     */
+  double lin_tol;              /* FGMRES relative tolerance of the Gauss-Newton
+                                  solves (default 1e-6, the value of Sec. 6)    */
+  int maxit;                   /* dogleg iterations per viscosity (default 50) */
+  double eta;                  /* a step is taken when actual / predicted
+                                  decrease of |F|^2 exceeds eta (default 1e-4) */
+} pitmg_dogleg_params;
+
+typedef struct {
+  int iters;                   /* dogleg iterations (trial steps)              */
+  int accepted;                /* steps taken                                  */
+  int converged;               /* 1 if |F| met ftol                            */
+  int solves;                  /* Gauss-Newton augmented solves                */
+  int fgmres_iters;            /* their FGMRES steps, summed                   */
+  int coarse_calls;            /* coarse-grid solves in them                   */
+  int coarse_its;              /* their SGS-preconditioned GMRES steps         */
+  double fnorm0, fnorm;        /* |F| at the start and at the end              */
+  double ms;                   /* wall time for this viscosity, ms             */
+} pitmg_dogleg_stats;
+
+void pitmg_default_dogleg_params(pitmg_dogleg_params* dp);
+/* F(x) into F (device, nx n values) for viscosity nu >= 0.  x as above.
+ * Synchronises the stream.  PITMG_ERR_INVALID for bad sizes or NULLs. */
+int pitmg_burgers_residual(const pitmg_burgers* bp, double nu, const double* x, double* F,
+                           void* stream);
+/* Dogleg solves of F(x) = 0 for the viscosities nus[0..n_nu) in order, each
+ * from the previous solution (x: device, in the starting point, out the
+ * last solution).  One dogleg iteration at x: the Gauss-Newton step s_N is
+ * the (u, z~) part of the unlifted solve A (s, y) = (0, -F) (FGMRES to
+ * lin_tol); g = B^T F; the Cauchy step -tau g, tau = |g|^2/|Bg|^2; the step
+ * s_N if |s_N| <= delta, the boundary point along -g if the Cauchy step
+ * leaves the radius, else the point of radius delta on the segment between
+ * them; rho = (|F(x)|^2 - |F(x+s)|^2)/(|F|^2 - |F + B s|^2); the step is
+ * taken when rho > eta; delta becomes |s|/4 when rho < 1/4 and doubles when
+ * rho > 3/4 at the boundary; delta starts at |s_N| of the first iteration
+ * of each viscosity.  opt: the augmented solver's options (NULL:
+ * defaults; unlifted is forced to 1).  st: n_nu entries.  Returns PITMG_OK,
+ * PITMG_NOT_CONVERGED when a viscosity ran out of iterations (x is the last
+ * iterate), or an error (pitmg_burgers_last_error gives the message). */
+int pitmg_burgers_dogleg(const pitmg_burgers* bp, const pitmg_options* opt, const double* nus,
+                         int n_nu, double* x, const pitmg_dogleg_params* dp,
+                         pitmg_dogleg_stats* st, void* stream);
+const char* pitmg_burgers_last_error(void);
+
 /* Bytes of device memory held by the handle. */
 long long pitmg_device_bytes(const pitmg_handle* h);
 

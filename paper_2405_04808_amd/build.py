@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpitmg.so")
 SOURCES = ["pitmg_kernels.hip", "pitmg_factor.hip", "pitmg_jacobi_tiled.hip",
-           "pitmg_coarse.hip", "pitmg_small.hip", "pitmg_split.hip", "pitmg_gs.hip", "pitmg_unlifted.hip",
-           "pitmg_net.hip", "pitmg_host.hip"]
+           "pitmg_coarse.hip", "pitmg_small.hip", "pitmg_split.hip", "pitmg_gs.hip",
+           "pitmg_unlifted.hip", "pitmg_dogleg.hip", "pitmg_net.hip", "pitmg_host.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -63,6 +63,26 @@ class pitmg_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class pitmg_burgers(C.Structure):
+    _fields_ = [("nx", C.c_int), ("n", C.c_int), ("n_levels", C.c_int), ("T", C.c_double),
+                ("gamma", C.c_double), ("w0", C.POINTER(C.c_double))]
+
+
+class pitmg_dogleg_params(C.Structure):
+    _fields_ = [("ftol", C.c_double), ("lin_tol", C.c_double), ("maxit", C.c_int),
+                ("eta", C.c_double)]
+
+
+class pitmg_dogleg_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("accepted", C.c_int), ("converged", C.c_int),
+                ("solves", C.c_int), ("fgmres_iters", C.c_int), ("coarse_calls", C.c_int),
+                ("coarse_its", C.c_int), ("fnorm0", C.c_double), ("fnorm", C.c_double),
+                ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PitmgError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"pitmg error {code}: {msg}")
@@ -104,6 +124,12 @@ def load_library(path: str = LIB_PATH):
         "pitmg_failed_block": (i, [vp, C.POINTER(i), C.POINTER(i)]),
         "pitmg_device_bytes": (C.c_longlong, [vp]),
         "pitmg_level_info": (i, [vp, i, C.POINTER(i), C.POINTER(i)]),
+        "pitmg_default_dogleg_params": (None, [C.POINTER(pitmg_dogleg_params)]),
+        "pitmg_burgers_residual": (i, [C.POINTER(pitmg_burgers), d, vp, vp, vp]),
+        "pitmg_burgers_dogleg": (i, [C.POINTER(pitmg_burgers), C.POINTER(pitmg_options),
+                                     C.POINTER(d), i, vp, C.POINTER(pitmg_dogleg_params),
+                                     C.POINTER(pitmg_dogleg_stats), vp]),
+        "pitmg_burgers_last_error": (C.c_char_p, []),
         "pitmg_net_param_count": (C.c_longlong, [i, i]),
         "pitmg_net_create": (i, [C.POINTER(vp), i, i, i, i, vp]),
         "pitmg_net_set_params": (i, [vp, vp, i]),
@@ -436,6 +462,54 @@ def solve_batch(solvers: Sequence["Solver"], bs, tol: float = 1e-10, outs=None):
         msg = solvers[bad[0]].last_error() if bad else ""
         raise PitmgError(rc, f"system {bad[0] if bad else '?'}: {msg}")
     return xs, [st[i].as_dict() for i in range(n)], [status[i] for i in range(n)], rc
+
+
+class Burgers:
+    """Burgers' equation F(u, z~) = 0 on the device (pitmg_burgers_*): nx
+    interior nodes, n steps on [0, T], control scaling gamma, initial state
+    w0 (numpy, nx).  Vectors x = [u | z~] are torch FP64 device tensors of
+    2 nx n values; every computation runs in the HIP library."""
+
+    def __init__(self, nx: int, n: int, n_levels: int, T: float, gamma: float, w0):
+        import numpy as np
+        self.lib = load_library()
+        self._w0 = np.ascontiguousarray(w0, dtype=np.float64)
+        if self._w0.shape != (nx,):
+            raise ValueError("w0 must hold nx values")
+        self.spec = pitmg_burgers(nx, n, n_levels, float(T), float(gamma),
+                                  self._w0.ctypes.data_as(C.POINTER(C.c_double)))
+
+    def _stream(self, x):
+        import torch
+        return C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+
+    def _err(self, rc):
+        raise PitmgError(rc, self.lib.pitmg_burgers_last_error().decode())
+
+    def residual(self, x, nu: float, out=None):
+        import torch
+        out = out if out is not None else torch.empty(self.spec.nx * self.spec.n,
+                                                      dtype=torch.float64, device=x.device)
+        rc = self.lib.pitmg_burgers_residual(C.byref(self.spec), float(nu), _ptr(x), _ptr(out),
+                                             self._stream(x))
+        if rc < 0:
+            self._err(rc)
+        return out
+
+    def dogleg(self, x, nus: Sequence[float], options: Optional[pitmg_options] = None,
+               ftol: float = 1e-8, lin_tol: float = 1e-6, maxit: int = 50, eta: float = 1e-4):
+        """Continuation over nus from x (updated in place); returns (stats
+        dicts, status code >= 0)."""
+        dp = pitmg_dogleg_params(float(ftol), float(lin_tol), int(maxit), float(eta))
+        k = len(nus)
+        arr = (C.c_double * k)(*[float(v) for v in nus])
+        st = (pitmg_dogleg_stats * k)()
+        o = options if options is not None else default_options()
+        rc = self.lib.pitmg_burgers_dogleg(C.byref(self.spec), C.byref(o), arr, k, _ptr(x),
+                                           C.byref(dp), st, self._stream(x))
+        if rc < 0:
+            self._err(rc)
+        return [st[i].as_dict() for i in range(k)], rc
 
 
 class Net:
