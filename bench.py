@@ -325,6 +325,55 @@ def variants_leg(pm, torch, prob, db, wl, reps=2):
     return out
 
 
+# Table 6 of the paper (viscosity: dogleg iterations, SGS steps per coarse
+# solve, FGMRES steps per solve), for context only: its iterates come from
+# the paper's own runs.
+TABLE6 = {"0.1": (2, 1.00, 2.00), "0.01": (7, 1.00, 5.62), "0.001": (9, 1.00, 11.00),
+          "0.0001": (6, 1.00, 7.33), "0.0": (5, 1.00, 12.80)}
+
+
+def dogleg_leg(pm, torch, nx=512, n=512, levels=7, gamma=1e5):
+    """The nonlinear solve of Sec. 6.2 / Table 6 on the GPU: Burgers'
+    equation with the step initial state, 512 steps on [0, 1], seven levels,
+    gamma = 1e5, V(4,4), viscosity continuation 1e-1 .. 1e-4, 0; Powell's
+    dogleg with minimum-norm Gauss-Newton steps (unlifted FGMRES to 1e-6).
+    The whole continuation is timed once (from the step initial state)."""
+    import numpy as np
+    from workloads import burgers_step_state
+    nus = [1e-1, 1e-2, 1e-3, 1e-4, 0.0]
+    w0 = burgers_step_state(nx)
+    b = pm.Burgers(nx, n, levels, 1.0, gamma, w0)
+    x = torch.from_numpy(np.concatenate([np.tile(w0, n), np.zeros(n * nx)])).to("cuda:0")
+    opts = pm.default_options(nu_pre=4, nu_post=4, restart=100, maxit=400)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, rc = b.dogleg(x, nus, opts, ftol=1e-8, lin_tol=1e-6)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    stages = []
+    for nu, st in zip(nus, stats):
+        stages.append({"nu": nu, "dogleg_iters": st["iters"], "accepted": st["accepted"],
+                       "converged": st["converged"] == 1,
+                       "sgs_per_coarse_solve": round(st["coarse_its"] / max(st["coarse_calls"], 1), 2),
+                       "fgmres_per_solve": round(st["fgmres_iters"] / max(st["solves"], 1), 2),
+                       "solves": st["solves"], "ms": round(st["ms"], 1),
+                       "fnorm_start": st["fnorm0"], "fnorm_end": st["fnorm"],
+                       "table6": TABLE6.get(repr(nu))})
+        print(f"# dogleg nu={nu}: {st['iters']} iterations, "
+              f"{st['fgmres_iters'] / max(st['solves'], 1):.2f} FGMRES steps per solve",
+              file=sys.stderr, flush=True)
+    u1 = x[(n - 1) * nx:n * nx].cpu().numpy()
+    xg = np.arange(1, nx + 1) / (nx + 1)
+    mid = (xg > 0.1) & (xg < 0.8)
+    return {"problem": f"Burgers nx={nx} (p=q={nx}), n={n} steps on [0,1], {levels} levels, "
+                       f"gamma={gamma:g}, step initial state, flux-form upwind convection, "
+                       "V(4,4) weighted block Jacobi, unlifted FGMRES(100) to 1e-6, "
+                       "dogleg stop |F| <= 1e-8 |F(start)| per viscosity",
+            "status": rc, "total_s": round(total, 3), "stages": stages,
+            "inviscid_u_t1_vs_x_maxdev_mid": float(np.abs(u1[mid] - xg[mid]).max()),
+            "table6_columns": "dogleg iterations, SGS per coarse solve, FGMRES per solve"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -340,6 +389,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the cycle / smoother variants leg")
+    ap.add_argument("--no-dogleg", action="store_true",
+                    help="skip the Burgers dogleg / continuation leg (Table 6)")
     ap.add_argument("--no-setup6", action="store_true",
                     help="skip the refactor + 6 solves measurement")
     ap.add_argument("--sweep-shapes", default=None,
@@ -355,6 +406,7 @@ def main():
         args.no_cpu_baseline = args.no_profile = args.no_fp32 = args.no_learned = True
         args.no_variants = True
         args.no_batch = True
+        args.no_dogleg = True
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
               "supported (the time-parallel path shards by time blocks, see the design "
@@ -563,6 +615,10 @@ def main():
     if not args.no_batch and args.workload == "burgers128":
         batch = batch_leg(pm, torch, count=args.batch_count)
 
+    dogleg = None
+    if not args.no_dogleg and args.workload == "burgers128":
+        dogleg = dogleg_leg(pm, torch)
+
     cpu = None
     if not args.no_cpu_baseline and args.workload not in ("burgers512", "burgers256"):
         cpu = cpu_baseline(args.workload)
@@ -593,6 +649,7 @@ def main():
         "cycle_variants": variants,
         "learned_coarse": learned,
         "uneven_batch": batch,
+        "burgers_dogleg": dogleg,
         "kernel_ms": kern,
         "refactor_plus_6_solves": setup6,
     }

@@ -21,6 +21,7 @@
 // and mu_k of the previous iterate.
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
+#include "pitmg_onepass.h"
 #include "pitmg_blocks.h"
 #include "pitmg_mfma.h"
 #include <algorithm>
@@ -367,86 +368,32 @@ __global__ __launch_bounds__(NT) void k_apply(LevelView L, const double* __restr
 
 // The same product for p = q = 64 MB in {256, 512} with V and Z~ diagonal
 // (shared by every step), one work-group of 512 threads per step and one
-// pass over N_k: thread (r, c) = (tid / 32, tid % 32) takes row 16 i + r of
-// row panel i and the columns 2c + 64m + e (m < MB, e < 2, 16-byte loads, a
-// half-wave reading 512 contiguous bytes), so each entry of N_k serves the
-// row product (N u_k)_row, summed over the 32 lanes of the row, and the
-// column product N^T lambda_k, accumulated in registers over the panels and
-// summed over the rows at the end (lane ^ 32, then the 8 waves in LDS in a
-// fixed order).  The next panel's loads are issued before the current one is
-// used.  Rows of block k as in apply_step; the products with V and Z~ are
-// elementwise with their diagonals.
+// pass over N_k (onepass_products, pitmg_onepass.h): the row product
+// N u_k and the column product N^T lambda_k from the same loads.  Rows of
+// block k as in apply_step; the products with V and Z~ are elementwise with
+// their diagonals.
 template <int MB>
-__global__ __launch_bounds__(512) void k_apply_big(LevelView L, const double* __restrict__ x,
-                                                   const double* __restrict__ b, double alpha,
-                                                   double beta, double* __restrict__ out) {
-  constexpr int P = 64 * MB, CT = 2 * MB, NP = P / 16, NTH = 512, NW = NTH / kWave;
-  static_assert(NP % 2 == 0, "panels in pairs");
+__global__ __launch_bounds__(kOnePassThreads) void k_apply_big(LevelView L,
+                                                               const double* __restrict__ x,
+                                                               const double* __restrict__ b,
+                                                               double alpha, double beta,
+                                                               double* __restrict__ out) {
+  constexpr int P = 64 * MB, NTH = kOnePassThreads, NW = kOnePassWaves;
   __shared__ double sxu[P], sxl[P], sxz[P], sxv[P], srow[P];
   __shared__ double red[NW][P];
-  const int tid = threadIdx.x, r = tid / 32, c = tid % 32, w = tid / kWave;
+  const int tid = threadIdx.x;
   const int n = L.n, k = blockIdx.x + 1;
   const long long kk = k - 1;
   const bool hv = k >= 2;
   const TypeMajor T(P, P, n);
-  const double* __restrict__ Nk = L.N + kk * L.sN;
   for (int i = tid; i < P; i += NTH) {
     sxu[i] = x[T.u + kk * P + i];
     sxl[i] = x[T.l + kk * P + i];
     sxz[i] = x[T.z + kk * P + i];
     sxv[i] = hv ? x[T.v + (kk - 1) * P + i] : 0.0;
   }
-  // the thread's columns of u_k
-  double xu[CT];
-#pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const double2 v = *reinterpret_cast<const double2*>(x + T.u + kk * P + 2 * c + 64 * m);
-    xu[2 * m] = v.x;
-    xu[2 * m + 1] = v.y;
-  }
-  double acc[CT];
-#pragma unroll
-  for (int t = 0; t < CT; ++t) acc[t] = 0.0;
-  auto load = [&](int pn, double (&dst)[CT]) {
-    const double* row = Nk + (long long)(16 * pn + r) * P + 2 * c;
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-      const double2 v = *reinterpret_cast<const double2*>(row + 64 * m);
-      dst[2 * m] = v.x;
-      dst[2 * m + 1] = v.y;
-    }
-  };
-  auto use = [&](int pn, const double (&cur)[CT]) {
-    const int row = 16 * pn + r;
-    double s = 0.0;
-#pragma unroll
-    for (int t = 0; t < CT; ++t) s += cur[t] * xu[t];
-    s = xor16_sum(row_sum16(s));                 // over the 32 lanes of the row
-    if (c == 0) srow[row] = s;
-    const double lr = sxl[row];
-#pragma unroll
-    for (int t = 0; t < CT; ++t) acc[t] += cur[t] * lr;
-  };
-  double A[CT], B[CT];
-  load(0, A);
-  __syncthreads();                              // sxl, sxu, sxz, sxv
-#pragma unroll 1
-  for (int pn = 0; pn < NP; pn += 2) {
-    load(pn + 1, B);
-    use(pn, A);
-    if (pn + 2 < NP) load(pn + 2, A);
-    use(pn + 1, B);
-  }
-  // column sums: the two rows of a wave (lane ^ 32), then the waves
-#pragma unroll
-  for (int t = 0; t < CT; ++t) acc[t] = xor32_sum(acc[t]);
-  if (r % 2 == 0) {
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-      red[w][2 * c + 64 * m] = acc[2 * m];
-      red[w][2 * c + 64 * m + 1] = acc[2 * m + 1];
-    }
-  }
+  __syncthreads();
+  onepass_products<MB>(L.N + kk * L.sN, x + T.u + kk * P, sxl, srow, red);
   __syncthreads();
   const double* __restrict__ Vd = L.Vd;
   const double* __restrict__ Zd = L.Zd;
@@ -487,9 +434,11 @@ hipError_t launch_apply(const LevelView& L, const double* x, const double* b, do
   if (apply_shared_supported(L)) return launch_apply_shared(L, x, b, alpha, beta, out, s);
   if (apply_big_supported(L, x)) {
     if (L.p == 512)
-      hipLaunchKernelGGL(k_apply_big<8>, dim3(L.n), dim3(512), 0, s, L, x, b, alpha, beta, out);
+      hipLaunchKernelGGL(k_apply_big<8>, dim3(L.n), dim3(kOnePassThreads), 0, s, L, x, b, alpha,
+                         beta, out);
     else
-      hipLaunchKernelGGL(k_apply_big<4>, dim3(L.n), dim3(512), 0, s, L, x, b, alpha, beta, out);
+      hipLaunchKernelGGL(k_apply_big<4>, dim3(L.n), dim3(kOnePassThreads), 0, s, L, x, b, alpha,
+                         beta, out);
     return hipGetLastError();
   }
   const size_t lds = apply_lds_doubles(L.p, L.q, kApplyThreads) * sizeof(double);

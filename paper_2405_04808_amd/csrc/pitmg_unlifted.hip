@@ -16,6 +16,7 @@
 // the lifted cycle to the unlifted system.
 #include "pitmg_internal.h"
 #include "pitmg_device.h"
+#include "pitmg_onepass.h"
 
 namespace pitmg {
 namespace {
@@ -91,6 +92,46 @@ __global__ __launch_bounds__(kUnlThreads) void k_unlifted_apply(
   }
 }
 
+// The same rows for p = q = 64 MB with V and Z~ diagonal (shared by every
+// step): one pass over N_k gives N u_k and N^T lambda_k (onepass_products),
+// the V and Z~ terms are elementwise with their diagonals.
+template <int MB>
+__global__ __launch_bounds__(kOnePassThreads) void k_unlifted_apply_big(
+    LevelView L, double bscale, const double* __restrict__ x, const double* __restrict__ b,
+    double alpha, double beta, double* __restrict__ out) {
+  constexpr int P = 64 * MB, NTH = kOnePassThreads, NW = kOnePassWaves;
+  __shared__ double sl[P], srow[P];
+  __shared__ double red[NW][P];
+  const int tid = threadIdx.x, n = L.n, k = blockIdx.x;      // k 0-based
+  const long long pn = (long long)P * n;
+  const double* xu = x;
+  const double* xz = x + pn;
+  const double* xl = x + 2 * pn;
+  for (int i = tid; i < P; i += NTH) sl[i] = xl[(long long)k * P + i];
+  __syncthreads();
+  onepass_products<MB>(L.N + (long long)k * L.sN, xu + (long long)k * P, sl, srow, red);
+  __syncthreads();
+  const double* __restrict__ Vd = L.Vd;
+  const double* __restrict__ Zd = L.Zd;
+  auto put = [&](long long idx, double val) {
+    out[idx] = (beta != 0.0 ? beta * b[idx] : 0.0) + alpha * val;
+  };
+  for (int i = tid; i < P; i += NTH) {
+    double nl = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) nl += red[q][i];
+    const long long o = (long long)k * P + i;
+    const double uk = xu[o], zk = xz[o], lk = sl[i];
+    const double um = k > 0 ? xu[o - P] : 0.0;
+    const double ln = k + 1 < n ? xl[o + P] : 0.0;
+    // lambda row: bscale (N_k u_k + V u_{k-1}) + Z~ z_k
+    put(2 * pn + o, bscale * (srow[i] + Vd[i] * um) + Zd[i] * zk);
+    // u row: u_k + bscale (N_k^T lambda_k + V^T lambda_{k+1});  z row: z_k + Z~^T lambda_k
+    put(o, uk + bscale * (nl + Vd[i] * ln));
+    put(pn + o, zk + Zd[i] * lk);
+  }
+}
+
 constexpr double kRsqrt2 = 0.70710678118654752440;
 
 __global__ void k_lift(long long pn, long long qn, const double* __restrict__ r,
@@ -125,6 +166,20 @@ unsigned grid_for(long long len) {
 hipError_t launch_unlifted_apply(const LevelView& L, double bscale, const double* x,
                                  const double* b, double alpha, double beta, double* out,
                                  hipStream_t s) {
+  const int MB = L.p / 64;
+  const bool big = L.vz_diag && L.Vd && L.Zd && L.p == L.q && L.p % 64 == 0 &&
+                   (MB == 1 || MB == 2 || MB == 4 || MB == 8) &&
+                   ((reinterpret_cast<uintptr_t>(L.N) | reinterpret_cast<uintptr_t>(x)) & 15u) == 0;
+  if (big) {
+    const dim3 g(L.n), t(kOnePassThreads);
+    switch (MB) {
+      case 1: hipLaunchKernelGGL(k_unlifted_apply_big<1>, g, t, 0, s, L, bscale, x, b, alpha, beta, out); break;
+      case 2: hipLaunchKernelGGL(k_unlifted_apply_big<2>, g, t, 0, s, L, bscale, x, b, alpha, beta, out); break;
+      case 4: hipLaunchKernelGGL(k_unlifted_apply_big<4>, g, t, 0, s, L, bscale, x, b, alpha, beta, out); break;
+      default: hipLaunchKernelGGL(k_unlifted_apply_big<8>, g, t, 0, s, L, bscale, x, b, alpha, beta, out); break;
+    }
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(4 * L.p + L.q) * sizeof(double);
   hipLaunchKernelGGL(k_unlifted_apply, dim3(L.n), dim3(kUnlThreads), lds, s, L.p, L.q, L.n, L.N,
                      L.sN, L.V, L.sV, L.Z, L.sZ, bscale, x, b, alpha, beta, out);

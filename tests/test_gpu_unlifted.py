@@ -32,6 +32,9 @@ CASES = {
     "burgers_p64_theta05": dict(kind="burgers", nx=64, nu=0.01, n=16, n_levels=2, seed=55,
                                 theta=0.5),
     "burgers_p256": dict(kind="burgers", nx=256, nu=0.01, n=8, n_levels=2, seed=56),
+    # a dense shared V (non-diagonal mass matrix): the general product
+    "burgers_p64_mass": dict(kind="burgers", nx=64, nu=0.01, n=16, n_levels=2, seed=57,
+                             mass_offdiag=0.1),
 }
 
 

@@ -16,12 +16,13 @@ one by injection (states) and averaging (controls), i.e. by the same
 restriction the multigrid cycle uses (Sec. 5.3.1).
 
 It also draws the seeded initial parameters of the learned coarse
-correction's network (coarse_net_params).
+correction's network (coarse_net_params), and gives the step initial state
+of the nonlinear Burgers solve of Sec. 6.2 (burgers_step_state).
 """
 from .problems import (Problem, Level, vanderpol_jacobians, burgers_jacobians,
                        lifted_blocks, make_problem, make_rhs, config_problem,
-                       coarse_net_params, batch_mix, CONFIGS)
+                       coarse_net_params, batch_mix, burgers_step_state, CONFIGS)
 
 __all__ = ["Problem", "Level", "vanderpol_jacobians", "burgers_jacobians",
            "lifted_blocks", "make_problem", "make_rhs", "config_problem",
-           "coarse_net_params", "batch_mix", "CONFIGS"]
+           "coarse_net_params", "batch_mix", "burgers_step_state", "CONFIGS"]

@@ -92,6 +92,13 @@ def burgers_jacobians(nx: int, nu: float) -> Callable:
     return jac
 
 
+def burgers_step_state(nx: int) -> np.ndarray:
+    """The initial state of Sec. 6.2 at the nx interior nodes of [0, 1]
+    (h = 1/(nx+1)): 1 on (0, 1/2], 0 on (1/2, 1)."""
+    x = np.arange(1, nx + 1) / (nx + 1)
+    return np.where(x <= 0.5, 1.0, 0.0)
+
+
 def burgers_rhs(nx: int, nu: float) -> Callable:
     h = 1.0 / (nx + 1)
 
