@@ -156,6 +156,33 @@ int main() {
   expect(pitmg_profile_enable(nullptr, 1) < 0, "profile NULL");
   int lev = 0, k = 0;
   expect(pitmg_failed_block(nullptr, &lev, &k) < 0, "failed_block NULL");
+  int nl = 0, fl = 0;
+  expect(pitmg_level_info(nullptr, 0, &nl, &fl) < 0, "level_info NULL");
+
+  // the Burgers dogleg's validation (before any device work)
+  {
+    double w0[16] = {0};
+    pitmg_burgers bp{16, 10, 3, 1.0, 1e5, w0};       // 10 steps, 3 levels: 10 % 4 != 0
+    pitmg_dogleg_params dp;
+    pitmg_default_dogleg_params(&dp);
+    expect(dp.lin_tol == 1e-6 && dp.maxit == 50, "dogleg defaults");
+    pitmg_dogleg_stats ds[2];
+    const double nus[2] = {0.1, 0.0};
+    expect(pitmg_burgers_dogleg(&bp, &o, nus, 2, v, &dp, ds, nullptr) == PITMG_ERR_INVALID,
+           "dogleg: n not divisible");
+    bp.n = 12;
+    expect(pitmg_burgers_dogleg(&bp, &o, nullptr, 2, v, &dp, ds, nullptr) == PITMG_ERR_INVALID,
+           "dogleg: NULL viscosities");
+    const double bad[1] = {-1.0};
+    expect(pitmg_burgers_dogleg(&bp, &o, bad, 1, v, &dp, ds, nullptr) == PITMG_ERR_INVALID,
+           "dogleg: negative viscosity");
+    bp.gamma = 0.0;
+    expect(pitmg_burgers_residual(&bp, 0.1, v, v, nullptr) == PITMG_ERR_INVALID,
+           "residual: gamma 0");
+    expect(pitmg_burgers_residual(nullptr, 0.1, v, v, nullptr) == PITMG_ERR_INVALID,
+           "residual: NULL problem");
+    expect(std::strlen(pitmg_burgers_last_error()) > 0, "dogleg message");
+  }
 
   // past validation: device calls fail without a GPU; the handle is kept
   // for its message and destroyed
