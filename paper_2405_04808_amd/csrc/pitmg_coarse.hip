@@ -674,16 +674,29 @@ hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, 
   return hipGetLastError();
 }
 
-hipError_t launch_gi_times_n(const LevelView& L, double* out, hipStream_t s) {
-  if (L.p != L.q || (L.p != 64 && L.p != 128)) return hipErrorInvalidValue;
-  const size_t lds = wg_gemm_lds_doubles(L.p) * sizeof(double);
-  const void* fn = L.p == 128 ? (const void*)k_gi_times_mfma<8> : (const void*)k_gi_times_mfma<4>;
+template <int NT>
+__global__ __launch_bounds__(kGemmThreads) void k_gi_times_batch(GiNBatch B) {
+  extern __shared__ double lds[];
+  constexpr int P = 16 * NT;
+  const int b = blockIdx.x;
+  int l = 0;
+  while (l + 1 < B.nlev && b >= B.start[l + 1]) ++l;
+  const long long s = b - B.start[l];
+  wg_gemm<NT, false, false>(B.Gi[l] + s * P * P, P, B.N[l] + s * B.sN, P, 1.0,
+                            B.out[l] + s * P * P, P, lds);
+}
+
+hipError_t launch_gi_times_batch(const GiNBatch& B, hipStream_t s) {
+  if (B.nlev < 1 || B.nlev > 20 || (B.p != 64 && B.p != 128)) return hipErrorInvalidValue;
+  const size_t lds = wg_gemm_lds_doubles(B.p) * sizeof(double);
+  const void* fn = B.p == 128 ? (const void*)k_gi_times_batch<8> : (const void*)k_gi_times_batch<4>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  if (L.p == 128)
-    hipLaunchKernelGGL(k_gi_times_mfma<8>, dim3(L.n), dim3(kGemmThreads), lds, s, L, 0, out);
+  const dim3 g(B.start[B.nlev]);
+  if (B.p == 128)
+    hipLaunchKernelGGL(k_gi_times_batch<8>, g, dim3(kGemmThreads), lds, s, B);
   else
-    hipLaunchKernelGGL(k_gi_times_mfma<4>, dim3(L.n), dim3(kGemmThreads), lds, s, L, 0, out);
+    hipLaunchKernelGGL(k_gi_times_batch<4>, g, dim3(kGemmThreads), lds, s, B);
   return hipGetLastError();
 }
 

@@ -219,6 +219,8 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatchT<T> 
   const T* __restrict__ Nk = F.N[lev] + (long long)k * F.sN;
   const T* __restrict__ Zk = F.Z[lev] + (long long)k * F.sZ;
   T* __restrict__ Gk = F.Gi[lev] + (long long)k * P * P;
+  // diagonal Z~: S = N N^T + diag(Zd)^2, the panels of N alone
+  const T* __restrict__ zd = (F.zflag && F.zflag[F.level0 + lev]) ? F.Zd[lev] : nullptr;
   if (tid == 0) sfail = 0;
 
   // ---- 1. S = X X^T --------------------------------------------------------
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatchT<T> 
     tI[m] = I;
     tJ[m] = t - I * (I + 1) / 2;
   }
-  const int K = P + q;
+  const int K = zd ? P : P + q;
   for (int c0 = 0; c0 < K; c0 += kPanel) {
     __syncthreads();
     // stage X[:, c0 .. c0+31] as [row][32] (zero past the last column)
@@ -263,7 +265,14 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatchT<T> 
     if (w + m * kFacWaves < TL::kTiles) {
       T* Tp = St + TL::id(tI[m], tJ[m]) * 256;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) Tp[tix(arow<T>(g, i), r)] = acc[m][i];
+      for (int i = 0; i < 4; ++i) {
+        T v = acc[m][i];
+        if (zd && tI[m] == tJ[m] && arow<T>(g, i) == r) {
+          const T z = zd[16 * tI[m] + r];
+          v += z * z;
+        }
+        Tp[tix(arow<T>(g, i), r)] = v;
+      }
     }
   }
   __syncthreads();
@@ -301,6 +310,8 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_big(FactorBatchT<T> F
   const T* __restrict__ Zk = F.Z[lev] + (long long)k * F.sZ;
   T* __restrict__ Gk = F.Gi[lev] + (long long)k * P * P;
   auto at = [&](int I, int J) { return Gk + (long long)128 * I * P + 128 * J; };
+  // diagonal Z~: S = N N^T + diag(Zd)^2, no product with the dense Z~
+  const T* __restrict__ zd = (F.zflag && F.zflag[F.level0 + lev]) ? F.Zd[lev] : nullptr;
   if (tid == 0) sfail = 0;
   Gemm128<T> gm;
 
@@ -310,9 +321,18 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_big(FactorBatchT<T> F
       gm.zero();
       gm.template mul<false, true>(Nk + (long long)128 * I * P, P, Nk + (long long)128 * J * P, P,
                                    P, lds);
-      gm.template mul<false, true>(Zk + (long long)128 * I * q, q, Zk + (long long)128 * J * q, q,
-                                   q, lds);
+      if (!zd)
+        gm.template mul<false, true>(Zk + (long long)128 * I * q, q, Zk + (long long)128 * J * q,
+                                     q, q, lds);
       gm.store(at(I, J), P, T(1), T(0));
+      if (zd && I == J) {
+        __syncthreads();                                // the stored block, then its diagonal
+        for (int i = tid; i < 128; i += kFacThreads) {
+          const T z = zd[128 * I + i];
+          at(I, I)[(long long)i * P + i] += z * z;
+        }
+        __syncthreads();
+      }
     }
     for (int J = I + 1; J < NB; ++J)
       for (int e = tid; e < 128 * 128; e += kFacThreads) at(I, J)[(long long)(e >> 7) * P + (e & 127)] = T(0);

@@ -132,6 +132,7 @@ struct pitmg_handle {
   int coarse_log_cap = 0;
   int coarse_calls = 0;
   int* fail = nullptr;
+  int* vz_flags = nullptr;           // [20]: levels whose shared V, Z~ are diagonal
   int fail_code = INT_MAX;
   long long dev_bytes = 0;
   std::string err;
@@ -459,40 +460,30 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
     if (rc) return rc;
   }
   // shared V and Z~ that are diagonal (theta = 1 with an identity mass matrix
-  // and distributed control) are used through their diagonals
-  {
-    const bool cand = h->p == h->q && pb->V_stride == 0 && pb->Z_stride == 0;
-    std::vector<double> hv(cand ? pp : 0), hz(cand ? pp : 0), dg(2 * (size_t)h->p);
+  // and distributed control) are used through their diagonals: tested on
+  // the device for every level at once; the flags come back with the
+  // factorisation's status below
+  const bool vz_cand = h->p == h->q && pb->V_stride == 0 && pb->Z_stride == 0;
+  int vz_flags[20] = {0};
+  for (int l = 0; l < h->L; ++l) h->lv[l].vz_diag = false;
+  if (vz_cand) {
+    VZDiagBatch B;
+    B.nlev = h->L;
+    B.p = h->p;
     for (int l = 0; l < h->L; ++l) {
-      LevelBuf& b = h->lv[l];
-      b.vz_diag = false;
-      if (!cand) continue;
-      HIPCHK(h, hipMemcpyAsync(hv.data(), b.V, pp * 8, hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(h, hipMemcpyAsync(hz.data(), b.Z, pp * 8, hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(h, hipStreamSynchronize(h->stream));
-      bool diag = true;
-      for (int i = 0; i < h->p && diag; ++i)
-        for (int j = 0; j < h->p; ++j)
-          if (i != j && (hv[(size_t)i * h->p + j] != 0.0 || hz[(size_t)i * h->p + j] != 0.0)) {
-            diag = false;
-            break;
-          }
-      if (!diag) continue;
-      for (int i = 0; i < h->p; ++i) {
-        dg[i] = hv[(size_t)i * h->p + i];
-        dg[h->p + i] = hz[(size_t)i * h->p + i];
-      }
-      HIPCHK(h, hipMemcpyAsync(b.vzd, dg.data(), 2 * (size_t)h->p * 8, hipMemcpyHostToDevice,
-                               h->stream));
-      if (b.fp32) {
-        const int rc = timed(h, 0, [&] {
-          return launch_to_f32(b.vzd32, b.vzd, 2LL * h->p, h->stream);
-        });
-        if (rc) return rc;
-      }
-      HIPCHK(h, hipStreamSynchronize(h->stream));        // dg is reused per level
-      b.vz_diag = true;
+      B.V[l] = h->lv[l].V;
+      B.Z[l] = h->lv[l].Z;
+      B.out[l] = h->lv[l].vzd;
     }
+    int rc = timed(h, 0, [&] { return launch_vz_diag(B, h->vz_flags, h->stream); });
+    for (int l = 0; l < h->L && !rc; ++l)
+      if (h->lv[l].fp32)
+        rc = timed(h, 0, [&] {
+          return launch_to_f32(h->lv[l].vzd32, h->lv[l].vzd, 2LL * h->p, h->stream);
+        });
+    if (rc) return rc;
+    HIPCHK(h, hipMemcpyAsync(vz_flags, h->vz_flags, h->L * sizeof(int), hipMemcpyDeviceToHost,
+                             h->stream));
   }
   if (factor_mfma_supported(h->p, h->q)) {
     // the levels of each element type in one launch on the matrix cores; the
@@ -503,18 +494,23 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
     F.q = F32.q = h->q;
     F.sN = F32.sN = pb->N_stride;
     F.sZ = F32.sZ = pb->Z_stride;
+    // the diagonal test above runs first on the stream: where it flags a
+    // level, the factor forms S from N and the diagonal of Z~ alone
+    F.zflag = F32.zflag = vz_cand ? h->vz_flags : nullptr;
     for (int l = 0; l < h->L; ++l) {
       const LevelBuf& b = h->lv[l];
       if (b.fp32) {
         F32.N[F32.nlev] = b.N32;
         F32.Z[F32.nlev] = b.Z32;
         F32.Gi[F32.nlev] = b.Gi32;
+        F32.Zd[F32.nlev] = b.vzd32 ? b.vzd32 + h->p : nullptr;
         F32.start[F32.nlev + 1] = F32.start[F32.nlev] + b.n;
         F32.nlev++;
       } else {
         F.N[F.nlev] = b.N;
         F.Z[F.nlev] = b.Z;
         F.Gi[F.nlev] = b.Gi;
+        F.Zd[F.nlev] = b.vzd + h->p;
         F.start[F.nlev + 1] = F.start[F.nlev] + b.n;
         F.nlev++;
       }
@@ -538,19 +534,32 @@ int load_and_factor(pitmg_handle* h, const pitmg_problem* pb) {
   HIPCHK(h, hipMemcpyAsync(&code, h->fail, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->fail_code = code;
+  for (int l = 0; l < h->L; ++l) h->lv[l].vz_diag = vz_cand && vz_flags[l] == 1;
   if (code != INT_MAX)
     return set_err(h, PITMG_ERR_SINGULAR,
                    "S_k not positive definite at level " + std::to_string(code >> 20) +
                        ", step " + std::to_string((code & 0xFFFFF) + 1));
-  // W_k = G_k^{-1} N_k where the one-step sweeps take it (diagonal V, Z~)
-  for (int l = 0; l < h->L; ++l) {
-    LevelBuf& b = h->lv[l];
-    b.gn = false;
-    if (!b.gin || !b.vz_diag) continue;
-    LevelView v = view(h, l);
-    const int rc = timed(h, 0, [&] { return launch_gi_times_n(v, b.gin, h->stream); });
-    if (rc) return rc;
-    b.gn = true;
+  // W_k = G_k^{-1} N_k where the one-step sweeps take it (diagonal V, Z~):
+  // every such level in one launch
+  {
+    GiNBatch W;
+    W.p = h->p;
+    W.sN = h->lv[0].sN;
+    for (int l = 0; l < h->L; ++l) {
+      LevelBuf& b = h->lv[l];
+      b.gn = false;
+      if (!b.gin || !b.vz_diag) continue;
+      W.Gi[W.nlev] = b.Gi;
+      W.N[W.nlev] = b.N;
+      W.out[W.nlev] = b.gin;
+      W.start[W.nlev + 1] = W.start[W.nlev] + b.n;
+      W.nlev++;
+      b.gn = true;
+    }
+    if (W.nlev) {
+      const int rc = timed(h, 0, [&] { return launch_gi_times_batch(W, h->stream); });
+      if (rc) return rc;
+    }
   }
   if (h->coarse_fast) {
     LevelView vc = view(h, h->L - 1);
@@ -1773,6 +1782,7 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   if ((rc = dalloc(h, (void**)&h->coarse_its, (size_t)h->coarse_log_cap * sizeof(int))))
     return fail(rc);
   if ((rc = dalloc(h, (void**)&h->fail, sizeof(int)))) return fail(rc);
+  if ((rc = dalloc(h, (void**)&h->vz_flags, 20 * sizeof(int)))) return fail(rc);
   if ((rc = dalloc(h, (void**)&h->hand_ticket, sizeof(unsigned long long))) ||
       (rc = dalloc(h, (void**)&h->hand_flag, (size_t)(h->n + 1) * sizeof(unsigned long long))) ||
       (rc = dalloc(h, (void**)&h->hand_timeout, sizeof(int))))
@@ -2158,6 +2168,7 @@ void pitmg_destroy(pitmg_handle* h) {
   release(h->Qb);
   if (h->its_pinned) (void)hipHostFree(h->its_pinned);
   release(h->fail);
+  release(h->vz_flags);
   release(h->hand_ticket);
   release(h->hand_flag);
   release(h->hand_timeout);

@@ -141,7 +141,22 @@ struct FactorBatchT {
   const T* N[20] = {};
   const T* Z[20] = {};
   T* Gi[20] = {};
+  // device flags by hierarchy level (launch_vz_diag) and the diagonals of
+  // Z~ (p = q): where a flag is set, S = N N^T + diag(Zd)^2 (no product
+  // with the dense Z~); NULL flags: always the dense product
+  const int* zflag = nullptr;
+  const T* Zd[20] = {};
 };
+// The shared V and Z~ (p x p each) of up to 20 levels: flags[l] = 1 when
+// both have only zeros off the diagonal (exact comparison), and then
+// out[l] = [diag V | diag Z~] (2p values); flags[l] = 0 otherwise.
+struct VZDiagBatch {
+  int nlev = 0, p = 0;
+  const double* V[20] = {};
+  const double* Z[20] = {};
+  double* out[20] = {};
+};
+hipError_t launch_vz_diag(const VZDiagBatch& B, int* flags, hipStream_t s);
 bool factor_mfma_supported(int p, int q);
 hipError_t launch_factor_mfma(const FactorBatchT<double>& F, int* fail, hipStream_t s);
 hipError_t launch_factor_mfma(const FactorBatchT<float>& F, int* fail, hipStream_t s);
@@ -270,9 +285,18 @@ hipError_t launch_propagators(const LevelView& L, double* scratch, double* Phi, 
 // scratch of n p^2 doubles each).
 hipError_t launch_phi_pair(const LevelView& L, double* W, double* X, double* Phi, double* PhiT,
                            hipStream_t s);
-// W_k = G_k^{-1} N_k for every step of level L (p in {64, 128}, FP64), on
-// the matrix cores; out: [n][p][p] row-major.
-hipError_t launch_gi_times_n(const LevelView& L, double* out, hipStream_t s);
+// W_k = G_k^{-1} N_k (p in {64, 128}, FP64, out [n][p][p] row-major) on the
+// matrix cores for every step of up to 20 levels in one launch (block b of
+// the launch is step b - start[l] of entry l).
+struct GiNBatch {
+  int nlev = 0, p = 0;
+  long long sN = 0;
+  int start[21] = {0};
+  const double* Gi[20] = {};
+  const double* N[20] = {};
+  double* out[20] = {};
+};
+hipError_t launch_gi_times_batch(const GiNBatch& B, hipStream_t s);
 // The chain of a block Gauss-Seidel substitution (pitmg_gs.hip): from
 // t = D^{-1} r (type-major), hat's u slots (forward, M = Phi^T) or mu slots
 // (backward, M = Phi) receive the substituted values; its other slots are

@@ -366,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_apply(LevelView L, const double* __restr
   apply_step<NT>(L, blockIdx.x + 1, x, b, alpha, beta, out, sm);
 }
 
-// The same product for p = q = 64 MB in {256, 512} with V and Z~ diagonal
+// The same product for p = q = 64 MB in {64, 128, 256, 512} with V and Z~ diagonal
 // (shared by every step), one work-group of 512 threads per step and one
 // pass over N_k (onepass_products, pitmg_onepass.h): the row product
 // N u_k and the column product N^T lambda_k from the same loads.  Rows of
@@ -424,23 +424,24 @@ __global__ __launch_bounds__(kOnePassThreads) void k_apply_big(LevelView L,
 }
 
 static bool apply_big_supported(const LevelView& L, const double* x) {
-  return L.vz_diag && L.Vd && L.Zd && L.p == L.q && (L.p == 256 || L.p == 512) &&
-         aligned16(L.N) && aligned16(x);
+  return L.vz_diag && L.Vd && L.Zd && L.p == L.q &&
+         (L.p == 64 || L.p == 128 || L.p == 256 || L.p == 512) && aligned16(L.N) && aligned16(x);
 }
 
 hipError_t launch_apply(const LevelView& L, const double* x, const double* b, double alpha,
                         double beta, double* out, hipStream_t s) {
   if (small_supported(L.p, L.q)) return launch_apply_small(L, x, b, alpha, beta, out, s);
-  if (apply_shared_supported(L)) return launch_apply_shared(L, x, b, alpha, beta, out, s);
   if (apply_big_supported(L, x)) {
-    if (L.p == 512)
-      hipLaunchKernelGGL(k_apply_big<8>, dim3(L.n), dim3(kOnePassThreads), 0, s, L, x, b, alpha,
-                         beta, out);
-    else
-      hipLaunchKernelGGL(k_apply_big<4>, dim3(L.n), dim3(kOnePassThreads), 0, s, L, x, b, alpha,
-                         beta, out);
+    const dim3 g(L.n), t(kOnePassThreads);
+    switch (L.p) {
+      case 64: hipLaunchKernelGGL(k_apply_big<1>, g, t, 0, s, L, x, b, alpha, beta, out); break;
+      case 128: hipLaunchKernelGGL(k_apply_big<2>, g, t, 0, s, L, x, b, alpha, beta, out); break;
+      case 256: hipLaunchKernelGGL(k_apply_big<4>, g, t, 0, s, L, x, b, alpha, beta, out); break;
+      default: hipLaunchKernelGGL(k_apply_big<8>, g, t, 0, s, L, x, b, alpha, beta, out); break;
+    }
     return hipGetLastError();
   }
+  if (apply_shared_supported(L)) return launch_apply_shared(L, x, b, alpha, beta, out, s);
   const size_t lds = apply_lds_doubles(L.p, L.q, kApplyThreads) * sizeof(double);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_apply<kApplyThreads>,
@@ -1061,6 +1062,32 @@ hipError_t launch_dots(const double* basis, int nb, const double* x1, const doub
   const int ng = dot_groups(len, nb);
   hipLaunchKernelGGL(k_dots, dim3(krylov_slices(len), ng), dim3(kDotThreads), 0, s, basis, nb,
                      x1, x2, len, partial);
+  return hipGetLastError();
+}
+
+// One work-group per level (VZDiagBatch); the off-diagonal test over all
+// threads by a barrier reduction.
+__global__ __launch_bounds__(1024) void k_vz_diag(VZDiagBatch B, int* __restrict__ flags) {
+  const int l = blockIdx.x, p = B.p;
+  const double* __restrict__ V = B.V[l];
+  const double* __restrict__ Z = B.Z[l];
+  const long long pp = (long long)p * p;
+  int off = 0;
+  for (long long e = threadIdx.x; e < pp; e += blockDim.x) {
+    const long long i = e / p, j = e % p;
+    if (i != j && (V[e] != 0.0 || Z[e] != 0.0)) off = 1;
+  }
+  const int any = __syncthreads_or(off);
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    B.out[l][i] = V[(long long)i * p + i];
+    B.out[l][p + i] = Z[(long long)i * p + i];
+  }
+  if (threadIdx.x == 0) flags[l] = any ? 0 : 1;
+}
+
+hipError_t launch_vz_diag(const VZDiagBatch& B, int* flags, hipStream_t s) {
+  if (B.nlev < 1 || B.nlev > 20) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_vz_diag, dim3(B.nlev), dim3(1024), 0, s, B, flags);
   return hipGetLastError();
 }
 
