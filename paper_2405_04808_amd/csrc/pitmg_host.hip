@@ -133,6 +133,7 @@ struct pitmg_handle {
   int coarse_calls = 0;
   int* fail = nullptr;
   int* vz_flags = nullptr;           // [20]: levels whose shared V, Z~ are diagonal
+  double* zeros = nullptr;           // 64 zero bytes (LevelView::zeros)
   int fail_code = INT_MAX;
   long long dev_bytes = 0;
   std::string err;
@@ -337,6 +338,7 @@ LevelView view(const pitmg_handle* h, int l) {
   v.Vd32 = b.vzd32;
   v.Zd32 = b.vzd32 ? b.vzd32 + h->p : nullptr;
   v.GiN = b.gn ? b.gin : nullptr;
+  v.zeros = h->zeros;
   // the coarsest level's block solves (inside the coarse SGS) take one step
   // per work-group: at 8 steps the one-step kernel has the shorter latency
   if (l == h->L - 1 && v.sweep_cfg == 0 && jacobi_tiled_supported(h->p, h->q))
@@ -1783,6 +1785,9 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
     return fail(rc);
   if ((rc = dalloc(h, (void**)&h->fail, sizeof(int)))) return fail(rc);
   if ((rc = dalloc(h, (void**)&h->vz_flags, 20 * sizeof(int)))) return fail(rc);
+  if ((rc = dalloc(h, (void**)&h->zeros, 8 * sizeof(double)))) return fail(rc);
+  if (launch_fill(h->zeros, 0.0, 8, h->stream) != hipSuccess)
+    return fail(set_err(h, PITMG_ERR_HIP, "fill of the zero line failed"));
   if ((rc = dalloc(h, (void**)&h->hand_ticket, sizeof(unsigned long long))) ||
       (rc = dalloc(h, (void**)&h->hand_flag, (size_t)(h->n + 1) * sizeof(unsigned long long))) ||
       (rc = dalloc(h, (void**)&h->hand_timeout, sizeof(int))))
@@ -2169,6 +2174,7 @@ void pitmg_destroy(pitmg_handle* h) {
   if (h->its_pinned) (void)hipHostFree(h->its_pinned);
   release(h->fail);
   release(h->vz_flags);
+  release(h->zeros);
   release(h->hand_ticket);
   release(h->hand_flag);
   release(h->hand_timeout);

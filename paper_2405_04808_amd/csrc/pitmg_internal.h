@@ -61,6 +61,9 @@ struct LevelView {
   // shared V, Z~ and p = q in {64, 128}, else NULL: the one-step sweeps then
   // take s = W r_u + G^{-1} d and N^T lambda = W^T s (pitmg_tiled.h)
   const double* GiN = nullptr;
+  // 16 zero bytes in device memory (the one-step kernels read the factor's
+  // vectors above the diagonal from here)
+  const void* zeros = nullptr;
 };
 
 // Block pointers of a level in the arithmetic of the smoother.

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   };
   typename TS::Regs R;
   __builtin_amdgcn_sched_barrier(0);           // keep the loads above ahead of the tile's
-  TS::load_raw(L, kk, gn, R);
+  TS::load_straight(L, kk, gn, R);
   __builtin_amdgcn_sched_barrier(0);
   if (on) {
     cmk = prev.value(fcm, 4, k);
@@ -168,8 +168,6 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
     if (gn) srd[i] = TS::d_of(dg, srz, srm, srl, i);
   }
   __syncthreads();
-  __builtin_amdgcn_sched_barrier(0);           // the factor's zeros after the gather
-  TS::mask_g(R);
   if (gn) TS::solve_gn(R, sru, srd, slam, scr);
   else TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
   if (on) {
@@ -375,7 +373,7 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   };
   typename TS::Regs R;
   __builtin_amdgcn_sched_barrier(0);           // keep the loads above ahead of the tile's
-  TS::load_raw(L, kk, gn, R);
+  TS::load_straight(L, kk, gn, R);
   __builtin_amdgcn_sched_barrier(0);
   if (on) {
     cmk = prev.value(fcm, 4, k);
@@ -397,8 +395,6 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
     if (gn) srd[i] = TS::d_of(dg, srz, srm, srl, i);
   }
   __syncthreads();
-  __builtin_amdgcn_sched_barrier(0);           // the factor's zeros after the gather
-  TS::mask_g(R);
   if (gn) TS::solve_gn(R, sru, srd, slam, scr);
   else TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
   // the work-group of block n also takes block n+1 = (v_n, mu_n), whose

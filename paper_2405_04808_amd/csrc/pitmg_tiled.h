@@ -85,32 +85,22 @@ __device__ __forceinline__ void tile_load_row_lower(const T* __restrict__ row, i
   }
 }
 
-// tile_load_row_lower without the zeroing: lanes whose vector lies above the
-// diagonal hold a copy of their first vector until tile_mask_lower clears it.
-// A kernel calls that after the barrier that ends its gather, so that the
-// gather does not wait for the factor's loads.
+// tile_load_row_lower as straight-line code: every lane issues every load,
+// and a vector wholly above the diagonal is read from `zeros` (16 zero bytes
+// in device memory, a line every such lane shares, so no block bytes are
+// fetched for it).  With no branch around the loads the compiler can wait
+// for loads issued before the tile without waiting for the tile.
 template <int CT, class T>
-__device__ __forceinline__ void tile_load_row_lower_raw(const T* __restrict__ row, int i,
-                                                        T (&dst)[CT]) {
+__device__ __forceinline__ void tile_load_row_lower_z(const T* __restrict__ row, int i,
+                                                      const T* __restrict__ zeros,
+                                                      T (&dst)[CT]) {
   constexpr int E = Vec16<T>::n;
   const int j0 = E * (threadIdx.x % 16);
   const T* src = row + j0;
 #pragma unroll
   for (int c = 0; c < CT; c += E) {
-    const T* a = j0 + 16 * c <= i ? src + 16 * c : src;
+    const T* a = j0 + 16 * c <= i ? src + 16 * c : zeros;
     Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(a), dst + c);
-  }
-}
-
-template <int CT, class T>
-__device__ __forceinline__ void tile_mask_lower(int i, T (&dst)[CT]) {
-  constexpr int E = Vec16<T>::n;
-  const int j0 = E * (threadIdx.x % 16);
-#pragma unroll
-  for (int c = 0; c < CT; c += E) {
-    const bool in = j0 + 16 * c <= i;
-#pragma unroll
-    for (int e = 0; e < E; ++e) dst[c + e] = in ? dst[c + e] : T(0);
   }
 }
 
@@ -154,23 +144,19 @@ struct TiledSolve {
   }
 
   // The one-step kernels' tiles: W_k = G_k^{-1} N_k (gn, levels whose L.GiN
-  // is set) or N_k, and G_k^{-1} unmasked; mask_g() completes them.
-  __device__ __forceinline__ static void load_raw(const LevelView& L, long long kk, bool gn,
-                                                  Regs& R) {
+  // is set) or N_k, and G_k^{-1} with its zeros from L.zeros.
+  __device__ __forceinline__ static void load_straight(const LevelView& L, long long kk, bool gn,
+                                                       Regs& R) {
     const int r0 = RT * (threadIdx.x / 16);
     const T* __restrict__ Nk =
         gn ? Mats<T>::GiN(L) + kk * (long long)P * P : Mats<T>::N(L) + kk * L.sN;
 #pragma unroll
     for (int r = 0; r < RT; ++r) tile_load_row<CT, T>(Nk + (long long)(r0 + r) * P, R.nt[r]);
     const T* __restrict__ Gk = Mats<T>::Gi(L) + kk * (long long)P * P;
+    const T* __restrict__ z = reinterpret_cast<const T*>(L.zeros);
 #pragma unroll
     for (int r = 0; r < RT; ++r)
-      tile_load_row_lower_raw<CT, T>(Gk + (long long)(r0 + r) * P, r0 + r, R.gt[r]);
-  }
-  __device__ __forceinline__ static void mask_g(Regs& R) {
-    const int r0 = RT * (threadIdx.x / 16);
-#pragma unroll
-    for (int r = 0; r < RT; ++r) tile_mask_lower<CT, T>(r0 + r, R.gt[r]);
+      tile_load_row_lower_z<CT, T>(Gk + (long long)(r0 + r) * P, r0 + r, z, R.gt[r]);
   }
 
   // Column partials of one thread -> per-wave slot of red (lanes 0..15).
