@@ -57,6 +57,39 @@ __device__ __forceinline__ double xor32_sum(double v) {
   return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
 }
 
+// Two sums for one swap: x + x[lane ^ 16] in the even rows (0, 2) and
+// y + y[lane ^ 16] in the odd rows (1, 3).  The swap exchanges the odd rows
+// of its first operand with the even rows of its second, so each register
+// it returns holds one value of each pair.
+__device__ __forceinline__ float pair16_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double pair16_sum(double x, double y) {
+  const auto l = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x),
+                                                  (unsigned)__double2loint(y), false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x),
+                                                  (unsigned)__double2hiint(y), false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
+// x + x[lane ^ 32] in lanes 0..31 and y + y[lane ^ 32] in lanes 32..63
+// (the swap exchanges the upper half of its first operand with the lower
+// half of its second).
+__device__ __forceinline__ float pair32_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double pair32_sum(double x, double y) {
+  const auto l = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x),
+                                                  (unsigned)__double2loint(y), false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x),
+                                                  (unsigned)__double2hiint(y), false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
   return xor32_sum(xor16_sum(row_sum16(v)));

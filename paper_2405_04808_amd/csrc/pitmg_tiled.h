@@ -172,6 +172,27 @@ struct TiledSolve {
     }
   }
 
+  // Column partials of two arrays at once, va -> per-wave slots of redA and
+  // vb -> redB: each swap of pair16_sum / pair32_sum serves a value of both,
+  // so lane (row rho) of the wave ends with the total of array rho & 1 for
+  // column c + (rho >> 1) CT/2, and every lane stores CT/2 values.  Same sums
+  // in the same order as two col_partial calls.
+  __device__ __forceinline__ static void col_partial_pair(T (&va)[CT], T (&vb)[CT], T* redA,
+                                                          T* redB) {
+    static_assert(CT % 2 == 0, "columns in pairs");
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, rho = lane / 16;
+    T a[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) a[c] = pair16_sum(va[c], vb[c]);
+    T* red = (rho & 1) ? redB : redA;
+    const int off = (rho >> 1) * (CT / 2);
+#pragma unroll
+    for (int c = 0; c < CT / 2; ++c) {
+      const T v = pair32_sum(a[c], a[c + CT / 2]);
+      red[w * P + tile_col<T>(c + off)] = v;
+    }
+  }
+
   __device__ __forceinline__ static T col_total(const T* red, int j) {
     T s = 0;
 #pragma unroll
@@ -357,8 +378,7 @@ struct TiledSolve {
       wacc[c] = sw;
       lacc[c] = sl;
     }
-    col_partial(wacc, red);
-    col_partial(lacc, red + kTiledWaves * P);
+    col_partial_pair(wacc, lacc, red, red + kTiledWaves * P);
     __syncthreads();
     for (int j = tid; j < P; j += kThreads) ol[j] = col_total(red + kTiledWaves * P, j);
   }
