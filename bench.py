@@ -120,10 +120,20 @@ def vcycle_launches(L, nu_pre, nu_post, pairs):
     return out
 
 
-def vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes=8):
+def chained(L, nu_pre, nu_post, pairs, pair_sweeps):
+    """Whether the library runs the pre-smoothing of every level above the
+    coarsest in one launch and the post-smoothing in another (pair_sweeps 2,
+    the one-step kernel on every such level, V(2,2), at most 8 such levels)."""
+    return (pair_sweeps == 2 and nu_pre == 2 and nu_post == 2 and 2 <= L - 1 <= 8
+            and all(pr == "tiled" for pr in pairs))
+
+
+def vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_bytes=8,
+                  chain=False):
     """Sweep bytes of one V-cycle and its number of sweep launches: (bytes
     with the blocks counted once per sweep, bytes with the blocks counted
-    once per launch, launches)."""
+    once per launch, launches).  A chained cycle has the same sweeps in two
+    launches."""
     per_sweep = per_launch = 0.0
     launches = vcycle_launches(L, nu_pre, nu_post, pairs)
     for lev, k in launches:
@@ -131,7 +141,7 @@ def vcycle_sweeps(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, pairs, mat_by
         one = sweep_bytes(p, q, nl, shared_V, shared_Z, mat_bytes)
         per_sweep += k * one
         per_launch += one + (k - 1) * vector_bytes(p, q, nl)
-    return per_sweep, per_launch, len(launches)
+    return per_sweep, per_launch, 2 if chain else len(launches)
 
 
 def vcycle_bytes(p, q, n, L, nu_pre, nu_post, shared_V, shared_Z, mat_bytes=8, fp64_residual=False,
@@ -516,9 +526,10 @@ def main():
         # algorithmic bytes of the Jacobi launches of the timed steps: whole
         # V-cycles' sweeps, so bytes per launch is the V-cycle's sweep bytes
         # over its sweep launches
+        chain = chained(L, opts.nu_pre, opts.nu_post, pairs, opts.pair_sweeps)
         per_sweep, per_launch_once, nlaunch = vcycle_sweeps(p, q, n, L, opts.nu_pre,
                                                             opts.nu_post, shared_V, shared_Z,
-                                                            pairs)
+                                                            pairs, chain=chain)
         launches, ms = prof["jacobi"]
         alg_bytes = per_sweep / nlaunch * launches
         achieved = alg_bytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -527,7 +538,10 @@ def main():
         # the counter profile covers the Burgers nx=128 workload only
         rec = read_traffic(COUNTERS) if args.workload == "burgers128" else None
         names = {0: "built-in", -1: "k_jacobi_tiled<%d, %d, double>" % (p // 32, p // 16)}
-        kname = "block Jacobi sweep, levels 0..%d: " % (L - 2) + ", ".join(
+        kname = ("block Jacobi sweep, levels 0..%d chained: k_jacobi_chain<%d, %d, double>, "
+                 "one launch for the pre-smoothing and one for the post-smoothing of every "
+                 "level, two sweeps per level" % (L - 2, p // 32, p // 16)) if chain else \
+            "block Jacobi sweep, levels 0..%d: " % (L - 2) + ", ".join(
             ("k_jacobi_tiled2<%d, %d, double> (two sweeps per launch)" % (p // 32, p // 16)
              if pairs[lev] == "tiled" else
              "k_jacobi_shared_nl2<%d, %d> x%d steps (two sweeps per launch)" % (p // 32, p // 16, c)

@@ -150,6 +150,16 @@ typedef struct {
                                   solve that contains it returns
                                   PITMG_ERR_HIP.  Streams under capture get
                                   one sweep per launch.
+                                  2: as 1, and where every level above the
+                                  coarsest sweeps with the one-step kernel
+                                  (V-cycle, nu 2/2, step ratio 2, block
+                                  Jacobi), the pre-smoothing of all those
+                                  levels is one launch and their
+                                  post-smoothing another: a block of level
+                                  l + 1 starts as soon as the blocks of level
+                                  l it reads have finished (dataflow flags,
+                                  bounded waits as above), so the levels
+                                  overlap.  Results are bitwise those of 1.
                                   0: one sweep per launch.                     */
   double omega;                /* weight of the block Jacobi correction on every
                                   level above the coarsest:
@@ -228,7 +238,7 @@ typedef struct {
 
 /* Defaults: nu 2/2, coarse tol 1e-3, coarse maxit 50, restart 30, maxit 300,
  * transfer_variant 0, smoother_fp32 0, coarse_mode 0, stall_ratio 0.9,
- * stall_steps 2, vcycle_graph 0, apply_from_sweep 1, pair_sweeps 1,
+ * stall_steps 2, vcycle_graph 0, apply_from_sweep 1, pair_sweeps 2,
  * omega 0.5, mu_scale 2, cycle 0 (V), smoother 0 (block Jacobi), unlifted
  * 0, coarsen 2.  (omega = 1 with mu_scale = 1 is the cycle exactly as
  * printed.) */

@@ -115,6 +115,16 @@ __device__ __forceinline__ double interp_node(const double* __restrict__ seg, in
   return 0.5 * (a + b);
 }
 
+// Stores and loads of values that another work-group of the same launch
+// reads or wrote: agent-scope atomics, which gfx950 performs at the device's
+// coherence point (the sc1 bit), past the non-coherent L2 of each XCD.
+__device__ __forceinline__ void coherent_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double coherent_load(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The loads behind one entry of PrevIterate::at, issued together by
 // PrevIterate::fetch and combined by PrevIterate::value (same arithmetic as
 // at()), so that a kernel can request several entries before it needs any.
@@ -131,6 +141,12 @@ struct PrevIterate {
   const double* ec;
   int p, q, n, variant;
   double mu_scale;
+  // ec is written by other work-groups of the same launch: read it with
+  // coherent loads
+  bool ec_coherent = false;
+  __device__ __forceinline__ double ec_at(long long idx) const {
+    return ec_coherent ? coherent_load(ec + idx) : ec[idx];
+  }
   __device__ double at(int type, int k, int i) const {
     const TypeMajor Tm(p, q, n);
     const long long seg[5] = {Tm.u, Tm.v, Tm.z, Tm.l, Tm.m};
@@ -140,10 +156,19 @@ struct PrevIterate {
       const int nc = n / 2;
       const TypeMajor Tc(p, q, nc > 0 ? nc : 1);
       if (type == 2) {
-        v += ec[Tc.z + (long long)((k + 1) / 2 - 1) * q + i];
+        v += ec_at(Tc.z + (long long)((k + 1) / 2 - 1) * q + i);
       } else {
         const long long sc[5] = {Tc.u, Tc.v, Tc.z, Tc.l, Tc.m};
-        const double e = interp_node(ec + sc[type], nc, p, k, i, variant);
+        double e;
+        if (ec_coherent) {
+          int ma, mb, two;
+          node_terms(nc, k, variant, &ma, &mb, &two);
+          const double a = ec_at(sc[type] + (long long)(ma - 1) * p + i);
+          const double b2 = ec_at(sc[type] + (long long)(mb - 1) * p + i);
+          e = two == 0 ? a : 0.5 * (a + (two == 1 ? b2 : 0.0));
+        } else {
+          e = interp_node(ec + sc[type], nc, p, k, i, variant);
+        }
         v += type == 4 ? mu_scale * e : e;
       }
     }
@@ -185,13 +210,13 @@ struct PrevIterate {
       const int nc = n / 2;
       const TypeMajor Tc(p, q, nc > 0 ? nc : 1);
       if (type == 2) {
-        f.a = ec[Tc.z + (long long)((k + 1) / 2 - 1) * q + i];
+        f.a = ec_at(Tc.z + (long long)((k + 1) / 2 - 1) * q + i);
       } else {
         const long long sc[5] = {Tc.u, Tc.v, Tc.z, Tc.l, Tc.m};
         int ma, mb, two;
         node_terms(nc, k, variant, &ma, &mb, &two);
-        f.a = ec[sc[type] + (long long)(ma - 1) * p + i];
-        f.b = ec[sc[type] + (long long)(mb - 1) * p + i];
+        f.a = ec_at(sc[type] + (long long)(ma - 1) * p + i);
+        f.b = ec_at(sc[type] + (long long)(mb - 1) * p + i);
       }
     }
     return f;

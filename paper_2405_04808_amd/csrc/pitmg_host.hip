@@ -362,8 +362,8 @@ int check_options(pitmg_handle* h, const pitmg_options& o) {
     return set_err(h, PITMG_ERR_INVALID, "stall_ratio must be > 0 and stall_steps >= 1");
   if (o.apply_from_sweep != 0 && o.apply_from_sweep != 1)
     return set_err(h, PITMG_ERR_INVALID, "apply_from_sweep must be 0 or 1");
-  if (o.pair_sweeps != 0 && o.pair_sweeps != 1)
-    return set_err(h, PITMG_ERR_INVALID, "pair_sweeps must be 0 or 1");
+  if (o.pair_sweeps < 0 || o.pair_sweeps > 2)
+    return set_err(h, PITMG_ERR_INVALID, "pair_sweeps must be 0, 1 or 2");
   if (o.vcycle_graph != 0 && o.vcycle_graph != 1)
     return set_err(h, PITMG_ERR_INVALID, "vcycle_graph must be 0 or 1");
   if (o.vcycle_graph && h && h->stream == nullptr)
@@ -794,6 +794,67 @@ hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, cons
   return e;
 }
 
+// MG_0(b) -> out with the pre-smoothing of levels 0 .. L-2 in one launch and
+// their post-smoothing in another (pair_sweeps = 2): the same sweeps, fused
+// restrictions and interpolations, into the same buffers, as the level by
+// level recursion of vcycle_level with two sweeps per launch.
+// chained_cycle says whether the handle's cycle has that form.
+int coarse_correction(pitmg_handle* h, int l, int cyc);
+
+bool chain_form(const pitmg_options& o, int n_levels) {
+  const int ns = n_levels - 1;                 // levels that smooth
+  return o.pair_sweeps == 2 && o.smoother == 0 && o.cycle == 0 && o.coarsen == 2 &&
+         o.nu_pre == 2 && o.nu_post == 2 && ns >= 2 && ns <= jacobi_chain_max();
+}
+
+bool chained_cycle(pitmg_handle* h) {
+  const int ns = h->L - 1;
+  if (!chain_form(h->opt, h->L)) return false;
+  for (int l = 0; l < ns; ++l)
+    if (h->lv[l].res || !jacobi_chain_supported(view(h, l), h->stream)) return false;
+  return true;
+}
+
+int vcycle_chained(pitmg_handle* h, const double* b, double* out) {
+  const int ns = h->L - 1;
+  ChainSweep dn[16], up[16];
+  int off = 0;
+  for (int l = 0; l < ns; ++l) {
+    const LevelView v = view(h, l);
+    LevelBuf& B = h->lv[l];
+    LevelBuf& C = h->lv[l + 1];
+    const double w = v.omega;
+    const double rbeta = w != 1.0 ? (1.0 - w) * (1.0 - w) : 0.0;
+    const double ra = w != 1.0 ? w : 1.0;
+    const double* bl = l == 0 ? b : B.b;
+    dn[l] = ChainSweep{v, bl, nullptr, nullptr, B.y0, B.y1, C.b, rbeta, ra, off};
+    up[ns - 1 - l] = ChainSweep{v, bl, B.y1, C.out, B.y0, l == 0 ? out : B.out, nullptr,
+                                0.0, 1.0, off};
+    off += v.n;
+  }
+  auto chain = [&](const ChainSweep* sw, int dir) {
+    const PairSync ps{h->hand_ticket, h->hand_tickets, h->hand_flag, h->hand_epoch + 1,
+                      h->hand_timeout, h->hand_spin};
+    int groups = 0;
+    const hipError_t e = launch_jacobi_chain(sw, ns, dir, h->opt.transfer_variant, ps, &groups,
+                                             h->stream);
+    if (e == hipSuccess) {
+      h->hand_tickets += (unsigned long long)groups;
+      h->hand_epoch += 2;
+    }
+    return e;
+  };
+  int rc = timed_kernel(h, 1, [&] { return chain(dn, 0); });
+  if (rc) return rc;
+  if ((rc = coarse_correction(h, ns - 1, 0))) return rc;
+  rc = timed_kernel(h, 1, [&] { return chain(up, 1); });
+  if (rc) return rc;
+  // A~ z from the last sweep's identity needs an undamped FP64 sweep
+  const LevelView v0 = view(h, 0);
+  if (v0.omega == 1.0 && !v0.fp32) h->top_prev = h->lv[0].y0;
+  return PITMG_OK;
+}
+
 // The transfers between level l and l + 1 for the handle's step ratio:
 // R r into C.b-shaped bc, and y += P e.
 int restrict_level(pitmg_handle* h, int l, const double* r, double* bc) {
@@ -959,6 +1020,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out, int cyc) 
   if (l == 0) h->top_prev = nullptr;
   if (l == h->L - 1) return coarse_dispatch(h, b, out);
   if (o.smoother != 0) return vcycle_level_gs(h, l, b, out, cyc);
+  if (l == 0 && cyc == 0 && chained_cycle(h)) return vcycle_chained(h, b, out);
   LevelBuf& B = h->lv[l];
   LevelBuf& C = h->lv[l + 1];
   double* bufs[2] = {B.y0, B.y1};
@@ -1505,7 +1567,7 @@ void pitmg_default_options(pitmg_options* o) {
   o->stall_steps = 2;
   o->vcycle_graph = 0;
   o->apply_from_sweep = 1;
-  o->pair_sweeps = 1;
+  o->pair_sweeps = 2;
   o->omega = 0.5;
   o->mu_scale = 2.0;
   o->cycle = 0;
@@ -1522,10 +1584,18 @@ int pitmg_autotune(pitmg_handle* h, int* cfg) {
   HIPCHK(h, hipEventCreate(&e1));
   int rc = PITMG_OK;
   constexpr int kReps = 10;
+  // a cycle that can chain its levels keeps the one-step kernel on every
+  // level it applies to (the chained launches need it on all of them)
+  const bool chain = chain_form(h->opt, h->L) && jacobi_tiled_supported(h->p, h->q);
   for (int l = 0; l < h->L; ++l) {
     LevelBuf& B = h->lv[l];
     if (cfg) cfg[l] = 0;
     if (l == h->L - 1 || !B.y0 || !B.y1) continue;
+    if (chain) {
+      B.sweep_cfg = -1;
+      if (cfg) cfg[l] = -1;
+      continue;
+    }
     B.sweep_cfg = 0;
     LevelView v = view(h, l);
     std::vector<int> cands;
@@ -1789,11 +1859,11 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
   if (launch_fill(h->zeros, 0.0, 8, h->stream) != hipSuccess)
     return fail(set_err(h, PITMG_ERR_HIP, "fill of the zero line failed"));
   if ((rc = dalloc(h, (void**)&h->hand_ticket, sizeof(unsigned long long))) ||
-      (rc = dalloc(h, (void**)&h->hand_flag, (size_t)(h->n + 1) * sizeof(unsigned long long))) ||
+      (rc = dalloc(h, (void**)&h->hand_flag, (size_t)(2 * h->n + 2) * sizeof(unsigned long long))) ||
       (rc = dalloc(h, (void**)&h->hand_timeout, sizeof(int))))
     return fail(rc);
   if (hipMemsetAsync(h->hand_ticket, 0, sizeof(unsigned long long), h->stream) != hipSuccess ||
-      hipMemsetAsync(h->hand_flag, 0, (size_t)(h->n + 1) * sizeof(unsigned long long),
+      hipMemsetAsync(h->hand_flag, 0, (size_t)(2 * h->n + 2) * sizeof(unsigned long long),
                      h->stream) != hipSuccess ||
       hipMemsetAsync(h->hand_timeout, 0, sizeof(int), h->stream) != hipSuccess)
     return fail(set_err(h, PITMG_ERR_HIP, "hipMemsetAsync failed"));

@@ -210,6 +210,28 @@ hipError_t launch_jacobi_pair(const LevelView& L, const double* b, const double*
                               const double* ecoarse, int variant, double* y1, double* y2,
                               double* restrict_out, double rbeta, double ra,
                               const PairSync& ps, int* groups, hipStream_t s);
+// Two-sweep smoothing of several levels in one launch (pitmg_jacobi_tiled.hip):
+// sw[0..nlev) in ticket order, levels 0, 1, ... (up = 0: pre-smoothing, each
+// level restricting into the next one's b) or ..., 1, 0 (up = 1:
+// post-smoothing, each level's ec the previous one's y2).  Every level sweeps
+// with the one-step tiled kernel (same p, q and precision); flag_off gives
+// each level its own range of hand-off flags.  The launch uses the epochs
+// ps.epoch (first sweeps) and ps.epoch + 1 (finished blocks).
+struct ChainSweep {
+  LevelView L;
+  const double* b;
+  const double* yold;
+  const double* ec;
+  double* y1;
+  double* y2;
+  double* restrict_out;
+  double rbeta, ra;
+  int flag_off;
+};
+int jacobi_chain_max();
+bool jacobi_chain_supported(const LevelView& L, hipStream_t s);
+hipError_t launch_jacobi_chain(const ChainSweep* sw, int nlev, int up, int variant,
+                               const PairSync& ps, int* groups, hipStream_t s);
 hipError_t launch_jacobi_shared2(const LevelView& L, const double* b, const double* yold,
                                  const double* ecoarse, int variant, double* y1, double* y2,
                                  double* restrict_out, double rbeta, double ra,

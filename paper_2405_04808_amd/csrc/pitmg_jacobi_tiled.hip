@@ -28,6 +28,16 @@ struct FusedRestrict {
   double* rc;                  // coarse vector, or NULL (no restriction)
   int variant;
   double beta, a, mu_scale;
+  // b written by other work-groups of the same launch (read it with coherent
+  // loads); rc read by other work-groups of the same launch (coherent stores)
+  int coh_b = 0, coh_rc = 0;
+  __device__ __forceinline__ double ldb(const double* __restrict__ b, long long idx) const {
+    return coh_b ? coherent_load(b + idx) : b[idx];
+  }
+  __device__ __forceinline__ void put(long long idx, double v) const {
+    if (coh_rc) coherent_store(rc + idx, v);
+    else rc[idx] = v;
+  }
   // coarse step m (1-based) whose mu, v, z, lambda block k writes, else 0
   __device__ int mu_writer(int k) const {
     if (!rc) return 0;
@@ -48,23 +58,23 @@ struct FusedRestrict {
     const long long o = (long long)(m - 1) * P + i;
     const long long f = (long long)(fine(m) - 1) * P + i;
     if (beta != 0.0) {
-      rc[Tc.m + o] = mu_scale * (beta * b[Tm.m + f] + cu);
-      rc[Tc.v + o] = beta * b[Tm.v + f];
-      rc[Tc.l + o] = beta * b[Tm.l + f];
-      rc[Tc.z + o] = 0.5 * beta * (b[Tm.z + (long long)(2 * m - 2) * P + i] +
-                                   b[Tm.z + (long long)(2 * m - 1) * P + i]);
+      put(Tc.m + o, mu_scale * (beta * ldb(b, Tm.m + f) + cu));
+      put(Tc.v + o, beta * ldb(b, Tm.v + f));
+      put(Tc.l + o, beta * ldb(b, Tm.l + f));
+      put(Tc.z + o, 0.5 * beta * (ldb(b, Tm.z + (long long)(2 * m - 2) * P + i) +
+                                  ldb(b, Tm.z + (long long)(2 * m - 1) * P + i)));
     } else {
-      rc[Tc.m + o] = mu_scale * cu;
-      rc[Tc.v + o] = 0.0;
-      rc[Tc.z + o] = 0.0;
-      rc[Tc.l + o] = 0.0;
+      put(Tc.m + o, mu_scale * cu);
+      put(Tc.v + o, 0.0);
+      put(Tc.z + o, 0.0);
+      put(Tc.l + o, 0.0);
     }
   }
   // coarse u of step m from c_mu = a y_A,mu - y_mu at fine step kf
   __device__ void put_u(int m, int i, double cmu, const double* __restrict__ b,
                         const TypeMajor& Tm, const TypeMajor& Tc, int P) const {
     const long long f = (long long)(fine(m) - 1) * P + i;
-    rc[Tc.u + (long long)(m - 1) * P + i] = (beta != 0.0 ? beta * b[Tm.u + f] : 0.0) + cmu;
+    put(Tc.u + (long long)(m - 1) * P + i, (beta != 0.0 ? beta * ldb(b, Tm.u + f) : 0.0) + cmu);
   }
 };
 
@@ -254,22 +264,24 @@ hipError_t launch_jacobi_tiled(const LevelView& L, const double* b, const double
 
 namespace {
 
-__device__ __forceinline__ void coherent_store(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double coherent_load(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
-// thread 0: wait until *f >= epoch; returns false after spin ticks
-__device__ bool pair_wait(const unsigned long long* f, unsigned long long epoch,
-                          unsigned long long spin) {
+// Wave 0 of the work-group (all 64 lanes) waits until each lane's flag (NULL:
+// none) reads at least epoch, polling all of them at once; after ps.spin
+// ticks it gives up and raises bit 0 of *timeout.
+__device__ void await_wave(const unsigned long long* mine, unsigned long long epoch,
+                           const PairSync& ps) {
+  bool ok = !mine || __hip_atomic_load(mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+  if (__all(ok)) return;
   const unsigned long long t0 = wall_clock64();
-  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-    if (wall_clock64() - t0 > spin) return false;
+  for (;;) {
     __builtin_amdgcn_s_sleep(2);
+    if (!ok) ok = __hip_atomic_load(mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+    if (__all(ok)) return;
+    if (wall_clock64() - t0 > ps.spin) {
+      if (threadIdx.x == 0) atomicOr(ps.timeout, 1);
+      return;
+    }
   }
-  return true;
 }
 
 // Publish this work-group's first sweep (flag = epoch) and wait for the
@@ -279,29 +291,94 @@ __device__ void pair_handoff(unsigned long long* self, const unsigned long long*
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // no store sinks below
   __builtin_amdgcn_s_waitcnt(0x0F70);                      // vmcnt(0): stores performed
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
     __hip_atomic_store(self, ps.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool ok = true;
-    if (lo) ok = pair_wait(lo, ps.epoch, ps.spin) && ok;
-    if (hi) ok = pair_wait(hi, ps.epoch, ps.spin) && ok;
-    if (!ok) atomicOr(ps.timeout, 1);
-  }
+  if (threadIdx.x < kWave)
+    await_wave(threadIdx.x == 0 ? lo : threadIdx.x == 1 ? hi : nullptr, ps.epoch, ps);
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // no load rises above
 }
+
+// Wait until blocks lo..hi (at most 64) of an earlier level of the launch
+// have finished (flag = epoch + 1), same order as the hand-off.
+__device__ void await_done(const unsigned long long* f, int lo, int hi, const PairSync& ps) {
+  if (threadIdx.x < kWave) {
+    const int j = lo + (int)threadIdx.x;
+    await_wave(j <= hi ? f + j : nullptr, ps.epoch + 1, ps);
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// This block has finished: its outputs that a later level of the launch
+// reads were stored coherently; once they are performed, flag = epoch + 1.
+__device__ void publish_done(unsigned long long* self, const PairSync& ps) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(self, ps.epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Chained levels.  One launch can also run the two-sweep smoothing of
+// several levels (k_jacobi_chain): the pre-smoothing of levels 0, 1, ..., L-2
+// of a V-cycle, each level's last sweep restricting into the next level's
+// right-hand side, or the post-smoothing of levels L-2, ..., 0, each level's
+// first sweep interpolating the result of the coarser level of the same
+// launch.  Tickets run through the levels in that order.  A block of a
+// chained level first requests its tiles (written by an earlier launch), then
+// waits for the blocks of the previous level of the chain that write what it
+// reads, and only then loads them, with coherent loads; those blocks store
+// these values coherently and raise their flag to epoch + 1 once the stores
+// are performed.
+//   * Restriction: coarse step m is written by the fine blocks that produce
+//     fine steps 2m-1 and 2m (0-based blocks 2m-2, 2m-1; 2m-1, 2m in the
+//     time-aligned variant), and coarse block k (1-based) reads coarse steps
+//     k-1, k and, for the control mean, the fine right-hand side of the step
+//     after its own, so it waits for fine blocks 2k-4 .. 2k+2 (0-based).
+//   * Interpolation: fine step j takes coarse steps j/2 - 1 .. j/2 + 1 at
+//     most, and coarse step m is written by coarse blocks m-1 and m (the
+//     work-group of the last block also writes the last step's v and mu), so
+//     fine block kb (0-based) waits for coarse blocks kb/2 - 2 .. kb/2 + 2.
+// Every wait is for a lower ticket (the previous level) or for a neighbour's
+// first sweep, which waits only for lower tickets, so the lowest unfinished
+// ticket always progresses and the grid drains as above.
+// ---------------------------------------------------------------------------
+
+// One level's share of a two-sweep launch.
+struct PairLevel {
+  LevelView L;
+  const double* b;
+  const double* yold;
+  const double* ec;
+  double* y1;
+  double* y2;
+  FusedRestrict fr;
+  int variant;
+  int flag_off;   // flags of this level's blocks: ps.flag + flag_off + kb
+  int dep;        // 0: inputs from earlier launches; 1: b is written by the
+                  // previous (finer) level of the chain; 2: ec is the result
+                  // of the previous (coarser) level of the chain
+  int dep_off;    // flags of that level
+  int dep_n;      // its block count
+  int coh_y2;     // y2 is read by the next level of the chain
+  int publish;    // the next level of the chain waits for this level's blocks
+};
+
 template <int RT, int CT, class T>
-__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
-    LevelView L, const double* __restrict__ b, const double* yold,
-    const double* __restrict__ ec, int variant, double* y1, double* y2, FusedRestrict fr,
-    PairSync ps) {
+__device__ __forceinline__ void pair_block(const PairLevel& lv, const PairSync& ps, int kb) {
   using TS = TiledSolve<RT, CT, T>;
   constexpr int P = TS::P;
   static_assert(P <= kTiledThreads, "one entry per thread");
   __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P], srd[P];
   __shared__ T scr[TS::kScratch];
-  __shared__ int skb;
+  const LevelView& L = lv.L;
+  const double* __restrict__ b = lv.b;
+  double* y1 = lv.y1;
+  double* y2 = lv.y2;
+  const FusedRestrict& fr = lv.fr;
   const bool gn = Mats<T>::GiN(L) != nullptr;   // W = G^{-1} N form (diagonal V, Z~)
   const int tid = threadIdx.x;
   const int n = L.n;
@@ -309,22 +386,19 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   const int nc = n / 2;
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
   const double w = L.omega;
-  if (tid == 0) {
-    const unsigned long long t = atomicAdd(ps.ticket, 1ull) - ps.base;
-    skb = t < (unsigned long long)n ? (int)t : -1;
-  }
-  __syncthreads();
-  const int kb = skb;
-  if (kb < 0) {                                // more tickets than blocks: a fault
-    if (tid == 0) atomicOr(ps.timeout, 2);
-    return;
-  }
   const bool on = tid < P;
   const int i = tid;
+  unsigned long long* fl = ps.flag + lv.flag_off;
+  const bool cb = lv.dep == 1;                 // b written in this launch
+  auto ldb = [&](long long idx) -> double { return cb ? coherent_load(b + idx) : b[idx]; };
+  auto put2 = [&](long long idx, double v) {
+    if (lv.coh_y2) coherent_store(y2 + idx, v);
+    else y2[idx] = v;
+  };
 
   // first sweep: from the previous iterate plus the interpolated coarse
   // correction (first post-smoothing sweep)
-  const PrevIterate prev{yold, ec, P, P, n, variant, L.mu_scale};
+  const PrevIterate prev{lv.yold, lv.ec, P, P, n, lv.variant, L.mu_scale, lv.dep == 2};
   // second sweep: weighted against this block's own first-sweep values
   auto weigh1 = [&](double yhat, double y1v) -> double {
     return w == 1.0 ? yhat : w * yhat + (1.0 - w) * y1v;
@@ -332,56 +406,71 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   // publish this block's first sweep, then wait for the neighbours' (lo, hi:
   // block indices kb-1 and kb+1, or -1)
   auto hand_off = [&](int lo, int hi) {
-    pair_handoff(ps.flag + kb, lo >= 0 ? ps.flag + lo : nullptr,
-                 hi >= 0 ? ps.flag + hi : nullptr, ps);
+    pair_handoff(fl + kb, lo >= 0 ? fl + lo : nullptr, hi >= 0 ? fl + hi : nullptr, ps);
   };
 
   const int k = kb + 1;
   const bool hv = k >= 2;
   const long long kk = k - 1;
   // the block's right-hand side, its couplings and the previous values that
-  // weigh the first sweep are requested before the tiles: loads complete in
-  // order, so the gather waits for these alone and the tiles arrive during it
+  // weigh the first sweep
   double bu = 0.0, bm = 0.0, rl = 0.0, rz = 0.0, rv = 0.0, cmk = 0.0, cuk = 0.0;
   double pu = 0.0, pz = 0.0, pl = 0.0, pm = 0.0, pv = 0.0;
   typename TS::Diag dg;
-  PrevFetch fcm, fcu, fu, fz, fl, fm, fv;
-  if (on) {
-    bu = b[Tm.u + kk * P + i];
-    rl = b[Tm.l + kk * P + i];
-    rz = b[Tm.z + kk * P + i];
-    fcm = prev.fetch(4, k, i);
-    if (hv) {
-      rv = b[Tm.v + (kk - 1) * P + i];
-      bm = b[Tm.m + (kk - 1) * P + i];
-      fcu = prev.fetch(0, k - 1, i);
-    }
-    if (w != 1.0) {
-      fu = prev.fetch(0, k, i);
-      fz = prev.fetch(2, k, i);
-      fl = prev.fetch(3, k, i);
+  PrevFetch fcm, fcu, fu, fz, fl0, fm, fv;
+  auto gather = [&]() {
+    if (on) {
+      bu = ldb(Tm.u + kk * P + i);
+      rl = ldb(Tm.l + kk * P + i);
+      rz = ldb(Tm.z + kk * P + i);
+      fcm = prev.fetch(4, k, i);
       if (hv) {
-        fm = prev.fetch(4, k - 1, i);
-        fv = prev.fetch(1, k - 1, i);
+        rv = ldb(Tm.v + (kk - 1) * P + i);
+        bm = ldb(Tm.m + (kk - 1) * P + i);
+        fcu = prev.fetch(0, k - 1, i);
       }
+      if (w != 1.0) {
+        fu = prev.fetch(0, k, i);
+        fz = prev.fetch(2, k, i);
+        fl0 = prev.fetch(3, k, i);
+        if (hv) {
+          fm = prev.fetch(4, k - 1, i);
+          fv = prev.fetch(1, k - 1, i);
+        }
+      }
+      dg = TS::diag_at(L, i);
     }
-    dg = TS::diag_at(L, i);
+  };
+  typename TS::Regs R;
+  if (lv.dep == 0) {
+    // requested before the tiles: loads complete in order, so the gather
+    // waits for these alone and the tiles arrive during it
+    gather();
+    __builtin_amdgcn_sched_barrier(0);         // keep the loads above ahead of the tile's
+    TS::load_straight(L, kk, gn, R);
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+    // the tiles come from an earlier launch: in flight while this block
+    // waits for the previous level of the chain
+    TS::load_straight(L, kk, gn, R);
+    __builtin_amdgcn_sched_barrier(0);
+    const int lo = lv.dep == 1 ? 2 * kb - 2 : kb / 2 - 2;
+    const int hi = lv.dep == 1 ? 2 * kb + 4 : kb / 2 + 2;
+    await_done(ps.flag + lv.dep_off, lo > 0 ? lo : 0, hi < lv.dep_n - 1 ? hi : lv.dep_n - 1,
+               ps);
+    gather();
   }
   // first-sweep output (1 - omega) y_prev + omega y_hat, as weigh() forms it
   auto weigh0 = [&](double yhat, double yp) -> double {
     return w == 1.0 ? yhat : w * yhat + (1.0 - w) * yp;
   };
-  typename TS::Regs R;
-  __builtin_amdgcn_sched_barrier(0);           // keep the loads above ahead of the tile's
-  TS::load_straight(L, kk, gn, R);
-  __builtin_amdgcn_sched_barrier(0);
   if (on) {
     cmk = prev.value(fcm, 4, k);
     if (hv) cuk = prev.value(fcu, 0, k - 1);
     if (w != 1.0) {
       pu = prev.value(fu, 0, k);
       pz = prev.value(fz, 2, k);
-      pl = prev.value(fl, 3, k);
+      pl = prev.value(fl0, 3, k);
       if (hv) {
         pm = prev.value(fm, 4, k - 1);
         pv = prev.value(fv, 1, k - 1);
@@ -403,8 +492,8 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   const bool tail = kb == n - 1;
   double rvn = 0.0, mon1 = 0.0, von1 = 0.0;
   if (tail && on) {
-    rvn = b[Tm.v + (long long)(n - 1) * P + i];
-    const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - prev.at(0, n, i);
+    rvn = ldb(Tm.v + (long long)(n - 1) * P + i);
+    const double rmm = ldb(Tm.m + (long long)(n - 1) * P + i) - prev.at(0, n, i);
     mon1 = weigh(w, -rmm - rvn, prev, 4, n, i);
     von1 = weigh(w, -rmm, prev, 1, n, i);
     y1[Tm.m + (long long)(n - 1) * P + i] = mon1;
@@ -437,37 +526,91 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(
   const int rm_m = fr.mu_writer(k), ru_m = fr.u_writer(k);
   if (on) {
     const double uo = weigh1((double)TS::u_of(scr, sru, i), uo1);
-    y2[Tm.u + kk * P + i] = uo;
-    y2[Tm.z + kk * P + i] = weigh1((double)TS::z_of(L, dg, scr, srz, slam, i), zo1);
-    y2[Tm.l + kk * P + i] = weigh1((double)slam[i], lo1);
+    put2(Tm.u + kk * P + i, uo);
+    put2(Tm.z + kk * P + i, weigh1((double)TS::z_of(L, dg, scr, srz, slam, i), zo1));
+    put2(Tm.l + kk * P + i, weigh1((double)slam[i], lo1));
     if (hv) {
       const double mo = weigh1((double)TS::mu_of(L, dg, scr, srm, srv, slam, i), mo1);
-      y2[Tm.m + (kk - 1) * P + i] = mo;
-      y2[Tm.v + (kk - 1) * P + i] = weigh1(-(double)srm[i], vo1);
+      put2(Tm.m + (kk - 1) * P + i, mo);
+      put2(Tm.v + (kk - 1) * P + i, weigh1(-(double)srm[i], vo1));
       if (ru_m) fr.put_u(ru_m, i, fr.a * mo1 - mo, b, Tm, Tc, P);
     }
     if (rm_m) fr.put_mu(rm_m, i, fr.a * uo1 - uo, b, Tm, Tc, P);
   }
   if (tail && on) {                            // block n+1, second sweep
     const int mu_m = fr.u_writer(n + 1);
-    const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - uo1;
+    const double rmm = ldb(Tm.m + (long long)(n - 1) * P + i) - uo1;
     const double mo = weigh1(-rmm - rvn, mon1);
-    y2[Tm.v + (long long)(n - 1) * P + i] = weigh1(-rmm, von1);
-    y2[Tm.m + (long long)(n - 1) * P + i] = mo;
+    put2(Tm.v + (long long)(n - 1) * P + i, weigh1(-rmm, von1));
+    put2(Tm.m + (long long)(n - 1) * P + i, mo);
     if (mu_m) fr.put_u(mu_m, i, fr.a * mon1 - mo, b, Tm, Tc, P);
   }
+  if (lv.publish) publish_done(fl + kb, ps);
+}
+
+template <int RT, int CT, class T>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled2(PairLevel lv, PairSync ps) {
+  __shared__ int skb;
+  if (threadIdx.x == 0) {
+    const unsigned long long t = atomicAdd(ps.ticket, 1ull) - ps.base;
+    skb = t < (unsigned long long)lv.L.n ? (int)t : -1;
+  }
+  __syncthreads();
+  const int kb = skb;
+  if (kb < 0) {                                // more tickets than blocks: a fault
+    if (threadIdx.x == 0) atomicOr(ps.timeout, 2);
+    return;
+  }
+  pair_block<RT, CT, T>(lv, ps, kb);
+}
+
+constexpr int kChainMax = 8;
+struct PairChain {
+  PairLevel lv[kChainMax];
+  int start[kChainMax + 1];   // first ticket of each level; start[nlev] = all
+  int nlev;
+};
+static_assert(sizeof(PairChain) <= 4096, "kernel argument size");
+
+template <int RT, int CT, class T>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_chain(PairChain ch, PairSync ps) {
+  __shared__ int st;
+  if (threadIdx.x == 0) {
+    const unsigned long long t = atomicAdd(ps.ticket, 1ull) - ps.base;
+    st = t < (unsigned long long)ch.start[ch.nlev] ? (int)t : -1;
+  }
+  __syncthreads();
+  const int t = __builtin_amdgcn_readfirstlane(st);
+  if (t < 0) {
+    if (threadIdx.x == 0) atomicOr(ps.timeout, 2);
+    return;
+  }
+  int c = 0;
+  while (c + 1 < ch.nlev && t >= ch.start[c + 1]) ++c;
+  pair_block<RT, CT, T>(ch.lv[c], ps, t - ch.start[c]);
+}
+
+static PairLevel pair_level(const LevelView& L, const double* b, const double* yold,
+                            const double* ecoarse, int variant, double* y1, double* y2,
+                            double* restrict_out, double rbeta, double ra) {
+  PairLevel lv{};
+  lv.L = L;
+  lv.b = b;
+  lv.yold = yold;
+  lv.ec = ecoarse;
+  lv.y1 = y1;
+  lv.y2 = y2;
+  lv.fr = FusedRestrict{restrict_out, variant, rbeta, ra, L.mu_scale};
+  lv.variant = variant;
+  return lv;
 }
 
 template <class T>
-static hipError_t launch_tiled2_t(const LevelView& L, const double* b, const double* yold,
-                                  const double* ecoarse, int variant, double* y1, double* y2,
-                                  FusedRestrict fr, const PairSync& ps, hipStream_t s) {
-  if (L.p == 128 && L.q == 128)
-    return launch_k(k_jacobi_tiled2<4, 8, T>, dim3(L.n), dim3(kTiledThreads), 0, s, L, b,
-                    yold, ecoarse, variant, y1, y2, fr, ps);
-  if (L.p == 64 && L.q == 64)
-    return launch_k(k_jacobi_tiled2<2, 4, T>, dim3(L.n), dim3(kTiledThreads), 0, s, L, b,
-                    yold, ecoarse, variant, y1, y2, fr, ps);
+static hipError_t launch_tiled2_t(const PairLevel& lv, const PairSync& ps, hipStream_t s) {
+  if (lv.L.p == 128 && lv.L.q == 128)
+    return launch_k(k_jacobi_tiled2<4, 8, T>, dim3(lv.L.n), dim3(kTiledThreads), 0, s, lv, ps);
+  if (lv.L.p == 64 && lv.L.q == 64)
+    return launch_k(k_jacobi_tiled2<2, 4, T>, dim3(lv.L.n), dim3(kTiledThreads), 0, s, lv, ps);
   return hipErrorInvalidValue;
 }
 
@@ -475,9 +618,62 @@ hipError_t launch_jacobi_tiled2(const LevelView& L, const double* b, const doubl
                                 const double* ecoarse, int variant, double* y1, double* y2,
                                 double* restrict_out, double rbeta, double ra,
                                 const PairSync& ps, hipStream_t s) {
-  const FusedRestrict fr{restrict_out, variant, rbeta, ra, L.mu_scale};
-  return L.fp32 ? launch_tiled2_t<float>(L, b, yold, ecoarse, variant, y1, y2, fr, ps, s)
-                : launch_tiled2_t<double>(L, b, yold, ecoarse, variant, y1, y2, fr, ps, s);
+  const PairLevel lv = pair_level(L, b, yold, ecoarse, variant, y1, y2, restrict_out, rbeta, ra);
+  return L.fp32 ? launch_tiled2_t<float>(lv, ps, s) : launch_tiled2_t<double>(lv, ps, s);
+}
+
+template <class T>
+static hipError_t launch_chain_t(const PairChain& ch, const PairSync& ps, hipStream_t s) {
+  const LevelView& L = ch.lv[0].L;
+  const dim3 grid(ch.start[ch.nlev]);
+  if (L.p == 128 && L.q == 128)
+    return launch_k(k_jacobi_chain<4, 8, T>, grid, dim3(kTiledThreads), 0, s, ch, ps);
+  if (L.p == 64 && L.q == 64)
+    return launch_k(k_jacobi_chain<2, 4, T>, grid, dim3(kTiledThreads), 0, s, ch, ps);
+  return hipErrorInvalidValue;
+}
+
+int jacobi_chain_max() { return kChainMax; }
+
+hipError_t launch_jacobi_chain(const ChainSweep* sw, int nlev, int up, int variant,
+                               const PairSync& ps, int* groups, hipStream_t s) {
+  *groups = 0;
+  if (nlev < 1 || nlev > kChainMax || !ps.ticket || !ps.flag || !ps.timeout)
+    return hipErrorInvalidValue;
+  PairChain ch{};
+  ch.nlev = nlev;
+  int t = 0;
+  for (int c = 0; c < nlev; ++c) {
+    const ChainSweep& x = sw[c];
+    if (x.L.p != sw[0].L.p || x.L.q != sw[0].L.q || x.L.fp32 != sw[0].L.fp32)
+      return hipErrorInvalidValue;
+    if (x.y1 == x.y2 || x.y1 == x.yold || x.y1 == x.b || x.y2 == x.b) return hipErrorInvalidValue;
+    if (c > 0) {
+      // the chain's own data flow: the restriction of the previous level is
+      // this level's right-hand side (down), or the previous level's result
+      // is this level's coarse correction (up)
+      const ChainSweep& pr = sw[c - 1];
+      const bool ok = up ? (pr.y2 == x.ec && pr.L.n * 2 == x.L.n && !x.restrict_out)
+                         : (pr.restrict_out == x.b && x.L.n * 2 == pr.L.n && !x.ec);
+      if (!ok) return hipErrorInvalidValue;
+    }
+    PairLevel lv = pair_level(x.L, x.b, x.yold, x.ec, variant, x.y1, x.y2, x.restrict_out,
+                              x.rbeta, x.ra);
+    lv.flag_off = x.flag_off;
+    lv.dep = c == 0 ? 0 : (up ? 2 : 1);
+    lv.dep_off = c == 0 ? 0 : sw[c - 1].flag_off;
+    lv.dep_n = c == 0 ? 0 : sw[c - 1].L.n;
+    lv.publish = c + 1 < nlev;
+    lv.coh_y2 = up && c + 1 < nlev;
+    lv.fr.coh_b = !up && c > 0;
+    lv.fr.coh_rc = !up && c + 1 < nlev;
+    ch.lv[c] = lv;
+    ch.start[c] = t;
+    t += x.L.n;
+  }
+  ch.start[nlev] = t;
+  *groups = t;
+  return sw[0].L.fp32 ? launch_chain_t<float>(ch, ps, s) : launch_chain_t<double>(ch, ps, s);
 }
 
 // ---------------------------------------------------------------------------

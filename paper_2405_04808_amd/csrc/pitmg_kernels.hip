@@ -335,6 +335,13 @@ bool jacobi_pair_supported(const LevelView& L, hipStream_t s) {
   return st == hipStreamCaptureStatusNone;
 }
 
+bool jacobi_chain_supported(const LevelView& L, hipStream_t s) {
+  if (!sweeps_tiled(L)) return false;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st == hipStreamCaptureStatusNone;
+}
+
 hipError_t launch_jacobi_pair(const LevelView& L, const double* b, const double* yold,
                               const double* ecoarse, int variant, double* y1, double* y2,
                               double* restrict_out, double rbeta, double ra,

@@ -22,7 +22,7 @@ def test_default_options_and_status_strings():
     o = pm.default_options()
     assert (o.nu_pre, o.nu_post, o.coarse_maxit, o.restart, o.maxit) == (2, 2, 50, 30, 300)
     assert o.coarse_tol == 1e-3 and o.coarse_fixed_its == 0 and o.transfer_variant == 0
-    assert o.apply_from_sweep == 1 and o.pair_sweeps == 1
+    assert o.apply_from_sweep == 1 and o.pair_sweeps == 2
     lib = pm.load_library()
     for code in range(-6, 2):
         assert lib.pitmg_status_string(code).decode() != "unknown status"
@@ -63,7 +63,7 @@ def test_setup_rejects_bad_options_on_host():
     lib = pm.load_library()
     pb, keep = _problem()
     for field, val in [("restart", 0), ("nu_pre", -1), ("transfer_variant", 3),
-                       ("coarse_maxit", 0), ("apply_from_sweep", 2), ("pair_sweeps", 2)]:
+                       ("coarse_maxit", 0), ("apply_from_sweep", 2), ("pair_sweeps", 3)]:
         o = pm.default_options(**{field: val})
         h = C.c_void_p()
         assert lib.pitmg_setup(C.byref(h), C.byref(pb), C.byref(o), None) == pm.PITMG_ERR_INVALID

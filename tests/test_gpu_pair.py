@@ -1,9 +1,13 @@
-"""Two block Jacobi sweeps in one launch (pair_sweeps = 1).
+"""Two block Jacobi sweeps in one launch (pair_sweeps = 1), and the
+pre- and post-smoothing of every level in one launch each (pair_sweeps = 2).
 
 The two-sweep kernel hands each block's first-sweep coupling values to its
 neighbours inside the launch, so its results must be bitwise those of two
 one-sweep launches: the same arithmetic in the same order on the same
-inputs.  The cases force the one-step tiled sweep on every smoothed level,
+inputs.  The chained launch runs the same two-sweep blocks level after level
+with dataflow flags between the levels (restriction on the way down,
+interpolation on the way up), so it must be bitwise the level-by-level cycle
+as well; where the cycle has another form it falls back to that cycle.  The cases force the one-step tiled sweep on every smoothed level,
 including a finest level of 1,024 steps (1,025 work-groups, more than the
 device holds at once, so the ticket order and the hand-off waits both
 matter), with odd and even sweep counts, both transfer variants, the FP32
@@ -33,7 +37,7 @@ def tiled_everywhere(s, n_levels, shape=-1):
 
 def vcycle_pair(prob, r, shape=-1, **opt):
     outs = []
-    for pair in (0, 1):
+    for pair in (0, 1, 2):
         s = pm.Solver(prob.levels, pm.default_options(pair_sweeps=pair, **opt))
         tiled_everywhere(s, prob.n_levels, shape)
         outs.append(s.vcycle(dev(r)))
@@ -52,9 +56,10 @@ def test_pair_vcycle_bitwise(nx, n, n_levels, nu, variant, reading):
     prob, rng = make_problem(kind="burgers", nx=nx, nu=0.01, n=n, n_levels=n_levels, seed=31)
     r = rng.normal(size=prob.size)
     print(f"pair vcycle nx={nx} n={n} nu={nu} variant={variant} {reading}", flush=True)
-    a, b = vcycle_pair(prob, r, nu_pre=nu[0], nu_post=nu[1], coarse_fixed_its=2,
-                       transfer_variant=variant, **READINGS[reading])
+    a, b, c = vcycle_pair(prob, r, nu_pre=nu[0], nu_post=nu[1], coarse_fixed_its=2,
+                          transfer_variant=variant, **READINGS[reading])
     assert torch.equal(a, b)
+    assert torch.equal(a, c)
 
 
 @pytest.mark.parametrize("nx,n,n_levels", [(64, 40, 3), (128, 20, 3), (128, 1024, 8)])
@@ -69,9 +74,10 @@ def test_pair_vcycle_bitwise_shared_block_groups(nx, n, n_levels, per, nu):
     r = rng.normal(size=prob.size)
     print(f"pair shared vcycle nx={nx} n={n} per={per} nu={nu}", flush=True)
     for variant in (0, 1):
-        a, b = vcycle_pair(prob, r, shape=per, nu_pre=nu[0], nu_post=nu[1], coarse_fixed_its=2,
-                           transfer_variant=variant)
+        a, b, c = vcycle_pair(prob, r, shape=per, nu_pre=nu[0], nu_post=nu[1],
+                              coarse_fixed_its=2, transfer_variant=variant)
         assert torch.equal(a, b)
+        assert torch.equal(a, c)
 
 
 @pytest.mark.parametrize("case", ["fp32", "theta05"])
@@ -85,8 +91,9 @@ def test_pair_vcycle_bitwise_fp32_and_per_step_blocks(case):
         opt = {}
     r = rng.normal(size=prob.size)
     print(f"pair vcycle {case}", flush=True)
-    a, b = vcycle_pair(prob, r, coarse_fixed_its=2, **opt)
+    a, b, c = vcycle_pair(prob, r, coarse_fixed_its=2, **opt)
     assert torch.equal(a, b)
+    assert torch.equal(a, c)
 
 
 def test_pair_vcycle_matches_oracle():
@@ -113,12 +120,42 @@ def test_pair_fgmres_bitwise(shape):
     prob, rng = make_problem(kind="burgers", nx=64, nu=0.01, n=64, n_levels=4, seed=35)
     b = make_rhs(prob, rng)
     res = []
-    for pair in (0, 1):
+    for pair in (0, 1, 2):
         s = pm.Solver(prob.levels, pm.default_options(restart=200, maxit=400, pair_sweeps=pair))
         tiled_everywhere(s, prob.n_levels, shape)
         x, st, rc = s.solve(dev(b), tol=1e-10)
         torch.cuda.synchronize()
         assert rc == pm.PITMG_OK
+        res.append((x.clone(), st["iters"]))
+        s.close()
+    for other in res[1:]:
+        assert res[0][1] == other[1]
+        assert torch.equal(res[0][0], other[0])
+
+
+@pytest.mark.parametrize("nx,n,n_levels", [(64, 64, 4), (128, 48, 4), (128, 1024, 8)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_chain_runs_two_sweep_launches_per_cycle(nx, n, n_levels, variant):
+    # the chained cycle issues one pre- and one post-smoothing launch per
+    # V-cycle (the level-by-level cycle one of each per level) and matches it
+    # bitwise over a whole FGMRES solve; n = 48 leaves an odd step count (3)
+    # on the last level that smooths
+    prob, rng = make_problem(kind="burgers", nx=nx, nu=0.01, n=n, n_levels=n_levels, seed=38)
+    b = make_rhs(prob, rng)
+    res = []
+    for pair in (1, 2):
+        s = pm.Solver(prob.levels, pm.default_options(transfer_variant=variant, pair_sweeps=pair))
+        tiled_everywhere(s, prob.n_levels)
+        s.profile(2)
+        x, st, rc = s.solve(dev(b), tol=1e-10)
+        torch.cuda.synchronize()
+        assert rc == pm.PITMG_OK
+        launches = s.profile_read()["jacobi"][0]
+        cycles = st["iters"] + 1
+        print(f"chain nx={nx} n={n} L={n_levels} variant={variant} pair={pair}: "
+              f"{st['iters']} steps, {launches} sweep launches", flush=True)
+        per = 2 if pair == 2 else 2 * (n_levels - 1)
+        assert launches >= per * st["iters"] and launches <= per * cycles
         res.append((x.clone(), st["iters"]))
         s.close()
     assert res[0][1] == res[1][1]
@@ -131,7 +168,19 @@ def test_pair_handoff_wait_bound_reports_error():
     # with the bound restored the same handle solves normally again
     prob, rng = make_problem(kind="burgers", nx=128, nu=0.01, n=1024, n_levels=8, seed=37)
     b = make_rhs(prob, rng)
-    s = pm.Solver(prob.levels, pm.default_options(restart=8, maxit=8, pair_sweeps=1))
+    run_wait_bound_case(prob, b, 1)
+
+
+def test_chain_wait_bound_reports_error():
+    # the same with the chained cycle, whose blocks also wait for the
+    # previous level's
+    prob, rng = make_problem(kind="burgers", nx=128, nu=0.01, n=1024, n_levels=8, seed=39)
+    b = make_rhs(prob, rng)
+    run_wait_bound_case(prob, b, 2)
+
+
+def run_wait_bound_case(prob, b, pair):
+    s = pm.Solver(prob.levels, pm.default_options(restart=8, maxit=8, pair_sweeps=pair))
     tiled_everywhere(s, prob.n_levels)
     with pytest.raises(pm.PitmgError):
         s.set_handoff_wait(-1.0)

@@ -391,17 +391,22 @@ def test_full_burgers128_operator_and_sweep():
     s.close()
 
 
-# the benchmark's launch configuration on the Burgers nx = 128, n = 1024
-# system: the shared-block sweep at 4 and 2 steps per work-group on levels
-# 0 and 1, the one-step sweep below, two sweeps per launch
-BENCH_SHAPES = [4, 2, -1, -1, -1, -1, -1, 0]
+# launch configurations on the Burgers nx = 128, n = 1024 system: the
+# benchmark's, the one-step sweep on every level above the coarsest with the
+# pre- and post-smoothing of all levels chained into one launch each; and
+# the shared-block sweep at 4 and 2 steps per work-group on levels 0 and 1,
+# the one-step sweep below, two sweeps per launch level by level
+SHAPES = {"chain": ([-1, -1, -1, -1, -1, -1, -1, 0], 2),
+          "shared": ([4, 2, -1, -1, -1, -1, -1, 0], 1)}
 
 
-def test_full_burgers128_vcycle_matches_oracle():
+@pytest.mark.parametrize("cfg", list(SHAPES))
+def test_full_burgers128_vcycle_matches_oracle(cfg):
     prob, b = config_problem("burgers128")
-    o = pm.default_options(coarse_fixed_its=2, pair_sweeps=1)
+    shapes, pair = SHAPES[cfg]
+    o = pm.default_options(coarse_fixed_its=2, pair_sweeps=pair)
     s = pm.Solver(prob.levels, o)
-    s.set_sweep_shapes(BENCH_SHAPES)
+    s.set_sweep_shapes(shapes)
     H = Hierarchy(prob.levels, mg_opts(o))
     r = np.random.default_rng(8).normal(size=prob.size)
     got = host(s.vcycle(dev(r)))
@@ -411,16 +416,18 @@ def test_full_burgers128_vcycle_matches_oracle():
     s.close()
 
 
-def test_full_burgers128_solve_matches_oracle():
+@pytest.mark.parametrize("cfg", list(SHAPES))
+def test_full_burgers128_solve_matches_oracle(cfg):
     # P1: the true residual of the GPU iterate, formed by the oracle's CSR
     # matvec, meets 1e-10 and equals the reported one to rounding (each row
     # sums at most k products: |difference| <= 2 k u || |A| |x| || / ||b||);
     # P2/P3: the oracle's FGMRES on the same system takes the same number of
     # steps (+-1) and reaches the same iterate
     prob, b = config_problem("burgers128")
-    o = pm.default_options(restart=300, maxit=300, pair_sweeps=1)
+    shapes, pair = SHAPES[cfg]
+    o = pm.default_options(restart=300, maxit=300, pair_sweeps=pair)
     s = pm.Solver(prob.levels, o)
-    s.set_sweep_shapes(BENCH_SHAPES)
+    s.set_sweep_shapes(shapes)
     xg, st, rc = s.solve(dev(b), tol=1e-10)
     assert rc == pm.PITMG_OK and st["converged"] == 1
     x = host(xg)
