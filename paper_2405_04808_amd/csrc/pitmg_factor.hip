@@ -9,18 +9,20 @@
 // (the FP32 smoother's levels) v_mfma_f32_16x16x4f32.  One work-group of 512
 // threads per block.
 //
-// p = 16 NT <= 128 (k_factor_mfma): S_k and then G_k^{-1} stay in LDS as
-// 16x16 tiles of the lower triangle, worked on tile by tile:
+// p = 16 NT <= 128 (k_factor_mfma): S_k, then G_k, then G_k^{-1} stay in one
+// LDS array of 16x16 tiles of the lower triangle (73.7 KB for p = 128 in
+// FP64, so two work-groups share a CU and one's sequential pivot steps
+// overlap the other's), worked on tile by tile:
 //
-//   1. S = X X^T, X = [N_k | Z~_k]: column panels of X staged in LDS through
-//      coalesced row loads, each wave accumulating its lower tiles in
-//      registers;
+//   1. S = X X^T, X = [N_k | Z~_k]: column panels of X staged in the same
+//      LDS array through coalesced row loads, each wave accumulating its
+//      lower tiles in registers;
 //   2. right-looking blocked Cholesky: factor the diagonal tile (one wave),
 //      solve the panel below it (one thread per row), update the trailing
 //      tiles S_IJ -= G_IK G_JK^T (matrix cores);
-//   3. blocked inverse X = G^{-1}: the diagonal tiles' inverses (a lane per
-//      column), then the off-diagonal tiles by diagonals,
-//      X_IJ = -X_II sum_{K=J}^{I-1} G_IK X_KJ (matrix cores);
+//   3. blocked inverse X = G^{-1} in place: the diagonal tiles' inverses (a
+//      lane per column), then the off-diagonal tiles by tile columns from
+//      the right, X_IJ = -(sum_{K=J+1}^{I} X_IK G_KJ) X_JJ (matrix cores);
 //   4. X to global memory, row-major, zero above the diagonal.
 //
 // p = 128 NB, NB in {2, 4} (k_factor_big): the same algorithm one level up,
@@ -68,10 +70,11 @@ template <class T>
 __device__ __forceinline__ int arow(int g, int i) { return Mfma4<T>::row(g, i); }
 
 // Steps 2 and 3 on the lower tiles of a P x P symmetric matrix in St:
-// Cholesky in place (St then holds G), the inverse of G into Xt.  Returns
-// false (uniformly, after a barrier) when a pivot is not positive.
+// Cholesky in place (St then holds G), then the inverse of G in place (St
+// then holds G^{-1}).  Returns false (uniformly, after a barrier) when a
+// pivot is not positive.
 template <class T, int NT>
-__device__ bool tile_cholesky_inverse(T* St, T* Xt, int* sfail) {
+__device__ __forceinline__ bool tile_cholesky_inverse(T* St, int* sfail) {
   using TL = Tiles<NT>;
   typedef typename Mfma4<T>::v4 v4;
   const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
@@ -142,12 +145,12 @@ __device__ bool tile_cholesky_inverse(T* St, T* Xt, int* sfail) {
     __syncthreads();
   }
 
-  // ---- X = G^{-1}, blocked -------------------------------------------------
-  // diagonal tiles: column j of X_KK solves G_KK x = e_j (lane j of a wave)
+  // ---- X = G^{-1}, blocked, in place ---------------------------------------
+  // diagonal tiles: column j of X_KK solves G_KK x = e_j (lane j of a wave);
+  // the wave reads the whole tile before any lane writes its column
   for (int Kt = w; Kt < NT; Kt += kFacWaves) {
     if (lane < 16) {
-      const T* D = St + TL::id(Kt, Kt) * 256;
-      T* X = Xt + TL::id(Kt, Kt) * 256;
+      T* D = St + TL::id(Kt, Kt) * 256;
       const int j = lane;
       T x[16];
 #pragma unroll
@@ -158,36 +161,50 @@ __device__ bool tile_cholesky_inverse(T* St, T* Xt, int* sfail) {
         x[i] = i < j ? T(0) : v / D[tix(i, i)];
       }
 #pragma unroll
-      for (int i = 0; i < 16; ++i) X[tix(i, j)] = x[i];
+      for (int i = 0; i < 16; ++i) D[tix(i, j)] = x[i];
     }
   }
   __syncthreads();
-  // off-diagonal tiles by diagonals d = I - J
-  for (int d = 1; d < NT; ++d) {
-    for (int J = w; J + d < NT; J += kFacWaves) {
-      const int I = J + d;
+  // off-diagonal tiles by tile columns J from the right: from X G = I,
+  // X_IJ = -(sum_{K=J+1}^{I} X_IK G_KJ) X_JJ.  The X_IK (K > J) are done, and
+  // column J still holds G until all of its tiles have been formed.
+  for (int J = NT - 2; J >= 0; --J) {
+    const int nI = NT - 1 - J;                           // tiles I = J+1 .. NT-1
+    v4 x4 = v4{0, 0, 0, 0};
+    const int I = J + 1 + w;
+    if (w < nI) {
+      // T^T = sum_K G_KJ^T X_IK^T (accumulator: T[r][arow(g, i)])
       v4 t4 = v4{0, 0, 0, 0};
-      for (int Kt = J; Kt < I; ++Kt) {
-        const T* A = St + TL::id(I, Kt) * 256;           // G_IK
-        const T* B = Xt + TL::id(Kt, J) * 256;           // X_KJ
+      for (int Kt = J + 1; Kt <= I; ++Kt) {
+        const T* A = St + TL::id(Kt, J) * 256;           // G_KJ
+        const T* B = St + TL::id(I, Kt) * 256;           // X_IK
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-          t4 = Mfma4<T>::step(A[tix(r, 4 * s + g)], B[tix(4 * s + g, r)], t4);
+          t4 = Mfma4<T>::step(A[tix(4 * s + g, r)], B[tix(r, 4 * s + g)], t4);
       }
-      // X_IJ = -X_II T with T's accumulator as the B operand: element s of
-      // the lane is T[arow(g, s)][r], so k-chunk s takes the inner indices
-      // arow(g, s) of the A operand too
-      const T* A = Xt + TL::id(I, I) * 256;
-      v4 x4 = v4{0, 0, 0, 0};
+      // X_IJ^T = -X_JJ^T T^T with T^T's accumulator as the B operand (element
+      // s of the lane is T^T[arow(g, s)][r], so k-chunk s takes the inner
+      // indices arow(g, s) of the A operand too)
+      const T* X = St + TL::id(J, J) * 256;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) x4 = Mfma4<T>::step(-A[tix(r, arow<T>(g, s))], t4[s], x4);
-      T* X = Xt + TL::id(I, J) * 256;
+      for (int s = 0; s < 4; ++s) x4 = Mfma4<T>::step(-X[tix(arow<T>(g, s), r)], t4[s], x4);
+    }
+    __syncthreads();                                     // column J's G read
+    if (w < nI) {
+      T* X = St + TL::id(I, J) * 256;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) X[tix(arow<T>(g, i), r)] = x4[i];
+      for (int i = 0; i < 4; ++i) X[tix(r, arow<T>(g, i))] = x4[i];
     }
     __syncthreads();
   }
   return true;
+}
+
+// The same as a call of its own (k_factor_big keeps its GEMM state in
+// registers around it).
+template <class T>
+__device__ __noinline__ bool tile_cholesky_inverse_call(T* St, int* sfail) {
+  return tile_cholesky_inverse<T, 8>(St, sfail);
 }
 
 // Which level and block a work-group of a batch launch factors.
@@ -201,15 +218,14 @@ __device__ void batch_block(const FactorBatchT<T>& F, int& lev, int& k) {
 }  // namespace
 
 template <class T, int NT>
-__global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatchT<T> F, int* fail) {
+__global__ __launch_bounds__(kFacThreads, 4) void k_factor_mfma(FactorBatchT<T> F, int* fail) {
   using TL = Tiles<NT>;
   typedef typename Mfma4<T>::v4 v4;
   constexpr int P = TL::P;
   extern __shared__ double lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
-  T* St = lds;                                          // S, then G: kTiles tiles
-  T* Xt = lds + TL::kTiles * 256;                       // G^{-1} tiles
-  T* stage = Xt;                                        // X panel (before step 3)
+  T* St = lds;                                          // S, G, then G^{-1}: kTiles tiles
+  T* stage = St;                                        // X panels (step 1, before S)
   __shared__ int sfail;
   const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
   const int r = lane & 15, g = lane >> 4;
@@ -278,7 +294,7 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatchT<T> 
   __syncthreads();
 
   // ---- 2-3. Cholesky and inverse ------------------------------------------
-  if (!tile_cholesky_inverse<T, NT>(St, Xt, &sfail)) {
+  if (!tile_cholesky_inverse<T, NT>(St, &sfail)) {
     if (tid == 0) atomicMin(fail, (F.level0 + lev) << 20 | k);
     return;
   }
@@ -288,8 +304,8 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_mfma(FactorBatchT<T> 
     const int i = e / P, j = e % P;
     const int I = i >> 4, J = j >> 4;
     T v = T(0);
-    if (J < I) v = Xt[TL::id(I, J) * 256 + tix(i & 15, j & 15)];
-    else if (J == I && (j & 15) <= (i & 15)) v = Xt[TL::id(I, I) * 256 + tix(i & 15, j & 15)];
+    if (J < I) v = St[TL::id(I, J) * 256 + tix(i & 15, j & 15)];
+    else if (J == I && (j & 15) <= (i & 15)) v = St[TL::id(I, I) * 256 + tix(i & 15, j & 15)];
     Gk[e] = v;
   }
 }
@@ -299,8 +315,7 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_big(FactorBatchT<T> F
   using TL = Tiles<8>;
   extern __shared__ double lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
-  T* St = lds;                                          // diagonal super-block
-  T* Xt = lds + TL::kTiles * 256;                       // its inverse
+  T* St = lds;                                          // diagonal super-block, then its inverse
   __shared__ int sfail;
   const int tid = threadIdx.x;
   int lev, k;
@@ -350,7 +365,7 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_big(FactorBatchT<T> F
       St[t * 256 + tix(rr, cc)] = Skk[(long long)(16 * I + rr) * P + 16 * J + cc];
     }
     __syncthreads();
-    if (!tile_cholesky_inverse<T, 8>(St, Xt, &sfail)) {
+    if (!tile_cholesky_inverse_call<T>(St, &sfail)) {
       if (tid == 0) atomicMin(fail, (F.level0 + lev) << 20 | k);
       return;
     }
@@ -359,8 +374,8 @@ __global__ __launch_bounds__(kFacThreads, 1) void k_factor_big(FactorBatchT<T> F
     for (int e = tid; e < 128 * 128; e += kFacThreads) {
       const int i = e >> 7, j = e & 127, I = i >> 4, J = j >> 4;
       T v = T(0);
-      if (J < I) v = Xt[TL::id(I, J) * 256 + tix(i & 15, j & 15)];
-      else if (J == I && (j & 15) <= (i & 15)) v = Xt[TL::id(I, I) * 256 + tix(i & 15, j & 15)];
+      if (J < I) v = St[TL::id(I, J) * 256 + tix(i & 15, j & 15)];
+      else if (J == I && (j & 15) <= (i & 15)) v = St[TL::id(I, I) * 256 + tix(i & 15, j & 15)];
       Xkk[(long long)i * P + j] = v;
     }
     // panel: G_IK = S_IK X_KK^T (in place)
@@ -403,7 +418,7 @@ static hipError_t launch_t(const FactorBatchT<T>& F, int* fail, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   if (!factor_mfma_supported(F.p, F.q)) return hipErrorInvalidValue;
   const int nt = F.p <= 128 ? F.p / 16 : 8;
-  const size_t lds = (size_t)nt * (nt + 1) * 256 * sizeof(T);   // S tiles + X tiles
+  const size_t lds = (size_t)nt * (nt + 1) / 2 * 256 * sizeof(T);   // the lower tiles
   auto go = [&](auto kern) -> hipError_t {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
