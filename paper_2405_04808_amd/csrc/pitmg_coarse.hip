@@ -265,6 +265,93 @@ __global__ __launch_bounds__(kCtrlThreads) void k_coarse_arnoldi_sgs(
                              red, &sflag);
 }
 
+// The same step with w held in registers: thread t keeps entries t, t + NT,
+// ... (at most MAXE) of w, so the orthogonalisation makes no round trip
+// through memory.  The sums and updates are those of arnoldi_step in the
+// same order (per-thread partials in index order, then block_sum), so the
+// results are the same doubles; w is stored back at the end.
+template <int NT, int MAXE>
+__global__ __launch_bounds__(NT) void k_coarse_arnoldi_sgs_reg(
+    int j, double* __restrict__ wv, double* __restrict__ Vb, double* __restrict__ zj,
+    const double* __restrict__ a, const double* __restrict__ d, long long mu0, long long len,
+    double* cst, int* ist, int cap, double tol, int fixed_its, int nsteps) {
+  __shared__ double red[NT / kWave];
+  __shared__ int sflag;
+  if (ist[1]) return;                          // solved at an earlier step
+  const int tid = threadIdx.x;
+  const CState S{cap};
+  const double* __restrict__ v = Vb + (size_t)j * len;
+  double w[MAXE];
+#pragma unroll
+  for (int k = 0; k < MAXE; ++k) {
+    const long long e = tid + (long long)k * NT;
+    w[k] = 0.0;
+    if (e < len) {
+      zj[e] = a[e] + d[e];
+      w[k] = e >= mu0 ? v[e] + d[e - mu0] : v[e];
+    }
+  }
+  auto dot_w = [&](const double* __restrict__ x) -> double {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXE; ++k) {
+      const long long e = tid + (long long)k * NT;
+      if (e < len) acc += w[k] * (x ? x[e] : w[k]);
+    }
+    return block_sum<NT>(acc, red);
+  };
+  const double w0 = sqrt(dot_w(nullptr));
+  double* H = S.H(cst);
+  for (int i = 0; i <= j; ++i) {
+    const double* __restrict__ vi = Vb + (size_t)i * len;
+    const double h = dot_w(vi);
+#pragma unroll
+    for (int k = 0; k < MAXE; ++k) {
+      const long long e = tid + (long long)k * NT;
+      if (e < len) w[k] -= h * vi[e];
+    }
+    if (tid == 0) H[(size_t)i * S.cap + j] = h;
+  }
+  const double hn = sqrt(dot_w(nullptr));
+  if (tid == 0) {
+    double* cs = S.cs(cst);
+    double* sn = S.sn(cst);
+    double* g = S.g(cst);
+    H[(size_t)(j + 1) * cap + j] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a0 = H[(size_t)i * cap + j], a1 = H[(size_t)(i + 1) * cap + j];
+      H[(size_t)i * cap + j] = cs[i] * a0 + sn[i] * a1;
+      H[(size_t)(i + 1) * cap + j] = -sn[i] * a0 + cs[i] * a1;
+    }
+    const double a0 = H[(size_t)j * cap + j], a1 = hn;
+    const double r = hypot(a0, a1);
+    cs[j] = r > 0.0 ? a0 / r : 1.0;
+    sn[j] = r > 0.0 ? a1 / r : 0.0;
+    H[(size_t)j * cap + j] = r;
+    H[(size_t)(j + 1) * cap + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    const double res = fabs(g[j + 1]);
+    int st = fixed_its > 0 ? (j + 1 == fixed_its) : (res <= tol * S.beta(cst));
+    if (!st && hn <= 1e-14 * w0) st = 1;
+    if (j + 1 >= nsteps) st = 1;
+    ist[0] = j + 1;
+    ist[1] = st;
+    sflag = st;
+  }
+  __syncthreads();
+  const bool stop = sflag != 0;
+  double* vn = Vb + (size_t)(j + 1) * len;
+#pragma unroll
+  for (int k = 0; k < MAXE; ++k) {
+    const long long e = tid + (long long)k * NT;
+    if (e < len) {
+      wv[e] = w[k];
+      if (!stop) vn[e] = w[k] / hn;
+    }
+  }
+}
+
 // Finish the coarse solve: continue block by block if the enqueued steps did
 // not meet the test, then x = Z y with H y = g.
 template <class Pol>
@@ -487,8 +574,15 @@ hipError_t launch_coarse_arnoldi_sgs(int j, double* w, double* Vb, double* zj, c
                                      int cap, double tol, int fixed_its, int nsteps,
                                      hipStream_t s) {
   const TypeMajor T(p, q, n);
-  hipLaunchKernelGGL(k_coarse_arnoldi_sgs, dim3(1), dim3(kCtrlThreads), 0, s, j, w, Vb, zj, a, d,
-                     T.m, T.len, cst, ist, cap, tol, fixed_its, nsteps);
+  if (T.len <= 16LL * kCtrlThreads)
+    hipLaunchKernelGGL((k_coarse_arnoldi_sgs_reg<kCtrlThreads, 16>), dim3(1), dim3(kCtrlThreads),
+                       0, s, j, w, Vb, zj, a, d, T.m, T.len, cst, ist, cap, tol, fixed_its, nsteps);
+  else if (T.len <= 48LL * kCtrlThreads)
+    hipLaunchKernelGGL((k_coarse_arnoldi_sgs_reg<kCtrlThreads, 48>), dim3(1), dim3(kCtrlThreads),
+                       0, s, j, w, Vb, zj, a, d, T.m, T.len, cst, ist, cap, tol, fixed_its, nsteps);
+  else
+    hipLaunchKernelGGL(k_coarse_arnoldi_sgs, dim3(1), dim3(kCtrlThreads), 0, s, j, w, Vb, zj, a,
+                       d, T.m, T.len, cst, ist, cap, tol, fixed_its, nsteps);
   return hipGetLastError();
 }
 
