@@ -794,41 +794,46 @@ hipError_t sweep_pair(pitmg_handle* h, const LevelView& v, const double* b, cons
   return e;
 }
 
-// MG_0(b) -> out with the pre-smoothing of levels 0 .. L-2 in one launch and
-// their post-smoothing in another (pair_sweeps = 2): the same sweeps, fused
-// restrictions and interpolations, into the same buffers, as the level by
-// level recursion of vcycle_level with two sweeps per launch.
-// chained_cycle says whether the handle's cycle has that form.
+// MG_l0(b) -> out with the pre-smoothing of levels l0 .. L-2 in one launch
+// and their post-smoothing in another (pair_sweeps = 2): the same sweeps,
+// fused restrictions and interpolations, into the same buffers, as the level
+// by level recursion of vcycle_level with two sweeps per launch.
+// chained_cycle says whether the handle's cycle has that form from level l0
+// on (an FP32 finest level, whose residual is an explicit FP64 product, is
+// swept on its own and the levels below it chain).
 int coarse_correction(pitmg_handle* h, int l, int cyc);
 
-bool chain_form(const pitmg_options& o, int n_levels) {
-  const int ns = n_levels - 1;                 // levels that smooth
+bool chain_form(const pitmg_options& o, int n_levels, int l0) {
+  const int nc = n_levels - 1 - l0;            // levels that smooth from l0 on
   return o.pair_sweeps == 2 && o.smoother == 0 && o.cycle == 0 && o.coarsen == 2 &&
-         o.nu_pre == 2 && o.nu_post == 2 && ns >= 2 && ns <= jacobi_chain_max();
+         o.nu_pre == 2 && o.nu_post == 2 && nc >= 2 && nc <= jacobi_chain_max();
 }
 
-bool chained_cycle(pitmg_handle* h) {
-  const int ns = h->L - 1;
-  if (!chain_form(h->opt, h->L)) return false;
-  for (int l = 0; l < ns; ++l)
-    if (h->lv[l].res || !jacobi_chain_supported(view(h, l), h->stream)) return false;
+bool chained_cycle(pitmg_handle* h, int l0) {
+  if (!chain_form(h->opt, h->L, l0)) return false;
+  const int fp = view(h, l0).fp32;             // one precision along the chain
+  for (int l = l0; l < h->L - 1; ++l) {
+    const LevelView v = view(h, l);
+    if (h->lv[l].res || v.fp32 != fp || !jacobi_chain_supported(v, h->stream)) return false;
+  }
   return true;
 }
 
-int vcycle_chained(pitmg_handle* h, const double* b, double* out) {
-  const int ns = h->L - 1;
+int vcycle_chained(pitmg_handle* h, int l0, const double* b, double* out) {
+  const int ns = h->L - 1 - l0;                // levels in the chain
   ChainSweep dn[16], up[16];
   int off = 0;
-  for (int l = 0; l < ns; ++l) {
+  for (int c = 0; c < ns; ++c) {
+    const int l = l0 + c;
     const LevelView v = view(h, l);
     LevelBuf& B = h->lv[l];
     LevelBuf& C = h->lv[l + 1];
     const double w = v.omega;
     const double rbeta = w != 1.0 ? (1.0 - w) * (1.0 - w) : 0.0;
     const double ra = w != 1.0 ? w : 1.0;
-    const double* bl = l == 0 ? b : B.b;
-    dn[l] = ChainSweep{v, bl, nullptr, nullptr, B.y0, B.y1, C.b, rbeta, ra, off};
-    up[ns - 1 - l] = ChainSweep{v, bl, B.y1, C.out, B.y0, l == 0 ? out : B.out, nullptr,
+    const double* bl = c == 0 ? b : B.b;
+    dn[c] = ChainSweep{v, bl, nullptr, nullptr, B.y0, B.y1, C.b, rbeta, ra, off};
+    up[ns - 1 - c] = ChainSweep{v, bl, B.y1, C.out, B.y0, c == 0 ? out : B.out, nullptr,
                                 0.0, 1.0, off};
     off += v.n;
   }
@@ -846,12 +851,12 @@ int vcycle_chained(pitmg_handle* h, const double* b, double* out) {
   };
   int rc = timed_kernel(h, 1, [&] { return chain(dn, 0); });
   if (rc) return rc;
-  if ((rc = coarse_correction(h, ns - 1, 0))) return rc;
+  if ((rc = coarse_correction(h, h->L - 2, 0))) return rc;
   rc = timed_kernel(h, 1, [&] { return chain(up, 1); });
   if (rc) return rc;
   // A~ z from the last sweep's identity needs an undamped FP64 sweep
   const LevelView v0 = view(h, 0);
-  if (v0.omega == 1.0 && !v0.fp32) h->top_prev = h->lv[0].y0;
+  if (l0 == 0 && v0.omega == 1.0 && !v0.fp32) h->top_prev = h->lv[0].y0;
   return PITMG_OK;
 }
 
@@ -1020,7 +1025,7 @@ int vcycle_level(pitmg_handle* h, int l, const double* b, double* out, int cyc) 
   if (l == 0) h->top_prev = nullptr;
   if (l == h->L - 1) return coarse_dispatch(h, b, out);
   if (o.smoother != 0) return vcycle_level_gs(h, l, b, out, cyc);
-  if (l == 0 && cyc == 0 && chained_cycle(h)) return vcycle_chained(h, b, out);
+  if (cyc == 0 && chained_cycle(h, l)) return vcycle_chained(h, l, b, out);
   LevelBuf& B = h->lv[l];
   LevelBuf& C = h->lv[l + 1];
   double* bufs[2] = {B.y0, B.y1};
@@ -1586,7 +1591,7 @@ int pitmg_autotune(pitmg_handle* h, int* cfg) {
   constexpr int kReps = 10;
   // a cycle that can chain its levels keeps the one-step kernel on every
   // level it applies to (the chained launches need it on all of them)
-  const bool chain = chain_form(h->opt, h->L) && jacobi_tiled_supported(h->p, h->q);
+  const bool chain = chain_form(h->opt, h->L, 0) && jacobi_tiled_supported(h->p, h->q);
   for (int l = 0; l < h->L; ++l) {
     LevelBuf& B = h->lv[l];
     if (cfg) cfg[l] = 0;

@@ -195,3 +195,26 @@ def run_wait_bound_case(prob, b, pair):
     torch.cuda.synchronize()
     assert rc in (pm.PITMG_OK, pm.PITMG_NOT_CONVERGED) and st["iters"] == 8
     s.close()
+
+
+@pytest.mark.parametrize("fp32,launches", [(99, 4), (2, 6)])
+def test_chain_below_fp32_levels_bitwise(fp32, launches):
+    # an FP32 finest level forms its residual explicitly, so it sweeps on its
+    # own and the levels below it chain (all of them FP32 with smoother_fp32
+    # = 99; only the FP64 levels 2-3 with smoother_fp32 = 2, the FP32 level 1
+    # sweeping on its own too): per V-cycle the sweeps of the levels outside
+    # the chain (one pre- and one post-smoothing launch each) plus the two
+    # chained launches, and the same doubles as level by level
+    prob, rng = make_problem(kind="burgers", nx=128, nu=0.01, n=64, n_levels=5, seed=40)
+    r = rng.normal(size=prob.size)
+    print(f"chain below FP32 levels: smoother_fp32={fp32}", flush=True)
+    a, b, c = vcycle_pair(prob, r, coarse_fixed_its=2, smoother_fp32=fp32)
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+    s = pm.Solver(prob.levels, pm.default_options(coarse_fixed_its=2, smoother_fp32=fp32))
+    tiled_everywhere(s, prob.n_levels)
+    s.profile(2)
+    s.vcycle(dev(r))
+    torch.cuda.synchronize()
+    assert s.profile_read()["jacobi"][0] == launches
+    s.close()
