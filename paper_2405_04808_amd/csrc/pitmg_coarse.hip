@@ -601,8 +601,7 @@ hipError_t launch_coarse_finish(const LevelView& L, double* x, double tol, int f
 
 // The same products on the matrix cores for p in {64, 128} (pitmg_mfma.h):
 // W_s = G_s^{-1} N_s and X_s = G_s^{-1} V_s (which = 0, 1), Phi_s = W_s^T X_s,
-// and the propagator columns, P columns in work-groups 0..nc-1 and Q columns
-// in nc..2nc-1.
+// and the propagators (below).
 template <int NT>
 __global__ __launch_bounds__(kGemmThreads) void k_gi_times_mfma(LevelView L, int which,
                                                                 double* __restrict__ out) {
@@ -624,29 +623,64 @@ __global__ __launch_bounds__(kGemmThreads) void k_phi_mfma(const double* __restr
   wg_gemm<NT, true, false>(W + s * P * P, P, X + s * P * P, P, 1.0, Phi + s * P * P, P, lds);
 }
 
+// The propagators by doubling spans: P[s][i] = (-1)^(s-i) Phi_s ... Phi_{i+1}
+// composes, P[s][i] = P[s][m] P[m][i] for i < m < s, and Q[m][i] =
+// P[i][m]^T likewise, Q[m][i] = Q[m][k] Q[k][i].  k_prop_init writes the
+// identity blocks and the span-1 blocks (-Phi_{i+1}, -Phi_{i+1}^T); round r
+// forms every block of span d in (2^(r-1), 2^r] from a span-2^(r-1) block
+// and a shorter one, one work-group per block (P blocks in the first half of
+// the grid, Q in the second): ceil(log2(nc - 1)) rounds of independent
+// products instead of a chain of nc - 1.
 template <int NT>
-__global__ __launch_bounds__(kGemmThreads) void k_propagators_mfma(int nc,
-                                                                   const double* __restrict__ Phi,
-                                                                   double* P_, double* Q_) {
-  extern __shared__ double lds[];
+__global__ __launch_bounds__(kGemmThreads) void k_prop_init(int nc, const double* __restrict__ Phi,
+                                                            double* P_, double* Q_) {
   constexpr int P = 16 * NT;
-  const bool lower = (int)blockIdx.x < nc;
-  const int i = lower ? blockIdx.x : blockIdx.x - nc;
   const long long ld = (long long)nc * P;
-  double* M = lower ? P_ : Q_;
-  auto blk = [&](int rr, int cc) { return M + (long long)rr * P * ld + (long long)cc * P; };
+  const int i = blockIdx.x;                     // block column of P (row of Q)
   for (int idx = threadIdx.x; idx < P * P; idx += kGemmThreads) {
     const int a = idx / P, b = idx % P;
-    blk(i, i)[(long long)a * ld + b] = a == b ? 1.0 : 0.0;
+    const double id = a == b ? 1.0 : 0.0;
+    P_[(long long)i * P * ld + (long long)i * P + (long long)a * ld + b] = id;
+    Q_[(long long)i * P * ld + (long long)i * P + (long long)a * ld + b] = id;
+    if (i + 1 < nc) {
+      const double* F = Phi + (long long)(i + 1) * P * P;
+      P_[(long long)(i + 1) * P * ld + (long long)i * P + (long long)a * ld + b] = -F[a * P + b];
+      Q_[(long long)i * P * ld + (long long)(i + 1) * P + (long long)a * ld + b] = -F[b * P + a];
+    }
   }
-  if (lower) {
-    for (int s = i + 1; s < nc; ++s)        // P[s][i] = -Phi_s P[s-1][i]
-      wg_gemm<NT, false, false>(Phi + (long long)s * P * P, P, blk(s - 1, i), ld, -1.0,
-                                blk(s, i), ld, lds);
-  } else {
-    for (int m = i - 1; m >= 0; --m)        // Q[m][i] = -Phi_{m+1}^T Q[m+1][i]
-      wg_gemm<NT, true, false>(Phi + (long long)(m + 1) * P * P, P, blk(m + 1, i), ld, -1.0,
-                               blk(m, i), ld, lds);
+}
+
+// Blocks of round r: span d = h + e, h = 2^(r-1), e in [1, h], d <= nc - 1,
+// row s = i + d for i = 0 .. nc-1-d, enumerated by e, then i.
+__host__ __device__ inline int prop_round_count(int nc, int h) {
+  int c = 0;
+  for (int e = 1; e <= h && h + e <= nc - 1; ++e) c += nc - (h + e);
+  return c;
+}
+
+template <int NT>
+__global__ __launch_bounds__(kGemmThreads) void k_prop_round(int nc, int h, double* P_,
+                                                             double* Q_) {
+  extern __shared__ double lds[];
+  constexpr int P = 16 * NT;
+  const long long ld = (long long)nc * P;
+  const int per = prop_round_count(nc, h);
+  const bool lower = (int)blockIdx.x < per;
+  int t = lower ? blockIdx.x : blockIdx.x - per;
+  int e = 1;
+  while (t >= nc - (h + e)) {
+    t -= nc - (h + e);
+    ++e;
+  }
+  const int i = t, d = h + e;
+  double* M = lower ? P_ : Q_;
+  auto blk = [&](int rr, int cc) { return M + (long long)rr * P * ld + (long long)cc * P; };
+  if (lower) {                                  // P[i+d][i] = P[i+d][i+e] P[i+e][i]
+    wg_gemm<NT, false, false>(blk(i + d, i + e), ld, blk(i + e, i), ld, 1.0, blk(i + d, i), ld,
+                              lds);
+  } else {                                      // Q[i][i+d] = Q[i][i+h] Q[i+h][i+d]
+    wg_gemm<NT, false, false>(blk(i, i + h), ld, blk(i + h, i + d), ld, 1.0, blk(i, i + d), ld,
+                              lds);
   }
 }
 
@@ -656,7 +690,7 @@ static hipError_t launch_propagators_mfma(const LevelView& L, double* W, double*
   const int nc = L.n;
   const size_t lds = wg_gemm_lds_doubles(16 * NT) * sizeof(double);
   const void* fns[4] = {(const void*)k_gi_times_mfma<NT>, (const void*)k_phi_mfma<NT>,
-                        (const void*)k_propagators_mfma<NT>, nullptr};
+                        (const void*)k_prop_round<NT>, nullptr};
   for (int f = 0; f < 3; ++f) {
     hipError_t e = hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -665,8 +699,11 @@ static hipError_t launch_propagators_mfma(const LevelView& L, double* W, double*
   hipLaunchKernelGGL(k_gi_times_mfma<NT>, dim3(nc), dim3(kGemmThreads), lds, s, L, 0, W);
   hipLaunchKernelGGL(k_gi_times_mfma<NT>, dim3(nc), dim3(kGemmThreads), lds, s, L, 1, X);
   hipLaunchKernelGGL(k_phi_mfma<NT>, dim3(nc), dim3(kGemmThreads), lds, s, W, X, Phi);
-  hipLaunchKernelGGL(k_propagators_mfma<NT>, dim3(2 * nc), dim3(kGemmThreads), lds, s, nc, Phi,
-                     P, Q);
+  hipLaunchKernelGGL(k_prop_init<NT>, dim3(nc), dim3(kGemmThreads), 0, s, nc, Phi, P, Q);
+  for (int h = 1; h < nc - 1; h *= 2) {
+    const int per = prop_round_count(nc, h);
+    hipLaunchKernelGGL(k_prop_round<NT>, dim3(2 * per), dim3(kGemmThreads), lds, s, nc, h, P, Q);
+  }
   return hipGetLastError();
 }
 
