@@ -141,17 +141,21 @@ struct PrevIterate {
   const double* ec;
   int p, q, n, variant;
   double mu_scale;
-  // ec is written by other work-groups of the same launch: read it with
-  // coherent loads
+  // ec (yold) is written by other work-groups of the same launch: read it
+  // with coherent loads
   bool ec_coherent = false;
+  bool yold_coherent = false;
   __device__ __forceinline__ double ec_at(long long idx) const {
     return ec_coherent ? coherent_load(ec + idx) : ec[idx];
+  }
+  __device__ __forceinline__ double yold_at(long long idx) const {
+    return yold_coherent ? coherent_load(yold + idx) : yold[idx];
   }
   __device__ double at(int type, int k, int i) const {
     const TypeMajor Tm(p, q, n);
     const long long seg[5] = {Tm.u, Tm.v, Tm.z, Tm.l, Tm.m};
     const int w = type == 2 ? q : p;
-    double v = yold ? yold[seg[type] + (long long)(k - 1) * w + i] : 0.0;
+    double v = yold ? yold_at(seg[type] + (long long)(k - 1) * w + i) : 0.0;
     if (ec) {
       const int nc = n / 2;
       const TypeMajor Tc(p, q, nc > 0 ? nc : 1);
@@ -205,7 +209,7 @@ struct PrevIterate {
     const TypeMajor Tm(p, q, n);
     const long long seg[5] = {Tm.u, Tm.v, Tm.z, Tm.l, Tm.m};
     const int w = type == 2 ? q : p;
-    if (yold) f.y = yold[seg[type] + (long long)(k - 1) * w + i];
+    if (yold) f.y = yold_at(seg[type] + (long long)(k - 1) * w + i);
     if (ec) {
       const int nc = n / 2;
       const TypeMajor Tc(p, q, nc > 0 ? nc : 1);

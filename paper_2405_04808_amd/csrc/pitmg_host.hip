@@ -168,6 +168,7 @@ struct pitmg_handle {
   unsigned long long* hand_ticket = nullptr;
   unsigned long long* hand_flag = nullptr;
   int* hand_timeout = nullptr;
+  unsigned long long* sgs_flag = nullptr;   // phase flags of the fused coarse SGS
   unsigned long long hand_tickets = 0;   // tickets issued so far (host mirror)
   unsigned long long hand_epoch = 0;     // last epoch issued
   double wall_hz = 1e8;                  // the device's constant wall clock
@@ -618,28 +619,47 @@ int coarse_solve_with(pitmg_handle* h, const double* b, double* out, const Coars
     return launch_coarse_init(b, len, Vb, cw.cst, cw.ist, cap, h->stream);
   });
   if (rc) return rc;
+  // the SGS application as one launch (phases with dataflow flags) where the
+  // level sweeps with the one-step kernel
+  const bool fused = h->sgs_flag && !v.fp32 && jacobi_chain_supported(v, h->stream);
   for (int j = 0; j < K; ++j) {
     double* vj = Vb + (size_t)j * len;
     double* zj = Zb + (size_t)j * len;
+    if (fused) {
+      if ((rc = timed(h, 4, [&] {
+             const PairSync ps{h->hand_ticket, h->hand_tickets, h->sgs_flag, h->hand_epoch + 1,
+                               h->hand_timeout, h->hand_spin};
+             int groups = 0;
+             const hipError_t e = launch_sgs_fused(v, vj, cw.czero, cw.cC, cw.cA, cw.cD, cw.cY,
+                                                   cw.cY2, h->Pf, h->Qb, var, ps, &groups,
+                                                   h->stream);
+             if (e == hipSuccess) {
+               h->hand_tickets += (unsigned long long)groups;
+               h->hand_epoch += 2;
+             }
+             return e;
+           })))
+        return rc;
+    }
     // forward sweep: c = D^{-1} v, a_u = P c_u, a = D^{-1}(v - L a)
-    if ((rc = timed(h, 4, [&] {
+    if (!fused && (rc = timed(h, 4, [&] {
            return launch_jacobi(v, vj, nullptr, nullptr, var, cw.cC, h->stream);
          })))
       return rc;
-    if ((rc = timed(h, 4, [&] {
+    if (!fused && (rc = timed(h, 4, [&] {
            return launch_gemv_tri(h->Pf, v.n, h->p, 0, cw.cC + T.u, cw.cY + T.u, h->stream);
          })))
       return rc;
-    if ((rc = timed(h, 4, [&] {
+    if (!fused && (rc = timed(h, 4, [&] {
            return launch_jacobi(v, vj, cw.cY, nullptr, var, cw.cA, h->stream);
          })))
       return rc;
     // backward sweep: y_mu = Q a_mu, z = a - D^{-1} L^T y
-    if ((rc = timed(h, 4, [&] {
+    if (!fused && (rc = timed(h, 4, [&] {
            return launch_gemv_tri(h->Qb, v.n, h->p, 1, cw.cA + T.m, cw.cY2 + T.m, h->stream);
          })))
       return rc;
-    if ((rc = timed(h, 4, [&] {
+    if (!fused && (rc = timed(h, 4, [&] {
            return launch_jacobi(v, cw.czero, cw.cY2, nullptr, var, cw.cD, h->stream);
          })))
       return rc;
@@ -1850,6 +1870,13 @@ int pitmg_setup(pitmg_handle** hp, const pitmg_problem* pb, const pitmg_options*
       if (hipMemset(h->Pf, 0, (size_t)ncp * ncp * 8) != hipSuccess ||
           hipMemset(h->Qb, 0, (size_t)ncp * ncp * 8) != hipSuccess)
         return fail(set_err(h, PITMG_ERR_HIP, "hipMemset failed"));
+      if ((h->p == 64 || h->p == 128) && h->p == h->q && lc.n + 1 <= 64) {
+        const size_t nf = (size_t)sgs_fused_flags(lc.n, h->p);
+        if ((rc = dalloc(h, (void**)&h->sgs_flag, nf * sizeof(unsigned long long))))
+          return fail(rc);
+        if (hipMemset(h->sgs_flag, 0, nf * sizeof(unsigned long long)) != hipSuccess)
+          return fail(set_err(h, PITMG_ERR_HIP, "hipMemset failed"));
+      }
     }
     if (hipHostMalloc((void**)&h->its_pinned, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
       return fail(set_err(h, PITMG_ERR_OOM, "hipHostMalloc failed"));
@@ -2245,6 +2272,7 @@ void pitmg_destroy(pitmg_handle* h) {
   release(h->Phi);
   release(h->pscr);
   release(h->Pf);
+  release(h->sgs_flag);
   release(h->Qb);
   if (h->its_pinned) (void)hipHostFree(h->its_pinned);
   release(h->fail);

@@ -229,6 +229,15 @@ struct ChainSweep {
   int flag_off;
 };
 int jacobi_chain_max();
+// The coarse solve's block-parallel SGS application (three block sweeps and
+// the two propagator products of pitmg_coarse.hip) as one launch with
+// dataflow flags between its phases (pitmg_jacobi_tiled.hip).  FP64, p = q in
+// {64, 128}, n + 1 <= 64 blocks; ps.flag needs sgs_fused_flags(n, p) words.
+int sgs_fused_flags(int n, int p);
+hipError_t launch_sgs_fused(const LevelView& L, const double* v, const double* zero, double* c,
+                            double* a, double* d, double* yf, double* yb, const double* Pf,
+                            const double* Qb, int variant, const PairSync& ps, int* groups,
+                            hipStream_t s);
 bool jacobi_chain_supported(const LevelView& L, hipStream_t s);
 hipError_t launch_jacobi_chain(const ChainSweep* sw, int nlev, int up, int variant,
                                const PairSync& ps, int* groups, hipStream_t s);

@@ -78,10 +78,15 @@ struct FusedRestrict {
   }
 };
 
+// One block of a single sweep (block kb + 1, or block n+1 when kb = n), the
+// body of k_jacobi_tiled.  coh_y: yold is written by other work-groups of the
+// same launch (coherent loads); coh_out: ynew is read by other work-groups
+// of the same launch (coherent stores).
 template <int RT, int CT, class T>
-__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
-    LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
-    const double* __restrict__ ec, int variant, double* __restrict__ ynew, FusedRestrict fr) {
+__device__ __forceinline__ void one_block(const LevelView& L, const double* __restrict__ b,
+                                          const double* yold, const double* __restrict__ ec,
+                                          int variant, double* ynew, const FusedRestrict& fr,
+                                          int kb, bool coh_y, bool coh_out) {
   using TS = TiledSolve<RT, CT, T>;
   constexpr int P = TS::P;
   __shared__ T sru[P], srz[P], srm[P], srl[P], srv[P], slam[P], srd[P];
@@ -92,12 +97,15 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   const TypeMajor Tm(P, P, n);
   const int nc = n / 2;
   const TypeMajor Tc(P, P, nc > 0 ? nc : 1);
-  const int kb = blockIdx.x;
   const double w = L.omega;
-  const PrevIterate prev{yold, ec, P, P, n, variant, L.mu_scale};
+  const PrevIterate prev{yold, ec, P, P, n, variant, L.mu_scale, false, coh_y};
   auto cu = [&](int k1, int i) -> double { return prev.at(0, k1, i); };
   auto cm = [&](int k1, int i) -> double { return prev.at(4, k1, i); };
-  auto ya = [&](long long idx) -> double { return yold ? fr.a * yold[idx] : 0.0; };
+  auto ya = [&](long long idx) -> double { return yold ? fr.a * prev.yold_at(idx) : 0.0; };
+  auto out = [&](long long idx, double v) {
+    if (coh_out) coherent_store(ynew + idx, v);
+    else ynew[idx] = v;
+  };
 
   if (kb == n) {                               // block n+1 = (v_n, mu_n)
     const int mu_m = fr.u_writer(n + 1);
@@ -105,8 +113,8 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
       const double rvv = b[Tm.v + (long long)(n - 1) * P + i];
       const double rmm = b[Tm.m + (long long)(n - 1) * P + i] - cu(n, i);
       const double mo = weigh(w, -rmm - rvv, prev, 4, n, i);
-      ynew[Tm.v + (long long)(n - 1) * P + i] = weigh(w, -rmm, prev, 1, n, i);
-      ynew[Tm.m + (long long)(n - 1) * P + i] = mo;
+      out(Tm.v + (long long)(n - 1) * P + i, weigh(w, -rmm, prev, 1, n, i));
+      out(Tm.m + (long long)(n - 1) * P + i, mo);
       if (mu_m) fr.put_u(mu_m, i, ya(Tm.m + (long long)(n - 1) * P + i) - mo, b, Tm, Tc, P);
     }
     return;
@@ -182,17 +190,24 @@ __global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
   else TS::solve(L, kk, hv, R, sru, srz, srm, srl, slam, scr);
   if (on) {
     const double uo = weigh0((double)TS::u_of(scr, sru, i), pu);
-    ynew[Tm.u + kk * P + i] = uo;
-    ynew[Tm.z + kk * P + i] = weigh0((double)TS::z_of(L, dg, scr, srz, slam, i), pz);
-    ynew[Tm.l + kk * P + i] = weigh0((double)slam[i], pl);
+    out(Tm.u + kk * P + i, uo);
+    out(Tm.z + kk * P + i, weigh0((double)TS::z_of(L, dg, scr, srz, slam, i), pz));
+    out(Tm.l + kk * P + i, weigh0((double)slam[i], pl));
     if (hv) {
       const double mo = weigh0((double)TS::mu_of(L, dg, scr, srm, srv, slam, i), pm);
-      ynew[Tm.m + (kk - 1) * P + i] = mo;
-      ynew[Tm.v + (kk - 1) * P + i] = weigh0(-(double)srm[i], pv);
+      out(Tm.m + (kk - 1) * P + i, mo);
+      out(Tm.v + (kk - 1) * P + i, weigh0(-(double)srm[i], pv));
       if (ru_m) fr.put_u(ru_m, i, yam - mo, b, Tm, Tc, P);
     }
     if (rm_m) fr.put_mu(rm_m, i, yau - uo, b, Tm, Tc, P);
   }
+}
+
+template <int RT, int CT, class T>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_jacobi_tiled(
+    LevelView L, const double* __restrict__ b, const double* __restrict__ yold,
+    const double* __restrict__ ec, int variant, double* __restrict__ ynew, FusedRestrict fr) {
+  one_block<RT, CT, T>(L, b, yold, ec, variant, ynew, fr, blockIdx.x, false, false);
 }
 
 bool jacobi_tiled_supported(int p, int q) { return p == q && (p == 128 || p == 64); }
@@ -634,6 +649,142 @@ static hipError_t launch_chain_t(const PairChain& ch, const PairSync& ps, hipStr
 }
 
 int jacobi_chain_max() { return kChainMax; }
+
+// ---------------------------------------------------------------------------
+// The block-parallel SGS application of the coarse solve (pitmg_coarse.hip)
+// in one launch: its three block sweeps and two propagator products as five
+// phases of one grid, tickets in phase order,
+//   0  c = D^{-1} v                                   (blocks 1 .. n+1)
+//   1  y_f,u = P c_u          (rows of the lower block-triangular propagator)
+//   2  a = D^{-1} (v - L a), the coupling u_{k-1} from y_f
+//   3  y_b,mu = Q a_mu        (rows of the upper block-triangular propagator)
+//   4  d = -D^{-1} L^T y, the coupling mu_k from y_b (right-hand side zero).
+// Each work-group waits only for the work-groups of the previous phase that
+// write what it reads (so only for lower tickets: the grid drains with any
+// number of resident work-groups), reads those values with coherent loads,
+// and raises its flag to epoch + 1 once its coherent stores are performed.
+// Sweeps are one_block (k_jacobi_tiled's body) and the rows k_gemv_tri's
+// sums, so the results are those of the five separate launches.
+// ---------------------------------------------------------------------------
+
+struct SgsPhases {
+  LevelView L;
+  const double* v;       // right-hand side of sweeps 1 and 2
+  const double* zero;    // zero vector, the right-hand side of sweep 3
+  double* c;             // sweep outputs
+  double* a;
+  double* d;
+  double* yf;            // propagated couplings (zero outside the u / mu rows)
+  double* yb;
+  const double* Pf;      // propagators, [n p][n p]
+  const double* Qb;
+  int variant;
+};
+
+constexpr int kSgsRows = kTiledThreads / kWave;   // propagator rows per work-group
+
+// y[r] = x[r] + (off-diagonal blocks of row r) x, one wave, the sums of
+// k_gemv_tri in its order; x read and y written coherently.
+__device__ void sgs_row(const double* __restrict__ M, int nc, int p, int upper,
+                        const double* x, double* y, long long r) {
+  const long long ld = (long long)nc * p;
+  const int lane = threadIdx.x % kWave;
+  const int s = (int)(r / p);
+  const long long c0 = upper ? (long long)(s + 1) * p : 0;
+  const long long c1 = upper ? ld : (long long)s * p;
+  const double* __restrict__ Mr = M + r * ld;
+  double a[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) a[t] = 0.0;
+  long long c = c0 + lane;
+  for (; c + 7 * kWave < c1; c += 8 * kWave) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) a[t] += Mr[c + t * kWave] * coherent_load(x + c + t * kWave);
+  }
+  for (; c < c1; c += kWave) a[0] += Mr[c] * coherent_load(x + c);
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  acc = wave_sum(acc);
+  if (lane == 0) coherent_store(y + r, coherent_load(x + r) + acc);
+}
+
+template <int RT, int CT, class T>
+__global__ __launch_bounds__(kTiledThreads, 1) void k_sgs_fused(SgsPhases F, PairSync ps) {
+  __shared__ int st;
+  const int n = F.L.n, p = F.L.p, nb = n + 1;
+  const long long ld = (long long)n * p;
+  const int ng = (int)((ld + kSgsRows - 1) / kSgsRows);
+  const int b1 = nb, b2 = nb + ng, b3 = 2 * nb + ng, b4 = 2 * nb + 2 * ng, b5 = 3 * nb + 2 * ng;
+  if (threadIdx.x == 0) {
+    const unsigned long long t = atomicAdd(ps.ticket, 1ull) - ps.base;
+    st = t < (unsigned long long)b5 ? (int)t : -1;
+  }
+  __syncthreads();
+  const int t = __builtin_amdgcn_readfirstlane(st);
+  if (t < 0) {
+    if (threadIdx.x == 0) atomicOr(ps.timeout, 2);
+    return;
+  }
+  const TypeMajor Tm(p, p, n);
+  const FusedRestrict none{nullptr, F.variant, 0.0, 1.0, F.L.mu_scale};
+  unsigned long long* fl = ps.flag;
+  const long long r = (long long)(t - (t < b2 ? b1 : b3)) * kSgsRows + threadIdx.x / kWave;
+  // propagator work-groups holding block rows s0 .. s1 of the u / mu rows
+  auto wgs = [&](int s0, int s1, int& lo, int& hi) {
+    lo = (int)((long long)s0 * p / kSgsRows);
+    hi = (int)(((long long)(s1 + 1) * p - 1) / kSgsRows);
+  };
+  if (t < b1) {                                    // 0: c = D^{-1} v
+    one_block<RT, CT, T>(F.L, F.v, nullptr, nullptr, F.variant, F.c, none, t, false, true);
+    publish_done(fl + t, ps);
+  } else if (t < b2) {                             // 1: forward propagation
+    const long long r0 = (long long)(t - b1) * kSgsRows;
+    const long long s1 = (r0 + kSgsRows - 1) / p;
+    await_done(fl, 0, (int)(s1 < n - 1 ? s1 : n - 1), ps);
+    if (r < ld) sgs_row(F.Pf, n, p, 0, F.c + Tm.u, F.yf + Tm.u, r);
+    publish_done(fl + t, ps);
+  } else if (t < b3) {                             // 2: a = D^{-1}(v - L a)
+    const int kb = t - b2;
+    int lo, hi;
+    wgs(kb < n ? (kb > 0 ? kb - 1 : 0) : n - 1, kb < n ? kb : n - 1, lo, hi);
+    await_done(fl + b1, lo, hi < ng - 1 ? hi : ng - 1, ps);
+    one_block<RT, CT, T>(F.L, F.v, F.yf, nullptr, F.variant, F.a, none, kb, true, true);
+    publish_done(fl + t, ps);
+  } else if (t < b4) {                             // 3: backward propagation
+    const long long r0 = (long long)(t - b3) * kSgsRows;
+    await_done(fl + b2, (int)(r0 / p) + 1, n, ps);
+    if (r < ld) sgs_row(F.Qb, n, p, 1, F.a + Tm.m, F.yb + Tm.m, r);
+    publish_done(fl + t, ps);
+  } else {                                         // 4: d = -D^{-1} L^T y
+    const int kb = t - b4;
+    int lo, hi;
+    wgs(kb < n ? (kb > 0 ? kb - 1 : 0) : n - 1, kb < n ? kb : n - 1, lo, hi);
+    await_done(fl + b3, lo, hi < ng - 1 ? hi : ng - 1, ps);
+    one_block<RT, CT, T>(F.L, F.zero, F.yb, nullptr, F.variant, F.d, none, kb, true, false);
+  }
+}
+
+int sgs_fused_flags(int n, int p) {
+  const long long ld = (long long)n * p;
+  return 2 * (n + 1) + 2 * (int)((ld + kSgsRows - 1) / kSgsRows);
+}
+
+hipError_t launch_sgs_fused(const LevelView& L, const double* v, const double* zero, double* c,
+                            double* a, double* d, double* yf, double* yb, const double* Pf,
+                            const double* Qb, int variant, const PairSync& ps, int* groups,
+                            hipStream_t s) {
+  *groups = 0;
+  if (L.fp32 || L.p != L.q || (L.p != 64 && L.p != 128) || L.n + 1 > 64 || !ps.ticket ||
+      !ps.flag || !ps.timeout)
+    return hipErrorInvalidValue;
+  SgsPhases F{L, v, zero, c, a, d, yf, yb, Pf, Qb, variant};
+  const long long ld = (long long)L.n * L.p;
+  const int ng = (int)((ld + kSgsRows - 1) / kSgsRows);
+  const int total = 3 * (L.n + 1) + 2 * ng;
+  *groups = total;
+  if (L.p == 128)
+    return launch_k(k_sgs_fused<4, 8, double>, dim3(total), dim3(kTiledThreads), 0, s, F, ps);
+  return launch_k(k_sgs_fused<2, 4, double>, dim3(total), dim3(kTiledThreads), 0, s, F, ps);
+}
 
 hipError_t launch_jacobi_chain(const ChainSweep* sw, int nlev, int up, int variant,
                                const PairSync& ps, int* groups, hipStream_t s) {
